@@ -1,0 +1,227 @@
+"""Python access to the FP64 CPU oracle (``oracle/lhf_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the product library never does.
+It shares no code with the HIP path (see the header of ``lhf_oracle.c`` for
+what is computed and which passage of the paper each routine follows).
+
+Every array crossing this wrapper is a contiguous float64 (or complex128)
+numpy array; points and strengths are ``[N, 3]`` row-major.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lhf_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_lhf_oracle.so")
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_cp = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
+               "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Stats(C.Structure):
+    _fields_ = [("n_m2l", C.c_int64), ("n_m2m", C.c_int64), ("n_l2l", C.c_int64),
+                ("n_p2p_pairs", C.c_int64)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = C.CDLL(_LIB_PATH)
+        L.lho_basis_R.argtypes = [C.c_int, _dp, _cp]
+        L.lho_basis_S.argtypes = [C.c_int, _dp, _cp]
+        L.lho_kernel_fg.argtypes = [C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]
+        for nm in ("lho_p2m_method1", "lho_p2m_method2"):
+            getattr(L, nm).argtypes = [C.c_int, _dp, C.c_int64, _dp, _dp, _cp, _cp]
+        for nm in ("lho_m2m", "lho_m2l", "lho_l2l"):
+            getattr(L, nm).argtypes = [C.c_int, _dp, _cp, _cp, _cp, _cp]
+        L.lho_l2p.argtypes = [C.c_int, _dp, _cp, _cp, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.lho_direct.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int, C.c_int, _dp, C.c_double,
+                                 C.c_int64, C.c_void_p, _dp, _dp, C.c_void_p]
+        L.lho_fmm.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int, C.c_int, _dp, C.c_double,
+                              C.c_int, C.c_int, C.c_int64, C.c_void_p, _dp, _dp, C.c_void_p,
+                              C.POINTER(_Stats)]
+        L.lho_fmm.restype = C.c_int
+        L.lho_tree_counts.argtypes = [C.c_int64, _dp, C.c_int, _dp, C.c_double, _ip,
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.lho_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def num_threads() -> int:
+    return int(lib().lho_num_threads())
+
+
+def idx(n: int, m: int) -> int:
+    """storage index of coefficient (n, m)"""
+    return n * n + n + m
+
+
+def basis_R(nmax: int, r) -> np.ndarray:
+    out = np.zeros(nmax * nmax, np.complex128)
+    lib().lho_basis_R(nmax, _f64(r, (3,)), out)
+    return out
+
+
+def basis_S(nmax: int, r) -> np.ndarray:
+    out = np.zeros(nmax * nmax, np.complex128)
+    lib().lho_basis_S(nmax, _f64(r, (3,)), out)
+    return out
+
+
+def kernel_fg(r: float, a: float, smooth: bool = True):
+    f, g = C.c_double(), C.c_double()
+    lib().lho_kernel_fg(float(r), float(a), int(bool(smooth)), C.byref(f), C.byref(g))
+    return f.value, g.value
+
+
+def p2m(p: int, centre, x, w, method: int = 2):
+    """(phi, chi) multipole coefficients about centre (eq. eve4 / eqs. eve5-eve10)."""
+    x = _f64(x).reshape(-1, 3)
+    w = _f64(w).reshape(-1, 3)
+    phi = np.zeros(p * p, np.complex128)
+    chi = np.zeros(p * p, np.complex128)
+    fn = lib().lho_p2m_method2 if method == 2 else lib().lho_p2m_method1
+    fn(p, _f64(centre, (3,)), x.shape[0], x, w, phi, chi)
+    return phi, chi
+
+
+def _translate(fn, p, t, phi, chi):
+    oph = np.zeros(p * p, np.complex128)
+    och = np.zeros(p * p, np.complex128)
+    fn(p, _f64(t, (3,)), np.ascontiguousarray(phi, np.complex128),
+       np.ascontiguousarray(chi, np.complex128), oph, och)
+    return oph, och
+
+
+def m2m(p, t, phi, chi):
+    return _translate(lib().lho_m2m, p, t, phi, chi)
+
+
+def m2l(p, t, phi, chi):
+    return _translate(lib().lho_m2l, p, t, phi, chi)
+
+
+def l2l(p, t, phi, chi):
+    return _translate(lib().lho_l2l, p, t, phi, chi)
+
+
+def l2p(p, centre, phi, chi, x, w):
+    """Evaluate a local expansion: returns v, s, grad v, Im v, Im grad v."""
+    x = _f64(x).reshape(-1, 3)
+    w = _f64(w).reshape(-1, 3)
+    n = x.shape[0]
+    v = np.zeros((n, 3)); s = np.zeros((n, 3)); g = np.zeros((n, 9))
+    iv = np.zeros((n, 3)); ig = np.zeros((n, 9))
+    lib().lho_l2p(p, _f64(centre, (3,)), np.ascontiguousarray(phi, np.complex128),
+                  np.ascontiguousarray(chi, np.complex128), n, x, w, v, s, g, iv, ig)
+    return v, s, g.reshape(n, 3, 3), iv, ig.reshape(n, 3, 3)
+
+
+DIRECT_SINGULAR, DIRECT_SMOOTH, DIRECT_SPLIT = 0, 1, 2
+
+
+def direct(x, w, a, mode=DIRECT_SPLIT, depth=2, lo=(0.0, 0.0, 0.0), L=1.0, targets=None,
+           grad=False):
+    """Direct O(N |targets|) sums of v, s (and grad v) -- eqs. 1, 2, s1.1, vem1.
+
+    mode: DIRECT_SINGULAR (K=1), DIRECT_SMOOTH (Gaussian everywhere) or
+    DIRECT_SPLIT (Gaussian between adjacent leaves of the depth-``depth``
+    octree on [lo, lo+L]^3, singular otherwise)."""
+    x = _f64(x).reshape(-1, 3)
+    w = _f64(w).reshape(-1, 3)
+    n = x.shape[0]
+    if targets is None:
+        nt, tp = n, None
+    else:
+        targets = np.ascontiguousarray(targets, np.int64)
+        nt, tp = targets.shape[0], targets.ctypes.data
+    v = np.zeros((nt, 3)); s = np.zeros((nt, 3))
+    g = np.zeros((nt, 9)) if grad else None
+    lib().lho_direct(n, x, w, float(a), int(mode), int(depth), _f64(lo, (3,)), float(L), nt, tp, v, s,
+                     g.ctypes.data if grad else None)
+    return (v, s, g.reshape(nt, 3, 3)) if grad else (v, s)
+
+
+def fmm(x, w, a, p, depth, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True, p2m_method=2,
+        sample=None, grad=False):
+    """Plain FP64 two-potential FMM (direct-mode translations).
+
+    With ``sample`` (element indices), only the leaves holding those elements
+    are evaluated; the outputs of the other elements are NaN."""
+    x = _f64(x).reshape(-1, 3)
+    w = _f64(w).reshape(-1, 3)
+    n = x.shape[0]
+    v = np.zeros((n, 3)); s = np.zeros((n, 3))
+    g = np.zeros((n, 9)) if grad else None
+    if sample is None:
+        ns, sp = 0, None
+    else:
+        sample = np.ascontiguousarray(sample, np.int64)
+        ns, sp = sample.shape[0], sample.ctypes.data
+    st = _Stats()
+    what = (1 if far else 0) | (2 if near else 0)
+    rc = lib().lho_fmm(n, x, w, float(a), int(p), int(depth), _f64(lo, (3,)), float(L), what,
+                       int(p2m_method), ns, sp, v, s, g.ctypes.data if grad else None, C.byref(st))
+    if rc != 0:
+        raise ValueError("oracle fmm rejected its arguments")
+    if sample is not None:
+        # mark untouched outputs
+        mask = np.zeros(n, bool)
+        mask[_leaf_members(x, depth, lo, L, sample)] = True
+        v[~mask] = np.nan
+        s[~mask] = np.nan
+        if grad:
+            g[~mask] = np.nan
+    stats = dict(n_m2l=st.n_m2l, n_l2l=st.n_l2l, n_p2p_pairs=st.n_p2p_pairs)
+    out = (v, s, g.reshape(n, 3, 3)) if grad else (v, s)
+    return out + (stats,)
+
+
+def _leaf_coords(x, depth, lo, L):
+    scale = float(2 ** 21) / L
+    q = np.floor((x - np.asarray(lo)[None, :]) * scale)
+    q = np.clip(q, 0, 2 ** 21 - 1).astype(np.int64)
+    return q >> (21 - depth)
+
+
+def _leaf_members(x, depth, lo, L, sample):
+    lc = _leaf_coords(x, depth, lo, L)
+    keys = lc[:, 0] * (1 << 42) + lc[:, 1] * (1 << 21) + lc[:, 2]
+    return np.isin(keys, np.unique(keys[sample]))
+
+
+def tree_counts(x, depth, lo=(0.0, 0.0, 0.0), L=1.0):
+    x = _f64(x).reshape(-1, 3)
+    nb = np.zeros(depth + 1, np.int64)
+    a, b = C.c_int64(), C.c_int64()
+    lib().lho_tree_counts(x.shape[0], x, int(depth), _f64(lo, (3,)), float(L), nb, C.byref(a), C.byref(b))
+    return nb, a.value, b.value

@@ -1,0 +1,1082 @@
+/*
+ * lhf_oracle.c -- plain FP64 CPU oracle for the Lamb-Helmholtz vortex FMM.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * generator with the HIP library.
+ *
+ * What it computes (Gumerov & Duraiswami, "Efficient FMM accelerated vortex
+ * methods in three dimensions via the Lamb-Helmholtz decomposition"):
+ *
+ *   (A) direct sums of the Biot-Savart velocity v (eq. 1, with the smoothing
+ *       kernel of eq. 2 / eq. vem1) and of the stretching term
+ *       s_j = (omega_j . grad) v at x_j (eq. s1.1), self term excluded;
+ *   (B) a plain FMM in the two-potential (phi, chi) form (eq. 4):
+ *       P2M by Method 2 (eq. eve4) and Method 1 (eqs. eve5-eve10),
+ *       M2M / M2L / L2L with the full translation matrices of eq. mr3
+ *       followed by the general conversion operators of eqs. drt10 / drt11
+ *       (no rotations: this is the plain definition, O(p^4) per translation),
+ *       L2P of v (eq. evf3) and of grad v / s (eqs. dt3, evf5, evf6),
+ *       near field by (A) over adjacent leaves.
+ *
+ * Storage is the plain complex one: coefficient (n, m), -n <= m <= n, at
+ * index n*n + n + m; truncation number p keeps orders n = 0..p-1 (Sec. 5.1).
+ * Precision: FP64 throughout; compiled with -ffp-contract=off.
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - no 1/(4 pi) factor: eq. 1 is used literally (eq. 7 absorbs it);
+ *   - translation vector t = new centre - old centre (eq. bas1);
+ *   - M2L computes chi-hat to order p (one extra row) before the R-basis
+ *     conversion, then truncates to p-1 ("reading B");
+ *   - octree: cube [lo, lo+L]^3, integer coordinates
+ *     q = min(floor((x-lo)*(2^21/L)), 2^21-1), level-l box = q >> (21-l),
+ *     empty boxes skipped, M2L from level 2, V-list = children of the
+ *     parent's neighbours that are not adjacent (adjacency is closed),
+ *     U-list = adjacent leaves (incl. self);
+ *   - the near field (U-list pairs) uses the smoothed kernel, the far field
+ *     the singular one (eq. 2: the core only changes the near field).
+ *
+ * Parity pins: every routine here is checked by the CPU tests against closed
+ * forms, identities, finite differences or brute force (see tests/).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define IDX(n, m) ((n) * (n) + (n) + (m))
+#define QBITS 21
+#define MAXLEV 21
+
+/* ------------------------------------------------------------------------- */
+/* small helpers                                                              */
+/* ------------------------------------------------------------------------- */
+
+static double fact(int k)
+{
+    double f = 1.0;
+    for (int i = 2; i <= k; i++) f *= (double)i;
+    return f;
+}
+
+/* i^k for integer k (any sign) */
+static cplx ipow(int k)
+{
+    int r = ((k % 4) + 4) % 4;
+    switch (r) {
+    case 0: return 1.0;
+    case 1: return I;
+    case 2: return -1.0;
+    default: return -I;
+    }
+}
+
+static double sgn_pow(int k) { return (k & 1) ? -1.0 : 1.0; }
+
+/* coefficient lookup with the zero extension of eq. rsbf7 */
+static cplx cget(const cplx *c, int nmax, int n, int m)
+{
+    if (n < 0 || n >= nmax || m < -n || m > n) return 0.0;
+    return c[IDX(n, m)];
+}
+
+/* ------------------------------------------------------------------------- */
+/* Basis functions, eqs. rsbf1-rsbf3                                          */
+/* ------------------------------------------------------------------------- */
+
+/* Associated Legendre functions P_n^m(mu), 0<=m<=n<nmax, WITH the
+ * Condon-Shortley phase (-1)^m of eq. rsbf3, by the textbook recurrences
+ *   P_m^m = (-1)^m (2m-1)!! (1-mu^2)^{m/2},  P_{m+1}^m = mu (2m+1) P_m^m,
+ *   (n-m) P_n^m = (2n-1) mu P_{n-1}^m - (n+m-1) P_{n-2}^m.
+ * P[n*nmax+m]. */
+static void legendre(int nmax, double mu, double *P)
+{
+    double sth = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double pmm = 1.0;
+    for (int m = 0; m < nmax; m++) {
+        if (m > 0) pmm *= -(2.0 * m - 1.0) * sth;
+        P[m * nmax + m] = pmm;
+        if (m + 1 < nmax) P[(m + 1) * nmax + m] = mu * (2.0 * m + 1.0) * pmm;
+        for (int n = m + 2; n < nmax; n++)
+            P[n * nmax + m] = ((2.0 * n - 1.0) * mu * P[(n - 1) * nmax + m] -
+                               (n + m - 1.0) * P[(n - 2) * nmax + m]) / (double)(n - m);
+    }
+}
+
+/* R_n^m(r) (eq. rsbf2) for n < nmax, all m. */
+void lho_basis_R(int nmax, const double r[3], cplx *out)
+{
+    double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    memset(out, 0, sizeof(cplx) * (size_t)nmax * nmax);
+    if (rr == 0.0) {
+        out[0] = 1.0;
+        return;
+    }
+    double mu = r[2] / rr, ph = atan2(r[1], r[0]);
+    double *P = (double *)malloc(sizeof(double) * (size_t)nmax * nmax);
+    legendre(nmax, mu, P);
+    for (int n = 0; n < nmax; n++) {
+        double rn = pow(rr, (double)n);
+        for (int m = -n; m <= n; m++) {
+            int am = abs(m);
+            out[IDX(n, m)] = sgn_pow(n) * ipow(am) / fact(n + am) * rn * P[n * nmax + am] *
+                             cexp(I * (double)m * ph);
+        }
+    }
+    free(P);
+}
+
+/* S_n^m(r) (eq. rsbf2) for n < nmax, all m; r != 0. */
+void lho_basis_S(int nmax, const double r[3], cplx *out)
+{
+    double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    double mu = r[2] / rr, ph = atan2(r[1], r[0]);
+    double *P = (double *)malloc(sizeof(double) * (size_t)nmax * nmax);
+    legendre(nmax, mu, P);
+    for (int n = 0; n < nmax; n++) {
+        double rn1 = pow(rr, -(double)(n + 1));
+        for (int m = -n; m <= n; m++) {
+            int am = abs(m);
+            out[IDX(n, m)] = ipow(-am) * fact(n - am) * rn1 * P[n * nmax + am] *
+                             cexp(I * (double)m * ph);
+        }
+    }
+    free(P);
+}
+
+/* value of an expansion sum_{n<p} c_n^m F_n^m(y - centre), F = R (kind 0) or S (kind 1) */
+cplx lho_eval_expansion(int p, int kind, const double centre[3], const cplx *c, const double y[3])
+{
+    double r[3] = {y[0] - centre[0], y[1] - centre[1], y[2] - centre[2]};
+    cplx *F = (cplx *)malloc(sizeof(cplx) * (size_t)p * p);
+    if (kind == 0) lho_basis_R(p, r, F);
+    else lho_basis_S(p, r, F);
+    cplx acc = 0.0;
+    for (int k = 0; k < p * p; k++) acc += c[k] * F[k];
+    free(F);
+    return acc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Smoothed core, eqs. 2 and vem1                                             */
+/* ------------------------------------------------------------------------- */
+
+/* f(r) = K(r;a)/r^3 and g(r) = f'(r)/r.  smooth = 0: singular kernel K = 1.
+ * Gaussian core: K = erf(r/(a sqrt2)) - sqrt(2/pi)(r/a) exp(-r^2/2a^2),
+ * K' = sqrt(2/pi) (r^2/a^3) exp(-r^2/2a^2).  For small u = r^2/(2a^2) the
+ * closed form cancels, so the Taylor series of
+ *   f = sqrt(2/pi)/a^3 * (1/r^3) int_0^r s^2 exp(-s^2/2a^2) ds
+ *     = sqrt(2/pi)/a^3 * sum_k (-u)^k / (k! (2k+3))
+ * and of g = (1/a^2) df/du is used there. */
+void lho_kernel_fg(double r, double a, int smooth, double *f, double *g)
+{
+    if (!smooth) {
+        double r2 = r * r;
+        double ir3 = 1.0 / (r2 * r);
+        *f = ir3;
+        *g = -3.0 * ir3 / r2;
+        return;
+    }
+    const double c = sqrt(2.0 / M_PI);
+    double u = r * r / (2.0 * a * a);
+    if (u < 0.02) {
+        double fs = 0.0, gs = 0.0, term = 1.0; /* term = (-u)^k / k! */
+        for (int k = 0; k < 12; k++) {
+            fs += term / (2.0 * k + 3.0);
+            term *= -u / (double)(k + 1);
+        }
+        /* g series: sum_{k>=1} (-1)^k u^{k-1} / ((k-1)! (2k+3)) */
+        double t2 = -1.0; /* k=1: (-1)^1 u^0 / 0! */
+        for (int k = 1; k < 13; k++) {
+            gs += t2 / (2.0 * k + 3.0);
+            t2 *= -u / (double)k;
+        }
+        *f = c / (a * a * a) * fs;
+        *g = c / (a * a * a * a * a) * gs;
+    } else {
+        double K = erf(r / (a * sqrt(2.0))) - c * (r / a) * exp(-u);
+        double r2 = r * r;
+        *f = K / (r2 * r);
+        *g = c * exp(-u) / (a * a * a * r2) - 3.0 * K / (r2 * r2 * r);
+    }
+}
+
+/* contribution of source (xi, wi) to target (xj, wj): v, grad v (row k = component,
+ * column l = derivative) and s.  r = xj - xi. */
+static void pair_accum(const double *xj, const double *wj, const double *xi, const double *wi,
+                       double a, int smooth, double *v, double *s, double *gv)
+{
+    double r[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
+    double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    double rr = sqrt(r2);
+    if (rr == 0.0 && !smooth) return; /* coincident distinct points, singular: defined as 0 */
+    double f, g;
+    lho_kernel_fg(rr, a, smooth, &f, &g);
+    double wxr[3] = {wi[1] * r[2] - wi[2] * r[1], wi[2] * r[0] - wi[0] * r[2], wi[0] * r[1] - wi[1] * r[0]};
+    double wxw[3] = {wi[1] * wj[2] - wi[2] * wj[1], wi[2] * wj[0] - wi[0] * wj[2], wi[0] * wj[1] - wi[1] * wj[0]};
+    double wjr = wj[0] * r[0] + wj[1] * r[1] + wj[2] * r[2];
+    for (int k = 0; k < 3; k++) {
+        v[k] += f * wxr[k];
+        s[k] += f * wxw[k] + g * wjr * wxr[k];
+    }
+    if (gv) {
+        /* d_l (f (w x r))_k = g r_l (w x r)_k + f eps_{k a l} w_a */
+        for (int k = 0; k < 3; k++)
+            for (int l = 0; l < 3; l++) gv[3 * k + l] += g * r[l] * wxr[k];
+        gv[3 * 0 + 1] += f * (-wi[2]); /* eps_{0 a 1}: a=2 -> eps_{021} = -1 */
+        gv[3 * 0 + 2] += f * (wi[1]);  /* eps_{012} = +1 */
+        gv[3 * 1 + 0] += f * (wi[2]);  /* eps_{120} = +1 */
+        gv[3 * 1 + 2] += f * (-wi[0]); /* eps_{102} = -1 */
+        gv[3 * 2 + 0] += f * (-wi[1]); /* eps_{210} = -1 */
+        gv[3 * 2 + 1] += f * (wi[0]);  /* eps_{201} = +1 */
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Octree (uniform depth), rule stated in the header                          */
+/* ------------------------------------------------------------------------- */
+
+static uint64_t spread3(uint32_t v)
+{
+    uint64_t k = 0;
+    for (int b = 0; b < QBITS; b++) k |= (uint64_t)((v >> b) & 1u) << (3 * b);
+    return k;
+}
+static uint32_t gather3(uint64_t k)
+{
+    uint32_t v = 0;
+    for (int b = 0; b < QBITS; b++) v |= (uint32_t)((k >> (3 * b)) & 1u) << b;
+    return v;
+}
+static uint64_t morton(uint32_t ix, uint32_t iy, uint32_t iz)
+{
+    return spread3(ix) | (spread3(iy) << 1) | (spread3(iz) << 2);
+}
+
+/* integer coordinate of one component: min(floor((x-lo)*(2^21/L)), 2^21-1) */
+static uint32_t qcoord(double x, double lo, double scale)
+{
+    double t = (x - lo) * scale;
+    double fl = floor(t);
+    if (fl < 0.0) fl = 0.0; /* callers validate the domain; clamp for safety */
+    if (fl > (double)((1u << QBITS) - 1u)) fl = (double)((1u << QBITS) - 1u);
+    return (uint32_t)fl;
+}
+
+typedef struct {
+    int depth;
+    double lo[3], L;
+    int64_t n;
+    uint32_t *q;     /* [n][3] integer coordinates */
+    int64_t *order;  /* particle indices sorted by leaf key (stable) */
+    int64_t nb[MAXLEV + 1];
+    uint64_t *key[MAXLEV + 1];
+    int64_t *first[MAXLEV + 1];
+    int64_t *count[MAXLEV + 1];
+} otree;
+
+typedef struct {
+    uint64_t k;
+    int64_t i;
+} kidx;
+
+static int cmp_kidx(const void *a, const void *b)
+{
+    const kidx *x = (const kidx *)a, *y = (const kidx *)b;
+    if (x->k < y->k) return -1;
+    if (x->k > y->k) return 1;
+    return (x->i < y->i) ? -1 : (x->i > y->i);
+}
+
+static void tree_build(otree *T, int64_t n, const double *x, int depth, const double lo[3], double L)
+{
+    memset(T, 0, sizeof(*T));
+    T->depth = depth;
+    T->n = n;
+    T->L = L;
+    for (int d = 0; d < 3; d++) T->lo[d] = lo[d];
+    double scale = (double)(1u << QBITS) / L;
+    T->q = (uint32_t *)malloc(sizeof(uint32_t) * 3 * (size_t)n);
+    kidx *ki = (kidx *)malloc(sizeof(kidx) * (size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        for (int d = 0; d < 3; d++) T->q[3 * i + d] = qcoord(x[3 * i + d], lo[d], scale);
+        int sh = QBITS - depth;
+        ki[i].k = morton(T->q[3 * i] >> sh, T->q[3 * i + 1] >> sh, T->q[3 * i + 2] >> sh);
+        ki[i].i = i;
+    }
+    qsort(ki, (size_t)n, sizeof(kidx), cmp_kidx);
+    T->order = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; i++) T->order[i] = ki[i].i;
+    for (int l = 0; l <= depth; l++) {
+        int sh = 3 * (depth - l);
+        int64_t nb = 0;
+        for (int64_t i = 0; i < n; i++)
+            if (i == 0 || (ki[i].k >> sh) != (ki[i - 1].k >> sh)) nb++;
+        T->nb[l] = nb;
+        T->key[l] = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(nb + 1));
+        T->first[l] = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb + 1));
+        T->count[l] = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nb + 1));
+        int64_t b = -1;
+        for (int64_t i = 0; i < n; i++) {
+            if (i == 0 || (ki[i].k >> sh) != (ki[i - 1].k >> sh)) {
+                b++;
+                T->key[l][b] = ki[i].k >> sh;
+                T->first[l][b] = i;
+                T->count[l][b] = 0;
+            }
+            T->count[l][b]++;
+        }
+    }
+    free(ki);
+}
+
+static void tree_free(otree *T)
+{
+    free(T->q);
+    free(T->order);
+    for (int l = 0; l <= T->depth; l++) {
+        free(T->key[l]);
+        free(T->first[l]);
+        free(T->count[l]);
+    }
+}
+
+/* index of the box with Morton key k at level l, or -1 */
+static int64_t tree_find(const otree *T, int l, uint64_t k)
+{
+    int64_t lo = 0, hi = T->nb[l] - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (T->key[l][mid] == k) return mid;
+        if (T->key[l][mid] < k) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+static void box_coords(uint64_t k, int c[3])
+{
+    c[0] = (int)gather3(k);
+    c[1] = (int)gather3(k >> 1);
+    c[2] = (int)gather3(k >> 2);
+}
+
+static void box_centre(const otree *T, int l, uint64_t k, double c[3])
+{
+    int ic[3];
+    box_coords(k, ic);
+    double h = T->L / (double)(1u << l);
+    for (int d = 0; d < 3; d++) c[d] = T->lo[d] + ((double)ic[d] + 0.5) * h;
+}
+
+/* ------------------------------------------------------------------------- */
+/* P2M, Sec. 4.3                                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Method 2 (eq. eve4): add the (phi, chi) multipole coefficients about
+ * 'centre' of the vortex elements (x_l, w_l) into phi, chi (p^2 each). */
+void lho_p2m_method2(int p, const double centre[3], int64_t n, const double *x, const double *w,
+                     cplx *phi, cplx *chi)
+{
+    cplx *g = (cplx *)malloc(sizeof(cplx) * (size_t)p * p);
+    cplx *R = (cplx *)malloc(sizeof(cplx) * (size_t)p * p);
+    for (int64_t l = 0; l < n; l++) {
+        double mr[3] = {-(x[3 * l] - centre[0]), -(x[3 * l + 1] - centre[1]), -(x[3 * l + 2] - centre[2])};
+        lho_basis_R(p, mr, R);
+        /* g_n^m = R_n^{-m}(-r_l) */
+        for (int nn = 0; nn < p; nn++)
+            for (int m = -nn; m <= nn; m++) g[IDX(nn, m)] = R[IDX(nn, -m)];
+        double wx = w[3 * l], wy = w[3 * l + 1], wz = w[3 * l + 2];
+        for (int nn = 0; nn < p; nn++)
+            for (int m = -nn; m <= nn; m++) {
+                cplx a = (wx - I * wy) * (nn - m + 1) / 2.0 * cget(g, p, nn, m - 1) -
+                         (wx + I * wy) * (nn + m + 1) / 2.0 * cget(g, p, nn, m + 1) -
+                         I * wz * (double)m * cget(g, p, nn, m);
+                phi[IDX(nn, m)] += a / (double)(nn + 1);
+                if (nn > 0) {
+                    cplx b = 0.5 * (wy + I * wx) * cget(g, p, nn - 1, m - 1) -
+                             0.5 * (wy - I * wx) * cget(g, p, nn - 1, m + 1) -
+                             wz * cget(g, p, nn - 1, m);
+                    chi[IDX(nn, m)] += -b / (double)nn;
+                }
+            }
+    }
+    free(g);
+    free(R);
+}
+
+/* Method 1 (eqs. eve5-eve10): psi and varpi are dipoles with moments
+ * r_l x w_l and -w_l; the dipole expansion is obtained by differentiating
+ * eq. rsbf5 with respect to the source point, using eq. dt2:
+ *   psi_n^m = -1/2 (P_y + i P_x) g_{n-1}^{m-1} + 1/2 (P_y - i P_x) g_{n-1}^{m+1} + P_z g_{n-1}^m,
+ * then phi_n^m = -psi_n^m/(n+1), chi_n^m = -varpi_n^m/n, chi_0^0 = 0. */
+void lho_p2m_method1(int p, const double centre[3], int64_t n, const double *x, const double *w,
+                     cplx *phi, cplx *chi)
+{
+    cplx *g = (cplx *)malloc(sizeof(cplx) * (size_t)p * p);
+    cplx *R = (cplx *)malloc(sizeof(cplx) * (size_t)p * p);
+    for (int64_t l = 0; l < n; l++) {
+        double rl[3] = {x[3 * l] - centre[0], x[3 * l + 1] - centre[1], x[3 * l + 2] - centre[2]};
+        double mr[3] = {-rl[0], -rl[1], -rl[2]};
+        lho_basis_R(p, mr, R);
+        for (int nn = 0; nn < p; nn++)
+            for (int m = -nn; m <= nn; m++) g[IDX(nn, m)] = R[IDX(nn, -m)];
+        const double *wl = &w[3 * l];
+        double P[3] = {rl[1] * wl[2] - rl[2] * wl[1], rl[2] * wl[0] - rl[0] * wl[2], rl[0] * wl[1] - rl[1] * wl[0]};
+        double Q[3] = {-wl[0], -wl[1], -wl[2]};
+        for (int nn = 1; nn < p; nn++)
+            for (int m = -nn; m <= nn; m++) {
+                cplx psi = -0.5 * (P[1] + I * P[0]) * cget(g, p, nn - 1, m - 1) +
+                           0.5 * (P[1] - I * P[0]) * cget(g, p, nn - 1, m + 1) + P[2] * cget(g, p, nn - 1, m);
+                cplx vpi = -0.5 * (Q[1] + I * Q[0]) * cget(g, p, nn - 1, m - 1) +
+                           0.5 * (Q[1] - I * Q[0]) * cget(g, p, nn - 1, m + 1) + Q[2] * cget(g, p, nn - 1, m);
+                phi[IDX(nn, m)] += -psi / (double)(nn + 1);
+                chi[IDX(nn, m)] += -vpi / (double)nn;
+            }
+    }
+    free(g);
+    free(R);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Translations: eq. mr3 (full matrices) + conversion, eqs. drt10 / drt11    */
+/* ------------------------------------------------------------------------- */
+
+/* R-basis conversion (eq. drt10) of translated (ph, ch) with general t.
+ * ph has p orders, ch has pc orders (pc = p or p+1); result truncated to p. */
+static void convert_R(int p, int pc, const double t[3], const cplx *ph, const cplx *ch, cplx *outph,
+                      cplx *outch)
+{
+    cplx tp = t[0] + I * t[1], tm = t[0] - I * t[1];
+    cplx sp = t[1] + I * t[0], sm = t[1] - I * t[0];
+    for (int n = 0; n < p; n++)
+        for (int m = -n; m <= n; m++) {
+            cplx f = ph[IDX(n, m)];
+            if (n > 0)
+                f -= (tp * (double)(n - m) / 2.0 * cget(ch, pc, n, m + 1) -
+                      tm * (double)(n + m) / 2.0 * cget(ch, pc, n, m - 1) -
+                      I * t[2] * (double)m * cget(ch, pc, n, m)) / (double)n;
+            cplx c = cget(ch, pc, n, m) +
+                     (0.5 * sp * cget(ch, pc, n + 1, m - 1) - 0.5 * sm * cget(ch, pc, n + 1, m + 1) -
+                      t[2] * cget(ch, pc, n + 1, m)) / (double)(n + 1);
+            outph[IDX(n, m)] = f;
+            outch[IDX(n, m)] = c;
+        }
+}
+
+/* S-basis conversion (eq. drt11), p orders in and out. */
+static void convert_S(int p, const double t[3], const cplx *ph, const cplx *ch, cplx *outph, cplx *outch)
+{
+    cplx tp = t[0] + I * t[1], tm = t[0] - I * t[1];
+    cplx sp = t[1] + I * t[0], sm = t[1] - I * t[0];
+    for (int n = 0; n < p; n++)
+        for (int m = -n; m <= n; m++) {
+            cplx f = ph[IDX(n, m)] +
+                     (-tp * (double)(n + m + 1) / 2.0 * cget(ch, p, n, m + 1) +
+                      tm * (double)(n - m + 1) / 2.0 * cget(ch, p, n, m - 1) -
+                      I * t[2] * (double)m * cget(ch, p, n, m)) / (double)(n + 1);
+            cplx c = ch[IDX(n, m)];
+            if (n > 0)
+                c -= (0.5 * sp * cget(ch, p, n - 1, m - 1) - 0.5 * sm * cget(ch, p, n - 1, m + 1) -
+                      t[2] * cget(ch, p, n - 1, m)) / (double)n;
+            outph[IDX(n, m)] = f;
+            outch[IDX(n, m)] = c;
+        }
+}
+
+/* M2M: multipole (phi, chi) about c_old -> about c_new, t = c_new - c_old.
+ * (S|S): hat_n^m = sum_{n'<=n, m'} R_{n-n'}^{m'-m}(t) in_{n'}^{m'}; then drt11.
+ * Result is ADDED into (oph, och). */
+void lho_m2m(int p, const double t[3], const cplx *phi, const cplx *chi, cplx *oph, cplx *och)
+{
+    size_t P2 = (size_t)p * p;
+    cplx *Rt = (cplx *)malloc(sizeof(cplx) * P2);
+    cplx *hp = (cplx *)calloc(P2, sizeof(cplx)), *hc = (cplx *)calloc(P2, sizeof(cplx));
+    cplx *tp = (cplx *)malloc(sizeof(cplx) * P2), *tc = (cplx *)malloc(sizeof(cplx) * P2);
+    lho_basis_R(p, t, Rt);
+    for (int n = 0; n < p; n++)
+        for (int m = -n; m <= n; m++) {
+            cplx ap = 0.0, ac = 0.0;
+            for (int n2 = 0; n2 <= n; n2++)
+                for (int m2 = -n2; m2 <= n2; m2++) {
+                    cplx c = cget(Rt, p, n - n2, m2 - m);
+                    ap += c * phi[IDX(n2, m2)];
+                    ac += c * chi[IDX(n2, m2)];
+                }
+            hp[IDX(n, m)] = ap;
+            hc[IDX(n, m)] = ac;
+        }
+    convert_S(p, t, hp, hc, tp, tc);
+    for (size_t k = 0; k < P2; k++) {
+        oph[k] += tp[k];
+        och[k] += tc[k];
+    }
+    free(Rt);
+    free(hp);
+    free(hc);
+    free(tp);
+    free(tc);
+}
+
+/* M2L: multipole about c_s -> local about c_t, t = c_t - c_s.
+ * (S|R): hat_n^m = sum_{n'<p, m'} S_{n+n'}^{m'-m}(t) in_{n'}^{m'}, phi-hat for
+ * n<p, chi-hat for n<=p (reading B), then drt10 truncated to n<p.  ADDED. */
+void lho_m2l(int p, const double t[3], const cplx *phi, const cplx *chi, cplx *oph, cplx *och)
+{
+    int ns = 2 * p + 1;
+    size_t P2 = (size_t)p * p, P21 = (size_t)(p + 1) * (p + 1);
+    cplx *St = (cplx *)malloc(sizeof(cplx) * (size_t)ns * ns);
+    cplx *hp = (cplx *)calloc(P2, sizeof(cplx)), *hc = (cplx *)calloc(P21, sizeof(cplx));
+    cplx *tp = (cplx *)malloc(sizeof(cplx) * P2), *tc = (cplx *)malloc(sizeof(cplx) * P2);
+    lho_basis_S(ns, t, St);
+    for (int n = 0; n <= p; n++)
+        for (int m = -n; m <= n; m++) {
+            cplx ap = 0.0, ac = 0.0;
+            for (int n2 = 0; n2 < p; n2++)
+                for (int m2 = -n2; m2 <= n2; m2++) {
+                    cplx c = cget(St, ns, n + n2, m2 - m);
+                    ap += c * phi[IDX(n2, m2)];
+                    ac += c * chi[IDX(n2, m2)];
+                }
+            if (n < p) hp[IDX(n, m)] = ap;
+            hc[IDX(n, m)] = ac;
+        }
+    convert_R(p, p + 1, t, hp, hc, tp, tc);
+    for (size_t k = 0; k < P2; k++) {
+        oph[k] += tp[k];
+        och[k] += tc[k];
+    }
+    free(St);
+    free(hp);
+    free(hc);
+    free(tp);
+    free(tc);
+}
+
+/* L2L: local about c_old -> local about c_new, t = c_new - c_old.
+ * (R|R): hat_n^m = sum_{n'>=n, m'} R_{n'-n}^{m'-m}(t) in_{n'}^{m'}; drt10. ADDED. */
+void lho_l2l(int p, const double t[3], const cplx *phi, const cplx *chi, cplx *oph, cplx *och)
+{
+    size_t P2 = (size_t)p * p;
+    cplx *Rt = (cplx *)malloc(sizeof(cplx) * P2);
+    cplx *hp = (cplx *)calloc(P2, sizeof(cplx)), *hc = (cplx *)calloc(P2, sizeof(cplx));
+    cplx *tp = (cplx *)malloc(sizeof(cplx) * P2), *tc = (cplx *)malloc(sizeof(cplx) * P2);
+    lho_basis_R(p, t, Rt);
+    for (int n = 0; n < p; n++)
+        for (int m = -n; m <= n; m++) {
+            cplx ap = 0.0, ac = 0.0;
+            for (int n2 = n; n2 < p; n2++)
+                for (int m2 = -n2; m2 <= n2; m2++) {
+                    cplx c = cget(Rt, p, n2 - n, m2 - m);
+                    ap += c * phi[IDX(n2, m2)];
+                    ac += c * chi[IDX(n2, m2)];
+                }
+            hp[IDX(n, m)] = ap;
+            hc[IDX(n, m)] = ac;
+        }
+    convert_R(p, p, t, hp, hc, tp, tc);
+    for (size_t k = 0; k < P2; k++) {
+        oph[k] += tp[k];
+        och[k] += tc[k];
+    }
+    free(Rt);
+    free(hp);
+    free(hc);
+    free(tp);
+    free(tc);
+}
+
+/* ------------------------------------------------------------------------- */
+/* L2P, Sec. 4.5                                                              */
+/* ------------------------------------------------------------------------- */
+
+/* velocity coefficients v_k (eq. evf3) from local (phi, chi), p orders */
+static void vel_coeffs(int p, const cplx *phi, const cplx *chi, cplx *vx, cplx *vy, cplx *vz)
+{
+    for (int n = 0; n < p; n++)
+        for (int m = -n; m <= n; m++) {
+            cplx pm1 = cget(phi, p, n + 1, m - 1), pp1 = cget(phi, p, n + 1, m + 1), p0 = cget(phi, p, n + 1, m);
+            cplx cm1 = cget(chi, p, n, m - 1), cp1 = cget(chi, p, n, m + 1), c0 = cget(chi, p, n, m);
+            vx[IDX(n, m)] = 0.5 * (I * pm1 + I * pp1 + (double)(n - m) * cp1 - (double)(n + m) * cm1);
+            vy[IDX(n, m)] = 0.5 * (pm1 - pp1 + I * (double)(n - m) * cp1 + I * (double)(n + m) * cm1);
+            vz[IDX(n, m)] = -p0 - I * (double)m * c0;
+        }
+}
+
+/* D_t in the R basis (eq. dt3): out_n^m = 1/2 (ty + i tx) in_{n+1}^{m-1}
+ *   - 1/2 (ty - i tx) in_{n+1}^{m+1} - tz in_{n+1}^m */
+static void apply_Dt_R(int p, const double t[3], const cplx *in, cplx *out)
+{
+    cplx sp = t[1] + I * t[0], sm = t[1] - I * t[0];
+    for (int n = 0; n < p; n++)
+        for (int m = -n; m <= n; m++)
+            out[IDX(n, m)] = 0.5 * sp * cget(in, p, n + 1, m - 1) - 0.5 * sm * cget(in, p, n + 1, m + 1) -
+                             t[2] * cget(in, p, n + 1, m);
+}
+
+/* Evaluate the local expansion (phi, chi) about 'centre' at the points x with
+ * strengths w: v (3), s (3), grad v (9, row = component, col = derivative),
+ * optional imaginary parts of v (3) and grad v (9) (they must vanish).  ADDED. */
+void lho_l2p(int p, const double centre[3], const cplx *phi, const cplx *chi, int64_t n, const double *x,
+             const double *w, double *v, double *s, double *gv, double *imv, double *imgv)
+{
+    size_t P2 = (size_t)p * p;
+    cplx *vk[3], *u[3][3];
+    for (int k = 0; k < 3; k++) {
+        vk[k] = (cplx *)malloc(sizeof(cplx) * P2);
+        for (int l = 0; l < 3; l++) u[l][k] = (cplx *)malloc(sizeof(cplx) * P2);
+    }
+    vel_coeffs(p, phi, chi, vk[0], vk[1], vk[2]);
+    /* u_lk = D_{e_l} v_k (eq. evf6) */
+    for (int l = 0; l < 3; l++) {
+        double e[3] = {0, 0, 0};
+        e[l] = 1.0;
+        for (int k = 0; k < 3; k++) apply_Dt_R(p, e, vk[k], u[l][k]);
+    }
+    cplx *R = (cplx *)malloc(sizeof(cplx) * P2);
+    for (int64_t j = 0; j < n; j++) {
+        double r[3] = {x[3 * j] - centre[0], x[3 * j + 1] - centre[1], x[3 * j + 2] - centre[2]};
+        lho_basis_R(p, r, R);
+        cplx V[3] = {0, 0, 0}, G[3][3] = {{0}};
+        for (size_t q = 0; q < P2; q++) {
+            for (int k = 0; k < 3; k++) {
+                V[k] += vk[k][q] * R[q];
+                for (int l = 0; l < 3; l++) G[k][l] += u[l][k][q] * R[q];
+            }
+        }
+        const double *wj = &w[3 * j];
+        for (int k = 0; k < 3; k++) {
+            v[3 * j + k] += creal(V[k]);
+            if (imv) imv[3 * j + k] += cimag(V[k]);
+            /* s_k = sum_l w_l u_lk (eq. evf6) */
+            s[3 * j + k] += wj[0] * creal(G[k][0]) + wj[1] * creal(G[k][1]) + wj[2] * creal(G[k][2]);
+            for (int l = 0; l < 3; l++) {
+                if (gv) gv[9 * j + 3 * k + l] += creal(G[k][l]);
+                if (imgv) imgv[9 * j + 3 * k + l] += cimag(G[k][l]);
+            }
+        }
+    }
+    free(R);
+    for (int k = 0; k < 3; k++) {
+        free(vk[k]);
+        for (int l = 0; l < 3; l++) free(u[l][k]);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* (A) direct sums                                                            */
+/* ------------------------------------------------------------------------- */
+
+/* mode 0: singular kernel everywhere; 1: smoothed everywhere;
+ * 2: split by the uniform octree of depth 'depth' on the cube [lo, lo+L]^3:
+ *    smoothed if the leaves of source and target are adjacent, else singular.
+ * Targets: ntarg indices into the n elements (all if targ == NULL).
+ * Outputs are indexed by target position in the list. */
+void lho_direct(int64_t n, const double *x, const double *w, double a, int mode, int depth,
+                const double lo[3], double L, int64_t ntarg, const int64_t *targ, double *v, double *s,
+                double *gv)
+{
+    uint32_t *lq = NULL;
+    if (mode == 2) {
+        double scale = (double)(1u << QBITS) / L;
+        lq = (uint32_t *)malloc(sizeof(uint32_t) * 3 * (size_t)n);
+        for (int64_t i = 0; i < n; i++)
+            for (int d = 0; d < 3; d++) lq[3 * i + d] = qcoord(x[3 * i + d], lo[d], scale) >> (QBITS - depth);
+    }
+    int64_t nt = targ ? ntarg : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t jj = 0; jj < nt; jj++) {
+        int64_t j = targ ? targ[jj] : jj;
+        double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gg[9] = {0};
+        for (int64_t i = 0; i < n; i++) {
+            if (i == j) continue;
+            int smooth = (mode == 1);
+            if (mode == 2) {
+                int adj = 1;
+                for (int d = 0; d < 3; d++) {
+                    int64_t dd = (int64_t)lq[3 * i + d] - (int64_t)lq[3 * j + d];
+                    if (dd < -1 || dd > 1) adj = 0;
+                }
+                smooth = adj;
+            }
+            pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, smooth, vv, ss, gv ? gg : NULL);
+        }
+        for (int k = 0; k < 3; k++) {
+            v[3 * jj + k] = vv[k];
+            s[3 * jj + k] = ss[k];
+        }
+        if (gv)
+            for (int k = 0; k < 9; k++) gv[9 * jj + k] = gg[k];
+    }
+    free(lq);
+}
+
+/* ------------------------------------------------------------------------- */
+/* (B) the FMM                                                                */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t n_m2l, n_m2m, n_l2l, n_p2p_pairs;
+} lho_stats;
+
+/* Visit the V-list (interaction list) of box (l, k): children of the parent's
+ * neighbours that are not adjacent to the box and are non-empty. */
+static int vlist(const otree *T, int l, uint64_t k, int64_t *out)
+{
+    int c[3];
+    box_coords(k, c);
+    int nside = 1 << l;
+    int cnt = 0;
+    int pc[3] = {c[0] >> 1, c[1] >> 1, c[2] >> 1};
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                int np[3] = {pc[0] + dx, pc[1] + dy, pc[2] + dz};
+                for (int ch = 0; ch < 8; ch++) {
+                    int cc[3] = {2 * np[0] + (ch & 1), 2 * np[1] + ((ch >> 1) & 1), 2 * np[2] + ((ch >> 2) & 1)};
+                    if (cc[0] < 0 || cc[1] < 0 || cc[2] < 0 || cc[0] >= nside || cc[1] >= nside || cc[2] >= nside)
+                        continue;
+                    if (abs(cc[0] - c[0]) <= 1 && abs(cc[1] - c[1]) <= 1 && abs(cc[2] - c[2]) <= 1) continue;
+                    int64_t b = tree_find(T, l, morton((uint32_t)cc[0], (uint32_t)cc[1], (uint32_t)cc[2]));
+                    if (b >= 0) out[cnt++] = b;
+                }
+            }
+    return cnt;
+}
+
+/* gather the elements of box (l, b) */
+static void box_points(const otree *T, const double *x, const double *w, int l, int64_t b, double *bx,
+                       double *bw)
+{
+    int64_t f = T->first[l][b], c = T->count[l][b];
+    for (int64_t i = 0; i < c; i++) {
+        int64_t e = T->order[f + i];
+        for (int d = 0; d < 3; d++) {
+            bx[3 * i + d] = x[3 * e + d];
+            bw[3 * i + d] = w[3 * e + d];
+        }
+    }
+}
+
+/* Full or leaf-sampled FMM evaluation of v and s (and optionally grad v).
+ *  what: bit 0 = far field (expansions), bit 1 = near field (direct, U-list).
+ *  sample: list of element indices; only the leaves holding them are
+ *          evaluated (their outputs written, others untouched); NULL = all.
+ *  p2m_method: 1 or 2.
+ * Returns 0 on success. */
+int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int depth, const double lo[3],
+            double L, int what, int p2m_method, int64_t nsample, const int64_t *sample, double *v,
+            double *s, double *gv, lho_stats *st)
+{
+    if (depth < 2 || depth > 10 || p < 1 || n < 1) return -1;
+    otree T;
+    tree_build(&T, n, x, depth, lo, L);
+    size_t P2 = (size_t)p * p;
+    int smooth = a > 0.0;
+    lho_stats stats = {0, 0, 0, 0};
+
+    /* which leaves to evaluate */
+    int64_t nleaf = T.nb[depth];
+    char *want = (char *)calloc((size_t)nleaf, 1);
+    if (!sample) {
+        memset(want, 1, (size_t)nleaf);
+    } else {
+        int sh = QBITS - depth;
+        for (int64_t i = 0; i < nsample; i++) {
+            int64_t e = sample[i];
+            uint64_t k = morton(T.q[3 * e] >> sh, T.q[3 * e + 1] >> sh, T.q[3 * e + 2] >> sh);
+            int64_t b = tree_find(&T, depth, k);
+            if (b >= 0) want[b] = 1;
+        }
+    }
+
+    if (what & 1) {
+        /* ---------- upward pass: P2M at leaves, M2M to level 2 ---------- */
+        cplx *M[MAXLEV + 1];
+        for (int l = 2; l <= depth; l++) M[l] = (cplx *)calloc((size_t)T.nb[l] * 2 * P2, sizeof(cplx));
+#pragma omp parallel
+        {
+            double *bx = NULL, *bw = NULL;
+            int64_t cap = 0;
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t b = 0; b < nleaf; b++) {
+                int64_t c = T.count[depth][b];
+                if (c > cap) {
+                    free(bx);
+                    free(bw);
+                    cap = c;
+                    bx = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                    bw = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                }
+                box_points(&T, x, w, depth, b, bx, bw);
+                double cen[3];
+                box_centre(&T, depth, T.key[depth][b], cen);
+                cplx *ph = &M[depth][(size_t)b * 2 * P2], *ch = ph + P2;
+                if (p2m_method == 1) lho_p2m_method1(p, cen, c, bx, bw, ph, ch);
+                else lho_p2m_method2(p, cen, c, bx, bw, ph, ch);
+            }
+            free(bx);
+            free(bw);
+        }
+        for (int l = depth - 1; l >= 2; l--) {
+            int sh = 3;
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int64_t b = 0; b < T.nb[l]; b++) {
+                double cp[3];
+                box_centre(&T, l, T.key[l][b], cp);
+                cplx *ph = &M[l][(size_t)b * 2 * P2], *ch = ph + P2;
+                for (int chn = 0; chn < 8; chn++) {
+                    int64_t cb = tree_find(&T, l + 1, (T.key[l][b] << sh) | (uint64_t)chn);
+                    if (cb < 0) continue;
+                    double cc[3];
+                    box_centre(&T, l + 1, T.key[l + 1][cb], cc);
+                    double t[3] = {cp[0] - cc[0], cp[1] - cc[1], cp[2] - cc[2]};
+                    const cplx *iph = &M[l + 1][(size_t)cb * 2 * P2];
+                    lho_m2m(p, t, iph, iph + P2, ph, ch);
+                }
+            }
+        }
+
+        /* ---------- downward pass ---------- */
+        if (!sample) {
+            cplx *Lc[MAXLEV + 1];
+            for (int l = 2; l <= depth; l++) Lc[l] = (cplx *)calloc((size_t)T.nb[l] * 2 * P2, sizeof(cplx));
+            int64_t nm2l = 0, nl2l = 0;
+            for (int l = 2; l <= depth; l++) {
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : nm2l, nl2l)
+                for (int64_t b = 0; b < T.nb[l]; b++) {
+                    double ct[3];
+                    box_centre(&T, l, T.key[l][b], ct);
+                    cplx *ph = &Lc[l][(size_t)b * 2 * P2], *ch = ph + P2;
+                    if (l > 2) {
+                        int64_t pb = tree_find(&T, l - 1, T.key[l][b] >> 3);
+                        double cp[3];
+                        box_centre(&T, l - 1, T.key[l - 1][pb], cp);
+                        double t[3] = {ct[0] - cp[0], ct[1] - cp[1], ct[2] - cp[2]};
+                        const cplx *iph = &Lc[l - 1][(size_t)pb * 2 * P2];
+                        lho_l2l(p, t, iph, iph + P2, ph, ch);
+                        nl2l++;
+                    }
+                    int64_t vl[189];
+                    int nv = vlist(&T, l, T.key[l][b], vl);
+                    for (int i = 0; i < nv; i++) {
+                        double cs[3];
+                        box_centre(&T, l, T.key[l][vl[i]], cs);
+                        double t[3] = {ct[0] - cs[0], ct[1] - cs[1], ct[2] - cs[2]};
+                        const cplx *iph = &M[l][(size_t)vl[i] * 2 * P2];
+                        lho_m2l(p, t, iph, iph + P2, ph, ch);
+                    }
+                    nm2l += nv;
+                }
+            }
+            stats.n_m2l = nm2l;
+            stats.n_l2l = nl2l;
+            /* L2P */
+#pragma omp parallel
+            {
+                double *bx = NULL, *bw = NULL, *bv = NULL, *bs = NULL, *bg = NULL;
+                int64_t cap = 0;
+#pragma omp for schedule(dynamic, 4)
+                for (int64_t b = 0; b < nleaf; b++) {
+                    if (!want[b]) continue;
+                    int64_t c = T.count[depth][b];
+                    if (c > cap) {
+                        free(bx); free(bw); free(bv); free(bs); free(bg);
+                        cap = c;
+                        bx = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bw = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bv = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bs = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bg = (double *)malloc(sizeof(double) * 9 * (size_t)cap);
+                    }
+                    box_points(&T, x, w, depth, b, bx, bw);
+                    memset(bv, 0, sizeof(double) * 3 * (size_t)c);
+                    memset(bs, 0, sizeof(double) * 3 * (size_t)c);
+                    memset(bg, 0, sizeof(double) * 9 * (size_t)c);
+                    double cen[3];
+                    box_centre(&T, depth, T.key[depth][b], cen);
+                    const cplx *ph = &Lc[depth][(size_t)b * 2 * P2];
+                    lho_l2p(p, cen, ph, ph + P2, c, bx, bw, bv, bs, bg, NULL, NULL);
+                    for (int64_t i = 0; i < c; i++) {
+                        int64_t e = T.order[T.first[depth][b] + i];
+                        for (int d = 0; d < 3; d++) {
+                            v[3 * e + d] += bv[3 * i + d];
+                            s[3 * e + d] += bs[3 * i + d];
+                        }
+                        if (gv)
+                            for (int d = 0; d < 9; d++) gv[9 * e + d] += bg[9 * i + d];
+                    }
+                }
+                free(bx); free(bw); free(bv); free(bs); free(bg);
+            }
+            for (int l = 2; l <= depth; l++) free(Lc[l]);
+        } else {
+            /* leaf-sampled: for each wanted leaf walk its ancestor chain */
+            int64_t nm2l = 0;
+#pragma omp parallel
+            {
+                cplx *chain = (cplx *)malloc(sizeof(cplx) * 2 * P2 * (size_t)(depth + 1));
+                double *bx = NULL, *bw = NULL, *bv = NULL, *bs = NULL, *bg = NULL;
+                int64_t cap = 0;
+#pragma omp for schedule(dynamic, 1) reduction(+ : nm2l)
+                for (int64_t b = 0; b < nleaf; b++) {
+                    if (!want[b]) continue;
+                    memset(chain, 0, sizeof(cplx) * 2 * P2 * (size_t)(depth + 1));
+                    uint64_t lk = T.key[depth][b];
+                    for (int l = 2; l <= depth; l++) {
+                        uint64_t k = lk >> (3 * (depth - l));
+                        double ct[3];
+                        box_centre(&T, l, k, ct);
+                        cplx *ph = &chain[(size_t)l * 2 * P2], *ch = ph + P2;
+                        if (l > 2) {
+                            double cp[3];
+                            box_centre(&T, l - 1, k >> 3, cp);
+                            double t[3] = {ct[0] - cp[0], ct[1] - cp[1], ct[2] - cp[2]};
+                            const cplx *iph = &chain[(size_t)(l - 1) * 2 * P2];
+                            lho_l2l(p, t, iph, iph + P2, ph, ch);
+                        }
+                        int64_t vl[189];
+                        int nv = vlist(&T, l, k, vl);
+                        for (int i = 0; i < nv; i++) {
+                            double cs[3];
+                            box_centre(&T, l, T.key[l][vl[i]], cs);
+                            double t[3] = {ct[0] - cs[0], ct[1] - cs[1], ct[2] - cs[2]};
+                            const cplx *iph = &M[l][(size_t)vl[i] * 2 * P2];
+                            lho_m2l(p, t, iph, iph + P2, ph, ch);
+                        }
+                        nm2l += nv;
+                    }
+                    int64_t c = T.count[depth][b];
+                    if (c > cap) {
+                        free(bx); free(bw); free(bv); free(bs); free(bg);
+                        cap = c;
+                        bx = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bw = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bv = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bs = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bg = (double *)malloc(sizeof(double) * 9 * (size_t)cap);
+                    }
+                    box_points(&T, x, w, depth, b, bx, bw);
+                    memset(bv, 0, sizeof(double) * 3 * (size_t)c);
+                    memset(bs, 0, sizeof(double) * 3 * (size_t)c);
+                    memset(bg, 0, sizeof(double) * 9 * (size_t)c);
+                    double cen[3];
+                    box_centre(&T, depth, lk, cen);
+                    const cplx *ph = &chain[(size_t)depth * 2 * P2];
+                    lho_l2p(p, cen, ph, ph + P2, c, bx, bw, bv, bs, bg, NULL, NULL);
+                    for (int64_t i = 0; i < c; i++) {
+                        int64_t e = T.order[T.first[depth][b] + i];
+                        for (int d = 0; d < 3; d++) {
+                            v[3 * e + d] += bv[3 * i + d];
+                            s[3 * e + d] += bs[3 * i + d];
+                        }
+                        if (gv)
+                            for (int d = 0; d < 9; d++) gv[9 * e + d] += bg[9 * i + d];
+                    }
+                }
+                free(chain);
+                free(bx); free(bw); free(bv); free(bs); free(bg);
+            }
+            stats.n_m2l = nm2l;
+        }
+        for (int l = 2; l <= depth; l++) free(M[l]);
+    }
+
+    if (what & 2) {
+        /* ---------- near field: adjacent leaves, smoothed kernel ---------- */
+        int64_t npairs = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : npairs)
+        for (int64_t b = 0; b < nleaf; b++) {
+            if (!want[b]) continue;
+            int c[3];
+            box_coords(T.key[depth][b], c);
+            int nside = 1 << depth;
+            int64_t nb_list[27];
+            int nn = 0;
+            for (int dz = -1; dz <= 1; dz++)
+                for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                        int cc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                        if (cc[0] < 0 || cc[1] < 0 || cc[2] < 0 || cc[0] >= nside || cc[1] >= nside ||
+                            cc[2] >= nside)
+                            continue;
+                        int64_t nbx = tree_find(&T, depth, morton((uint32_t)cc[0], (uint32_t)cc[1], (uint32_t)cc[2]));
+                        if (nbx >= 0) nb_list[nn++] = nbx;
+                    }
+            for (int64_t it = 0; it < T.count[depth][b]; it++) {
+                int64_t j = T.order[T.first[depth][b] + it];
+                double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gg[9] = {0};
+                for (int q = 0; q < nn; q++) {
+                    for (int64_t is = 0; is < T.count[depth][nb_list[q]]; is++) {
+                        int64_t i = T.order[T.first[depth][nb_list[q]] + is];
+                        if (i == j) continue;
+                        pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, smooth, vv, ss, gv ? gg : NULL);
+                        npairs++;
+                    }
+                }
+                for (int d = 0; d < 3; d++) {
+                    v[3 * j + d] += vv[d];
+                    s[3 * j + d] += ss[d];
+                }
+                if (gv)
+                    for (int d = 0; d < 9; d++) gv[9 * j + d] += gg[d];
+            }
+        }
+        stats.n_p2p_pairs = npairs;
+    }
+    if (st) *st = stats;
+    free(want);
+    tree_free(&T);
+    return 0;
+}
+
+/* number of OpenMP threads the oracle uses */
+int lho_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Tree summary for tests: per level the number of non-empty boxes, and the
+ * total number of V-list pairs (M2L translations) and U-list pairs. */
+int lho_tree_counts(int64_t n, const double *x, int depth, const double lo[3], double L, int64_t *nb,
+                    int64_t *n_m2l, int64_t *n_p2p)
+{
+    otree T;
+    tree_build(&T, n, x, depth, lo, L);
+    int64_t tot = 0, pp = 0;
+    for (int l = 0; l <= depth; l++) nb[l] = T.nb[l];
+    for (int l = 2; l <= depth; l++)
+        for (int64_t b = 0; b < T.nb[l]; b++) {
+            int64_t vl[189];
+            tot += vlist(&T, l, T.key[l][b], vl);
+        }
+    int nside = 1 << depth;
+    for (int64_t b = 0; b < T.nb[depth]; b++) {
+        int c[3];
+        box_coords(T.key[depth][b], c);
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    int cc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                    if (cc[0] < 0 || cc[1] < 0 || cc[2] < 0 || cc[0] >= nside || cc[1] >= nside || cc[2] >= nside)
+                        continue;
+                    int64_t nbx = tree_find(&T, depth, morton((uint32_t)cc[0], (uint32_t)cc[1], (uint32_t)cc[2]));
+                    if (nbx >= 0) pp += T.count[depth][b] * T.count[depth][nbx];
+                }
+    }
+    *n_m2l = tot;
+    *n_p2p = pp - n; /* self pairs excluded */
+    tree_free(&T);
+    return 0;
+}
