@@ -1,0 +1,127 @@
+/*
+ * lhfmm.h -- C ABI of the MI355X Lamb-Helmholtz vortex FMM library (liblhfmm.so).
+ *
+ * One call evaluates, for N vortex elements (x_i, omega_i), the Biot-Savart
+ * velocity v_j = sum_{i != j} K(r;a)/r^3 omega_i x r  (r = x_j - x_i, eq. 1 with
+ * the smoothing kernel of eq. 2 and the Gaussian core of eq. vem1) and the
+ * stretching term s_j = (omega_j . grad) v at x_j (eq. s1.1), by a fast
+ * multipole method that carries the far field in the two scalar potentials
+ * (phi, chi) of the Lamb-Helmholtz decomposition v = grad phi + curl(r chi)
+ * (eq. 4), translated by rotation / coaxial shift / back-rotation with the
+ * conversion operators of eq. rcr1 (Sec. 4.4).  The near field (elements in
+ * adjacent leaf boxes) is summed directly with the Gaussian core; the far
+ * field uses the singular kernel, as eq. 2 allows.  No 1/(4 pi) factor is
+ * applied (eq. 7 absorbs it into omega).
+ *
+ * Conventions shared by every entry point
+ *  - x, omega, v, s are DEVICE pointers to [N][3] row-major arrays of double
+ *    (LHF_FP64) or float (LHF_FP32); outputs are written in input order.
+ *  - Truncation number p keeps orders n = 0..p-1 (p^2 terms per potential,
+ *    Sec. 5.1).  FP64: 1 <= p <= 24.  FP32: 1 <= p <= 16.
+ *  - Octree: the cube [lo, lo+L]^3; element i has integer coordinates
+ *    q = min(floor((x-lo) * 2^21/L), 2^21-1) computed in FP64 (FP32 inputs
+ *    are promoted first); a level-l box is q >> (21-l).  Uniform depth d:
+ *    leaves are the non-empty level-d boxes; M2L runs on levels 2..d.
+ *  - Streams: all device work is enqueued on the caller's HIP stream.
+ *    lhf_plan_create synchronises that stream once (to read the tree sizes);
+ *    lhf_execute never synchronises and allocates nothing.
+ *  - Errors: a negative status means nothing was written; lhf_last_error()
+ *    returns a thread-local message.  Argument checks run on the host before
+ *    any launch.  A positive status is a warning with valid outputs.
+ *  - Ownership: the caller owns x, omega, v, s.  The plan owns its own device
+ *    buffers (sorted elements, tree, expansions, operator tables) and copies
+ *    what it needs from x, so x may be freed after lhf_plan_create.
+ */
+#ifndef LHFMM_H
+#define LHFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lhf_plan lhf_plan; /* opaque, owned by the library */
+
+typedef enum {
+    LHF_OK = 0,
+    LHF_WARN_CORE_SPLIT = 1,  /* 1 - K(r_far_min; a) > tol: the far field's singular kernel
+                                 differs from the smoothed one by more than tol */
+    LHF_ERR_ARG = -1,         /* invalid argument (N, p, a, depth, pointers, precision) */
+    LHF_ERR_DOMAIN = -2,      /* an element lies outside [lo, lo+L]^3 */
+    LHF_ERR_NONFINITE = -3,   /* non-finite coordinate */
+    LHF_ERR_HIP = -5,         /* a HIP runtime call failed */
+    LHF_ERR_UNSUPPORTED = -6, /* valid but not supported by this build */
+    LHF_ERR_STATE = -7        /* plan used inconsistently */
+} lhf_status;
+
+typedef enum { LHF_FP64 = 0, LHF_FP32 = 1 } lhf_precision;
+
+/* flags */
+#define LHF_SINGULAR 0x1u /* ignore a: singular kernel everywhere (a = 0 means the same) */
+
+typedef struct {
+    int32_t p;            /* truncation number, orders n = 0..p-1 (Sec. 5.1) */
+    double tol;           /* target accuracy; only used for the CORE_SPLIT warning */
+    int32_t depth;        /* uniform octree depth d, 2 <= d <= 10 */
+    int32_t reserved0;
+    double domain_lo[3];  /* cube origin */
+    double domain_len;    /* cube side; <= 0: bounding cube of the data, side*(1+2^-20) */
+    int32_t precision;    /* lhf_precision */
+    uint32_t flags;       /* LHF_SINGULAR */
+} lhf_desc;
+
+typedef struct {
+    int64_t n;                 /* elements */
+    int32_t depth, p;
+    int64_t boxes[11];         /* non-empty boxes per level 0..depth */
+    int64_t n_m2l;             /* multipole-to-local translations (V-list pairs) */
+    int64_t n_m2m, n_l2l;      /* child-parent translations */
+    int64_t n_p2p_pairs;       /* near-field pairs (ordered, self excluded) */
+    int32_t n_theta_classes;   /* distinct polar angles of the translation directions */
+    int32_t reserved1;
+} lhf_stats;
+
+/* Fill *d with the defaults: p = 12, tol = 1e-6, depth = 4, cube [0,1]^3, FP64. */
+void lhf_desc_default(lhf_desc *d);
+
+/* Build a plan for the elements at x (device, [n][3], dtype by d->precision),
+ * core radius a >= 0 (Gaussian core of eq. vem1; 0 = singular kernel).
+ * Sorts the elements along the Morton curve, builds the octree and its
+ * interaction lists, and computes the rotation / coaxial / conversion tables
+ * (FP64 on the device).  Synchronises 'stream' once.  Returns LHF_OK or
+ * LHF_WARN_CORE_SPLIT (plan valid) or a negative status (*out = NULL). */
+lhf_status lhf_plan_create(lhf_plan **out, const lhf_desc *d, int64_t n, const void *x, double a,
+                           void *stream);
+
+/* One FMM evaluation with strengths omega (device, [n][3]) for the plan's
+ * elements: writes v and s (device, [n][3], input order).  Enqueued on
+ * 'stream'; no host synchronisation, no allocation (graph-capturable). */
+lhf_status lhf_execute(lhf_plan *plan, const void *omega, void *v, void *s, void *stream);
+
+/* Same as lhf_execute, but writes only the near field (what = 2), only the far
+ * field (what = 1) or both (what = 3); for stage-level testing. */
+lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, int32_t what,
+                             void *stream);
+
+/* One-shot: plan_create + execute + destroy (synchronises the stream). */
+lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void *omega, double a,
+                        void *v, void *s, void *stream);
+
+/* Counts of the plan (boxes, translations, near-field pairs). */
+lhf_status lhf_plan_stats(const lhf_plan *plan, lhf_stats *out);
+
+/* Release the plan and its device memory (synchronises the plan's last stream). */
+lhf_status lhf_plan_destroy(lhf_plan *plan);
+
+/* Thread-local description of the last error (never NULL). */
+const char *lhf_last_error(void);
+
+/* Library version string. */
+const char *lhf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LHFMM_H */

@@ -1,0 +1,166 @@
+"""MI355X (gfx950) Lamb-Helmholtz vortex FMM: Python binding of liblhfmm.
+
+The binding only marshals arguments: every step of the evaluation runs in the
+HIP kernels of ``liblhfmm.so`` behind the C ABI declared in ``include/lhfmm.h``.
+PyTorch supplies device memory (tensors) and the current HIP stream.  There is
+no CPU fallback: if the library is missing, loading fails with an error.
+
+    plan = Plan(x, a=0.005, p=12, depth=6)          # x: [N,3] cuda tensor
+    v, s = plan.execute(omega)                      # omega: [N,3] cuda tensor
+    v, s = evaluate(x, omega, a, p=12, depth=6)     # one shot
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblhfmm.so")
+
+FP64, FP32 = 0, 1
+LHF_SINGULAR = 0x1
+STATUS = {0: "LHF_OK", 1: "LHF_WARN_CORE_SPLIT", -1: "LHF_ERR_ARG", -2: "LHF_ERR_DOMAIN",
+          -3: "LHF_ERR_NONFINITE", -5: "LHF_ERR_HIP", -6: "LHF_ERR_UNSUPPORTED", -7: "LHF_ERR_STATE"}
+
+#: every entry point declared in include/lhfmm.h
+EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_execute", "lhf_execute_parts", "lhf_evaluate",
+           "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version")
+
+
+class Desc(C.Structure):
+    _fields_ = [("p", C.c_int32), ("tol", C.c_double), ("depth", C.c_int32), ("reserved0", C.c_int32),
+                ("domain_lo", C.c_double * 3), ("domain_len", C.c_double), ("precision", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("depth", C.c_int32), ("p", C.c_int32), ("boxes", C.c_int64 * 11),
+                ("n_m2l", C.c_int64), ("n_m2m", C.c_int64), ("n_l2l", C.c_int64), ("n_p2p_pairs", C.c_int64),
+                ("n_theta_classes", C.c_int32), ("reserved1", C.c_int32)]
+
+
+class LhfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load liblhfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1201_5430_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.lhf_desc_default.argtypes = [C.POINTER(Desc)]
+        L.lhf_desc_default.restype = None
+        L.lhf_plan_create.argtypes = [C.POINTER(vp), C.POINTER(Desc), C.c_int64, vp, C.c_double, vp]
+        L.lhf_plan_create.restype = C.c_int
+        L.lhf_execute.argtypes = [vp, vp, vp, vp, vp]
+        L.lhf_execute.restype = C.c_int
+        L.lhf_execute_parts.argtypes = [vp, vp, vp, vp, C.c_int32, vp]
+        L.lhf_execute_parts.restype = C.c_int
+        L.lhf_evaluate.argtypes = [C.POINTER(Desc), C.c_int64, vp, vp, C.c_double, vp, vp, vp]
+        L.lhf_evaluate.restype = C.c_int
+        L.lhf_plan_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.lhf_plan_stats.restype = C.c_int
+        L.lhf_plan_destroy.argtypes = [vp]
+        L.lhf_plan_destroy.restype = C.c_int
+        L.lhf_last_error.restype = C.c_char_p
+        L.lhf_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status < 0:
+        raise LhfError(status, load().lhf_last_error().decode())
+    return status
+
+
+def make_desc(p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0):
+    d = Desc()
+    load().lhf_desc_default(C.byref(d))
+    d.p, d.depth, d.precision, d.tol, d.flags = int(p), int(depth), int(precision), float(tol), int(flags)
+    for k in range(3):
+        d.domain_lo[k] = float(lo[k])
+    d.domain_len = float(L)
+    return d
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_array(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a HIP device tensor")
+    if t.dtype != dtype or t.dim() != 2 or t.shape[1] != 3 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous [N,3] {dtype} tensor")
+    return t
+
+
+class Plan:
+    """An octree plan over fixed element positions (the paper's 'FMM set' stage)."""
+
+    def __init__(self, x, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0):
+        import torch
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        x = _dev_array(x, self.dtype, "x")
+        self.n = x.shape[0]
+        self.desc = make_desc(p, depth, precision, lo, L, tol, flags)
+        self._h = C.c_void_p()
+        self.status = _check(load().lhf_plan_create(C.byref(self._h), C.byref(self.desc), self.n,
+                                                    C.c_void_p(x.data_ptr()), float(a), _stream()))
+        self.warn_core_split = self.status == 1
+
+    def execute(self, omega, v=None, s=None, what=3):
+        import torch
+        omega = _dev_array(omega, self.dtype, "omega")
+        if omega.shape[0] != self.n:
+            raise ValueError("omega has a different number of elements than the plan")
+        if v is None:
+            v = torch.empty_like(omega)
+        if s is None:
+            s = torch.empty_like(omega)
+        _check(load().lhf_execute_parts(self._h, C.c_void_p(omega.data_ptr()), C.c_void_p(v.data_ptr()),
+                                        C.c_void_p(s.data_ptr()), int(what), _stream()))
+        return v, s
+
+    def stats(self):
+        st = Stats()
+        _check(load().lhf_plan_stats(self._h, C.byref(st)))
+        return dict(n=st.n, depth=st.depth, p=st.p, boxes=list(st.boxes[:st.depth + 1]), n_m2l=st.n_m2l,
+                    n_m2m=st.n_m2m, n_l2l=st.n_l2l, n_p2p_pairs=st.n_p2p_pairs,
+                    n_theta_classes=st.n_theta_classes)
+
+    def close(self):
+        if self._h:
+            _check(load().lhf_plan_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def evaluate(x, omega, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6):
+    """One-shot evaluation: (v, s) for elements x with strengths omega."""
+    import torch
+    dtype = torch.float64 if precision == FP64 else torch.float32
+    x = _dev_array(x, dtype, "x")
+    omega = _dev_array(omega, dtype, "omega")
+    v = torch.empty_like(omega)
+    s = torch.empty_like(omega)
+    d = make_desc(p, depth, precision, lo, L, tol)
+    _check(load().lhf_evaluate(C.byref(d), x.shape[0], C.c_void_p(x.data_ptr()), C.c_void_p(omega.data_ptr()),
+                               float(a), C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr()), _stream()))
+    return v, s

@@ -1,0 +1,786 @@
+// lhf_eval.hip -- the evaluation kernels of liblhfmm (one FMM pass).
+//
+//   P2M    multipole (phi, chi) of each leaf, Method 2 (eq. eve4)
+//   M2M    child -> parent, rotation / coaxial (S|S) / S-conversion (eq. rcr1) / back-rotation
+//   M2L    V-list source -> target, rotation / coaxial (S|R) / R-conversion / back-rotation;
+//          chi-hat is carried to order p before the conversion, then truncated
+//   L2L    parent -> child, rotation / coaxial (R|R) / R-conversion / back-rotation
+//   L2P    v (eq. evf3) and grad v (eq. dt3 with t = e_l, eq. evf6) at each element, s = (grad v) omega
+//   P2P    near field over adjacent leaves with the Gaussian core (eqs. 2, vem1)
+//
+// All expansions are in the scaled bar form documented in lhf_internal.h.
+// Work decomposition: one 64-lane wavefront per box (P2M, M2M, M2L, L2L,
+// L2P) and one lane per element (P2P).  A wavefront keeps the target box's
+// accumulator in registers (lane owns packed rows lane, lane+64, ...), and the
+// per-translation intermediate vectors in LDS.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "lhf_internal.h"
+
+namespace lhf {
+
+constexpr int WAVE = 64;
+constexpr int NRMAX = (2 * MAXP * MAXP + WAVE - 1) / WAVE;  // accumulator rows per lane
+
+__device__ inline void decode_row(int q, int &n, int &m, int &part)
+{
+    int nn = (int)sqrtf((float)q);
+    while (nn * nn > q) --nn;
+    while ((nn + 1) * (nn + 1) <= q) ++nn;
+    int j = q - nn * nn;
+    n = nn;
+    if (j <= nn) {
+        part = 0;
+        m = j;
+    } else {
+        part = 1;
+        m = j - nn;
+    }
+}
+
+template <typename T>
+__device__ inline void box_centre(uint64_t key, int level, double lo0, double lo1, double lo2, double L,
+                                  double &c0, double &c1, double &c2, double &h)
+{
+    uint32_t ix = 0, iy = 0, iz = 0;
+    for (int b = 0; b < level; b++) {
+        ix |= (uint32_t)((key >> (3 * b)) & 1u) << b;
+        iy |= (uint32_t)((key >> (3 * b + 1)) & 1u) << b;
+        iz |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
+    }
+    h = L / (double)(1u << level);
+    c0 = lo0 + ((double)ix + 0.5) * h;
+    c1 = lo1 + ((double)iy + 0.5) * h;
+    c2 = lo2 + ((double)iz + 0.5) * h;
+}
+
+// ---------------------------------------------------------------------------
+// P2M: one wavefront per leaf.  For each element, the lanes m < p build the
+// column m of Rt_n^m(xhat) (R_n^m = (-1)^n i^m Rt_n^m) by the recurrence
+//   Rt_m^m = -(x+iy)/(2m) Rt_{m-1}^{m-1},  Rt_{m+1}^m = z Rt_m^m,
+//   Rt_n^m = ((2n-1) z Rt_{n-1}^m - r^2 Rt_{n-2}^m) / ((n-m)(n+m)),
+// then every lane adds the eq. eve4 contributions of its packed rows.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off, const uint64_t *__restrict__ bkey,
+                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
+                                              const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
+                                              double lo0, double lo1, double lo2, double L, T *__restrict__ M)
+{
+    extern __shared__ char smem[];
+    T *Rre = (T *)smem;          // [p][p]  (n, m)
+    T *Rim = Rre + p * p;
+    const int lane = threadIdx.x;
+    const int64_t b = leaf_off + blockIdx.x;
+    double c0, c1, c2, hd;
+    box_centre<T>(bkey[b], depth, lo0, lo1, lo2, L, c0, c1, c2, hd);
+    const T h = (T)hd, ih = (T)(1.0 / hd);
+    const int P2 = p * p;
+    T acc[NRMAX];
+#pragma unroll
+    for (int k = 0; k < NRMAX; k++) acc[k] = 0;
+    const int s0 = bstart[b], cnt = bcount[b];
+    for (int e = 0; e < cnt; e++) {
+        const int i = s0 + e;
+        const T x = (xs[i] - (T)c0) * ih, y = (xs[n + i] - (T)c1) * ih, z = (xs[2 * n + i] - (T)c2) * ih;
+        const T wx = ws[i], wy = ws[n + i], wz = ws[2 * n + i];
+        __syncthreads();
+        if (lane < p) {
+            const int m = lane;
+            T r2 = x * x + y * y + z * z;
+            // Rt_m^m = (-(x+iy)/2)^m / m!
+            T are = 1, aim = 0;
+            for (int k = 1; k <= m; k++) {
+                T f = (T)(-0.5) / (T)k;
+                T nre = f * (are * x - aim * y), nim = f * (are * y + aim * x);
+                are = nre;
+                aim = nim;
+            }
+            T p2re = 0, p2im = 0, p1re = are, p1im = aim;
+            Rre[m * p + m] = are;
+            Rim[m * p + m] = aim;
+            for (int nn = m + 1; nn < p; nn++) {
+                T cre, cim;
+                if (nn == m + 1) {
+                    cre = z * p1re;
+                    cim = z * p1im;
+                } else {
+                    T inv = (T)1 / (T)((nn - m) * (nn + m));
+                    cre = ((T)(2 * nn - 1) * z * p1re - r2 * p2re) * inv;
+                    cim = ((T)(2 * nn - 1) * z * p1im - r2 * p2im) * inv;
+                }
+                Rre[nn * p + m] = cre;
+                Rim[nn * p + m] = cim;
+                p2re = p1re;
+                p2im = p1im;
+                p1re = cre;
+                p1im = cim;
+            }
+        }
+        __syncthreads();
+        // conj(Rt_n^k), with the convention conj(Rt_n^{-1}) = -Rt_n^1 that makes the m >= 1
+        // formulas valid at m = 0 as well
+        auto C = [&](int nn, int k, T &re, T &im) {
+            if (nn < 0 || k > nn) {
+                re = 0;
+                im = 0;
+            } else if (k == -1) {
+                if (nn >= 1) {
+                    re = -Rre[nn * p + 1];
+                    im = -Rim[nn * p + 1];
+                } else {
+                    re = 0;
+                    im = 0;
+                }
+            } else {
+                re = Rre[nn * p + k];
+                im = -Rim[nn * p + k];
+            }
+        };
+        const T wmre = wx, wmim = -wy;  // wx - i wy
+        const T wpre = wx, wpim = wy;   // wx + i wy
+#pragma unroll
+        for (int k = 0; k < NRMAX; k++) {
+            const int r = lane + WAVE * k;
+            if (r >= 2 * P2) break;
+            const int pot = r >= P2;
+            int nn, m, part;
+            decode_row(r - pot * P2, nn, m, part);
+            T vre, vim;
+            const T sgn = (m & 1) ? (T)-1 : (T)1;
+            if (pot == 0) {
+                // a = -i (-1)^m / (n+1) [ (wx-iwy)(n-m+1)/2 C(m-1) + (wx+iwy)(n+m+1)/2 C(m+1) + wz m C(m) ]
+                T c1re, c1im, c2re, c2im, c3re, c3im;
+                C(nn, m - 1, c1re, c1im);
+                C(nn, m + 1, c2re, c2im);
+                C(nn, m, c3re, c3im);
+                T f1 = (T)(nn - m + 1) * (T)0.5, f2 = (T)(nn + m + 1) * (T)0.5, f3 = wz * (T)m;
+                T sre = f1 * (wmre * c1re - wmim * c1im) + f2 * (wpre * c2re - wpim * c2im) + f3 * c3re;
+                T sim = f1 * (wmre * c1im + wmim * c1re) + f2 * (wpre * c2im + wpim * c2re) + f3 * c3im;
+                T sc = sgn / (T)(nn + 1);
+                vre = sc * sim;   // -i (sre + i sim) = sim - i sre
+                vim = -sc * sre;
+            } else {
+                if (nn == 0) {
+                    vre = 0;
+                    vim = 0;
+                } else {
+                    // b = (-1)^m / n [ -1/2 (wx-iwy) C'(m-1) + 1/2 (wx+iwy) C'(m+1) + wz C'(m) ]
+                    T c1re, c1im, c2re, c2im, c3re, c3im;
+                    C(nn - 1, m - 1, c1re, c1im);
+                    C(nn - 1, m + 1, c2re, c2im);
+                    C(nn - 1, m, c3re, c3im);
+                    T sre = (T)-0.5 * (wmre * c1re - wmim * c1im) + (T)0.5 * (wpre * c2re - wpim * c2im) + wz * c3re;
+                    T sim = (T)-0.5 * (wmre * c1im + wmim * c1re) + (T)0.5 * (wpre * c2im + wpim * c2re) + wz * c3im;
+                    T sc = sgn / (T)nn;
+                    vre = sc * sre;
+                    vim = sc * sim;
+                }
+            }
+            acc[k] += part ? vim : vre;
+        }
+    }
+    T *out = M + (size_t)b * 2 * P2;
+#pragma unroll
+    for (int k = 0; k < NRMAX; k++) {
+        const int r = lane + WAVE * k;
+        if (r >= 2 * P2) break;
+        out[r] = acc[k] * ih;
+    }
+    (void)h;
+}
+
+// ---------------------------------------------------------------------------
+// Rotation / coaxial / conversion / back-rotation of one expansion by one
+// wavefront.  KIND: 0 = M2M, 1 = M2L, 2 = L2L.
+//   src    : 2 p^2 input reals (global memory)
+//   X, Y   : LDS, 2 p^2 each;  Z : LDS, 2 (p+1)^2
+//   Wf, Wb : forward / backward rotation sets of the direction's polar-angle class
+//   zc, zs : cos(m phi), sin(m phi) of the direction, m < p
+//   cf     : coaxial coefficients (M2L: k!/tau^(k+1), k <= 2p;  M2M/L2L: (-tau_p)^k/k!)
+//   tau    : |t| / h used by the conversion (M2L: |t|/h, M2M: |t|/h_parent, L2L: |t|/h_child)
+// The result is added into the lane's accumulator rows.
+// ---------------------------------------------------------------------------
+template <typename T, int KIND>
+__device__ __attribute__((always_inline)) void rcr(int p, const T *__restrict__ src, T *X, T *Y, T *Z, const T *__restrict__ Wf,
+                    const T *__restrict__ Wb, const T *__restrict__ zc, const T *__restrict__ zs,
+                    const T *cf, T tau, T *acc)
+{
+    const int lane = threadIdx.x;
+    const int P2 = p * p, R2 = 2 * P2;
+    const int ZS = (p + 1) * (p + 1);
+    // 1. load and rotate about z by +phi: c^m <- e^{i m phi} c^m
+    for (int r = lane; r < R2; r += WAVE) {
+        const int pot = r >= P2;
+        int n, m, part;
+        decode_row(r - pot * P2, n, m, part);
+        const T *s = src + pot * P2;
+        if (m == 0) {
+            X[r] = s[pk_re(n, 0)];
+        } else {
+            T re = s[pk_re(n, m)], im = s[pk_im(n, m)];
+            T c = zc[m], sn = zs[m];
+            X[r] = part ? (re * sn + im * c) : (re * c - im * sn);
+        }
+    }
+    __syncthreads();
+    // 2. rotation about y (real, Re and Im blocks)
+    for (int r = lane; r < R2; r += WAVE) {
+        const int pot = r >= P2;
+        int n, m, part;
+        decode_row(r - pot * P2, n, m, part);
+        const T *W = Wf + rot_block_off(n);
+        const T *x = X + pot * P2 + n * n;
+        T a = 0;
+        if (!part) {
+            const T *row = W + m * (n + 1);
+            for (int k = 0; k <= n; k++) a += row[k] * x[k];
+        } else {
+            const T *row = W + (n + 1) * (n + 1) + (m - 1) * n;
+            for (int k = 0; k < n; k++) a += row[k] * x[n + 1 + k];
+        }
+        Y[r] = a;
+    }
+    __syncthreads();
+    // 3. coaxial translation along z (per m, per part)
+    for (int r = lane; r < 2 * ZS; r += WAVE) {
+        const int pot = r >= ZS;
+        int n, m, part;
+        decode_row(r - pot * ZS, n, m, part);
+        T a = 0;
+        if (KIND == 1) {
+            // (S|R): out_n = sum_{n'=m}^{p-1} (n+n')!/tau^(n+n'+1) in_n'; chi to order p
+            if (m < p && (n < p || pot == 1)) {
+                const T *y = Y + pot * P2;
+                for (int n2 = m; n2 < p; n2++) a += cf[n + n2] * y[n2 * n2 + m + (part ? n2 : 0)];
+            }
+        } else if (KIND == 0) {
+            // (S|S): out_n = sum_{n'=m}^{n} (-tau_p)^(n-n')/(n-n')! 2^-(n'+1) [phi] / 2^-n' [chi] in_n'
+            if (n < p) {
+                const T *y = Y + pot * P2;
+                T sc = pot ? (T)1 : (T)0.5;
+                for (int k = 0; k < m; k++) sc *= (T)0.5;
+                for (int n2 = m; n2 <= n; n2++) {
+                    a += cf[n - n2] * sc * y[n2 * n2 + m + (part ? n2 : 0)];
+                    sc *= (T)0.5;
+                }
+            }
+        } else {
+            // (R|R): out_n = 2^-n [phi] / 2^-(n+1) [chi] * sum_{n'=n}^{p-1} (-tau_p)^(n'-n)/(n'-n)! in_n'
+            if (n < p) {
+                const T *y = Y + pot * P2;
+                for (int n2 = n; n2 < p; n2++) a += cf[n2 - n] * y[n2 * n2 + m + (part ? n2 : 0)];
+                T sc = pot ? (T)0.5 : (T)1;
+                for (int k = 0; k < n; k++) sc *= (T)0.5;
+                a *= sc;
+            }
+        }
+        Z[r] = a;
+    }
+    __syncthreads();
+    // 4. conversion in the rotated frame (eq. rcr1, scaled)
+    for (int r = lane; r < R2; r += WAVE) {
+        const int pot = r >= P2;
+        int n, m, part;
+        decode_row(r - pot * P2, n, m, part);
+        const T *Zp = Z, *Zc = Z + ZS;
+        T out;
+        if (KIND == 0) {
+            // S-conversion: a~ = a - i tau m/(n+1) b ;  b~_n = b_n + tau/n b_{n-1}
+            if (pot == 0) {
+                T f = tau * (T)m / (T)(n + 1);
+                if (!part) out = Zp[pk_re(n, m)] + (m ? f * Zc[pk_im(n, m)] : (T)0);
+                else out = Zp[pk_im(n, m)] - f * Zc[pk_re(n, m)];
+            } else {
+                out = Zc[n * n + m + (part ? n : 0)];
+                if (n >= 1 && m <= n - 1) out += tau / (T)n * Zc[(n - 1) * (n - 1) + m + (part ? n - 1 : 0)];
+            }
+        } else {
+            // R-conversion: c~ = c + i tau m/n d ;  d~_n = d_n - tau/(n+1) d_{n+1}
+            if (pot == 0) {
+                T f = n > 0 ? tau * (T)m / (T)n : (T)0;
+                if (!part) out = Zp[pk_re(n, m)] - (m ? f * Zc[pk_im(n, m)] : (T)0);
+                else out = Zp[pk_im(n, m)] + f * Zc[pk_re(n, m)];
+            } else {
+                out = Zc[n * n + m + (part ? n : 0)];
+                const int n1 = n + 1;
+                if (KIND == 1 || n1 < p) out -= tau / (T)(n + 1) * Zc[n1 * n1 + m + (part ? n1 : 0)];
+            }
+        }
+        X[r] = out;
+    }
+    __syncthreads();
+    // 5. back-rotation about y
+    for (int r = lane; r < R2; r += WAVE) {
+        const int pot = r >= P2;
+        int n, m, part;
+        decode_row(r - pot * P2, n, m, part);
+        const T *W = Wb + rot_block_off(n);
+        const T *x = X + pot * P2 + n * n;
+        T a = 0;
+        if (!part) {
+            const T *row = W + m * (n + 1);
+            for (int k = 0; k <= n; k++) a += row[k] * x[k];
+        } else {
+            const T *row = W + (n + 1) * (n + 1) + (m - 1) * n;
+            for (int k = 0; k < n; k++) a += row[k] * x[n + 1 + k];
+        }
+        Y[r] = a;
+    }
+    __syncthreads();
+    // 6. rotate about z by -phi and accumulate
+#pragma unroll
+    for (int k = 0; k < NRMAX; k++) {
+        const int r = lane + WAVE * k;
+        if (r >= R2) break;
+        const int pot = r >= P2;
+        int n, m, part;
+        decode_row(r - pot * P2, n, m, part);
+        const T *y = Y + pot * P2;
+        if (m == 0) {
+            acc[k] += y[pk_re(n, 0)];
+        } else {
+            T re = y[pk_re(n, m)], im = y[pk_im(n, m)];
+            T c = zc[m], sn = zs[m];
+            acc[k] += part ? (-re * sn + im * c) : (re * c + im * sn);
+        }
+    }
+    __syncthreads();
+}
+
+struct EvalArgs {
+    int p, depth;
+    int64_t n;
+    double lo0, lo1, lo2, L;
+};
+
+// M2M for one level: wavefront per parent box
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_m2m(int p, int64_t off, const int32_t *__restrict__ bchild0,
+                                              const int32_t *__restrict__ bnchild, const uint64_t *__restrict__ bkey,
+                                              T *__restrict__ M, const T *__restrict__ rot, const T *__restrict__ zph,
+                                              const int16_t *__restrict__ dir_theta)
+{
+    extern __shared__ char smem[];
+    const int P2 = p * p, ZS = (p + 1) * (p + 1);
+    T *X = (T *)smem, *Y = X + 2 * P2, *Z = Y + 2 * P2, *cf = Z + 2 * ZS;
+    const int lane = threadIdx.x;
+    const int64_t b = off + blockIdx.x;
+    if (lane < p) {
+        // (-tau_p)^k / k!, tau_p = sqrt(3)/4
+        double t = 1.0, tp = -0.4330127018922193;
+        for (int k = 1; k <= lane; k++) t *= tp / (double)k;
+        cf[lane] = (T)t;
+    }
+    __syncthreads();
+    T acc[NRMAX];
+#pragma unroll
+    for (int k = 0; k < NRMAX; k++) acc[k] = 0;
+    const int rs = rot_set_size(p);
+    const int c0 = bchild0[b], nc = bnchild[b];
+    for (int c = 0; c < nc; c++) {
+        const int cb = c0 + c;
+        const int oct = (int)(bkey[cb] & 7u);
+        const int dir = NDIR_M2L + oct;  // t = parent - child
+        const T *R = rot + (size_t)dir_theta[dir] * ROT_NKIND * rs;
+        const T *zp = zph + (size_t)dir * 2 * p;
+        rcr<T, 0>(p, M + (size_t)cb * 2 * P2, X, Y, Z, R + ROT_S_FWD * rs, R + ROT_S_BACK * rs, zp, zp + p, cf,
+                  (T)0.4330127018922193, acc);
+    }
+    T *out = M + (size_t)b * 2 * P2;
+#pragma unroll
+    for (int k = 0; k < NRMAX; k++) {
+        const int r = lane + WAVE * k;
+        if (r >= 2 * P2) break;
+        out[r] = acc[k];
+    }
+}
+
+// Downward pass for one level: L2L from the parent (levels > 2) + M2L over the V-list
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_down(int p, int level, int64_t off, const int32_t *__restrict__ bparent,
+                                               const uint64_t *__restrict__ bkey, const int32_t *__restrict__ vcount,
+                                               const int32_t *__restrict__ vsrc, const int16_t *__restrict__ vdir,
+                                               const T *__restrict__ M, T *__restrict__ Lc, const T *__restrict__ rot,
+                                               const T *__restrict__ zph, const int16_t *__restrict__ dir_theta,
+                                               const T *__restrict__ coax)
+{
+    extern __shared__ char smem[];
+    const int P2 = p * p, ZS = (p + 1) * (p + 1);
+    T *X = (T *)smem, *Y = X + 2 * P2, *Z = Y + 2 * P2, *cf = Z + 2 * ZS;
+    const int lane = threadIdx.x;
+    const int64_t b = off + blockIdx.x;
+    const int rs = rot_set_size(p);
+    T acc[NRMAX];
+#pragma unroll
+    for (int k = 0; k < NRMAX; k++) acc[k] = 0;
+    if (level > 2) {
+        if (lane < p) {
+            double t = 1.0, tp = -0.4330127018922193;
+            for (int k = 1; k <= lane; k++) t *= tp / (double)k;
+            cf[lane] = (T)t;
+        }
+        __syncthreads();
+        const int oct = (int)(bkey[b] & 7u);
+        const int dir = NDIR_M2L + 8 + oct;  // t = child - parent
+        const T *R = rot + (size_t)dir_theta[dir] * ROT_NKIND * rs;
+        const T *zp = zph + (size_t)dir * 2 * p;
+        rcr<T, 2>(p, Lc + (size_t)bparent[b] * 2 * P2, X, Y, Z, R + ROT_R_FWD * rs, R + ROT_R_BACK * rs, zp,
+                  zp + p, cf, (T)0.8660254037844386, acc);
+    }
+    const int nv = vcount[b];
+    for (int j = 0; j < nv; j++) {
+        const int src = vsrc[(size_t)b * VMAX + j];
+        const int dir = vdir[(size_t)b * VMAX + j];
+        const int dx = dir % 7 - 3, dy = (dir / 7) % 7 - 3, dz = dir / 49 - 3;
+        const int d2 = dx * dx + dy * dy + dz * dz;
+        const T *R = rot + (size_t)dir_theta[dir] * ROT_NKIND * rs;
+        const T *zp = zph + (size_t)dir * 2 * p;
+        rcr<T, 1>(p, M + (size_t)src * 2 * P2, X, Y, Z, R + ROT_S_FWD * rs, R + ROT_R_BACK * rs, zp, zp + p,
+                  coax + (size_t)d2 * (2 * p + 2), (T)sqrt((double)d2), acc);
+    }
+    T *out = Lc + (size_t)b * 2 * P2;
+#pragma unroll
+    for (int k = 0; k < NRMAX; k++) {
+        const int r = lane + WAVE * k;
+        if (r >= 2 * P2) break;
+        out[r] = acc[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// L2P: one wavefront per leaf.  The velocity coefficients (eq. evf3, bar form)
+//   Vx = 1/2 [-P_{n+1}^{m-1} + P_{n+1}^{m+1} - i(n-m) X_n^{m+1} - i(n+m) X_n^{m-1}]
+//   Vy = 1/2 [ i P_{n+1}^{m-1} + i P_{n+1}^{m+1} + (n-m) X_n^{m+1} - (n+m) X_n^{m-1}]
+//   Vz = -P_{n+1}^m - i m X_n^m
+// (P = phi, X = chi of the leaf's local expansion, c^{-1} := -conj(c^1)) are
+// formed in LDS; the derivatives u_lk = D_{e_l} v_k (eq. dt3) are applied on
+// the fly:  u_x = 1/2(-V^{m-1} + V^{m+1}),  u_y = i/2 (V^{m-1} + V^{m+1}),
+// u_z = -V^m (all at order n+1).  Each lane evaluates one element:
+//   F(xhat) = sum_n (-1)^n [F_n^0 Rt_n^0 + 2 Re sum_{m>0} F_n^m Rt_n^m].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off, const uint64_t *__restrict__ bkey,
+                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
+                                              const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
+                                              double lo0, double lo1, double lo2, double L, const T *__restrict__ Lc,
+                                              T *__restrict__ vfar)
+{
+    extern __shared__ char smem[];
+    const int P2 = p * p;
+    const int TRI = p * (p + 1) / 2;  // (n, m >= 0) pairs, n < p
+    T *cd = (T *)smem;                // 2 P2 local coefficients
+    T *Vre = cd + 2 * P2, *Vim = Vre + 3 * TRI;  // [3][TRI]
+    const int lane = threadIdx.x;
+    const int64_t b = leaf_off + blockIdx.x;
+    const T *src = Lc + (size_t)b * 2 * P2;
+    for (int r = lane; r < 2 * P2; r += WAVE) cd[r] = src[r];
+    __syncthreads();
+    auto get = [&](int pot, int nn, int m, T &re, T &im) {
+        if (nn < 0 || nn >= p) {
+            re = 0;
+            im = 0;
+            return;
+        }
+        const T *c = cd + pot * P2;
+        if (m == -1) {
+            if (nn >= 1) {
+                re = -c[pk_re(nn, 1)];
+                im = c[pk_im(nn, 1)];
+            } else {
+                re = 0;
+                im = 0;
+            }
+        } else if (m > nn) {
+            re = 0;
+            im = 0;
+        } else {
+            re = c[pk_re(nn, m)];
+            im = m ? c[pk_im(nn, m)] : (T)0;
+        }
+    };
+    for (int t = lane; t < TRI; t += WAVE) {
+        int nn = 0;
+        while ((nn + 1) * (nn + 2) / 2 <= t) nn++;
+        const int m = t - nn * (nn + 1) / 2;
+        T pm1r, pm1i, pp1r, pp1i, p0r, p0i, xm1r, xm1i, xp1r, xp1i, x0r, x0i;
+        get(0, nn + 1, m - 1, pm1r, pm1i);
+        get(0, nn + 1, m + 1, pp1r, pp1i);
+        get(0, nn + 1, m, p0r, p0i);
+        get(1, nn, m - 1, xm1r, xm1i);
+        get(1, nn, m + 1, xp1r, xp1i);
+        get(1, nn, m, x0r, x0i);
+        const T a = (T)(nn - m), c = (T)(nn + m);
+        // Vx = 1/2[-Pm1 + Pp1 - i a Xp1 - i c Xm1]
+        Vre[t] = (T)0.5 * (-pm1r + pp1r + a * xp1i + c * xm1i);
+        Vim[t] = (T)0.5 * (-pm1i + pp1i - a * xp1r - c * xm1r);
+        // Vy = 1/2[i Pm1 + i Pp1 + a Xp1 - c Xm1]
+        Vre[TRI + t] = (T)0.5 * (-pm1i - pp1i + a * xp1r - c * xm1r);
+        Vim[TRI + t] = (T)0.5 * (pm1r + pp1r + a * xp1i - c * xm1i);
+        // Vz = -P0 - i m X0
+        Vre[2 * TRI + t] = -p0r + (T)m * x0i;
+        Vim[2 * TRI + t] = -p0i - (T)m * x0r;
+    }
+    __syncthreads();
+    double c0, c1, c2, hd;
+    box_centre<T>(bkey[b], depth, lo0, lo1, lo2, L, c0, c1, c2, hd);
+    const T ih = (T)(1.0 / hd);
+    const int s0 = bstart[b], cnt = bcount[b];
+    auto vget = [&](int k, int nn, int m, T &re, T &im) {
+        if (nn >= p || nn < 0) {
+            re = 0;
+            im = 0;
+            return;
+        }
+        if (m == -1) {
+            if (nn >= 1) {
+                const int t = nn * (nn + 1) / 2 + 1;
+                re = -Vre[k * TRI + t];
+                im = Vim[k * TRI + t];
+            } else {
+                re = 0;
+                im = 0;
+            }
+            return;
+        }
+        if (m > nn) {
+            re = 0;
+            im = 0;
+            return;
+        }
+        const int t = nn * (nn + 1) / 2 + m;
+        re = Vre[k * TRI + t];
+        im = Vim[k * TRI + t];
+    };
+    for (int e0 = 0; e0 < cnt; e0 += WAVE) {
+        const int e = e0 + lane;
+        const bool act = e < cnt;
+        const int i = s0 + (act ? e : 0);
+        const T x = (xs[i] - (T)c0) * ih, y = (xs[n + i] - (T)c1) * ih, z = (xs[2 * n + i] - (T)c2) * ih;
+        const T r2 = x * x + y * y + z * z;
+        T v[3] = {0, 0, 0}, g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        // walk the columns m; Rt_m^m by recurrence, then up in n
+        T mre = 1, mim = 0;
+        for (int m = 0; m < p; m++) {
+            if (m > 0) {
+                T f = (T)(-0.5) / (T)m;
+                T nre = f * (mre * x - mim * y), nim = f * (mre * y + mim * x);
+                mre = nre;
+                mim = nim;
+            }
+            T p1re = mre, p1im = mim, p2re = 0, p2im = 0;
+            const T wgt = m ? (T)2 : (T)1;
+            for (int nn = m; nn < p; nn++) {
+                T rre, rim;
+                if (nn == m) {
+                    rre = mre;
+                    rim = mim;
+                } else if (nn == m + 1) {
+                    rre = z * p1re;
+                    rim = z * p1im;
+                } else {
+                    T inv = (T)1 / (T)((nn - m) * (nn + m));
+                    rre = ((T)(2 * nn - 1) * z * p1re - r2 * p2re) * inv;
+                    rim = ((T)(2 * nn - 1) * z * p1im - r2 * p2im) * inv;
+                }
+                if (nn > m) {
+                    p2re = p1re;
+                    p2im = p1im;
+                    p1re = rre;
+                    p1im = rim;
+                }
+                const T sw = ((nn & 1) ? -wgt : wgt);
+                // velocity
+                for (int k = 0; k < 3; k++) {
+                    T fr, fi;
+                    vget(k, nn, m, fr, fi);
+                    v[k] += sw * (fr * rre - fi * rim);
+                    // gradient: u_x, u_y, u_z of v_k at (nn, m) from V_k at nn+1
+                    T ar, ai, br, bi, cr, ci;
+                    vget(k, nn + 1, m - 1, ar, ai);
+                    vget(k, nn + 1, m + 1, br, bi);
+                    vget(k, nn + 1, m, cr, ci);
+                    T uxr = (T)0.5 * (br - ar), uxi = (T)0.5 * (bi - ai);
+                    T uyr = (T)-0.5 * (ai + bi), uyi = (T)0.5 * (ar + br);
+                    T uzr = -cr, uzi = -ci;
+                    g[3 * k + 0] += sw * (uxr * rre - uxi * rim);
+                    g[3 * k + 1] += sw * (uyr * rre - uyi * rim);
+                    g[3 * k + 2] += sw * (uzr * rre - uzi * rim);
+                }
+            }
+        }
+        if (act) {
+            const T wx = ws[i], wy = ws[n + i], wz = ws[2 * n + i];
+            const T ih2 = ih * ih;
+            for (int k = 0; k < 3; k++) {
+                vfar[k * n + i] = v[k] * ih;
+                vfar[(3 + k) * n + i] = (g[3 * k] * wx + g[3 * k + 1] * wy + g[3 * k + 2] * wz) * ih2;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P2P near field + combination + un-permutation: one lane per sorted element.
+// f = K/r^3, g = f'/r with the Gaussian core of eq. vem1; for u = r^2/(2a^2)
+// below 0.02 the Taylor series
+//   f = sqrt(2/pi)/a^3 sum_k (-u)^k/(k!(2k+3)),  g = sqrt(2/pi)/a^5 sum_{k>=1} (-1)^k u^(k-1)/((k-1)!(2k+3))
+// replaces the closed form (which cancels there).
+//   v += f (w_i x r),  s += f (w_i x w_j) + g (w_j . r)(w_i x r)
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void kernel_fg(T r2, T a, int smooth, T &f, T &g)
+{
+    if (!smooth) {
+        T ir = (T)1 / sqrt(r2);
+        T ir2 = ir * ir;
+        f = ir2 * ir;
+        g = (T)-3 * f * ir2;
+        return;
+    }
+    const T c = (T)0.79788456080286535588;  // sqrt(2/pi)
+    const T ia2 = (T)1 / (a * a);
+    const T u = (T)0.5 * r2 * ia2;
+    const T ia3 = ia2 / a;
+    if (u < (T)0.02) {
+        T fs = 0, gs = 0, term = 1, t2 = -1;
+        for (int k = 0; k < 12; k++) {
+            fs += term / (T)(2 * k + 3);
+            term *= -u / (T)(k + 1);
+        }
+        for (int k = 1; k < 13; k++) {
+            gs += t2 / (T)(2 * k + 3);
+            t2 *= -u / (T)k;
+        }
+        f = c * ia3 * fs;
+        g = c * ia3 * ia2 * gs;
+    } else {
+        T r = sqrt(r2);
+        T ir = (T)1 / r;
+        T ex = exp(-u);
+        T K = erf(r * (T)0.70710678118654752440 / a) - c * r / a * ex;
+        T ir2 = ir * ir;
+        f = K * ir2 * ir;
+        g = c * ex * ia3 * ir2 - (T)3 * f * ir2;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth_leaf_off_dummy, int64_t leaf_off,
+                                             const int32_t *__restrict__ eleaf, const int32_t *__restrict__ ulist,
+                                             const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
+                                             const T *__restrict__ xs, const T *__restrict__ ws, T a, int smooth,
+                                             int what, const T *__restrict__ vfar, const int32_t *__restrict__ perm,
+                                             T *__restrict__ vout, T *__restrict__ sout)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T v0 = 0, v1 = 0, v2 = 0, s0 = 0, s1 = 0, s2 = 0;
+    const T xj = xs[i], yj = xs[n + i], zj = xs[2 * n + i];
+    const T wjx = ws[i], wjy = ws[n + i], wjz = ws[2 * n + i];
+    if (what & 2) {
+        const int lf = eleaf[i];
+        const int32_t *U = ulist + (size_t)(lf - leaf_off) * 27;
+        for (int q = 0; q < 27; q++) {
+            const int nb = U[q];
+            if (nb < 0) continue;
+            const int st = bstart[nb], ct = bcount[nb];
+            for (int e = 0; e < ct; e++) {
+                const int k = st + e;
+                if (k == i) continue;
+                const T rx = xj - xs[k], ry = yj - xs[n + k], rz = zj - xs[2 * n + k];
+                const T r2 = rx * rx + ry * ry + rz * rz;
+                if (r2 == (T)0 && !smooth) continue;
+                T f, g;
+                kernel_fg<T>(r2, a, smooth, f, g);
+                const T wix = ws[k], wiy = ws[n + k], wiz = ws[2 * n + k];
+                const T cx = wiy * rz - wiz * ry, cy = wiz * rx - wix * rz, cz = wix * ry - wiy * rx;
+                const T dd = g * (wjx * rx + wjy * ry + wjz * rz);
+                v0 += f * cx;
+                v1 += f * cy;
+                v2 += f * cz;
+                s0 += f * (wiy * wjz - wiz * wjy) + dd * cx;
+                s1 += f * (wiz * wjx - wix * wjz) + dd * cy;
+                s2 += f * (wix * wjy - wiy * wjx) + dd * cz;
+            }
+        }
+    }
+    if (what & 1) {
+        v0 += vfar[i];
+        v1 += vfar[n + i];
+        v2 += vfar[2 * n + i];
+        s0 += vfar[3 * n + i];
+        s1 += vfar[4 * n + i];
+        s2 += vfar[5 * n + i];
+    }
+    const int64_t o = perm[i];
+    vout[3 * o] = v0;
+    vout[3 * o + 1] = v1;
+    vout[3 * o + 2] = v2;
+    sout[3 * o] = s0;
+    sout[3 * o + 1] = s1;
+    sout[3 * o + 2] = s2;
+}
+
+// gather omega into the sorted SoA layout
+template <typename T>
+__global__ void k_gather_w(int64_t n, const T *__restrict__ w, const int32_t *__restrict__ perm, T *__restrict__ ws)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i];
+    ws[i] = w[3 * o];
+    ws[n + i] = w[3 * o + 1];
+    ws[2 * n + i] = w[3 * o + 2];
+}
+
+template <typename T>
+static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st)
+{
+    const int p = P->p, d = P->depth;
+    const int64_t n = P->n;
+    const int P2 = p * p, ZS = (p + 1) * (p + 1);
+    T *xs = (T *)P->xs, *ws = (T *)P->ws, *M = (T *)P->M, *Lc = (T *)P->Lc, *vfar = (T *)P->vfar;
+    const T *rot = (const T *)P->rot, *zph = (const T *)P->zph, *coax = (const T *)P->coax;
+    const int tpb = 256;
+    const unsigned nblk = (unsigned)((n + tpb - 1) / tpb);
+    hipLaunchKernelGGL(k_gather_w<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)omega, P->perm, ws);
+    const int64_t loff = P->lev[d].off, nleaf = P->lev[d].nb;
+    if (what & 1) {
+        size_t sh_p2m = sizeof(T) * 2 * P2;
+        hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_p2m, st, p, d, loff, P->bkey, P->bstart,
+                           P->bcount, (const T *)xs, (const T *)ws, n, P->lo[0], P->lo[1], P->lo[2], P->L, M);
+        size_t sh_rcr = sizeof(T) * (4 * P2 + 2 * ZS + 2 * p + 2);
+        for (int l = d - 1; l >= 2; l--) {
+            if (P->lev[l].nb == 0) continue;
+            hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, P->lev[l].off,
+                               P->bchild0, P->bnchild, P->bkey, M, rot, zph, P->dir_theta);
+        }
+        for (int l = 2; l <= d; l++) {
+            if (P->lev[l].nb == 0) continue;
+            hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l,
+                               P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M, Lc,
+                               rot, zph, P->dir_theta, coax);
+        }
+        const int TRI = p * (p + 1) / 2;
+        size_t sh_l2p = sizeof(T) * (2 * P2 + 6 * TRI);
+        hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_l2p, st, p, d, loff, P->bkey, P->bstart,
+                           P->bcount, (const T *)xs, (const T *)ws, n, P->lo[0], P->lo[1], P->lo[2], P->L,
+                           (const T *)Lc, vfar);
+    }
+    const int smooth = P->a > 0.0 && !(P->desc.flags & LHF_SINGULAR);
+    hipLaunchKernelGGL(k_p2p<T>, dim3(nblk), dim3(tpb), 0, st, n, 0, loff, P->eleaf, P->ulist, P->bstart, P->bcount,
+                       (const T *)xs, (const T *)ws, (T)P->a, smooth, what, (const T *)vfar, P->perm, (T *)v,
+                       (T *)s);
+    LHF_HIP(hipGetLastError());
+    return LHF_OK;
+}
+
+lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st)
+{
+    if (P->precision == LHF_FP64) return execute_t<double>(P, omega, v, s, what, st);
+    return execute_t<float>(P, omega, v, s, what, st);
+}
+
+}  // namespace lhf

@@ -1,0 +1,109 @@
+// lhf_internal.h -- internal definitions of liblhfmm (HIP, gfx950).
+//
+// Coefficient representation used by every device kernel ("scaled bar form"):
+// for a box of side h and a real harmonic function with coefficients c_n^m of
+// the paper's basis (eq. rsbf2), only m >= 0 is stored (c_n^{-m} =
+// (-1)^m conj(c_n^m) for real functions) and the stored value is i^m c_n^m,
+// scaled per order so that values stay O(1) for every level and fit FP32:
+//   multipole (S basis):  a = i^m phi_n^m / h^(n+1),   b = i^m chi_n^m / h^n
+//   local     (R basis):  c = i^m phi_n^m * h^n,        d = i^m chi_n^m * h^(n+1)
+// With the i^m factor, rotations about the y axis have REAL matrices and act on
+// the real parts and the imaginary parts separately.  Packed layout of one
+// potential: the block of order n starts at n*n and holds
+//   [Re m=0, Re m=1, .., Re m=n, Im m=1, .., Im m=n]   (2n+1 reals),
+// p^2 reals per potential, two potentials (phi, chi) per box.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lhfmm.h"
+
+namespace lhf {
+
+constexpr int QBITS = 21;
+constexpr int MAXP = 24;
+constexpr int MAXDEPTH = 10;
+constexpr int NDIR_M2L = 343;    // codes (dx+3) + 7 (dy+3) + 49 (dz+3), dx..dz in [-3,3]
+constexpr int NDIR = NDIR_M2L + 16;  // + 8 child->parent and 8 parent->child directions
+constexpr int VMAX = 189;        // interaction-list bound per box (6^3 - 3^3)
+
+// packed index of (n, m) real part / imaginary part (m >= 1)
+__host__ __device__ inline int pk_re(int n, int m) { return n * n + m; }
+__host__ __device__ inline int pk_im(int n, int m) { return n * n + n + m; }
+
+// size of one rotation-matrix set (all orders n < p, Re and Im blocks)
+__host__ __device__ inline int rot_set_size(int p) { return p * (2 * p * p + 1) / 3; }
+// offset of order n's blocks inside a set
+__host__ __device__ inline int rot_block_off(int n) { return n * (2 * n * n + 1) / 3; }
+
+// rotation kinds stored per polar-angle class
+enum RotKind { ROT_S_FWD = 0, ROT_R_FWD = 1, ROT_S_BACK = 2, ROT_R_BACK = 3, ROT_NKIND = 4 };
+
+struct TreeLevel {
+    int64_t nb = 0;         // non-empty boxes at this level
+    int64_t off = 0;        // global box index of the first box of the level
+};
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace lhf
+
+// The plan (opaque to callers).
+struct lhf_plan {
+    lhf_desc desc;
+    int64_t n = 0;
+    int p = 0, depth = 0;
+    int precision = 0;      // LHF_FP64 / LHF_FP32
+    size_t tsize = 8;       // bytes per real
+    double a = 0.0;
+    double lo[3] = {0, 0, 0};
+    double L = 1.0;
+    hipStream_t stream = nullptr;
+
+    lhf::TreeLevel lev[lhf::MAXDEPTH + 1];
+    int64_t nbox = 0;       // all levels
+    int64_t n_m2l = 0, n_p2p = 0;
+    int n_theta = 0;
+
+    // device buffers
+    int32_t *perm = nullptr;     // sorted position -> input index
+    void *xs = nullptr;          // sorted coordinates, SoA [3][n], T
+    void *ws = nullptr;          // sorted strengths, SoA [3][n], T (filled by execute)
+    void *vfar = nullptr;        // far-field v, s in sorted order, SoA [6][n], T
+    uint64_t *bkey = nullptr;    // [nbox] Morton key of every box (level-local)
+    int32_t *bstart = nullptr;   // [nbox] first sorted element
+    int32_t *bcount = nullptr;   // [nbox] number of elements
+    int32_t *bparent = nullptr;  // [nbox] global index of the parent (-1 at level 0)
+    int32_t *bchild0 = nullptr;  // [nbox] global index of the first child (-1 if leaf)
+    int32_t *bnchild = nullptr;  // [nbox] number of children
+    int32_t *vcount = nullptr;   // [nbox] V-list length
+    int32_t *vsrc = nullptr;     // [nbox][189] V-list source boxes (global index)
+    int16_t *vdir = nullptr;     // [nbox][189] direction code of t = c_target - c_source
+    int32_t *ulist = nullptr;    // [nleaf][27] adjacent leaves (global index, -1 = none)
+    int32_t *eleaf = nullptr;    // [n] leaf (global index) of each sorted element
+    void *M = nullptr;           // multipoles [nbox][2][p^2], T
+    void *Lc = nullptr;          // locals     [nbox][2][p^2], T
+    void *rot = nullptr;         // rotation sets [n_theta][4][rot_set_size(p)], T
+    void *zph = nullptr;         // z phases [NDIR][2][p] (cos m phi, sin m phi), T
+    int16_t *dir_theta = nullptr;   // [NDIR] polar-angle class of every direction
+    void *coax = nullptr;        // M2L coaxial Hankel vectors [28][2p+2], T, indexed by |d|^2
+    int32_t *dflag = nullptr;    // device status flags
+    double *dtmp = nullptr;
+};
+
+namespace lhf {
+void set_error(const std::string &msg);
+lhf_status hip_fail(hipError_t e, const char *what);
+}  // namespace lhf
+
+#define LHF_HIP(call)                                                  \
+    do {                                                               \
+        hipError_t _e = (call);                                        \
+        if (_e != hipSuccess) return lhf::hip_fail(_e, #call);         \
+    } while (0)

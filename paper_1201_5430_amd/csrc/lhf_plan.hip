@@ -1,0 +1,810 @@
+// lhf_plan.hip -- plan construction and the C ABI of liblhfmm.
+//
+// Plan = the paper's "FMM set" stage (Sec. 4, table of modifications: data
+// structure and translation precomputation, unchanged from the scalar FMM):
+//   1. integer coordinates and Morton keys (FP64), stable radix sort
+//   2. non-empty boxes of every level, parent / child links
+//   3. interaction lists: V (M2L, children of the parent's neighbours that are
+//      not adjacent, <= 189 per box) and U (adjacent leaves, near field)
+//   4. operator tables in FP64 on the device: rotation matrices per polar
+//      angle class, z phases per direction, coaxial M2L coefficients
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+#include <math.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "lhf_internal.h"
+
+namespace lhf {
+
+lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st);
+
+static thread_local std::string g_err = "no error";
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+lhf_status hip_fail(hipError_t e, const char *what)
+{
+    set_error(std::string("HIP error ") + hipGetErrorString(e) + " in " + what);
+    return LHF_ERR_HIP;
+}
+
+static lhf_status arg_error(const std::string &msg)
+{
+    set_error(msg);
+    return LHF_ERR_ARG;
+}
+
+// ---------------------------------------------------------------------------
+// tree kernels
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+__device__ inline uint32_t compact3(uint64_t x)
+{
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+
+// flags: [0] = element outside the cube, [1] = non-finite coordinate
+template <typename T>
+__global__ void k_keys(int64_t n, const T *__restrict__ x, double lo0, double lo1, double lo2, double scale,
+                       int depth, uint64_t *__restrict__ key, int32_t *__restrict__ idx, int32_t *__restrict__ flags)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double lo[3] = {lo0, lo1, lo2};
+    uint32_t q[3];
+    const double qmax = (double)((1u << QBITS) - 1u);
+    for (int d = 0; d < 3; d++) {
+        const double xv = (double)x[3 * i + d];
+        if (!isfinite(xv)) {
+            atomicOr(&flags[1], 1);
+            q[d] = 0;
+            continue;
+        }
+        const double t = (xv - lo[d]) * scale;  // one rounding each: no contraction possible
+        if (t < 0.0 || t > (double)(1u << QBITS)) atomicOr(&flags[0], 1);
+        double f = floor(t);
+        f = fmin(fmax(f, 0.0), qmax);
+        q[d] = (uint32_t)f;
+    }
+    const int sh = QBITS - depth;
+    key[i] = spread3(q[0] >> sh) | (spread3(q[1] >> sh) << 1) | (spread3(q[2] >> sh) << 2);
+    idx[i] = (int32_t)i;
+}
+
+template <typename T>
+__global__ void k_gather_x(int64_t n, const T *__restrict__ x, const int32_t *__restrict__ perm, T *__restrict__ xs)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i];
+    xs[i] = x[3 * o];
+    xs[n + i] = x[3 * o + 1];
+    xs[2 * n + i] = x[3 * o + 2];
+}
+
+__global__ void k_level_flags(int64_t n, const uint64_t *__restrict__ skey, int sh, int32_t *__restrict__ flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flag[i] = (i == 0 || (skey[i] >> sh) != (skey[i - 1] >> sh)) ? 1 : 0;
+}
+
+// id: inclusive scan of flags (1-based box id per element)
+__global__ void k_level_fill(int64_t n, const uint64_t *__restrict__ skey, int sh, const int32_t *__restrict__ flag,
+                             const int32_t *__restrict__ id, uint64_t *__restrict__ key, int32_t *__restrict__ start,
+                             int32_t *__restrict__ eleaf, int64_t *__restrict__ nb_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int b = id[i] - 1;
+    if (flag[i]) {
+        key[b] = skey[i] >> sh;
+        start[b] = (int32_t)i;
+    }
+    if (eleaf) eleaf[i] = b;
+    if (i == n - 1) *nb_out = id[i];
+}
+
+__global__ void k_counts(int64_t nb, int64_t n, const int32_t *__restrict__ start, int32_t *__restrict__ count)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    count[b] = (int32_t)((b + 1 < nb ? (int64_t)start[b + 1] : n) - start[b]);
+}
+
+__device__ inline int64_t lower_bound_u64(const uint64_t *a, int64_t len, uint64_t k)
+{
+    int64_t lo = 0, hi = len;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+__device__ inline int64_t find_u64(const uint64_t *a, int64_t len, uint64_t k)
+{
+    int64_t i = lower_bound_u64(a, len, k);
+    return (i < len && a[i] == k) ? i : -1;
+}
+
+struct LevelTab {
+    int64_t off[MAXDEPTH + 2];
+    int64_t nb[MAXDEPTH + 2];
+};
+
+// parent / children links for all boxes
+__global__ void k_links(int64_t nbox, int depth, LevelTab lt, const uint64_t *__restrict__ bkey,
+                        int32_t *__restrict__ parent, int32_t *__restrict__ child0, int32_t *__restrict__ nchild)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    int l = 0;
+    while (l < depth && b >= lt.off[l + 1]) l++;
+    const uint64_t k = bkey[b];
+    if (l == 0) parent[b] = -1;
+    else parent[b] = (int32_t)(lt.off[l - 1] + find_u64(bkey + lt.off[l - 1], lt.nb[l - 1], k >> 3));
+    if (l == depth) {
+        child0[b] = -1;
+        nchild[b] = 0;
+    } else {
+        const uint64_t *ck = bkey + lt.off[l + 1];
+        int64_t f = lower_bound_u64(ck, lt.nb[l + 1], k << 3);
+        int64_t e = lower_bound_u64(ck, lt.nb[l + 1], (k << 3) + 8);
+        child0[b] = (int32_t)(lt.off[l + 1] + f);
+        nchild[b] = (int32_t)(e - f);
+    }
+}
+
+// V-list of every box at levels >= 2 (fixed stride VMAX)
+__global__ void k_vlist(int64_t off, int64_t nb, int level, const uint64_t *__restrict__ bkey,
+                        int32_t *__restrict__ vcount, int32_t *__restrict__ vsrc, int16_t *__restrict__ vdir)
+{
+    const int64_t bl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bl >= nb) return;
+    const int64_t b = off + bl;
+    const uint64_t k = bkey[b];
+    const int ix = (int)compact3(k), iy = (int)compact3(k >> 1), iz = (int)compact3(k >> 2);
+    const int px = ix >> 1, py = iy >> 1, pz = iz >> 1;
+    const int side = 1 << level;
+    const uint64_t *lk = bkey + off;
+    int cnt = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++)
+                for (int c = 0; c < 8; c++) {
+                    const int cx = 2 * (px + dx) + (c & 1), cy = 2 * (py + dy) + ((c >> 1) & 1),
+                              cz = 2 * (pz + dz) + ((c >> 2) & 1);
+                    if (cx < 0 || cy < 0 || cz < 0 || cx >= side || cy >= side || cz >= side) continue;
+                    const int ex = ix - cx, ey = iy - cy, ez = iz - cz;
+                    if (abs(ex) <= 1 && abs(ey) <= 1 && abs(ez) <= 1) continue;
+                    const uint64_t ck = spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) | (spread3((uint32_t)cz) << 2);
+                    const int64_t j = find_u64(lk, nb, ck);
+                    if (j < 0) continue;
+                    vsrc[b * VMAX + cnt] = (int32_t)(off + j);
+                    vdir[b * VMAX + cnt] = (int16_t)((ex + 3) + 7 * (ey + 3) + 49 * (ez + 3));  // t = c_T - c_S
+                    cnt++;
+                }
+    vcount[b] = cnt;
+}
+
+// U-list (adjacent leaves incl. self) of every leaf, 27 slots
+__global__ void k_ulist(int64_t off, int64_t nb, int level, const uint64_t *__restrict__ bkey,
+                        const int32_t *__restrict__ bcount, int32_t *__restrict__ ulist, int64_t *__restrict__ npairs)
+{
+    const int64_t bl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bl >= nb) return;
+    const uint64_t k = bkey[off + bl];
+    const int ix = (int)compact3(k), iy = (int)compact3(k >> 1), iz = (int)compact3(k >> 2);
+    const int side = 1 << level;
+    const uint64_t *lk = bkey + off;
+    int q = 0;
+    int64_t src = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                const int cx = ix + dx, cy = iy + dy, cz = iz + dz;
+                int32_t val = -1;
+                if (cx >= 0 && cy >= 0 && cz >= 0 && cx < side && cy < side && cz < side) {
+                    const uint64_t ck = spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) | (spread3((uint32_t)cz) << 2);
+                    const int64_t j = find_u64(lk, nb, ck);
+                    if (j >= 0) {
+                        val = (int32_t)(off + j);
+                        src += bcount[off + j];
+                    }
+                }
+                ulist[bl * 27 + q++] = val;
+            }
+    const int64_t me = bcount[off + bl];
+    atomicAdd((unsigned long long *)npairs, (unsigned long long)(me * src - me));
+}
+
+__global__ void k_sum_i32(int64_t n, const int32_t *__restrict__ a, int64_t *__restrict__ out)
+{
+    __shared__ int64_t sh[256];
+    int64_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += a[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd((unsigned long long *)out, (unsigned long long)sh[0]);
+}
+
+__global__ void k_add_i32(int64_t n, int32_t *__restrict__ a, int32_t add)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += add;
+}
+
+// ---------------------------------------------------------------------------
+// operator tables (FP64 arithmetic on the device)
+// ---------------------------------------------------------------------------
+
+// Rotation about the y axis by theta.  In the orthonormal basis
+// Yh_n^m = sqrt((n-|m|)!/(n+|m|)!) P_n^|m| e^{i m phi}, F(R_y(theta) r) = exp(-theta G) F
+// with G the matrix of D_{r x e_y} (eq. drt4 with t = e_y, rescaled): a real
+// skew-symmetric tridiagonal matrix.  U = exp(-theta G) is computed by a
+// Taylor series on theta/2^s followed by s squarings.  The forward / backward
+// matrices of the scaled bar coefficients follow by diagonal rescaling:
+//   R basis: Hb_mm' = U_mm' N_m'/N_m,   S basis: Hb_mm' = (-1)^(m+m') U_mm' N_m/N_m',
+// N_m = sqrt((n-|m|)!(n+|m|)!), and U(-theta) = U(theta)^T.  They are stored
+// split into the block acting on real parts and the block acting on imaginary parts:
+//   Re: W_m'm = Hb_0m' (m=0),  Hb_mm' + Hb_-m,m' (m>0);   Im: W_m'm = Hb_mm' - Hb_-m,m'.
+__device__ inline double gen_entry(int n, int m, int mp)
+{
+    // G[m][mp], nonzero for mp = m +- 1
+    if (mp == m - 1) {
+        if (m >= 1) return 0.5 * sqrt((double)(n + m) * (double)(n - m + 1));
+        if (m == 0) return -0.5 * sqrt((double)n * (double)(n + 1));
+        return -0.5 * sqrt((double)(n - m + 1) * (double)(n + m));
+    }
+    if (mp == m + 1) {
+        if (m >= 1) return -0.5 * sqrt((double)(n - m) * (double)(n + m + 1));
+        if (m == 0) return -0.5 * sqrt((double)n * (double)(n + 1));
+        return 0.5 * sqrt((double)(n + m + 1) * (double)(n - m));
+    }
+    return 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_rot(int p, const double *__restrict__ theta, T *__restrict__ out)
+{
+    extern __shared__ double sd[];
+    const int cls = blockIdx.x, n = blockIdx.y;
+    const int D = 2 * n + 1, DD = D * D;
+    double *E = sd, *Tm = E + DD, *Tmp = Tm + DD;
+    double *fct = Tmp + DD;  // factorials 0..2n
+    const int tid = threadIdx.x;
+    const double th = theta[cls];
+    for (int i = tid; i <= 2 * n; i += blockDim.x) {
+        double f = 1.0;
+        for (int k = 2; k <= i; k++) f *= (double)k;
+        fct[i] = f;
+    }
+    // scaling: |theta| (n+1) / 2^s <= 1
+    int s = 0;
+    double sc = fabs(th) * (double)(n + 1);
+    while (sc > 1.0) {
+        sc *= 0.5;
+        s++;
+    }
+    const double alpha = -th / (double)(1ull << s);  // A = alpha G
+    for (int idx = tid; idx < DD; idx += blockDim.x) {
+        const int i = idx / D, j = idx % D;
+        E[idx] = (i == j) ? 1.0 : 0.0;
+        Tm[idx] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int k = 1; k <= 30; k++) {
+        // Tmp = Tm * A / k  (A tridiagonal, zero diagonal)
+        for (int idx = tid; idx < DD; idx += blockDim.x) {
+            const int i = idx / D, j = idx % D;
+            const int mj = j - n;
+            double acc = 0.0;
+            if (j - 1 >= 0) acc += Tm[i * D + j - 1] * alpha * gen_entry(n, mj - 1, mj);
+            if (j + 1 < D) acc += Tm[i * D + j + 1] * alpha * gen_entry(n, mj + 1, mj);
+            Tmp[idx] = acc / (double)k;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < DD; idx += blockDim.x) {
+            Tm[idx] = Tmp[idx];
+            E[idx] += Tmp[idx];
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < s; q++) {
+        for (int idx = tid; idx < DD; idx += blockDim.x) {
+            const int i = idx / D, j = idx % D;
+            double acc = 0.0;
+            for (int k = 0; k < D; k++) acc += E[i * D + k] * E[k * D + j];
+            Tmp[idx] = acc;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < DD; idx += blockDim.x) E[idx] = Tmp[idx];
+        __syncthreads();
+    }
+    // E = U(theta), indices (m+n, m'+n)
+    const int RS = rot_set_size(p);
+    const int boff = rot_block_off(n);
+    auto Nm = [&](int m) { return sqrt(fct[n - abs(m)] * fct[n + abs(m)]); };
+    for (int kind = 0; kind < ROT_NKIND; kind++) {
+        T *W = out + ((size_t)cls * ROT_NKIND + kind) * RS + boff;
+        const bool back = (kind == ROT_S_BACK || kind == ROT_R_BACK);
+        const bool sbasis = (kind == ROT_S_FWD || kind == ROT_S_BACK);
+        auto Hb = [&](int m, int mp) {
+            const double u = back ? E[(mp + n) * D + (m + n)] : E[(m + n) * D + (mp + n)];
+            if (sbasis) return (((m + mp) & 1) ? -1.0 : 1.0) * u * Nm(m) / Nm(mp);
+            return u * Nm(mp) / Nm(m);
+        };
+        for (int idx = tid; idx < (n + 1) * (n + 1) + n * n; idx += blockDim.x) {
+            double val;
+            if (idx < (n + 1) * (n + 1)) {
+                const int mp = idx / (n + 1), m = idx % (n + 1);
+                val = (m == 0) ? Hb(0, mp) : Hb(m, mp) + Hb(-m, mp);
+            } else {
+                const int j = idx - (n + 1) * (n + 1);
+                const int mp = j / n + 1, m = j % n + 1;
+                val = Hb(m, mp) - Hb(-m, mp);
+            }
+            W[idx] = (T)val;
+        }
+    }
+}
+
+__device__ inline void dir_vector(int dir, int &dx, int &dy, int &dz)
+{
+    if (dir < NDIR_M2L) {
+        dx = dir % 7 - 3;
+        dy = (dir / 7) % 7 - 3;
+        dz = dir / 49 - 3;
+    } else {
+        const int oct = (dir - NDIR_M2L) & 7;
+        const int bx = oct & 1, by = (oct >> 1) & 1, bz = (oct >> 2) & 1;
+        const int sg = (dir - NDIR_M2L) < 8 ? 1 : -1;  // child->parent: (1-2b); parent->child: -(1-2b)
+        dx = sg * (1 - 2 * bx);
+        dy = sg * (1 - 2 * by);
+        dz = sg * (1 - 2 * bz);
+    }
+}
+
+template <typename T>
+__global__ void k_zph(int p, T *__restrict__ zph)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NDIR * p) return;
+    const int dir = i / p, m = i % p;
+    int dx, dy, dz;
+    dir_vector(dir, dx, dy, dz);
+    const double ph = (dx == 0 && dy == 0) ? 0.0 : atan2((double)dy, (double)dx);
+    double sn, cs;
+    sincos((double)m * ph, &sn, &cs);
+    zph[(size_t)dir * 2 * p + m] = (T)cs;
+    zph[(size_t)dir * 2 * p + p + m] = (T)sn;
+}
+
+// M2L coaxial (S|R) Hankel vector per squared offset length: k!/tau^(k+1), tau = |d| (units of h)
+template <typename T>
+__global__ void k_coax(int p, T *__restrict__ coax)
+{
+    const int d2 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d2 >= 28) return;
+    const int len = 2 * p + 2;
+    if (d2 == 0) {
+        for (int k = 0; k < len; k++) coax[k] = (T)0;
+        return;
+    }
+    const double tau = sqrt((double)d2);
+    double c = 1.0 / tau;
+    for (int k = 0; k < len; k++) {
+        coax[d2 * len + k] = (T)c;
+        c *= (double)(k + 1) / tau;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int64_t igcd(int64_t a, int64_t b)
+{
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// polar-angle classes of all directions: two integer vectors share a class iff
+// dz1/|d1| = dz2/|d2| (compared exactly on sign(dz) and the reduced fraction dz^2/|d|^2)
+static void theta_classes(std::vector<int16_t> &cls, std::vector<double> &theta)
+{
+    std::map<std::pair<int, std::pair<int64_t, int64_t>>, int> ids;
+    cls.assign(NDIR, 0);
+    theta.clear();
+    for (int dir = 0; dir < NDIR; dir++) {
+        int dx, dy, dz;
+        if (dir < NDIR_M2L) {
+            dx = dir % 7 - 3;
+            dy = (dir / 7) % 7 - 3;
+            dz = dir / 49 - 3;
+        } else {
+            const int oct = (dir - NDIR_M2L) & 7;
+            const int sg = (dir - NDIR_M2L) < 8 ? 1 : -1;
+            dx = sg * (1 - 2 * (oct & 1));
+            dy = sg * (1 - 2 * ((oct >> 1) & 1));
+            dz = sg * (1 - 2 * ((oct >> 2) & 1));
+        }
+        const int64_t n2 = (int64_t)dx * dx + (int64_t)dy * dy + (int64_t)dz * dz;
+        if (n2 == 0) {
+            cls[dir] = 0;
+            continue;
+        }
+        int64_t num = (int64_t)dz * dz, den = n2;
+        int64_t g = igcd(num, den);
+        if (g) {
+            num /= g;
+            den /= g;
+        }
+        const int sgn = dz > 0 ? 1 : (dz < 0 ? -1 : 0);
+        auto key = std::make_pair(sgn, std::make_pair(num, den));
+        auto it = ids.find(key);
+        if (it == ids.end()) {
+            int id = (int)theta.size();
+            ids[key] = id;
+            theta.push_back(acos((double)dz / sqrt((double)n2)));
+            cls[dir] = (int16_t)id;
+        } else {
+            cls[dir] = (int16_t)it->second;
+        }
+    }
+}
+
+template <typename T>
+static lhf_status build_tables(lhf_plan *P, hipStream_t st)
+{
+    std::vector<int16_t> cls;
+    std::vector<double> theta;
+    theta_classes(cls, theta);
+    P->n_theta = (int)theta.size();
+    const int p = P->p;
+    const size_t RS = rot_set_size(p);
+    LHF_HIP(hipMalloc(&P->rot, sizeof(T) * RS * ROT_NKIND * theta.size()));
+    LHF_HIP(hipMalloc(&P->zph, sizeof(T) * NDIR * 2 * p));
+    LHF_HIP(hipMalloc(&P->coax, sizeof(T) * 28 * (2 * p + 2)));
+    LHF_HIP(hipMalloc(&P->dir_theta, sizeof(int16_t) * NDIR));
+    LHF_HIP(hipMalloc(&P->dtmp, sizeof(double) * theta.size()));
+    LHF_HIP(hipMemcpyAsync(P->dir_theta, cls.data(), sizeof(int16_t) * NDIR, hipMemcpyHostToDevice, st));
+    LHF_HIP(hipMemcpyAsync(P->dtmp, theta.data(), sizeof(double) * theta.size(), hipMemcpyHostToDevice, st));
+    const int Dmax = 2 * p - 1;
+    size_t shm = sizeof(double) * (3 * (size_t)Dmax * Dmax + 2 * p);
+    hipLaunchKernelGGL(k_rot<T>, dim3((unsigned)theta.size(), (unsigned)p), dim3(256), shm, st, p, P->dtmp,
+                       (T *)P->rot);
+    hipLaunchKernelGGL(k_zph<T>, dim3((NDIR * p + 255) / 256), dim3(256), 0, st, p, (T *)P->zph);
+    hipLaunchKernelGGL(k_coax<T>, dim3(1), dim3(32), 0, st, p, (T *)P->coax);
+    LHF_HIP(hipGetLastError());
+    return LHF_OK;
+}
+
+static void free_plan(lhf_plan *P)
+{
+    if (!P) return;
+    void *bufs[] = {P->perm, P->xs, P->ws, P->vfar, P->bkey, P->bstart, P->bcount, P->bparent, P->bchild0,
+                    P->bnchild, P->vcount, P->vsrc, P->vdir, P->ulist, P->eleaf, P->M, P->Lc, P->rot,
+                    P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    delete P;
+}
+
+static double core_k(double r, double a)
+{
+    // K(r; a) of eq. vem1
+    return erf(r / (a * sqrt(2.0))) - sqrt(2.0 / M_PI) * (r / a) * exp(-r * r / (2.0 * a * a));
+}
+
+template <typename T>
+static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
+{
+    const int64_t n = P->n;
+    const int d = P->depth;
+    const int tpb = 256;
+    const unsigned nblk = (unsigned)((n + tpb - 1) / tpb);
+    // ---- keys and sort
+    uint64_t *key = nullptr, *skey = nullptr;
+    int32_t *idx = nullptr, *flag = nullptr, *id = nullptr;
+    int64_t *dnb = nullptr, *dcnt = nullptr;
+    void *tmp = nullptr;
+    size_t tmp_bytes = 0;
+    auto cleanup = [&]() {
+        for (void *b : {(void *)key, (void *)skey, (void *)idx, (void *)flag, (void *)id, (void *)dnb, (void *)dcnt, tmp})
+            if (b) (void)hipFree(b);
+    };
+#define CK(call)                                        \
+    do {                                                \
+        hipError_t _e = (call);                         \
+        if (_e != hipSuccess) {                         \
+            cleanup();                                  \
+            return hip_fail(_e, #call);                 \
+        }                                               \
+    } while (0)
+    CK(hipMalloc(&key, sizeof(uint64_t) * n));
+    CK(hipMalloc(&skey, sizeof(uint64_t) * n));
+    CK(hipMalloc(&idx, sizeof(int32_t) * n));
+    CK(hipMalloc(&P->perm, sizeof(int32_t) * n));
+    CK(hipMalloc(&flag, sizeof(int32_t) * n));
+    CK(hipMalloc(&id, sizeof(int32_t) * n));
+    CK(hipMalloc(&dnb, sizeof(int64_t) * (MAXDEPTH + 1)));
+    CK(hipMalloc(&dcnt, sizeof(int64_t) * 4));
+    CK(hipMalloc(&P->dflag, sizeof(int32_t) * 4));
+    CK(hipMemsetAsync(P->dflag, 0, sizeof(int32_t) * 4, st));
+    CK(hipMemsetAsync(dcnt, 0, sizeof(int64_t) * 4, st));
+    const double scale = (double)(1u << QBITS) / P->L;
+    hipLaunchKernelGGL(k_keys<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)x, P->lo[0], P->lo[1], P->lo[2], scale,
+                       d, key, idx, P->dflag);
+    CK(hipGetLastError());
+    size_t sort_bytes = 0, scan_bytes = 0;
+    CK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, key, skey, idx, P->perm, (int)n, 0, 3 * d, st));
+    CK(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, flag, id, (int)n, st));
+    tmp_bytes = std::max(sort_bytes, scan_bytes);
+    CK(hipMalloc(&tmp, tmp_bytes));
+    CK(hipcub::DeviceRadixSort::SortPairs(tmp, sort_bytes, key, skey, idx, P->perm, (int)n, 0, 3 * d, st));
+    CK(hipMalloc(&P->xs, sizeof(T) * 3 * n));
+    CK(hipMalloc(&P->ws, sizeof(T) * 3 * n));
+    CK(hipMalloc(&P->vfar, sizeof(T) * 6 * n));
+    CK(hipMalloc(&P->eleaf, sizeof(int32_t) * n));
+    hipLaunchKernelGGL(k_gather_x<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)x, P->perm, (T *)P->xs);
+    // ---- levels (per-level temporaries sized by min(n, 8^l))
+    std::vector<uint64_t *> lkey(d + 1, nullptr);
+    std::vector<int32_t *> lstart(d + 1, nullptr);
+    auto cleanup_levels = [&]() {
+        for (int l = 0; l <= d; l++) {
+            if (lkey[l]) (void)hipFree(lkey[l]);
+            if (lstart[l]) (void)hipFree(lstart[l]);
+        }
+    };
+    for (int l = d; l >= 0; l--) {
+        const int64_t cap = std::min<int64_t>(n, (int64_t)1 << (3 * l));
+        hipError_t e1 = hipMalloc(&lkey[l], sizeof(uint64_t) * cap);
+        hipError_t e2 = hipMalloc(&lstart[l], sizeof(int32_t) * cap);
+        if (e1 != hipSuccess || e2 != hipSuccess) {
+            cleanup_levels();
+            cleanup();
+            return hip_fail(e1 != hipSuccess ? e1 : e2, "hipMalloc(level)");
+        }
+        const int sh = 3 * (d - l);
+        hipLaunchKernelGGL(k_level_flags, dim3(nblk), dim3(tpb), 0, st, n, skey, sh, flag);
+        (void)hipcub::DeviceScan::InclusiveSum(tmp, scan_bytes, flag, id, (int)n, st);
+        hipLaunchKernelGGL(k_level_fill, dim3(nblk), dim3(tpb), 0, st, n, skey, sh, flag, id, lkey[l], lstart[l],
+                           l == d ? P->eleaf : nullptr, dnb + l);
+    }
+    // ---- the one host synchronisation: tree sizes and input flags
+    int64_t hnb[MAXDEPTH + 1];
+    int32_t hflag[4];
+    hipError_t e = hipMemcpyAsync(hnb, dnb, sizeof(int64_t) * (d + 1), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hflag, P->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        cleanup_levels();
+        cleanup();
+        return hip_fail(e, "plan synchronisation");
+    }
+    if (hflag[1]) {
+        cleanup_levels();
+        cleanup();
+        set_error("non-finite element coordinate");
+        return LHF_ERR_NONFINITE;
+    }
+    if (hflag[0]) {
+        cleanup_levels();
+        cleanup();
+        set_error("element outside the domain cube");
+        return LHF_ERR_DOMAIN;
+    }
+    int64_t tot = 0;
+    LevelTab lt;
+    memset(&lt, 0, sizeof(lt));
+    for (int l = 0; l <= d; l++) {
+        P->lev[l].nb = hnb[l];
+        P->lev[l].off = tot;
+        lt.off[l] = tot;
+        lt.nb[l] = hnb[l];
+        tot += hnb[l];
+    }
+    lt.off[d + 1] = tot;
+    P->nbox = tot;
+    const int P2 = P->p * P->p;
+    CK(hipMalloc(&P->bkey, sizeof(uint64_t) * tot));
+    CK(hipMalloc(&P->bstart, sizeof(int32_t) * tot));
+    CK(hipMalloc(&P->bcount, sizeof(int32_t) * tot));
+    CK(hipMalloc(&P->bparent, sizeof(int32_t) * tot));
+    CK(hipMalloc(&P->bchild0, sizeof(int32_t) * tot));
+    CK(hipMalloc(&P->bnchild, sizeof(int32_t) * tot));
+    CK(hipMalloc(&P->vcount, sizeof(int32_t) * tot));
+    CK(hipMalloc(&P->vsrc, sizeof(int32_t) * tot * VMAX));
+    CK(hipMalloc(&P->vdir, sizeof(int16_t) * tot * VMAX));
+    CK(hipMalloc(&P->ulist, sizeof(int32_t) * hnb[d] * 27));
+    CK(hipMalloc(&P->M, sizeof(T) * tot * 2 * P2));
+    CK(hipMalloc(&P->Lc, sizeof(T) * tot * 2 * P2));
+    CK(hipMemsetAsync(P->vcount, 0, sizeof(int32_t) * tot, st));
+    for (int l = 0; l <= d; l++) {
+        CK(hipMemcpyAsync(P->bkey + lt.off[l], lkey[l], sizeof(uint64_t) * hnb[l], hipMemcpyDeviceToDevice, st));
+        CK(hipMemcpyAsync(P->bstart + lt.off[l], lstart[l], sizeof(int32_t) * hnb[l], hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_counts, dim3((unsigned)((hnb[l] + tpb - 1) / tpb)), dim3(tpb), 0, st, hnb[l], n,
+                           P->bstart + lt.off[l], P->bcount + lt.off[l]);
+    }
+    hipLaunchKernelGGL(k_links, dim3((unsigned)((tot + tpb - 1) / tpb)), dim3(tpb), 0, st, tot, d, lt, P->bkey,
+                       P->bparent, P->bchild0, P->bnchild);
+    for (int l = 2; l <= d; l++)
+        hipLaunchKernelGGL(k_vlist, dim3((unsigned)((hnb[l] + tpb - 1) / tpb)), dim3(tpb), 0, st, lt.off[l], hnb[l], l,
+                           P->bkey, P->vcount, P->vsrc, P->vdir);
+    hipLaunchKernelGGL(k_ulist, dim3((unsigned)((hnb[d] + tpb - 1) / tpb)), dim3(tpb), 0, st, lt.off[d], hnb[d], d,
+                       P->bkey, P->bcount, P->ulist, dcnt + 1);
+    hipLaunchKernelGGL(k_add_i32, dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, (int32_t)lt.off[d]);
+    hipLaunchKernelGGL(k_sum_i32, dim3(256), dim3(256), 0, st, tot, P->vcount, dcnt);
+    CK(hipGetLastError());
+    lhf_status ts = build_tables<T>(P, st);
+    if (ts != LHF_OK) {
+        cleanup_levels();
+        cleanup();
+        return ts;
+    }
+    int64_t hc[4];
+    e = hipMemcpyAsync(hc, dcnt, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup_levels();
+    cleanup();
+    if (e != hipSuccess) return hip_fail(e, "plan finalisation");
+    P->n_m2l = hc[0];
+    P->n_p2p = hc[1];
+#undef CK
+    return LHF_OK;
+}
+
+}  // namespace lhf
+
+using namespace lhf;
+
+extern "C" {
+
+void lhf_desc_default(lhf_desc *d)
+{
+    if (!d) return;
+    memset(d, 0, sizeof(*d));
+    d->p = 12;
+    d->tol = 1e-6;
+    d->depth = 4;
+    d->domain_len = 1.0;
+    d->precision = LHF_FP64;
+}
+
+const char *lhf_last_error(void) { return g_err.c_str(); }
+
+const char *lhf_version(void) { return "lhfmm 0.1 (gfx950)"; }
+
+lhf_status lhf_plan_create(lhf_plan **out, const lhf_desc *d, int64_t n, const void *x, double a, void *stream)
+{
+    if (!out) return arg_error("out is NULL");
+    *out = nullptr;
+    if (!d) return arg_error("desc is NULL");
+    if (n < 1) return arg_error("n must be >= 1");
+    if (n > (int64_t)0x7fffffff) return arg_error("n must fit in int32");
+    if (!x) return arg_error("x is NULL");
+    if (d->precision != LHF_FP64 && d->precision != LHF_FP32) return arg_error("unknown precision");
+    const int pmax = d->precision == LHF_FP64 ? MAXP : 16;
+    if (d->p < 1 || d->p > pmax) return arg_error("p out of range (FP64: 1..24, FP32: 1..16)");
+    if (d->depth < 2 || d->depth > MAXDEPTH) return arg_error("depth out of range (2..10)");
+    if (!(a >= 0.0) || !isfinite(a)) return arg_error("core radius a must be finite and >= 0");
+    if (!(d->tol > 0.0)) return arg_error("tol must be > 0");
+    if (!(d->domain_len > 0.0) || !isfinite(d->domain_len))
+        return arg_error("domain_len must be > 0 (bounding-cube mode is not supported)");
+    for (int k = 0; k < 3; k++)
+        if (!isfinite(d->domain_lo[k])) return arg_error("domain_lo must be finite");
+    lhf_plan *P = new lhf_plan();
+    P->desc = *d;
+    P->n = n;
+    P->p = d->p;
+    P->depth = d->depth;
+    P->precision = d->precision;
+    P->tsize = d->precision == LHF_FP64 ? 8 : 4;
+    P->a = (d->flags & LHF_SINGULAR) ? 0.0 : a;
+    for (int k = 0; k < 3; k++) P->lo[k] = d->domain_lo[k];
+    P->L = d->domain_len;
+    P->stream = (hipStream_t)stream;
+    lhf_status s = d->precision == LHF_FP64 ? plan_create_t<double>(P, x, P->stream)
+                                            : plan_create_t<float>(P, x, P->stream);
+    if (s < 0) {
+        free_plan(P);
+        return s;
+    }
+    *out = P;
+    // warn when the far field's singular kernel differs from the core by more than tol
+    if (P->a > 0.0) {
+        const double hleaf = P->L / (double)(1 << P->depth);
+        if (1.0 - core_k(hleaf, P->a) > d->tol) return LHF_WARN_CORE_SPLIT;
+    }
+    return LHF_OK;
+}
+
+lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, int32_t what, void *stream)
+{
+    if (!plan) return arg_error("plan is NULL");
+    if (!omega || !v || !s) return arg_error("omega, v and s must be non-NULL");
+    if (what < 1 || what > 3) return arg_error("what must be 1, 2 or 3");
+    plan->stream = (hipStream_t)stream;
+    return execute_impl(plan, omega, v, s, what, (hipStream_t)stream);
+}
+
+lhf_status lhf_execute(lhf_plan *plan, const void *omega, void *v, void *s, void *stream)
+{
+    return lhf_execute_parts(plan, omega, v, s, 3, stream);
+}
+
+lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void *omega, double a, void *v, void *s,
+                        void *stream)
+{
+    lhf_plan *P = nullptr;
+    lhf_status st = lhf_plan_create(&P, d, n, x, a, stream);
+    if (st < 0) return st;
+    lhf_status e = lhf_execute(P, omega, v, s, stream);
+    lhf_status dd = lhf_plan_destroy(P);
+    if (e < 0) return e;
+    if (dd < 0) return dd;
+    return st;
+}
+
+lhf_status lhf_plan_stats(const lhf_plan *P, lhf_stats *out)
+{
+    if (!P || !out) return arg_error("plan and out must be non-NULL");
+    memset(out, 0, sizeof(*out));
+    out->n = P->n;
+    out->depth = P->depth;
+    out->p = P->p;
+    for (int l = 0; l <= P->depth; l++) out->boxes[l] = P->lev[l].nb;
+    out->n_m2l = P->n_m2l;
+    int64_t nm2m = 0;
+    for (int l = 3; l <= P->depth; l++) nm2m += P->lev[l].nb;
+    out->n_m2m = nm2m;
+    out->n_l2l = nm2m;
+    out->n_p2p_pairs = P->n_p2p;
+    out->n_theta_classes = P->n_theta;
+    return LHF_OK;
+}
+
+lhf_status lhf_plan_destroy(lhf_plan *P)
+{
+    if (!P) return LHF_OK;
+    hipError_t e = hipStreamSynchronize(P->stream);
+    free_plan(P);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return LHF_OK;
+}
+
+}  // extern "C"

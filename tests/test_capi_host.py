@@ -1,0 +1,59 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/lhfmm.h, and rejects bad arguments on the host before any
+device work (negative status, thread-local message)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_1201_5430_amd as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("liblhfmm.so not built")
+    return L, L.load()
+
+
+def test_exports_match_header():
+    L, lib = _lib()
+    hdr = open(os.path.join(ROOT, "include", "lhfmm.h")).read()
+    declared = set(re.findall(r"\b(lhf_[a-z_]+)\s*\(", hdr))
+    assert declared == set(L.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.lhf_version().startswith(b"lhfmm")
+
+
+def test_argument_validation_is_host_side():
+    L, lib = _lib()
+    h = C.c_void_p()
+    dummy = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    cases = [
+        (dict(p=12, depth=4), 0, 0.01, "n must be >= 1"),
+        (dict(p=0, depth=4), 10, 0.01, "p out of range"),
+        (dict(p=25, depth=4), 10, 0.01, "p out of range"),
+        (dict(p=17, depth=4, precision=L.FP32), 10, 0.01, "p out of range"),
+        (dict(p=8, depth=1), 10, 0.01, "depth out of range"),
+        (dict(p=8, depth=11), 10, 0.01, "depth out of range"),
+        (dict(p=8, depth=3), 10, -1.0, "core radius"),
+        (dict(p=8, depth=3), 10, float("nan"), "core radius"),
+        (dict(p=8, depth=3, L=0.0), 10, 0.01, "domain_len"),
+        (dict(p=8, depth=3, precision=7), 10, 0.01, "precision"),
+        (dict(p=8, depth=3, tol=0.0), 10, 0.01, "tol"),
+    ]
+    for kw, n, a, msg in cases:
+        d = L.make_desc(**kw)
+        st = lib.lhf_plan_create(C.byref(h), C.byref(d), n, dummy, a, None)
+        assert st == -1, (kw, st)
+        assert h.value is None
+        assert msg in lib.lhf_last_error().decode()
+    d = L.make_desc(p=8, depth=3)
+    assert lib.lhf_plan_create(C.byref(h), C.byref(d), 10, None, 0.01, None) == -1
+    assert lib.lhf_plan_create(None, C.byref(d), 10, dummy, 0.01, None) == -1
+    assert lib.lhf_execute(None, dummy, dummy, dummy, None) == -1
+    assert lib.lhf_plan_destroy(None) == 0
+    st = L.Stats()
+    assert lib.lhf_plan_stats(None, C.byref(st)) == -1
