@@ -118,6 +118,18 @@ lhf_status lhf_plan_destroy(lhf_plan *plan);
 /* Thread-local description of the last error (never NULL). */
 const char *lhf_last_error(void);
 
+/* Phase timing (HIP events recorded on the execute stream).  After
+ * lhf_profile_begin(plan, k), each of the next k calls of lhf_execute records
+ * events between its phases; lhf_profile_end waits for them and returns the
+ * summed milliseconds per phase over those calls in phase_ms[LHF_NPHASE]:
+ *   0 gather omega, 1 P2M, 2 M2M, 3 downward pass (L2L + M2L, one launch per
+ *   level 2..d), 4 L2P, 5 P2P + combine + un-permute,
+ * and the number of profiled calls in *n_exec.  Recording adds no host
+ * synchronisation; begin/end are called outside timed or captured regions. */
+#define LHF_NPHASE 6
+lhf_status lhf_profile_begin(lhf_plan *plan, int32_t max_exec);
+lhf_status lhf_profile_end(lhf_plan *plan, double *phase_ms, int32_t *n_exec);
+
 /* Library version string. */
 const char *lhf_version(void);
 

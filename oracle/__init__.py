@@ -38,7 +38,8 @@ def build(force: bool = True) -> str:
 
 class _Stats(C.Structure):
     _fields_ = [("n_m2l", C.c_int64), ("n_m2m", C.c_int64), ("n_l2l", C.c_int64),
-                ("n_p2p_pairs", C.c_int64)]
+                ("n_p2p_pairs", C.c_int64), ("t_tree", C.c_double), ("t_up", C.c_double),
+                ("t_down", C.c_double), ("t_near", C.c_double)]
 
 
 def lib():
@@ -201,7 +202,8 @@ def fmm(x, w, a, p, depth, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True, p2m_m
         s[~mask] = np.nan
         if grad:
             g[~mask] = np.nan
-    stats = dict(n_m2l=st.n_m2l, n_l2l=st.n_l2l, n_p2p_pairs=st.n_p2p_pairs)
+    stats = dict(n_m2l=st.n_m2l, n_l2l=st.n_l2l, n_p2p_pairs=st.n_p2p_pairs, t_tree=st.t_tree,
+                 t_up=st.t_up, t_down=st.t_down, t_near=st.t_near)
     out = (v, s, g.reshape(n, 3, 3)) if grad else (v, s)
     return out + (stats,)
 

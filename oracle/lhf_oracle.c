@@ -724,7 +724,17 @@ void lho_direct(int64_t n, const double *x, const double *w, double a, int mode,
 
 typedef struct {
     int64_t n_m2l, n_m2m, n_l2l, n_p2p_pairs;
+    double t_tree, t_up, t_down, t_near; /* wall-clock seconds of the phases */
 } lho_stats;
+
+static double wtime(void)
+{
+#ifdef _OPENMP
+    return omp_get_wtime();
+#else
+    return 0.0;
+#endif
+}
 
 /* Visit the V-list (interaction list) of box (l, k): children of the parent's
  * neighbours that are not adjacent to the box and are non-empty. */
@@ -776,11 +786,13 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
             double *s, double *gv, lho_stats *st)
 {
     if (depth < 2 || depth > 10 || p < 1 || n < 1) return -1;
+    double t0 = wtime();
     otree T;
     tree_build(&T, n, x, depth, lo, L);
     size_t P2 = (size_t)p * p;
     int smooth = a > 0.0;
-    lho_stats stats = {0, 0, 0, 0};
+    lho_stats stats = {0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+    stats.t_tree = wtime() - t0;
 
     /* which leaves to evaluate */
     int64_t nleaf = T.nb[depth];
@@ -799,6 +811,7 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
 
     if (what & 1) {
         /* ---------- upward pass: P2M at leaves, M2M to level 2 ---------- */
+        double t1 = wtime();
         cplx *M[MAXLEV + 1];
         for (int l = 2; l <= depth; l++) M[l] = (cplx *)calloc((size_t)T.nb[l] * 2 * P2, sizeof(cplx));
 #pragma omp parallel
@@ -844,6 +857,8 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
             }
         }
 
+        stats.t_up = wtime() - t1;
+        t1 = wtime();
         /* ---------- downward pass ---------- */
         if (!sample) {
             cplx *Lc[MAXLEV + 1];
@@ -987,10 +1002,12 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
             stats.n_m2l = nm2l;
         }
         for (int l = 2; l <= depth; l++) free(M[l]);
+        stats.t_down = wtime() - t1;
     }
 
     if (what & 2) {
         /* ---------- near field: adjacent leaves, smoothed kernel ---------- */
+        double t2 = wtime();
         int64_t npairs = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : npairs)
         for (int64_t b = 0; b < nleaf; b++) {
@@ -1030,6 +1047,7 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
             }
         }
         stats.n_p2p_pairs = npairs;
+        stats.t_near = wtime() - t2;
     }
     if (st) *st = stats;
     free(want);

@@ -24,7 +24,9 @@ STATUS = {0: "LHF_OK", 1: "LHF_WARN_CORE_SPLIT", -1: "LHF_ERR_ARG", -2: "LHF_ERR
 
 #: every entry point declared in include/lhfmm.h
 EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_execute", "lhf_execute_parts", "lhf_evaluate",
-           "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version")
+           "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version", "lhf_profile_begin",
+           "lhf_profile_end")
+PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p")
 
 
 class Desc(C.Structure):
@@ -72,6 +74,10 @@ def load():
         L.lhf_plan_destroy.restype = C.c_int
         L.lhf_last_error.restype = C.c_char_p
         L.lhf_version.restype = C.c_char_p
+        L.lhf_profile_begin.argtypes = [vp, C.c_int32]
+        L.lhf_profile_begin.restype = C.c_int
+        L.lhf_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.lhf_profile_end.restype = C.c_int
         _lib = L
     return _lib
 
@@ -139,6 +145,16 @@ class Plan:
         return dict(n=st.n, depth=st.depth, p=st.p, boxes=list(st.boxes[:st.depth + 1]), n_m2l=st.n_m2l,
                     n_m2m=st.n_m2m, n_l2l=st.n_l2l, n_p2p_pairs=st.n_p2p_pairs,
                     n_theta_classes=st.n_theta_classes)
+
+    def profile_begin(self, max_exec):
+        _check(load().lhf_profile_begin(self._h, int(max_exec)))
+
+    def profile_end(self):
+        """summed per-phase milliseconds over the profiled executes, and their number"""
+        ms = (C.c_double * len(PHASES))()
+        k = C.c_int32()
+        _check(load().lhf_profile_end(self._h, ms, C.byref(k)))
+        return dict(zip(PHASES, list(ms))), k.value
 
     def close(self):
         if self._h:

@@ -20,6 +20,8 @@
 
 namespace lhf {
 
+void m2l_tile_launch(const lhf_plan *Pl, int level, hipStream_t st);
+
 constexpr int WAVE = 64;
 constexpr int NRMAX = (2 * MAXP * MAXP + WAVE - 1) / WAVE;  // accumulator rows per lane
 
@@ -399,7 +401,7 @@ __global__ void __launch_bounds__(WAVE) k_m2m(int p, int64_t off, const int32_t 
 
 // Downward pass for one level: L2L from the parent (levels > 2) + M2L over the V-list
 template <typename T>
-__global__ void __launch_bounds__(WAVE) k_down(int p, int level, int64_t off, const int32_t *__restrict__ bparent,
+__global__ void __launch_bounds__(WAVE) k_down(int p, int level, int do_m2l, int64_t off, const int32_t *__restrict__ bparent,
                                                const uint64_t *__restrict__ bkey, const int32_t *__restrict__ vcount,
                                                const int32_t *__restrict__ vsrc, const int16_t *__restrict__ vdir,
                                                const T *__restrict__ M, T *__restrict__ Lc, const T *__restrict__ rot,
@@ -429,7 +431,7 @@ __global__ void __launch_bounds__(WAVE) k_down(int p, int level, int64_t off, co
         rcr<T, 2>(p, Lc + (size_t)bparent[b] * 2 * P2, X, Y, Z, R + ROT_R_FWD * rs, R + ROT_R_BACK * rs, zp,
                   zp + p, cf, (T)0.8660254037844386, acc);
     }
-    const int nv = vcount[b];
+    const int nv = do_m2l ? vcount[b] : 0;
     for (int j = 0; j < nv; j++) {
         const int src = vsrc[(size_t)b * VMAX + j];
         const int dir = vdir[(size_t)b * VMAX + j];
@@ -745,34 +747,51 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
     const T *rot = (const T *)P->rot, *zph = (const T *)P->zph, *coax = (const T *)P->coax;
     const int tpb = 256;
     const unsigned nblk = (unsigned)((n + tpb - 1) / tpb);
+    hipEvent_t *ev = nullptr;
+    if (P->prof_ev && P->prof_used < P->prof_cap) ev = P->prof_ev + (size_t)(P->prof_used++) * (LHF_NPHASE + 1);
+    auto mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], st);
+    };
+    mark(0);
     hipLaunchKernelGGL(k_gather_w<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)omega, P->perm, ws);
+    mark(1);
     const int64_t loff = P->lev[d].off, nleaf = P->lev[d].nb;
     if (what & 1) {
         size_t sh_p2m = sizeof(T) * 2 * P2;
         hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_p2m, st, p, d, loff, P->bkey, P->bstart,
                            P->bcount, (const T *)xs, (const T *)ws, n, P->lo[0], P->lo[1], P->lo[2], P->L, M);
+        mark(2);
         size_t sh_rcr = sizeof(T) * (4 * P2 + 2 * ZS + 2 * p + 2);
         for (int l = d - 1; l >= 2; l--) {
             if (P->lev[l].nb == 0) continue;
             hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, P->lev[l].off,
                                P->bchild0, P->bnchild, P->bkey, M, rot, zph, P->dir_theta);
         }
+        mark(3);
         for (int l = 2; l <= d; l++) {
             if (P->lev[l].nb == 0) continue;
             hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l,
-                               P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M, Lc,
-                               rot, zph, P->dir_theta, coax);
+                               P->use_tile ? 0 : 1, P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir,
+                               (const T *)M, Lc, rot, zph, P->dir_theta, coax);
+            if (P->use_tile) m2l_tile_launch(P, l, st);
         }
+        mark(4);
         const int TRI = p * (p + 1) / 2;
         size_t sh_l2p = sizeof(T) * (2 * P2 + 6 * TRI);
         hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_l2p, st, p, d, loff, P->bkey, P->bstart,
                            P->bcount, (const T *)xs, (const T *)ws, n, P->lo[0], P->lo[1], P->lo[2], P->L,
                            (const T *)Lc, vfar);
+    } else {
+        mark(2);
+        mark(3);
+        mark(4);
     }
+    mark(5);
     const int smooth = P->a > 0.0 && !(P->desc.flags & LHF_SINGULAR);
     hipLaunchKernelGGL(k_p2p<T>, dim3(nblk), dim3(tpb), 0, st, n, 0, loff, P->eleaf, P->ulist, P->bstart, P->bcount,
                        (const T *)xs, (const T *)ws, (T)P->a, smooth, what, (const T *)vfar, P->perm, (T *)v,
                        (T *)s);
+    mark(6);
     LHF_HIP(hipGetLastError());
     return LHF_OK;
 }

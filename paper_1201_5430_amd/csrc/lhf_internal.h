@@ -95,6 +95,20 @@ struct lhf_plan {
     void *coax = nullptr;        // M2L coaxial Hankel vectors [28][2p+2], T, indexed by |d|^2
     int32_t *dflag = nullptr;    // device status flags
     double *dtmp = nullptr;
+
+    // batched M2L: dense box map per level (levels <= 8) and the static
+    // translation schedule of one sibling group sorted by polar-angle class
+    int32_t *dmap[lhf::MAXDEPTH + 1] = {nullptr};
+    int16_t *sched_cls_start = nullptr;  // [ncls + 1]
+    int16_t *sched_c = nullptr;          // [1512] child position of the target
+    int16_t *sched_dir = nullptr;        // [1512] direction code
+    int16_t *sched_cls_theta = nullptr;  // [ncls] rotation-table class
+    int sched_ncls = 0;
+    bool use_tile = false;
+
+    // phase profiling: events[k][0..LHF_NPHASE] for the k-th profiled execute
+    hipEvent_t *prof_ev = nullptr;
+    int prof_cap = 0, prof_used = 0;
 };
 
 namespace lhf {

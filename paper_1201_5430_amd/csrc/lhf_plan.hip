@@ -13,6 +13,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -24,6 +25,8 @@
 namespace lhf {
 
 lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st);
+bool m2l_tile_supported(int precision, int p);
+void dmap_build(const lhf_plan *Pl, int level, hipStream_t st);
 
 static thread_local std::string g_err = "no error";
 
@@ -487,6 +490,49 @@ static void theta_classes(std::vector<int16_t> &cls, std::vector<double> &theta)
     }
 }
 
+// Static M2L schedule of one sibling group: for each child position c and each
+// of its 189 interaction offsets d (children of the parent's neighbours, not
+// adjacent to the child), the entry (c, code(d)) with d = c_T - c_S, grouped
+// by the polar-angle class of d.
+static lhf_status build_schedule(lhf_plan *P, const std::vector<int16_t> &cls, int ntheta, hipStream_t st)
+{
+    std::vector<std::vector<std::pair<int16_t, int16_t>>> by(ntheta);
+    for (int c = 0; c < 8; c++) {
+        const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+        for (int pz = -1; pz <= 1; pz++)
+            for (int py = -1; py <= 1; py++)
+                for (int px = -1; px <= 1; px++)
+                    for (int ch = 0; ch < 8; ch++) {
+                        const int sx = 2 * px + (ch & 1), sy = 2 * py + ((ch >> 1) & 1), sz = 2 * pz + ((ch >> 2) & 1);
+                        const int dx = cx - sx, dy = cy - sy, dz = cz - sz;  // t = c_T - c_S (units of h)
+                        if (abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1) continue;
+                        const int code = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
+                        by[cls[code]].push_back({(int16_t)c, (int16_t)code});
+                    }
+    }
+    std::vector<int16_t> start, ec, ed, cth;
+    for (int k = 0; k < ntheta; k++) {
+        if (by[k].empty()) continue;
+        start.push_back((int16_t)ec.size());
+        cth.push_back((int16_t)k);
+        for (auto &e : by[k]) {
+            ec.push_back(e.first);
+            ed.push_back(e.second);
+        }
+    }
+    start.push_back((int16_t)ec.size());
+    P->sched_ncls = (int)cth.size();
+    LHF_HIP(hipMalloc(&P->sched_cls_start, sizeof(int16_t) * start.size()));
+    LHF_HIP(hipMalloc(&P->sched_c, sizeof(int16_t) * ec.size()));
+    LHF_HIP(hipMalloc(&P->sched_dir, sizeof(int16_t) * ed.size()));
+    LHF_HIP(hipMalloc(&P->sched_cls_theta, sizeof(int16_t) * cth.size()));
+    LHF_HIP(hipMemcpyAsync(P->sched_cls_start, start.data(), sizeof(int16_t) * start.size(), hipMemcpyHostToDevice, st));
+    LHF_HIP(hipMemcpyAsync(P->sched_c, ec.data(), sizeof(int16_t) * ec.size(), hipMemcpyHostToDevice, st));
+    LHF_HIP(hipMemcpyAsync(P->sched_dir, ed.data(), sizeof(int16_t) * ed.size(), hipMemcpyHostToDevice, st));
+    LHF_HIP(hipMemcpyAsync(P->sched_cls_theta, cth.data(), sizeof(int16_t) * cth.size(), hipMemcpyHostToDevice, st));
+    return LHF_OK;
+}
+
 template <typename T>
 static lhf_status build_tables(lhf_plan *P, hipStream_t st)
 {
@@ -510,16 +556,45 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     hipLaunchKernelGGL(k_zph<T>, dim3((NDIR * p + 255) / 256), dim3(256), 0, st, p, (T *)P->zph);
     hipLaunchKernelGGL(k_coax<T>, dim3(1), dim3(32), 0, st, p, (T *)P->coax);
     LHF_HIP(hipGetLastError());
+    // batched M2L: used when the tiled kernel exists for (precision, p), fits in LDS and the
+    // dense box maps stay small (levels <= 8)
+    P->use_tile = m2l_tile_supported(P->precision, p) && P->depth <= 8 && !getenv("LHF_NO_TILE");
+    if (P->use_tile) {
+        lhf_status s = build_schedule(P, cls, (int)theta.size(), st);
+        if (s != LHF_OK) return s;
+        for (int l = 2; l <= P->depth; l++) {
+            const size_t side = (size_t)1 << l;
+            LHF_HIP(hipMalloc(&P->dmap[l], sizeof(int32_t) * side * side * side));
+            LHF_HIP(hipMemsetAsync(P->dmap[l], 0xff, sizeof(int32_t) * side * side * side, st));
+            dmap_build(P, l, st);
+        }
+    }
     return LHF_OK;
+}
+
+static void free_profile(lhf_plan *P)
+{
+    if (P->prof_ev) {
+        for (int k = 0; k < P->prof_cap * (LHF_NPHASE + 1); k++) (void)hipEventDestroy(P->prof_ev[k]);
+        delete[] P->prof_ev;
+    }
+    P->prof_ev = nullptr;
+    P->prof_cap = P->prof_used = 0;
 }
 
 static void free_plan(lhf_plan *P)
 {
     if (!P) return;
+    free_profile(P);
     void *bufs[] = {P->perm, P->xs, P->ws, P->vfar, P->bkey, P->bstart, P->bcount, P->bparent, P->bchild0,
                     P->bnchild, P->vcount, P->vsrc, P->vdir, P->ulist, P->eleaf, P->M, P->Lc, P->rot,
                     P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp};
     for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (int l = 0; l <= MAXDEPTH; l++)
+        if (P->dmap[l]) (void)hipFree(P->dmap[l]);
+    void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta};
+    for (void *b : sb)
         if (b) (void)hipFree(b);
     delete P;
 }
@@ -795,6 +870,52 @@ lhf_status lhf_plan_stats(const lhf_plan *P, lhf_stats *out)
     out->n_l2l = nm2m;
     out->n_p2p_pairs = P->n_p2p;
     out->n_theta_classes = P->n_theta;
+    return LHF_OK;
+}
+
+lhf_status lhf_profile_begin(lhf_plan *P, int32_t max_exec)
+{
+    if (!P) return arg_error("plan is NULL");
+    if (max_exec < 1 || max_exec > 100000) return arg_error("max_exec must be in 1..100000");
+    free_profile(P);
+    const int ne = max_exec * (LHF_NPHASE + 1);
+    P->prof_ev = new hipEvent_t[ne];
+    for (int k = 0; k < ne; k++) {
+        hipError_t e = hipEventCreate(&P->prof_ev[k]);
+        if (e != hipSuccess) {
+            P->prof_cap = k / (LHF_NPHASE + 1);
+            for (int j = k; j < ne; j++) P->prof_ev[j] = nullptr;
+            for (int j = 0; j < k; j++) (void)hipEventDestroy(P->prof_ev[j]);
+            delete[] P->prof_ev;
+            P->prof_ev = nullptr;
+            P->prof_cap = 0;
+            return hip_fail(e, "hipEventCreate");
+        }
+    }
+    P->prof_cap = max_exec;
+    P->prof_used = 0;
+    return LHF_OK;
+}
+
+lhf_status lhf_profile_end(lhf_plan *P, double *phase_ms, int32_t *n_exec)
+{
+    if (!P || !phase_ms || !n_exec) return arg_error("plan, phase_ms and n_exec must be non-NULL");
+    if (!P->prof_ev) {
+        set_error("lhf_profile_begin was not called");
+        return LHF_ERR_STATE;
+    }
+    for (int k = 0; k < LHF_NPHASE; k++) phase_ms[k] = 0.0;
+    for (int e = 0; e < P->prof_used; e++) {
+        hipEvent_t *ev = P->prof_ev + (size_t)e * (LHF_NPHASE + 1);
+        LHF_HIP(hipEventSynchronize(ev[LHF_NPHASE]));
+        for (int k = 0; k < LHF_NPHASE; k++) {
+            float ms = 0.f;
+            LHF_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            phase_ms[k] += ms;
+        }
+    }
+    *n_exec = P->prof_used;
+    free_profile(P);
     return LHF_OK;
 }
 

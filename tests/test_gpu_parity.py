@@ -129,3 +129,32 @@ def test_cube1m_fp64_sampled_leaves(oracle):
     assert m.sum() >= 48
     _check(v[m], s[m], vr[m], sr[m], l2=1e-11, mx=1e-10)
     assert st["boxes"][d] > 250000
+
+
+def test_generic_and_tiled_m2l_agree(oracle, monkeypatch):
+    # the class-batched M2L kernel and the generic one-wave-per-box kernel give the same field
+    rng = np.random.default_rng(31)
+    n = 6000
+    x = rng.uniform(0, 1, (n, 3))
+    w = rng.normal(size=(n, 3))
+    a = 0.5 * n ** (-1 / 3)
+    v1, s1, _ = _gpu_fmm(x, w, a, 12, 4)
+    monkeypatch.setenv("LHF_NO_TILE", "1")
+    v2, s2, _ = _gpu_fmm(x, w, a, 12, 4)
+    _check(v1, s1, v2, s2, l2=1e-13, mx=1e-12)
+
+
+@pytest.mark.parametrize("p,depth", [(8, 3), (10, 4), (12, 4), (16, 3)])
+def test_fp32_path_matches_fp64_oracle(oracle, p, depth):
+    # FP32 elements and expansions; the oracle sees the FP32-rounded inputs in FP64.
+    # The FP32 path's own rounding must stay far below the FMM truncation error.
+    rng = np.random.default_rng(40 + p)
+    n = 8000
+    x = rng.uniform(0, 1, (n, 3)).astype(np.float32).astype(np.float64)
+    w = rng.normal(size=(n, 3)).astype(np.float32).astype(np.float64)
+    a = float(np.float32(0.5 * n ** (-1 / 3)))
+    vr, sr, _ = oracle.fmm(x, w, a, p, depth)
+    v, s, _ = _gpu_fmm(x, w, a, p, depth, precision=1)
+    ev, es = _rel(v, vr), _rel(s, sr)
+    print(f"FP32 p={p} depth={depth}: rel L2 v {ev:.3e} s {es:.3e}", flush=True)
+    assert ev < 2e-6 and es < 2e-6
