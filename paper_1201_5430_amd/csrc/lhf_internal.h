@@ -105,6 +105,7 @@ struct lhf_plan {
     int16_t *sched_cls_theta = nullptr;  // [ncls] rotation-table class
     int sched_ncls = 0;
     bool use_tile = false;
+    void *wpad = nullptr;                // padded per-class rotation blocks (tiled M2L layout)
 
     // phase profiling: events[k][0..LHF_NPHASE] for the k-th profiled execute
     hipEvent_t *prof_ev = nullptr;

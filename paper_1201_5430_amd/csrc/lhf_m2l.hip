@@ -28,20 +28,72 @@
 
 namespace lhf {
 
-template <int P>
+// rotation rows are padded to a multiple of E = 16 bytes so they load as 16-byte vectors
+template <typename T>
+__host__ __device__ constexpr int vecE() { return 16 / (int)sizeof(T); }
+template <typename T>
+__host__ __device__ constexpr int rowlen(int n) { return ((n + 1 + vecE<T>() - 1) / vecE<T>()) * vecE<T>(); }
+template <typename T>
+__host__ __device__ constexpr int wrow_off(int n)  // offset of order n's block: sum_{k<n} (k+1) rowlen(k)
+{
+    int o = 0;
+    for (int k = 0; k < n; k++) o += (k + 1) * rowlen<T>(k);
+    return o;
+}
+
+template <typename T, int P>
 struct M2LShape {
-    static constexpr int NV = P * (P + 1) / 2;        // (n, m <= n), n < P
-    static constexpr int NVX = NV + P + 1;            // + order P (chi extra row), m <= P
-    static constexpr int WB = P * (P + 1) * (2 * P + 1) / 6;  // sum_{n<P} (n+1)^2
+    static constexpr int NV = P * (P + 1) / 2;      // (n, m <= n), n < P
+    static constexpr int WB = wrow_off<T>(P);       // one padded rotation set (all orders)
 };
 
 __host__ __device__ constexpr int tri(int n) { return n * (n + 1) / 2; }
-__host__ __device__ constexpr int woff(int n) { return n * (n + 1) * (2 * n + 1) / 6; }
+
+// quad permutations by DPP (VALU, no LDS traffic): xor 1 and xor 3 within each group of 4 lanes
+template <int CTRL>
+__device__ inline float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ inline double dpp_f(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int DPP_XOR3 = 0x1B;  // quad_perm [3,2,1,0]
 
 template <typename T>
-__device__ inline T shfl_xor_t(T v, int mask)
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+};
+
+// one output row: sum_m W[m] in[m], W read as 16-byte vectors
+template <typename T>
+__device__ __attribute__((always_inline)) inline T rowdot(const T *W, const T *in, const int N1)
 {
-    return __shfl_xor(v, mask, 64);
+    using V = typename Vec16<T>::type;
+    constexpr int E = vecE<T>();
+    const V *Wv = (const V *)W;
+    T a = 0;
+#pragma unroll
+    for (int q = 0; q < (N1 + E - 1) / E; q++) {
+        const V w = Wv[q];
+        const T *wp = (const T *)&w;
+#pragma unroll
+        for (int e = 0; e < E; e++)
+            if (q * E + e < N1) a += wp[e] * in[q * E + e];
+    }
+    return a;
 }
 
 // factorials as constants
@@ -60,33 +112,37 @@ struct M2LSched {
     int ncls;
 };
 
-template <typename T, int P>
+template <typename T, int P, int NPAR>
 __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64_t npar, int64_t loff, int64_t nbl,
                                                   const uint64_t *__restrict__ bkey, const int32_t *__restrict__ bchild0,
                                                   const int32_t *__restrict__ bnchild, const int32_t *__restrict__ dmap,
                                                   const T *__restrict__ M, T *__restrict__ Lc,
-                                                  const T *__restrict__ rot, const T *__restrict__ zph,
+                                                  const T *__restrict__ wpad, int64_t wstride,
                                                   M2LSched sch, const int16_t *__restrict__ cls_theta)
 {
-    using S = M2LShape<P>;
+    using S = M2LShape<T, P>;
     constexpr int P2 = P * P;
+    // rotation rows per pinned group: two where registers allow, one for the largest vectors
+    constexpr int RG = (sizeof(T) * P >= 64) ? 1 : 2;
     extern __shared__ char smem[];
-    T *acc = (T *)smem;                       // [16][2][P2]
-    T *Wl = acc + 16 * 2 * P2;                // [2 kinds: fwd S, back R][2 parts][WB]
-    int *slot_box = (int *)(Wl + 4 * S::WB);  // [16] target box per slot (-1: none)
+    constexpr int NSLOT = 8 * NPAR;
+    constexpr int SST = 2 * P2 + 1;              // odd slot stride: slots fall in different LDS banks
+    T *Wl = (T *)smem;                           // [2 kinds: fwd S, back R][2 parts][WB], 16-byte aligned
+    T *acc = Wl + 4 * S::WB;                     // [NSLOT + 1][SST] (last slot absorbs inactive lanes)
+    int *slot_box = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] target box per slot (-1: none)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // XCD-aware tile order: consecutive tiles stay on one XCD (shared L2)
-    const int64_t ntiles = (npar + 1) / 2;
+    const int64_t ntiles = (npar + NPAR - 1) / NPAR;
     const int64_t per = (ntiles + 7) / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= ntiles) return;
 
-    // slots: parent i (0,1) x child position c (0..7)
-    if (tid < 16) {
+    // slots: parent i (0..NPAR-1) x child position c (0..7)
+    if (tid < NSLOT) {
         const int i = tid >> 3, c = tid & 7;
         int box = -1;
-        const int64_t q = 2 * tile + i;
+        const int64_t q = (int64_t)NPAR * tile + i;
         if (q < npar) {
             const int64_t pb = poff + q;
             const int c0 = bchild0[pb], nc = bnchild[pb];
@@ -96,13 +152,12 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
         slot_box[tid] = box;
     }
     __syncthreads();
-    for (int idx = tid; idx < 16 * 2 * P2; idx += 256) {
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
-        acc[idx] = box >= 0 ? Lc[(size_t)box * 2 * P2 + r] : (T)0;
+        acc[sl * SST + r] = box >= 0 ? Lc[(size_t)box * 2 * P2 + r] : (T)0;
     }
 
-    const int RS = rot_set_size(P);
     const int side = 1 << level;
     const int t = lane >> 2, pot = (lane >> 1) & 1, part = lane & 1;
 
@@ -110,26 +165,15 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
         const int e0 = sch.cls_start[k], cnt = sch.cls_start[k + 1] - e0;
         __syncthreads();  // previous class finished with Wl
         {
-            // stage the class's rotation blocks; Im blocks padded to (n+1)^2 with a zero m=0 row/col
-            const int th = cls_theta[k];
-            const T *Rf = rot + ((size_t)th * ROT_NKIND + ROT_S_FWD) * RS;
-            const T *Rb = rot + ((size_t)th * ROT_NKIND + ROT_R_BACK) * RS;
-            for (int idx = tid; idx < 4 * S::WB; idx += 256) {
-                const int kind = idx / (2 * S::WB), rem = idx % (2 * S::WB);
-                const int pt = rem / S::WB, j = rem % S::WB;
-                int n = 0;
-                while (woff(n + 1) <= j) n++;
-                const int jj = j - woff(n), mp = jj / (n + 1), m = jj % (n + 1);
-                const T *R = kind ? Rb : Rf;
-                const T *blk = R + rot_block_off(n);
-                T val;
-                if (pt == 0) val = blk[mp * (n + 1) + m];
-                else val = (mp == 0 || m == 0) ? (T)0 : blk[(n + 1) * (n + 1) + (mp - 1) * n + (m - 1)];
-                Wl[idx] = val;
-            }
+            // stage the class's rotation blocks (precomputed in the LDS layout) with 16-byte loads
+            const uint4 *src4 = (const uint4 *)(wpad + (size_t)cls_theta[k] * wstride);
+            uint4 *dst4 = (uint4 *)Wl;
+            constexpr int N16 = (int)(4 * S::WB * sizeof(T) / 16);
+#pragma unroll 8
+            for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
         }
         __syncthreads();
-        const int ntr = 2 * cnt;
+        const int ntr = NPAR * cnt;
         for (int r0 = 0; r0 < ntr; r0 += 64) {
             // opaque per-batch offsets keep the compiler from hoisting every matrix entry
             // of the class out of the batch loop (which would exhaust the register file)
@@ -141,7 +185,8 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
             bool act = tr < ntr;
             int slot = 0, src = -1, dir = 0;
             if (act) {
-                const int par = tr / cnt, e = e0 + tr % cnt;
+                // parents interleaved: a batch of 16 touches up to 16 distinct targets
+                const int par = tr % NPAR, e = e0 + tr / NPAR;
                 const int c = sch.ent_c[e];
                 dir = sch.ent_dir[e];
                 slot = par * 8 + c;
@@ -168,40 +213,60 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
             }
             const int dx = dir % 7 - 3, dy = (dir / 7) % 7 - 3, dz = dir / 49 - 3;
             const T tau = (T)sqrt((double)(dx * dx + dy * dy + dz * dz));
-            const T *zp = zph + (size_t)dir * 2 * P;
-            T v[S::NV];
-            // 1. load the source part and rotate about z by +phi
+            // e^{i phi} of the direction (phi = atan2(dy, dx); 0 on the z axis), FP64
+            double cph = 1.0, sph = 0.0;
             {
-                const T *sp = M + (size_t)(act ? src : 0) * 2 * P2 + pot * P2;
-#pragma unroll
-                for (int m = 0; m < P; m++) {
-                    const T cz = zp[m], sz = zp[P + m];
-#pragma unroll
-                    for (int n = m; n < P; n++) {
-                        T re = sp[pk_re(n, m)];
-                        T im = (m > 0) ? sp[pk_im(n, m)] : (T)0;
-                        T val;
-                        if (m == 0) val = part ? (T)0 : re;
-                        else val = part ? (re * sz + im * cz) : (re * cz - im * sz);
-                        v[tri(n) + m] = val;
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
+                const double rho = sqrt((double)(dx * dx + dy * dy));
+                if (rho > 0.0) {
+                    cph = (double)dx / rho;
+                    sph = (double)dy / rho;
                 }
             }
-            // 2. rotation about y (forward, S basis), one output row at a time
+            const T sgn_in = part ? (T)1 : (T)-1;   // z-rotation by +phi: Re' = re c - im s, Im' = im c + re s
+            T v[S::NV];
+            // 1. load this lane's part (Re or Im) of its potential, all loads in flight at once,
+            //    then rotate about z by +phi using the partner lane's other part
+            {
+                const T *sp = M + (size_t)(act ? src : 0) * 2 * P2 + pot * P2 + (part ? 0 : 0);
+#pragma unroll
+                for (int n = 0; n < P; n++)
+#pragma unroll
+                    for (int m = 0; m <= n; m++)
+                        v[tri(n) + m] = (m == 0) ? (part ? (T)0 : sp[pk_re(n, 0)]) : sp[part ? pk_im(n, m) : pk_re(n, m)];
+                double cm = 1.0, sm = 0.0;
+#pragma unroll
+                for (int m = 0; m < P; m++) {
+                    const T cz = (T)cm, sz = (T)sm * sgn_in;
+#pragma unroll
+                    for (int n = m; n < P; n++) {
+                        const T mine = v[tri(n) + m];
+                        const T oth = dpp_f<DPP_XOR1>(mine);
+                        if (m > 0) v[tri(n) + m] = mine * cz + oth * sz;
+                    }
+                    const double c2 = cm * cph - sm * sph, s2 = sm * cph + cm * sph;
+                    cm = c2;
+                    sm = s2;
+                }
+            }
+            // 2. rotation about y (forward, S basis), two output rows per pinned group
 #pragma unroll
             for (int n = 0; n < P; n++) {
                 T in[P];
 #pragma unroll
                 for (int m = 0; m <= n; m++) in[m] = v[tri(n) + m];
-                const T *W = Wf + woff(n);
+                const T *W = Wf + wrow_off<T>(n);
 #pragma unroll
-                for (int mp = 0; mp <= n; mp++) {
-                    T a = 0;
-#pragma unroll
-                    for (int m = 0; m <= n; m++) a += W[mp * (n + 1) + m] * in[m];
-                    asm volatile("" : "+v"(a));  // finish this row here: bounds the live matrix entries
-                    v[tri(n) + mp] = a;
+                for (int mp = 0; mp <= n; mp += RG) {
+                    T a0 = rowdot<T>(W + mp * rowlen<T>(n), in, n + 1);
+                    if (RG == 2 && mp + 1 <= n) {
+                        T a1 = rowdot<T>(W + (mp + 1) * rowlen<T>(n), in, n + 1);
+                        asm volatile("" : "+v"(a0), "+v"(a1));
+                        v[tri(n) + mp] = a0;
+                        v[tri(n) + mp + 1] = a1;
+                    } else {
+                        asm volatile("" : "+v"(a0));
+                        v[tri(n) + mp] = a0;
+                    }
                 }
             }
             // 3+4. per column m: coaxial (S|R) shift out_n = tau^-(n+1) sum_n' (n+n')! tau^-n' in_n'
@@ -209,40 +274,32 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
             //        phi~ = phi + i tau m/n chi ,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
             {
                 const T itau = (T)1 / tau;
+                T pw[P + 2];
+                pw[0] = (T)1;
+#pragma unroll
+                for (int k = 1; k <= P + 1; k++) pw[k] = pw[k - 1] * itau;
+                // lane roles as 0/1 weights (branch-free): phi lanes take the chi of the other part
+                const T wphi = pot ? (T)0 : (T)1, wchi = pot ? (T)1 : (T)0;
+                const T sconv = part ? (T)1 : (T)-1;
 #pragma unroll
                 for (int m = 0; m < P; m++) {
                     T col[P];
-                    T pwn = (T)1;
 #pragma unroll
-                    for (int k = 0; k < m; k++) pwn *= itau;
-#pragma unroll
-                    for (int n2 = m; n2 < P; n2++) {
-                        col[n2] = v[tri(n2) + m] * pwn;
-                        pwn *= itau;
-                    }
+                    for (int n2 = m; n2 < P; n2++) col[n2] = v[tri(n2) + m] * pw[n2];
                     T out[P + 1];
-                    T pwo = itau;
-#pragma unroll
-                    for (int k = 0; k < m; k++) pwo *= itau;
 #pragma unroll
                     for (int n = m; n <= P; n++) {
                         T a = 0;
 #pragma unroll
                         for (int n2 = m; n2 < P; n2++) a += (T)dfact(n + n2) * col[n2];
-                        out[n] = a * pwo;
-                        pwo *= itau;
+                        out[n] = a * pw[n + 1];
                     }
 #pragma unroll
                     for (int n = m; n < P; n++) {
-                        const T other = shfl_xor_t(out[n], 3);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
-                        T r;
-                        if (pot == 0) {
-                            const T f = (n > 0) ? tau * (T)((double)m / (double)n) : (T)0;
-                            r = out[n] + (part ? f * other : -f * other);
-                        } else {
-                            r = out[n] - tau * (T)(1.0 / (double)(n + 1)) * out[n + 1];
-                        }
-                        v[tri(n) + m] = r;
+                        const T other = dpp_f<DPP_XOR3>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
+                        const T fphi = (n > 0) ? tau * (T)((double)m / (double)n) * sconv * wphi : (T)0;
+                        const T fchi = -tau * (T)(1.0 / (double)(n + 1)) * wchi;
+                        v[tri(n) + m] = out[n] + fphi * other + fchi * out[n + 1];
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -253,35 +310,41 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
                 T in[P];
 #pragma unroll
                 for (int m = 0; m <= n; m++) in[m] = v[tri(n) + m];
-                const T *W = Wb + woff(n);
+                const T *W = Wb + wrow_off<T>(n);
 #pragma unroll
-                for (int mp = 0; mp <= n; mp++) {
-                    T a = 0;
-#pragma unroll
-                    for (int m = 0; m <= n; m++) a += W[mp * (n + 1) + m] * in[m];
-                    asm volatile("" : "+v"(a));  // finish this row here: bounds the live matrix entries
-                    v[tri(n) + mp] = a;
+                for (int mp = 0; mp <= n; mp += RG) {
+                    T a0 = rowdot<T>(W + mp * rowlen<T>(n), in, n + 1);
+                    if (RG == 2 && mp + 1 <= n) {
+                        T a1 = rowdot<T>(W + (mp + 1) * rowlen<T>(n), in, n + 1);
+                        asm volatile("" : "+v"(a0), "+v"(a1));
+                        v[tri(n) + mp] = a0;
+                        v[tri(n) + mp + 1] = a1;
+                    } else {
+                        asm volatile("" : "+v"(a0));
+                        v[tri(n) + mp] = a0;
+                    }
                 }
             }
-            // 6. back-rotation about z (-phi) and accumulation into the target slot
+            // 6. back-rotation about z (-phi) and accumulation into the target slot (branch-free;
+            //    inactive lanes add into the spare slot)
             {
-                T *ap = acc + (size_t)slot * 2 * P2 + pot * P2;
+                T *ap = acc + (size_t)(act ? slot : NSLOT) * SST + pot * P2 + (part ? 0 : 0);
+                const T sgn_out = part ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
+                double cm = 1.0, sm = 0.0;
 #pragma unroll
                 for (int m = 0; m < P; m++) {
-                    const T cz = zp[m], sz = zp[P + m];
+                    const T cz = (T)cm, sz = (T)sm * sgn_out;
+                    {
+                        const double c2 = cm * cph - sm * sph, s2 = sm * cph + cm * sph;
+                        cm = c2;
+                        sm = s2;
+                    }
 #pragma unroll
                     for (int n = m; n < P; n++) {
                         const T mine = v[tri(n) + m];
-                        const T oth = shfl_xor_t(mine, 1);
-                        if (act) {
-                            if (m == 0) {
-                                if (!part) atomicAdd(&ap[pk_re(n, 0)], mine);
-                            } else {
-                                const T re = part ? oth : mine, im = part ? mine : oth;
-                                if (!part) atomicAdd(&ap[pk_re(n, m)], re * cz + im * sz);
-                                else atomicAdd(&ap[pk_im(n, m)], -re * sz + im * cz);
-                            }
-                        }
+                        const T oth = dpp_f<DPP_XOR1>(mine);
+                        const int off = (m == 0) ? pk_re(n, 0) : (part ? pk_im(n, m) : pk_re(n, m));
+                        atomicAdd(&ap[off], (m == 0) ? mine : mine * cz + oth * sz);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -289,10 +352,11 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
         }
     }
     __syncthreads();
-    for (int idx = tid; idx < 16 * 2 * P2; idx += 256) {
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
-        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[idx];
+        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SST + r];
+        if (false) Lc[(size_t)box * 2 * P2 + r] = acc[idx];
     }
 }
 
@@ -312,24 +376,79 @@ __global__ void k_dmap(int level, int64_t off, int64_t nb, const uint64_t *__res
     dmap[((size_t)iz * side + iy) * side + ix] = (int32_t)(off + b);
 }
 
+// per-class stride (elements) of the padded rotation blocks, a multiple of 16 bytes
+template <typename T, int P>
+static int64_t wpad_stride()
+{
+    return 4 * (int64_t)M2LShape<T, P>::WB;  // a multiple of 16 bytes (padded rows)
+}
+
+// Padded rotation blocks of every polar-angle class in the tiled kernel's LDS layout:
+// [kind: forward S, backward R][part: Re, Im][order n][(n+1) x (n+1)], the Im block of
+// order n (n x n) embedded with a zero m = 0 row and column.
+template <typename T, int P>
+__global__ void k_wpad(int ntheta, const T *__restrict__ rot, T *__restrict__ wpad, int64_t stride)
+{
+    using S = M2LShape<T, P>;
+    const int th = blockIdx.x;
+    const int RS = rot_set_size(P);
+    const T *Rf = rot + ((size_t)th * ROT_NKIND + ROT_S_FWD) * RS;
+    const T *Rb = rot + ((size_t)th * ROT_NKIND + ROT_R_BACK) * RS;
+    for (int idx = threadIdx.x; idx < stride; idx += blockDim.x) {
+        T val = (T)0;
+        if (idx < 4 * S::WB) {
+            const int kind = idx / (2 * S::WB), rem = idx % (2 * S::WB);
+            const int pt = rem / S::WB, j = rem % S::WB;
+            int n = 0;
+            while (wrow_off<T>(n + 1) <= j) n++;
+            const int jj = j - wrow_off<T>(n), mp = jj / rowlen<T>(n), m = jj % rowlen<T>(n);
+            const T *blk = (kind ? Rb : Rf) + rot_block_off(n);
+            if (m <= n) {
+                if (pt == 0) val = blk[mp * (n + 1) + m];
+                else if (mp > 0 && m > 0) val = blk[(n + 1) * (n + 1) + (mp - 1) * n + (m - 1)];
+            }
+        }
+        wpad[(size_t)th * stride + idx] = val;
+    }
+}
+
+template <typename T, int P>
+static size_t wpad_build_t(lhf_plan *Pl, hipStream_t st)
+{
+    const int64_t stride = wpad_stride<T, P>();
+    if (hipMalloc(&Pl->wpad, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return 0;
+    k_wpad<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>(Pl->n_theta, (const T *)Pl->rot, (T *)Pl->wpad,
+                                                                     stride);
+    return (size_t)stride;
+}
+
+// parents per tile: as many as keep the LDS footprint within 64 KB (at most 4)
+template <typename T, int P>
+constexpr int tile_npar()
+{
+    return (sizeof(T) * (33 * (2 * P * P + 1) + 4 * M2LShape<T, P>::WB) + 4 * 32 <= 65536) ? 4 : 2;
+}
+
 template <typename T, int P>
 static size_t m2l_tile_shmem()
 {
-    using S = M2LShape<P>;
-    return sizeof(T) * (16 * 2 * P * P + 4 * S::WB) + sizeof(int) * 16;
+    using S = M2LShape<T, P>;
+    constexpr int NS = 8 * tile_npar<T, P>();
+    return sizeof(T) * ((NS + 1) * (2 * P * P + 1) + 4 * S::WB) + sizeof(int) * NS;
 }
 
 template <typename T, int P>
 static void launch_tile(const lhf_plan *Pl, int level, hipStream_t st)
 {
+    constexpr int NPAR = tile_npar<T, P>();
     const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
-    const int64_t ntiles = (npar + 1) / 2;
+    const int64_t ntiles = (npar + NPAR - 1) / NPAR;
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls};
     const size_t shm = m2l_tile_shmem<T, P>();
-    k_m2l_tile<T, P><<<dim3((unsigned)(per * 8)), dim3(256), shm, st>>>(
+    k_m2l_tile<T, P, NPAR><<<dim3((unsigned)(per * 8)), dim3(256), shm, st>>>(
         level, poff, npar, Pl->lev[level].off, Pl->lev[level].nb, Pl->bkey, Pl->bchild0, Pl->bnchild,
-        Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc, (const T *)Pl->rot, (const T *)Pl->zph, sch,
+        Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc, (const T *)Pl->wpad, wpad_stride<T, P>(), sch,
         Pl->sched_cls_theta);
 }
 
@@ -362,6 +481,30 @@ void m2l_tile_launch(const lhf_plan *Pl, int level, hipStream_t st)
         case 16: launch_tile<float, 16>(Pl, level, st); break;
         }
     }
+}
+
+bool wpad_build(lhf_plan *Pl, hipStream_t st)
+{
+    size_t r = 0;
+    if (Pl->precision == LHF_FP64) {
+        switch (Pl->p) {
+        case 4: r = wpad_build_t<double, 4>(Pl, st); break;
+        case 6: r = wpad_build_t<double, 6>(Pl, st); break;
+        case 8: r = wpad_build_t<double, 8>(Pl, st); break;
+        case 10: r = wpad_build_t<double, 10>(Pl, st); break;
+        case 12: r = wpad_build_t<double, 12>(Pl, st); break;
+        }
+    } else {
+        switch (Pl->p) {
+        case 4: r = wpad_build_t<float, 4>(Pl, st); break;
+        case 6: r = wpad_build_t<float, 6>(Pl, st); break;
+        case 8: r = wpad_build_t<float, 8>(Pl, st); break;
+        case 10: r = wpad_build_t<float, 10>(Pl, st); break;
+        case 12: r = wpad_build_t<float, 12>(Pl, st); break;
+        case 16: r = wpad_build_t<float, 16>(Pl, st); break;
+        }
+    }
+    return r != 0;
 }
 
 void dmap_build(const lhf_plan *Pl, int level, hipStream_t st)

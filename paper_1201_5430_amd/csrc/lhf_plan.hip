@@ -27,6 +27,7 @@ namespace lhf {
 lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st);
 bool m2l_tile_supported(int precision, int p);
 void dmap_build(const lhf_plan *Pl, int level, hipStream_t st);
+bool wpad_build(lhf_plan *Pl, hipStream_t st);
 
 static thread_local std::string g_err = "no error";
 
@@ -510,15 +511,23 @@ static lhf_status build_schedule(lhf_plan *P, const std::vector<int16_t> &cls, i
                         by[cls[code]].push_back({(int16_t)c, (int16_t)code});
                     }
     }
+    // within a class, entries go round-robin over the child positions so that
+    // consecutive translations (one wavefront's batch) have distinct targets
     std::vector<int16_t> start, ec, ed, cth;
     for (int k = 0; k < ntheta; k++) {
         if (by[k].empty()) continue;
         start.push_back((int16_t)ec.size());
         cth.push_back((int16_t)k);
-        for (auto &e : by[k]) {
-            ec.push_back(e.first);
-            ed.push_back(e.second);
-        }
+        std::vector<std::vector<int16_t>> perc(8);
+        for (auto &e : by[k]) perc[e.first].push_back(e.second);
+        size_t left = by[k].size();
+        for (size_t r = 0; left > 0; r++)
+            for (int c = 0; c < 8; c++)
+                if (r < perc[c].size()) {
+                    ec.push_back((int16_t)c);
+                    ed.push_back(perc[c][r]);
+                    left--;
+                }
     }
     start.push_back((int16_t)ec.size());
     P->sched_ncls = (int)cth.size();
@@ -562,6 +571,10 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     if (P->use_tile) {
         lhf_status s = build_schedule(P, cls, (int)theta.size(), st);
         if (s != LHF_OK) return s;
+        if (!wpad_build(P, st)) {
+            set_error("allocation of the padded rotation table failed");
+            return LHF_ERR_HIP;
+        }
         for (int l = 2; l <= P->depth; l++) {
             const size_t side = (size_t)1 << l;
             LHF_HIP(hipMalloc(&P->dmap[l], sizeof(int32_t) * side * side * side));
@@ -593,7 +606,7 @@ static void free_plan(lhf_plan *P)
         if (b) (void)hipFree(b);
     for (int l = 0; l <= MAXDEPTH; l++)
         if (P->dmap[l]) (void)hipFree(P->dmap[l]);
-    void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta};
+    void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta, P->wpad};
     for (void *b : sb)
         if (b) (void)hipFree(b);
     delete P;
