@@ -103,6 +103,8 @@ struct lhf_plan {
     int16_t *sched_c = nullptr;          // [1512] child position of the target
     int16_t *sched_dir = nullptr;        // [1512] direction code
     int16_t *sched_cls_theta = nullptr;  // [ncls] rotation-table class
+    int16_t *sched_row_start = nullptr;  // [ncls + 1] first row of each class in sched_rows
+    int16_t *sched_rows = nullptr;       // [nrows][8] direction codes by child position (-1: hole)
     int sched_ncls = 0;
     bool use_tile = false;
     void *wpad = nullptr;                // padded per-class rotation blocks (tiled M2L layout)

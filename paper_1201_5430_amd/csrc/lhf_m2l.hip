@@ -78,20 +78,26 @@ struct Vec16<double> {
 };
 
 // one output row: sum_m W[m] in[m], W read as 16-byte vectors
-template <typename T>
+template <typename T, bool WIDE>
 __device__ __attribute__((always_inline)) inline T rowdot(const T *W, const T *in, const int N1)
 {
-    using V = typename Vec16<T>::type;
-    constexpr int E = vecE<T>();
-    const V *Wv = (const V *)W;
     T a = 0;
+    if (WIDE) {
+        using V = typename Vec16<T>::type;
+        constexpr int E = vecE<T>();
+        const V *Wv = (const V *)W;
 #pragma unroll
-    for (int q = 0; q < (N1 + E - 1) / E; q++) {
-        const V w = Wv[q];
-        const T *wp = (const T *)&w;
+        for (int q = 0; q < (N1 + E - 1) / E; q++) {
+            const V w = Wv[q];
+            const T *wp = (const T *)&w;
 #pragma unroll
-        for (int e = 0; e < E; e++)
-            if (q * E + e < N1) a += wp[e] * in[q * E + e];
+            for (int e = 0; e < E; e++)
+                if (q * E + e < N1) a += wp[e] * in[q * E + e];
+        }
+    } else {
+        // element reads: every lane of a part reads the same address (LDS broadcast)
+#pragma unroll
+        for (int m = 0; m < N1; m++) a += W[m] * in[m];
     }
     return a;
 }
@@ -110,9 +116,16 @@ struct M2LSched {
     const int16_t *ent_c;      // [1512] child position of the target
     const int16_t *ent_dir;    // [1512] direction code of t = c_T - c_S
     int ncls;
+    // the same entries as rows of 8 (column = child position, -1 = hole)
+    const int16_t *row_start;  // [ncls+1] first row of each class
+    const int16_t *rows;       // [nrows][8] direction codes
 };
 
-template <typename T, int P, int NPAR>
+// OWN = true: each wavefront owns two of the tile's eight sibling groups and walks the
+// row table, so the 16 translations of a batch always have distinct targets that no
+// other wavefront touches: accumulation is a plain LDS read-add-write.  OWN = false:
+// the four wavefronts share the tile's targets and accumulate with LDS atomics.
+template <typename T, int P, int NPAR, bool OWN>
 __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64_t npar, int64_t loff, int64_t nbl,
                                                   const uint64_t *__restrict__ bkey, const int32_t *__restrict__ bchild0,
                                                   const int32_t *__restrict__ bnchild, const int32_t *__restrict__ dmap,
@@ -124,12 +137,20 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
     constexpr int P2 = P * P;
     // rotation rows per pinned group: two where registers allow, one for the largest vectors
     constexpr int RG = (sizeof(T) * P >= 64) ? 1 : 2;
-    extern __shared__ char smem[];
+    // 16-byte rotation-row reads for FP64; element reads (broadcast) for FP32
+    constexpr bool WIDE = sizeof(T) == 8;
+    // the next batch's source vector is loaded during the current batch where registers allow
+    constexpr bool PREFETCH = (int)sizeof(T) * S::NV <= 256;
     constexpr int NSLOT = 8 * NPAR;
     constexpr int SST = 2 * P2 + 1;              // odd slot stride: slots fall in different LDS banks
+    constexpr int NENT = 1512;                   // schedule entries of one sibling group
+    extern __shared__ char smem[];
     T *Wl = (T *)smem;                           // [2 kinds: fwd S, back R][2 parts][WB], 16-byte aligned
     T *acc = Wl + 4 * S::WB;                     // [NSLOT + 1][SST] (last slot absorbs inactive lanes)
-    int *slot_box = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] target box per slot (-1: none)
+    int *slot_xyz = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] packed target coordinates, -1: no box
+    int *slot_box = slot_xyz + NSLOT;            // [NSLOT] target box
+    int16_t *cst = (int16_t *)(slot_box + NSLOT);       // [ncls + 1] class starts (entries or rows)
+    int16_t *ent = cst + 64;                     // [NENT] (dir << 3) | child position (shared mode)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // XCD-aware tile order: consecutive tiles stay on one XCD (shared L2)
@@ -137,11 +158,12 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
     const int64_t per = (ntiles + 7) / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= ntiles) return;
+    const int ncls = sch.ncls;
 
     // slots: parent i (0..NPAR-1) x child position c (0..7)
     if (tid < NSLOT) {
         const int i = tid >> 3, c = tid & 7;
-        int box = -1;
+        int box = -1, xyz = -1;
         const int64_t q = (int64_t)NPAR * tile + i;
         if (q < npar) {
             const int64_t pb = poff + q;
@@ -149,8 +171,22 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
             for (int k = 0; k < nc; k++)
                 if ((int)(bkey[c0 + k] & 7u) == c) box = c0 + k;
         }
+        if (box >= 0) {
+            const uint64_t key = bkey[box];
+            uint32_t ix = 0, iy = 0, iz = 0;
+            for (int b = 0; b < level; b++) {
+                ix |= (uint32_t)((key >> (3 * b)) & 1u) << b;
+                iy |= (uint32_t)((key >> (3 * b + 1)) & 1u) << b;
+                iz |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
+            }
+            xyz = (int)(ix | (iy << 10) | (iz << 20));
+        }
         slot_box[tid] = box;
+        slot_xyz[tid] = xyz;
     }
+    if (!OWN)
+        for (int i = tid; i < NENT; i += 256) ent[i] = (int16_t)((sch.ent_dir[i] << 3) | sch.ent_c[i]);
+    for (int i = tid; i <= ncls; i += 256) cst[i] = OWN ? sch.row_start[i] : sch.cls_start[i];
     __syncthreads();
     for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
@@ -161,202 +197,257 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
     const int side = 1 << level;
     const int t = lane >> 2, pot = (lane >> 1) & 1, part = lane & 1;
 
-    for (int k = 0; k < sch.ncls; k++) {
-        const int e0 = sch.cls_start[k], cnt = sch.cls_start[k + 1] - e0;
-        __syncthreads();  // previous class finished with Wl
-        {
+    // per-lane description of one batch position: (slot, dir) from LDS, source box by one global load
+    struct Job {
+        int slot, dir, src;
+    };
+    auto setup = [&](int k, int r0) -> Job {
+        Job j{NSLOT, 0, -1};
+        if (k >= ncls) return j;
+        int slot, dir;
+        if (OWN) {
+            // r0 = row of the class; column = child position; wavefront w owns parents 2w, 2w+1
+            const int col = t >> 1;
+            dir = sch.rows[(size_t)(cst[k] + r0) * 8 + col];
+            if (dir < 0) return j;
+            slot = (2 * wave + (t & 1)) * 8 + col;
+        } else {
+            const int e0 = cst[k], cnt = cst[k + 1] - e0;
+            const int tr = r0 + wave * 16 + t;
+            if (tr >= NPAR * cnt) return j;
+            const int code = ent[e0 + tr / NPAR];
+            dir = code >> 3;
+            slot = (tr % NPAR) * 8 + (code & 7);
+        }
+        const int xyz = slot_xyz[slot];
+        if (xyz < 0) return j;
+        const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
+                  sz = (xyz >> 20) - (dir / 49 - 3);
+        if (sx < 0 || sy < 0 || sz < 0 || sx >= side || sy >= side || sz >= side) return j;
+        const int src = dmap[((size_t)sz * side + sy) * side + sx];
+        if (src < 0) return j;
+        j.slot = slot;
+        j.dir = dir;
+        j.src = src;
+        return j;
+    };
+    auto advance = [&](int &k, int &r0) {
+        if (OWN) {
+            r0 += 1;
+            if (k < ncls && r0 >= cst[k + 1] - cst[k]) {
+                k++;
+                r0 = 0;
+            }
+        } else {
+            r0 += 64;
+            if (k < ncls && r0 >= NPAR * (cst[k + 1] - cst[k])) {
+                k++;
+                r0 = 0;
+            }
+        }
+    };
+    auto load_part = [&](const Job &j, T *dst) {
+        const T *sp = M + (size_t)(j.src >= 0 ? j.src : 0) * 2 * P2 + pot * P2;
+#pragma unroll
+        for (int n = 0; n < P; n++)
+#pragma unroll
+            for (int m = 0; m <= n; m++)
+                dst[tri(n) + m] = (m == 0) ? (part ? (T)0 : sp[pk_re(n, 0)]) : sp[part ? pk_im(n, m) : pk_re(n, m)];
+    };
+
+    int k = 0, r0 = 0;           // current batch
+    int k1 = 0, r1 = 0;          // next batch
+    advance(k1, r1);
+    Job cur = setup(k, r0), nxt = setup(k1, r1);
+    T nv[PREFETCH ? S::NV : 1];
+    if (PREFETCH) load_part(cur, nv);
+    int staged = -1;
+    while (k < ncls) {
+        if (k != staged) {
             // stage the class's rotation blocks (precomputed in the LDS layout) with 16-byte loads
+            __syncthreads();
             const uint4 *src4 = (const uint4 *)(wpad + (size_t)cls_theta[k] * wstride);
             uint4 *dst4 = (uint4 *)Wl;
             constexpr int N16 = (int)(4 * S::WB * sizeof(T) / 16);
 #pragma unroll 8
             for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
+            __syncthreads();
+            staged = k;
         }
-        __syncthreads();
-        const int ntr = NPAR * cnt;
-        for (int r0 = 0; r0 < ntr; r0 += 64) {
-            // opaque per-batch offsets keep the compiler from hoisting every matrix entry
-            // of the class out of the batch loop (which would exhaust the register file)
-            int wfo = part * S::WB, wbo = 2 * S::WB + part * S::WB;
-            asm volatile("" : "+v"(wfo), "+v"(wbo));
-            const T *Wf = Wl + wfo;
-            const T *Wb = Wl + wbo;
-            const int tr = r0 + wave * 16 + t;
-            bool act = tr < ntr;
-            int slot = 0, src = -1, dir = 0;
-            if (act) {
-                // parents interleaved: a batch of 16 touches up to 16 distinct targets
-                const int par = tr % NPAR, e = e0 + tr / NPAR;
-                const int c = sch.ent_c[e];
-                dir = sch.ent_dir[e];
-                slot = par * 8 + c;
-                const int tb = slot_box[slot];
-                if (tb < 0) {
-                    act = false;
+        // opaque per-batch offsets keep the compiler from hoisting every matrix entry
+        // of the class out of the batch loop (which would exhaust the register file)
+        int wfo = part * S::WB, wbo = 2 * S::WB + part * S::WB;
+        asm volatile("" : "+v"(wfo), "+v"(wbo));
+        const T *Wf = Wl + wfo;
+        const T *Wb = Wl + wbo;
+
+        const Job j = cur;
+        const bool act = j.src >= 0;
+        T v[S::NV];
+        if (PREFETCH) {
+#pragma unroll
+            for (int q = 0; q < S::NV; q++) v[q] = nv[q];
+        } else {
+            load_part(j, v);
+        }
+        // look one batch further ahead: its source index now, its data right after
+        int k2 = k1, r2 = r1;
+        advance(k2, r2);
+        const Job nn = setup(k2, r2);
+        if (PREFETCH) load_part(nxt, nv);
+
+        const int dir = j.dir;
+        const int dx = dir % 7 - 3, dy = (dir / 7) % 7 - 3, dz = dir / 49 - 3;
+        const T tau = (T)sqrt((double)(dx * dx + dy * dy + dz * dz));
+        // e^{i phi} of the direction (phi = atan2(dy, dx); 0 on the z axis), FP64
+        double cph = 1.0, sph = 0.0;
+        {
+            const double rho = sqrt((double)(dx * dx + dy * dy));
+            if (rho > 0.0) {
+                cph = (double)dx / rho;
+                sph = (double)dy / rho;
+            }
+        }
+        const T sgn_in = part ? (T)1 : (T)-1;   // z-rotation by +phi: Re' = re c - im s, Im' = im c + re s
+        // 1. rotate about z by +phi using the partner lane's other part
+        {
+            double cm = 1.0, sm = 0.0;
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const T cz = (T)cm, sz = (T)sm * sgn_in;
+#pragma unroll
+                for (int n = m; n < P; n++) {
+                    const T mine = v[tri(n) + m];
+                    const T oth = dpp_f<DPP_XOR1>(mine);
+                    if (m > 0) v[tri(n) + m] = mine * cz + oth * sz;
+                }
+                const double c2 = cm * cph - sm * sph, s2 = sm * cph + cm * sph;
+                cm = c2;
+                sm = s2;
+            }
+        }
+        // 2. rotation about y (forward, S basis), two output rows per pinned group
+#pragma unroll
+        for (int n = 0; n < P; n++) {
+            T in[P];
+#pragma unroll
+            for (int m = 0; m <= n; m++) in[m] = v[tri(n) + m];
+            const T *W = Wf + wrow_off<T>(n);
+#pragma unroll
+            for (int mp = 0; mp <= n; mp += RG) {
+                T a0 = rowdot<T, WIDE>(W + mp * rowlen<T>(n), in, n + 1);
+                if (RG == 2 && mp + 1 <= n) {
+                    T a1 = rowdot<T, WIDE>(W + (mp + 1) * rowlen<T>(n), in, n + 1);
+                    asm volatile("" : "+v"(a0), "+v"(a1));
+                    v[tri(n) + mp] = a0;
+                    v[tri(n) + mp + 1] = a1;
                 } else {
-                    const uint64_t key = bkey[tb];
-                    uint32_t ix = 0, iy = 0, iz = 0;
-                    for (int b = 0; b < level; b++) {
-                        ix |= (uint32_t)((key >> (3 * b)) & 1u) << b;
-                        iy |= (uint32_t)((key >> (3 * b + 1)) & 1u) << b;
-                        iz |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
-                    }
-                    const int sx = (int)ix - (dir % 7 - 3), sy = (int)iy - ((dir / 7) % 7 - 3),
-                              sz = (int)iz - (dir / 49 - 3);
-                    if (sx < 0 || sy < 0 || sz < 0 || sx >= side || sy >= side || sz >= side) {
-                        act = false;
-                    } else {
-                        src = dmap[((size_t)sz * side + sy) * side + sx];
-                        if (src < 0) act = false;
-                    }
+                    asm volatile("" : "+v"(a0));
+                    v[tri(n) + mp] = a0;
                 }
             }
-            const int dx = dir % 7 - 3, dy = (dir / 7) % 7 - 3, dz = dir / 49 - 3;
-            const T tau = (T)sqrt((double)(dx * dx + dy * dy + dz * dz));
-            // e^{i phi} of the direction (phi = atan2(dy, dx); 0 on the z axis), FP64
-            double cph = 1.0, sph = 0.0;
-            {
-                const double rho = sqrt((double)(dx * dx + dy * dy));
-                if (rho > 0.0) {
-                    cph = (double)dx / rho;
-                    sph = (double)dy / rho;
+        }
+        // 3+4. per column m: coaxial (S|R) shift out_n = tau^-(n+1) sum_n' (n+n')! tau^-n' in_n'
+        //      (chi to order P), then the R-conversion (eq. rcr1, scaled)
+        //        phi~ = phi + i tau m/n chi ,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
+        {
+            const T itau = (T)1 / tau;
+            T pw[P + 2];
+            pw[0] = (T)1;
+#pragma unroll
+            for (int k = 1; k <= P + 1; k++) pw[k] = pw[k - 1] * itau;
+            // lane roles as 0/1 weights (branch-free): phi lanes take the chi of the other part
+            const T wphi = pot ? (T)0 : (T)1, wchi = pot ? (T)1 : (T)0;
+            const T sconv = part ? (T)1 : (T)-1;
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                T col[P];
+#pragma unroll
+                for (int n2 = m; n2 < P; n2++) col[n2] = v[tri(n2) + m] * pw[n2];
+                T out[P + 1];
+#pragma unroll
+                for (int n = m; n <= P; n++) {
+                    T a = 0;
+#pragma unroll
+                    for (int n2 = m; n2 < P; n2++) a += (T)dfact(n + n2) * col[n2];
+                    out[n] = a * pw[n + 1];
+                }
+#pragma unroll
+                for (int n = m; n < P; n++) {
+                    const T other = dpp_f<DPP_XOR3>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
+                    const T fphi = (n > 0) ? tau * (T)((double)m / (double)n) * sconv * wphi : (T)0;
+                    const T fchi = -tau * (T)(1.0 / (double)(n + 1)) * wchi;
+                    v[tri(n) + m] = out[n] + fphi * other + fchi * out[n + 1];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // 5. back-rotation about y (R basis)
+#pragma unroll
+        for (int n = 0; n < P; n++) {
+            T in[P];
+#pragma unroll
+            for (int m = 0; m <= n; m++) in[m] = v[tri(n) + m];
+            const T *W = Wb + wrow_off<T>(n);
+#pragma unroll
+            for (int mp = 0; mp <= n; mp += RG) {
+                T a0 = rowdot<T, WIDE>(W + mp * rowlen<T>(n), in, n + 1);
+                if (RG == 2 && mp + 1 <= n) {
+                    T a1 = rowdot<T, WIDE>(W + (mp + 1) * rowlen<T>(n), in, n + 1);
+                    asm volatile("" : "+v"(a0), "+v"(a1));
+                    v[tri(n) + mp] = a0;
+                    v[tri(n) + mp + 1] = a1;
+                } else {
+                    asm volatile("" : "+v"(a0));
+                    v[tri(n) + mp] = a0;
                 }
             }
-            const T sgn_in = part ? (T)1 : (T)-1;   // z-rotation by +phi: Re' = re c - im s, Im' = im c + re s
-            T v[S::NV];
-            // 1. load this lane's part (Re or Im) of its potential, all loads in flight at once,
-            //    then rotate about z by +phi using the partner lane's other part
-            {
-                const T *sp = M + (size_t)(act ? src : 0) * 2 * P2 + pot * P2 + (part ? 0 : 0);
+        }
+        // 6. back-rotation about z (-phi) and accumulation into the target slot (branch-free;
+        //    inactive lanes add into the spare slot)
+        {
+            T *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + pot * P2;
+        T *spare = acc + (size_t)NSLOT * SST + pot * P2;
+            const T sgn_out = part ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
+            double cm = 1.0, sm = 0.0;
 #pragma unroll
-                for (int n = 0; n < P; n++)
-#pragma unroll
-                    for (int m = 0; m <= n; m++)
-                        v[tri(n) + m] = (m == 0) ? (part ? (T)0 : sp[pk_re(n, 0)]) : sp[part ? pk_im(n, m) : pk_re(n, m)];
-                double cm = 1.0, sm = 0.0;
-#pragma unroll
-                for (int m = 0; m < P; m++) {
-                    const T cz = (T)cm, sz = (T)sm * sgn_in;
-#pragma unroll
-                    for (int n = m; n < P; n++) {
-                        const T mine = v[tri(n) + m];
-                        const T oth = dpp_f<DPP_XOR1>(mine);
-                        if (m > 0) v[tri(n) + m] = mine * cz + oth * sz;
-                    }
+            for (int m = 0; m < P; m++) {
+                const T cz = (T)cm, sz = (T)sm * sgn_out;
+                {
                     const double c2 = cm * cph - sm * sph, s2 = sm * cph + cm * sph;
                     cm = c2;
                     sm = s2;
                 }
-            }
-            // 2. rotation about y (forward, S basis), two output rows per pinned group
 #pragma unroll
-            for (int n = 0; n < P; n++) {
-                T in[P];
-#pragma unroll
-                for (int m = 0; m <= n; m++) in[m] = v[tri(n) + m];
-                const T *W = Wf + wrow_off<T>(n);
-#pragma unroll
-                for (int mp = 0; mp <= n; mp += RG) {
-                    T a0 = rowdot<T>(W + mp * rowlen<T>(n), in, n + 1);
-                    if (RG == 2 && mp + 1 <= n) {
-                        T a1 = rowdot<T>(W + (mp + 1) * rowlen<T>(n), in, n + 1);
-                        asm volatile("" : "+v"(a0), "+v"(a1));
-                        v[tri(n) + mp] = a0;
-                        v[tri(n) + mp + 1] = a1;
+                for (int n = m; n < P; n++) {
+                    const T mine = v[tri(n) + m];
+                    const T oth = dpp_f<DPP_XOR1>(mine);
+                    const int off = (m == 0) ? pk_re(n, 0) : (part ? pk_im(n, m) : pk_re(n, m));
+                    const T val = (m == 0) ? mine : mine * cz + oth * sz;
+                    if (OWN) {
+                        // m = 0 has no imaginary part: the Im lane must not touch the Re entry
+                        T *dst = (m == 0 && part) ? spare + off : ap + off;
+                        *dst += val;
                     } else {
-                        asm volatile("" : "+v"(a0));
-                        v[tri(n) + mp] = a0;
+                        atomicAdd(&ap[off], val);
                     }
                 }
-            }
-            // 3+4. per column m: coaxial (S|R) shift out_n = tau^-(n+1) sum_n' (n+n')! tau^-n' in_n'
-            //      (chi to order P), then the R-conversion (eq. rcr1, scaled)
-            //        phi~ = phi + i tau m/n chi ,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
-            {
-                const T itau = (T)1 / tau;
-                T pw[P + 2];
-                pw[0] = (T)1;
-#pragma unroll
-                for (int k = 1; k <= P + 1; k++) pw[k] = pw[k - 1] * itau;
-                // lane roles as 0/1 weights (branch-free): phi lanes take the chi of the other part
-                const T wphi = pot ? (T)0 : (T)1, wchi = pot ? (T)1 : (T)0;
-                const T sconv = part ? (T)1 : (T)-1;
-#pragma unroll
-                for (int m = 0; m < P; m++) {
-                    T col[P];
-#pragma unroll
-                    for (int n2 = m; n2 < P; n2++) col[n2] = v[tri(n2) + m] * pw[n2];
-                    T out[P + 1];
-#pragma unroll
-                    for (int n = m; n <= P; n++) {
-                        T a = 0;
-#pragma unroll
-                        for (int n2 = m; n2 < P; n2++) a += (T)dfact(n + n2) * col[n2];
-                        out[n] = a * pw[n + 1];
-                    }
-#pragma unroll
-                    for (int n = m; n < P; n++) {
-                        const T other = dpp_f<DPP_XOR3>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
-                        const T fphi = (n > 0) ? tau * (T)((double)m / (double)n) * sconv * wphi : (T)0;
-                        const T fchi = -tau * (T)(1.0 / (double)(n + 1)) * wchi;
-                        v[tri(n) + m] = out[n] + fphi * other + fchi * out[n + 1];
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-            // 5. back-rotation about y (R basis)
-#pragma unroll
-            for (int n = 0; n < P; n++) {
-                T in[P];
-#pragma unroll
-                for (int m = 0; m <= n; m++) in[m] = v[tri(n) + m];
-                const T *W = Wb + wrow_off<T>(n);
-#pragma unroll
-                for (int mp = 0; mp <= n; mp += RG) {
-                    T a0 = rowdot<T>(W + mp * rowlen<T>(n), in, n + 1);
-                    if (RG == 2 && mp + 1 <= n) {
-                        T a1 = rowdot<T>(W + (mp + 1) * rowlen<T>(n), in, n + 1);
-                        asm volatile("" : "+v"(a0), "+v"(a1));
-                        v[tri(n) + mp] = a0;
-                        v[tri(n) + mp + 1] = a1;
-                    } else {
-                        asm volatile("" : "+v"(a0));
-                        v[tri(n) + mp] = a0;
-                    }
-                }
-            }
-            // 6. back-rotation about z (-phi) and accumulation into the target slot (branch-free;
-            //    inactive lanes add into the spare slot)
-            {
-                T *ap = acc + (size_t)(act ? slot : NSLOT) * SST + pot * P2 + (part ? 0 : 0);
-                const T sgn_out = part ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
-                double cm = 1.0, sm = 0.0;
-#pragma unroll
-                for (int m = 0; m < P; m++) {
-                    const T cz = (T)cm, sz = (T)sm * sgn_out;
-                    {
-                        const double c2 = cm * cph - sm * sph, s2 = sm * cph + cm * sph;
-                        cm = c2;
-                        sm = s2;
-                    }
-#pragma unroll
-                    for (int n = m; n < P; n++) {
-                        const T mine = v[tri(n) + m];
-                        const T oth = dpp_f<DPP_XOR1>(mine);
-                        const int off = (m == 0) ? pk_re(n, 0) : (part ? pk_im(n, m) : pk_re(n, m));
-                        atomicAdd(&ap[off], (m == 0) ? mine : mine * cz + oth * sz);
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
+
+        cur = nxt;
+        nxt = nn;
+        k = k1;
+        r0 = r1;
+        k1 = k2;
+        r1 = r2;
     }
     __syncthreads();
     for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
         if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SST + r];
-        if (false) Lc[(size_t)box * 2 * P2 + r] = acc[idx];
     }
 }
 
@@ -422,31 +513,43 @@ static size_t wpad_build_t(lhf_plan *Pl, hipStream_t st)
     return (size_t)stride;
 }
 
-// parents per tile: as many as keep the LDS footprint within 64 KB (at most 4)
+// LDS footprint of a tile with NPAR sibling groups (OWN: no entry list in LDS)
+template <typename T, int P>
+constexpr size_t tile_bytes(int npar, bool own)
+{
+    return sizeof(T) * ((size_t)(8 * npar + 1) * (2 * P * P + 1) + 4 * M2LShape<T, P>::WB) + sizeof(int) * 2 * 8 * npar +
+           sizeof(int16_t) * (64 + (own ? 0 : 1512));
+}
+// ownership mode (8 sibling groups, no atomics) when it fits in 64 KB; otherwise shared mode
+// with as many sibling groups (at most 4) as fit
+template <typename T, int P>
+constexpr bool tile_own()
+{
+    return tile_bytes<T, P>(8, true) <= 65536;
+}
 template <typename T, int P>
 constexpr int tile_npar()
 {
-    return (sizeof(T) * (33 * (2 * P * P + 1) + 4 * M2LShape<T, P>::WB) + 4 * 32 <= 65536) ? 4 : 2;
+    return tile_own<T, P>() ? 8 : (tile_bytes<T, P>(4, false) <= 65536 ? 4 : 2);
 }
 
 template <typename T, int P>
 static size_t m2l_tile_shmem()
 {
-    using S = M2LShape<T, P>;
-    constexpr int NS = 8 * tile_npar<T, P>();
-    return sizeof(T) * ((NS + 1) * (2 * P * P + 1) + 4 * S::WB) + sizeof(int) * NS;
+    return tile_bytes<T, P>(tile_npar<T, P>(), tile_own<T, P>());
 }
 
 template <typename T, int P>
 static void launch_tile(const lhf_plan *Pl, int level, hipStream_t st)
 {
     constexpr int NPAR = tile_npar<T, P>();
+    constexpr bool OWN = tile_own<T, P>();
     const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
     const int64_t ntiles = (npar + NPAR - 1) / NPAR;
     const int64_t per = (ntiles + 7) / 8;
-    M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls};
+    M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
     const size_t shm = m2l_tile_shmem<T, P>();
-    k_m2l_tile<T, P, NPAR><<<dim3((unsigned)(per * 8)), dim3(256), shm, st>>>(
+    k_m2l_tile<T, P, NPAR, OWN><<<dim3((unsigned)(per * 8)), dim3(256), shm, st>>>(
         level, poff, npar, Pl->lev[level].off, Pl->lev[level].nb, Pl->bkey, Pl->bchild0, Pl->bnchild,
         Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc, (const T *)Pl->wpad, wpad_stride<T, P>(), sch,
         Pl->sched_cls_theta);

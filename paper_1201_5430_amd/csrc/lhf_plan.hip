@@ -531,6 +531,23 @@ static lhf_status build_schedule(lhf_plan *P, const std::vector<int16_t> &cls, i
     }
     start.push_back((int16_t)ec.size());
     P->sched_ncls = (int)cth.size();
+    // the same entries as rows of 8 indexed by child position (holes = -1)
+    std::vector<int16_t> rstart, rows;
+    for (int k = 0; k < ntheta; k++) {
+        if (by[k].empty()) continue;
+        rstart.push_back((int16_t)(rows.size() / 8));
+        std::vector<std::vector<int16_t>> perc(8);
+        for (auto &e : by[k]) perc[e.first].push_back(e.second);
+        size_t nr = 0;
+        for (int c = 0; c < 8; c++) nr = std::max(nr, perc[c].size());
+        for (size_t r = 0; r < nr; r++)
+            for (int c = 0; c < 8; c++) rows.push_back(r < perc[c].size() ? perc[c][r] : (int16_t)-1);
+    }
+    rstart.push_back((int16_t)(rows.size() / 8));
+    LHF_HIP(hipMalloc(&P->sched_row_start, sizeof(int16_t) * rstart.size()));
+    LHF_HIP(hipMalloc(&P->sched_rows, sizeof(int16_t) * rows.size()));
+    LHF_HIP(hipMemcpyAsync(P->sched_row_start, rstart.data(), sizeof(int16_t) * rstart.size(), hipMemcpyHostToDevice, st));
+    LHF_HIP(hipMemcpyAsync(P->sched_rows, rows.data(), sizeof(int16_t) * rows.size(), hipMemcpyHostToDevice, st));
     LHF_HIP(hipMalloc(&P->sched_cls_start, sizeof(int16_t) * start.size()));
     LHF_HIP(hipMalloc(&P->sched_c, sizeof(int16_t) * ec.size()));
     LHF_HIP(hipMalloc(&P->sched_dir, sizeof(int16_t) * ed.size()));
@@ -606,7 +623,8 @@ static void free_plan(lhf_plan *P)
         if (b) (void)hipFree(b);
     for (int l = 0; l <= MAXDEPTH; l++)
         if (P->dmap[l]) (void)hipFree(P->dmap[l]);
-    void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta, P->wpad};
+    void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta, P->wpad, P->sched_row_start,
+                  P->sched_rows};
     for (void *b : sb)
         if (b) (void)hipFree(b);
     delete P;

@@ -158,3 +158,21 @@ def test_fp32_path_matches_fp64_oracle(oracle, p, depth):
     ev, es = _rel(v, vr), _rel(s, sr)
     print(f"FP32 p={p} depth={depth}: rel L2 v {ev:.3e} s {es:.3e}", flush=True)
     assert ev < 2e-6 and es < 2e-6
+
+
+@pytest.mark.parametrize("p", [4, 6, 8, 10])
+def test_fp32_batched_m2l_orders(oracle, p):
+    # every order with a batched-M2L instantiation (both accumulation modes), depth 5 so that
+    # tiles hold full sibling groups and the domain boundary cuts others
+    rng = np.random.default_rng(60 + p)
+    n = 30000
+    x = rng.uniform(0, 1, (n, 3)).astype(np.float32).astype(np.float64)
+    w = rng.normal(size=(n, 3)).astype(np.float32).astype(np.float64)
+    a = float(np.float32(0.5 * n ** (-1 / 3)))
+    samp = rng.choice(n, 40, replace=False)
+    vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
+    m = ~np.isnan(vr[:, 0])
+    v, s, _ = _gpu_fmm(x, w, a, p, 5, precision=1)
+    ev, es = _rel(v[m], vr[m]), _rel(s[m], sr[m])
+    print(f"FP32 p={p} depth=5 sampled: rel L2 v {ev:.3e} s {es:.3e}", flush=True)
+    assert ev < 2e-6 and es < 2e-6
