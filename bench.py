@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 METRIC = "vortex elements/s (v + stretching) at rel err 1e-6; FP32-MFMA vs FP64 speedup"
 PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP32_VALU_TFLOPS = 78.6  # non-packed FP32 FMA, same unit count as FP64
 PEAK_HBM_GBS = 8000.0
 
 
@@ -46,6 +47,41 @@ def f_m2l(p: int) -> int:
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(which):
+    """HBM bytes per M2L launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
+    or None when the kernel source changed after the counters were taken"""
+    import hashlib
+    import re
+    try:
+        md = open(os.path.join(ROOT, "profiles", "m2l_tile_cube1m_hbm.md")).read()
+        js = json.loads(re.search(r"```json\n(.*?)\n```", md, re.S).group(1))
+        src = open(os.path.join(ROOT, "paper_1201_5430_amd", "csrc", "lhf_m2l.hip"), "rb").read()
+        if hashlib.sha256(src).hexdigest()[:16] != js["source_sha256_prefix"]:
+            return None
+        return js[which]["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def accuracy(cfg, v, s, n_targets=1000):
+    """relative L2 error of v and s against the oracle's split-kernel direct sum on sampled
+    targets (the paper measures on 1000 random source points); oracle leg of the benchmark"""
+    import numpy as np
+    import oracle
+    import workloads
+    x, w, a, d = cfg["x"], cfg["w"], cfg["a"], cfg["depth"]
+    if cfg.get("precision") == "fp32":
+        x = x.astype(np.float32).astype(np.float64)
+        w = w.astype(np.float32).astype(np.float64)
+        a = float(np.float32(a))
+    tg = workloads.sample_targets(x.shape[0], n_targets, seed=1000)
+    vd, sd = oracle.direct(x, w, a, mode=oracle.DIRECT_SPLIT, depth=d, targets=tg)
+    ev = float(np.linalg.norm(v[tg] - vd) / np.linalg.norm(vd))
+    es = float(np.linalg.norm(s[tg] - sd) / np.linalg.norm(sd))
+    return {"rel_l2_v": ev, "rel_l2_s": es, "targets": int(len(tg)),
+            "reference": "split-kernel direct sum (Gaussian core between adjacent leaves, singular beyond), FP64 oracle"}
 
 
 def cpu_baseline(cfg, n_leaves=64):
@@ -77,14 +113,27 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cube1m_fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 run on the same input")
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="only copy a buffer of this many MiB on the device (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
+
+    if args.calib_copy:
+        nbytes = args.calib_copy << 20
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": nbytes}), flush=True)
+        return
 
     import paper_1201_5430_amd as lhf
     import workloads
@@ -92,59 +141,63 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
 
-    cfg = workloads.make(args.workload)
-    prec = lhf.FP64 if cfg["precision"] == "fp64" else lhf.FP32
-    dt = torch.float64 if prec == lhf.FP64 else torch.float32
-    n, p, d, a = cfg["n"], cfg["p"], cfg["depth"], cfg["a"]
-    log(f"bench: workload {args.workload} N={n} p={p} depth={d} precision={cfg['precision']}")
-    xt = torch.from_numpy(cfg["x"]).to(device="cuda", dtype=dt)
-    wt = torch.from_numpy(cfg["w"]).to(device="cuda", dtype=dt)
-    v = torch.empty_like(wt)
-    s = torch.empty_like(wt)
+    def run(name, steps, warmup):
+        cfg = workloads.make(name)
+        prec = lhf.FP64 if cfg["precision"] == "fp64" else lhf.FP32
+        dt = torch.float64 if prec == lhf.FP64 else torch.float32
+        n, p, d, a = cfg["n"], cfg["p"], cfg["depth"], cfg["a"]
+        log(f"bench: workload {name} N={n} p={p} depth={d} precision={cfg['precision']}")
+        xt = torch.from_numpy(cfg["x"]).to(device="cuda", dtype=dt)
+        wt = torch.from_numpy(cfg["w"]).to(device="cuda", dtype=dt)
+        v = torch.empty_like(wt)
+        s = torch.empty_like(wt)
 
-    def step(profile=False):
-        plan = lhf.Plan(xt, a, p=p, depth=d, precision=prec)
-        if profile:
-            plan.profile_begin(1)
-        plan.execute(wt, v, s)
-        ph = None
-        if profile:
-            ph, _ = plan.profile_end()
-        st = plan.stats()
-        plan.close()
-        return ph, st
+        def step(profile=False):
+            plan = lhf.Plan(xt, a, p=p, depth=d, precision=prec)
+            if profile:
+                plan.profile_begin(1)
+            plan.execute(wt, v, s)
+            ph = None
+            if profile:
+                ph, _ = plan.profile_end()
+            st = plan.stats()
+            plan.close()
+            return ph, st
 
-    for k in range(args.warmup):
-        step()
-        log(f"bench: warmup {k + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    phases = {k: 0.0 for k in lhf.PHASES}
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ph, st = step(profile=True)
-        for kk in phases:
-            phases[kk] += ph[kk]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log(f"bench: {args.steps} timed steps done")
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    ph_step = {k: vv / args.steps for k, vv in phases.items()}
-    exec_ms = sum(ph_step.values())
+        for k in range(warmup):
+            step()
+            log(f"bench: {name} warmup {k + 1}/{warmup} done")
+        torch.cuda.synchronize()
+        phases = {k: 0.0 for k in lhf.PHASES}
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ph, st = step(profile=True)
+            for kk in phases:
+                phases[kk] += ph[kk]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        log(f"bench: {name} {steps} timed steps done")
+        ms_step = (t1 - t0) * 1e3 / steps
+        ph_step = {k: vv / steps for k, vv in phases.items()}
+        exec_ms = sum(vv for kk, vv in ph_step.items() if kk != "m2l")  # m2l is part of "down"
+        launches = sum(1 for l in range(2, d + 1) if st["boxes"][l] > 0)
+        flops = st["n_m2l"] * f_m2l(p)
+        achieved = flops / (ph_step["m2l"] * 1e-3) / 1e12
+        peak = PEAK_FP64_TFLOPS if prec == lhf.FP64 else PEAK_FP32_MFMA_TFLOPS
+        return dict(cfg=cfg, prec=prec, n=n, p=p, d=d, ms_step=ms_step, ph_step=ph_step, exec_ms=exec_ms,
+                    st=st, launches=launches, flops=flops, achieved=achieved, peak=peak,
+                    v=v.double().cpu().numpy(), s=s.double().cpu().numpy())
 
-    # dominant kernel: downward pass (M2L + L2L), one launch per level 2..d
-    launches = sum(1 for l in range(2, d + 1) if st["boxes"][l] > 0)
-    flops = st["n_m2l"] * f_m2l(p)
-    down_s = ph_step["down"] * 1e-3
-    achieved = flops / down_s / 1e12
-    peak = PEAK_FP64_TFLOPS if prec == lhf.FP64 else PEAK_FP32_MFMA_TFLOPS
+    r = run(args.workload, args.steps, args.warmup)
+    cfg, prec, n, p, d = r["cfg"], r["prec"], r["n"], r["p"], r["d"]
     out = {
         "metric": METRIC,
-        "value": n / (ms_step * 1e-3),
+        "value": n / (r["ms_step"] * 1e-3),
         "unit": "elements/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -153,28 +206,46 @@ def main():
         "config": {"workload": args.workload, "n": n, "p": p, "depth": d, "precision": cfg["precision"],
                    "distribution": "uniform in [0,1)^3, omega ~ N(0,1)^3, Gaussian core a = 0.5 N^(-1/3)",
                    "step": "plan (keys, sort, octree, lists, tables) + execute (P2M, M2M, M2L/L2L, L2P, P2P)"},
-        "execute_ms": exec_ms,
-        "plan_ms": ms_step - exec_ms,
-        "execute_only_elements_per_s": n / (exec_ms * 1e-3),
-        "phases_ms": ph_step,
-        "counts": {"m2l": st["n_m2l"], "p2p_pairs": st["n_p2p_pairs"], "boxes": st["boxes"]},
+        "execute_ms": r["exec_ms"],
+        "plan_ms": r["ms_step"] - r["exec_ms"],
+        "execute_only_elements_per_s": n / (r["exec_ms"] * 1e-3),
+        "phases_ms": r["ph_step"],
+        "counts": {"m2l": r["st"]["n_m2l"], "p2p_pairs": r["st"]["n_p2p_pairs"], "boxes": r["st"]["boxes"]},
         "roofline": {
-            "kernel": "k_down (M2L + L2L, one launch per level)",
-            "bound": "alu" if prec == lhf.FP64 else "mfma",
-            "achieved": achieved,
-            "peak": peak,
+            "kernel": "k_m2l_tile (batched M2L), one launch per level 2..d",
+            "bound": "alu",
+            "achieved": r["achieved"],
+            "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / peak,
-            "traffic": None,
-            "launches_per_step": launches,
-            "avg_launch_ms": ph_step["down"] / launches,
-            "flop_per_launch": flops / launches,
+            "frac": r["achieved"] / PEAK_FP64_TFLOPS,
+            "traffic": measured_traffic("fp64" if prec == lhf.FP64 else "fp32"),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
+            "launches_per_step": r["launches"],
+            "avg_launch_ms": r["ph_step"]["m2l"] / r["launches"],
+            "flop_per_launch": r["flops"] / r["launches"],
             "flop_per_m2l": f_m2l(p),
         },
     }
+    r32 = None
+    if args.workload == "cube1m_fp64" and not args.no_fp32:
+        # the mixed-precision path on the same input (FP32 elements and expansions, p = 10)
+        r32 = run("cube1m_fp32", args.steps, args.warmup)
+        out["fp32"] = {
+            "workload": "cube1m_fp32", "p": r32["p"], "ms_per_step": r32["ms_step"],
+            "elements_per_s": r32["n"] / (r32["ms_step"] * 1e-3),
+            "execute_only_elements_per_s": r32["n"] / (r32["exec_ms"] * 1e-3),
+            "speedup_vs_fp64": r["ms_step"] / r32["ms_step"],
+            "phases_ms": r32["ph_step"],
+            "m2l_achieved_tflops": r32["achieved"],
+            "m2l_frac_of_fp32_vector_peak": r32["achieved"] / PEAK_FP32_VALU_TFLOPS,
+        }
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline (sampled) ...")
         out["cpu_baseline"] = cpu_baseline(cfg)
+        log("bench: accuracy against the oracle's direct sum on 1000 sampled targets ...")
+        out["cpu_baseline"]["accuracy_fp64_path"] = accuracy(cfg, r["v"], r["s"])
+        if r32 is not None:
+            out["cpu_baseline"]["accuracy_fp32_path"] = accuracy(r32["cfg"], r32["v"], r32["s"])
     print(json.dumps(out), flush=True)
 
 

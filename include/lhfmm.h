@@ -122,11 +122,11 @@ const char *lhf_last_error(void);
  * lhf_profile_begin(plan, k), each of the next k calls of lhf_execute records
  * events between its phases; lhf_profile_end waits for them and returns the
  * summed milliseconds per phase over those calls in phase_ms[LHF_NPHASE]:
- *   0 gather omega, 1 P2M, 2 M2M, 3 downward pass (L2L + M2L, one launch per
- *   level 2..d), 4 L2P, 5 P2P + combine + un-permute,
+ *   0 gather omega, 1 P2M, 2 M2M, 3 downward pass (L2L + M2L, levels 2..d),
+ *   4 L2P, 5 P2P + combine + un-permute, 6 the M2L launches alone (part of 3),
  * and the number of profiled calls in *n_exec.  Recording adds no host
  * synchronisation; begin/end are called outside timed or captured regions. */
-#define LHF_NPHASE 6
+#define LHF_NPHASE 7
 lhf_status lhf_profile_begin(lhf_plan *plan, int32_t max_exec);
 lhf_status lhf_profile_end(lhf_plan *plan, double *phase_ms, int32_t *n_exec);
 

@@ -26,7 +26,7 @@ STATUS = {0: "LHF_OK", 1: "LHF_WARN_CORE_SPLIT", -1: "LHF_ERR_ARG", -2: "LHF_ERR
 EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_execute", "lhf_execute_parts", "lhf_evaluate",
            "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version", "lhf_profile_begin",
            "lhf_profile_end")
-PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p")
+PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 
 
 class Desc(C.Structure):

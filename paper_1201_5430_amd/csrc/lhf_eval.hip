@@ -748,7 +748,8 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
     const int tpb = 256;
     const unsigned nblk = (unsigned)((n + tpb - 1) / tpb);
     hipEvent_t *ev = nullptr;
-    if (P->prof_ev && P->prof_used < P->prof_cap) ev = P->prof_ev + (size_t)(P->prof_used++) * (LHF_NPHASE + 1);
+    if (P->prof_ev && P->prof_used < P->prof_cap) ev = P->prof_ev + (size_t)(P->prof_used++) * PROF_EV_PER_EXEC;
+    // ev[0..6]: phase boundaries; ev[7 + 2l], ev[8 + 2l]: around the M2L launch of level l
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], st);
     };
@@ -769,11 +770,25 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         }
         mark(3);
         for (int l = 2; l <= d; l++) {
-            if (P->lev[l].nb == 0) continue;
-            hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l,
-                               P->use_tile ? 0 : 1, P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir,
-                               (const T *)M, Lc, rot, zph, P->dir_theta, coax);
-            if (P->use_tile) m2l_tile_launch(P, l, st);
+            if (P->lev[l].nb == 0) {
+                mark(7 + 2 * l);
+                mark(8 + 2 * l);
+                continue;
+            }
+            if (P->use_tile) {
+                hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 0,
+                                   P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M, Lc,
+                                   rot, zph, P->dir_theta, coax);
+                mark(7 + 2 * l);
+                m2l_tile_launch(P, l, st);
+                mark(8 + 2 * l);
+            } else {
+                mark(7 + 2 * l);
+                hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 1,
+                                   P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M, Lc,
+                                   rot, zph, P->dir_theta, coax);
+                mark(8 + 2 * l);
+            }
         }
         mark(4);
         const int TRI = p * (p + 1) / 2;
@@ -784,6 +799,10 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
     } else {
         mark(2);
         mark(3);
+        for (int l = 2; l <= d; l++) {
+            mark(7 + 2 * l);
+            mark(8 + 2 * l);
+        }
         mark(4);
     }
     mark(5);

@@ -29,6 +29,7 @@ constexpr int MAXDEPTH = 10;
 constexpr int NDIR_M2L = 343;    // codes (dx+3) + 7 (dy+3) + 49 (dz+3), dx..dz in [-3,3]
 constexpr int NDIR = NDIR_M2L + 16;  // + 8 child->parent and 8 parent->child directions
 constexpr int VMAX = 189;        // interaction-list bound per box (6^3 - 3^3)
+constexpr int PROF_EV_PER_EXEC = 7 + 2 * (MAXDEPTH + 1);  // phase marks + a pair per level
 
 // packed index of (n, m) real part / imaginary part (m >= 1)
 __host__ __device__ inline int pk_re(int n, int m) { return n * n + m; }

@@ -605,7 +605,7 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
 static void free_profile(lhf_plan *P)
 {
     if (P->prof_ev) {
-        for (int k = 0; k < P->prof_cap * (LHF_NPHASE + 1); k++) (void)hipEventDestroy(P->prof_ev[k]);
+        for (int k = 0; k < P->prof_cap * PROF_EV_PER_EXEC; k++) (void)hipEventDestroy(P->prof_ev[k]);
         delete[] P->prof_ev;
     }
     P->prof_ev = nullptr;
@@ -909,12 +909,12 @@ lhf_status lhf_profile_begin(lhf_plan *P, int32_t max_exec)
     if (!P) return arg_error("plan is NULL");
     if (max_exec < 1 || max_exec > 100000) return arg_error("max_exec must be in 1..100000");
     free_profile(P);
-    const int ne = max_exec * (LHF_NPHASE + 1);
+    const int ne = max_exec * PROF_EV_PER_EXEC;
     P->prof_ev = new hipEvent_t[ne];
     for (int k = 0; k < ne; k++) {
         hipError_t e = hipEventCreate(&P->prof_ev[k]);
         if (e != hipSuccess) {
-            P->prof_cap = k / (LHF_NPHASE + 1);
+            P->prof_cap = k / PROF_EV_PER_EXEC;
             for (int j = k; j < ne; j++) P->prof_ev[j] = nullptr;
             for (int j = 0; j < k; j++) (void)hipEventDestroy(P->prof_ev[j]);
             delete[] P->prof_ev;
@@ -937,12 +937,17 @@ lhf_status lhf_profile_end(lhf_plan *P, double *phase_ms, int32_t *n_exec)
     }
     for (int k = 0; k < LHF_NPHASE; k++) phase_ms[k] = 0.0;
     for (int e = 0; e < P->prof_used; e++) {
-        hipEvent_t *ev = P->prof_ev + (size_t)e * (LHF_NPHASE + 1);
-        LHF_HIP(hipEventSynchronize(ev[LHF_NPHASE]));
-        for (int k = 0; k < LHF_NPHASE; k++) {
+        hipEvent_t *ev = P->prof_ev + (size_t)e * PROF_EV_PER_EXEC;
+        LHF_HIP(hipEventSynchronize(ev[6]));
+        for (int k = 0; k < 6; k++) {
             float ms = 0.f;
             LHF_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
             phase_ms[k] += ms;
+        }
+        for (int l = 2; l <= P->depth; l++) {
+            float ms = 0.f;
+            LHF_HIP(hipEventElapsedTime(&ms, ev[7 + 2 * l], ev[8 + 2 * l]));
+            phase_ms[6] += ms;
         }
     }
     *n_exec = P->prof_used;
