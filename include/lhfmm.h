@@ -42,7 +42,8 @@
 extern "C" {
 #endif
 
-typedef struct lhf_plan lhf_plan; /* opaque, owned by the library */
+typedef struct lhf_plan lhf_plan;   /* opaque, owned by the library */
+typedef struct lhf_batch lhf_batch; /* opaque, owned by the library */
 
 typedef enum {
     LHF_OK = 0,
@@ -95,6 +96,19 @@ void lhf_desc_default(lhf_desc *d);
 lhf_status lhf_plan_create(lhf_plan **out, const lhf_desc *d, int64_t n, const void *x, double a,
                            void *stream);
 
+/* Plan over several independent systems evaluated together at one depth
+ * d->depth: system s owns elements sys_offsets[s] .. sys_offsets[s+1]-1 of x
+ * (host array of n_systems + 1 non-decreasing offsets, sys_offsets[0] = 0, empty
+ * systems allowed), lies in its own cube [sys_lo[3s..3s+2], + sys_len[s]]^3 and
+ * has core radius sys_a[s] (host arrays; LHF_SINGULAR sets every radius to 0).
+ * d->domain_lo and d->domain_len are ignored.  No element of one system sees
+ * another.  The system index is prefixed to the Morton key, so one sort and one
+ * launch per phase and level serve every system.  Otherwise as lhf_plan_create
+ * (the CORE_SPLIT warning is returned if any system triggers it). */
+lhf_status lhf_plan_create_multi(lhf_plan **out, const lhf_desc *d, int32_t n_systems,
+                                 const int64_t *sys_offsets, const void *x, const double *sys_lo,
+                                 const double *sys_len, const double *sys_a, void *stream);
+
 /* One FMM evaluation with strengths omega (device, [n][3]) for the plan's
  * elements: writes v and s (device, [n][3], input order).  Enqueued on
  * 'stream'; no host synchronisation, no allocation (graph-capturable). */
@@ -129,6 +143,61 @@ const char *lhf_last_error(void);
 #define LHF_NPHASE 7
 lhf_status lhf_profile_begin(lhf_plan *plan, int32_t max_exec);
 lhf_status lhf_profile_end(lhf_plan *plan, double *phase_ms, int32_t *n_exec);
+
+/* ---- Batches of independent systems with per-system depth (one HIP graph) ----
+ *
+ * Unit costs of the depth cost model (the paper's complexity analysis, Sec. 5,
+ * eqs. fmm2-fmm3): far-field nanoseconds per octree box of levels 2..d (P2M, M2M,
+ * M2L, L2L, L2P together) and near-field nanoseconds per ordered element pair. */
+typedef struct {
+    int32_t p, precision;
+    double t_box_ns;
+    double t_pair_ns;
+} lhf_tune;
+
+/* Built-in unit costs (host only, no device work). */
+void lhf_tune_default(int32_t p, int32_t precision, lhf_tune *t);
+
+/* Measure the unit costs on the current device: two plans over 2^17 uniform
+ * points (depths 5 and 3) executed with phase timing.  With a non-NULL
+ * cache_path the result is looked up first in, and else appended to, a JSON file
+ * keyed by device architecture, precision and p.  Synchronises 'stream';
+ * allocates temporary device memory. */
+lhf_status lhf_autotune(int32_t p, int32_t precision, const char *cache_path, lhf_tune *out,
+                        void *stream);
+
+/* Depth (2..8) minimising the modelled cost of n uniform points in a cube of side
+ * len among the depths whose leaf side h keeps 1 - K(h; a) <= tol (eq. vem1; any
+ * depth when a = 0).  Host only.  Returns LHF_WARN_CORE_SPLIT with *depth = 2 if
+ * no depth qualifies. */
+lhf_status lhf_choose_depth(const lhf_tune *t, int64_t n, double len, double a, double tol,
+                            int32_t *depth);
+
+/* Batch over n_systems independent systems (arrays as in lhf_plan_create_multi).
+ * Depth of system s: sys_depth[s] if sys_depth is non-NULL, else
+ * lhf_choose_depth(tune or the built-in costs, ...); d->depth is ignored.  Systems
+ * of equal depth share one plan; synchronises 'stream'. */
+lhf_status lhf_batch_create(lhf_batch **out, const lhf_desc *d, int32_t n_systems,
+                            const int64_t *sys_offsets, const void *x, const double *sys_lo,
+                            const double *sys_len, const double *sys_a, const int32_t *sys_depth,
+                            const lhf_tune *tune, void *stream);
+
+/* Evaluate every system: omega, v, s are device [N][3] arrays over all systems
+ * (N = sys_offsets[n_systems]).  use_graph = 1: the work of all depth groups is
+ * captured once into one HIP graph (one branch per group) and replayed by later
+ * calls with the same three pointers (new pointers: captured again); the graph
+ * is launched on 'stream'.  use_graph = 0: direct launches on 'stream'.  No host
+ * synchronisation; calls on one batch must not overlap. */
+lhf_status lhf_batch_execute(lhf_batch *b, const void *omega, void *v, void *s, int32_t use_graph,
+                             void *stream);
+
+/* Number of depth groups, the depth of every system (sys_depth[n_systems]) and
+ * the summed counts; any output pointer may be NULL. */
+lhf_status lhf_batch_info(const lhf_batch *b, int32_t *n_groups, int32_t *sys_depth,
+                          lhf_stats *total);
+
+/* Release the batch (synchronises its streams). */
+lhf_status lhf_batch_destroy(lhf_batch *b);
 
 /* Library version string. */
 const char *lhf_version(void);

@@ -23,9 +23,10 @@ STATUS = {0: "LHF_OK", 1: "LHF_WARN_CORE_SPLIT", -1: "LHF_ERR_ARG", -2: "LHF_ERR
           -3: "LHF_ERR_NONFINITE", -5: "LHF_ERR_HIP", -6: "LHF_ERR_UNSUPPORTED", -7: "LHF_ERR_STATE"}
 
 #: every entry point declared in include/lhfmm.h
-EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_execute", "lhf_execute_parts", "lhf_evaluate",
-           "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version", "lhf_profile_begin",
-           "lhf_profile_end")
+EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_plan_create_multi", "lhf_execute", "lhf_execute_parts",
+           "lhf_evaluate", "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version",
+           "lhf_profile_begin", "lhf_profile_end", "lhf_tune_default", "lhf_autotune", "lhf_choose_depth",
+           "lhf_batch_create", "lhf_batch_execute", "lhf_batch_info", "lhf_batch_destroy")
 PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 
 
@@ -39,6 +40,10 @@ class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("depth", C.c_int32), ("p", C.c_int32), ("boxes", C.c_int64 * 11),
                 ("n_m2l", C.c_int64), ("n_m2m", C.c_int64), ("n_l2l", C.c_int64), ("n_p2p_pairs", C.c_int64),
                 ("n_theta_classes", C.c_int32), ("reserved1", C.c_int32)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("p", C.c_int32), ("precision", C.c_int32), ("t_box_ns", C.c_double), ("t_pair_ns", C.c_double)]
 
 
 class LhfError(RuntimeError):
@@ -78,6 +83,24 @@ def load():
         L.lhf_profile_begin.restype = C.c_int
         L.lhf_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.lhf_profile_end.restype = C.c_int
+        dp, i64p, i32p = C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+        L.lhf_plan_create_multi.argtypes = [C.POINTER(vp), C.POINTER(Desc), C.c_int32, i64p, vp, dp, dp, dp, vp]
+        L.lhf_plan_create_multi.restype = C.c_int
+        L.lhf_tune_default.argtypes = [C.c_int32, C.c_int32, C.POINTER(Tune)]
+        L.lhf_tune_default.restype = None
+        L.lhf_autotune.argtypes = [C.c_int32, C.c_int32, C.c_char_p, C.POINTER(Tune), vp]
+        L.lhf_autotune.restype = C.c_int
+        L.lhf_choose_depth.argtypes = [C.POINTER(Tune), C.c_int64, C.c_double, C.c_double, C.c_double, i32p]
+        L.lhf_choose_depth.restype = C.c_int
+        L.lhf_batch_create.argtypes = [C.POINTER(vp), C.POINTER(Desc), C.c_int32, i64p, vp, dp, dp, dp, i32p,
+                                       C.POINTER(Tune), vp]
+        L.lhf_batch_create.restype = C.c_int
+        L.lhf_batch_execute.argtypes = [vp, vp, vp, vp, C.c_int32, vp]
+        L.lhf_batch_execute.restype = C.c_int
+        L.lhf_batch_info.argtypes = [vp, i32p, i32p, C.POINTER(Stats)]
+        L.lhf_batch_info.restype = C.c_int
+        L.lhf_batch_destroy.argtypes = [vp]
+        L.lhf_batch_destroy.restype = C.c_int
         _lib = L
     return _lib
 
@@ -112,18 +135,46 @@ def _dev_array(t, dtype, name):
     return t
 
 
-class Plan:
-    """An octree plan over fixed element positions (the paper's 'FMM set' stage)."""
+def _systems(offsets, lo, L, a):
+    """host arrays (int64 offsets[ns+1], float64 lo[ns][3], L[ns], a[ns]) for the multi-system calls"""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, np.int64).reshape(-1)
+    ns = off.shape[0] - 1
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(lo, np.float64), (ns, 3)))
+    L = np.ascontiguousarray(np.broadcast_to(np.asarray(L, np.float64), (ns,)))
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), (ns,)))
+    return ns, off, lo, L, a
 
-    def __init__(self, x, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0):
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class Plan:
+    """An octree plan over fixed element positions (the paper's 'FMM set' stage).
+
+    With ``offsets`` (host, n_systems + 1 entries), x holds several independent
+    systems; ``lo``, ``L`` and ``a`` are then per system (or broadcast)."""
+
+    def __init__(self, x, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0,
+                 offsets=None):
         import torch
         self.dtype = torch.float64 if precision == FP64 else torch.float32
         x = _dev_array(x, self.dtype, "x")
         self.n = x.shape[0]
-        self.desc = make_desc(p, depth, precision, lo, L, tol, flags)
+        self.desc = make_desc(p, depth, precision, lo if offsets is None else (0.0, 0.0, 0.0),
+                              L if offsets is None else 1.0, tol, flags)
         self._h = C.c_void_p()
-        self.status = _check(load().lhf_plan_create(C.byref(self._h), C.byref(self.desc), self.n,
-                                                    C.c_void_p(x.data_ptr()), float(a), _stream()))
+        if offsets is None:
+            self.status = _check(load().lhf_plan_create(C.byref(self._h), C.byref(self.desc), self.n,
+                                                        C.c_void_p(x.data_ptr()), float(a), _stream()))
+        else:
+            ns, off, glo, gL, ga = _systems(offsets, lo, L, a)
+            if off[-1] != self.n:
+                raise ValueError("offsets[-1] must equal the number of elements")
+            self.status = _check(load().lhf_plan_create_multi(
+                C.byref(self._h), C.byref(self.desc), ns, _ptr(off, C.c_int64), C.c_void_p(x.data_ptr()),
+                _ptr(glo, C.c_double), _ptr(gL, C.c_double), _ptr(ga, C.c_double), _stream()))
         self.warn_core_split = self.status == 1
 
     def execute(self, omega, v=None, s=None, what=3):
@@ -180,3 +231,83 @@ def evaluate(x, omega, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1
     _check(load().lhf_evaluate(C.byref(d), x.shape[0], C.c_void_p(x.data_ptr()), C.c_void_p(omega.data_ptr()),
                                float(a), C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr()), _stream()))
     return v, s
+
+
+def tune_default(p, precision=FP32):
+    t = Tune()
+    load().lhf_tune_default(int(p), int(precision), C.byref(t))
+    return t
+
+
+def autotune(p, precision=FP32, cache_path=None):
+    """measured unit costs of the depth cost model (device work; cached in a JSON file if given)"""
+    t = Tune()
+    _check(load().lhf_autotune(int(p), int(precision), cache_path.encode() if cache_path else None, C.byref(t),
+                               _stream()))
+    return t
+
+
+def choose_depth(tune, n, L=1.0, a=0.0, tol=1e-6):
+    """(depth, core_split_warning) for n uniform elements in a cube of side L"""
+    d = C.c_int32()
+    st = _check(load().lhf_choose_depth(C.byref(tune), int(n), float(L), float(a), float(tol), C.byref(d)))
+    return d.value, st == 1
+
+
+class Batch:
+    """Independent systems with per-system depth, evaluated by one HIP graph."""
+
+    def __init__(self, x, offsets, a, p=10, precision=FP32, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0,
+                 depths=None, tune=None):
+        import numpy as np
+        import torch
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        x = _dev_array(x, self.dtype, "x")
+        self.n = x.shape[0]
+        self.ns, off, glo, gL, ga = _systems(offsets, lo, L, a)
+        if off[-1] != self.n:
+            raise ValueError("offsets[-1] must equal the number of elements")
+        self.desc = make_desc(p, 4, precision, (0.0, 0.0, 0.0), 1.0, tol, flags)
+        dep = None
+        if depths is not None:
+            dep = np.ascontiguousarray(np.broadcast_to(np.asarray(depths, np.int32), (self.ns,)))
+        self._h = C.c_void_p()
+        self.status = _check(load().lhf_batch_create(
+            C.byref(self._h), C.byref(self.desc), self.ns, _ptr(off, C.c_int64), C.c_void_p(x.data_ptr()),
+            _ptr(glo, C.c_double), _ptr(gL, C.c_double), _ptr(ga, C.c_double),
+            _ptr(dep, C.c_int32) if dep is not None else None, C.byref(tune) if tune is not None else None,
+            _stream()))
+        self.warn_core_split = self.status == 1
+
+    def execute(self, omega, v=None, s=None, graph=True):
+        import torch
+        omega = _dev_array(omega, self.dtype, "omega")
+        if omega.shape[0] != self.n:
+            raise ValueError("omega has a different number of elements than the batch")
+        if v is None:
+            v = torch.empty_like(omega)
+        if s is None:
+            s = torch.empty_like(omega)
+        _check(load().lhf_batch_execute(self._h, C.c_void_p(omega.data_ptr()), C.c_void_p(v.data_ptr()),
+                                        C.c_void_p(s.data_ptr()), int(bool(graph)), _stream()))
+        return v, s
+
+    def info(self):
+        import numpy as np
+        ng = C.c_int32()
+        dep = np.zeros(self.ns, np.int32)
+        st = Stats()
+        _check(load().lhf_batch_info(self._h, C.byref(ng), _ptr(dep, C.c_int32), C.byref(st)))
+        return dict(n_groups=ng.value, depths=dep, n_m2l=st.n_m2l, n_p2p_pairs=st.n_p2p_pairs,
+                    boxes=list(st.boxes[:st.depth + 1]))
+
+    def close(self):
+        if self._h:
+            _check(load().lhf_batch_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -41,9 +41,10 @@ __device__ inline void decode_row(int q, int &n, int &m, int &part)
     }
 }
 
-template <typename T>
-__device__ inline void box_centre(uint64_t key, int level, double lo0, double lo1, double lo2, double L,
-                                  double &c0, double &c1, double &c2, double &h)
+// centre and side of a box; the key carries the system index above its 3*level Morton bits,
+// and sys_geo[4s..4s+3] = (lo0, lo1, lo2, L) is that system's cube
+__device__ inline void box_centre(uint64_t key, int level, const double *__restrict__ sys_geo, double &c0,
+                                  double &c1, double &c2, double &h)
 {
     uint32_t ix = 0, iy = 0, iz = 0;
     for (int b = 0; b < level; b++) {
@@ -51,10 +52,11 @@ __device__ inline void box_centre(uint64_t key, int level, double lo0, double lo
         iy |= (uint32_t)((key >> (3 * b + 1)) & 1u) << b;
         iz |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
     }
-    h = L / (double)(1u << level);
-    c0 = lo0 + ((double)ix + 0.5) * h;
-    c1 = lo1 + ((double)iy + 0.5) * h;
-    c2 = lo2 + ((double)iz + 0.5) * h;
+    const double *g = sys_geo + 4 * (key >> (3 * level));
+    h = g[3] / (double)(1u << level);
+    c0 = g[0] + ((double)ix + 0.5) * h;
+    c1 = g[1] + ((double)iy + 0.5) * h;
+    c2 = g[2] + ((double)iz + 0.5) * h;
 }
 
 // ---------------------------------------------------------------------------
@@ -68,7 +70,7 @@ template <typename T>
 __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off, const uint64_t *__restrict__ bkey,
                                               const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
                                               const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
-                                              double lo0, double lo1, double lo2, double L, T *__restrict__ M)
+                                              const double *__restrict__ sys_geo, T *__restrict__ M)
 {
     extern __shared__ char smem[];
     T *Rre = (T *)smem;          // [p][p]  (n, m)
@@ -76,7 +78,7 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
     const int lane = threadIdx.x;
     const int64_t b = leaf_off + blockIdx.x;
     double c0, c1, c2, hd;
-    box_centre<T>(bkey[b], depth, lo0, lo1, lo2, L, c0, c1, c2, hd);
+    box_centre(bkey[b], depth, sys_geo, c0, c1, c2, hd);
     const T h = (T)hd, ih = (T)(1.0 / hd);
     const int P2 = p * p;
     T acc[NRMAX];
@@ -466,7 +468,7 @@ template <typename T>
 __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off, const uint64_t *__restrict__ bkey,
                                               const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
                                               const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
-                                              double lo0, double lo1, double lo2, double L, const T *__restrict__ Lc,
+                                              const double *__restrict__ sys_geo, const T *__restrict__ Lc,
                                               T *__restrict__ vfar)
 {
     extern __shared__ char smem[];
@@ -526,7 +528,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off
     }
     __syncthreads();
     double c0, c1, c2, hd;
-    box_centre<T>(bkey[b], depth, lo0, lo1, lo2, L, c0, c1, c2, hd);
+    box_centre(bkey[b], depth, sys_geo, c0, c1, c2, hd);
     const T ih = (T)(1.0 / hd);
     const int s0 = bstart[b], cnt = bcount[b];
     auto vget = [&](int k, int nn, int m, T &re, T &im) {
@@ -669,15 +671,19 @@ __device__ inline void kernel_fg(T r2, T a, int smooth, T &f, T &g)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth_leaf_off_dummy, int64_t leaf_off,
-                                             const int32_t *__restrict__ eleaf, const int32_t *__restrict__ ulist,
+__global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_off, const int32_t *__restrict__ eleaf,
+                                             const int32_t *__restrict__ ulist, const uint64_t *__restrict__ bkey,
                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
-                                             const T *__restrict__ xs, const T *__restrict__ ws, T a, int smooth,
-                                             int what, const T *__restrict__ vfar, const int32_t *__restrict__ perm,
-                                             T *__restrict__ vout, T *__restrict__ sout)
+                                             const T *__restrict__ xs, const T *__restrict__ ws,
+                                             const double *__restrict__ sys_a, int what, const T *__restrict__ vfar,
+                                             const int32_t *__restrict__ perm, T *__restrict__ vout,
+                                             T *__restrict__ sout)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    // core radius of the element's system (0: singular kernel)
+    const T a = (T)sys_a[bkey[eleaf[i]] >> (3 * depth)];
+    const int smooth = a > (T)0;
     T v0 = 0, v1 = 0, v2 = 0, s0 = 0, s1 = 0, s2 = 0;
     const T xj = xs[i], yj = xs[n + i], zj = xs[2 * n + i];
     const T wjx = ws[i], wjy = ws[n + i], wjz = ws[2 * n + i];
@@ -760,7 +766,7 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
     if (what & 1) {
         size_t sh_p2m = sizeof(T) * 2 * P2;
         hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_p2m, st, p, d, loff, P->bkey, P->bstart,
-                           P->bcount, (const T *)xs, (const T *)ws, n, P->lo[0], P->lo[1], P->lo[2], P->L, M);
+                           P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, M);
         mark(2);
         size_t sh_rcr = sizeof(T) * (4 * P2 + 2 * ZS + 2 * p + 2);
         for (int l = d - 1; l >= 2; l--) {
@@ -794,8 +800,7 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         const int TRI = p * (p + 1) / 2;
         size_t sh_l2p = sizeof(T) * (2 * P2 + 6 * TRI);
         hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_l2p, st, p, d, loff, P->bkey, P->bstart,
-                           P->bcount, (const T *)xs, (const T *)ws, n, P->lo[0], P->lo[1], P->lo[2], P->L,
-                           (const T *)Lc, vfar);
+                           P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar);
     } else {
         mark(2);
         mark(3);
@@ -806,9 +811,8 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         mark(4);
     }
     mark(5);
-    const int smooth = P->a > 0.0 && !(P->desc.flags & LHF_SINGULAR);
-    hipLaunchKernelGGL(k_p2p<T>, dim3(nblk), dim3(tpb), 0, st, n, 0, loff, P->eleaf, P->ulist, P->bstart, P->bcount,
-                       (const T *)xs, (const T *)ws, (T)P->a, smooth, what, (const T *)vfar, P->perm, (T *)v,
+    hipLaunchKernelGGL(k_p2p<T>, dim3(nblk), dim3(tpb), 0, st, n, d, loff, P->eleaf, P->ulist, P->bkey, P->bstart,
+                       P->bcount, (const T *)xs, (const T *)ws, P->sys_a, what, (const T *)vfar, P->perm, (T *)v,
                        (T *)s);
     mark(6);
     LHF_HIP(hipGetLastError());

@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/lhfmm.h"
 
@@ -62,10 +63,18 @@ struct lhf_plan {
     int p = 0, depth = 0;
     int precision = 0;      // LHF_FP64 / LHF_FP32
     size_t tsize = 8;       // bytes per real
-    double a = 0.0;
-    double lo[3] = {0, 0, 0};
-    double L = 1.0;
     hipStream_t stream = nullptr;
+
+    // independent systems sharing the plan: system s owns input elements
+    // sys_off[s] .. sys_off[s+1]-1, has its own cube and core radius, and its
+    // index is prefixed to every Morton key (so no list crosses systems)
+    int nsys = 1;
+    std::vector<int64_t> h_sys_off;   // [nsys + 1]
+    std::vector<double> h_sys_geo;    // [nsys][4]: lo0, lo1, lo2, L
+    std::vector<double> h_sys_a;      // [nsys]: core radius (0: singular)
+    double *sys_geo = nullptr;        // device copies
+    double *sys_a = nullptr;
+    int64_t *sys_off = nullptr;
 
     lhf::TreeLevel lev[lhf::MAXDEPTH + 1];
     int64_t nbox = 0;       // all levels
@@ -118,6 +127,12 @@ struct lhf_plan {
 namespace lhf {
 void set_error(const std::string &msg);
 lhf_status hip_fail(hipError_t e, const char *what);
+lhf_status arg_error(const std::string &msg);
+// checked construction of a plan over nsys systems (host offsets, cubes and core radii)
+lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *off, const void *x,
+                    const double *lo, const double *len, const double *a, hipStream_t stream);
+void plan_free(lhf_plan *P);
+lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st);
 }  // namespace lhf
 
 #define LHF_HIP(call)                                                  \

@@ -149,7 +149,8 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
     T *acc = Wl + 4 * S::WB;                     // [NSLOT + 1][SST] (last slot absorbs inactive lanes)
     int *slot_xyz = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] packed target coordinates, -1: no box
     int *slot_box = slot_xyz + NSLOT;            // [NSLOT] target box
-    int16_t *cst = (int16_t *)(slot_box + NSLOT);       // [ncls + 1] class starts (entries or rows)
+    int *slot_sys = slot_box + NSLOT;            // [NSLOT] system of the target (offset into dmap)
+    int16_t *cst = (int16_t *)(slot_sys + NSLOT);       // [ncls + 1] class starts (entries or rows)
     int16_t *ent = cst + 64;                     // [NENT] (dir << 3) | child position (shared mode)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -180,6 +181,9 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
                 iz |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
             }
             xyz = (int)(ix | (iy << 10) | (iz << 20));
+            slot_sys[tid] = (int)(key >> (3 * level));
+        } else {
+            slot_sys[tid] = 0;
         }
         slot_box[tid] = box;
         slot_xyz[tid] = xyz;
@@ -224,7 +228,7 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
         const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
                   sz = (xyz >> 20) - (dir / 49 - 3);
         if (sx < 0 || sy < 0 || sz < 0 || sx >= side || sy >= side || sz >= side) return j;
-        const int src = dmap[((size_t)sz * side + sy) * side + sx];
+        const int src = dmap[(((size_t)slot_sys[slot] * side + sz) * side + sy) * side + sx];
         if (src < 0) return j;
         j.slot = slot;
         j.dir = dir;
@@ -464,7 +468,8 @@ __global__ void k_dmap(int level, int64_t off, int64_t nb, const uint64_t *__res
         iz |= (uint32_t)((key >> (3 * q + 2)) & 1u) << q;
     }
     const size_t side = (size_t)1 << level;
-    dmap[((size_t)iz * side + iy) * side + ix] = (int32_t)(off + b);
+    const size_t sys = key >> (3 * level);
+    dmap[((sys * side + iz) * side + iy) * side + ix] = (int32_t)(off + b);
 }
 
 // per-class stride (elements) of the padded rotation blocks, a multiple of 16 bytes
@@ -517,7 +522,7 @@ static size_t wpad_build_t(lhf_plan *Pl, hipStream_t st)
 template <typename T, int P>
 constexpr size_t tile_bytes(int npar, bool own)
 {
-    return sizeof(T) * ((size_t)(8 * npar + 1) * (2 * P * P + 1) + 4 * M2LShape<T, P>::WB) + sizeof(int) * 2 * 8 * npar +
+    return sizeof(T) * ((size_t)(8 * npar + 1) * (2 * P * P + 1) + 4 * M2LShape<T, P>::WB) + sizeof(int) * 3 * 8 * npar +
            sizeof(int16_t) * (64 + (own ? 0 : 1512));
 }
 // ownership mode (8 sibling groups, no atomics) when it fits in 64 KB; otherwise shared mode

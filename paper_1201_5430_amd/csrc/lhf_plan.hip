@@ -39,7 +39,7 @@ lhf_status hip_fail(hipError_t e, const char *what)
     return LHF_ERR_HIP;
 }
 
-static lhf_status arg_error(const std::string &msg)
+lhf_status arg_error(const std::string &msg)
 {
     set_error(msg);
     return LHF_ERR_ARG;
@@ -69,14 +69,25 @@ __device__ inline uint32_t compact3(uint64_t x)
     return (uint32_t)x;
 }
 
-// flags: [0] = element outside the cube, [1] = non-finite coordinate
+// flags: [0] = element outside its cube, [1] = non-finite coordinate.
+// System s of element i: sys_off[s] <= i < sys_off[s+1]; its cube is sys_geo[4s..4s+3] =
+// (lo0, lo1, lo2, L).  The key is (s << 3 depth) | Morton(q >> (21 - depth)).
 template <typename T>
-__global__ void k_keys(int64_t n, const T *__restrict__ x, double lo0, double lo1, double lo2, double scale,
-                       int depth, uint64_t *__restrict__ key, int32_t *__restrict__ idx, int32_t *__restrict__ flags)
+__global__ void k_keys(int64_t n, const T *__restrict__ x, int nsys, const int64_t *__restrict__ sys_off,
+                       const double *__restrict__ sys_geo, int depth, uint64_t *__restrict__ key,
+                       int32_t *__restrict__ idx, int32_t *__restrict__ flags)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double lo[3] = {lo0, lo1, lo2};
+    int lo_s = 0, hi_s = nsys - 1;  // last s with sys_off[s] <= i
+    while (lo_s < hi_s) {
+        const int mid = (lo_s + hi_s + 1) >> 1;
+        if (sys_off[mid] <= i) lo_s = mid;
+        else hi_s = mid - 1;
+    }
+    const int s = lo_s;
+    const double *g = sys_geo + 4 * s;
+    const double scale = (double)(1u << QBITS) / g[3];
     uint32_t q[3];
     const double qmax = (double)((1u << QBITS) - 1u);
     for (int d = 0; d < 3; d++) {
@@ -86,14 +97,15 @@ __global__ void k_keys(int64_t n, const T *__restrict__ x, double lo0, double lo
             q[d] = 0;
             continue;
         }
-        const double t = (xv - lo[d]) * scale;  // one rounding each: no contraction possible
+        const double t = (xv - g[d]) * scale;  // one rounding each: no contraction possible
         if (t < 0.0 || t > (double)(1u << QBITS)) atomicOr(&flags[0], 1);
         double f = floor(t);
         f = fmin(fmax(f, 0.0), qmax);
         q[d] = (uint32_t)f;
     }
     const int sh = QBITS - depth;
-    key[i] = spread3(q[0] >> sh) | (spread3(q[1] >> sh) << 1) | (spread3(q[2] >> sh) << 2);
+    key[i] = ((uint64_t)s << (3 * depth)) | spread3(q[0] >> sh) | (spread3(q[1] >> sh) << 1) |
+             (spread3(q[2] >> sh) << 2);
     idx[i] = (int32_t)i;
 }
 
@@ -189,7 +201,8 @@ __global__ void k_vlist(int64_t off, int64_t nb, int level, const uint64_t *__re
     const int64_t bl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (bl >= nb) return;
     const int64_t b = off + bl;
-    const uint64_t k = bkey[b];
+    const uint64_t kfull = bkey[b];
+    const uint64_t sys = kfull >> (3 * level), k = kfull & ((1ull << (3 * level)) - 1);
     const int ix = (int)compact3(k), iy = (int)compact3(k >> 1), iz = (int)compact3(k >> 2);
     const int px = ix >> 1, py = iy >> 1, pz = iz >> 1;
     const int side = 1 << level;
@@ -204,7 +217,8 @@ __global__ void k_vlist(int64_t off, int64_t nb, int level, const uint64_t *__re
                     if (cx < 0 || cy < 0 || cz < 0 || cx >= side || cy >= side || cz >= side) continue;
                     const int ex = ix - cx, ey = iy - cy, ez = iz - cz;
                     if (abs(ex) <= 1 && abs(ey) <= 1 && abs(ez) <= 1) continue;
-                    const uint64_t ck = spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) | (spread3((uint32_t)cz) << 2);
+                    const uint64_t ck = (sys << (3 * level)) | spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) |
+                                        (spread3((uint32_t)cz) << 2);
                     const int64_t j = find_u64(lk, nb, ck);
                     if (j < 0) continue;
                     vsrc[b * VMAX + cnt] = (int32_t)(off + j);
@@ -220,7 +234,8 @@ __global__ void k_ulist(int64_t off, int64_t nb, int level, const uint64_t *__re
 {
     const int64_t bl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (bl >= nb) return;
-    const uint64_t k = bkey[off + bl];
+    const uint64_t kfull = bkey[off + bl];
+    const uint64_t sys = kfull >> (3 * level), k = kfull & ((1ull << (3 * level)) - 1);
     const int ix = (int)compact3(k), iy = (int)compact3(k >> 1), iz = (int)compact3(k >> 2);
     const int side = 1 << level;
     const uint64_t *lk = bkey + off;
@@ -232,7 +247,8 @@ __global__ void k_ulist(int64_t off, int64_t nb, int level, const uint64_t *__re
                 const int cx = ix + dx, cy = iy + dy, cz = iz + dz;
                 int32_t val = -1;
                 if (cx >= 0 && cy >= 0 && cz >= 0 && cx < side && cy < side && cz < side) {
-                    const uint64_t ck = spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) | (spread3((uint32_t)cz) << 2);
+                    const uint64_t ck = (sys << (3 * level)) | spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) |
+                                        (spread3((uint32_t)cz) << 2);
                     const int64_t j = find_u64(lk, nb, ck);
                     if (j >= 0) {
                         val = (int32_t)(off + j);
@@ -584,7 +600,9 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     LHF_HIP(hipGetLastError());
     // batched M2L: used when the tiled kernel exists for (precision, p), fits in LDS and the
     // dense box maps stay small (levels <= 8)
-    P->use_tile = m2l_tile_supported(P->precision, p) && P->depth <= 8 && !getenv("LHF_NO_TILE");
+    // (dense maps: nsys 8^l entries per level, at most 2^28 at the leaf level)
+    P->use_tile = m2l_tile_supported(P->precision, p) && P->depth <= 8 &&
+                  ((int64_t)P->nsys << (3 * P->depth)) <= ((int64_t)1 << 28) && !getenv("LHF_NO_TILE");
     if (P->use_tile) {
         lhf_status s = build_schedule(P, cls, (int)theta.size(), st);
         if (s != LHF_OK) return s;
@@ -593,9 +611,9 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
             return LHF_ERR_HIP;
         }
         for (int l = 2; l <= P->depth; l++) {
-            const size_t side = (size_t)1 << l;
-            LHF_HIP(hipMalloc(&P->dmap[l], sizeof(int32_t) * side * side * side));
-            LHF_HIP(hipMemsetAsync(P->dmap[l], 0xff, sizeof(int32_t) * side * side * side, st));
+            const size_t cells = (size_t)P->nsys << (3 * l);
+            LHF_HIP(hipMalloc(&P->dmap[l], sizeof(int32_t) * cells));
+            LHF_HIP(hipMemsetAsync(P->dmap[l], 0xff, sizeof(int32_t) * cells, st));
             dmap_build(P, l, st);
         }
     }
@@ -618,7 +636,7 @@ static void free_plan(lhf_plan *P)
     free_profile(P);
     void *bufs[] = {P->perm, P->xs, P->ws, P->vfar, P->bkey, P->bstart, P->bcount, P->bparent, P->bchild0,
                     P->bnchild, P->vcount, P->vsrc, P->vdir, P->ulist, P->eleaf, P->M, P->Lc, P->rot,
-                    P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp};
+                    P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp, P->sys_geo, P->sys_a, P->sys_off};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int l = 0; l <= MAXDEPTH; l++)
@@ -672,22 +690,32 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(hipMalloc(&P->dflag, sizeof(int32_t) * 4));
     CK(hipMemsetAsync(P->dflag, 0, sizeof(int32_t) * 4, st));
     CK(hipMemsetAsync(dcnt, 0, sizeof(int64_t) * 4, st));
-    const double scale = (double)(1u << QBITS) / P->L;
-    hipLaunchKernelGGL(k_keys<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)x, P->lo[0], P->lo[1], P->lo[2], scale,
-                       d, key, idx, P->dflag);
+    const int ns = P->nsys;
+    CK(hipMalloc(&P->sys_geo, sizeof(double) * 4 * ns));
+    CK(hipMalloc(&P->sys_a, sizeof(double) * ns));
+    CK(hipMalloc(&P->sys_off, sizeof(int64_t) * (ns + 1)));
+    CK(hipMemcpyAsync(P->sys_geo, P->h_sys_geo.data(), sizeof(double) * 4 * ns, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(P->sys_a, P->h_sys_a.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(P->sys_off, P->h_sys_off.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_keys<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)x, ns, P->sys_off, P->sys_geo, d, key,
+                       idx, P->dflag);
     CK(hipGetLastError());
+    // the system index occupies the key bits above the 3*depth Morton bits
+    int sys_bits = 0;
+    while (((int64_t)1 << sys_bits) < ns) sys_bits++;
+    const int end_bit = 3 * d + sys_bits;
     size_t sort_bytes = 0, scan_bytes = 0;
-    CK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, key, skey, idx, P->perm, (int)n, 0, 3 * d, st));
+    CK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, key, skey, idx, P->perm, (int)n, 0, end_bit, st));
     CK(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, flag, id, (int)n, st));
     tmp_bytes = std::max(sort_bytes, scan_bytes);
     CK(hipMalloc(&tmp, tmp_bytes));
-    CK(hipcub::DeviceRadixSort::SortPairs(tmp, sort_bytes, key, skey, idx, P->perm, (int)n, 0, 3 * d, st));
+    CK(hipcub::DeviceRadixSort::SortPairs(tmp, sort_bytes, key, skey, idx, P->perm, (int)n, 0, end_bit, st));
     CK(hipMalloc(&P->xs, sizeof(T) * 3 * n));
     CK(hipMalloc(&P->ws, sizeof(T) * 3 * n));
     CK(hipMalloc(&P->vfar, sizeof(T) * 6 * n));
     CK(hipMalloc(&P->eleaf, sizeof(int32_t) * n));
     hipLaunchKernelGGL(k_gather_x<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)x, P->perm, (T *)P->xs);
-    // ---- levels (per-level temporaries sized by min(n, 8^l))
+    // ---- levels (per-level temporaries sized by min(n, nsys 8^l))
     std::vector<uint64_t *> lkey(d + 1, nullptr);
     std::vector<int32_t *> lstart(d + 1, nullptr);
     auto cleanup_levels = [&]() {
@@ -697,7 +725,7 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
         }
     };
     for (int l = d; l >= 0; l--) {
-        const int64_t cap = std::min<int64_t>(n, (int64_t)1 << (3 * l));
+        const int64_t cap = std::min<int64_t>(n, l >= 11 ? n : (int64_t)ns << (3 * l));
         hipError_t e1 = hipMalloc(&lkey[l], sizeof(uint64_t) * cap);
         hipError_t e2 = hipMalloc(&lstart[l], sizeof(int32_t) * cap);
         if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -794,6 +822,68 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     return LHF_OK;
 }
 
+// Checked plan construction shared by every creation entry point: nsys systems,
+// system s owning elements off[s] .. off[s+1]-1 of x, with cube (lo[3s..3s+2], len[s])
+// and core radius a[s] (host arrays).
+lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *off, const void *x,
+                    const double *lo, const double *len, const double *a, hipStream_t stream)
+{
+    *out = nullptr;
+    if (!d) return arg_error("desc is NULL");
+    if (nsys < 1) return arg_error("n_systems must be >= 1");
+    if (!off || !lo || !len || !a) return arg_error("system arrays must be non-NULL");
+    if (off[0] != 0) return arg_error("sys_offsets[0] must be 0");
+    for (int s = 0; s < nsys; s++)
+        if (off[s + 1] < off[s]) return arg_error("sys_offsets must be non-decreasing");
+    const int64_t n = off[nsys];
+    if (n < 1) return arg_error("n must be >= 1");
+    if (n > (int64_t)0x7fffffff) return arg_error("n must fit in int32");
+    if (!x) return arg_error("x is NULL");
+    if (d->precision != LHF_FP64 && d->precision != LHF_FP32) return arg_error("unknown precision");
+    const int pmax = d->precision == LHF_FP64 ? MAXP : 16;
+    if (d->p < 1 || d->p > pmax) return arg_error("p out of range (FP64: 1..24, FP32: 1..16)");
+    if (d->depth < 2 || d->depth > MAXDEPTH) return arg_error("depth out of range (2..10)");
+    if (!(d->tol > 0.0)) return arg_error("tol must be > 0");
+    if ((int64_t)nsys > ((int64_t)1 << (63 - 3 * d->depth)) / 2) return arg_error("too many systems for this depth");
+    for (int s = 0; s < nsys; s++) {
+        if (!(len[s] > 0.0) || !isfinite(len[s])) return arg_error("cube sides must be finite and > 0");
+        for (int k = 0; k < 3; k++)
+            if (!isfinite(lo[3 * s + k])) return arg_error("cube origins must be finite");
+        if (!(a[s] >= 0.0) || !isfinite(a[s])) return arg_error("core radius a must be finite and >= 0");
+    }
+    lhf_plan *P = new lhf_plan();
+    P->desc = *d;
+    P->n = n;
+    P->p = d->p;
+    P->depth = d->depth;
+    P->precision = d->precision;
+    P->tsize = d->precision == LHF_FP64 ? 8 : 4;
+    P->stream = stream;
+    P->nsys = nsys;
+    P->h_sys_off.assign(off, off + nsys + 1);
+    P->h_sys_geo.resize(4 * (size_t)nsys);
+    P->h_sys_a.resize(nsys);
+    for (int s = 0; s < nsys; s++) {
+        for (int k = 0; k < 3; k++) P->h_sys_geo[4 * s + k] = lo[3 * s + k];
+        P->h_sys_geo[4 * s + 3] = len[s];
+        P->h_sys_a[s] = (d->flags & LHF_SINGULAR) ? 0.0 : a[s];
+    }
+    lhf_status st = d->precision == LHF_FP64 ? plan_create_t<double>(P, x, stream) : plan_create_t<float>(P, x, stream);
+    if (st < 0) {
+        free_plan(P);
+        return st;
+    }
+    *out = P;
+    // warn when, in some system, the far field's singular kernel differs from the core by more than tol
+    for (int s = 0; s < nsys; s++) {
+        const double as = P->h_sys_a[s];
+        if (as > 0.0 && 1.0 - core_k(len[s] / (double)(1 << P->depth), as) > d->tol) return LHF_WARN_CORE_SPLIT;
+    }
+    return LHF_OK;
+}
+
+void plan_free(lhf_plan *P) { free_plan(P); }
+
 }  // namespace lhf
 
 using namespace lhf;
@@ -821,42 +911,19 @@ lhf_status lhf_plan_create(lhf_plan **out, const lhf_desc *d, int64_t n, const v
     *out = nullptr;
     if (!d) return arg_error("desc is NULL");
     if (n < 1) return arg_error("n must be >= 1");
-    if (n > (int64_t)0x7fffffff) return arg_error("n must fit in int32");
-    if (!x) return arg_error("x is NULL");
-    if (d->precision != LHF_FP64 && d->precision != LHF_FP32) return arg_error("unknown precision");
-    const int pmax = d->precision == LHF_FP64 ? MAXP : 16;
-    if (d->p < 1 || d->p > pmax) return arg_error("p out of range (FP64: 1..24, FP32: 1..16)");
-    if (d->depth < 2 || d->depth > MAXDEPTH) return arg_error("depth out of range (2..10)");
-    if (!(a >= 0.0) || !isfinite(a)) return arg_error("core radius a must be finite and >= 0");
-    if (!(d->tol > 0.0)) return arg_error("tol must be > 0");
     if (!(d->domain_len > 0.0) || !isfinite(d->domain_len))
         return arg_error("domain_len must be > 0 (bounding-cube mode is not supported)");
-    for (int k = 0; k < 3; k++)
-        if (!isfinite(d->domain_lo[k])) return arg_error("domain_lo must be finite");
-    lhf_plan *P = new lhf_plan();
-    P->desc = *d;
-    P->n = n;
-    P->p = d->p;
-    P->depth = d->depth;
-    P->precision = d->precision;
-    P->tsize = d->precision == LHF_FP64 ? 8 : 4;
-    P->a = (d->flags & LHF_SINGULAR) ? 0.0 : a;
-    for (int k = 0; k < 3; k++) P->lo[k] = d->domain_lo[k];
-    P->L = d->domain_len;
-    P->stream = (hipStream_t)stream;
-    lhf_status s = d->precision == LHF_FP64 ? plan_create_t<double>(P, x, P->stream)
-                                            : plan_create_t<float>(P, x, P->stream);
-    if (s < 0) {
-        free_plan(P);
-        return s;
-    }
-    *out = P;
-    // warn when the far field's singular kernel differs from the core by more than tol
-    if (P->a > 0.0) {
-        const double hleaf = P->L / (double)(1 << P->depth);
-        if (1.0 - core_k(hleaf, P->a) > d->tol) return LHF_WARN_CORE_SPLIT;
-    }
-    return LHF_OK;
+    const int64_t off[2] = {0, n};
+    return plan_new(out, d, 1, off, x, d->domain_lo, &d->domain_len, &a, (hipStream_t)stream);
+}
+
+lhf_status lhf_plan_create_multi(lhf_plan **out, const lhf_desc *d, int32_t n_systems, const int64_t *sys_offsets,
+                                 const void *x, const double *sys_lo, const double *sys_len, const double *sys_a,
+                                 void *stream)
+{
+    if (!out) return arg_error("out is NULL");
+    *out = nullptr;
+    return plan_new(out, d, n_systems, sys_offsets, x, sys_lo, sys_len, sys_a, (hipStream_t)stream);
 }
 
 lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, int32_t what, void *stream)

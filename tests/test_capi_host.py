@@ -57,3 +57,38 @@ def test_argument_validation_is_host_side():
     assert lib.lhf_plan_destroy(None) == 0
     st = L.Stats()
     assert lib.lhf_plan_stats(None, C.byref(st)) == -1
+
+
+def test_multi_system_and_batch_validation_is_host_side():
+    import numpy as np
+    L, lib = _lib()
+    h = C.c_void_p()
+    dummy = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    d = L.make_desc(p=8, depth=3)
+    f64 = lambda a: np.ascontiguousarray(a, np.float64)
+    i64 = lambda a: np.ascontiguousarray(a, np.int64)
+    P = lambda a, t: a.ctypes.data_as(C.POINTER(t))
+    lo, ln, a = f64([[0, 0, 0], [1, 1, 1]]), f64([1.0, 1.0]), f64([0.01, 0.01])
+    cases = [
+        (i64([1, 5, 9]), ln, a, "sys_offsets[0]"),
+        (i64([0, 5, 3]), ln, a, "non-decreasing"),
+        (i64([0, 0, 0]), ln, a, "n must be >= 1"),
+        (i64([0, 5, 9]), f64([1.0, 0.0]), a, "cube sides"),
+        (i64([0, 5, 9]), ln, f64([0.01, -1.0]), "core radius"),
+    ]
+    for off, lns, aa, msg in cases:
+        st = lib.lhf_plan_create_multi(C.byref(h), C.byref(d), 2, P(off, C.c_int64), dummy, P(lo, C.c_double),
+                                       P(lns, C.c_double), P(aa, C.c_double), None)
+        assert st == -1 and h.value is None, (msg, st)
+        assert msg in lib.lhf_last_error().decode()
+        st = lib.lhf_batch_create(C.byref(h), C.byref(d), 2, P(off, C.c_int64), dummy, P(lo, C.c_double),
+                                  P(lns, C.c_double), P(aa, C.c_double), None, None, None)
+        assert st == -1 and h.value is None, (msg, st)
+    off = i64([0, 5, 9])
+    bad_depth = np.ascontiguousarray([3, 11], np.int32)
+    st = lib.lhf_batch_create(C.byref(h), C.byref(d), 2, P(off, C.c_int64), dummy, P(lo, C.c_double),
+                              P(ln, C.c_double), P(a, C.c_double), P(bad_depth, C.c_int32), None, None)
+    assert st == -1 and "sys_depth" in lib.lhf_last_error().decode()
+    assert lib.lhf_batch_execute(None, dummy, dummy, dummy, 1, None) == -1
+    assert lib.lhf_batch_destroy(None) == 0
+    assert lib.lhf_autotune(8, 7, None, None, None) == -1

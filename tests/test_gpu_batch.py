@@ -1,0 +1,191 @@
+"""GPU parity of the multi-system plan and of the batch executor (one HIP graph).
+
+Every system of a multi-system plan or batch must equal the oracle's FMM of that
+system alone (its own cube, core radius and depth): FP64 relative L2 <= 1e-12 per
+system; FP32 <= 2e-6 against the FP64 oracle on the FP32-rounded inputs.  Graph
+replays must equal direct launches bit for bit where every kernel accumulates in
+a fixed order (orders whose batched M2L owns its targets, e.g. FP64 p = 6), and
+to 1e-14 where the batched M2L accumulates with LDS atomics (FP64 p = 8).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch
+
+
+def _systems(sizes, seed, dtype=np.float64):
+    """systems in distinct, differently sized cubes; returns x, w, offsets, lo, L, a"""
+    rng = np.random.default_rng(seed)
+    ns = len(sizes)
+    lo = np.stack([np.arange(ns) * 1.5, -0.5 * np.arange(ns), 0.25 * np.arange(ns)], axis=1).astype(np.float64)
+    L = 1.0 + 0.3 * (np.arange(ns) % 4)
+    xs, ws = [], []
+    for k, nk in enumerate(sizes):
+        xs.append(lo[k] + L[k] * rng.uniform(0.0, 1.0, (nk, 3)) * (1 - 1e-12))
+        ws.append(rng.normal(size=(nk, 3)))
+    x = np.concatenate(xs).astype(dtype).astype(np.float64)
+    w = np.concatenate(ws).astype(dtype).astype(np.float64)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    a = np.array([0.5 * L[k] * max(nk, 1) ** (-1 / 3) for k, nk in enumerate(sizes)])
+    a = a.astype(dtype).astype(np.float64)
+    return x, w, off, lo, L, a
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _per_system_oracle(oracle, x, w, off, lo, L, a, p, depths):
+    out_v, out_s = np.zeros_like(x), np.zeros_like(x)
+    for k in range(len(off) - 1):
+        i0, i1 = off[k], off[k + 1]
+        if i1 == i0:
+            continue
+        v, s, _ = oracle.fmm(x[i0:i1], w[i0:i1], float(a[k]), p, int(depths[k]), lo=lo[k], L=float(L[k]))
+        out_v[i0:i1], out_s[i0:i1] = v, s
+    return out_v, out_s
+
+
+def _check_systems(v, s, vr, sr, off, bar):
+    scale_v, scale_s = np.abs(vr).max(), np.abs(sr).max()
+    for k in range(len(off) - 1):
+        i0, i1 = off[k], off[k + 1]
+        if i1 - i0 < 2:
+            # zero or one element: no interaction at all
+            assert np.abs(v[i0:i1]).max(initial=0.0) <= bar * scale_v
+            assert np.abs(s[i0:i1]).max(initial=0.0) <= bar * scale_s
+            continue
+        ev, es = _rel(v[i0:i1], vr[i0:i1]), _rel(s[i0:i1], sr[i0:i1])
+        print(f"system {k} (n={i1 - i0}): rel L2 v {ev:.3e} s {es:.3e}", flush=True)
+        assert ev <= bar and es <= bar
+
+
+@pytest.mark.parametrize("tiled", [True, False])
+def test_multi_plan_fp64_matches_per_system_oracle(oracle, monkeypatch, tiled):
+    torch = _torch()
+    if not tiled:
+        monkeypatch.setenv("LHF_NO_TILE", "1")
+    import paper_1201_5430_amd as LH
+    sizes = [700, 0, 1500, 300, 2500, 1, 900]
+    p, depth = 8, 3
+    x, w, off, lo, L, a = _systems(sizes, 11)
+    xt = torch.from_numpy(x).cuda()
+    wt = torch.from_numpy(w).cuda()
+    plan = LH.Plan(xt, a, p=p, depth=depth, precision=LH.FP64, lo=lo, L=L, offsets=off)
+    v, s = plan.execute(wt)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    plan.close()
+    vr, sr = _per_system_oracle(oracle, x, w, off, lo, L, a, p, [depth] * len(sizes))
+    _check_systems(v.cpu().numpy(), s.cpu().numpy(), vr, sr, off, 1e-12)
+    # counts are the sums over systems
+    n_m2l = sum(oracle.fmm(x[off[k]:off[k + 1]], w[off[k]:off[k + 1]], float(a[k]), p, depth, lo=lo[k],
+                           L=float(L[k]), near=False)[2]["n_m2l"] for k in range(len(sizes)) if sizes[k] > 0)
+    assert st["n_m2l"] == n_m2l
+
+
+def test_multi_plan_tiled_m2l_fp32(oracle):
+    # depth 4 with many systems: the batched M2L kernel's box maps carry the system index
+    torch = _torch()
+    import paper_1201_5430_amd as LH
+    sizes = [3000, 2000, 4000, 1000, 2500]
+    p, depth = 8, 4
+    x, w, off, lo, L, a = _systems(sizes, 12, dtype=np.float32)
+    xt = torch.from_numpy(x).float().cuda()
+    wt = torch.from_numpy(w).float().cuda()
+    plan = LH.Plan(xt, a, p=p, depth=depth, precision=LH.FP32, lo=lo, L=L, offsets=off)
+    v, s = plan.execute(wt)
+    torch.cuda.synchronize()
+    plan.close()
+    vr, sr = _per_system_oracle(oracle, x, w, off, lo, L, a, p, [depth] * len(sizes))
+    _check_systems(v.double().cpu().numpy(), s.double().cpu().numpy(), vr, sr, off, 2e-6)
+
+
+def _same(a, b, exact):
+    assert np.isfinite(a).all()
+    if exact:
+        return np.array_equal(a, b)
+    d = _rel(a, b)
+    print(f"graph vs direct: rel L2 {d:.3e}", flush=True)
+    return d <= 1e-14
+
+
+@pytest.mark.parametrize("p,exact", [(6, True), (8, False)])
+def test_batch_graph_replays_and_matches_oracle(oracle, p, exact):
+    torch = _torch()
+    import paper_1201_5430_amd as LH
+    sizes, _ = workloads.batched_sizes(10, 21, lo=200, hi=4000)
+    sizes = [int(n) for n in sizes]
+    depths = [2 + (k % 3) for k in range(len(sizes))]
+    x, w, off, lo, L, a = _systems(sizes, 13)
+    xt = torch.from_numpy(x).cuda()
+    wt = torch.from_numpy(w).cuda()
+    B = LH.Batch(xt, off, a, p=p, precision=LH.FP64, lo=lo, L=L, depths=depths)
+    info = B.info()
+    assert info["n_groups"] == 3 and list(info["depths"]) == depths
+    ve, se = B.execute(wt, graph=False)
+    torch.cuda.synchronize()
+    ve, se = ve.cpu().numpy(), se.cpu().numpy()
+    vg = torch.empty_like(wt)
+    sg = torch.empty_like(wt)
+    for rep in range(3):
+        vg.fill_(float("nan"))
+        sg.fill_(float("nan"))
+        B.execute(wt, vg, sg, graph=True)
+        torch.cuda.synchronize()
+        # eager work between replays
+        _ = (wt * 2.0).sum().item()
+        assert _same(vg.cpu().numpy(), ve, exact) and _same(sg.cpu().numpy(), se, exact), f"replay {rep}"
+    # new output buffers: captured again
+    v2, s2 = B.execute(wt, graph=True)
+    torch.cuda.synchronize()
+    assert _same(v2.cpu().numpy(), ve, exact) and _same(s2.cpu().numpy(), se, exact)
+    B.close()
+    vr, sr = _per_system_oracle(oracle, x, w, off, lo, L, a, p, depths)
+    _check_systems(ve, se, vr, sr, off, 1e-12)
+
+
+def test_batch_auto_depths_fp32(oracle):
+    torch = _torch()
+    import paper_1201_5430_amd as LH
+    sizes, _ = workloads.batched_sizes(8, 22, lo=1024, hi=8192)
+    sizes = [int(n) for n in sizes]
+    p = 10
+    x, w, off, lo, L, a = _systems(sizes, 14, dtype=np.float32)
+    tune = LH.tune_default(p, LH.FP32)
+    # a looser tol than 1e-6 lets the cost model choose among several depths
+    tol = 1e-3
+    expect = [LH.choose_depth(tune, n, float(L[k]), float(a[k]), tol)[0] for k, n in enumerate(sizes)]
+    xt = torch.from_numpy(x).float().cuda()
+    wt = torch.from_numpy(w).float().cuda()
+    B = LH.Batch(xt, off, a, p=p, precision=LH.FP32, lo=lo, L=L, tol=tol, tune=tune)
+    info = B.info()
+    assert list(info["depths"]) == expect
+    v, s = B.execute(wt, graph=True)
+    torch.cuda.synchronize()
+    B.close()
+    vr, sr = _per_system_oracle(oracle, x, w, off, lo, L, a, p, expect)
+    _check_systems(v.double().cpu().numpy(), s.double().cpu().numpy(), vr, sr, off, 2e-6)
+
+
+def test_autotune_measures_and_caches(tmp_path):
+    _torch()
+    import paper_1201_5430_amd as LH
+    path = str(tmp_path / "tune.json")
+    t1 = LH.autotune(8, LH.FP32, cache_path=path)
+    assert t1.t_box_ns > 0 and t1.t_pair_ns > 0 and math.isfinite(t1.t_box_ns)
+    t2 = LH.autotune(8, LH.FP32, cache_path=path)
+    assert abs(t2.t_box_ns - t1.t_box_ns) <= 1e-6 * t1.t_box_ns
+    assert abs(t2.t_pair_ns - t1.t_pair_ns) <= 1e-6 * t1.t_pair_ns
+    print(f"p=8 FP32: {t1.t_box_ns:.2f} ns/box, {t1.t_pair_ns:.5f} ns/pair", flush=True)
