@@ -106,6 +106,99 @@ def cpu_baseline(cfg, n_leaves=64):
     }
 
 
+def run_batch(lhf, torch, steps, warmup, with_accuracy):
+    """256 independent systems (sizes log-uniform in [1024, 65536]) in one batch: per-system
+    depth from the measured cost model, all depth groups replayed as one HIP graph"""
+    import numpy as np
+    import workloads
+    cfg = workloads.CONFIGS["batch256_fp32"]
+    sizes, systems = workloads.batched(cfg["n_systems"], cfg["seed"])
+    p, ns = cfg["p"], len(sizes)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = np.concatenate([sx for sx, _ in systems])
+    w = np.concatenate([sw for _, sw in systems])
+    a = np.array([workloads.core_radius(int(k)) for k in sizes])
+    n = int(off[-1])
+    log(f"bench: batch of {ns} systems, N = {n}, p = {p}, FP32")
+    xt = torch.from_numpy(x).to(device="cuda", dtype=torch.float32)
+    wt = torch.from_numpy(w).to(device="cuda", dtype=torch.float32)
+    v = torch.empty_like(wt)
+    s = torch.empty_like(wt)
+    t0 = time.perf_counter()
+    tune = lhf.autotune(p, lhf.FP32)
+    t_tune = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B = lhf.Batch(xt, off, a, p=p, precision=lhf.FP32, tune=tune)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    info = B.info()
+    for _ in range(max(warmup, 1)):
+        B.execute(wt, v, s, graph=True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        B.execute(wt, v, s, graph=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_exec = ev0.elapsed_time(ev1) / steps
+    log(f"bench: batch graph {ms_exec:.3f} ms per execute")
+    # the same systems as separate single-system plans, executed one after another
+    plans = []
+    for k in range(ns):
+        i0, i1 = int(off[k]), int(off[k + 1])
+        plans.append((lhf.Plan(xt[i0:i1], float(a[k]), p=p, depth=int(info["depths"][k]), precision=lhf.FP32),
+                      i0, i1))
+    vs, ss = torch.empty_like(wt), torch.empty_like(wt)
+    for pl, i0, i1 in plans:
+        pl.execute(wt[i0:i1], vs[i0:i1], ss[i0:i1])
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        for pl, i0, i1 in plans:
+            pl.execute(wt[i0:i1], vs[i0:i1], ss[i0:i1])
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_sep = ev0.elapsed_time(ev1) / steps
+    for pl, _, _ in plans:
+        pl.close()
+    depths, counts = np.unique(info["depths"], return_counts=True)
+    res = {
+        "workload": "batch256_fp32", "n_systems": ns, "n": n, "p": p,
+        "sizes": {"min": int(sizes.min()), "median": int(np.median(sizes)), "max": int(sizes.max())},
+        "depth_groups": {int(dd): int(c) for dd, c in zip(depths, counts)},
+        "core_split_warning": bool(B.warn_core_split),
+        "tune": {"t_box_ns": tune.t_box_ns, "t_pair_ns": tune.t_pair_ns, "seconds": t_tune},
+        "plan_ms": t_plan * 1e3,
+        "execute_ms": ms_exec,
+        "elements_per_s": n / ((t_plan * 1e3 + ms_exec) * 1e-3),
+        "execute_only_elements_per_s": n / (ms_exec * 1e-3),
+        "mean_system_execute_us": ms_exec * 1e3 / ns,
+        "separate_plans_execute_ms": ms_sep,
+        "graph_speedup_vs_separate_plans": ms_sep / ms_exec,
+        "counts": {"m2l": info["n_m2l"], "p2p_pairs": info["n_p2p_pairs"]},
+    }
+    if with_accuracy:
+        import oracle
+        vh, sh = v.double().cpu().numpy(), s.double().cpu().numpy()
+        errs = []
+        order = np.argsort(sizes)
+        for k in (int(order[0]), int(order[ns // 2]), int(order[-1])):
+            i0, i1 = int(off[k]), int(off[k + 1])
+            xk = x[i0:i1].astype(np.float32).astype(np.float64)
+            wk = w[i0:i1].astype(np.float32).astype(np.float64)
+            tg = workloads.sample_targets(i1 - i0, 200, seed=2000 + k)
+            vd, sd = oracle.direct(xk, wk, float(np.float32(a[k])), mode=oracle.DIRECT_SPLIT,
+                                   depth=int(info["depths"][k]), targets=tg)
+            errs.append({"system": k, "n": i1 - i0, "depth": int(info["depths"][k]),
+                         "rel_l2_v": float(np.linalg.norm(vh[i0:i1][tg] - vd) / np.linalg.norm(vd)),
+                         "rel_l2_s": float(np.linalg.norm(sh[i0:i1][tg] - sd) / np.linalg.norm(sd))})
+        res["accuracy_sampled_systems"] = errs
+    B.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +207,7 @@ def main():
     ap.add_argument("--workload", default="cube1m_fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 run on the same input")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batched run")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only copy a buffer of this many MiB on the device (HBM counter calibration)")
     args = ap.parse_args()
@@ -239,6 +333,8 @@ def main():
             "m2l_achieved_tflops": r32["achieved"],
             "m2l_frac_of_fp32_vector_peak": r32["achieved"] / PEAK_FP32_VALU_TFLOPS,
         }
+    if args.workload == "cube1m_fp64" and not args.no_batch:
+        out["batch"] = run_batch(lhf, torch, args.steps, args.warmup, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline (sampled) ...")
         out["cpu_baseline"] = cpu_baseline(cfg)

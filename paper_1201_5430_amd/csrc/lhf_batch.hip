@@ -352,13 +352,13 @@ extern "C" {
 void lhf_tune_default(int32_t p, int32_t precision, lhf_tune *t)
 {
     if (!t) return;
-    // unit costs of the uniform-cube runs of this library on MI355X at p = 10 (FP32)
-    // and p = 12 (FP64), scaled to other p by the p^3 work of a rotation-based M2L
+    // unit costs measured with this library on MI355X (uniform cubes, FP32 at p = 10,
+    // FP64 at p = 12), scaled to other p by the p^3 work of a rotation-based M2L
     const double q = (double)p * p * p;
     t->p = p;
     t->precision = precision;
-    t->t_box_ns = precision == LHF_FP64 ? 40.0 * q / 1728.0 : 6.0 * q / 1000.0;
-    t->t_pair_ns = precision == LHF_FP64 ? 0.010 : 0.0025;
+    t->t_box_ns = precision == LHF_FP64 ? 430.0 * q / 1728.0 : 330.0 * q / 1000.0;
+    t->t_pair_ns = precision == LHF_FP64 ? 0.012 : 0.0042;
 }
 
 lhf_status lhf_autotune(int32_t p, int32_t precision, const char *cache_path, lhf_tune *out, void *stream)

@@ -189,3 +189,37 @@ def test_autotune_measures_and_caches(tmp_path):
     assert abs(t2.t_box_ns - t1.t_box_ns) <= 1e-6 * t1.t_box_ns
     assert abs(t2.t_pair_ns - t1.t_pair_ns) <= 1e-6 * t1.t_pair_ns
     print(f"p=8 FP32: {t1.t_box_ns:.2f} ns/box, {t1.t_pair_ns:.5f} ns/pair", flush=True)
+
+
+def test_batch256_full_size_sampled(oracle):
+    # the full 256-system workload (sizes log-uniform in [1024, 65536]) with the cost-model depths,
+    # in the launch configuration the benchmark times (graph replay); the three smallest systems are
+    # checked whole, the largest on the leaves of 30 seeded elements
+    torch = _torch()
+    import paper_1201_5430_amd as LH
+    cfg = workloads.CONFIGS["batch256_fp32"]
+    sizes, systems = workloads.batched(cfg["n_systems"], cfg["seed"])
+    p = cfg["p"]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = np.concatenate([sx for sx, _ in systems]).astype(np.float32)
+    w = np.concatenate([sw for _, sw in systems]).astype(np.float32)
+    a = np.array([workloads.core_radius(int(k)) for k in sizes]).astype(np.float32)
+    xt, wt = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+    B = LH.Batch(xt, off, a.astype(np.float64), p=p, precision=LH.FP32)
+    depths = B.info()["depths"]
+    B.execute(wt, graph=True)
+    v, s = B.execute(wt, graph=True)
+    torch.cuda.synchronize()
+    B.close()
+    v, s = v.double().cpu().numpy(), s.double().cpu().numpy()
+    assert np.isfinite(v).all() and np.isfinite(s).all()
+    order = np.argsort(sizes)
+    for k in list(order[:3]) + [order[-1]]:
+        i0, i1 = int(off[k]), int(off[k + 1])
+        xk, wk = x[i0:i1].astype(np.float64), w[i0:i1].astype(np.float64)
+        samp = None if k != order[-1] else np.random.default_rng(7).choice(i1 - i0, 30, replace=False)
+        vr, sr, _ = oracle.fmm(xk, wk, float(a[k]), p, int(depths[k]), sample=samp)
+        m = ~np.isnan(vr[:, 0])
+        ev, es = _rel(v[i0:i1][m], vr[m]), _rel(s[i0:i1][m], sr[m])
+        print(f"system {k} n={i1 - i0} depth={depths[k]}: rel L2 v {ev:.3e} s {es:.3e}", flush=True)
+        assert ev < 2e-6 and es < 2e-6
