@@ -39,7 +39,9 @@ def build(force: bool = True) -> str:
 class _Stats(C.Structure):
     _fields_ = [("n_m2l", C.c_int64), ("n_m2m", C.c_int64), ("n_l2l", C.c_int64),
                 ("n_p2p_pairs", C.c_int64), ("t_tree", C.c_double), ("t_up", C.c_double),
-                ("t_down", C.c_double), ("t_near", C.c_double)]
+                ("t_down", C.c_double), ("t_near", C.c_double), ("n_wx_pairs", C.c_int64),
+                ("n_leaf", C.c_int64), ("n_box", C.c_int64), ("max_level", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 def lib():
@@ -66,6 +68,14 @@ def lib():
         L.lho_tree_counts.argtypes = [C.c_int64, _dp, C.c_int, _dp, C.c_double, _ip,
                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lho_num_threads.restype = C.c_int
+        L.lho_fmm_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int, C.c_int64, C.c_int, _dp,
+                                       C.c_double, C.c_int, C.c_int64, C.c_void_p, _dp, _dp, C.POINTER(_Stats)]
+        L.lho_fmm_adaptive.restype = C.c_int
+        L.lho_direct_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int64, C.c_int, _dp, C.c_double,
+                                          C.c_int64, C.c_void_p, _dp, _dp]
+        L.lho_adaptive_coverage.argtypes = [C.c_int64, _dp, C.c_int64, C.c_int, _dp, C.c_double,
+                                            C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.lho_adaptive_counts.argtypes = [C.c_int64, _dp, C.c_int64, C.c_int, _dp, C.c_double, _ip, _ip]
         _lib = L
     return _lib
 
@@ -227,3 +237,84 @@ def tree_counts(x, depth, lo=(0.0, 0.0, 0.0), L=1.0):
     a, b = C.c_int64(), C.c_int64()
     lib().lho_tree_counts(x.shape[0], x, int(depth), _f64(lo, (3,)), float(L), nb, C.byref(a), C.byref(b))
     return nb, a.value, b.value
+
+
+def fmm_adaptive(x, w, a, p, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True,
+                 sample=None):
+    """Adaptive-octree FMM (split while a box holds more than max_per_leaf elements, down to
+    max_level); W/X interactions summed directly with the singular kernel.  With ``sample``
+    only the leaves holding those elements are evaluated (other outputs NaN)."""
+    x = _f64(x).reshape(-1, 3)
+    w = _f64(w).reshape(-1, 3)
+    n = x.shape[0]
+    v = np.zeros((n, 3)); s = np.zeros((n, 3))
+    if sample is None:
+        ns, sp = 0, None
+    else:
+        sample = np.ascontiguousarray(sample, np.int64)
+        ns, sp = sample.shape[0], sample.ctypes.data
+    st = _Stats()
+    what = (1 if far else 0) | (2 if near else 0)
+    rc = lib().lho_fmm_adaptive(n, x, w, float(a), int(p), int(max_per_leaf), int(max_level), _f64(lo, (3,)),
+                                float(L), what, ns, sp, v, s, C.byref(st))
+    if rc != 0:
+        raise ValueError("oracle adaptive fmm rejected its arguments")
+    if sample is not None:
+        leaf = adaptive_leaf_of(x, max_per_leaf, max_level, lo, L)
+        mask = np.isin(leaf, np.unique(leaf[sample]))
+        v[~mask] = np.nan
+        s[~mask] = np.nan
+    stats = dict(n_m2l=st.n_m2l, n_p2p_pairs=st.n_p2p_pairs, n_wx_pairs=st.n_wx_pairs, n_leaf=st.n_leaf,
+                 n_box=st.n_box, max_level=st.max_level, t_tree=st.t_tree, t_up=st.t_up, t_down=st.t_down,
+                 t_near=st.t_near)
+    return v, s, stats
+
+
+def adaptive_leaf_of(x, max_per_leaf, max_level, lo=(0.0, 0.0, 0.0), L=1.0):
+    """(level << 40) | cell index of the adaptive leaf holding each element (numpy, for sampling)"""
+    q = np.clip(np.floor((np.asarray(x) - np.asarray(lo)[None, :]) * (float(2 ** 21) / L)), 0, 2 ** 21 - 1)
+    q = q.astype(np.int64)
+    out = np.full(q.shape[0], -1, np.int64)
+    undecided = np.ones(q.shape[0], bool)
+    for l in range(max_level + 1):
+        c = q >> (21 - l)
+        cell = (c[:, 0] << (2 * l)) | (c[:, 1] << l) | c[:, 2]
+        _, inv, cnt = np.unique(cell, return_inverse=True, return_counts=True)
+        stop = undecided & ((cnt[inv] <= max_per_leaf) | (l == max_level))
+        out[stop] = (l << 40) | cell[stop]
+        undecided &= ~stop
+    return out
+
+
+def direct_adaptive(x, w, a, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), L=1.0, targets=None):
+    """Direct sums with the adaptive split rule (smoothed kernel between adjacent leaves)."""
+    x = _f64(x).reshape(-1, 3)
+    w = _f64(w).reshape(-1, 3)
+    n = x.shape[0]
+    if targets is None:
+        nt, tp = n, None
+    else:
+        targets = np.ascontiguousarray(targets, np.int64)
+        nt, tp = targets.shape[0], targets.ctypes.data
+    v = np.zeros((nt, 3)); s = np.zeros((nt, 3))
+    lib().lho_direct_adaptive(n, x, w, float(a), int(max_per_leaf), int(max_level), _f64(lo, (3,)), float(L),
+                              nt, tp, v, s)
+    return v, s
+
+
+def adaptive_coverage(x, max_per_leaf, max_level, lo=(0.0, 0.0, 0.0), L=1.0):
+    """(min, max) number of mechanisms carrying each ordered leaf pair, and the leaf count"""
+    x = _f64(x).reshape(-1, 3)
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    lib().lho_adaptive_coverage(x.shape[0], x, int(max_per_leaf), int(max_level), _f64(lo, (3,)), float(L),
+                                C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value
+
+
+def adaptive_counts(x, max_per_leaf, max_level, lo=(0.0, 0.0, 0.0), L=1.0):
+    """boxes and leaves per level of the adaptive tree"""
+    x = _f64(x).reshape(-1, 3)
+    nb = np.zeros(max_level + 1, np.int64)
+    nl = np.zeros(max_level + 1, np.int64)
+    lib().lho_adaptive_counts(x.shape[0], x, int(max_per_leaf), int(max_level), _f64(lo, (3,)), float(L), nb, nl)
+    return nb, nl

@@ -725,6 +725,9 @@ void lho_direct(int64_t n, const double *x, const double *w, double a, int mode,
 typedef struct {
     int64_t n_m2l, n_m2m, n_l2l, n_p2p_pairs;
     double t_tree, t_up, t_down, t_near; /* wall-clock seconds of the phases */
+    int64_t n_wx_pairs;                  /* adaptive: W/X pairs summed directly (singular) */
+    int64_t n_leaf, n_box;               /* adaptive: leaves and boxes of the tree */
+    int32_t max_level, reserved;
 } lho_stats;
 
 static double wtime(void)
@@ -791,7 +794,8 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
     tree_build(&T, n, x, depth, lo, L);
     size_t P2 = (size_t)p * p;
     int smooth = a > 0.0;
-    lho_stats stats = {0, 0, 0, 0, 0.0, 0.0, 0.0, 0.0};
+    lho_stats stats;
+    memset(&stats, 0, sizeof(stats));
     stats.t_tree = wtime() - t0;
 
     /* which leaves to evaluate */
@@ -1097,4 +1101,577 @@ int lho_tree_counts(int64_t n, const double *x, int depth, const double lo[3], d
     *n_p2p = pp - n; /* self pairs excluded */
     tree_free(&T);
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* (C) adaptive octree FMM                                                     */
+/*                                                                            */
+/* Tree: a box is split while it holds more than maxleaf elements, down to    */
+/* level maxl.  Box (l, k) belongs to the tree iff l = 0 or its parent holds  */
+/* more than maxleaf elements; it is a leaf iff it belongs and holds at most  */
+/* maxleaf elements or l = maxl.  Lists after Carrier, Greengard & Rokhlin    */
+/* (the adaptive scheme the paper builds on), with closed adjacency of boxes  */
+/* of any sizes:                                                              */
+/*   U(b), b leaf:  leaves adjacent to b (b included) -- direct, smoothed;    */
+/*   V(B), level>=2: same-level boxes of the tree, not adjacent to B, whose   */
+/*                   parents are adjacent -- M2L;                             */
+/*   W(b), b leaf:  boxes of the tree below a colleague of b (same-level      */
+/*                   adjacent box), whose parent is adjacent to b but which   */
+/*                   are not -- here summed directly with the singular kernel;*/
+/*   X(B):          leaves C with B in W(C) -- likewise direct, singular.     */
+/* A target leaf b receives L2P of its local expansion (levels >= 2, built by */
+/* L2L + M2L over V down its ancestor chain), U(b) smoothed, and W(b) plus    */
+/* X(A) for every A from b up to the root, singular.                          */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    otree T;
+    int maxl;
+    int64_t maxleaf;
+    char *in[MAXLEV + 1];
+    char *leaf[MAXLEV + 1];
+} atree;
+
+static void atree_build(atree *A, int64_t n, const double *x, int64_t maxleaf, int maxl, const double lo[3],
+                        double L)
+{
+    tree_build(&A->T, n, x, maxl, lo, L);
+    A->maxl = maxl;
+    A->maxleaf = maxleaf;
+    for (int l = 0; l <= maxl; l++) {
+        A->in[l] = (char *)calloc((size_t)A->T.nb[l] + 1, 1);
+        A->leaf[l] = (char *)calloc((size_t)A->T.nb[l] + 1, 1);
+        for (int64_t b = 0; b < A->T.nb[l]; b++) {
+            int in = 1;
+            if (l > 0) {
+                int64_t pb = tree_find(&A->T, l - 1, A->T.key[l][b] >> 3);
+                in = A->in[l - 1][pb] && A->T.count[l - 1][pb] > maxleaf;
+            }
+            A->in[l][b] = (char)in;
+            A->leaf[l][b] = (char)(in && (A->T.count[l][b] <= maxleaf || l == maxl));
+        }
+    }
+}
+
+static void atree_free(atree *A)
+{
+    for (int l = 0; l <= A->maxl; l++) {
+        free(A->in[l]);
+        free(A->leaf[l]);
+    }
+    tree_free(&A->T);
+}
+
+/* closed boxes (l1, k1) and (l2, k2) touch or overlap */
+static int adjacent(int l1, uint64_t k1, int l2, uint64_t k2)
+{
+    int c1[3], c2[3];
+    box_coords(k1, c1);
+    box_coords(k2, c2);
+    for (int d = 0; d < 3; d++) {
+        int64_t lo1 = (int64_t)c1[d] << (QBITS - l1), hi1 = (int64_t)(c1[d] + 1) << (QBITS - l1);
+        int64_t lo2 = (int64_t)c2[d] << (QBITS - l2), hi2 = (int64_t)(c2[d] + 1) << (QBITS - l2);
+        if (lo1 > hi2 || lo2 > hi1) return 0;
+    }
+    return 1;
+}
+
+/* tree box at level l with key k, or -1 */
+static int64_t atree_find(const atree *A, int l, uint64_t k)
+{
+    int64_t b = tree_find(&A->T, l, k);
+    return (b >= 0 && A->in[l][b]) ? b : -1;
+}
+
+/* first index at level l whose key is >= k */
+static int64_t lower_key(const otree *T, int l, uint64_t k)
+{
+    int64_t lo = 0, hi = T->nb[l];
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (T->key[l][mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+/* same-level neighbours (colleagues) of (l, k) that belong to the tree, self excluded */
+static int colleagues(const atree *A, int l, uint64_t k, int64_t *out)
+{
+    int c[3];
+    box_coords(k, c);
+    int nside = 1 << l, cnt = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                if (!dx && !dy && !dz) continue;
+                int cc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                if (cc[0] < 0 || cc[1] < 0 || cc[2] < 0 || cc[0] >= nside || cc[1] >= nside || cc[2] >= nside)
+                    continue;
+                int64_t b = atree_find(A, l, morton((uint32_t)cc[0], (uint32_t)cc[1], (uint32_t)cc[2]));
+                if (b >= 0) out[cnt++] = b;
+            }
+    return cnt;
+}
+
+/* a growable list of (level, box) */
+typedef struct {
+    int *lev;
+    int64_t *box;
+    int64_t n, cap;
+} blist;
+
+static void blist_push(blist *L, int l, int64_t b)
+{
+    if (L->n == L->cap) {
+        L->cap = L->cap ? 2 * L->cap : 64;
+        L->lev = (int *)realloc(L->lev, sizeof(int) * (size_t)L->cap);
+        L->box = (int64_t *)realloc(L->box, sizeof(int64_t) * (size_t)L->cap);
+    }
+    L->lev[L->n] = l;
+    L->box[L->n] = b;
+    L->n++;
+}
+
+static void blist_free(blist *L)
+{
+    free(L->lev);
+    free(L->box);
+}
+
+/* U(b): leaves adjacent to leaf (lb, b) -- every leaf lies below some tree box at
+ * level min(lb, its level); scan all leaves inside the 3x3x3 block around b at each level */
+static void list_U(const atree *A, int lb, int64_t b, blist *out)
+{
+    const otree *T = &A->T;
+    uint64_t kb = T->key[lb][b];
+    for (int l = 0; l <= A->maxl; l++) {
+        if (l <= lb) {
+            /* coarser or same level: the candidate is the neighbour of b's ancestor */
+            uint64_t ka = kb >> (3 * (lb - l));
+            int c[3];
+            box_coords(ka, c);
+            int nside = 1 << l;
+            for (int dz = -1; dz <= 1; dz++)
+                for (int dy = -1; dy <= 1; dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                        int cc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                        if (cc[0] < 0 || cc[1] < 0 || cc[2] < 0 || cc[0] >= nside || cc[1] >= nside ||
+                            cc[2] >= nside)
+                            continue;
+                        uint64_t kc = morton((uint32_t)cc[0], (uint32_t)cc[1], (uint32_t)cc[2]);
+                        int64_t q = atree_find(A, l, kc);
+                        if (q >= 0 && A->leaf[l][q] && adjacent(lb, kb, l, kc)) blist_push(out, l, q);
+                    }
+        } else {
+            /* finer leaves: descendants of b's colleagues */
+            int64_t col[26];
+            int nc = colleagues(A, lb, kb, col);
+            for (int i = 0; i < nc; i++) {
+                uint64_t kc = T->key[lb][col[i]];
+                int sh = 3 * (l - lb);
+                for (int64_t q = lower_key(T, l, kc << sh); q < T->nb[l] && (T->key[l][q] >> sh) == kc; q++)
+                    if (A->leaf[l][q] && adjacent(lb, kb, l, T->key[l][q])) blist_push(out, l, q);
+            }
+        }
+    }
+}
+
+/* W(b): tree boxes below a colleague of leaf (lb, b), parent adjacent to b, itself not */
+static void list_W(const atree *A, int lb, int64_t b, blist *out)
+{
+    const otree *T = &A->T;
+    uint64_t kb = T->key[lb][b];
+    int64_t col[26];
+    int nc = colleagues(A, lb, kb, col);
+    for (int i = 0; i < nc; i++) {
+        uint64_t kc = T->key[lb][col[i]];
+        for (int l = lb + 1; l <= A->maxl; l++) {
+            int sh = 3 * (l - lb);
+            for (int64_t q = lower_key(T, l, kc << sh); q < T->nb[l] && (T->key[l][q] >> sh) == kc; q++) {
+                if (!A->in[l][q]) continue;
+                uint64_t kq = T->key[l][q];
+                if (adjacent(l - 1, kq >> 3, lb, kb) && !adjacent(l, kq, lb, kb)) blist_push(out, l, q);
+            }
+        }
+    }
+}
+
+/* X(B) for tree box (la, a): leaves C (coarser than B) with B in W(C), i.e. C is a
+ * colleague of B's ancestor at C's level, C is adjacent to B's parent, not to B */
+static void list_X(const atree *A, int la, int64_t a, blist *out)
+{
+    const otree *T = &A->T;
+    uint64_t ka = T->key[la][a];
+    for (int lc = 0; lc < la; lc++) {
+        uint64_t kanc = ka >> (3 * (la - lc));
+        int64_t col[26];
+        int nc = colleagues(A, lc, kanc, col);
+        for (int i = 0; i < nc; i++) {
+            if (!A->leaf[lc][col[i]]) continue;
+            uint64_t kc = T->key[lc][col[i]];
+            if (adjacent(la - 1, ka >> 3, lc, kc) && !adjacent(la, ka, lc, kc)) blist_push(out, lc, col[i]);
+        }
+    }
+}
+
+/* V(B) restricted to the tree (level >= 2) */
+static int list_V(const atree *A, int l, uint64_t k, int64_t *out)
+{
+    int64_t tmp[189];
+    int nv = vlist(&A->T, l, k, tmp), cnt = 0;
+    for (int i = 0; i < nv; i++)
+        if (A->in[l][tmp[i]]) out[cnt++] = tmp[i];
+    return cnt;
+}
+
+/* add the direct sum over the elements of box (l, q) into target element j */
+static int64_t box_direct(const atree *A, const double *x, const double *w, double a, int smooth, int l,
+                          int64_t q, int64_t j, double *vv, double *ss)
+{
+    const otree *T = &A->T;
+    int64_t np = 0;
+    for (int64_t is = 0; is < T->count[l][q]; is++) {
+        int64_t i = T->order[T->first[l][q] + is];
+        if (i == j) continue;
+        pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, smooth, vv, ss, NULL);
+        np++;
+    }
+    return np;
+}
+
+/* Adaptive FMM of v and s (FP64, direct-mode translations).  what / sample as
+ * in lho_fmm (sample: the leaves holding the sampled elements are evaluated).
+ * maxleaf >= 0, 1 <= maxl <= 10.  Returns 0 on success. */
+int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int p, int64_t maxleaf, int maxl,
+                     const double lo[3], double L, int what, int64_t nsample, const int64_t *sample, double *v,
+                     double *s, lho_stats *st)
+{
+    if (maxl < 1 || maxl > 10 || p < 1 || n < 1 || maxleaf < 0) return -1;
+    double t0 = wtime();
+    atree A;
+    atree_build(&A, n, x, maxleaf, maxl, lo, L);
+    const otree *T = &A.T;
+    size_t P2 = (size_t)p * p;
+    int smooth = a > 0.0;
+    lho_stats stats;
+    memset(&stats, 0, sizeof(stats));
+    for (int l = 0; l <= maxl; l++)
+        for (int64_t b = 0; b < T->nb[l]; b++) {
+            stats.n_box += A.in[l][b];
+            stats.n_leaf += A.leaf[l][b];
+            if (A.in[l][b]) stats.max_level = l;
+        }
+    /* wanted leaves */
+    char *want[MAXLEV + 1];
+    for (int l = 0; l <= maxl; l++) {
+        want[l] = (char *)calloc((size_t)T->nb[l] + 1, 1);
+        for (int64_t b = 0; b < T->nb[l]; b++) want[l][b] = (char)(A.leaf[l][b] && !sample);
+    }
+    if (sample)
+        for (int64_t i = 0; i < nsample; i++) {
+            int64_t e = sample[i];
+            for (int l = 0; l <= maxl; l++) {
+                int sh = QBITS - l;
+                int64_t b = atree_find(&A, l, morton(T->q[3 * e] >> sh, T->q[3 * e + 1] >> sh, T->q[3 * e + 2] >> sh));
+                if (b >= 0 && A.leaf[l][b]) {
+                    want[l][b] = 1;
+                    break;
+                }
+            }
+        }
+    stats.t_tree = wtime() - t0;
+
+    if (what & 1) {
+        double t1 = wtime();
+        /* upward: P2M at leaves of levels >= 2, M2M into the non-leaf boxes */
+        cplx *M[MAXLEV + 1] = {0}, *Lc[MAXLEV + 1] = {0};
+        for (int l = 2; l <= maxl; l++) {
+            M[l] = (cplx *)calloc((size_t)T->nb[l] * 2 * P2 + 1, sizeof(cplx));
+            Lc[l] = (cplx *)calloc((size_t)T->nb[l] * 2 * P2 + 1, sizeof(cplx));
+        }
+        for (int l = maxl; l >= 2; l--) {
+#pragma omp parallel
+            {
+                double *bx = NULL, *bw = NULL;
+                int64_t cap = 0;
+#pragma omp for schedule(dynamic, 4)
+                for (int64_t b = 0; b < T->nb[l]; b++) {
+                    if (!A.in[l][b]) continue;
+                    double cen[3];
+                    box_centre(T, l, T->key[l][b], cen);
+                    cplx *ph = &M[l][(size_t)b * 2 * P2], *ch = ph + P2;
+                    if (A.leaf[l][b]) {
+                        int64_t c = T->count[l][b];
+                        if (c > cap) {
+                            free(bx);
+                            free(bw);
+                            cap = c;
+                            bx = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                            bw = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        }
+                        box_points(T, x, w, l, b, bx, bw);
+                        lho_p2m_method2(p, cen, c, bx, bw, ph, ch);
+                    } else {
+                        for (int chn = 0; chn < 8; chn++) {
+                            int64_t cb = atree_find(&A, l + 1, (T->key[l][b] << 3) | (uint64_t)chn);
+                            if (cb < 0) continue;
+                            double cc[3];
+                            box_centre(T, l + 1, T->key[l + 1][cb], cc);
+                            double t[3] = {cen[0] - cc[0], cen[1] - cc[1], cen[2] - cc[2]};
+                            const cplx *iph = &M[l + 1][(size_t)cb * 2 * P2];
+                            lho_m2m(p, t, iph, iph + P2, ph, ch);
+                        }
+                    }
+                }
+                free(bx);
+                free(bw);
+            }
+        }
+        stats.t_up = wtime() - t1;
+        t1 = wtime();
+        /* downward: every tree box of levels >= 2 (only the chains of wanted leaves when sampling) */
+        char *need[MAXLEV + 1] = {0};
+        for (int l = 2; l <= maxl; l++) {
+            need[l] = (char *)calloc((size_t)T->nb[l] + 1, 1);
+            for (int64_t b = 0; b < T->nb[l]; b++) need[l][b] = (char)(A.in[l][b] && !sample);
+        }
+        if (sample)
+            for (int l = 2; l <= maxl; l++)
+                for (int64_t b = 0; b < T->nb[l]; b++)
+                    if (want[l][b])
+                        for (int la = 2; la <= l; la++)
+                            need[la][tree_find(T, la, T->key[l][b] >> (3 * (l - la)))] = 1;
+        int64_t nm2l = 0;
+        for (int l = 2; l <= maxl; l++) {
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : nm2l)
+            for (int64_t b = 0; b < T->nb[l]; b++) {
+                if (!need[l][b]) continue;
+                double ct[3];
+                box_centre(T, l, T->key[l][b], ct);
+                cplx *ph = &Lc[l][(size_t)b * 2 * P2], *ch = ph + P2;
+                if (l > 2) {
+                    int64_t pb = tree_find(T, l - 1, T->key[l][b] >> 3);
+                    double cp[3];
+                    box_centre(T, l - 1, T->key[l - 1][pb], cp);
+                    double t[3] = {ct[0] - cp[0], ct[1] - cp[1], ct[2] - cp[2]};
+                    const cplx *iph = &Lc[l - 1][(size_t)pb * 2 * P2];
+                    lho_l2l(p, t, iph, iph + P2, ph, ch);
+                }
+                int64_t vl[189];
+                int nv = list_V(&A, l, T->key[l][b], vl);
+                for (int i = 0; i < nv; i++) {
+                    double cs[3];
+                    box_centre(T, l, T->key[l][vl[i]], cs);
+                    double t[3] = {ct[0] - cs[0], ct[1] - cs[1], ct[2] - cs[2]};
+                    const cplx *iph = &M[l][(size_t)vl[i] * 2 * P2];
+                    lho_m2l(p, t, iph, iph + P2, ph, ch);
+                }
+                nm2l += nv;
+            }
+        }
+        stats.n_m2l = nm2l;
+        /* L2P at the wanted leaves of levels >= 2 */
+        for (int l = 2; l <= maxl; l++) {
+#pragma omp parallel
+            {
+                double *bx = NULL, *bw = NULL, *bv = NULL, *bs = NULL;
+                int64_t cap = 0;
+#pragma omp for schedule(dynamic, 4)
+                for (int64_t b = 0; b < T->nb[l]; b++) {
+                    if (!want[l][b]) continue;
+                    int64_t c = T->count[l][b];
+                    if (c > cap) {
+                        free(bx); free(bw); free(bv); free(bs);
+                        cap = c;
+                        bx = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bw = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bv = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bs = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                    }
+                    box_points(T, x, w, l, b, bx, bw);
+                    memset(bv, 0, sizeof(double) * 3 * (size_t)c);
+                    memset(bs, 0, sizeof(double) * 3 * (size_t)c);
+                    double cen[3];
+                    box_centre(T, l, T->key[l][b], cen);
+                    const cplx *ph = &Lc[l][(size_t)b * 2 * P2];
+                    lho_l2p(p, cen, ph, ph + P2, c, bx, bw, bv, bs, NULL, NULL, NULL);
+                    for (int64_t i = 0; i < c; i++) {
+                        int64_t e = T->order[T->first[l][b] + i];
+                        for (int d = 0; d < 3; d++) {
+                            v[3 * e + d] += bv[3 * i + d];
+                            s[3 * e + d] += bs[3 * i + d];
+                        }
+                    }
+                }
+                free(bx); free(bw); free(bv); free(bs);
+            }
+        }
+        for (int l = 2; l <= maxl; l++) {
+            free(M[l]);
+            free(Lc[l]);
+            free(need[l]);
+        }
+        stats.t_down = wtime() - t1;
+    }
+
+    if (what & 2) {
+        /* near field: U smoothed, W and X (of the leaf and its ancestors) singular */
+        double t2 = wtime();
+        int64_t nu = 0, nwx = 0;
+        for (int l = 0; l <= maxl; l++) {
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nu, nwx)
+            for (int64_t b = 0; b < T->nb[l]; b++) {
+                if (!want[l][b]) continue;
+                blist U = {0}, WX = {0};
+                list_U(&A, l, b, &U);
+                list_W(&A, l, b, &WX);
+                for (int la = l; la >= 0; la--) {
+                    int64_t ab = tree_find(T, la, T->key[l][b] >> (3 * (l - la)));
+                    list_X(&A, la, ab, &WX);
+                }
+                for (int64_t it = 0; it < T->count[l][b]; it++) {
+                    int64_t j = T->order[T->first[l][b] + it];
+                    double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+                    for (int64_t q = 0; q < U.n; q++) nu += box_direct(&A, x, w, a, smooth, U.lev[q], U.box[q], j, vv, ss);
+                    for (int64_t q = 0; q < WX.n; q++) nwx += box_direct(&A, x, w, a, 0, WX.lev[q], WX.box[q], j, vv, ss);
+                    for (int d = 0; d < 3; d++) {
+                        v[3 * j + d] += vv[d];
+                        s[3 * j + d] += ss[d];
+                    }
+                }
+                blist_free(&U);
+                blist_free(&WX);
+            }
+        }
+        stats.n_p2p_pairs = nu;
+        stats.n_wx_pairs = nwx;
+        stats.t_near = wtime() - t2;
+    }
+    if (st) *st = stats;
+    for (int l = 0; l <= maxl; l++) free(want[l]);
+    atree_free(&A);
+    return 0;
+}
+
+/* Direct sums with the adaptive split rule: the smoothed kernel between
+ * elements of adjacent leaves of the adaptive tree, the singular one otherwise. */
+void lho_direct_adaptive(int64_t n, const double *x, const double *w, double a, int64_t maxleaf, int maxl,
+                         const double lo[3], double L, int64_t ntarg, const int64_t *targ, double *v, double *s)
+{
+    atree A;
+    atree_build(&A, n, x, maxleaf, maxl, lo, L);
+    const otree *T = &A.T;
+    int *el = (int *)malloc(sizeof(int) * (size_t)n);
+    uint64_t *ek = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    for (int64_t e = 0; e < n; e++)
+        for (int l = 0; l <= maxl; l++) {
+            int sh = QBITS - l;
+            uint64_t k = morton(T->q[3 * e] >> sh, T->q[3 * e + 1] >> sh, T->q[3 * e + 2] >> sh);
+            int64_t b = atree_find(&A, l, k);
+            if (b >= 0 && A.leaf[l][b]) {
+                el[e] = l;
+                ek[e] = k;
+                break;
+            }
+        }
+    int smooth_ok = a > 0.0;
+    int64_t nt = targ ? ntarg : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t jj = 0; jj < nt; jj++) {
+        int64_t j = targ ? targ[jj] : jj;
+        double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+        for (int64_t i = 0; i < n; i++) {
+            if (i == j) continue;
+            int sm = smooth_ok && adjacent(el[i], ek[i], el[j], ek[j]);
+            pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, sm, vv, ss, NULL);
+        }
+        for (int k = 0; k < 3; k++) {
+            v[3 * jj + k] = vv[k];
+            s[3 * jj + k] = ss[k];
+        }
+    }
+    free(el);
+    free(ek);
+    atree_free(&A);
+}
+
+/* Test of the list definitions: for every ordered pair of leaves (target b,
+ * source c) count the mechanisms that carry c's elements to b's -- c in U(b);
+ * levels l >= 2 where c's ancestor is in V(b's ancestor); an ancestor-or-self of
+ * c in W(b); c in X(an ancestor-or-self of b).  Each pair must be carried once.
+ * Returns the minimum and maximum count and the number of leaves. */
+void lho_adaptive_coverage(int64_t n, const double *x, int64_t maxleaf, int maxl, const double lo[3], double L,
+                           int64_t *minc, int64_t *maxc, int64_t *nleaf)
+{
+    atree A;
+    atree_build(&A, n, x, maxleaf, maxl, lo, L);
+    const otree *T = &A.T;
+    int64_t nl = 0;
+    for (int l = 0; l <= maxl; l++)
+        for (int64_t b = 0; b < T->nb[l]; b++) nl += A.leaf[l][b];
+    int *ll = (int *)malloc(sizeof(int) * (size_t)nl);
+    int64_t *lb = (int64_t *)malloc(sizeof(int64_t) * (size_t)nl);
+    int64_t q = 0;
+    for (int l = 0; l <= maxl; l++)
+        for (int64_t b = 0; b < T->nb[l]; b++)
+            if (A.leaf[l][b]) {
+                ll[q] = l;
+                lb[q++] = b;
+            }
+    int64_t mn = INT64_MAX, mx = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(min : mn) reduction(max : mx)
+    for (int64_t i = 0; i < nl; i++) {
+        int l1 = ll[i];
+        uint64_t k1 = T->key[l1][lb[i]];
+        blist U = {0}, W = {0}, X = {0};
+        list_U(&A, l1, lb[i], &U);
+        list_W(&A, l1, lb[i], &W);
+        for (int la = l1; la >= 0; la--) {
+            blist Xa = {0};
+            list_X(&A, la, tree_find(T, la, k1 >> (3 * (l1 - la))), &Xa);
+            for (int64_t t = 0; t < Xa.n; t++) blist_push(&X, Xa.lev[t], Xa.box[t]);
+            blist_free(&Xa);
+        }
+        for (int64_t j = 0; j < nl; j++) {
+            int l2 = ll[j];
+            uint64_t k2 = T->key[l2][lb[j]];
+            int64_t cnt = 0;
+            for (int64_t t = 0; t < U.n; t++) cnt += (U.lev[t] == l2 && U.box[t] == lb[j]);
+            for (int l = 2; l <= (l1 < l2 ? l1 : l2); l++) {
+                uint64_t a1 = k1 >> (3 * (l1 - l)), a2 = k2 >> (3 * (l2 - l));
+                if (!adjacent(l, a1, l, a2) && adjacent(l - 1, a1 >> 3, l - 1, a2 >> 3)) cnt++;
+            }
+            for (int64_t t = 0; t < W.n; t++)
+                if (W.lev[t] <= l2 && (k2 >> (3 * (l2 - W.lev[t]))) == T->key[W.lev[t]][W.box[t]]) cnt++;
+            for (int64_t t = 0; t < X.n; t++) cnt += (X.lev[t] == l2 && X.box[t] == lb[j]);
+            if (cnt < mn) mn = cnt;
+            if (cnt > mx) mx = cnt;
+        }
+        blist_free(&U);
+        blist_free(&W);
+        blist_free(&X);
+    }
+    *minc = mn;
+    *maxc = mx;
+    *nleaf = nl;
+    free(ll);
+    free(lb);
+    atree_free(&A);
+}
+
+/* Adaptive tree summary: boxes and leaves per level (nb, nlf: [maxl + 1]) */
+void lho_adaptive_counts(int64_t n, const double *x, int64_t maxleaf, int maxl, const double lo[3], double L,
+                         int64_t *nb, int64_t *nlf)
+{
+    atree A;
+    atree_build(&A, n, x, maxleaf, maxl, lo, L);
+    for (int l = 0; l <= maxl; l++) {
+        nb[l] = nlf[l] = 0;
+        for (int64_t b = 0; b < A.T.nb[l]; b++) {
+            nb[l] += A.in[l][b];
+            nlf[l] += A.leaf[l][b];
+        }
+    }
+    atree_free(&A);
 }
