@@ -199,6 +199,70 @@ def run_batch(lhf, torch, steps, warmup, with_accuracy):
     return res
 
 
+def run_ring(lhf, torch, steps, warmup, with_accuracy):
+    """clustered workload: 4,194,304 elements on a vortex ring + 10% background, adaptive octree
+    (<= 64 per leaf, deepest level 8), p = 16; the FP32 path timed per step (plan + execute),
+    the FP64 path on the same input for the speedup"""
+    import numpy as np
+    import workloads
+    cfg = workloads.CONFIGS["ring4m_fp32"]
+    n, p, mx, depth = cfg["n"], cfg["p"], cfg["max_per_leaf"], 8
+    x, w = workloads.vortex_ring(n, cfg["seed"])
+    a = workloads.core_radius(n)
+    log(f"bench: ring N={n} p={p} adaptive <= {mx}/leaf")
+    res = {"workload": "ring4m_fp32", "n": n, "p": p, "max_per_leaf": mx, "max_level": depth,
+           "distribution": "vortex ring R0 = 0.3, Gaussian cross-section sigma = 0.05, + 10% uniform background"}
+    outs = {}
+    for prec, name, k_steps in ((lhf.FP32, "fp32", steps), (lhf.FP64, "fp64", max(1, min(steps, 2)))):
+        dt = torch.float32 if prec == lhf.FP32 else torch.float64
+        xt = torch.from_numpy(x).to(device="cuda", dtype=dt)
+        wt = torch.from_numpy(w).to(device="cuda", dtype=dt)
+        v, s = torch.empty_like(wt), torch.empty_like(wt)
+        for _ in range(warmup if prec == lhf.FP32 else 1):
+            pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=mx)
+            pl.execute(wt, v, s)
+            pl.close()
+        torch.cuda.synchronize()
+        phases = {k: 0.0 for k in lhf.PHASES}
+        t0 = time.perf_counter()
+        for _ in range(k_steps):
+            pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=mx)
+            pl.profile_begin(1)
+            pl.execute(wt, v, s)
+            ph, _ = pl.profile_end()
+            st = pl.stats()
+            pl.close()
+            for kk in phases:
+                phases[kk] += ph[kk] / k_steps
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / k_steps
+        exec_ms = sum(vv for kk, vv in phases.items() if kk != "m2l")
+        log(f"bench: ring {name} {ms:.1f} ms per step")
+        res[name] = {"ms_per_step": ms, "elements_per_s": n / (ms * 1e-3), "execute_ms": exec_ms,
+                     "execute_only_elements_per_s": n / (exec_ms * 1e-3), "phases_ms": phases, "steps": k_steps,
+                     "m2l_achieved_tflops": st["n_m2l"] * f_m2l(p) / (phases["m2l"] * 1e-3) / 1e12}
+        res["counts"] = {"boxes": st["boxes"], "leaves": st["n_leaves"], "m2l": st["n_m2l"],
+                         "u_pairs": st["n_p2p_pairs"], "wx_pairs": st["n_wx_pairs"]}
+        outs[name] = (v.double().cpu().numpy(), s.double().cpu().numpy())
+        del xt, wt, v, s
+    res["speedup_fp32_vs_fp64"] = res["fp64"]["ms_per_step"] / res["fp32"]["ms_per_step"]
+    if with_accuracy:
+        import oracle
+        tg = workloads.sample_targets(n, 200, seed=3000)
+        xr = x.astype(np.float32).astype(np.float64)
+        wr = w.astype(np.float32).astype(np.float64)
+        vd, sd = oracle.direct_adaptive(xr, wr, float(np.float32(a)), mx, depth, targets=tg)
+        vd64, sd64 = oracle.direct_adaptive(x, w, a, mx, depth, targets=tg)
+        acc = {}
+        for name, (vv, ss) in outs.items():
+            rv, rs = (vd, sd) if name == "fp32" else (vd64, sd64)
+            acc[name] = {"rel_l2_v": float(np.linalg.norm(vv[tg] - rv) / np.linalg.norm(rv)),
+                         "rel_l2_s": float(np.linalg.norm(ss[tg] - rs) / np.linalg.norm(rs))}
+        res["accuracy_vs_direct_sum"] = dict(acc, targets=int(len(tg)),
+                                             reference="adaptive split-kernel direct sum, FP64 oracle")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +272,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 run on the same input")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batched run")
+    ap.add_argument("--no-ring", action="store_true", help="skip the clustered (vortex ring, adaptive) run")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only copy a buffer of this many MiB on the device (HBM counter calibration)")
     args = ap.parse_args()
@@ -335,6 +400,8 @@ def main():
         }
     if args.workload == "cube1m_fp64" and not args.no_batch:
         out["batch"] = run_batch(lhf, torch, args.steps, args.warmup, not args.no_cpu_baseline)
+    if args.workload == "cube1m_fp64" and not args.no_ring:
+        out["ring"] = run_ring(lhf, torch, args.steps, args.warmup, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("bench: CPU oracle baseline (sampled) ...")
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -22,6 +22,13 @@
  *    q = min(floor((x-lo) * 2^21/L), 2^21-1) computed in FP64 (FP32 inputs
  *    are promoted first); a level-l box is q >> (21-l).  Uniform depth d:
  *    leaves are the non-empty level-d boxes; M2L runs on levels 2..d.
+ *    Adaptive (max_per_leaf > 0): a box belongs to the tree iff it is the root
+ *    or its parent holds more than max_per_leaf elements, and is a leaf iff it
+ *    holds at most max_per_leaf elements or is on level d.  Lists after
+ *    Carrier, Greengard & Rokhlin: M2L over V-lists as in the uniform tree;
+ *    the near field of a leaf covers its adjacent leaves of any size (U,
+ *    smoothed kernel) and its W and X interactions, which are summed directly
+ *    with the singular kernel (the far-field kernel; eq. 2).
  *  - Streams: all device work is enqueued on the caller's HIP stream.
  *    lhf_plan_create synchronises that stream once (to read the tree sizes);
  *    lhf_execute never synchronises and allocates nothing.
@@ -65,8 +72,9 @@ typedef enum { LHF_FP64 = 0, LHF_FP32 = 1 } lhf_precision;
 typedef struct {
     int32_t p;            /* truncation number, orders n = 0..p-1 (Sec. 5.1) */
     double tol;           /* target accuracy; only used for the CORE_SPLIT warning */
-    int32_t depth;        /* uniform octree depth d, 2 <= d <= 10 */
-    int32_t reserved0;
+    int32_t depth;        /* uniform octree depth d, or the deepest level of an adaptive tree; 2..10 */
+    int32_t max_per_leaf; /* 0: uniform tree of depth d.  > 0: adaptive tree -- a box is split
+                             while it holds more than max_per_leaf elements, down to level d */
     double domain_lo[3];  /* cube origin */
     double domain_len;    /* cube side; <= 0: bounding cube of the data, side*(1+2^-20) */
     int32_t precision;    /* lhf_precision */
@@ -81,7 +89,10 @@ typedef struct {
     int64_t n_m2m, n_l2l;      /* child-parent translations */
     int64_t n_p2p_pairs;       /* near-field pairs (ordered, self excluded) */
     int32_t n_theta_classes;   /* distinct polar angles of the translation directions */
-    int32_t reserved1;
+    int32_t max_level;         /* deepest level holding a box */
+    int64_t n_leaves;          /* leaf boxes */
+    int64_t n_wx_pairs;        /* adaptive tree: element pairs of W/X interactions, summed directly
+                                  with the singular kernel (ordered) */
 } lhf_stats;
 
 /* Fill *d with the defaults: p = 12, tol = 1e-6, depth = 4, cube [0,1]^3, FP64. */

@@ -31,7 +31,7 @@ PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 
 
 class Desc(C.Structure):
-    _fields_ = [("p", C.c_int32), ("tol", C.c_double), ("depth", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("p", C.c_int32), ("tol", C.c_double), ("depth", C.c_int32), ("max_per_leaf", C.c_int32),
                 ("domain_lo", C.c_double * 3), ("domain_len", C.c_double), ("precision", C.c_int32),
                 ("flags", C.c_uint32)]
 
@@ -39,7 +39,8 @@ class Desc(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("depth", C.c_int32), ("p", C.c_int32), ("boxes", C.c_int64 * 11),
                 ("n_m2l", C.c_int64), ("n_m2m", C.c_int64), ("n_l2l", C.c_int64), ("n_p2p_pairs", C.c_int64),
-                ("n_theta_classes", C.c_int32), ("reserved1", C.c_int32)]
+                ("n_theta_classes", C.c_int32), ("max_level", C.c_int32), ("n_leaves", C.c_int64),
+                ("n_wx_pairs", C.c_int64)]
 
 
 class Tune(C.Structure):
@@ -111,10 +112,11 @@ def _check(status):
     return status
 
 
-def make_desc(p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0):
+def make_desc(p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0, max_per_leaf=0):
     d = Desc()
     load().lhf_desc_default(C.byref(d))
     d.p, d.depth, d.precision, d.tol, d.flags = int(p), int(depth), int(precision), float(tol), int(flags)
+    d.max_per_leaf = int(max_per_leaf)
     for k in range(3):
         d.domain_lo[k] = float(lo[k])
     d.domain_len = float(L)
@@ -154,16 +156,17 @@ class Plan:
     """An octree plan over fixed element positions (the paper's 'FMM set' stage).
 
     With ``offsets`` (host, n_systems + 1 entries), x holds several independent
-    systems; ``lo``, ``L`` and ``a`` are then per system (or broadcast)."""
+    systems; ``lo``, ``L`` and ``a`` are then per system (or broadcast).  With
+    ``max_per_leaf`` > 0 the octree is adaptive and ``depth`` its deepest level."""
 
     def __init__(self, x, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0,
-                 offsets=None):
+                 offsets=None, max_per_leaf=0):
         import torch
         self.dtype = torch.float64 if precision == FP64 else torch.float32
         x = _dev_array(x, self.dtype, "x")
         self.n = x.shape[0]
         self.desc = make_desc(p, depth, precision, lo if offsets is None else (0.0, 0.0, 0.0),
-                              L if offsets is None else 1.0, tol, flags)
+                              L if offsets is None else 1.0, tol, flags, max_per_leaf)
         self._h = C.c_void_p()
         if offsets is None:
             self.status = _check(load().lhf_plan_create(C.byref(self._h), C.byref(self.desc), self.n,
@@ -195,7 +198,8 @@ class Plan:
         _check(load().lhf_plan_stats(self._h, C.byref(st)))
         return dict(n=st.n, depth=st.depth, p=st.p, boxes=list(st.boxes[:st.depth + 1]), n_m2l=st.n_m2l,
                     n_m2m=st.n_m2m, n_l2l=st.n_l2l, n_p2p_pairs=st.n_p2p_pairs,
-                    n_theta_classes=st.n_theta_classes)
+                    n_theta_classes=st.n_theta_classes, max_level=st.max_level, n_leaves=st.n_leaves,
+                    n_wx_pairs=st.n_wx_pairs)
 
     def profile_begin(self, max_exec):
         _check(load().lhf_profile_begin(self._h, int(max_exec)))

@@ -67,7 +67,8 @@ __device__ inline void box_centre(uint64_t key, int level, const double *__restr
 // then every lane adds the eq. eve4 contributions of its packed rows.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off, const uint64_t *__restrict__ bkey,
+__global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off, const int32_t *__restrict__ leaves,
+                                              const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
                                               const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
                                               const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
                                               const double *__restrict__ sys_geo, T *__restrict__ M)
@@ -76,9 +77,12 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
     T *Rre = (T *)smem;          // [p][p]  (n, m)
     T *Rim = Rre + p * p;
     const int lane = threadIdx.x;
-    const int64_t b = leaf_off + blockIdx.x;
+    // uniform tree: leaves leaf_off + blockIdx.x at level depth; adaptive: leaves[blockIdx.x] at blev[]
+    const int64_t b = leaves ? (int64_t)leaves[blockIdx.x] : leaf_off + blockIdx.x;
+    const int level = blev ? (int)blev[b] : depth;
+    if (level < 2) return;  // no far field above level 2
     double c0, c1, c2, hd;
-    box_centre(bkey[b], depth, sys_geo, c0, c1, c2, hd);
+    box_centre(bkey[b], level, sys_geo, c0, c1, c2, hd);
     const T h = (T)hd, ih = (T)(1.0 / hd);
     const int P2 = p * p;
     T acc[NRMAX];
@@ -371,6 +375,7 @@ __global__ void __launch_bounds__(WAVE) k_m2m(int p, int64_t off, const int32_t 
     T *X = (T *)smem, *Y = X + 2 * P2, *Z = Y + 2 * P2, *cf = Z + 2 * ZS;
     const int lane = threadIdx.x;
     const int64_t b = off + blockIdx.x;
+    if (bnchild[b] == 0) return;  // a leaf keeps the multipole of its own elements
     if (lane < p) {
         // (-tau_p)^k / k!, tau_p = sqrt(3)/4
         double t = 1.0, tp = -0.4330127018922193;
@@ -465,7 +470,8 @@ __global__ void __launch_bounds__(WAVE) k_down(int p, int level, int do_m2l, int
 //   F(xhat) = sum_n (-1)^n [F_n^0 Rt_n^0 + 2 Re sum_{m>0} F_n^m Rt_n^m].
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off, const uint64_t *__restrict__ bkey,
+__global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off, const int32_t *__restrict__ leaves,
+                                              const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
                                               const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
                                               const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
                                               const double *__restrict__ sys_geo, const T *__restrict__ Lc,
@@ -477,7 +483,14 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off
     T *cd = (T *)smem;                // 2 P2 local coefficients
     T *Vre = cd + 2 * P2, *Vim = Vre + 3 * TRI;  // [3][TRI]
     const int lane = threadIdx.x;
-    const int64_t b = leaf_off + blockIdx.x;
+    const int64_t b = leaves ? (int64_t)leaves[blockIdx.x] : leaf_off + blockIdx.x;
+    const int level = blev ? (int)blev[b] : depth;
+    if (level < 2) {
+        // a leaf above level 2 has no local expansion: its far field is zero
+        for (int e = lane; e < bcount[b]; e += WAVE)
+            for (int k = 0; k < 6; k++) vfar[(size_t)k * n + bstart[b] + e] = (T)0;
+        return;
+    }
     const T *src = Lc + (size_t)b * 2 * P2;
     for (int r = lane; r < 2 * P2; r += WAVE) cd[r] = src[r];
     __syncthreads();
@@ -528,7 +541,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off
     }
     __syncthreads();
     double c0, c1, c2, hd;
-    box_centre(bkey[b], depth, sys_geo, c0, c1, c2, hd);
+    box_centre(bkey[b], level, sys_geo, c0, c1, c2, hd);
     const T ih = (T)(1.0 / hd);
     const int s0 = bstart[b], cnt = bcount[b];
     auto vget = [&](int k, int nn, int m, T &re, T &im) {
@@ -670,6 +683,97 @@ __device__ inline void kernel_fg(T r2, T a, int smooth, T &f, T &g)
     }
 }
 
+// Compensated running sum (Knuth's TwoSum, branch-free): the rounding error of each
+// addition is carried in c.  The near field adds one source box's partial sum at a
+// time, so the accumulation error no longer grows with the number of source boxes.
+template <typename T>
+struct CompSum {
+    T s = 0, c = 0;
+    __device__ __forceinline__ void add(T x)
+    {
+        const T t = s + x;
+        const T bp = t - s;
+        c += (s - (t - bp)) + (x - bp);
+        s = t;
+    }
+    __device__ __forceinline__ T value() const { return s + c; }
+};
+
+// contribution of sorted source k to the target (xj, wj); r = x_j - x_k
+template <typename T>
+__device__ __forceinline__ void p2p_pair(int k, int64_t n, const T *__restrict__ xs, const T *__restrict__ ws, T xj,
+                                         T yj, T zj, T wjx, T wjy, T wjz, T a, int smooth, T &v0, T &v1, T &v2,
+                                         T &s0, T &s1, T &s2)
+{
+    const T rx = xj - xs[k], ry = yj - xs[n + k], rz = zj - xs[2 * n + k];
+    const T r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 == (T)0 && !smooth) return;  // coincident distinct points, singular kernel: no contribution
+    T f, g;
+    kernel_fg<T>(r2, a, smooth, f, g);
+    const T wix = ws[k], wiy = ws[n + k], wiz = ws[2 * n + k];
+    const T cx = wiy * rz - wiz * ry, cy = wiz * rx - wix * rz, cz = wix * ry - wiy * rx;
+    const T dd = g * (wjx * rx + wjy * ry + wjz * rz);
+    v0 += f * cx;
+    v1 += f * cy;
+    v2 += f * cz;
+    s0 += f * (wiy * wjz - wiz * wjy) + dd * cx;
+    s1 += f * (wiz * wjx - wix * wjz) + dd * cy;
+    s2 += f * (wix * wjy - wiy * wjx) + dd * cz;
+}
+
+// adaptive tree: near field of one sorted element over its leaf's source list (entries
+// (box << 1) | singular: U-list leaves with the smoothed kernel, W/X boxes with the singular
+// one), then combination with the far field and un-permutation as in k_p2p
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2p_list(int64_t n, const int32_t *__restrict__ eleaf,
+                                                  const int32_t *__restrict__ leaves, const int8_t *__restrict__ blev,
+                                                  const int32_t *__restrict__ nl_start, const int32_t *__restrict__ nl_ent,
+                                                  const uint64_t *__restrict__ bkey, const int32_t *__restrict__ bstart,
+                                                  const int32_t *__restrict__ bcount, const T *__restrict__ xs,
+                                                  const T *__restrict__ ws, const double *__restrict__ sys_a, int what,
+                                                  const T *__restrict__ vfar, const int32_t *__restrict__ perm,
+                                                  T *__restrict__ vout, T *__restrict__ sout)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int lp = eleaf[i];
+    const int lb = leaves[lp];
+    const T a = (T)sys_a[bkey[lb] >> (3 * blev[lb])];
+    const int smooth = a > (T)0;
+    CompSum<T> acc[6];
+    const T xj = xs[i], yj = xs[n + i], zj = xs[2 * n + i];
+    const T wjx = ws[i], wjy = ws[n + i], wjz = ws[2 * n + i];
+    if (what & 1)
+        for (int k = 0; k < 6; k++) acc[k].add(vfar[(size_t)k * n + i]);
+    if (what & 2) {
+        const int e1 = nl_start[lp + 1];
+        for (int q = nl_start[lp]; q < e1; q++) {
+            const int code = nl_ent[q];
+            const int src = code >> 1, sm = smooth && !(code & 1);
+            const int st = bstart[src], ct = bcount[src];
+            T v0 = 0, v1 = 0, v2 = 0, s0 = 0, s1 = 0, s2 = 0;
+            for (int e = 0; e < ct; e++) {
+                const int k = st + e;
+                if (k == i) continue;
+                p2p_pair<T>(k, n, xs, ws, xj, yj, zj, wjx, wjy, wjz, a, sm, v0, v1, v2, s0, s1, s2);
+            }
+            acc[0].add(v0);
+            acc[1].add(v1);
+            acc[2].add(v2);
+            acc[3].add(s0);
+            acc[4].add(s1);
+            acc[5].add(s2);
+        }
+    }
+    const int64_t o = perm[i];
+    vout[3 * o] = acc[0].value();
+    vout[3 * o + 1] = acc[1].value();
+    vout[3 * o + 2] = acc[2].value();
+    sout[3 * o] = acc[3].value();
+    sout[3 * o + 1] = acc[4].value();
+    sout[3 * o + 2] = acc[5].value();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_off, const int32_t *__restrict__ eleaf,
                                              const int32_t *__restrict__ ulist, const uint64_t *__restrict__ bkey,
@@ -684,9 +788,11 @@ __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_
     // core radius of the element's system (0: singular kernel)
     const T a = (T)sys_a[bkey[eleaf[i]] >> (3 * depth)];
     const int smooth = a > (T)0;
-    T v0 = 0, v1 = 0, v2 = 0, s0 = 0, s1 = 0, s2 = 0;
+    CompSum<T> acc[6];
     const T xj = xs[i], yj = xs[n + i], zj = xs[2 * n + i];
     const T wjx = ws[i], wjy = ws[n + i], wjz = ws[2 * n + i];
+    if (what & 1)
+        for (int k = 0; k < 6; k++) acc[k].add(vfar[(size_t)k * n + i]);
     if (what & 2) {
         const int lf = eleaf[i];
         const int32_t *U = ulist + (size_t)(lf - leaf_off) * 27;
@@ -694,41 +800,27 @@ __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_
             const int nb = U[q];
             if (nb < 0) continue;
             const int st = bstart[nb], ct = bcount[nb];
+            T v0 = 0, v1 = 0, v2 = 0, s0 = 0, s1 = 0, s2 = 0;
             for (int e = 0; e < ct; e++) {
                 const int k = st + e;
                 if (k == i) continue;
-                const T rx = xj - xs[k], ry = yj - xs[n + k], rz = zj - xs[2 * n + k];
-                const T r2 = rx * rx + ry * ry + rz * rz;
-                if (r2 == (T)0 && !smooth) continue;
-                T f, g;
-                kernel_fg<T>(r2, a, smooth, f, g);
-                const T wix = ws[k], wiy = ws[n + k], wiz = ws[2 * n + k];
-                const T cx = wiy * rz - wiz * ry, cy = wiz * rx - wix * rz, cz = wix * ry - wiy * rx;
-                const T dd = g * (wjx * rx + wjy * ry + wjz * rz);
-                v0 += f * cx;
-                v1 += f * cy;
-                v2 += f * cz;
-                s0 += f * (wiy * wjz - wiz * wjy) + dd * cx;
-                s1 += f * (wiz * wjx - wix * wjz) + dd * cy;
-                s2 += f * (wix * wjy - wiy * wjx) + dd * cz;
+                p2p_pair<T>(k, n, xs, ws, xj, yj, zj, wjx, wjy, wjz, a, smooth, v0, v1, v2, s0, s1, s2);
             }
+            acc[0].add(v0);
+            acc[1].add(v1);
+            acc[2].add(v2);
+            acc[3].add(s0);
+            acc[4].add(s1);
+            acc[5].add(s2);
         }
     }
-    if (what & 1) {
-        v0 += vfar[i];
-        v1 += vfar[n + i];
-        v2 += vfar[2 * n + i];
-        s0 += vfar[3 * n + i];
-        s1 += vfar[4 * n + i];
-        s2 += vfar[5 * n + i];
-    }
     const int64_t o = perm[i];
-    vout[3 * o] = v0;
-    vout[3 * o + 1] = v1;
-    vout[3 * o + 2] = v2;
-    sout[3 * o] = s0;
-    sout[3 * o + 1] = s1;
-    sout[3 * o + 2] = s2;
+    vout[3 * o] = acc[0].value();
+    vout[3 * o + 1] = acc[1].value();
+    vout[3 * o + 2] = acc[2].value();
+    sout[3 * o] = acc[3].value();
+    sout[3 * o + 1] = acc[4].value();
+    sout[3 * o + 2] = acc[5].value();
 }
 
 // gather omega into the sorted SoA layout
@@ -762,11 +854,12 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
     mark(0);
     hipLaunchKernelGGL(k_gather_w<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)omega, P->perm, ws);
     mark(1);
-    const int64_t loff = P->lev[d].off, nleaf = P->lev[d].nb;
+    // uniform tree: the leaves are the boxes of level d; adaptive: the explicit leaf list
+    const int64_t loff = P->lev[d].off, nleaf = P->adaptive ? P->nleaf : P->lev[d].nb;
     if (what & 1) {
         size_t sh_p2m = sizeof(T) * 2 * P2;
-        hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_p2m, st, p, d, loff, P->bkey, P->bstart,
-                           P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, M);
+        hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_p2m, st, p, d, loff, P->leaves, P->blev,
+                           P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, M);
         mark(2);
         size_t sh_rcr = sizeof(T) * (4 * P2 + 2 * ZS + 2 * p + 2);
         for (int l = d - 1; l >= 2; l--) {
@@ -799,8 +892,9 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         mark(4);
         const int TRI = p * (p + 1) / 2;
         size_t sh_l2p = sizeof(T) * (2 * P2 + 6 * TRI);
-        hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_l2p, st, p, d, loff, P->bkey, P->bstart,
-                           P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar);
+        hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_l2p, st, p, d, loff, P->leaves, P->blev,
+                           P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, (const T *)Lc,
+                           vfar);
     } else {
         mark(2);
         mark(3);
@@ -811,9 +905,14 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         mark(4);
     }
     mark(5);
-    hipLaunchKernelGGL(k_p2p<T>, dim3(nblk), dim3(tpb), 0, st, n, d, loff, P->eleaf, P->ulist, P->bkey, P->bstart,
-                       P->bcount, (const T *)xs, (const T *)ws, P->sys_a, what, (const T *)vfar, P->perm, (T *)v,
-                       (T *)s);
+    if (P->adaptive)
+        hipLaunchKernelGGL(k_p2p_list<T>, dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, P->leaves, P->blev, P->nl_start,
+                           P->nl_ent, P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, P->sys_a, what,
+                           (const T *)vfar, P->perm, (T *)v, (T *)s);
+    else
+        hipLaunchKernelGGL(k_p2p<T>, dim3(nblk), dim3(tpb), 0, st, n, d, loff, P->eleaf, P->ulist, P->bkey,
+                           P->bstart, P->bcount, (const T *)xs, (const T *)ws, P->sys_a, what, (const T *)vfar,
+                           P->perm, (T *)v, (T *)s);
     mark(6);
     LHF_HIP(hipGetLastError());
     return LHF_OK;

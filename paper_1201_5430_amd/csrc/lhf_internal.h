@@ -95,8 +95,21 @@ struct lhf_plan {
     int32_t *vcount = nullptr;   // [nbox] V-list length
     int32_t *vsrc = nullptr;     // [nbox][189] V-list source boxes (global index)
     int16_t *vdir = nullptr;     // [nbox][189] direction code of t = c_target - c_source
-    int32_t *ulist = nullptr;    // [nleaf][27] adjacent leaves (global index, -1 = none)
-    int32_t *eleaf = nullptr;    // [n] leaf (global index) of each sorted element
+    int32_t *ulist = nullptr;    // [nleaf][27] adjacent leaves (global index, -1 = none); uniform tree
+    int32_t *eleaf = nullptr;    // [n] leaf of each sorted element: global box index (uniform tree)
+                                 //     or position in 'leaves' (adaptive tree)
+
+    // adaptive tree (boxes split while they hold more than max_per_leaf elements, down to
+    // level 'depth'): leaves on several levels, per-leaf near-field source lists
+    bool adaptive = false;
+    int max_per_leaf = 0;
+    int max_level = 0;           // deepest level holding a box
+    int64_t nleaf = 0;
+    int64_t n_wx = 0;            // element pairs summed directly for W/X interactions
+    int8_t *blev = nullptr;      // [nbox] level of every box
+    int32_t *leaves = nullptr;   // [nleaf] leaf boxes in element (Morton) order
+    int32_t *nl_start = nullptr; // [nleaf + 1] source-list offsets per leaf
+    int32_t *nl_ent = nullptr;   // source entries (box << 1) | singular
     void *M = nullptr;           // multipoles [nbox][2][p^2], T
     void *Lc = nullptr;          // locals     [nbox][2][p^2], T
     void *rot = nullptr;         // rotation sets [n_theta][4][rot_set_size(p)], T

@@ -618,6 +618,7 @@ bool wpad_build(lhf_plan *Pl, hipStream_t st)
 void dmap_build(const lhf_plan *Pl, int level, hipStream_t st)
 {
     const int64_t nb = Pl->lev[level].nb;
+    if (nb == 0) return;  // an adaptive tree may leave deep levels empty
     hipLaunchKernelGGL(k_dmap, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, level, Pl->lev[level].off, nb,
                        Pl->bkey, Pl->dmap[level]);
 }

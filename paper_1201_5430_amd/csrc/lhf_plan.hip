@@ -283,6 +283,226 @@ __global__ void k_add_i32(int64_t n, int32_t *__restrict__ a, int32_t add)
 }
 
 // ---------------------------------------------------------------------------
+// adaptive tree.  A box belongs to the tree iff it is a root or its parent holds
+// more than maxleaf elements; it is a leaf iff it belongs and holds at most maxleaf
+// elements or sits on the deepest level D.  Built from the full set of non-empty
+// boxes of every level (the uniform levels of the sorted keys).
+// ---------------------------------------------------------------------------
+
+// keep flag of each non-empty box of level l (cap entries, nb[l] of them valid);
+// leaves are counted per level
+__global__ void k_akeep(int64_t cap, int l, int D, int64_t maxleaf, int64_t n, const int64_t *__restrict__ dnb,
+                        const uint64_t *__restrict__ key, const int32_t *__restrict__ start,
+                        const uint64_t *__restrict__ pkey, const int32_t *__restrict__ pstart,
+                        int32_t *__restrict__ flag, int64_t *__restrict__ nleaf)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= cap) return;
+    const int64_t nb = dnb[l];
+    if (b >= nb) {
+        flag[b] = 0;
+        return;
+    }
+    const int64_t cnt = (b + 1 < nb ? (int64_t)start[b + 1] : n) - start[b];
+    int keep = 1;
+    if (l > 0) {
+        const int64_t pnb = dnb[l - 1];
+        const int64_t pb = find_u64(pkey, pnb, key[b] >> 3);
+        const int64_t pcnt = (pb + 1 < pnb ? (int64_t)pstart[pb + 1] : n) - pstart[pb];
+        keep = pcnt > maxleaf;
+    }
+    flag[b] = keep;
+    if (keep && (cnt <= maxleaf || l == D)) atomicAdd((unsigned long long *)(nleaf + l), 1ull);
+}
+
+__global__ void k_last_i32(int64_t len, const int32_t *__restrict__ a, int64_t *__restrict__ out)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *out = len > 0 ? (int64_t)a[len - 1] : 0;
+}
+
+// kept boxes of level l into the global box arrays (kid: inclusive scan of the keep flags)
+__global__ void k_acompact(int64_t cap, int l, int64_t n, const int64_t *__restrict__ dnb,
+                           const int32_t *__restrict__ kid, const uint64_t *__restrict__ key,
+                           const int32_t *__restrict__ start, uint64_t *__restrict__ okey,
+                           int32_t *__restrict__ ostart, int32_t *__restrict__ ocount)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= cap) return;
+    const int64_t nb = dnb[l];
+    if (b >= nb) return;
+    const int prev = b > 0 ? kid[b - 1] : 0;
+    if (kid[b] == prev) return;
+    okey[prev] = key[b];
+    ostart[prev] = start[b];
+    ocount[prev] = (int32_t)((b + 1 < nb ? (int64_t)start[b + 1] : n) - start[b]);
+}
+
+// level of every box, and head[first element of each leaf] = leaf box
+__global__ void k_blev(int64_t nbox, int D, LevelTab lt, int64_t maxleaf, const int32_t *__restrict__ bstart,
+                       const int32_t *__restrict__ bcount, int8_t *__restrict__ blev, int32_t *__restrict__ head)
+{
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbox) return;
+    int l = 0;
+    while (l < D && b >= lt.off[l + 1]) l++;
+    blev[b] = (int8_t)l;
+    if (bcount[b] <= maxleaf || l == D) head[bstart[b]] = (int32_t)b;
+}
+
+// leaf list in element order (pos: inclusive scan of the head flags)
+__global__ void k_leaf_list(int64_t n, const int32_t *__restrict__ head, const int32_t *__restrict__ pos,
+                            int32_t *__restrict__ leaves)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && head[i] >= 0) leaves[pos[i] - 1] = head[i];
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t *__restrict__ a, int32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ void k_is_head(int64_t n, const int32_t *__restrict__ head, int32_t *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = head[i] >= 0 ? 1 : 0;
+}
+
+// eleaf[i] = position of the leaf holding sorted element i (one block per leaf)
+__global__ void k_leaf_fill(int64_t nleaf, const int32_t *__restrict__ leaves, const int32_t *__restrict__ bstart,
+                            const int32_t *__restrict__ bcount, int32_t *__restrict__ eleaf)
+{
+    const int64_t t = blockIdx.x;
+    if (t >= nleaf) return;
+    const int b = leaves[t];
+    const int s0 = bstart[b], c = bcount[b];
+    for (int e = threadIdx.x; e < c; e += blockDim.x) eleaf[s0 + e] = (int32_t)t;
+}
+
+__device__ inline void box_ijk(uint64_t key, int l, uint32_t c[3])
+{
+    const uint64_t k = key & ((1ull << (3 * l)) - 1);
+    c[0] = compact3(k);
+    c[1] = compact3(k >> 1);
+    c[2] = compact3(k >> 2);
+}
+
+// closed boxes (l1, c1), (l2, c2) touch or overlap; coordinates on the grid of level D
+__device__ inline bool boxes_touch(int l1, const uint32_t c1[3], int l2, const uint32_t c2[3], int D)
+{
+    for (int d = 0; d < 3; d++) {
+        const uint32_t lo1 = c1[d] << (D - l1), hi1 = (c1[d] + 1) << (D - l1);
+        const uint32_t lo2 = c2[d] << (D - l2), hi2 = (c2[d] + 1) << (D - l2);
+        if (lo1 > hi2 || lo2 > hi1) return false;
+    }
+    return true;
+}
+
+// Near-field source list of every leaf b (level lb), after Carrier, Greengard & Rokhlin:
+//   U: b, same-level leaves adjacent to b, finer leaves adjacent to b below its colleagues,
+//      coarser adjacent leaves (colleagues of b's ancestors) -- smoothed kernel;
+//   W: boxes below a colleague of b whose parent touches b but which do not -- singular;
+//   X: coarser leaves that are colleagues of an ancestor of b but do not touch b -- singular
+//      (these are exactly the leaves C with b or one of its ancestors in W(C)).
+// The finer boxes are found by a depth-first walk from each non-leaf colleague that
+// descends only into boxes touching b.  PASS 0 counts entries and element pairs;
+// PASS 1 writes the entries at the scanned offsets.
+template <int PASS>
+__global__ void k_adlist(int64_t nleaf, int D, LevelTab lt, const int32_t *__restrict__ leaves,
+                         const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
+                         const int32_t *__restrict__ bcount, const int32_t *__restrict__ bchild0,
+                         const int32_t *__restrict__ bnchild, int32_t *__restrict__ cnt_or_start,
+                         int32_t *__restrict__ ent, int64_t *__restrict__ pairs, int32_t *__restrict__ flags)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nleaf) return;
+    const int b = leaves[t];
+    const int lb = blev[b];
+    const uint64_t kb = bkey[b];
+    const uint64_t sys = kb >> (3 * lb);
+    uint32_t cb[3];
+    box_ijk(kb, lb, cb);
+    const int64_t nb_el = bcount[b];
+    int64_t pu = 0, pw = 0;
+    int nent = 0;
+    const int base = PASS ? cnt_or_start[t] : 0;
+    auto emit = [&](int q, int sing) {
+        const int64_t c = bcount[q];
+        if (sing) pw += nb_el * c;
+        else pu += nb_el * c;
+        if (PASS) ent[base + nent] = (q << 1) | sing;
+        nent++;
+    };
+    auto find_box = [&](int l, const int32_t c[3]) -> int {
+        const int side = 1 << l;
+        if (c[0] < 0 || c[1] < 0 || c[2] < 0 || c[0] >= side || c[1] >= side || c[2] >= side) return -1;
+        const uint64_t k = (sys << (3 * l)) | spread3((uint32_t)c[0]) | (spread3((uint32_t)c[1]) << 1) |
+                           (spread3((uint32_t)c[2]) << 2);
+        const int64_t j = find_u64(bkey + lt.off[l], lt.nb[l], k);
+        return j < 0 ? -1 : (int)(lt.off[l] + j);
+    };
+    // same level: b itself, leaf colleagues, and the walk below non-leaf colleagues
+    constexpr int STK = 64;
+    int stq[STK];
+    int8_t stl[STK];
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                const int32_t c[3] = {(int32_t)cb[0] + dx, (int32_t)cb[1] + dy, (int32_t)cb[2] + dz};
+                const int q = find_box(lb, c);
+                if (q < 0) continue;
+                if (q == b || bnchild[q] == 0) {
+                    emit(q, 0);
+                    continue;
+                }
+                int sp = 0;
+                stq[sp] = q;
+                stl[sp++] = (int8_t)lb;
+                while (sp > 0) {
+                    sp--;
+                    const int node = stq[sp], ln = stl[sp];
+                    const int c0 = bchild0[node], nc = bnchild[node];
+                    for (int k = 0; k < nc; k++) {
+                        const int ch = c0 + k;
+                        uint32_t cc[3];
+                        box_ijk(bkey[ch], ln + 1, cc);
+                        if (!boxes_touch(ln + 1, cc, lb, cb, D)) {
+                            emit(ch, 1);  // W
+                        } else if (bnchild[ch] == 0) {
+                            emit(ch, 0);
+                        } else if (sp < STK) {
+                            stq[sp] = ch;
+                            stl[sp++] = (int8_t)(ln + 1);
+                        } else {
+                            atomicOr(&flags[2], 1);  // walk deeper than the stack: reported as an error
+                        }
+                    }
+                }
+            }
+    // coarser leaves: colleagues of the ancestors
+    for (int l = lb - 1; l >= 1; l--) {
+        const int sh = lb - l;
+        const int32_t ca[3] = {(int32_t)(cb[0] >> sh), (int32_t)(cb[1] >> sh), (int32_t)(cb[2] >> sh)};
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    if (!dx && !dy && !dz) continue;
+                    const int32_t c[3] = {ca[0] + dx, ca[1] + dy, ca[2] + dz};
+                    const int q = find_box(l, c);
+                    if (q < 0 || bnchild[q] != 0) continue;
+                    const uint32_t cq[3] = {(uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2]};
+                    emit(q, boxes_touch(l, cq, lb, cb, D) ? 0 : 1);  // U or X
+                }
+    }
+    if (!PASS) {
+        cnt_or_start[t] = nent;
+        atomicAdd((unsigned long long *)&pairs[1], (unsigned long long)(pu - nb_el));
+        atomicAdd((unsigned long long *)&pairs[2], (unsigned long long)pw);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // operator tables (FP64 arithmetic on the device)
 // ---------------------------------------------------------------------------
 
@@ -636,7 +856,8 @@ static void free_plan(lhf_plan *P)
     free_profile(P);
     void *bufs[] = {P->perm, P->xs, P->ws, P->vfar, P->bkey, P->bstart, P->bcount, P->bparent, P->bchild0,
                     P->bnchild, P->vcount, P->vsrc, P->vdir, P->ulist, P->eleaf, P->M, P->Lc, P->rot,
-                    P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp, P->sys_geo, P->sys_a, P->sys_off};
+                    P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp, P->sys_geo, P->sys_a, P->sys_off,
+                    P->blev, P->leaves, P->nl_start, P->nl_ent};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int l = 0; l <= MAXDEPTH; l++)
@@ -659,17 +880,30 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
 {
     const int64_t n = P->n;
     const int d = P->depth;
+    const int ns = P->nsys;
+    const bool adaptive = P->adaptive;
     const int tpb = 256;
     const unsigned nblk = (unsigned)((n + tpb - 1) / tpb);
-    // ---- keys and sort
+    auto grid = [&](int64_t m) { return dim3((unsigned)((m + tpb - 1) / tpb)); };
+    // per-level temporaries are sized by the number of cells or n, whichever is smaller
+    auto level_cap = [&](int l) { return std::min<int64_t>(n, (int64_t)ns << (3 * l)); };
+    // ---- temporaries (all freed by cleanup)
     uint64_t *key = nullptr, *skey = nullptr;
-    int32_t *idx = nullptr, *flag = nullptr, *id = nullptr;
-    int64_t *dnb = nullptr, *dcnt = nullptr;
+    int32_t *idx = nullptr, *flag = nullptr, *id = nullptr, *lcnt = nullptr;
+    int64_t *dnb = nullptr, *dcnt = nullptr, *dad = nullptr;
     void *tmp = nullptr;
     size_t tmp_bytes = 0;
+    std::vector<uint64_t *> lkey(d + 1, nullptr);
+    std::vector<int32_t *> lstart(d + 1, nullptr), kid(d + 1, nullptr);
     auto cleanup = [&]() {
-        for (void *b : {(void *)key, (void *)skey, (void *)idx, (void *)flag, (void *)id, (void *)dnb, (void *)dcnt, tmp})
+        for (void *b : {(void *)key, (void *)skey, (void *)idx, (void *)flag, (void *)id, (void *)dnb, (void *)dcnt,
+                        (void *)dad, (void *)lcnt, tmp})
             if (b) (void)hipFree(b);
+        for (int l = 0; l <= d; l++) {
+            if (lkey[l]) (void)hipFree(lkey[l]);
+            if (lstart[l]) (void)hipFree(lstart[l]);
+            if (kid[l]) (void)hipFree(kid[l]);
+        }
     };
 #define CK(call)                                        \
     do {                                                \
@@ -679,6 +913,7 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
             return hip_fail(_e, #call);                 \
         }                                               \
     } while (0)
+    // ---- keys and sort
     CK(hipMalloc(&key, sizeof(uint64_t) * n));
     CK(hipMalloc(&skey, sizeof(uint64_t) * n));
     CK(hipMalloc(&idx, sizeof(int32_t) * n));
@@ -690,7 +925,6 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(hipMalloc(&P->dflag, sizeof(int32_t) * 4));
     CK(hipMemsetAsync(P->dflag, 0, sizeof(int32_t) * 4, st));
     CK(hipMemsetAsync(dcnt, 0, sizeof(int64_t) * 4, st));
-    const int ns = P->nsys;
     CK(hipMalloc(&P->sys_geo, sizeof(double) * 4 * ns));
     CK(hipMalloc(&P->sys_a, sizeof(double) * ns));
     CK(hipMalloc(&P->sys_off, sizeof(int64_t) * (ns + 1)));
@@ -715,62 +949,74 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(hipMalloc(&P->vfar, sizeof(T) * 6 * n));
     CK(hipMalloc(&P->eleaf, sizeof(int32_t) * n));
     hipLaunchKernelGGL(k_gather_x<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)x, P->perm, (T *)P->xs);
-    // ---- levels (per-level temporaries sized by min(n, nsys 8^l))
-    std::vector<uint64_t *> lkey(d + 1, nullptr);
-    std::vector<int32_t *> lstart(d + 1, nullptr);
-    auto cleanup_levels = [&]() {
-        for (int l = 0; l <= d; l++) {
-            if (lkey[l]) (void)hipFree(lkey[l]);
-            if (lstart[l]) (void)hipFree(lstart[l]);
-        }
-    };
+    // ---- every non-empty box of every level
     for (int l = d; l >= 0; l--) {
-        const int64_t cap = std::min<int64_t>(n, l >= 11 ? n : (int64_t)ns << (3 * l));
-        hipError_t e1 = hipMalloc(&lkey[l], sizeof(uint64_t) * cap);
-        hipError_t e2 = hipMalloc(&lstart[l], sizeof(int32_t) * cap);
-        if (e1 != hipSuccess || e2 != hipSuccess) {
-            cleanup_levels();
-            cleanup();
-            return hip_fail(e1 != hipSuccess ? e1 : e2, "hipMalloc(level)");
-        }
+        const int64_t cap = level_cap(l);
+        CK(hipMalloc(&lkey[l], sizeof(uint64_t) * cap));
+        CK(hipMalloc(&lstart[l], sizeof(int32_t) * cap));
         const int sh = 3 * (d - l);
         hipLaunchKernelGGL(k_level_flags, dim3(nblk), dim3(tpb), 0, st, n, skey, sh, flag);
-        (void)hipcub::DeviceScan::InclusiveSum(tmp, scan_bytes, flag, id, (int)n, st);
+        CK(hipcub::DeviceScan::InclusiveSum(tmp, scan_bytes, flag, id, (int)n, st));
         hipLaunchKernelGGL(k_level_fill, dim3(nblk), dim3(tpb), 0, st, n, skey, sh, flag, id, lkey[l], lstart[l],
                            l == d ? P->eleaf : nullptr, dnb + l);
     }
-    // ---- the one host synchronisation: tree sizes and input flags
-    int64_t hnb[MAXDEPTH + 1];
-    int32_t hflag[4];
-    hipError_t e = hipMemcpyAsync(hnb, dnb, sizeof(int64_t) * (d + 1), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(hflag, P->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-        cleanup_levels();
-        cleanup();
-        return hip_fail(e, "plan synchronisation");
+    // ---- adaptive tree: keep flags, kept boxes and leaves per level
+    if (adaptive) {
+        CK(hipMalloc(&dad, sizeof(int64_t) * 2 * (MAXDEPTH + 1)));
+        CK(hipMemsetAsync(dad, 0, sizeof(int64_t) * 2 * (MAXDEPTH + 1), st));
+        for (int l = 0; l <= d; l++) {
+            const int64_t cap = level_cap(l);
+            CK(hipMalloc(&kid[l], sizeof(int32_t) * cap));
+            hipLaunchKernelGGL(k_akeep, grid(cap), dim3(tpb), 0, st, cap, l, d, (int64_t)P->max_per_leaf, n, dnb,
+                               lkey[l], lstart[l], l ? lkey[l - 1] : nullptr, l ? lstart[l - 1] : nullptr, flag,
+                               dad + MAXDEPTH + 1);
+            size_t need = 0;
+            CK(hipcub::DeviceScan::InclusiveSum(nullptr, need, flag, kid[l], (int)cap, st));
+            if (need > tmp_bytes) {
+                cleanup();
+                set_error("internal: scan workspace too small");
+                return LHF_ERR_HIP;
+            }
+            CK(hipcub::DeviceScan::InclusiveSum(tmp, need, flag, kid[l], (int)cap, st));
+            hipLaunchKernelGGL(k_last_i32, dim3(1), dim3(1), 0, st, cap, kid[l], dad + l);
+        }
+        CK(hipGetLastError());
     }
+    // ---- host synchronisation: tree sizes and input flags
+    int64_t hnb[MAXDEPTH + 1], had[2 * (MAXDEPTH + 1)];
+    int32_t hflag[4];
+    CK(hipMemcpyAsync(hnb, dnb, sizeof(int64_t) * (d + 1), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(hflag, P->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
+    if (adaptive) CK(hipMemcpyAsync(had, dad, sizeof(int64_t) * 2 * (MAXDEPTH + 1), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
     if (hflag[1]) {
-        cleanup_levels();
         cleanup();
         set_error("non-finite element coordinate");
         return LHF_ERR_NONFINITE;
     }
     if (hflag[0]) {
-        cleanup_levels();
         cleanup();
         set_error("element outside the domain cube");
         return LHF_ERR_DOMAIN;
     }
+    int64_t kept[MAXDEPTH + 1];
+    P->nleaf = 0;
+    for (int l = 0; l <= d; l++) {
+        kept[l] = adaptive ? had[l] : hnb[l];
+        if (adaptive) P->nleaf += had[MAXDEPTH + 1 + l];
+    }
+    if (!adaptive) P->nleaf = hnb[d];
     int64_t tot = 0;
     LevelTab lt;
     memset(&lt, 0, sizeof(lt));
+    P->max_level = 0;
     for (int l = 0; l <= d; l++) {
-        P->lev[l].nb = hnb[l];
+        P->lev[l].nb = kept[l];
         P->lev[l].off = tot;
         lt.off[l] = tot;
-        lt.nb[l] = hnb[l];
-        tot += hnb[l];
+        lt.nb[l] = kept[l];
+        tot += kept[l];
+        if (kept[l] > 0) P->max_level = l;
     }
     lt.off[d + 1] = tot;
     P->nbox = tot;
@@ -784,40 +1030,86 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(hipMalloc(&P->vcount, sizeof(int32_t) * tot));
     CK(hipMalloc(&P->vsrc, sizeof(int32_t) * tot * VMAX));
     CK(hipMalloc(&P->vdir, sizeof(int16_t) * tot * VMAX));
-    CK(hipMalloc(&P->ulist, sizeof(int32_t) * hnb[d] * 27));
     CK(hipMalloc(&P->M, sizeof(T) * tot * 2 * P2));
     CK(hipMalloc(&P->Lc, sizeof(T) * tot * 2 * P2));
     CK(hipMemsetAsync(P->vcount, 0, sizeof(int32_t) * tot, st));
     for (int l = 0; l <= d; l++) {
-        CK(hipMemcpyAsync(P->bkey + lt.off[l], lkey[l], sizeof(uint64_t) * hnb[l], hipMemcpyDeviceToDevice, st));
-        CK(hipMemcpyAsync(P->bstart + lt.off[l], lstart[l], sizeof(int32_t) * hnb[l], hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_counts, dim3((unsigned)((hnb[l] + tpb - 1) / tpb)), dim3(tpb), 0, st, hnb[l], n,
-                           P->bstart + lt.off[l], P->bcount + lt.off[l]);
+        if (adaptive) {
+            const int64_t cap = level_cap(l);
+            hipLaunchKernelGGL(k_acompact, grid(cap), dim3(tpb), 0, st, cap, l, n, dnb, kid[l], lkey[l], lstart[l],
+                               P->bkey + lt.off[l], P->bstart + lt.off[l], P->bcount + lt.off[l]);
+        } else {
+            CK(hipMemcpyAsync(P->bkey + lt.off[l], lkey[l], sizeof(uint64_t) * hnb[l], hipMemcpyDeviceToDevice, st));
+            CK(hipMemcpyAsync(P->bstart + lt.off[l], lstart[l], sizeof(int32_t) * hnb[l], hipMemcpyDeviceToDevice,
+                              st));
+            hipLaunchKernelGGL(k_counts, grid(hnb[l]), dim3(tpb), 0, st, hnb[l], n, P->bstart + lt.off[l],
+                               P->bcount + lt.off[l]);
+        }
     }
-    hipLaunchKernelGGL(k_links, dim3((unsigned)((tot + tpb - 1) / tpb)), dim3(tpb), 0, st, tot, d, lt, P->bkey,
-                       P->bparent, P->bchild0, P->bnchild);
+    hipLaunchKernelGGL(k_links, grid(tot), dim3(tpb), 0, st, tot, d, lt, P->bkey, P->bparent, P->bchild0, P->bnchild);
     for (int l = 2; l <= d; l++)
-        hipLaunchKernelGGL(k_vlist, dim3((unsigned)((hnb[l] + tpb - 1) / tpb)), dim3(tpb), 0, st, lt.off[l], hnb[l], l,
-                           P->bkey, P->vcount, P->vsrc, P->vdir);
-    hipLaunchKernelGGL(k_ulist, dim3((unsigned)((hnb[d] + tpb - 1) / tpb)), dim3(tpb), 0, st, lt.off[d], hnb[d], d,
-                       P->bkey, P->bcount, P->ulist, dcnt + 1);
-    hipLaunchKernelGGL(k_add_i32, dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, (int32_t)lt.off[d]);
+        if (kept[l] > 0)
+            hipLaunchKernelGGL(k_vlist, grid(kept[l]), dim3(tpb), 0, st, lt.off[l], kept[l], l, P->bkey, P->vcount,
+                               P->vsrc, P->vdir);
+    if (!adaptive) {
+        CK(hipMalloc(&P->ulist, sizeof(int32_t) * hnb[d] * 27));
+        hipLaunchKernelGGL(k_ulist, grid(hnb[d]), dim3(tpb), 0, st, lt.off[d], hnb[d], d, P->bkey, P->bcount,
+                           P->ulist, dcnt + 1);
+        hipLaunchKernelGGL(k_add_i32, dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, (int32_t)lt.off[d]);
+    } else {
+        // levels, the leaf list in element order, the leaf of every element
+        const int64_t nl = P->nleaf;
+        CK(hipMalloc(&P->blev, sizeof(int8_t) * tot));
+        CK(hipMalloc(&P->leaves, sizeof(int32_t) * nl));
+        CK(hipMalloc(&P->nl_start, sizeof(int32_t) * (nl + 1)));
+        CK(hipMalloc(&lcnt, sizeof(int32_t) * (nl + 1)));
+        int32_t *head = flag, *ishead = idx;
+        hipLaunchKernelGGL(k_fill_i32, dim3(nblk), dim3(tpb), 0, st, n, head, -1);
+        hipLaunchKernelGGL(k_blev, grid(tot), dim3(tpb), 0, st, tot, d, lt, (int64_t)P->max_per_leaf, P->bstart,
+                           P->bcount, P->blev, head);
+        hipLaunchKernelGGL(k_is_head, dim3(nblk), dim3(tpb), 0, st, n, head, ishead);
+        CK(hipcub::DeviceScan::InclusiveSum(tmp, scan_bytes, ishead, id, (int)n, st));
+        hipLaunchKernelGGL(k_leaf_list, dim3(nblk), dim3(tpb), 0, st, n, head, id, P->leaves);
+        hipLaunchKernelGGL(k_leaf_fill, dim3((unsigned)nl), dim3(64), 0, st, nl, P->leaves, P->bstart, P->bcount,
+                           P->eleaf);
+        // near-field source lists: count, scan, size on the host, fill
+        hipLaunchKernelGGL(k_fill_i32, grid(nl + 1), dim3(tpb), 0, st, nl + 1, lcnt, 0);
+        hipLaunchKernelGGL(k_adlist<0>, grid(nl), dim3(tpb), 0, st, nl, d, lt, P->leaves, P->blev, P->bkey,
+                           P->bcount, P->bchild0, P->bnchild, lcnt, nullptr, dcnt, P->dflag);
+        size_t need = 0;
+        CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, lcnt, P->nl_start, (int)(nl + 1), st));
+        if (need > tmp_bytes) {
+            cleanup();
+            set_error("internal: scan workspace too small");
+            return LHF_ERR_HIP;
+        }
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, lcnt, P->nl_start, (int)(nl + 1), st));
+        int32_t nent = 0;
+        CK(hipMemcpyAsync(&nent, P->nl_start + nl, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        CK(hipMalloc(&P->nl_ent, sizeof(int32_t) * std::max<int64_t>(nent, 1)));
+        hipLaunchKernelGGL(k_adlist<1>, grid(nl), dim3(tpb), 0, st, nl, d, lt, P->leaves, P->blev, P->bkey,
+                           P->bcount, P->bchild0, P->bnchild, P->nl_start, P->nl_ent, dcnt, P->dflag);
+    }
     hipLaunchKernelGGL(k_sum_i32, dim3(256), dim3(256), 0, st, tot, P->vcount, dcnt);
     CK(hipGetLastError());
     lhf_status ts = build_tables<T>(P, st);
     if (ts != LHF_OK) {
-        cleanup_levels();
         cleanup();
         return ts;
     }
     int64_t hc[4];
-    e = hipMemcpyAsync(hc, dcnt, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    cleanup_levels();
+    CK(hipMemcpyAsync(hc, dcnt, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(hflag, P->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
     cleanup();
-    if (e != hipSuccess) return hip_fail(e, "plan finalisation");
+    if (hflag[2]) {
+        set_error("internal: adaptive near-list walk exceeded its stack");
+        return LHF_ERR_HIP;
+    }
     P->n_m2l = hc[0];
     P->n_p2p = hc[1];
+    P->n_wx = hc[2];
 #undef CK
     return LHF_OK;
 }
@@ -843,6 +1135,7 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
     const int pmax = d->precision == LHF_FP64 ? MAXP : 16;
     if (d->p < 1 || d->p > pmax) return arg_error("p out of range (FP64: 1..24, FP32: 1..16)");
     if (d->depth < 2 || d->depth > MAXDEPTH) return arg_error("depth out of range (2..10)");
+    if (d->max_per_leaf < 0) return arg_error("max_per_leaf must be >= 0");
     if (!(d->tol > 0.0)) return arg_error("tol must be > 0");
     if ((int64_t)nsys > ((int64_t)1 << (63 - 3 * d->depth)) / 2) return arg_error("too many systems for this depth");
     for (int s = 0; s < nsys; s++) {
@@ -859,6 +1152,8 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
     P->precision = d->precision;
     P->tsize = d->precision == LHF_FP64 ? 8 : 4;
     P->stream = stream;
+    P->adaptive = d->max_per_leaf > 0;
+    P->max_per_leaf = d->max_per_leaf;
     P->nsys = nsys;
     P->h_sys_off.assign(off, off + nsys + 1);
     P->h_sys_geo.resize(4 * (size_t)nsys);
@@ -877,7 +1172,7 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
     // warn when, in some system, the far field's singular kernel differs from the core by more than tol
     for (int s = 0; s < nsys; s++) {
         const double as = P->h_sys_a[s];
-        if (as > 0.0 && 1.0 - core_k(len[s] / (double)(1 << P->depth), as) > d->tol) return LHF_WARN_CORE_SPLIT;
+        if (as > 0.0 && 1.0 - core_k(len[s] / (double)(1 << P->max_level), as) > d->tol) return LHF_WARN_CORE_SPLIT;
     }
     return LHF_OK;
 }
@@ -962,12 +1257,16 @@ lhf_status lhf_plan_stats(const lhf_plan *P, lhf_stats *out)
     out->p = P->p;
     for (int l = 0; l <= P->depth; l++) out->boxes[l] = P->lev[l].nb;
     out->n_m2l = P->n_m2l;
+    // one M2M per box below level 2 (into its parent) and one L2L per box below level 2
     int64_t nm2m = 0;
     for (int l = 3; l <= P->depth; l++) nm2m += P->lev[l].nb;
     out->n_m2m = nm2m;
     out->n_l2l = nm2m;
     out->n_p2p_pairs = P->n_p2p;
     out->n_theta_classes = P->n_theta;
+    out->max_level = P->max_level;
+    out->n_leaves = P->nleaf;
+    out->n_wx_pairs = P->n_wx;
     return LHF_OK;
 }
 
