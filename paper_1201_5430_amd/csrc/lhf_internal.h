@@ -131,6 +131,8 @@ struct lhf_plan {
     int sched_ncls = 0;
     bool use_tile = false;
     void *wpad = nullptr;                // padded per-class rotation blocks (tiled M2L layout)
+    bool use_mfma = false;               // matrix-core M2L (same schedule and box maps)
+    void *wmfma = nullptr;               // per-class rotation blocks in MFMA A-operand lane order
 
     // phase profiling: events[k][0..LHF_NPHASE] for the k-th profiled execute
     hipEvent_t *prof_ev = nullptr;

@@ -28,6 +28,8 @@ lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int wh
 bool m2l_tile_supported(int precision, int p);
 void dmap_build(const lhf_plan *Pl, int level, hipStream_t st);
 bool wpad_build(lhf_plan *Pl, hipStream_t st);
+bool m2l_mfma_supported(int precision, int p);
+bool wmfma_build(lhf_plan *Pl, hipStream_t st);
 
 static thread_local std::string g_err = "no error";
 
@@ -836,6 +838,16 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
             LHF_HIP(hipMemsetAsync(P->dmap[l], 0xff, sizeof(int32_t) * cells, st));
             dmap_build(P, l, st);
         }
+        // the matrix-core kernel walks the same schedule; it is the default where it is the
+        // faster of the two (FP32 at p = 16, where the VALU tile holds only two sibling groups);
+        // LHF_MFMA=1 selects it for every supported order, LHF_NO_MFMA=1 never
+        const bool mfma_default = P->precision == LHF_FP32 && p >= 16;
+        P->use_mfma = m2l_mfma_supported(P->precision, p) && (mfma_default || getenv("LHF_MFMA")) &&
+                      !getenv("LHF_NO_MFMA");
+        if (P->use_mfma && !wmfma_build(P, st)) {
+            set_error("matrix-core M2L set-up failed");
+            return LHF_ERR_HIP;
+        }
     }
     return LHF_OK;
 }
@@ -863,7 +875,7 @@ static void free_plan(lhf_plan *P)
     for (int l = 0; l <= MAXDEPTH; l++)
         if (P->dmap[l]) (void)hipFree(P->dmap[l]);
     void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta, P->wpad, P->sched_row_start,
-                  P->sched_rows};
+                  P->sched_rows, P->wmfma};
     for (void *b : sb)
         if (b) (void)hipFree(b);
     delete P;
