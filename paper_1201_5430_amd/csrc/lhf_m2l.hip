@@ -125,7 +125,9 @@ struct M2LSched {
 // row table, so the 16 translations of a batch always have distinct targets that no
 // other wavefront touches: accumulation is a plain LDS read-add-write.  OWN = false:
 // the four wavefronts share the tile's targets and accumulate with LDS atomics.
-template <typename T, int P, int NPAR, bool OWN>
+// NREAL <= NPAR parents of the tile are real: in ownership mode the LDS may hold fewer than
+// the eight sibling groups the wavefront layout addresses, and the missing ones stay empty.
+template <typename T, int P, int NPAR, bool OWN, int NREAL>
 __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64_t npar, int64_t loff, int64_t nbl,
                                                   const uint64_t *__restrict__ bkey, const int32_t *__restrict__ bchild0,
                                                   const int32_t *__restrict__ bnchild, const int32_t *__restrict__ dmap,
@@ -141,13 +143,14 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
     constexpr bool WIDE = sizeof(T) == 8;
     // the next batch's source vector is loaded during the current batch where registers allow
     constexpr bool PREFETCH = (int)sizeof(T) * S::NV <= 256;
-    constexpr int NSLOT = 8 * NPAR;
+    constexpr int NSLOT = 8 * NPAR;              // addressable target slots
+    constexpr int NACC = 8 * NREAL;              // slots with an accumulator (the rest never have a box)
     constexpr int SST = 2 * P2 + 1;              // odd slot stride: slots fall in different LDS banks
     constexpr int NENT = 1512;                   // schedule entries of one sibling group
     extern __shared__ char smem[];
     T *Wl = (T *)smem;                           // [2 kinds: fwd S, back R][2 parts][WB], 16-byte aligned
-    T *acc = Wl + 4 * S::WB;                     // [NSLOT + 1][SST] (last slot absorbs inactive lanes)
-    int *slot_xyz = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] packed target coordinates, -1: no box
+    T *acc = Wl + 4 * S::WB;                     // [NACC + 1][SST] (last slot absorbs inactive lanes)
+    int *slot_xyz = (int *)(acc + (NACC + 1) * SST);  // [NSLOT] packed target coordinates, -1: no box
     int *slot_box = slot_xyz + NSLOT;            // [NSLOT] target box
     int *slot_sys = slot_box + NSLOT;            // [NSLOT] system of the target (offset into dmap)
     int16_t *cst = (int16_t *)(slot_sys + NSLOT);       // [ncls + 1] class starts (entries or rows)
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // XCD-aware tile order: consecutive tiles stay on one XCD (shared L2)
-    const int64_t ntiles = (npar + NPAR - 1) / NPAR;
+    const int64_t ntiles = (npar + NREAL - 1) / NREAL;
     const int64_t per = (ntiles + 7) / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= ntiles) return;
@@ -165,8 +168,8 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
     if (tid < NSLOT) {
         const int i = tid >> 3, c = tid & 7;
         int box = -1, xyz = -1;
-        const int64_t q = (int64_t)NPAR * tile + i;
-        if (q < npar) {
+        const int64_t q = (int64_t)NREAL * tile + i;
+        if (i < NREAL && q < npar) {
             const int64_t pb = poff + q;
             const int c0 = bchild0[pb], nc = bnchild[pb];
             for (int k = 0; k < nc; k++)
@@ -192,7 +195,7 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
         for (int i = tid; i < NENT; i += 256) ent[i] = (int16_t)((sch.ent_dir[i] << 3) | sch.ent_c[i]);
     for (int i = tid; i <= ncls; i += 256) cst[i] = OWN ? sch.row_start[i] : sch.cls_start[i];
     __syncthreads();
-    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
+    for (int idx = tid; idx < NACC * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
         acc[sl * SST + r] = box >= 0 ? Lc[(size_t)box * 2 * P2 + r] : (T)0;
@@ -206,7 +209,7 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
         int slot, dir, src;
     };
     auto setup = [&](int k, int r0) -> Job {
-        Job j{NSLOT, 0, -1};
+        Job j{NACC, 0, -1};
         if (k >= ncls) return j;
         int slot, dir;
         if (OWN) {
@@ -410,8 +413,8 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
         // 6. back-rotation about z (-phi) and accumulation into the target slot (branch-free;
         //    inactive lanes add into the spare slot)
         {
-            T *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + pot * P2;
-        T *spare = acc + (size_t)NSLOT * SST + pot * P2;
+            T *ap = acc + (size_t)(act ? j.slot : NACC) * SST + pot * P2;
+            T *spare = acc + (size_t)NACC * SST + pot * P2;
             const T sgn_out = part ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
             double cm = 1.0, sm = 0.0;
 #pragma unroll
@@ -448,7 +451,7 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
         r1 = r2;
     }
     __syncthreads();
-    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
+    for (int idx = tid; idx < NACC * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
         if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SST + r];
@@ -518,30 +521,60 @@ static size_t wpad_build_t(lhf_plan *Pl, hipStream_t st)
     return (size_t)stride;
 }
 
-// LDS footprint of a tile with NPAR sibling groups (OWN: no entry list in LDS)
+// LDS footprint of a tile addressing NPAR sibling groups of which NREAL hold accumulators
+// (OWN: no entry list in LDS)
 template <typename T, int P>
-constexpr size_t tile_bytes(int npar, bool own)
+constexpr size_t tile_bytes(int npar, bool own, int nreal)
 {
-    return sizeof(T) * ((size_t)(8 * npar + 1) * (2 * P * P + 1) + 4 * M2LShape<T, P>::WB) + sizeof(int) * 3 * 8 * npar +
-           sizeof(int16_t) * (64 + (own ? 0 : 1512));
+    return sizeof(T) * ((size_t)(8 * nreal + 1) * (2 * P * P + 1) + 4 * M2LShape<T, P>::WB) +
+           sizeof(int) * 3 * 8 * npar + sizeof(int16_t) * (64 + (own ? 0 : 1512));
 }
-// ownership mode (8 sibling groups, no atomics) when it fits in 64 KB; otherwise shared mode
-// with as many sibling groups (at most 4) as fit
+// LDS of one workgroup on gfx950 (160 KB per compute unit, all of it addressable by one group)
+constexpr size_t LDS_MAX = 163840;
+// Budget used to choose the tile: 64 KB.  Ownership mode with fewer real sibling groups in
+// up to 160 KB (FP64 p = 12: 7 of 8) measured no faster than the shared mode (112 vs 108 ms
+// per execute on the 2^20 cube), so the choice stays within 64 KB and leaves room for two
+// workgroups per compute unit.
+constexpr size_t LDS_TILE = 65536;
+// ownership mode (no atomics): the eight sibling groups the wavefronts own, if they fit;
+// otherwise shared mode with 4 or 2 sibling groups
+template <typename T, int P>
+constexpr int tile_nreal_own()
+{
+    return tile_bytes<T, P>(8, true, 8) <= LDS_TILE ? 8 : 0;
+}
 template <typename T, int P>
 constexpr bool tile_own()
 {
-    return tile_bytes<T, P>(8, true) <= 65536;
+    return tile_nreal_own<T, P>() > 0;
 }
 template <typename T, int P>
 constexpr int tile_npar()
 {
-    return tile_own<T, P>() ? 8 : (tile_bytes<T, P>(4, false) <= 65536 ? 4 : 2);
+    return tile_own<T, P>() ? 8 : (tile_bytes<T, P>(4, false, 4) <= LDS_TILE ? 4 : 2);
+}
+template <typename T, int P>
+constexpr int tile_nreal()
+{
+    return tile_own<T, P>() ? tile_nreal_own<T, P>() : tile_npar<T, P>();
 }
 
 template <typename T, int P>
 static size_t m2l_tile_shmem()
 {
-    return tile_bytes<T, P>(tile_npar<T, P>(), tile_own<T, P>());
+    return tile_bytes<T, P>(tile_npar<T, P>(), tile_own<T, P>(), tile_nreal<T, P>());
+}
+
+// allow the tile's dynamic LDS beyond the default 64 KB
+template <typename T, int P>
+static bool tile_attr_t()
+{
+    constexpr int NPAR = tile_npar<T, P>();
+    constexpr bool OWN = tile_own<T, P>();
+    constexpr int NREAL = tile_nreal<T, P>();
+    static_assert(tile_bytes<T, P>(NPAR, OWN, NREAL) <= LDS_MAX, "tile exceeds the LDS");
+    return hipFuncSetAttribute((const void *)k_m2l_tile<T, P, NPAR, OWN, NREAL>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)m2l_tile_shmem<T, P>()) == hipSuccess;
 }
 
 template <typename T, int P>
@@ -549,12 +582,13 @@ static void launch_tile(const lhf_plan *Pl, int level, hipStream_t st)
 {
     constexpr int NPAR = tile_npar<T, P>();
     constexpr bool OWN = tile_own<T, P>();
+    constexpr int NREAL = tile_nreal<T, P>();
     const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
-    const int64_t ntiles = (npar + NPAR - 1) / NPAR;
+    const int64_t ntiles = (npar + NREAL - 1) / NREAL;
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
     const size_t shm = m2l_tile_shmem<T, P>();
-    k_m2l_tile<T, P, NPAR, OWN><<<dim3((unsigned)(per * 8)), dim3(256), shm, st>>>(
+    k_m2l_tile<T, P, NPAR, OWN, NREAL><<<dim3((unsigned)(per * 8)), dim3(256), shm, st>>>(
         level, poff, npar, Pl->lev[level].off, Pl->lev[level].nb, Pl->bkey, Pl->bchild0, Pl->bnchild,
         Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc, (const T *)Pl->wpad, wpad_stride<T, P>(), sch,
         Pl->sched_cls_theta);
@@ -596,20 +630,20 @@ bool wpad_build(lhf_plan *Pl, hipStream_t st)
     size_t r = 0;
     if (Pl->precision == LHF_FP64) {
         switch (Pl->p) {
-        case 4: r = wpad_build_t<double, 4>(Pl, st); break;
-        case 6: r = wpad_build_t<double, 6>(Pl, st); break;
-        case 8: r = wpad_build_t<double, 8>(Pl, st); break;
-        case 10: r = wpad_build_t<double, 10>(Pl, st); break;
-        case 12: r = wpad_build_t<double, 12>(Pl, st); break;
+        case 4: r = wpad_build_t<double, 4>(Pl, st) && tile_attr_t<double, 4>(); break;
+        case 6: r = wpad_build_t<double, 6>(Pl, st) && tile_attr_t<double, 6>(); break;
+        case 8: r = wpad_build_t<double, 8>(Pl, st) && tile_attr_t<double, 8>(); break;
+        case 10: r = wpad_build_t<double, 10>(Pl, st) && tile_attr_t<double, 10>(); break;
+        case 12: r = wpad_build_t<double, 12>(Pl, st) && tile_attr_t<double, 12>(); break;
         }
     } else {
         switch (Pl->p) {
-        case 4: r = wpad_build_t<float, 4>(Pl, st); break;
-        case 6: r = wpad_build_t<float, 6>(Pl, st); break;
-        case 8: r = wpad_build_t<float, 8>(Pl, st); break;
-        case 10: r = wpad_build_t<float, 10>(Pl, st); break;
-        case 12: r = wpad_build_t<float, 12>(Pl, st); break;
-        case 16: r = wpad_build_t<float, 16>(Pl, st); break;
+        case 4: r = wpad_build_t<float, 4>(Pl, st) && tile_attr_t<float, 4>(); break;
+        case 6: r = wpad_build_t<float, 6>(Pl, st) && tile_attr_t<float, 6>(); break;
+        case 8: r = wpad_build_t<float, 8>(Pl, st) && tile_attr_t<float, 8>(); break;
+        case 10: r = wpad_build_t<float, 10>(Pl, st) && tile_attr_t<float, 10>(); break;
+        case 12: r = wpad_build_t<float, 12>(Pl, st) && tile_attr_t<float, 12>(); break;
+        case 16: r = wpad_build_t<float, 16>(Pl, st) && tile_attr_t<float, 16>(); break;
         }
     }
     return r != 0;
