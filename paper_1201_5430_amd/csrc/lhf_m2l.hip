@@ -458,6 +458,292 @@ __global__ void __launch_bounds__(256) k_m2l_tile(int level, int64_t poff, int64
     }
 }
 
+// Ownership mode with two schedule rows per batch.  Each lane carries the translations of
+// rows r and r+1 of its (parent, child position): both have the same target, so every
+// rotation row read from LDS serves two translations and one accumulation adds both.  (The
+// rotation-row broadcasts, not the arithmetic, bound the one-row kernel.)
+template <typename T, int P>
+__global__ void __launch_bounds__(256) k_m2l_tile2(int level, int64_t poff, int64_t npar,
+                                                   const uint64_t *__restrict__ bkey,
+                                                   const int32_t *__restrict__ bchild0,
+                                                   const int32_t *__restrict__ bnchild, const int32_t *__restrict__ dmap,
+                                                   const T *__restrict__ M, T *__restrict__ Lc,
+                                                   const T *__restrict__ wpad, int64_t wstride, M2LSched sch,
+                                                   const int16_t *__restrict__ cls_theta)
+{
+    using S = M2LShape<T, P>;
+    constexpr int P2 = P * P;
+    constexpr bool WIDE = sizeof(T) == 8;
+    constexpr int NSLOT = 64;
+    constexpr int SST = 2 * P2 + 1;
+    extern __shared__ char smem[];
+    T *Wl = (T *)smem;                           // [2 kinds][2 parts][WB]
+    T *acc = Wl + 4 * S::WB;                     // [NSLOT + 1][SST] (last slot: Im lanes of m = 0)
+    int *slot_xyz = (int *)(acc + (NSLOT + 1) * SST);
+    int *slot_box = slot_xyz + NSLOT;
+    int *slot_sys = slot_box + NSLOT;
+    int16_t *cst = (int16_t *)(slot_sys + NSLOT);  // [ncls + 1] row starts
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t ntiles = (npar + 7) / 8;
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= ntiles) return;
+    const int ncls = sch.ncls;
+    if (tid < NSLOT) {
+        const int i = tid >> 3, c = tid & 7;
+        int box = -1, xyz = -1, sys = 0;
+        const int64_t q = (int64_t)8 * tile + i;
+        if (q < npar) {
+            const int64_t pb = poff + q;
+            const int c0 = bchild0[pb], nc = bnchild[pb];
+            for (int k = 0; k < nc; k++)
+                if ((int)(bkey[c0 + k] & 7u) == c) box = c0 + k;
+        }
+        if (box >= 0) {
+            const uint64_t key = bkey[box];
+            uint32_t ix = 0, iy = 0, iz = 0;
+            for (int b = 0; b < level; b++) {
+                ix |= (uint32_t)((key >> (3 * b)) & 1u) << b;
+                iy |= (uint32_t)((key >> (3 * b + 1)) & 1u) << b;
+                iz |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
+            }
+            xyz = (int)(ix | (iy << 10) | (iz << 20));
+            sys = (int)(key >> (3 * level));
+        }
+        slot_box[tid] = box;
+        slot_xyz[tid] = xyz;
+        slot_sys[tid] = sys;
+    }
+    for (int i = tid; i <= ncls; i += 256) cst[i] = sch.row_start[i];
+    __syncthreads();
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
+        const int sl = idx / (2 * P2), r = idx % (2 * P2);
+        const int box = slot_box[sl];
+        acc[sl * SST + r] = box >= 0 ? Lc[(size_t)box * 2 * P2 + r] : (T)0;
+    }
+
+    const int side = 1 << level;
+    const int t = lane >> 2, pot = (lane >> 1) & 1, part = lane & 1;
+    const int col = t >> 1;
+    const int slot = (2 * wave + (t & 1)) * 8 + col;  // this lane's target, the same for every row
+    // source box of this lane's translation in row r of class k (-1: none)
+    auto source = [&](int k, int r, int &dir) -> int {
+        dir = 0;
+        if (k >= ncls || r >= cst[k + 1] - cst[k]) return -1;
+        dir = sch.rows[(size_t)(cst[k] + r) * 8 + col];
+        const int xyz = slot_xyz[slot];
+        if (dir < 0 || xyz < 0) return -1;
+        const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
+                  sz = (xyz >> 20) - (dir / 49 - 3);
+        if (sx < 0 || sy < 0 || sz < 0 || sx >= side || sy >= side || sz >= side) return -1;
+        return dmap[(((size_t)slot_sys[slot] * side + sz) * side + sy) * side + sx];
+    };
+    auto load_part = [&](int src, T *dst) {
+        const T *sp = M + (size_t)(src >= 0 ? src : 0) * 2 * P2 + pot * P2;
+        const T on = src >= 0 ? (T)1 : (T)0;
+#pragma unroll
+        for (int n = 0; n < P; n++)
+#pragma unroll
+            for (int m = 0; m <= n; m++)
+                dst[tri(n) + m] = on * ((m == 0) ? (part ? (T)0 : sp[pk_re(n, 0)]) : sp[part ? pk_im(n, m) : pk_re(n, m)]);
+    };
+    // two dot products sharing one read of the rotation row
+    auto rowdot2 = [&](const T *W, const T *a, const T *b, const int N1, T &ra, T &rb) {
+        T x = 0, y = 0;
+        if (WIDE) {
+            using Vt = typename Vec16<T>::type;
+            constexpr int E = vecE<T>();
+            const Vt *Wv = (const Vt *)W;
+#pragma unroll
+            for (int q = 0; q < (P + E - 1) / E; q++) {
+                if (q * E >= N1) break;
+                const Vt w = Wv[q];
+                const T *wp = (const T *)&w;
+#pragma unroll
+                for (int e = 0; e < E; e++)
+                    if (q * E + e < N1) {
+                        x += wp[e] * a[q * E + e];
+                        y += wp[e] * b[q * E + e];
+                    }
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < P; m++)
+                if (m < N1) {
+                    const T w = W[m];
+                    x += w * a[m];
+                    y += w * b[m];
+                }
+        }
+        ra = x;
+        rb = y;
+    };
+    auto rotate_y = [&](const T *Wbase, T *v0, T *v1) {
+#pragma unroll
+        for (int n = 0; n < P; n++) {
+            T in0[P], in1[P];
+#pragma unroll
+            for (int m = 0; m <= n; m++) {
+                in0[m] = v0[tri(n) + m];
+                in1[m] = v1[tri(n) + m];
+            }
+            const T *W = Wbase + wrow_off<T>(n);
+#pragma unroll
+            for (int mp = 0; mp <= n; mp++) {
+                T a0, a1;
+                rowdot2(W + mp * rowlen<T>(n), in0, in1, n + 1, a0, a1);
+                asm volatile("" : "+v"(a0), "+v"(a1));
+                v0[tri(n) + mp] = a0;
+                v1[tri(n) + mp] = a1;
+            }
+        }
+    };
+    auto angles = [&](int dir, double &cph, double &sph, T &tau) {
+        const int dx = dir % 7 - 3, dy = (dir / 7) % 7 - 3, dz = dir / 49 - 3;
+        tau = (T)sqrt((double)(dx * dx + dy * dy + dz * dz));
+        cph = 1.0;
+        sph = 0.0;
+        const double rho = sqrt((double)(dx * dx + dy * dy));
+        if (rho > 0.0) {
+            cph = (double)dx / rho;
+            sph = (double)dy / rho;
+        }
+    };
+    // rotation about z by +phi (sgn = -1 on Re lanes, +1 on Im lanes) using the pair partner
+    auto rotate_z = [&](T *v, double cph, double sph, T sgn) {
+        double cm = 1.0, sm = 0.0;
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            const T cz = (T)cm, sz = (T)sm * sgn;
+#pragma unroll
+            for (int n = m; n < P; n++) {
+                const T mine = v[tri(n) + m];
+                const T oth = dpp_f<DPP_XOR1>(mine);
+                if (m > 0) v[tri(n) + m] = mine * cz + oth * sz;
+            }
+            const double c2 = cm * cph - sm * sph, s2 = sm * cph + cm * sph;
+            cm = c2;
+            sm = s2;
+        }
+    };
+    // coaxial (S|R) shift by tau and the R-conversion (eq. rcr1, scaled bar form)
+    auto coax = [&](T *v, T tau) {
+        const T itau = (T)1 / tau;
+        T pw[P + 2];
+        pw[0] = (T)1;
+#pragma unroll
+        for (int k = 1; k <= P + 1; k++) pw[k] = pw[k - 1] * itau;
+        const T wphi = pot ? (T)0 : (T)1, wchi = pot ? (T)1 : (T)0;
+        const T sconv = part ? (T)1 : (T)-1;
+#pragma unroll
+        for (int m = 0; m < P; m++) {
+            T cl[P];
+#pragma unroll
+            for (int n2 = m; n2 < P; n2++) cl[n2] = v[tri(n2) + m] * pw[n2];
+            T out[P + 1];
+#pragma unroll
+            for (int n = m; n <= P; n++) {
+                T a = 0;
+#pragma unroll
+                for (int n2 = m; n2 < P; n2++) a += (T)dfact(n + n2) * cl[n2];
+                out[n] = a * pw[n + 1];
+            }
+#pragma unroll
+            for (int n = m; n < P; n++) {
+                const T other = dpp_f<DPP_XOR3>(out[n]);
+                const T fphi = (n > 0) ? tau * (T)((double)m / (double)n) * sconv * wphi : (T)0;
+                const T fchi = -tau * (T)(1.0 / (double)(n + 1)) * wchi;
+                v[tri(n) + m] = out[n] + fphi * other + fchi * out[n + 1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    int k = 0, r0 = 0, staged = -1;
+    int d0, d1;
+    int s0 = source(0, 0, d0), s1 = source(0, 1, d1);
+    while (k < ncls) {
+        if (k != staged) {
+            __syncthreads();
+            const uint4 *src4 = (const uint4 *)(wpad + (size_t)cls_theta[k] * wstride);
+            uint4 *dst4 = (uint4 *)Wl;
+            constexpr int N16 = (int)(4 * S::WB * sizeof(T) / 16);
+#pragma unroll 8
+            for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
+            __syncthreads();
+            staged = k;
+        }
+        int wfo = part * S::WB, wbo = 2 * S::WB + part * S::WB;
+        asm volatile("" : "+v"(wfo), "+v"(wbo));
+        const T *Wf = Wl + wfo;
+        const T *Wb = Wl + wbo;
+        const int dir0 = d0, dir1 = d1, src0 = s0, src1 = s1;
+        // the next batch: its sources are looked up now
+        int k1 = k, r1 = r0 + 2;
+        if (r1 >= cst[k + 1] - cst[k]) {
+            k1 = k + 1;
+            r1 = 0;
+        }
+        s0 = source(k1, r1, d0);
+        s1 = source(k1, r1 + 1, d1);
+
+        T v0[S::NV], v1[S::NV];
+        load_part(src0, v0);
+        load_part(src1, v1);
+        double c0, sn0, c1, sn1;
+        T tau0, tau1;
+        angles(dir0, c0, sn0, tau0);
+        angles(dir1, c1, sn1, tau1);
+        if (src0 < 0) tau0 = (T)1;
+        if (src1 < 0) tau1 = (T)1;
+        const T sgn_in = part ? (T)1 : (T)-1;
+        rotate_z(v0, c0, sn0, sgn_in);
+        rotate_z(v1, c1, sn1, sgn_in);
+        rotate_y(Wf, v0, v1);
+        coax(v0, tau0);
+        coax(v1, tau1);
+        rotate_y(Wb, v0, v1);
+        // back about z (-phi) for each, then one accumulation of the sum
+        {
+            T *ap = acc + (size_t)slot * SST + pot * P2;
+            T *spare = acc + (size_t)NSLOT * SST + pot * P2;
+            const T sgn_out = part ? (T)-1 : (T)1;
+            double cm0 = 1.0, sm0 = 0.0, cm1 = 1.0, sm1 = 0.0;
+#pragma unroll
+            for (int m = 0; m < P; m++) {
+                const T cz0 = (T)cm0, sz0 = (T)sm0 * sgn_out, cz1 = (T)cm1, sz1 = (T)sm1 * sgn_out;
+                {
+                    const double a = cm0 * c0 - sm0 * sn0, b = sm0 * c0 + cm0 * sn0;
+                    cm0 = a;
+                    sm0 = b;
+                    const double a1 = cm1 * c1 - sm1 * sn1, b1 = sm1 * c1 + cm1 * sn1;
+                    cm1 = a1;
+                    sm1 = b1;
+                }
+#pragma unroll
+                for (int n = m; n < P; n++) {
+                    const T x0 = v0[tri(n) + m], x1 = v1[tri(n) + m];
+                    const T o0 = dpp_f<DPP_XOR1>(x0), o1 = dpp_f<DPP_XOR1>(x1);
+                    const int off = (m == 0) ? pk_re(n, 0) : (part ? pk_im(n, m) : pk_re(n, m));
+                    const T val = (m == 0) ? x0 + x1 : x0 * cz0 + o0 * sz0 + x1 * cz1 + o1 * sz1;
+                    T *dst = (m == 0 && part) ? spare + off : ap + off;
+                    *dst += val;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        k = k1;
+        r0 = r1;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
+        const int sl = idx / (2 * P2), r = idx % (2 * P2);
+        const int box = slot_box[sl];
+        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SST + r];
+    }
+}
+
 // dense box map of one level: dmap[(z*side + y)*side + x] = global box index or -1
 __global__ void k_dmap(int level, int64_t off, int64_t nb, const uint64_t *__restrict__ bkey, int32_t *__restrict__ dmap)
 {
@@ -594,6 +880,21 @@ static void launch_tile(const lhf_plan *Pl, int level, hipStream_t st)
         Pl->sched_cls_theta);
 }
 
+// two rows per batch (ownership-mode orders only)
+template <typename T, int P>
+static void launch_tile2(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    static_assert(tile_own<T, P>(), "two-row tiles need the ownership mode");
+    const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
+    const int64_t ntiles = (npar + 7) / 8;
+    const int64_t per = (ntiles + 7) / 8;
+    M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
+    const size_t shm = m2l_tile_shmem<T, P>();
+    k_m2l_tile2<T, P><<<dim3((unsigned)(per * 8)), dim3(256), shm, st>>>(
+        level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc,
+        (const T *)Pl->wpad, wpad_stride<T, P>(), sch, Pl->sched_cls_theta);
+}
+
 // true if the tiled kernel handles this (precision, p)
 bool m2l_tile_supported(int precision, int p)
 {
@@ -617,8 +918,14 @@ void m2l_tile_launch(const lhf_plan *Pl, int level, hipStream_t st)
         switch (p) {
         case 4: launch_tile<float, 4>(Pl, level, st); break;
         case 6: launch_tile<float, 6>(Pl, level, st); break;
-        case 8: launch_tile<float, 8>(Pl, level, st); break;
-        case 10: launch_tile<float, 10>(Pl, level, st); break;
+        case 8:
+            if (Pl->tile2) launch_tile2<float, 8>(Pl, level, st);
+            else launch_tile<float, 8>(Pl, level, st);
+            break;
+        case 10:
+            if (Pl->tile2) launch_tile2<float, 10>(Pl, level, st);
+            else launch_tile<float, 10>(Pl, level, st);
+            break;
         case 12: launch_tile<float, 12>(Pl, level, st); break;
         case 16: launch_tile<float, 16>(Pl, level, st); break;
         }

@@ -176,3 +176,23 @@ def test_fp32_batched_m2l_orders(oracle, p):
     ev, es = _rel(v[m], vr[m]), _rel(s[m], sr[m])
     print(f"FP32 p={p} depth=5 sampled: rel L2 v {ev:.3e} s {es:.3e}", flush=True)
     assert ev < 2e-6 and es < 2e-6
+
+
+@pytest.mark.parametrize("p", [8, 10])
+def test_fp32_two_row_tile(oracle, monkeypatch, p):
+    # the ownership tile with two schedule rows per batch: against the oracle and the one-row tile
+    rng = np.random.default_rng(100 + p)
+    n = 30000
+    x = rng.uniform(0, 1, (n, 3)).astype(np.float32).astype(np.float64)
+    w = rng.normal(size=(n, 3)).astype(np.float32).astype(np.float64)
+    a = float(np.float32(0.5 * n ** (-1 / 3)))
+    samp = rng.choice(n, 40, replace=False)
+    vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
+    m = ~np.isnan(vr[:, 0])
+    v2, s2, _ = _gpu_fmm(x, w, a, p, 5, precision=1)  # two rows per batch (the default here)
+    monkeypatch.setenv("LHF_TILE1", "1")
+    v1, s1, _ = _gpu_fmm(x, w, a, p, 5, precision=1)
+    ev, es = _rel(v2[m], vr[m]), _rel(s2[m], sr[m])
+    print(f"two-row tile FP32 p={p}: rel L2 v {ev:.3e} s {es:.3e}; vs one-row {_rel(v2, v1):.3e}", flush=True)
+    assert ev < 2e-6 and es < 2e-6
+    assert _rel(v2, v1) < 2e-6 and _rel(s2, s1) < 2e-6
