@@ -196,7 +196,8 @@ __global__ void k_links(int64_t nbox, int depth, LevelTab lt, const uint64_t *__
     }
 }
 
-// V-list of every box at levels >= 2 (fixed stride VMAX)
+// V-list of every box at levels >= 2 (fixed stride VMAX); with vsrc == nullptr only the
+// counts (the batched M2L kernels derive the lists from the dense box maps themselves)
 __global__ void k_vlist(int64_t off, int64_t nb, int level, const uint64_t *__restrict__ bkey,
                         int32_t *__restrict__ vcount, int32_t *__restrict__ vsrc, int16_t *__restrict__ vdir)
 {
@@ -223,8 +224,10 @@ __global__ void k_vlist(int64_t off, int64_t nb, int level, const uint64_t *__re
                                         (spread3((uint32_t)cz) << 2);
                     const int64_t j = find_u64(lk, nb, ck);
                     if (j < 0) continue;
-                    vsrc[b * VMAX + cnt] = (int32_t)(off + j);
-                    vdir[b * VMAX + cnt] = (int16_t)((ex + 3) + 7 * (ey + 3) + 49 * (ez + 3));  // t = c_T - c_S
+                    if (vsrc) {
+                        vsrc[b * VMAX + cnt] = (int32_t)(off + j);
+                        vdir[b * VMAX + cnt] = (int16_t)((ex + 3) + 7 * (ey + 3) + 49 * (ez + 3));  // t = c_T - c_S
+                    }
                     cnt++;
                 }
     vcount[b] = cnt;
@@ -820,11 +823,7 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     hipLaunchKernelGGL(k_zph<T>, dim3((NDIR * p + 255) / 256), dim3(256), 0, st, p, (T *)P->zph);
     hipLaunchKernelGGL(k_coax<T>, dim3(1), dim3(32), 0, st, p, (T *)P->coax);
     LHF_HIP(hipGetLastError());
-    // batched M2L: used when the tiled kernel exists for (precision, p), fits in LDS and the
-    // dense box maps stay small (levels <= 8)
-    // (dense maps: nsys 8^l entries per level, at most 2^28 at the leaf level)
-    P->use_tile = m2l_tile_supported(P->precision, p) && P->depth <= 8 &&
-                  ((int64_t)P->nsys << (3 * P->depth)) <= ((int64_t)1 << 28) && !getenv("LHF_NO_TILE");
+    // batched M2L (decided with the tree): schedule, padded rotation blocks, dense box maps
     if (P->use_tile) {
         lhf_status s = build_schedule(P, cls, (int)theta.size(), st);
         if (s != LHF_OK) return s;
@@ -1043,8 +1042,14 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(hipMalloc(&P->bchild0, sizeof(int32_t) * tot));
     CK(hipMalloc(&P->bnchild, sizeof(int32_t) * tot));
     CK(hipMalloc(&P->vcount, sizeof(int32_t) * tot));
-    CK(hipMalloc(&P->vsrc, sizeof(int32_t) * tot * VMAX));
-    CK(hipMalloc(&P->vdir, sizeof(int16_t) * tot * VMAX));
+    // batched M2L: used when the tiled kernel exists for (precision, p) and the dense box maps
+    // stay small (levels <= 8, at most 2^28 cells); then the V-lists are only counted
+    P->use_tile = m2l_tile_supported(P->precision, P->p) && P->depth <= 8 &&
+                  ((int64_t)ns << (3 * P->depth)) <= ((int64_t)1 << 28) && !getenv("LHF_NO_TILE");
+    if (!P->use_tile) {
+        CK(hipMalloc(&P->vsrc, sizeof(int32_t) * tot * VMAX));
+        CK(hipMalloc(&P->vdir, sizeof(int16_t) * tot * VMAX));
+    }
     CK(hipMalloc(&P->M, sizeof(T) * tot * 2 * P2));
     CK(hipMalloc(&P->Lc, sizeof(T) * tot * 2 * P2));
     CK(hipMemsetAsync(P->vcount, 0, sizeof(int32_t) * tot, st));
