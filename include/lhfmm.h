@@ -157,7 +157,7 @@ lhf_status lhf_profile_end(lhf_plan *plan, double *phase_ms, int32_t *n_exec);
 
 /* ---- Batches of independent systems with per-system depth (one HIP graph) ----
  *
- * Unit costs of the depth cost model (the paper's complexity analysis, Sec. 5,
+ * Unit costs of the depth cost model (the paper's complexity analysis, Sec. 4.1,
  * eqs. fmm2-fmm3): far-field nanoseconds per octree box of levels 2..d (P2M, M2M,
  * M2L, L2L, L2P together) and near-field nanoseconds per ordered element pair. */
 typedef struct {

@@ -11,7 +11,7 @@
 // streams) and replayed by every later execute with the same array pointers.
 //
 // Depth selection follows the cost model of the paper's complexity analysis
-// (Sec. 5, eqs. fmm2-fmm3): work = (far-field cost per box) x (boxes) + (near-field
+// (Sec. 4.1, eqs. fmm2-fmm3): work = (far-field cost per box) x (boxes) + (near-field
 // cost per pair) x (pairs), with both unit costs measured on the device by
 // lhf_autotune, subject to the accuracy constraint of the core split (the leaf side
 // must be wide enough that the singular far kernel is within tol of the Gaussian
