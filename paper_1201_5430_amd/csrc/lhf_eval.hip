@@ -22,6 +22,7 @@ namespace lhf {
 
 void m2l_tile_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_mfma_launch(const lhf_plan *Pl, int level, hipStream_t st);
+void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 
 constexpr int WAVE = 64;
 constexpr int NRMAX = (2 * MAXP * MAXP + WAVE - 1) / WAVE;  // accumulator rows per lane
@@ -881,6 +882,7 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
                                    rot, zph, P->dir_theta, coax);
                 mark(7 + 2 * l);
                 if (P->use_mfma) m2l_mfma_launch(P, l, st);
+                else if (P->use_half) m2l_half_launch(P, l, st);
                 else m2l_tile_launch(P, l, st);
                 mark(8 + 2 * l);
             } else {

@@ -132,6 +132,8 @@ struct lhf_plan {
     bool use_tile = false;
     void *wpad = nullptr;                // padded per-class rotation blocks (tiled M2L layout)
     bool use_mfma = false;               // matrix-core M2L (same schedule and box maps)
+    bool use_half = false;               // VALU M2L with each vector split over two lanes (large p)
+    void *whalf = nullptr;               // its rotation tables
     bool tile2 = false;                  // VALU tile with two schedule rows per batch (FP32 p = 8, 10)
     void *wmfma = nullptr;               // per-class rotation blocks in MFMA A-operand lane order
 

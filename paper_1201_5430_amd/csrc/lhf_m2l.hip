@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include "lhf_internal.h"
+#include "lhf_m2l_common.h"
 
 namespace lhf {
 
@@ -46,25 +47,6 @@ struct M2LShape {
     static constexpr int NV = P * (P + 1) / 2;      // (n, m <= n), n < P
     static constexpr int WB = wrow_off<T>(P);       // one padded rotation set (all orders)
 };
-
-__host__ __device__ constexpr int tri(int n) { return n * (n + 1) / 2; }
-
-// quad permutations by DPP (VALU, no LDS traffic): xor 1 and xor 3 within each group of 4 lanes
-template <int CTRL>
-__device__ inline float dpp_f(float v)
-{
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
-}
-template <int CTRL>
-__device__ inline double dpp_f(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-constexpr int DPP_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
-constexpr int DPP_XOR3 = 0x1B;  // quad_perm [3,2,1,0]
 
 template <typename T>
 struct Vec16;
@@ -101,25 +83,6 @@ __device__ __attribute__((always_inline)) inline T rowdot(const T *W, const T *i
     }
     return a;
 }
-
-// factorials as constants
-__device__ constexpr double dfact(int k)
-{
-    double f = 1.0;
-    for (int i = 2; i <= k; i++) f *= (double)i;
-    return f;
-}
-
-struct M2LSched {
-    // static schedule of one sibling group, sorted by polar-angle class
-    const int16_t *cls_start;  // [ncls+1]
-    const int16_t *ent_c;      // [1512] child position of the target
-    const int16_t *ent_dir;    // [1512] direction code of t = c_T - c_S
-    int ncls;
-    // the same entries as rows of 8 (column = child position, -1 = hole)
-    const int16_t *row_start;  // [ncls+1] first row of each class
-    const int16_t *rows;       // [nrows][8] direction codes
-};
 
 // OWN = true: each wavefront owns two of the tile's eight sibling groups and walks the
 // row table, so the 16 translations of a batch always have distinct targets that no
@@ -539,14 +502,18 @@ __global__ void __launch_bounds__(256) k_m2l_tile2(int level, int64_t poff, int6
         if (sx < 0 || sy < 0 || sz < 0 || sx >= side || sy >= side || sz >= side) return -1;
         return dmap[(((size_t)slot_sys[slot] * side + sz) * side + sy) * side + sx];
     };
+    // a missing source gives zeros by selection, never by scaling what box 0 holds (the two
+    // translations of a lane share one accumulation, so a NaN there would reach the target)
     auto load_part = [&](int src, T *dst) {
         const T *sp = M + (size_t)(src >= 0 ? src : 0) * 2 * P2 + pot * P2;
-        const T on = src >= 0 ? (T)1 : (T)0;
+        const bool on = src >= 0;
 #pragma unroll
         for (int n = 0; n < P; n++)
 #pragma unroll
-            for (int m = 0; m <= n; m++)
-                dst[tri(n) + m] = on * ((m == 0) ? (part ? (T)0 : sp[pk_re(n, 0)]) : sp[part ? pk_im(n, m) : pk_re(n, m)]);
+            for (int m = 0; m <= n; m++) {
+                const T x = (m == 0) ? (part ? (T)0 : sp[pk_re(n, 0)]) : sp[part ? pk_im(n, m) : pk_re(n, m)];
+                dst[tri(n) + m] = on ? x : (T)0;
+            }
     };
     // two dot products sharing one read of the rotation row
     auto rowdot2 = [&](const T *W, const T *a, const T *b, const int N1, T &ra, T &rb) {

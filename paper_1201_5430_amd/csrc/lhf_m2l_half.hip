@@ -1,0 +1,511 @@
+// lhf_m2l_half.hip -- batched M2L with each translation's coefficient vector split over two
+// lanes by the parity of m (the large orders: FP64 p = 8, 10, 12; FP32 p = 12, 16).
+//
+// The translation is the same as in the one-lane tile kernel: rotation about z and y,
+// coaxial (S|R) shift, R-conversion (eq. rcr1), back-rotation (Sec. 4.4), for both
+// potentials, summed into the local expansions of the tile's targets in LDS.  What differs
+// is the lane layout.  Holding a whole part vector per lane (P(P+1)/2 values) fills the
+// register file at these orders and leaves one wavefront per SIMD, which cannot hide the
+// latency of its own LDS reads and dependent FMAs.  Here
+//   lane = 8 t + 4 pot + 2 part + h      (t: translation of the batch, 8 per wavefront)
+// and the lane with parity h holds the entries m = 2j + h (j = 0 .. n/2) of every order n:
+//   * z-rotations act entry by entry (partner part by a DPP quad swap);
+//   * the coaxial shift and the conversion act column by column (fixed m), so they stay in
+//     the lane; the conversion's other-potential partner comes by ds_swizzle;
+//   * the y-rotation of order n mixes all m: each lane forms the partial sums over its own
+//     columns for its own output rows (o) and for its partner's rows (t), and a DPP pair swap
+//     adds the partner's t to the lane's o.  The rotation blocks are stored per (kind, part,
+//     parity) as [o rows | t rows] x own columns, zero where m or m' exceeds n.
+// Slots of odd lanes whose m exceeds n (even n) stay zero and are never accumulated.
+#include <hip/hip_runtime.h>
+
+#include "lhf_internal.h"
+#include "lhf_m2l_common.h"
+
+namespace lhf {
+namespace hv {
+
+// entries of order n held by one lane: m = 2j + h, j < S(n)
+__host__ __device__ constexpr int S(int n) { return n / 2 + 1; }
+__host__ __device__ constexpr int hoff(int n)
+{
+    int o = 0;
+    for (int k = 0; k < n; k++) o += S(k);
+    return o;
+}
+template <typename T>
+__host__ __device__ constexpr int E() { return 16 / (int)sizeof(T); }
+// rotation rows padded to whole 16-byte vectors
+template <typename T>
+__host__ __device__ constexpr int RL(int n) { return (S(n) + E<T>() - 1) / E<T>() * E<T>(); }
+// offset of order n's block in one (kind, part, parity) table: sum_{k<n} 2 S(k) RL(k)
+template <typename T>
+__host__ __device__ constexpr int woff(int n)
+{
+    int o = 0;
+    for (int k = 0; k < n; k++) o += 2 * S(k) * RL<T>(k);
+    return o;
+}
+
+template <typename T, int P>
+struct Shape {
+    static constexpr int NH = hoff(P);      // entries per lane
+    static constexpr int WH = woff<T>(P);   // one (kind, part, parity) rotation table
+    static constexpr int P2 = P * P;
+    static constexpr int SST = 2 * P2 + 1;  // odd slot stride: slots fall in different LDS banks
+};
+
+template <typename T>
+struct V16;
+template <>
+struct V16<float> {
+    using type = float4;
+};
+template <>
+struct V16<double> {
+    using type = double2;
+};
+
+// sum_{i<N} W[i] x[i], W read as 16-byte vectors
+template <typename T>
+__device__ __attribute__((always_inline)) inline T dotw(const T *W, const T *x, const int N)
+{
+    using V = typename V16<T>::type;
+    constexpr int e = E<T>();
+    T a = 0;
+#pragma unroll
+    for (int q = 0; q < (N + e - 1) / e; q++) {
+        const V w = ((const V *)W)[q];
+        const T *wp = (const T *)&w;
+#pragma unroll
+        for (int k = 0; k < e; k++)
+            if (q * e + k < N) a += wp[k] * x[q * e + k];
+    }
+    return a;
+}
+
+// LDS footprint of a tile of NPAR sibling groups
+template <typename T, int P>
+constexpr size_t tile_bytes(int npar)
+{
+    using Sh = Shape<T, P>;
+    return sizeof(T) * ((size_t)(8 * npar + 1) * Sh::SST + 8 * (size_t)Sh::WH) + sizeof(int) * 3 * 8 * npar +
+           sizeof(int16_t) * (64 + 1512);
+}
+// two workgroups per compute unit (160 KB of LDS)
+constexpr size_t LDS_HALF = 81920;
+template <typename T, int P>
+constexpr int tile_npar()
+{
+    return tile_bytes<T, P>(4) <= LDS_HALF ? 4 : 2;
+}
+
+}  // namespace hv
+
+// NPAR sibling groups per tile, shared by the four wavefronts (LDS atomics).
+// PF: the next batch's source entries are loaded during the current batch.
+template <typename T, int P, int NPAR, bool PF>
+__global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, int64_t npar,
+                                                  const uint64_t *__restrict__ bkey,
+                                                  const int32_t *__restrict__ bchild0,
+                                                  const int32_t *__restrict__ bnchild,
+                                                  const int32_t *__restrict__ dmap, const T *__restrict__ M,
+                                                  T *__restrict__ Lc, const T *__restrict__ wh, int64_t wstride,
+                                                  M2LSched sch, const int16_t *__restrict__ cls_theta)
+{
+    using Sh = hv::Shape<T, P>;
+    using hv::hoff;
+    using hv::S;
+    constexpr int P2 = Sh::P2, SST = Sh::SST, NH = Sh::NH;
+    constexpr int NSLOT = 8 * NPAR;
+    constexpr int NENT = 1512;  // schedule entries of one sibling group
+    extern __shared__ char smem[];
+    T *Wl = (T *)smem;                                // [kind: fwd S, back R][part][parity][WH]
+    T *acc = Wl + 8 * Sh::WH;                         // [NSLOT + 1][SST] (last slot absorbs)
+    int *slot_xyz = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] packed target coordinates, -1: no box
+    int *slot_box = slot_xyz + NSLOT;                 // [NSLOT] target box
+    int *slot_sys = slot_box + NSLOT;                 // [NSLOT] system of the target
+    int16_t *cst = (int16_t *)(slot_sys + NSLOT);     // [ncls + 1] class starts
+    int16_t *ent = cst + 64;                          // [NENT] (dir << 3) | child position
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // XCD-aware tile order: consecutive tiles stay on one XCD (shared L2)
+    const int64_t ntiles = (npar + NPAR - 1) / NPAR;
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= ntiles) return;
+    const int ncls = sch.ncls;
+
+    if (tid < NSLOT) {
+        const int i = tid >> 3, c = tid & 7;
+        int box = -1, xyz = -1, sys = 0;
+        const int64_t q = (int64_t)NPAR * tile + i;
+        if (q < npar) {
+            const int64_t pb = poff + q;
+            const int c0 = bchild0[pb], nc = bnchild[pb];
+            for (int k = 0; k < nc; k++)
+                if ((int)(bkey[c0 + k] & 7u) == c) box = c0 + k;
+        }
+        if (box >= 0) {
+            const uint64_t key = bkey[box];
+            uint32_t ix = 0, iy = 0, iz = 0;
+            for (int b = 0; b < level; b++) {
+                ix |= (uint32_t)((key >> (3 * b)) & 1u) << b;
+                iy |= (uint32_t)((key >> (3 * b + 1)) & 1u) << b;
+                iz |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
+            }
+            xyz = (int)(ix | (iy << 10) | (iz << 20));
+            sys = (int)(key >> (3 * level));
+        }
+        slot_box[tid] = box;
+        slot_xyz[tid] = xyz;
+        slot_sys[tid] = sys;
+    }
+    for (int i = tid; i < NENT; i += 256) ent[i] = (int16_t)((sch.ent_dir[i] << 3) | sch.ent_c[i]);
+    for (int i = tid; i <= ncls; i += 256) cst[i] = sch.cls_start[i];
+    __syncthreads();
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
+        const int sl = idx / (2 * P2), r = idx % (2 * P2);
+        const int box = slot_box[sl];
+        acc[sl * SST + r] = box >= 0 ? Lc[(size_t)box * 2 * P2 + r] : (T)0;
+    }
+
+    const int side = 1 << level;
+    const int t = lane >> 3, pot = (lane >> 2) & 1, part = (lane >> 1) & 1, h = lane & 1;
+
+    struct Job {
+        int slot, dir, src;
+    };
+    // translation tr of class k (8 per wavefront and batch): (slot, dir) from LDS, source by one load
+    auto setup = [&](int k, int r0) -> Job {
+        Job j{NSLOT, 0, -1};
+        if (k >= ncls) return j;
+        const int e0 = cst[k], cnt = cst[k + 1] - e0;
+        const int tr = r0 + wave * 8 + t;
+        if (tr >= NPAR * cnt) return j;
+        const int code = ent[e0 + tr / NPAR];
+        const int dir = code >> 3;
+        const int slot = (tr % NPAR) * 8 + (code & 7);
+        const int xyz = slot_xyz[slot];
+        if (xyz < 0) return j;
+        const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
+                  sz = (xyz >> 20) - (dir / 49 - 3);
+        if (sx < 0 || sy < 0 || sz < 0 || sx >= side || sy >= side || sz >= side) return j;
+        const int src = dmap[(((size_t)slot_sys[slot] * side + sz) * side + sy) * side + sx];
+        if (src < 0) return j;
+        j.slot = slot;
+        j.dir = dir;
+        j.src = src;
+        return j;
+    };
+    auto advance = [&](int &k, int &r0) {
+        r0 += 32;
+        if (k < ncls && r0 >= NPAR * (cst[k + 1] - cst[k])) {
+            k++;
+            r0 = 0;
+        }
+    };
+    // this lane's entries of the source: order n, m = 2j + h; zero where m > n or (Im, m = 0)
+    auto load_part = [&](const Job &j, T *dst) {
+        const T *sp = M + (size_t)(j.src >= 0 ? j.src : 0) * 2 * P2 + pot * P2;
+#pragma unroll
+        for (int n = 0; n < P; n++)
+#pragma unroll
+            for (int jj = 0; jj < S(n); jj++) {
+                const int m = 2 * jj + h;
+                const bool ok = m <= n && !(part && m == 0);
+                const int off = ok ? n * n + (part ? n : 0) + m : 0;
+                const T x = sp[off];
+                dst[hoff(n) + jj] = ok ? x : (T)0;
+            }
+    };
+
+    int k = 0, r0 = 0;   // current batch
+    int k1 = 0, r1 = 0;  // next batch
+    advance(k1, r1);
+    Job cur = setup(k, r0), nxt = setup(k1, r1);
+    T nv[PF ? NH : 1];
+    if (PF) load_part(cur, nv);
+    int staged = -1;
+    while (k < ncls) {
+        if (k != staged) {
+            // stage the class's rotation tables with 16-byte loads
+            __syncthreads();
+            const uint4 *src4 = (const uint4 *)(wh + (size_t)cls_theta[k] * wstride);
+            uint4 *dst4 = (uint4 *)Wl;
+            constexpr int N16 = (int)(8 * Sh::WH * sizeof(T) / 16);
+#pragma unroll 4
+            for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
+            __syncthreads();
+            staged = k;
+        }
+        // opaque per-batch offset: keeps the compiler from hoisting the class's rotation
+        // entries out of the batch loop
+        int wo = (part * 2 + h) * Sh::WH;
+        asm volatile("" : "+v"(wo));
+        const T *Wf = Wl + wo;
+        const T *Wb = Wl + 4 * Sh::WH + wo;
+
+        const Job j = cur;
+        const bool act = j.src >= 0;
+        T v[NH];
+        if (PF) {
+#pragma unroll
+            for (int q = 0; q < NH; q++) v[q] = nv[q];
+        } else {
+            load_part(j, v);
+        }
+        int k2 = k1, r2 = r1;
+        advance(k2, r2);
+        const Job nn = setup(k2, r2);
+        if (PF) load_part(nxt, nv);
+
+        const int dir = j.dir;
+        const int dx = dir % 7 - 3, dy = (dir / 7) % 7 - 3, dz = dir / 49 - 3;
+        const T tau = (T)sqrt((double)(dx * dx + dy * dy + dz * dz));
+        // e^{i phi} of the direction (phi = atan2(dy, dx); 0 on the z axis), FP64
+        double cph = 1.0, sph = 0.0;
+        {
+            const double rho = sqrt((double)(dx * dx + dy * dy));
+            if (rho > 0.0) {
+                cph = (double)dx / rho;
+                sph = (double)dy / rho;
+            }
+        }
+        const double c2 = cph * cph - sph * sph, s2 = 2.0 * cph * sph;  // e^{2 i phi}
+        // 1. rotate about z by +phi: Re' = re c - im s, Im' = im c + re s (m = 2j + h)
+        {
+            const T sgn = part ? (T)1 : (T)-1;
+            double cm = h ? cph : 1.0, sm = h ? sph : 0.0;
+#pragma unroll
+            for (int jj = 0; jj < P / 2; jj++) {
+                const T cz = (T)cm, sz = (T)sm * sgn;
+#pragma unroll
+                for (int n = 2 * jj; n < P; n++) {
+                    const T x = v[hoff(n) + jj];
+                    const T o = dpp_f<DPP_XOR2>(x);
+                    v[hoff(n) + jj] = x * cz + o * sz;
+                }
+                const double a = cm * c2 - sm * s2, b = sm * c2 + cm * s2;
+                cm = a;
+                sm = b;
+            }
+        }
+        // 2. and 5. rotation about y of every order: partial sums over the lane's columns for
+        //    its own rows (o) and its partner's rows (t), then o + partner's t
+        auto rotate_y = [&](const T *W) __attribute__((always_inline)) {
+#pragma unroll
+            for (int n = 0; n < P; n++) {
+                const T *Wn = W + hv::woff<T>(n);
+                constexpr int SM = P / 2 + 1;
+                T o[SM], tt[SM];
+#pragma unroll
+                for (int jj = 0; jj < S(n); jj++) {
+                    o[jj] = hv::dotw<T>(Wn + jj * hv::RL<T>(n), &v[hoff(n)], S(n));
+                    tt[jj] = hv::dotw<T>(Wn + (S(n) + jj) * hv::RL<T>(n), &v[hoff(n)], S(n));
+                    asm volatile("" : "+v"(o[jj]), "+v"(tt[jj]));
+                }
+#pragma unroll
+                for (int jj = 0; jj < S(n); jj++) v[hoff(n) + jj] = o[jj] + dpp_f<DPP_XOR1>(tt[jj]);
+            }
+        };
+        rotate_y(Wf);
+        // 3+4. per column m = 2c + h: coaxial (S|R) shift out_n = tau^-(n+1) sum_n' (n+n')! tau^-n' in_n'
+        //      (chi to order P), then the R-conversion (eq. rcr1, scaled)
+        //        phi~ = phi + i tau m/n chi ,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
+        {
+            const T itau = (T)1 / tau, itau2 = itau * itau;
+            const T wphi = pot ? (T)0 : (T)1, wchi = pot ? (T)1 : (T)0;
+            const T sconv = part ? (T)1 : (T)-1;
+            const T keep0 = h ? (T)0 : (T)1;  // slot (n = 2c, c) holds m = 2c + h: empty on odd lanes
+            T p0 = (T)1;                      // tau^-(2c), kept as a running product
+#pragma unroll
+            for (int c = 0; c < P / 2; c++) {
+                const int n0 = 2 * c;
+                const T mval = (T)(2 * c + h);
+                T cl[P];
+                {
+                    T pq = p0;
+#pragma unroll
+                    for (int n2 = n0; n2 < P; n2++) {
+                        cl[n2] = v[hoff(n2) + c] * pq;
+                        pq *= itau;
+                    }
+                }
+                T out[P + 1];
+                {
+                    T pq = p0 * itau;
+#pragma unroll
+                    for (int n = n0; n <= P; n++) {
+                        T a = 0;
+#pragma unroll
+                        for (int n2 = n0; n2 < P; n2++) a += (T)dfact(n + n2) * cl[n2];
+                        out[n] = a * pq;
+                        pq *= itau;
+                    }
+                }
+                p0 *= itau2;
+#pragma unroll
+                for (int n = n0; n < P; n++) {
+                    const T other = swz_xor<6>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
+                    const T fphi = (n > 0) ? tau * mval * (T)(1.0 / (double)n) * sconv * wphi : (T)0;
+                    const T fchi = -tau * (T)(1.0 / (double)(n + 1)) * wchi;
+                    T val = out[n] + fphi * other + fchi * out[n + 1];
+                    if (n == n0) val *= keep0;
+                    v[hoff(n) + c] = val;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        rotate_y(Wb);
+        // 6. back-rotation about z (-phi) and accumulation into the target slot (inactive lanes
+        //    and empty entries add into the spare slot)
+        {
+            T *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + pot * P2;
+            T *spare = acc + (size_t)NSLOT * SST + pot * P2;
+            const T sgn = part ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
+            double cm = h ? cph : 1.0, sm = h ? sph : 0.0;
+#pragma unroll
+            for (int jj = 0; jj < P / 2; jj++) {
+                const T cz = (T)cm, sz = (T)sm * sgn;
+                {
+                    const double a = cm * c2 - sm * s2, b = sm * c2 + cm * s2;
+                    cm = a;
+                    sm = b;
+                }
+                const int m = 2 * jj + h;
+#pragma unroll
+                for (int n = 2 * jj; n < P; n++) {
+                    const T x = v[hoff(n) + jj];
+                    const T o = dpp_f<DPP_XOR2>(x);
+                    const T val = x * cz + o * sz;
+                    const bool ok = m <= n && !(part && m == 0);
+                    const int off = n * n + (part ? n : 0) + m;  // < P^2 also where !ok
+                    atomicAdd((ok ? ap : spare) + off, val);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+
+        cur = nxt;
+        nxt = nn;
+        k = k1;
+        r0 = r1;
+        k1 = k2;
+        r1 = r2;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
+        const int sl = idx / (2 * P2), r = idx % (2 * P2);
+        const int box = slot_box[sl];
+        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SST + r];
+    }
+}
+
+// Rotation tables of every polar-angle class in the half-vector layout:
+// [kind: forward S, backward R][part: Re, Im][parity h][order n][o rows, t rows][RL(n)],
+// row j of o is m' = 2j + h, row j of t is m' = 2j + 1 - h, column i is m = 2i + h; the Im
+// block (m, m' >= 1) is embedded with zeros at m = 0 and m' = 0; zero where m or m' > n.
+template <typename T, int P>
+__global__ void k_whalf(const T *__restrict__ rot, T *__restrict__ wh, int64_t stride)
+{
+    using Sh = hv::Shape<T, P>;
+    const int th = blockIdx.x;
+    const int RS = rot_set_size(P);
+    const T *Rf = rot + ((size_t)th * ROT_NKIND + ROT_S_FWD) * RS;
+    const T *Rb = rot + ((size_t)th * ROT_NKIND + ROT_R_BACK) * RS;
+    for (int idx = threadIdx.x; idx < stride; idx += blockDim.x) {
+        T val = (T)0;
+        const int tb = idx / Sh::WH, e = idx % Sh::WH;
+        const int kind = tb >> 2, part = (tb >> 1) & 1, h = tb & 1;
+        int n = 0;
+        while (hv::woff<T>(n + 1) <= e) n++;
+        const int r = e - hv::woff<T>(n), row = r / hv::RL<T>(n), i = r % hv::RL<T>(n);
+        const int ot = row / hv::S(n), jr = row % hv::S(n);
+        const int mp = 2 * jr + (ot ? 1 - h : h), m = 2 * i + h;
+        if (i < hv::S(n) && mp <= n && m <= n) {
+            const T *blk = (kind ? Rb : Rf) + rot_block_off(n);
+            if (part == 0) val = blk[mp * (n + 1) + m];
+            else if (mp > 0 && m > 0) val = blk[(n + 1) * (n + 1) + (mp - 1) * n + (m - 1)];
+        }
+        wh[(size_t)th * stride + idx] = val;
+    }
+}
+
+namespace {
+
+template <typename T, int P>
+constexpr bool half_prefetch()
+{
+    return false;
+}
+
+template <typename T, int P>
+static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
+{
+    constexpr int NPAR = hv::tile_npar<T, P>();
+    constexpr size_t shm = hv::tile_bytes<T, P>(NPAR);
+    static_assert(shm <= 163840, "tile exceeds the LDS");
+    const int64_t stride = 8 * (int64_t)hv::Shape<T, P>::WH;
+    if (hipMalloc(&Pl->whalf, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
+    k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->whalf, stride);
+    return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, half_prefetch<T, P>()>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess;
+}
+
+template <typename T, int P>
+static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    constexpr int NPAR = hv::tile_npar<T, P>();
+    const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
+    const int64_t ntiles = (npar + NPAR - 1) / NPAR;
+    const int64_t per = (ntiles + 7) / 8;
+    M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
+    k_m2l_half<T, P, NPAR, half_prefetch<T, P>()><<<dim3((unsigned)(per * 8)), dim3(256), hv::tile_bytes<T, P>(NPAR),
+                                                     st>>>(
+        level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc,
+        (const T *)Pl->whalf, 8 * (int64_t)hv::Shape<T, P>::WH, sch, Pl->sched_cls_theta);
+}
+
+}  // namespace
+
+bool m2l_half_supported(int precision, int p)
+{
+    if (precision == LHF_FP64) return p == 8 || p == 10 || p == 12;
+    return p == 12 || p == 16;
+}
+
+bool whalf_build(lhf_plan *Pl, hipStream_t st)
+{
+    if (Pl->precision == LHF_FP64) {
+        switch (Pl->p) {
+        case 8: return whalf_build_t<double, 8>(Pl, st);
+        case 10: return whalf_build_t<double, 10>(Pl, st);
+        case 12: return whalf_build_t<double, 12>(Pl, st);
+        }
+    } else {
+        switch (Pl->p) {
+        case 12: return whalf_build_t<float, 12>(Pl, st);
+        case 16: return whalf_build_t<float, 16>(Pl, st);
+        }
+    }
+    return false;
+}
+
+void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    if (Pl->precision == LHF_FP64) {
+        switch (Pl->p) {
+        case 8: launch_half<double, 8>(Pl, level, st); break;
+        case 10: launch_half<double, 10>(Pl, level, st); break;
+        case 12: launch_half<double, 12>(Pl, level, st); break;
+        }
+    } else {
+        switch (Pl->p) {
+        case 12: launch_half<float, 12>(Pl, level, st); break;
+        case 16: launch_half<float, 16>(Pl, level, st); break;
+        }
+    }
+}
+
+}  // namespace lhf

@@ -29,6 +29,8 @@ bool m2l_tile_supported(int precision, int p);
 void dmap_build(const lhf_plan *Pl, int level, hipStream_t st);
 bool wpad_build(lhf_plan *Pl, hipStream_t st);
 bool m2l_mfma_supported(int precision, int p);
+bool m2l_half_supported(int precision, int p);
+bool whalf_build(lhf_plan *Pl, hipStream_t st);
 bool wmfma_build(lhf_plan *Pl, hipStream_t st);
 
 static thread_local std::string g_err = "no error";
@@ -850,6 +852,13 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
             set_error("matrix-core M2L set-up failed");
             return LHF_ERR_HIP;
         }
+        // the half-vector VALU kernel at the large orders (two lanes per part vector);
+        // LHF_NO_HALF=1 keeps the one-lane tile
+        P->use_half = !P->use_mfma && m2l_half_supported(P->precision, p) && !getenv("LHF_NO_HALF");
+        if (P->use_half && !whalf_build(P, st)) {
+            set_error("half-vector M2L set-up failed");
+            return LHF_ERR_HIP;
+        }
     }
     return LHF_OK;
 }
@@ -877,7 +886,7 @@ static void free_plan(lhf_plan *P)
     for (int l = 0; l <= MAXDEPTH; l++)
         if (P->dmap[l]) (void)hipFree(P->dmap[l]);
     void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta, P->wpad, P->sched_row_start,
-                  P->sched_rows, P->wmfma};
+                  P->sched_rows, P->wmfma, P->whalf};
     for (void *b : sb)
         if (b) (void)hipFree(b);
     delete P;
@@ -1052,6 +1061,9 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     }
     CK(hipMalloc(&P->M, sizeof(T) * tot * 2 * P2));
     CK(hipMalloc(&P->Lc, sizeof(T) * tot * 2 * P2));
+    // multipoles of levels 0 and 1 are never formed, yet kernels read box 0 as a stand-in
+    // source for inactive lanes: every multipole starts as a defined zero
+    CK(hipMemsetAsync(P->M, 0, sizeof(T) * tot * 2 * P2, st));
     CK(hipMemsetAsync(P->vcount, 0, sizeof(int32_t) * tot, st));
     for (int l = 0; l <= d; l++) {
         if (adaptive) {

@@ -156,6 +156,32 @@ def test_batch_graph_replays_and_matches_oracle(oracle, p, exact):
     _check_systems(ve, se, vr, sr, off, 1e-12)
 
 
+@pytest.mark.parametrize("p,depth", [(10, 2), (10, 3), (12, 3)])
+def test_recycled_nan_memory_stays_out(oracle, p, depth):
+    # Device memory handed back to the allocator full of NaN and then reused by the plan: the
+    # multipoles of levels 0 and 1 are never formed, and the M2L kernels read box 0 for inactive
+    # lanes, so nothing of that memory may reach a result (FP32 two-row tile at p = 10, the
+    # half-vector kernel at p = 12).
+    torch = _torch()
+    import paper_1201_5430_amd as LH
+    junk = torch.full((1 << 28,), float("nan"), device="cuda")
+    del junk
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    sizes = [2193, 1549, 1231, 3982]
+    x, w, off, lo, L, a = _systems(sizes, 23, dtype=np.float32)
+    xt = torch.from_numpy(x).float().cuda()
+    wt = torch.from_numpy(w).float().cuda()
+    plan = LH.Plan(xt, a, p=p, depth=depth, precision=LH.FP32, lo=lo, L=L, offsets=off)
+    v, s = plan.execute(wt)
+    torch.cuda.synchronize()
+    plan.close()
+    v, s = v.double().cpu().numpy(), s.double().cpu().numpy()
+    assert np.isfinite(v).all() and np.isfinite(s).all()
+    vr, sr = _per_system_oracle(oracle, x, w, off, lo, L, a, p, [depth] * len(sizes))
+    _check_systems(v, s, vr, sr, off, 2e-6)
+
+
 def test_batch_auto_depths_fp32(oracle):
     torch = _torch()
     import paper_1201_5430_amd as LH

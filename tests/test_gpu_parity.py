@@ -196,3 +196,36 @@ def test_fp32_two_row_tile(oracle, monkeypatch, p):
     print(f"two-row tile FP32 p={p}: rel L2 v {ev:.3e} s {es:.3e}; vs one-row {_rel(v2, v1):.3e}", flush=True)
     assert ev < 2e-6 and es < 2e-6
     assert _rel(v2, v1) < 2e-6 and _rel(s2, s1) < 2e-6
+
+
+@pytest.mark.parametrize("prec,p", [(0, 8), (0, 10), (0, 12), (1, 12), (1, 16)])
+def test_half_vector_m2l(oracle, monkeypatch, prec, p):
+    # the M2L kernel with each part vector split over two lanes by the parity of m (the default
+    # at these orders; FP32 p = 16 only when the matrix-core kernel is switched off): against the
+    # oracle on sampled leaves and against the one-lane tile on every element
+    if p == 16:
+        monkeypatch.setenv("LHF_NO_MFMA", "1")
+    rng = np.random.default_rng(110 + p + prec)
+    n = 30000
+    x = rng.uniform(0, 1, (n, 3))
+    w = rng.normal(size=(n, 3))
+    a = 0.5 * n ** (-1 / 3)
+    if prec:
+        x = x.astype(np.float32).astype(np.float64)
+        w = w.astype(np.float32).astype(np.float64)
+        a = float(np.float32(a))
+    samp = rng.choice(n, 40, replace=False)
+    vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
+    m = ~np.isnan(vr[:, 0])
+    vh, sh, _ = _gpu_fmm(x, w, a, p, 5, precision=prec)
+    monkeypatch.setenv("LHF_NO_HALF", "1")
+    v1, s1, _ = _gpu_fmm(x, w, a, p, 5, precision=prec)
+    ev, es = _rel(vh[m], vr[m]), _rel(sh[m], sr[m])
+    print(f"half-vector M2L prec={prec} p={p}: rel L2 v {ev:.3e} s {es:.3e}; "
+          f"vs one-lane {_rel(vh, v1):.3e} {_rel(sh, s1):.3e}", flush=True)
+    if prec == 0:
+        _check(vh[m], sh[m], vr[m], sr[m])
+        _check(vh, sh, v1, s1, l2=1e-13, mx=1e-12)
+    else:
+        assert ev < 2e-6 and es < 2e-6
+        assert _rel(vh, v1) < 2e-6 and _rel(sh, s1) < 2e-6
