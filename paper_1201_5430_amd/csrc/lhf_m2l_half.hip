@@ -51,8 +51,12 @@ template <typename T, int P>
 struct Shape {
     static constexpr int NH = hoff(P);      // entries per lane
     static constexpr int WH = woff<T>(P);   // one (kind, part, parity) rotation table
+    // tables one 16-byte vector apart beyond their length: the four tables a wavefront reads
+    // at once (part x parity) start in different LDS banks
+    static constexpr int WHS = WH + E<T>();
     static constexpr int P2 = P * P;
-    static constexpr int SST = 2 * P2 + 1;  // odd slot stride: slots fall in different LDS banks
+    static constexpr int POS = P2 + 1;        // potential stride in the LDS accumulator (phi, chi apart)
+    static constexpr int SST = 2 * POS + 1;   // odd slot stride: slots fall in different LDS banks
 };
 
 template <typename T>
@@ -89,7 +93,7 @@ template <typename T, int P>
 constexpr size_t tile_bytes(int npar)
 {
     using Sh = Shape<T, P>;
-    return sizeof(T) * ((size_t)(8 * npar + 1) * Sh::SST + 8 * (size_t)Sh::WH) + sizeof(int) * 3 * 8 * npar +
+    return sizeof(T) * ((size_t)(8 * npar + 1) * Sh::SST + 8 * (size_t)Sh::WHS) + sizeof(int) * 3 * 8 * npar +
            sizeof(int16_t) * (64 + 1512);
 }
 // two workgroups per compute unit (160 KB of LDS)
@@ -116,12 +120,12 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
     using Sh = hv::Shape<T, P>;
     using hv::hoff;
     using hv::S;
-    constexpr int P2 = Sh::P2, SST = Sh::SST, NH = Sh::NH;
+    constexpr int P2 = Sh::P2, SST = Sh::SST, NH = Sh::NH, POS = Sh::POS;
     constexpr int NSLOT = 8 * NPAR;
     constexpr int NENT = 1512;  // schedule entries of one sibling group
     extern __shared__ char smem[];
-    T *Wl = (T *)smem;                                // [kind: fwd S, back R][part][parity][WH]
-    T *acc = Wl + 8 * Sh::WH;                         // [NSLOT + 1][SST] (last slot absorbs)
+    T *Wl = (T *)smem;                                // [kind: fwd S, back R][part][parity][WHS]
+    T *acc = Wl + 8 * Sh::WHS;                        // [NSLOT + 1][SST]: [pot][POS] (last slot absorbs)
     int *slot_xyz = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] packed target coordinates, -1: no box
     int *slot_box = slot_xyz + NSLOT;                 // [NSLOT] target box
     int *slot_sys = slot_box + NSLOT;                 // [NSLOT] system of the target
@@ -167,7 +171,7 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
     for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
-        acc[sl * SST + r] = box >= 0 ? Lc[(size_t)box * 2 * P2 + r] : (T)0;
+        acc[sl * SST + (r >= P2 ? POS - P2 : 0) + r] = box >= 0 ? Lc[(size_t)box * 2 * P2 + r] : (T)0;
     }
 
     const int side = 1 << level;
@@ -233,7 +237,7 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
             __syncthreads();
             const uint4 *src4 = (const uint4 *)(wh + (size_t)cls_theta[k] * wstride);
             uint4 *dst4 = (uint4 *)Wl;
-            constexpr int N16 = (int)(8 * Sh::WH * sizeof(T) / 16);
+            constexpr int N16 = (int)(8 * Sh::WHS * sizeof(T) / 16);
 #pragma unroll 4
             for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
             __syncthreads();
@@ -241,10 +245,10 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
         }
         // opaque per-batch offset: keeps the compiler from hoisting the class's rotation
         // entries out of the batch loop
-        int wo = (part * 2 + h) * Sh::WH;
+        int wo = (part * 2 + h) * Sh::WHS;
         asm volatile("" : "+v"(wo));
         const T *Wf = Wl + wo;
-        const T *Wb = Wl + 4 * Sh::WH + wo;
+        const T *Wb = Wl + 4 * Sh::WHS + wo;
 
         const Job j = cur;
         const bool act = j.src >= 0;
@@ -361,8 +365,8 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
         // 6. back-rotation about z (-phi) and accumulation into the target slot (inactive lanes
         //    and empty entries add into the spare slot)
         {
-            T *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + pot * P2;
-            T *spare = acc + (size_t)NSLOT * SST + pot * P2;
+            T *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + pot * POS;
+            T *spare = acc + (size_t)NSLOT * SST + pot * POS;
             const T sgn = part ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
             double cm = h ? cph : 1.0, sm = h ? sph : 0.0;
 #pragma unroll
@@ -398,12 +402,13 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
     for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
-        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SST + r];
+        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SST + (r >= P2 ? POS - P2 : 0) + r];
     }
 }
 
 // Rotation tables of every polar-angle class in the half-vector layout:
-// [kind: forward S, backward R][part: Re, Im][parity h][order n][o rows, t rows][RL(n)],
+// [kind: forward S, backward R][part: Re, Im][parity h][order n][o rows, t rows][RL(n)]
+// (each table padded to WHS entries),
 // row j of o is m' = 2j + h, row j of t is m' = 2j + 1 - h, column i is m = 2i + h; the Im
 // block (m, m' >= 1) is embedded with zeros at m = 0 and m' = 0; zero where m or m' > n.
 template <typename T, int P>
@@ -416,8 +421,12 @@ __global__ void k_whalf(const T *__restrict__ rot, T *__restrict__ wh, int64_t s
     const T *Rb = rot + ((size_t)th * ROT_NKIND + ROT_R_BACK) * RS;
     for (int idx = threadIdx.x; idx < stride; idx += blockDim.x) {
         T val = (T)0;
-        const int tb = idx / Sh::WH, e = idx % Sh::WH;
+        const int tb = idx / Sh::WHS, e = idx % Sh::WHS;
         const int kind = tb >> 2, part = (tb >> 1) & 1, h = tb & 1;
+        if (e >= Sh::WH) {
+            wh[(size_t)th * stride + idx] = val;
+            continue;
+        }
         int n = 0;
         while (hv::woff<T>(n + 1) <= e) n++;
         const int r = e - hv::woff<T>(n), row = r / hv::RL<T>(n), i = r % hv::RL<T>(n);
@@ -446,7 +455,7 @@ static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
     constexpr int NPAR = hv::tile_npar<T, P>();
     constexpr size_t shm = hv::tile_bytes<T, P>(NPAR);
     static_assert(shm <= 163840, "tile exceeds the LDS");
-    const int64_t stride = 8 * (int64_t)hv::Shape<T, P>::WH;
+    const int64_t stride = 8 * (int64_t)hv::Shape<T, P>::WHS;
     if (hipMalloc(&Pl->whalf, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
     k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->whalf, stride);
     return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, half_prefetch<T, P>()>,
@@ -464,7 +473,7 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
     k_m2l_half<T, P, NPAR, half_prefetch<T, P>()><<<dim3((unsigned)(per * 8)), dim3(256), hv::tile_bytes<T, P>(NPAR),
                                                      st>>>(
         level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc,
-        (const T *)Pl->whalf, 8 * (int64_t)hv::Shape<T, P>::WH, sch, Pl->sched_cls_theta);
+        (const T *)Pl->whalf, 8 * (int64_t)hv::Shape<T, P>::WHS, sch, Pl->sched_cls_theta);
 }
 
 }  // namespace
