@@ -19,11 +19,17 @@ FLAGS = [
 ]
 
 
+# per-source additions: the half-vector M2L's fully unrolled FP32 p = 16 body exceeds the
+# default size limit of '#pragma unroll' (a partly rolled loop would move its vectors to scratch)
+EXTRA = {"lhf_m2l_half.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
+
+
 def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = ["hipcc", "-c", *[f for f in FLAGS if f != "-shared"], "-o", obj, os.path.join(CSRC, src)]
+        cmd = ["hipcc", "-c", *[f for f in FLAGS if f != "-shared"], *EXTRA.get(src, []), "-o", obj,
+               os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

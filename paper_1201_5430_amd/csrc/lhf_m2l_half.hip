@@ -88,13 +88,18 @@ __device__ __attribute__((always_inline)) inline T dotw(const T *W, const T *x, 
     return a;
 }
 
+// accumulator type of the LDS local expansions: FP64 for both paths (LDS FP64 atomic adds
+// are much cheaper than FP32 ones here, and the FP32 path gains a wider sum)
+template <typename T>
+using Acc = double;
+
 // LDS footprint of a tile of NPAR sibling groups
 template <typename T, int P>
 constexpr size_t tile_bytes(int npar)
 {
     using Sh = Shape<T, P>;
-    return sizeof(T) * ((size_t)(8 * npar + 1) * Sh::SST + 8 * (size_t)Sh::WHS) + sizeof(int) * 3 * 8 * npar +
-           sizeof(int16_t) * (64 + 1512);
+    return sizeof(T) * 8 * (size_t)Sh::WHS + sizeof(Acc<T>) * (size_t)(8 * npar + 1) * Sh::SST +
+           sizeof(int) * 3 * 8 * npar + sizeof(int16_t) * (64 + 1512);
 }
 // two workgroups per compute unit (160 KB of LDS)
 constexpr size_t LDS_HALF = 81920;
@@ -124,8 +129,9 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
     constexpr int NSLOT = 8 * NPAR;
     constexpr int NENT = 1512;  // schedule entries of one sibling group
     extern __shared__ char smem[];
+    using A = hv::Acc<T>;
     T *Wl = (T *)smem;                                // [kind: fwd S, back R][part][parity][WHS]
-    T *acc = Wl + 8 * Sh::WHS;                        // [NSLOT + 1][SST]: [pot][POS] (last slot absorbs)
+    A *acc = (A *)(Wl + 8 * Sh::WHS);                 // [NSLOT + 1][SST]: [pot][POS] (last slot absorbs)
     int *slot_xyz = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] packed target coordinates, -1: no box
     int *slot_box = slot_xyz + NSLOT;                 // [NSLOT] target box
     int *slot_sys = slot_box + NSLOT;                 // [NSLOT] system of the target
@@ -171,7 +177,7 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
     for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
-        acc[sl * SST + (r >= P2 ? POS - P2 : 0) + r] = box >= 0 ? Lc[(size_t)box * 2 * P2 + r] : (T)0;
+        acc[sl * SST + (r >= P2 ? POS - P2 : 0) + r] = box >= 0 ? (A)Lc[(size_t)box * 2 * P2 + r] : (A)0;
     }
 
     const int side = 1 << level;
@@ -365,8 +371,8 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
         // 6. back-rotation about z (-phi) and accumulation into the target slot (inactive lanes
         //    and empty entries add into the spare slot)
         {
-            T *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + pot * POS;
-            T *spare = acc + (size_t)NSLOT * SST + pot * POS;
+            A *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + pot * POS;
+            A *spare = acc + (size_t)NSLOT * SST + pot * POS;
             const T sgn = part ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
             double cm = h ? cph : 1.0, sm = h ? sph : 0.0;
 #pragma unroll
@@ -385,7 +391,7 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
                     const T val = x * cz + o * sz;
                     const bool ok = m <= n && !(part && m == 0);
                     const int off = n * n + (part ? n : 0) + m;  // < P^2 also where !ok
-                    atomicAdd((ok ? ap : spare) + off, val);
+                    atomicAdd((ok ? ap : spare) + off, (A)val);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -402,7 +408,7 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
     for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
-        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SST + (r >= P2 ? POS - P2 : 0) + r];
+        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = (T)acc[sl * SST + (r >= P2 ? POS - P2 : 0) + r];
     }
 }
 
@@ -481,7 +487,7 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
 bool m2l_half_supported(int precision, int p)
 {
     if (precision == LHF_FP64) return p == 8 || p == 10 || p == 12;
-    return p == 12 || p == 16;
+    return p == 8 || p == 10 || p == 12 || p == 16;
 }
 
 bool whalf_build(lhf_plan *Pl, hipStream_t st)
@@ -494,6 +500,8 @@ bool whalf_build(lhf_plan *Pl, hipStream_t st)
         }
     } else {
         switch (Pl->p) {
+        case 8: return whalf_build_t<float, 8>(Pl, st);
+        case 10: return whalf_build_t<float, 10>(Pl, st);
         case 12: return whalf_build_t<float, 12>(Pl, st);
         case 16: return whalf_build_t<float, 16>(Pl, st);
         }
@@ -511,6 +519,8 @@ void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st)
         }
     } else {
         switch (Pl->p) {
+        case 8: launch_half<float, 8>(Pl, level, st); break;
+        case 10: launch_half<float, 10>(Pl, level, st); break;
         case 12: launch_half<float, 12>(Pl, level, st); break;
         case 16: launch_half<float, 16>(Pl, level, st); break;
         }

@@ -854,7 +854,9 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
         }
         // the half-vector VALU kernel at the large orders (two lanes per part vector);
         // LHF_NO_HALF=1 keeps the one-lane tile
-        P->use_half = !P->use_mfma && m2l_half_supported(P->precision, p) && !getenv("LHF_NO_HALF");
+        const bool half_default = P->precision == LHF_FP64 || p == 12 || p == 16;
+        P->use_half = !P->use_mfma && m2l_half_supported(P->precision, p) && (half_default || getenv("LHF_HALF")) &&
+                      !getenv("LHF_NO_HALF");
         if (P->use_half && !whalf_build(P, st)) {
             set_error("half-vector M2L set-up failed");
             return LHF_ERR_HIP;

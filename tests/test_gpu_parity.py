@@ -198,13 +198,15 @@ def test_fp32_two_row_tile(oracle, monkeypatch, p):
     assert _rel(v2, v1) < 2e-6 and _rel(s2, s1) < 2e-6
 
 
-@pytest.mark.parametrize("prec,p", [(0, 8), (0, 10), (0, 12), (1, 12), (1, 16)])
+@pytest.mark.parametrize("prec,p", [(0, 8), (0, 10), (0, 12), (1, 8), (1, 10), (1, 12), (1, 16)])
 def test_half_vector_m2l(oracle, monkeypatch, prec, p):
     # the M2L kernel with each part vector split over two lanes by the parity of m (the default
-    # at these orders; FP32 p = 16 only when the matrix-core kernel is switched off): against the
-    # oracle on sampled leaves and against the one-lane tile on every element
+    # at FP64 p = 8..12 and FP32 p = 12; FP32 p = 8, 10 on request, FP32 p = 16 when the
+    # matrix-core kernel is switched off): against the oracle on sampled leaves and against the
+    # one-lane tile on every element
     if p == 16:
         monkeypatch.setenv("LHF_NO_MFMA", "1")
+    monkeypatch.setenv("LHF_HALF", "1")
     rng = np.random.default_rng(110 + p + prec)
     n = 30000
     x = rng.uniform(0, 1, (n, 3))
@@ -218,6 +220,7 @@ def test_half_vector_m2l(oracle, monkeypatch, prec, p):
     vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
     m = ~np.isnan(vr[:, 0])
     vh, sh, _ = _gpu_fmm(x, w, a, p, 5, precision=prec)
+    monkeypatch.delenv("LHF_HALF")
     monkeypatch.setenv("LHF_NO_HALF", "1")
     v1, s1, _ = _gpu_fmm(x, w, a, p, 5, precision=prec)
     ev, es = _rel(vh[m], vr[m]), _rel(sh[m], sr[m])
