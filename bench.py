@@ -45,22 +45,26 @@ def f_m2l(p: int) -> int:
     return 2 * (2 * f_roty + 2 * f_rotz + f_coax) + 6 * p * p
 
 
+# the M2L kernel the library runs for the cube workloads (FP64 p = 12, FP32 p = 10)
+M2L_KERNEL = {0: "k_m2l_half", 1: "k_m2l_tile2"}  # by lhf_precision (FP64 = 0, FP32 = 1)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
 def measured_traffic(which):
     """HBM bytes per M2L launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
-    or None when the kernel source changed after the counters were taken"""
+    or None when the kernel's source changed after the counters were taken"""
     import hashlib
     import re
     try:
-        md = open(os.path.join(ROOT, "profiles", "m2l_tile_cube1m_hbm.md")).read()
-        js = json.loads(re.search(r"```json\n(.*?)\n```", md, re.S).group(1))
-        src = open(os.path.join(ROOT, "paper_1201_5430_amd", "csrc", "lhf_m2l.hip"), "rb").read()
+        md = open(os.path.join(ROOT, "profiles", "m2l_cube1m_hbm.md")).read()
+        js = json.loads(re.search(r"```json\n(.*?)\n```", md, re.S).group(1))[which]
+        src = open(os.path.join(ROOT, "paper_1201_5430_amd", "csrc", js["source"]), "rb").read()
         if hashlib.sha256(src).hexdigest()[:16] != js["source_sha256_prefix"]:
             return None
-        return js[which]["bytes_per_launch"]
+        return js["bytes_per_launch"]
     except Exception:
         return None
 
@@ -371,7 +375,7 @@ def main():
         "phases_ms": r["ph_step"],
         "counts": {"m2l": r["st"]["n_m2l"], "p2p_pairs": r["st"]["n_p2p_pairs"], "boxes": r["st"]["boxes"]},
         "roofline": {
-            "kernel": "k_m2l_tile (batched M2L), one launch per level 2..d",
+            "kernel": M2L_KERNEL[prec] + " (batched M2L), one launch per level 2..d",
             "bound": "alu",
             "achieved": r["achieved"],
             "peak": PEAK_FP64_TFLOPS,

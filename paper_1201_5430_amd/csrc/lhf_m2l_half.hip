@@ -88,32 +88,51 @@ __device__ __attribute__((always_inline)) inline T dotw(const T *W, const T *x, 
     return a;
 }
 
-// accumulator type of the LDS local expansions: FP64 for both paths (LDS FP64 atomic adds
-// are much cheaper than FP32 ones here, and the FP32 path gains a wider sum)
+// accumulator type of the LDS local expansions.  Shared mode: FP64 for both paths (LDS FP64
+// atomic adds are much cheaper than FP32 ones here, and the FP32 path gains a wider sum).
+// Ownership mode: plain adds in the working precision.
+template <typename T, bool OWN>
+struct AccT {
+    using type = double;
+};
 template <typename T>
-using Acc = double;
+struct AccT<T, true> {
+    using type = T;
+};
+template <typename T, bool OWN>
+using Acc = typename AccT<T, OWN>::type;
 
 // LDS footprint of a tile of NPAR sibling groups
-template <typename T, int P>
+template <typename T, int P, bool OWN>
 constexpr size_t tile_bytes(int npar)
 {
     using Sh = Shape<T, P>;
-    return sizeof(T) * 8 * (size_t)Sh::WHS + sizeof(Acc<T>) * (size_t)(8 * npar + 1) * Sh::SST +
-           sizeof(int) * 3 * 8 * npar + sizeof(int16_t) * (64 + 1512);
+    return sizeof(T) * 8 * (size_t)Sh::WHS + sizeof(Acc<T, OWN>) * (size_t)(8 * npar + 1) * Sh::SST +
+           sizeof(int) * 3 * 8 * npar + sizeof(int16_t) * (64 + (OWN ? 0 : 1512));
 }
 // two workgroups per compute unit (160 KB of LDS)
 constexpr size_t LDS_HALF = 81920;
+// ownership mode (FP32 p <= 10): one parent per wavefront; shared mode: 4 or 2 parents
+template <typename T, int P>
+constexpr bool tile_own()
+{
+    return sizeof(T) == 4 && P <= 10;
+}
 template <typename T, int P>
 constexpr int tile_npar()
 {
-    return tile_bytes<T, P>(4) <= LDS_HALF ? 4 : 2;
+    return tile_own<T, P>() ? 4 : (tile_bytes<T, P, false>(4) <= LDS_HALF ? 4 : 2);
 }
 
 }  // namespace hv
 
-// NPAR sibling groups per tile, shared by the four wavefronts (LDS atomics).
+// NPAR sibling groups per tile.  OWN = false: shared by the four wavefronts, which walk each
+// class's entry list 32 translations at a time and accumulate with LDS atomics.  OWN = true
+// (NPAR = 4): wavefront w owns sibling group w and walks the class's rows of 8 (one column
+// per child position), so the 8 translations of a batch hit 8 distinct targets that no other
+// lane touches: accumulation is a plain LDS read-add-write.
 // PF: the next batch's source entries are loaded during the current batch.
-template <typename T, int P, int NPAR, bool PF>
+template <typename T, int P, int NPAR, bool OWN, bool PF>
 __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, int64_t npar,
                                                   const uint64_t *__restrict__ bkey,
                                                   const int32_t *__restrict__ bchild0,
@@ -129,7 +148,8 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
     constexpr int NSLOT = 8 * NPAR;
     constexpr int NENT = 1512;  // schedule entries of one sibling group
     extern __shared__ char smem[];
-    using A = hv::Acc<T>;
+    using A = hv::Acc<T, OWN>;
+    static_assert(!OWN || NPAR == 4, "ownership mode: one sibling group per wavefront");
     T *Wl = (T *)smem;                                // [kind: fwd S, back R][part][parity][WHS]
     A *acc = (A *)(Wl + 8 * Sh::WHS);                 // [NSLOT + 1][SST]: [pot][POS] (last slot absorbs)
     int *slot_xyz = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] packed target coordinates, -1: no box
@@ -171,8 +191,9 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
         slot_xyz[tid] = xyz;
         slot_sys[tid] = sys;
     }
-    for (int i = tid; i < NENT; i += 256) ent[i] = (int16_t)((sch.ent_dir[i] << 3) | sch.ent_c[i]);
-    for (int i = tid; i <= ncls; i += 256) cst[i] = sch.cls_start[i];
+    if (!OWN)
+        for (int i = tid; i < NENT; i += 256) ent[i] = (int16_t)((sch.ent_dir[i] << 3) | sch.ent_c[i]);
+    for (int i = tid; i <= ncls; i += 256) cst[i] = OWN ? sch.row_start[i] : sch.cls_start[i];
     __syncthreads();
     for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
@@ -190,12 +211,20 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
     auto setup = [&](int k, int r0) -> Job {
         Job j{NSLOT, 0, -1};
         if (k >= ncls) return j;
-        const int e0 = cst[k], cnt = cst[k + 1] - e0;
-        const int tr = r0 + wave * 8 + t;
-        if (tr >= NPAR * cnt) return j;
-        const int code = ent[e0 + tr / NPAR];
-        const int dir = code >> 3;
-        const int slot = (tr % NPAR) * 8 + (code & 7);
+        int dir, slot;
+        if (OWN) {
+            // row r0 of class k; column t = child position of the wavefront's sibling group
+            dir = sch.rows[(size_t)(cst[k] + r0) * 8 + t];
+            if (dir < 0) return j;
+            slot = wave * 8 + t;
+        } else {
+            const int e0 = cst[k], cnt = cst[k + 1] - e0;
+            const int tr = r0 + wave * 8 + t;
+            if (tr >= NPAR * cnt) return j;
+            const int code = ent[e0 + tr / NPAR];
+            dir = code >> 3;
+            slot = (tr % NPAR) * 8 + (code & 7);
+        }
         const int xyz = slot_xyz[slot];
         if (xyz < 0) return j;
         const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
@@ -209,8 +238,8 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
         return j;
     };
     auto advance = [&](int &k, int &r0) {
-        r0 += 32;
-        if (k < ncls && r0 >= NPAR * (cst[k + 1] - cst[k])) {
+        r0 += OWN ? 1 : 32;
+        if (k < ncls && r0 >= (OWN ? 1 : NPAR) * (cst[k + 1] - cst[k])) {
             k++;
             r0 = 0;
         }
@@ -391,7 +420,9 @@ __global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, in
                     const T val = x * cz + o * sz;
                     const bool ok = m <= n && !(part && m == 0);
                     const int off = n * n + (part ? n : 0) + m;  // < P^2 also where !ok
-                    atomicAdd((ok ? ap : spare) + off, (A)val);
+                    A *dst = (ok ? ap : spare) + off;
+                    if (OWN) *dst += (A)val;
+                    else atomicAdd(dst, (A)val);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -459,12 +490,13 @@ template <typename T, int P>
 static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
 {
     constexpr int NPAR = hv::tile_npar<T, P>();
-    constexpr size_t shm = hv::tile_bytes<T, P>(NPAR);
+    constexpr bool OWN = hv::tile_own<T, P>();
+    constexpr size_t shm = hv::tile_bytes<T, P, OWN>(NPAR);
     static_assert(shm <= 163840, "tile exceeds the LDS");
     const int64_t stride = 8 * (int64_t)hv::Shape<T, P>::WHS;
     if (hipMalloc(&Pl->whalf, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
     k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->whalf, stride);
-    return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, half_prefetch<T, P>()>,
+    return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, OWN, half_prefetch<T, P>()>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess;
 }
 
@@ -472,11 +504,13 @@ template <typename T, int P>
 static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
 {
     constexpr int NPAR = hv::tile_npar<T, P>();
+    constexpr bool OWN = hv::tile_own<T, P>();
     const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
     const int64_t ntiles = (npar + NPAR - 1) / NPAR;
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
-    k_m2l_half<T, P, NPAR, half_prefetch<T, P>()><<<dim3((unsigned)(per * 8)), dim3(256), hv::tile_bytes<T, P>(NPAR),
+    k_m2l_half<T, P, NPAR, OWN, half_prefetch<T, P>()><<<dim3((unsigned)(per * 8)), dim3(256),
+                                                          hv::tile_bytes<T, P, OWN>(NPAR),
                                                      st>>>(
         level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc,
         (const T *)Pl->whalf, 8 * (int64_t)hv::Shape<T, P>::WHS, sch, Pl->sched_cls_theta);
