@@ -112,16 +112,25 @@ constexpr size_t tile_bytes(int npar)
 }
 // two workgroups per compute unit (160 KB of LDS)
 constexpr size_t LDS_HALF = 81920;
-// ownership mode (FP32 p <= 10): one parent per wavefront; shared mode: 4 or 2 parents
+// ownership mode (FP32 p <= 10): one parent per wavefront; shared mode: the largest of 4, 2, 1
+// parents that leaves room for two workgroups per compute unit
 template <typename T, int P>
 constexpr bool tile_own()
 {
     return sizeof(T) == 4 && P <= 10;
 }
+// wavefronts per SIMD the register allocation aims at: two, except FP64 p = 16, whose 72-double
+// part vectors need the whole register file (its tile leaves room for one workgroup anyway)
+template <typename T, int P>
+constexpr int min_waves()
+{
+    return (sizeof(T) == 8 && P > 12) ? 1 : 2;
+}
 template <typename T, int P>
 constexpr int tile_npar()
 {
-    return tile_own<T, P>() ? 4 : (tile_bytes<T, P, false>(4) <= LDS_HALF ? 4 : 2);
+    return tile_own<T, P>() ? 4
+                            : tile_bytes<T, P, false>(4) <= LDS_HALF ? 4 : (tile_bytes<T, P, false>(2) <= LDS_HALF ? 2 : 1);
 }
 
 }  // namespace hv
@@ -133,7 +142,7 @@ constexpr int tile_npar()
 // lane touches: accumulation is a plain LDS read-add-write.
 // PF: the next batch's source entries are loaded during the current batch.
 template <typename T, int P, int NPAR, bool OWN, bool PF>
-__global__ void __launch_bounds__(256, 2) k_m2l_half(int level, int64_t poff, int64_t npar,
+__global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int level, int64_t poff, int64_t npar,
                                                   const uint64_t *__restrict__ bkey,
                                                   const int32_t *__restrict__ bchild0,
                                                   const int32_t *__restrict__ bnchild,
@@ -520,7 +529,7 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
 
 bool m2l_half_supported(int precision, int p)
 {
-    if (precision == LHF_FP64) return p == 8 || p == 10 || p == 12;
+    if (precision == LHF_FP64) return p == 8 || p == 10 || p == 12 || p == 16;
     return p == 8 || p == 10 || p == 12 || p == 16;
 }
 
@@ -531,6 +540,7 @@ bool whalf_build(lhf_plan *Pl, hipStream_t st)
         case 8: return whalf_build_t<double, 8>(Pl, st);
         case 10: return whalf_build_t<double, 10>(Pl, st);
         case 12: return whalf_build_t<double, 12>(Pl, st);
+        case 16: return whalf_build_t<double, 16>(Pl, st);
         }
     } else {
         switch (Pl->p) {
@@ -550,6 +560,7 @@ void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st)
         case 8: launch_half<double, 8>(Pl, level, st); break;
         case 10: launch_half<double, 10>(Pl, level, st); break;
         case 12: launch_half<double, 12>(Pl, level, st); break;
+        case 16: launch_half<double, 16>(Pl, level, st); break;
         }
     } else {
         switch (Pl->p) {

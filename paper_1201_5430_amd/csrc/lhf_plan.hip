@@ -33,6 +33,12 @@ bool m2l_half_supported(int precision, int p);
 bool whalf_build(lhf_plan *Pl, hipStream_t st);
 bool wmfma_build(lhf_plan *Pl, hipStream_t st);
 
+// a batched M2L kernel exists: the one-lane tile, or the half-vector kernel unless switched off
+static bool batched_m2l_supported(int precision, int p)
+{
+    return m2l_tile_supported(precision, p) || (m2l_half_supported(precision, p) && !getenv("LHF_NO_HALF"));
+}
+
 static thread_local std::string g_err = "no error";
 
 void set_error(const std::string &msg) { g_err = msg; }
@@ -829,7 +835,8 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     if (P->use_tile) {
         lhf_status s = build_schedule(P, cls, (int)theta.size(), st);
         if (s != LHF_OK) return s;
-        if (!wpad_build(P, st)) {
+        const bool tile_ok = m2l_tile_supported(P->precision, p);
+        if (tile_ok && !wpad_build(P, st)) {
             set_error("allocation of the padded rotation table failed");
             return LHF_ERR_HIP;
         }
@@ -839,15 +846,13 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
             LHF_HIP(hipMemsetAsync(P->dmap[l], 0xff, sizeof(int32_t) * cells, st));
             dmap_build(P, l, st);
         }
-        // the matrix-core kernel walks the same schedule; it is the default where it is the
-        // faster of the two (FP32 at p = 16, where the VALU tile holds only two sibling groups);
-        // LHF_MFMA=1 selects it for every supported order, LHF_NO_MFMA=1 never
         // two schedule rows per batch where the ownership tile allows it (FP32 p = 8, 10: 14% faster
         // M2L on the 2^20 cube); LHF_TILE1=1 keeps one row per batch
         P->tile2 = P->precision == LHF_FP32 && (p == 8 || p == 10) && getenv("LHF_TILE1") == nullptr;
-        const bool mfma_default = P->precision == LHF_FP32 && p >= 16;
-        P->use_mfma = m2l_mfma_supported(P->precision, p) && (mfma_default || getenv("LHF_MFMA")) &&
-                      !getenv("LHF_NO_MFMA");
+        // the matrix-core kernel walks the same schedule; it is slower than the VALU kernels at
+        // every order measured (FP32 p = 16 on the 4M ring: 524 ms against 470 ms for the
+        // half-vector kernel), so it runs only on request: LHF_MFMA=1 (LHF_NO_MFMA=1 never)
+        P->use_mfma = m2l_mfma_supported(P->precision, p) && getenv("LHF_MFMA") && !getenv("LHF_NO_MFMA");
         if (P->use_mfma && !wmfma_build(P, st)) {
             set_error("matrix-core M2L set-up failed");
             return LHF_ERR_HIP;
@@ -855,8 +860,12 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
         // the half-vector VALU kernel at the large orders (two lanes per part vector);
         // LHF_NO_HALF=1 keeps the one-lane tile
         const bool half_default = P->precision == LHF_FP64 || p == 12 || p == 16;
-        P->use_half = !P->use_mfma && m2l_half_supported(P->precision, p) && (half_default || getenv("LHF_HALF")) &&
-                      !getenv("LHF_NO_HALF");
+        P->use_half = !P->use_mfma && m2l_half_supported(P->precision, p) &&
+                      (half_default || getenv("LHF_HALF") || !tile_ok) && !getenv("LHF_NO_HALF");
+        if (!P->use_mfma && !P->use_half && !tile_ok) {
+            set_error("internal: no batched M2L kernel for this order");
+            return LHF_ERR_STATE;
+        }
         if (P->use_half && !whalf_build(P, st)) {
             set_error("half-vector M2L set-up failed");
             return LHF_ERR_HIP;
@@ -1053,9 +1062,9 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(hipMalloc(&P->bchild0, sizeof(int32_t) * tot));
     CK(hipMalloc(&P->bnchild, sizeof(int32_t) * tot));
     CK(hipMalloc(&P->vcount, sizeof(int32_t) * tot));
-    // batched M2L: used when the tiled kernel exists for (precision, p) and the dense box maps
+    // batched M2L: used when a batched kernel exists for (precision, p) and the dense box maps
     // stay small (levels <= 8, at most 2^28 cells); then the V-lists are only counted
-    P->use_tile = m2l_tile_supported(P->precision, P->p) && P->depth <= 8 &&
+    P->use_tile = batched_m2l_supported(P->precision, P->p) && P->depth <= 8 &&
                   ((int64_t)ns << (3 * P->depth)) <= ((int64_t)1 << 28) && !getenv("LHF_NO_TILE");
     if (!P->use_tile) {
         CK(hipMalloc(&P->vsrc, sizeof(int32_t) * tot * VMAX));

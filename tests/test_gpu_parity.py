@@ -198,14 +198,12 @@ def test_fp32_two_row_tile(oracle, monkeypatch, p):
     assert _rel(v2, v1) < 2e-6 and _rel(s2, s1) < 2e-6
 
 
-@pytest.mark.parametrize("prec,p", [(0, 8), (0, 10), (0, 12), (1, 8), (1, 10), (1, 12), (1, 16)])
+@pytest.mark.parametrize("prec,p", [(0, 8), (0, 10), (0, 12), (0, 16), (1, 8), (1, 10), (1, 12), (1, 16)])
 def test_half_vector_m2l(oracle, monkeypatch, prec, p):
     # the M2L kernel with each part vector split over two lanes by the parity of m (the default
-    # at FP64 p = 8..12 and FP32 p = 12; FP32 p = 8, 10 on request, FP32 p = 16 when the
-    # matrix-core kernel is switched off): against the oracle on sampled leaves and against the
-    # one-lane tile on every element
-    if p == 16:
-        monkeypatch.setenv("LHF_NO_MFMA", "1")
+    # at FP64 p = 8..16 and FP32 p = 12, 16; FP32 p = 8, 10 on request): against the oracle on
+    # sampled leaves and against the one-lane tile (FP64 p = 16: the generic per-box kernel)
+    # on every element
     monkeypatch.setenv("LHF_HALF", "1")
     rng = np.random.default_rng(110 + p + prec)
     n = 30000
