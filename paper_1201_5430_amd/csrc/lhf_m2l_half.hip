@@ -140,8 +140,8 @@ constexpr int tile_npar()
 // (NPAR = 4): wavefront w owns sibling group w and walks the class's rows of 8 (one column
 // per child position), so the 8 translations of a batch hit 8 distinct targets that no other
 // lane touches: accumulation is a plain LDS read-add-write.
-// PF: the next batch's source entries are loaded during the current batch.
-template <typename T, int P, int NPAR, bool OWN, bool PF>
+// Tiles without any child box leave at once; a wavefront skips batches with no active lane.
+template <typename T, int P, int NPAR, bool OWN>
 __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int level, int64_t poff, int64_t npar,
                                                   const uint64_t *__restrict__ bkey,
                                                   const int32_t *__restrict__ bchild0,
@@ -175,6 +175,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     if (tile >= ntiles) return;
     const int ncls = sch.ncls;
 
+    int has_box = 0;
     if (tid < NSLOT) {
         const int i = tid >> 3, c = tid & 7;
         int box = -1, xyz = -1, sys = 0;
@@ -199,7 +200,10 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         slot_box[tid] = box;
         slot_xyz[tid] = xyz;
         slot_sys[tid] = sys;
+        has_box = box >= 0;
     }
+    // a tile whose parents have no children (leaves of an adaptive tree) has nothing to do
+    if (!__syncthreads_or(has_box)) return;
     if (!OWN)
         for (int i = tid; i < NENT; i += 256) ent[i] = (int16_t)((sch.ent_dir[i] << 3) | sch.ent_c[i]);
     for (int i = tid; i <= ncls; i += 256) cst[i] = OWN ? sch.row_start[i] : sch.cls_start[i];
@@ -272,8 +276,6 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     int k1 = 0, r1 = 0;  // next batch
     advance(k1, r1);
     Job cur = setup(k, r0), nxt = setup(k1, r1);
-    T nv[PF ? NH : 1];
-    if (PF) load_part(cur, nv);
     int staged = -1;
     while (k < ncls) {
         if (k != staged) {
@@ -296,17 +298,13 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
 
         const Job j = cur;
         const bool act = j.src >= 0;
-        T v[NH];
-        if (PF) {
-#pragma unroll
-            for (int q = 0; q < NH; q++) v[q] = nv[q];
-        } else {
-            load_part(j, v);
-        }
+        // look one batch further ahead: its source index now
         int k2 = k1, r2 = r1;
         advance(k2, r2);
         const Job nn = setup(k2, r2);
-        if (PF) load_part(nxt, nv);
+        if (__ballot(act) != 0ull) {  // wavefront-uniform: skip batches with no active lane
+        T v[NH];
+        load_part(j, v);
 
         const int dir = j.dir;
         const int dx = dir % 7 - 3, dy = (dir / 7) % 7 - 3, dz = dir / 49 - 3;
@@ -436,6 +434,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
+        }  // active batch
 
         cur = nxt;
         nxt = nn;
@@ -489,11 +488,6 @@ __global__ void k_whalf(const T *__restrict__ rot, T *__restrict__ wh, int64_t s
 
 namespace {
 
-template <typename T, int P>
-constexpr bool half_prefetch()
-{
-    return false;
-}
 
 template <typename T, int P>
 static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
@@ -505,7 +499,7 @@ static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
     const int64_t stride = 8 * (int64_t)hv::Shape<T, P>::WHS;
     if (hipMalloc(&Pl->whalf, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
     k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->whalf, stride);
-    return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, OWN, half_prefetch<T, P>()>,
+    return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, OWN>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess;
 }
 
@@ -518,7 +512,7 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
     const int64_t ntiles = (npar + NPAR - 1) / NPAR;
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
-    k_m2l_half<T, P, NPAR, OWN, half_prefetch<T, P>()><<<dim3((unsigned)(per * 8)), dim3(256),
+    k_m2l_half<T, P, NPAR, OWN><<<dim3((unsigned)(per * 8)), dim3(256),
                                                           hv::tile_bytes<T, P, OWN>(NPAR),
                                                      st>>>(
         level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc,
