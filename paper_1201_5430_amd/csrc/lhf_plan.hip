@@ -204,8 +204,8 @@ __global__ void k_links(int64_t nbox, int depth, LevelTab lt, const uint64_t *__
     }
 }
 
-// V-list of every box at levels >= 2 (fixed stride VMAX); with vsrc == nullptr only the
-// counts (the batched M2L kernels derive the lists from the dense box maps themselves)
+// V-list of every box at levels >= 2 (fixed stride VMAX), for the generic per-box M2L (the
+// batched kernels derive the lists from the dense box maps themselves)
 __global__ void k_vlist(int64_t off, int64_t nb, int level, const uint64_t *__restrict__ bkey,
                         int32_t *__restrict__ vcount, int32_t *__restrict__ vsrc, int16_t *__restrict__ vdir)
 {
@@ -237,6 +237,34 @@ __global__ void k_vlist(int64_t off, int64_t nb, int level, const uint64_t *__re
                         vdir[b * VMAX + cnt] = (int16_t)((ex + 3) + 7 * (ey + 3) + 49 * (ez + 3));  // t = c_T - c_S
                     }
                     cnt++;
+                }
+    vcount[b] = cnt;
+}
+
+// V-list counts from the dense box map of the level (batched-M2L plans, which build the maps
+// anyway): the same walk as k_vlist with one map lookup per candidate instead of a search
+__global__ void k_vcount_map(int64_t off, int64_t nb, int level, const uint64_t *__restrict__ bkey,
+                             const int32_t *__restrict__ dmap, int32_t *__restrict__ vcount)
+{
+    const int64_t bl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (bl >= nb) return;
+    const int64_t b = off + bl;
+    const uint64_t kfull = bkey[b];
+    const uint64_t sys = kfull >> (3 * level), k = kfull & ((1ull << (3 * level)) - 1);
+    const int ix = (int)compact3(k), iy = (int)compact3(k >> 1), iz = (int)compact3(k >> 2);
+    const int px = ix >> 1, py = iy >> 1, pz = iz >> 1;
+    const int side = 1 << level;
+    const int32_t *map = dmap + (size_t)sys * side * side * side;
+    int cnt = 0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++)
+                for (int c = 0; c < 8; c++) {
+                    const int cx = 2 * (px + dx) + (c & 1), cy = 2 * (py + dy) + ((c >> 1) & 1),
+                              cz = 2 * (pz + dz) + ((c >> 2) & 1);
+                    if (cx < 0 || cy < 0 || cz < 0 || cx >= side || cy >= side || cz >= side) continue;
+                    if (abs(ix - cx) <= 1 && abs(iy - cy) <= 1 && abs(iz - cz) <= 1) continue;
+                    cnt += map[((size_t)cz * side + cy) * side + cx] >= 0;
                 }
     vcount[b] = cnt;
 }
@@ -1090,10 +1118,12 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
         }
     }
     hipLaunchKernelGGL(k_links, grid(tot), dim3(tpb), 0, st, tot, d, lt, P->bkey, P->bparent, P->bchild0, P->bnchild);
-    for (int l = 2; l <= d; l++)
-        if (kept[l] > 0)
-            hipLaunchKernelGGL(k_vlist, grid(kept[l]), dim3(tpb), 0, st, lt.off[l], kept[l], l, P->bkey, P->vcount,
-                               P->vsrc, P->vdir);
+    // V-lists: filled for the generic M2L; counted from the box maps after build_tables otherwise
+    if (!P->use_tile)
+        for (int l = 2; l <= d; l++)
+            if (kept[l] > 0)
+                hipLaunchKernelGGL(k_vlist, grid(kept[l]), dim3(tpb), 0, st, lt.off[l], kept[l], l, P->bkey,
+                                   P->vcount, P->vsrc, P->vdir);
     if (!adaptive) {
         CK(hipMalloc(&P->ulist, sizeof(int32_t) * hnb[d] * 27));
         hipLaunchKernelGGL(k_ulist, grid(hnb[d]), dim3(tpb), 0, st, lt.off[d], hnb[d], d, P->bkey, P->bcount,
@@ -1134,13 +1164,19 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
         hipLaunchKernelGGL(k_adlist<1>, grid(nl), dim3(tpb), 0, st, nl, d, lt, P->leaves, P->blev, P->bkey,
                            P->bcount, P->bchild0, P->bnchild, P->nl_start, P->nl_ent, dcnt, P->dflag);
     }
-    hipLaunchKernelGGL(k_sum_i32, dim3(256), dim3(256), 0, st, tot, P->vcount, dcnt);
     CK(hipGetLastError());
     lhf_status ts = build_tables<T>(P, st);
     if (ts != LHF_OK) {
         cleanup();
         return ts;
     }
+    if (P->use_tile)
+        for (int l = 2; l <= d; l++)
+            if (kept[l] > 0)
+                hipLaunchKernelGGL(k_vcount_map, grid(kept[l]), dim3(tpb), 0, st, lt.off[l], kept[l], l, P->bkey,
+                                   P->dmap[l], P->vcount);
+    hipLaunchKernelGGL(k_sum_i32, dim3(256), dim3(256), 0, st, tot, P->vcount, dcnt);
+    CK(hipGetLastError());
     int64_t hc[4];
     CK(hipMemcpyAsync(hc, dcnt, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(hflag, P->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
