@@ -23,6 +23,8 @@ namespace lhf {
 void m2l_tile_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_mfma_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
+void m2m_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
+void l2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 
 constexpr int WAVE = 64;
 constexpr int NRMAX = (2 * MAXP * MAXP + WAVE - 1) / WAVE;  // accumulator rows per lane
@@ -866,8 +868,10 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         size_t sh_rcr = sizeof(T) * (4 * P2 + 2 * ZS + 2 * p + 2);
         for (int l = d - 1; l >= 2; l--) {
             if (P->lev[l].nb == 0) continue;
-            hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, P->lev[l].off,
-                               P->bchild0, P->bnchild, P->bkey, M, rot, zph, P->dir_theta);
+            if (P->use_mmhalf) m2m_half_launch(P, l, st);
+            else
+                hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, P->lev[l].off,
+                                   P->bchild0, P->bnchild, P->bkey, M, rot, zph, P->dir_theta);
         }
         mark(3);
         for (int l = 2; l <= d; l++) {
@@ -877,9 +881,12 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
                 continue;
             }
             if (P->use_tile) {
-                hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 0,
-                                   P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M, Lc,
-                                   rot, zph, P->dir_theta, coax);
+                // L2L from the parents (zeros at level 2), then the batched M2L adds into it
+                if (P->use_mmhalf) l2l_half_launch(P, l, st);
+                else
+                    hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 0,
+                                       P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M,
+                                       Lc, rot, zph, P->dir_theta, coax);
                 mark(7 + 2 * l);
                 if (P->use_mfma) m2l_mfma_launch(P, l, st);
                 else if (P->use_half) m2l_half_launch(P, l, st);

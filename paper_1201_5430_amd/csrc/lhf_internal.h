@@ -134,6 +134,8 @@ struct lhf_plan {
     bool use_mfma = false;               // matrix-core M2L (same schedule and box maps)
     bool use_half = false;               // VALU M2L with each vector split over two lanes (large p)
     void *whalf = nullptr;               // its rotation tables
+    bool use_mmhalf = false;             // batched M2M and L2L in the same layout
+    void *wmm = nullptr, *wll = nullptr; // their rotation tables (S basis, R basis)
     bool tile2 = false;                  // VALU tile with two schedule rows per batch (FP32 p = 8, 10)
     void *wmfma = nullptr;               // per-class rotation blocks in MFMA A-operand lane order
 

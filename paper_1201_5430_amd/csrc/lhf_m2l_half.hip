@@ -19,6 +19,8 @@
 // Slots of odd lanes whose m exceeds n (even n) stay zero and are never accumulated.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "lhf_internal.h"
 #include "lhf_m2l_common.h"
 
@@ -457,13 +459,13 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
 // row j of o is m' = 2j + h, row j of t is m' = 2j + 1 - h, column i is m = 2i + h; the Im
 // block (m, m' >= 1) is embedded with zeros at m = 0 and m' = 0; zero where m or m' > n.
 template <typename T, int P>
-__global__ void k_whalf(const T *__restrict__ rot, T *__restrict__ wh, int64_t stride)
+__global__ void k_whalf(const T *__restrict__ rot, T *__restrict__ wh, int64_t stride, int kind_f, int kind_b)
 {
     using Sh = hv::Shape<T, P>;
     const int th = blockIdx.x;
     const int RS = rot_set_size(P);
-    const T *Rf = rot + ((size_t)th * ROT_NKIND + ROT_S_FWD) * RS;
-    const T *Rb = rot + ((size_t)th * ROT_NKIND + ROT_R_BACK) * RS;
+    const T *Rf = rot + ((size_t)th * ROT_NKIND + kind_f) * RS;
+    const T *Rb = rot + ((size_t)th * ROT_NKIND + kind_b) * RS;
     for (int idx = threadIdx.x; idx < stride; idx += blockDim.x) {
         T val = (T)0;
         const int tb = idx / Sh::WHS, e = idx % Sh::WHS;
@@ -486,8 +488,267 @@ __global__ void k_whalf(const T *__restrict__ rot, T *__restrict__ wh, int64_t s
     }
 }
 
-namespace {
+// ---------------------------------------------------------------------------
+// M2M and L2L in the same half-vector layout.  One wavefront per parent box; its 64 lanes are
+//   lane = 8 c + 4 pot + 2 part + h      (c: octant of the child)
+// so the eight child translations of the parent run side by side.  Their directions use two
+// polar-angle classes (the z bit of the octant), staged once per workgroup.  Coaxial shift
+// (S|S for M2M, R|R for L2L) and conversion (S for M2M, R for L2L, eq. rcr1 and its S form)
+// act column by column inside the lane, as in the M2L kernel.  M2M sums the eight results over
+// c (lane butterfly) into the parent's multipole; L2L writes each child's local expansion.
+// KIND 0 = M2M (child -> parent), 2 = L2L (parent -> child); the coefficients are those of the
+// generic per-box kernels: cf_k = (-tau_p)^k / k!, tau_p = sqrt(3)/4, conversion tau sqrt(3)/4
+// (M2M) and sqrt(3)/2 (L2L).
+// ---------------------------------------------------------------------------
+namespace hv {
+// class stride in LDS: eight tables plus 64 bytes, so the two classes' tables read together
+// fall in different banks
+template <typename T, int P>
+constexpr int mm_cstride()
+{
+    return 8 * Shape<T, P>::WHS + 64 / (int)sizeof(T);
+}
+template <typename T, int P>
+constexpr size_t mm_bytes()
+{
+    return sizeof(T) * 2 * (size_t)mm_cstride<T, P>();
+}
+__host__ __device__ constexpr double taup() { return 0.4330127018922193; }  // sqrt(3)/4
+// (-tau_p)^k / k! as a compile-time constant
+__host__ __device__ constexpr double mm_cf(int k)
+{
+    double c = 1.0;
+    for (int i = 1; i <= k; i++) c *= -taup() / (double)i;
+    return c;
+}
+}  // namespace hv
 
+// the value of lane ^ 32 (v_permlane32_swap of the value with itself: the two results sum to
+// the lane's value plus its partner's)
+__device__ inline float xor32_sum(float v)
+{
+    const unsigned u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline double xor32_sum(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)(u & 0xffffffffull), hi = (unsigned)(u >> 32);
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double a = __longlong_as_double((long long)(((unsigned long long)rh[0] << 32) | rl[0]));
+    const double b = __longlong_as_double((long long)(((unsigned long long)rh[1] << 32) | rl[1]));
+    return a + b;
+}
+
+template <typename T, int P, int KIND>
+__global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_mm_half(int64_t poff, int64_t npar,
+                                                                        const int32_t *__restrict__ bchild0,
+                                                                        const int32_t *__restrict__ bnchild,
+                                                                        const uint64_t *__restrict__ bkey,
+                                                                        const T *__restrict__ src_exp,
+                                                                        T *__restrict__ dst_exp,
+                                                                        const T *__restrict__ wtab, int64_t wstride,
+                                                                        const int16_t *__restrict__ dir_theta,
+                                                                        const T *__restrict__ zph)
+{
+    static_assert(KIND == 0 || KIND == 2, "M2M or L2L");
+    using Sh = hv::Shape<T, P>;
+    using hv::hoff;
+    using hv::S;
+    constexpr int P2 = Sh::P2, NH = Sh::NH, CST = hv::mm_cstride<T, P>();
+    constexpr int DIR0 = NDIR_M2L + (KIND == 0 ? 0 : 8);  // child->parent (M2M), parent->child (L2L)
+    extern __shared__ char smem[];
+    T *Wl = (T *)smem;  // [class: z bit 0, 1][kind: fwd, back][part][parity][WHS]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int k = 0; k < 2; k++) {
+        const int cls = dir_theta[DIR0 + 4 * k];
+        const uint4 *s4 = (const uint4 *)(wtab + (size_t)cls * wstride);
+        uint4 *d4 = (uint4 *)(Wl + k * CST);
+        constexpr int N16 = (int)(8 * Sh::WHS * sizeof(T) / 16);
+        for (int i = tid; i < N16; i += 256) d4[i] = s4[i];
+    }
+    __syncthreads();
+
+    const int c = lane >> 3, pot = (lane >> 2) & 1, part = (lane >> 1) & 1, h = lane & 1;
+    const int dir = DIR0 + c;
+
+    for (int64_t q = (int64_t)blockIdx.x * 4 + wave; q < npar; q += (int64_t)gridDim.x * 4) {
+        // opaque per-parent offsets: keep the compiler from hoisting the loop-invariant rotation
+        // entries and phases out of the parent loop (which would exhaust the register file)
+        int wo = (c >> 2) * CST + (part * 2 + h) * Sh::WHS, zo = dir * 2 * P + h, hh = h, pp = part, po = pot;
+        asm volatile("" : "+v"(wo), "+v"(zo), "+v"(hh), "+v"(pp), "+v"(po));
+        const T *Wf = Wl + wo;
+        const T *Wb = Wf + 4 * Sh::WHS;
+        const T *zc = zph + zo, *zs = zc + P;  // cos, sin of m phi at m = 2j + h: zc[2j], zs[2j]
+        const int64_t b = poff + q;
+        const int nc = bnchild[b];
+        if (nc == 0) continue;  // M2M: a leaf keeps its own multipole; L2L: nothing below
+        const int c0 = bchild0[b];
+        int cb = -1;
+        for (int k = 0; k < nc; k++)
+            if ((int)(bkey[c0 + k] & 7u) == c) cb = c0 + k;
+        const bool act = cb >= 0;
+        const T *sp = src_exp + (size_t)(KIND == 0 ? (act ? cb : 0) : b) * 2 * P2 + po * P2;
+        T v[NH];
+#pragma unroll
+        for (int n = 0; n < P; n++)
+#pragma unroll
+            for (int jj = 0; jj < S(n); jj++) {
+                const int m = 2 * jj + hh;
+                const bool ok = act && m <= n && !(pp && m == 0);
+                const T x = sp[ok ? n * n + pp * n + m : 0];
+                v[hoff(n) + jj] = ok ? x : (T)0;
+            }
+        // 1. rotate about z by +phi: Re' = re c - im s, Im' = im c + re s
+        {
+            const T sgn = pp ? (T)1 : (T)-1;
+#pragma unroll
+            for (int jj = 0; jj < P / 2; jj++) {
+                const T cj = zc[2 * jj], sj = zs[2 * jj] * sgn;
+#pragma unroll
+                for (int n = 2 * jj; n < P; n++) {
+                    const T x = v[hoff(n) + jj];
+                    const T o = dpp_f<DPP_XOR2>(x);
+                    v[hoff(n) + jj] = x * cj + o * sj;
+                }
+            }
+        }
+        auto rotate_y = [&](const T *W) __attribute__((always_inline)) {
+#pragma unroll
+            for (int n = 0; n < P; n++) {
+                const T *Wn = W + hv::woff<T>(n);
+                constexpr int SM = P / 2 + 1;
+                T o[SM], tt[SM];
+#pragma unroll
+                for (int jj = 0; jj < S(n); jj++) {
+                    o[jj] = hv::dotw<T>(Wn + jj * hv::RL<T>(n), &v[hoff(n)], S(n));
+                    tt[jj] = hv::dotw<T>(Wn + (S(n) + jj) * hv::RL<T>(n), &v[hoff(n)], S(n));
+                    asm volatile("" : "+v"(o[jj]), "+v"(tt[jj]));
+                }
+#pragma unroll
+                for (int jj = 0; jj < S(n); jj++) v[hoff(n) + jj] = o[jj] + dpp_f<DPP_XOR1>(tt[jj]);
+            }
+        };
+        rotate_y(Wf);
+        // 3+4. per column m = 2c' + h: coaxial shift, then the conversion
+        {
+            const T wphi = po ? (T)0 : (T)1, wchi = po ? (T)1 : (T)0;
+            const T keep0 = hh ? (T)0 : (T)1;  // slot (n = 2c', c') holds m = 2c' + h: empty on odd lanes
+#pragma unroll
+            for (int cc = 0; cc < P / 2; cc++) {
+                const int n0 = 2 * cc;
+                const T mval = (T)(2 * cc + hh);
+                T in[P];
+#pragma unroll
+                for (int n2 = n0; n2 < P; n2++) in[n2] = v[hoff(n2) + cc];
+                T out[P];
+                if (KIND == 0) {
+                    // (S|S): out_n = sum_{n' = m}^{n} cf_{n-n'} (1/2 [phi] | 1 [chi]) 2^-n' in_n'
+                    const T s0 = po ? (T)1 : (T)0.5;
+#pragma unroll
+                    for (int n2 = n0; n2 < P; n2++) in[n2] *= (T)(1.0 / (double)(1ull << n2));
+#pragma unroll
+                    for (int n = n0; n < P; n++) {
+                        T a = 0;
+#pragma unroll
+                        for (int n2 = n0; n2 <= n; n2++) a += (T)hv::mm_cf(n - n2) * in[n2];
+                        out[n] = a * s0;
+                    }
+                } else {
+                    // (R|R): out_n = (1 [phi] | 1/2 [chi]) 2^-n sum_{n' = n}^{p-1} cf_{n'-n} in_n'
+                    const T s0 = po ? (T)0.5 : (T)1;
+#pragma unroll
+                    for (int n = n0; n < P; n++) {
+                        T a = 0;
+#pragma unroll
+                        for (int n2 = n; n2 < P; n2++) a += (T)hv::mm_cf(n2 - n) * in[n2];
+                        out[n] = a * (s0 * (T)(1.0 / (double)(1ull << n)));
+                    }
+                }
+#pragma unroll
+                for (int n = n0; n < P; n++) {
+                    const T other = swz_xor<6>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
+                    T val;
+                    if (KIND == 0) {
+                        // S-conversion: phi~ = phi - i tau m/(n+1) chi,  chi~_n = chi_n + tau/n chi_{n-1}
+                        const T tau = (T)hv::taup();
+                        const T fphi = tau * mval * (T)(1.0 / (double)(n + 1)) * (pp ? (T)-1 : (T)1) * wphi;
+                        const T prev = (n > n0) ? out[n - 1] : (T)0;
+                        const T fchi = (n > 0) ? tau * (T)(1.0 / (double)n) * wchi : (T)0;
+                        val = out[n] + fphi * other + fchi * prev;
+                    } else {
+                        // R-conversion: phi~ = phi + i tau m/n chi,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
+                        const T tau = (T)(2.0 * hv::taup());
+                        const T fphi =
+                            (n > 0) ? tau * mval * (T)(1.0 / (double)n) * (pp ? (T)1 : (T)-1) * wphi : (T)0;
+                        const T next = (n + 1 < P) ? out[n + 1] : (T)0;
+                        const T fchi = -tau * (T)(1.0 / (double)(n + 1)) * wchi;
+                        val = out[n] + fphi * other + fchi * next;
+                    }
+                    if (n == n0) val *= keep0;
+                    v[hoff(n) + cc] = val;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        rotate_y(Wb);
+        // 6. rotate about z by -phi: Re' = re c + im s, Im' = im c - re s
+        {
+            const T sgn = pp ? (T)-1 : (T)1;
+#pragma unroll
+            for (int jj = 0; jj < P / 2; jj++) {
+                const T cj = zc[2 * jj], sj = zs[2 * jj] * sgn;
+#pragma unroll
+                for (int n = 2 * jj; n < P; n++) {
+                    const T x = v[hoff(n) + jj];
+                    const T o = dpp_f<DPP_XOR2>(x);
+                    v[hoff(n) + jj] = x * cj + o * sj;
+                }
+            }
+        }
+        if (KIND == 0) {
+            // sum over the eight children: lane butterfly over the octant bits (lane ^ 8, 16, 32)
+#pragma unroll
+            for (int q2 = 0; q2 < NH; q2++) {
+                T x = v[q2];
+                x += swz_xor<8>(x);
+                x += swz_xor<16>(x);
+                v[q2] = xor32_sum(x);
+            }
+            if (c == 0) {
+                T *dp = dst_exp + (size_t)b * 2 * P2 + po * P2;
+#pragma unroll
+                for (int n = 0; n < P; n++)
+#pragma unroll
+                    for (int jj = 0; jj < S(n); jj++) {
+                        const int m = 2 * jj + hh;
+                        if (m <= n && !(pp && m == 0)) dp[n * n + pp * n + m] = v[hoff(n) + jj];
+                    }
+            }
+        } else if (act) {
+            T *dp = dst_exp + (size_t)cb * 2 * P2 + po * P2;
+#pragma unroll
+            for (int n = 0; n < P; n++)
+#pragma unroll
+                for (int jj = 0; jj < S(n); jj++) {
+                    const int m = 2 * jj + hh;
+                    if (m <= n && !(pp && m == 0)) dp[n * n + pp * n + m] = v[hoff(n) + jj];
+                }
+        }
+    }
+}
+
+// zero local expansions (level 2 has no parent expansion to shift)
+template <typename T>
+__global__ void k_zero_exp(int64_t count, T *__restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = (T)0;
+}
+
+namespace {
 
 template <typename T, int P>
 static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
@@ -498,7 +759,8 @@ static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
     static_assert(shm <= 163840, "tile exceeds the LDS");
     const int64_t stride = 8 * (int64_t)hv::Shape<T, P>::WHS;
     if (hipMalloc(&Pl->whalf, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
-    k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->whalf, stride);
+    k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->whalf, stride,
+                                                                      ROT_S_FWD, ROT_R_BACK);
     return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, OWN>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess;
 }
@@ -519,7 +781,104 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
         (const T *)Pl->whalf, 8 * (int64_t)hv::Shape<T, P>::WHS, sch, Pl->sched_cls_theta);
 }
 
+// rotation tables of the M2M (S basis both ways) and L2L (R basis both ways) shifts
+template <typename T, int P>
+static bool mmhalf_build_t(lhf_plan *Pl, hipStream_t st)
+{
+    const int64_t stride = 8 * (int64_t)hv::Shape<T, P>::WHS;
+    if (hipMalloc(&Pl->wmm, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
+    if (hipMalloc(&Pl->wll, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
+    k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->wmm, stride,
+                                                                      ROT_S_FWD, ROT_S_BACK);
+    k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->wll, stride,
+                                                                      ROT_R_FWD, ROT_R_BACK);
+    constexpr size_t shm = hv::mm_bytes<T, P>();
+    static_assert(shm <= 163840, "rotation tables exceed the LDS");
+    return hipFuncSetAttribute((const void *)k_mm_half<T, P, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)shm) == hipSuccess &&
+           hipFuncSetAttribute((const void *)k_mm_half<T, P, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)shm) == hipSuccess;
+}
+
+// KIND 0: M2M into the parents of level l; KIND 2: L2L from level l - 1 into level l (l >= 3)
+template <typename T, int P, int KIND>
+static void launch_mm(const lhf_plan *Pl, int l, hipStream_t st)
+{
+    const int lp = KIND == 0 ? l : l - 1;
+    const int64_t poff = Pl->lev[lp].off, npar = Pl->lev[lp].nb;
+    if (npar == 0) return;
+    const unsigned grid = (unsigned)std::min<int64_t>((npar + 3) / 4, 2048);
+    const T *src = (const T *)(KIND == 0 ? Pl->M : Pl->Lc);
+    T *dst = (T *)(KIND == 0 ? Pl->M : Pl->Lc);
+    k_mm_half<T, P, KIND><<<dim3(grid), dim3(256), hv::mm_bytes<T, P>(), st>>>(
+        poff, npar, Pl->bchild0, Pl->bnchild, Pl->bkey, src, dst, (const T *)(KIND == 0 ? Pl->wmm : Pl->wll),
+        8 * (int64_t)hv::Shape<T, P>::WHS, Pl->dir_theta, (const T *)Pl->zph);
+}
+
+template <typename T>
+static void zero_level(const lhf_plan *Pl, int l, hipStream_t st)
+{
+    const int64_t cnt = Pl->lev[l].nb * 2 * (int64_t)Pl->p * Pl->p;
+    if (cnt == 0) return;
+    k_zero_exp<T><<<dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st>>>(
+        cnt, (T *)Pl->Lc + Pl->lev[l].off * 2 * (int64_t)Pl->p * Pl->p);
+}
+
 }  // namespace
+
+bool mmhalf_build(lhf_plan *Pl, hipStream_t st)
+{
+    if (Pl->precision == LHF_FP64) {
+        switch (Pl->p) {
+        case 8: return mmhalf_build_t<double, 8>(Pl, st);
+        case 10: return mmhalf_build_t<double, 10>(Pl, st);
+        case 12: return mmhalf_build_t<double, 12>(Pl, st);
+        case 16: return mmhalf_build_t<double, 16>(Pl, st);
+        }
+    } else {
+        switch (Pl->p) {
+        case 8: return mmhalf_build_t<float, 8>(Pl, st);
+        case 10: return mmhalf_build_t<float, 10>(Pl, st);
+        case 12: return mmhalf_build_t<float, 12>(Pl, st);
+        case 16: return mmhalf_build_t<float, 16>(Pl, st);
+        }
+    }
+    return false;
+}
+
+template <int KIND>
+static void mm_dispatch(const lhf_plan *Pl, int l, hipStream_t st)
+{
+    if (Pl->precision == LHF_FP64) {
+        switch (Pl->p) {
+        case 8: launch_mm<double, 8, KIND>(Pl, l, st); break;
+        case 10: launch_mm<double, 10, KIND>(Pl, l, st); break;
+        case 12: launch_mm<double, 12, KIND>(Pl, l, st); break;
+        case 16: launch_mm<double, 16, KIND>(Pl, l, st); break;
+        }
+    } else {
+        switch (Pl->p) {
+        case 8: launch_mm<float, 8, KIND>(Pl, l, st); break;
+        case 10: launch_mm<float, 10, KIND>(Pl, l, st); break;
+        case 12: launch_mm<float, 12, KIND>(Pl, l, st); break;
+        case 16: launch_mm<float, 16, KIND>(Pl, l, st); break;
+        }
+    }
+}
+
+// M2M into the boxes of level l from their children
+void m2m_half_launch(const lhf_plan *Pl, int l, hipStream_t st) { mm_dispatch<0>(Pl, l, st); }
+
+// L2L into the boxes of level l from their parents; level 2 starts from zero
+void l2l_half_launch(const lhf_plan *Pl, int l, hipStream_t st)
+{
+    if (l <= 2) {
+        if (Pl->precision == LHF_FP64) zero_level<double>(Pl, l, st);
+        else zero_level<float>(Pl, l, st);
+        return;
+    }
+    mm_dispatch<2>(Pl, l, st);
+}
 
 bool m2l_half_supported(int precision, int p)
 {

@@ -31,6 +31,7 @@ bool wpad_build(lhf_plan *Pl, hipStream_t st);
 bool m2l_mfma_supported(int precision, int p);
 bool m2l_half_supported(int precision, int p);
 bool whalf_build(lhf_plan *Pl, hipStream_t st);
+bool mmhalf_build(lhf_plan *Pl, hipStream_t st);
 bool wmfma_build(lhf_plan *Pl, hipStream_t st);
 
 // a batched M2L kernel exists: the one-lane tile, or the half-vector kernel unless switched off
@@ -859,6 +860,13 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     hipLaunchKernelGGL(k_zph<T>, dim3((NDIR * p + 255) / 256), dim3(256), 0, st, p, (T *)P->zph);
     hipLaunchKernelGGL(k_coax<T>, dim3(1), dim3(32), 0, st, p, (T *)P->coax);
     LHF_HIP(hipGetLastError());
+    // batched M2M and L2L (two lanes per part vector) at the orders the half-vector kernels
+    // cover; LHF_NO_MMHALF=1 keeps the generic per-box shifts
+    P->use_mmhalf = m2l_half_supported(P->precision, p) && !getenv("LHF_NO_MMHALF");
+    if (P->use_mmhalf && !mmhalf_build(P, st)) {
+        set_error("batched M2M/L2L set-up failed");
+        return LHF_ERR_HIP;
+    }
     // batched M2L (decided with the tree): schedule, padded rotation blocks, dense box maps
     if (P->use_tile) {
         lhf_status s = build_schedule(P, cls, (int)theta.size(), st);
@@ -925,7 +933,7 @@ static void free_plan(lhf_plan *P)
     for (int l = 0; l <= MAXDEPTH; l++)
         if (P->dmap[l]) (void)hipFree(P->dmap[l]);
     void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta, P->wpad, P->sched_row_start,
-                  P->sched_rows, P->wmfma, P->whalf};
+                  P->sched_rows, P->wmfma, P->whalf, P->wmm, P->wll};
     for (void *b : sb)
         if (b) (void)hipFree(b);
     delete P;
