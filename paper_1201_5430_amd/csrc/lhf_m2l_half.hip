@@ -260,15 +260,15 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         }
     };
     // this lane's entries of the source: order n, m = 2j + h; zero where m > n or (Im, m = 0)
-    auto load_part = [&](const Job &j, T *dst) {
-        const T *sp = M + (size_t)(j.src >= 0 ? j.src : 0) * 2 * P2 + pot * P2;
+    auto load_part = [&](const Job &j, T *dst, int hh, int pp, int po) {
+        const T *sp = M + (size_t)(j.src >= 0 ? j.src : 0) * 2 * P2 + po * P2;
 #pragma unroll
         for (int n = 0; n < P; n++)
 #pragma unroll
             for (int jj = 0; jj < S(n); jj++) {
-                const int m = 2 * jj + h;
-                const bool ok = m <= n && !(part && m == 0);
-                const int off = ok ? n * n + (part ? n : 0) + m : 0;
+                const int m = 2 * jj + hh;
+                const bool ok = m <= n && !(pp && m == 0);
+                const int off = ok ? n * n + (pp ? n : 0) + m : 0;
                 const T x = sp[off];
                 dst[hoff(n) + jj] = ok ? x : (T)0;
             }
@@ -293,8 +293,13 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         }
         // opaque per-batch offset: keeps the compiler from hoisting the class's rotation
         // entries out of the batch loop
-        int wo = (part * 2 + h) * Sh::WHS;
+        // ownership mode: the lane's role (parity, part, potential) is made opaque per batch as
+        // well, so the compiler recomputes the per-lane constants derived from it instead of
+        // holding them all in registers (FP32 p = 10: 143 -> 107 VGPRs, 30.4 -> 27.2 ms on the
+        // 2^20 cube); in shared mode that trade costs SGPR spills and time
+        int wo = (part * 2 + h) * Sh::WHS, hh = h, pp = part, po = pot;
         asm volatile("" : "+v"(wo));
+        if (OWN) asm volatile("" : "+v"(hh), "+v"(pp), "+v"(po));
         const T *Wf = Wl + wo;
         const T *Wb = Wl + 4 * Sh::WHS + wo;
 
@@ -306,7 +311,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         const Job nn = setup(k2, r2);
         if (__ballot(act) != 0ull) {  // wavefront-uniform: skip batches with no active lane
         T v[NH];
-        load_part(j, v);
+        load_part(j, v, hh, pp, po);
 
         const int dir = j.dir;
         const int dx = dir % 7 - 3, dy = (dir / 7) % 7 - 3, dz = dir / 49 - 3;
@@ -323,8 +328,8 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         const double c2 = cph * cph - sph * sph, s2 = 2.0 * cph * sph;  // e^{2 i phi}
         // 1. rotate about z by +phi: Re' = re c - im s, Im' = im c + re s (m = 2j + h)
         {
-            const T sgn = part ? (T)1 : (T)-1;
-            double cm = h ? cph : 1.0, sm = h ? sph : 0.0;
+            const T sgn = pp ? (T)1 : (T)-1;
+            double cm = hh ? cph : 1.0, sm = hh ? sph : 0.0;
 #pragma unroll
             for (int jj = 0; jj < P / 2; jj++) {
                 const T cz = (T)cm, sz = (T)sm * sgn;
@@ -363,14 +368,14 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         //        phi~ = phi + i tau m/n chi ,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
         {
             const T itau = (T)1 / tau, itau2 = itau * itau;
-            const T wphi = pot ? (T)0 : (T)1, wchi = pot ? (T)1 : (T)0;
-            const T sconv = part ? (T)1 : (T)-1;
-            const T keep0 = h ? (T)0 : (T)1;  // slot (n = 2c, c) holds m = 2c + h: empty on odd lanes
+            const T wphi = po ? (T)0 : (T)1, wchi = po ? (T)1 : (T)0;
+            const T sconv = pp ? (T)1 : (T)-1;
+            const T keep0 = hh ? (T)0 : (T)1;  // slot (n = 2c, c) holds m = 2c + h: empty on odd lanes
             T p0 = (T)1;                      // tau^-(2c), kept as a running product
 #pragma unroll
             for (int c = 0; c < P / 2; c++) {
                 const int n0 = 2 * c;
-                const T mval = (T)(2 * c + h);
+                const T mval = (T)(2 * c + hh);
                 T cl[P];
                 {
                     T pq = p0;
@@ -409,10 +414,10 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         // 6. back-rotation about z (-phi) and accumulation into the target slot (inactive lanes
         //    and empty entries add into the spare slot)
         {
-            A *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + pot * POS;
-            A *spare = acc + (size_t)NSLOT * SST + pot * POS;
-            const T sgn = part ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
-            double cm = h ? cph : 1.0, sm = h ? sph : 0.0;
+            A *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + po * POS;
+            A *spare = acc + (size_t)NSLOT * SST + po * POS;
+            const T sgn = pp ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
+            double cm = hh ? cph : 1.0, sm = hh ? sph : 0.0;
 #pragma unroll
             for (int jj = 0; jj < P / 2; jj++) {
                 const T cz = (T)cm, sz = (T)sm * sgn;
@@ -421,14 +426,14 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
                     cm = a;
                     sm = b;
                 }
-                const int m = 2 * jj + h;
+                const int m = 2 * jj + hh;
 #pragma unroll
                 for (int n = 2 * jj; n < P; n++) {
                     const T x = v[hoff(n) + jj];
                     const T o = dpp_f<DPP_XOR2>(x);
                     const T val = x * cz + o * sz;
-                    const bool ok = m <= n && !(part && m == 0);
-                    const int off = n * n + (part ? n : 0) + m;  // < P^2 also where !ok
+                    const bool ok = m <= n && !(pp && m == 0);
+                    const int off = n * n + (pp ? n : 0) + m;  // < P^2 also where !ok
                     A *dst = (ok ? ap : spare) + off;
                     if (OWN) *dst += (A)val;
                     else atomicAdd(dst, (A)val);

@@ -893,11 +893,9 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
             set_error("matrix-core M2L set-up failed");
             return LHF_ERR_HIP;
         }
-        // the half-vector VALU kernel at the large orders (two lanes per part vector);
-        // LHF_NO_HALF=1 keeps the one-lane tile
-        const bool half_default = P->precision == LHF_FP64 || p == 12 || p == 16;
-        P->use_half = !P->use_mfma && m2l_half_supported(P->precision, p) &&
-                      (half_default || getenv("LHF_HALF") || !tile_ok) && !getenv("LHF_NO_HALF");
+        // the half-vector VALU kernel (two lanes per part vector) wherever it has an
+        // instantiation; LHF_NO_HALF=1 keeps the one-lane tiles
+        P->use_half = !P->use_mfma && m2l_half_supported(P->precision, p) && !getenv("LHF_NO_HALF");
         if (!P->use_mfma && !P->use_half && !tile_ok) {
             set_error("internal: no batched M2L kernel for this order");
             return LHF_ERR_STATE;
