@@ -46,7 +46,7 @@ def f_m2l(p: int) -> int:
 
 
 # the M2L kernel the library runs for the cube workloads (FP64 p = 12, FP32 p = 10)
-M2L_KERNEL = {0: "k_m2l_half", 1: "k_m2l_tile2"}  # by lhf_precision (FP64 = 0, FP32 = 1)
+M2L_KERNEL = {0: "k_m2l_half", 1: "k_m2l_half"}  # by lhf_precision (FP64 = 0, FP32 = 1)
 
 
 def log(msg):

@@ -473,31 +473,30 @@ __global__ void __launch_bounds__(WAVE) k_down(int p, int level, int do_m2l, int
 // u_z = -V^m (all at order n+1).  Each lane evaluates one element:
 //   F(xhat) = sum_n (-1)^n [F_n^0 Rt_n^0 + 2 Re sum_{m>0} F_n^m Rt_n^m].
 // ---------------------------------------------------------------------------
+// Four leaves per 64-lane workgroup, 16 lanes each (leaves hold a few elements at the depths
+// that minimise the total work, so one wavefront per leaf would leave most lanes idle).
+constexpr int L2P_LPB = 4;   // leaves per workgroup
+constexpr int L2P_LANES = WAVE / L2P_LPB;
+
 template <typename T>
-__global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off, const int32_t *__restrict__ leaves,
-                                              const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
-                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
-                                              const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
-                                              const double *__restrict__ sys_geo, const T *__restrict__ Lc,
-                                              T *__restrict__ vfar)
+__global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, int64_t leaf_off,
+                                              const int32_t *__restrict__ leaves, const int8_t *__restrict__ blev,
+                                              const uint64_t *__restrict__ bkey, const int32_t *__restrict__ bstart,
+                                              const int32_t *__restrict__ bcount, const T *__restrict__ xs,
+                                              const T *__restrict__ ws, int64_t n, const double *__restrict__ sys_geo,
+                                              const T *__restrict__ Lc, T *__restrict__ vfar)
 {
     extern __shared__ char smem[];
     const int P2 = p * p;
     const int TRI = p * (p + 1) / 2;  // (n, m >= 0) pairs, n < p
-    T *cd = (T *)smem;                // 2 P2 local coefficients
-    T *Vre = cd + 2 * P2, *Vim = Vre + 3 * TRI;  // [3][TRI]
-    const int lane = threadIdx.x;
-    const int64_t b = leaves ? (int64_t)leaves[blockIdx.x] : leaf_off + blockIdx.x;
-    const int level = blev ? (int)blev[b] : depth;
-    if (level < 2) {
-        // a leaf above level 2 has no local expansion: its far field is zero
-        for (int e = lane; e < bcount[b]; e += WAVE)
-            for (int k = 0; k < 6; k++) vfar[(size_t)k * n + bstart[b] + e] = (T)0;
-        return;
-    }
-    const T *src = Lc + (size_t)b * 2 * P2;
-    for (int r = lane; r < 2 * P2; r += WAVE) cd[r] = src[r];
-    __syncthreads();
+    const int g = threadIdx.x / L2P_LANES, lane = threadIdx.x % L2P_LANES;
+    T *Vre = (T *)smem + (size_t)g * 6 * TRI, *Vim = Vre + 3 * TRI;  // this leaf's [3][TRI]
+    const int64_t li = (int64_t)blockIdx.x * L2P_LPB + g;
+    const bool has = li < nleaf;
+    const int64_t b = has ? (leaves ? (int64_t)leaves[li] : leaf_off + li) : 0;
+    const int level = has ? (blev ? (int)blev[b] : depth) : 0;
+    const bool far = has && level >= 2;  // a leaf above level 2 has no local expansion: far field zero
+    const T *cd = Lc + (size_t)b * 2 * P2;
     auto get = [&](int pot, int nn, int m, T &re, T &im) {
         if (nn < 0 || nn >= p) {
             re = 0;
@@ -521,33 +520,40 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off
             im = m ? c[pk_im(nn, m)] : (T)0;
         }
     };
-    for (int t = lane; t < TRI; t += WAVE) {
-        int nn = 0;
-        while ((nn + 1) * (nn + 2) / 2 <= t) nn++;
-        const int m = t - nn * (nn + 1) / 2;
-        T pm1r, pm1i, pp1r, pp1i, p0r, p0i, xm1r, xm1i, xp1r, xp1i, x0r, x0i;
-        get(0, nn + 1, m - 1, pm1r, pm1i);
-        get(0, nn + 1, m + 1, pp1r, pp1i);
-        get(0, nn + 1, m, p0r, p0i);
-        get(1, nn, m - 1, xm1r, xm1i);
-        get(1, nn, m + 1, xp1r, xp1i);
-        get(1, nn, m, x0r, x0i);
-        const T a = (T)(nn - m), c = (T)(nn + m);
-        // Vx = 1/2[-Pm1 + Pp1 - i a Xp1 - i c Xm1]
-        Vre[t] = (T)0.5 * (-pm1r + pp1r + a * xp1i + c * xm1i);
-        Vim[t] = (T)0.5 * (-pm1i + pp1i - a * xp1r - c * xm1r);
-        // Vy = 1/2[i Pm1 + i Pp1 + a Xp1 - c Xm1]
-        Vre[TRI + t] = (T)0.5 * (-pm1i - pp1i + a * xp1r - c * xm1r);
-        Vim[TRI + t] = (T)0.5 * (pm1r + pp1r + a * xp1i - c * xm1i);
-        // Vz = -P0 - i m X0
-        Vre[2 * TRI + t] = -p0r + (T)m * x0i;
-        Vim[2 * TRI + t] = -p0i - (T)m * x0r;
-    }
+    if (far)
+        for (int t = lane; t < TRI; t += L2P_LANES) {
+            int nn = 0;
+            while ((nn + 1) * (nn + 2) / 2 <= t) nn++;
+            const int m = t - nn * (nn + 1) / 2;
+            T pm1r, pm1i, pp1r, pp1i, p0r, p0i, xm1r, xm1i, xp1r, xp1i, x0r, x0i;
+            get(0, nn + 1, m - 1, pm1r, pm1i);
+            get(0, nn + 1, m + 1, pp1r, pp1i);
+            get(0, nn + 1, m, p0r, p0i);
+            get(1, nn, m - 1, xm1r, xm1i);
+            get(1, nn, m + 1, xp1r, xp1i);
+            get(1, nn, m, x0r, x0i);
+            const T a = (T)(nn - m), c = (T)(nn + m);
+            // Vx = 1/2[-Pm1 + Pp1 - i a Xp1 - i c Xm1]
+            Vre[t] = (T)0.5 * (-pm1r + pp1r + a * xp1i + c * xm1i);
+            Vim[t] = (T)0.5 * (-pm1i + pp1i - a * xp1r - c * xm1r);
+            // Vy = 1/2[i Pm1 + i Pp1 + a Xp1 - c Xm1]
+            Vre[TRI + t] = (T)0.5 * (-pm1i - pp1i + a * xp1r - c * xm1r);
+            Vim[TRI + t] = (T)0.5 * (pm1r + pp1r + a * xp1i - c * xm1i);
+            // Vz = -P0 - i m X0
+            Vre[2 * TRI + t] = -p0r + (T)m * x0i;
+            Vim[2 * TRI + t] = -p0i - (T)m * x0r;
+        }
     __syncthreads();
+    if (!has) return;
+    const int s0 = bstart[b], cnt = bcount[b];
+    if (!far) {
+        for (int e = lane; e < cnt; e += L2P_LANES)
+            for (int k = 0; k < 6; k++) vfar[(size_t)k * n + s0 + e] = (T)0;
+        return;
+    }
     double c0, c1, c2, hd;
     box_centre(bkey[b], level, sys_geo, c0, c1, c2, hd);
     const T ih = (T)(1.0 / hd);
-    const int s0 = bstart[b], cnt = bcount[b];
     auto vget = [&](int k, int nn, int m, T &re, T &im) {
         if (nn >= p || nn < 0) {
             re = 0;
@@ -574,13 +580,13 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off
         re = Vre[k * TRI + t];
         im = Vim[k * TRI + t];
     };
-    for (int e0 = 0; e0 < cnt; e0 += WAVE) {
+    for (int e0 = 0; e0 < cnt; e0 += L2P_LANES) {
         const int e = e0 + lane;
         const bool act = e < cnt;
         const int i = s0 + (act ? e : 0);
         const T x = (xs[i] - (T)c0) * ih, y = (xs[n + i] - (T)c1) * ih, z = (xs[2 * n + i] - (T)c2) * ih;
         const T r2 = x * x + y * y + z * z;
-        T v[3] = {0, 0, 0}, g[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        T v[3] = {0, 0, 0}, gr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         // walk the columns m; Rt_m^m by recurrence, then up in n
         T mre = 1, mim = 0;
         for (int m = 0; m < p; m++) {
@@ -625,9 +631,9 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off
                     T uxr = (T)0.5 * (br - ar), uxi = (T)0.5 * (bi - ai);
                     T uyr = (T)-0.5 * (ai + bi), uyi = (T)0.5 * (ar + br);
                     T uzr = -cr, uzi = -ci;
-                    g[3 * k + 0] += sw * (uxr * rre - uxi * rim);
-                    g[3 * k + 1] += sw * (uyr * rre - uyi * rim);
-                    g[3 * k + 2] += sw * (uzr * rre - uzi * rim);
+                    gr[3 * k + 0] += sw * (uxr * rre - uxi * rim);
+                    gr[3 * k + 1] += sw * (uyr * rre - uyi * rim);
+                    gr[3 * k + 2] += sw * (uzr * rre - uzi * rim);
                 }
             }
         }
@@ -636,7 +642,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t leaf_off
             const T ih2 = ih * ih;
             for (int k = 0; k < 3; k++) {
                 vfar[k * n + i] = v[k] * ih;
-                vfar[(3 + k) * n + i] = (g[3 * k] * wx + g[3 * k + 1] * wy + g[3 * k + 2] * wz) * ih2;
+                vfar[(3 + k) * n + i] = (gr[3 * k] * wx + gr[3 * k + 1] * wy + gr[3 * k + 2] * wz) * ih2;
             }
         }
     }
@@ -902,10 +908,10 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         }
         mark(4);
         const int TRI = p * (p + 1) / 2;
-        size_t sh_l2p = sizeof(T) * (2 * P2 + 6 * TRI);
-        hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_l2p, st, p, d, loff, P->leaves, P->blev,
-                           P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, (const T *)Lc,
-                           vfar);
+        size_t sh_l2p = sizeof(T) * L2P_LPB * 6 * TRI;
+        hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)((nleaf + L2P_LPB - 1) / L2P_LPB)), dim3(WAVE), sh_l2p, st, p, d,
+                           nleaf, loff, P->leaves, P->blev, P->bkey, P->bstart, P->bcount, (const T *)xs,
+                           (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar);
     } else {
         mark(2);
         mark(3);
