@@ -14,6 +14,8 @@
 // accumulator in registers (lane owns packed rows lane, lane+64, ...), and the
 // per-translation intermediate vectors in LDS.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <math.h>
 
 #include "lhf_internal.h"
@@ -75,11 +77,15 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                                               const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
                                               const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
                                               const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
-                                              const double *__restrict__ sys_geo, T *__restrict__ M)
+                                              const double *__restrict__ sys_geo, T *__restrict__ M, int ch)
 {
+    // the leaf's elements in chunks of ch: first every lane forms the regular solid harmonics of
+    // one (element, m) column of the chunk, then every lane adds the chunk's contributions to
+    // its coefficient rows (two barriers per chunk)
     extern __shared__ char smem[];
-    T *Rre = (T *)smem;          // [p][p]  (n, m)
-    T *Rim = Rre + p * p;
+    T *Rre = (T *)smem;              // [ch][p][p]  (element, n, m)
+    T *Rim = Rre + (size_t)ch * p * p;
+    T *wsh = Rim + (size_t)ch * p * p;  // [ch][3] strengths
     const int lane = threadIdx.x;
     // uniform tree: leaves leaf_off + blockIdx.x at level depth; adaptive: leaves[blockIdx.x] at blev[]
     const int64_t b = leaves ? (int64_t)leaves[blockIdx.x] : leaf_off + blockIdx.x;
@@ -87,21 +93,22 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
     if (level < 2) return;  // no far field above level 2
     double c0, c1, c2, hd;
     box_centre(bkey[b], level, sys_geo, c0, c1, c2, hd);
-    const T h = (T)hd, ih = (T)(1.0 / hd);
+    const T ih = (T)(1.0 / hd);
     const int P2 = p * p;
     T acc[NRMAX];
 #pragma unroll
     for (int k = 0; k < NRMAX; k++) acc[k] = 0;
     const int s0 = bstart[b], cnt = bcount[b];
-    for (int e = 0; e < cnt; e++) {
-        const int i = s0 + e;
-        const T x = (xs[i] - (T)c0) * ih, y = (xs[n + i] - (T)c1) * ih, z = (xs[2 * n + i] - (T)c2) * ih;
-        const T wx = ws[i], wy = ws[n + i], wz = ws[2 * n + i];
-        __syncthreads();
-        if (lane < p) {
-            const int m = lane;
-            T r2 = x * x + y * y + z * z;
-            // Rt_m^m = (-(x+iy)/2)^m / m!
+    for (int e0 = 0; e0 < cnt; e0 += ch) {
+        const int ne = min(ch, cnt - e0);
+        __syncthreads();  // the previous chunk's tables are no longer read
+        for (int q = lane; q < ne * p; q += WAVE) {
+            const int e = q / p, m = q - e * p;
+            const int i = s0 + e0 + e;
+            const T x = (xs[i] - (T)c0) * ih, y = (xs[n + i] - (T)c1) * ih, z = (xs[2 * n + i] - (T)c2) * ih;
+            const T r2 = x * x + y * y + z * z;
+            T *Re = Rre + (size_t)e * P2, *Im = Rim + (size_t)e * P2;
+            // Rt_m^m = (-(x+iy)/2)^m / m!, then up in n
             T are = 1, aim = 0;
             for (int k = 1; k <= m; k++) {
                 T f = (T)(-0.5) / (T)k;
@@ -110,8 +117,8 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                 aim = nim;
             }
             T p2re = 0, p2im = 0, p1re = are, p1im = aim;
-            Rre[m * p + m] = are;
-            Rim[m * p + m] = aim;
+            Re[m * p + m] = are;
+            Im[m * p + m] = aim;
             for (int nn = m + 1; nn < p; nn++) {
                 T cre, cim;
                 if (nn == m + 1) {
@@ -122,36 +129,20 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                     cre = ((T)(2 * nn - 1) * z * p1re - r2 * p2re) * inv;
                     cim = ((T)(2 * nn - 1) * z * p1im - r2 * p2im) * inv;
                 }
-                Rre[nn * p + m] = cre;
-                Rim[nn * p + m] = cim;
+                Re[nn * p + m] = cre;
+                Im[nn * p + m] = cim;
                 p2re = p1re;
                 p2im = p1im;
                 p1re = cre;
                 p1im = cim;
             }
+            if (m == 0) {
+                wsh[3 * e] = ws[i];
+                wsh[3 * e + 1] = ws[n + i];
+                wsh[3 * e + 2] = ws[2 * n + i];
+            }
         }
         __syncthreads();
-        // conj(Rt_n^k), with the convention conj(Rt_n^{-1}) = -Rt_n^1 that makes the m >= 1
-        // formulas valid at m = 0 as well
-        auto C = [&](int nn, int k, T &re, T &im) {
-            if (nn < 0 || k > nn) {
-                re = 0;
-                im = 0;
-            } else if (k == -1) {
-                if (nn >= 1) {
-                    re = -Rre[nn * p + 1];
-                    im = -Rim[nn * p + 1];
-                } else {
-                    re = 0;
-                    im = 0;
-                }
-            } else {
-                re = Rre[nn * p + k];
-                im = -Rim[nn * p + k];
-            }
-        };
-        const T wmre = wx, wmim = -wy;  // wx - i wy
-        const T wpre = wx, wpim = wy;   // wx + i wy
 #pragma unroll
         for (int k = 0; k < NRMAX; k++) {
             const int r = lane + WAVE * k;
@@ -159,38 +150,63 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
             const int pot = r >= P2;
             int nn, m, part;
             decode_row(r - pot * P2, nn, m, part);
-            T vre, vim;
             const T sgn = (m & 1) ? (T)-1 : (T)1;
-            if (pot == 0) {
-                // a = -i (-1)^m / (n+1) [ (wx-iwy)(n-m+1)/2 C(m-1) + (wx+iwy)(n+m+1)/2 C(m+1) + wz m C(m) ]
-                T c1re, c1im, c2re, c2im, c3re, c3im;
-                C(nn, m - 1, c1re, c1im);
-                C(nn, m + 1, c2re, c2im);
-                C(nn, m, c3re, c3im);
-                T f1 = (T)(nn - m + 1) * (T)0.5, f2 = (T)(nn + m + 1) * (T)0.5, f3 = wz * (T)m;
-                T sre = f1 * (wmre * c1re - wmim * c1im) + f2 * (wpre * c2re - wpim * c2im) + f3 * c3re;
-                T sim = f1 * (wmre * c1im + wmim * c1re) + f2 * (wpre * c2im + wpim * c2re) + f3 * c3im;
-                T sc = sgn / (T)(nn + 1);
-                vre = sc * sim;   // -i (sre + i sim) = sim - i sre
-                vim = -sc * sre;
-            } else {
-                if (nn == 0) {
-                    vre = 0;
-                    vim = 0;
-                } else {
-                    // b = (-1)^m / n [ -1/2 (wx-iwy) C'(m-1) + 1/2 (wx+iwy) C'(m+1) + wz C'(m) ]
+            for (int e = 0; e < ne; e++) {
+                const T *Re = Rre + (size_t)e * P2, *Im = Rim + (size_t)e * P2;
+                const T wx = wsh[3 * e], wy = wsh[3 * e + 1], wz = wsh[3 * e + 2];
+                // conj(Rt_n^k), with the convention conj(Rt_n^{-1}) = -Rt_n^1 that makes the m >= 1
+                // formulas valid at m = 0 as well
+                auto C = [&](int n2, int kk, T &re, T &im) {
+                    if (n2 < 0 || kk > n2) {
+                        re = 0;
+                        im = 0;
+                    } else if (kk == -1) {
+                        if (n2 >= 1) {
+                            re = -Re[n2 * p + 1];
+                            im = -Im[n2 * p + 1];
+                        } else {
+                            re = 0;
+                            im = 0;
+                        }
+                    } else {
+                        re = Re[n2 * p + kk];
+                        im = -Im[n2 * p + kk];
+                    }
+                };
+                const T wmre = wx, wmim = -wy;  // wx - i wy
+                const T wpre = wx, wpim = wy;   // wx + i wy
+                T vre, vim;
+                if (pot == 0) {
+                    // a = -i (-1)^m / (n+1) [ (wx-iwy)(n-m+1)/2 C(m-1) + (wx+iwy)(n+m+1)/2 C(m+1) + wz m C(m) ]
                     T c1re, c1im, c2re, c2im, c3re, c3im;
-                    C(nn - 1, m - 1, c1re, c1im);
-                    C(nn - 1, m + 1, c2re, c2im);
-                    C(nn - 1, m, c3re, c3im);
-                    T sre = (T)-0.5 * (wmre * c1re - wmim * c1im) + (T)0.5 * (wpre * c2re - wpim * c2im) + wz * c3re;
-                    T sim = (T)-0.5 * (wmre * c1im + wmim * c1re) + (T)0.5 * (wpre * c2im + wpim * c2re) + wz * c3im;
-                    T sc = sgn / (T)nn;
-                    vre = sc * sre;
-                    vim = sc * sim;
+                    C(nn, m - 1, c1re, c1im);
+                    C(nn, m + 1, c2re, c2im);
+                    C(nn, m, c3re, c3im);
+                    T f1 = (T)(nn - m + 1) * (T)0.5, f2 = (T)(nn + m + 1) * (T)0.5, f3 = wz * (T)m;
+                    T sre = f1 * (wmre * c1re - wmim * c1im) + f2 * (wpre * c2re - wpim * c2im) + f3 * c3re;
+                    T sim = f1 * (wmre * c1im + wmim * c1re) + f2 * (wpre * c2im + wpim * c2re) + f3 * c3im;
+                    T sc = sgn / (T)(nn + 1);
+                    vre = sc * sim;  // -i (sre + i sim) = sim - i sre
+                    vim = -sc * sre;
+                } else {
+                    if (nn == 0) {
+                        vre = 0;
+                        vim = 0;
+                    } else {
+                        // b = (-1)^m / n [ -1/2 (wx-iwy) C'(m-1) + 1/2 (wx+iwy) C'(m+1) + wz C'(m) ]
+                        T c1re, c1im, c2re, c2im, c3re, c3im;
+                        C(nn - 1, m - 1, c1re, c1im);
+                        C(nn - 1, m + 1, c2re, c2im);
+                        C(nn - 1, m, c3re, c3im);
+                        T sre = (T)-0.5 * (wmre * c1re - wmim * c1im) + (T)0.5 * (wpre * c2re - wpim * c2im) + wz * c3re;
+                        T sim = (T)-0.5 * (wmre * c1im + wmim * c1re) + (T)0.5 * (wpre * c2im + wpim * c2re) + wz * c3im;
+                        T sc = sgn / (T)nn;
+                        vre = sc * sre;
+                        vim = sc * sim;
+                    }
                 }
+                acc[k] += part ? vim : vre;
             }
-            acc[k] += part ? vim : vre;
         }
     }
     T *out = M + (size_t)b * 2 * P2;
@@ -200,7 +216,6 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
         if (r >= 2 * P2) break;
         out[r] = acc[k] * ih;
     }
-    (void)h;
 }
 
 // ---------------------------------------------------------------------------
@@ -867,9 +882,11 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
     // uniform tree: the leaves are the boxes of level d; adaptive: the explicit leaf list
     const int64_t loff = P->lev[d].off, nleaf = P->adaptive ? P->nleaf : P->lev[d].nb;
     if (what & 1) {
-        size_t sh_p2m = sizeof(T) * 2 * P2;
+        // elements per P2M chunk: 8, fewer at large p (LDS within 48 KB)
+        const int ch = std::max(1, std::min(8, (int)(49152 / (sizeof(T) * (2 * P2 + 3)))));
+        size_t sh_p2m = sizeof(T) * (size_t)ch * (2 * P2 + 3);
         hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_p2m, st, p, d, loff, P->leaves, P->blev,
-                           P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, M);
+                           P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, M, ch);
         mark(2);
         size_t sh_rcr = sizeof(T) * (4 * P2 + 2 * ZS + 2 * p + 2);
         for (int l = d - 1; l >= 2; l--) {
