@@ -137,8 +137,15 @@ lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void 
 /* Counts of the plan (boxes, translations, near-field pairs). */
 lhf_status lhf_plan_stats(const lhf_plan *plan, lhf_stats *out);
 
-/* Release the plan and its device memory (synchronises the plan's last stream). */
+/* Release the plan (synchronises the device first: executes may be queued on any stream).
+ * Its device blocks stay with the library and serve the next plan that asks for the same
+ * sizes (a plan rebuilt every step); LHF_NO_MEMCACHE=1 in the environment frees them at once,
+ * LHF_MEMCACHE_GB bounds the idle bytes kept (default 16). */
 lhf_status lhf_plan_destroy(lhf_plan *plan);
+
+/* Return every idle device block the library keeps to the HIP runtime.  Blocks of live plans
+ * and batches are not touched. */
+lhf_status lhf_release_cached_memory(void);
 
 /* Thread-local description of the last error (never NULL). */
 const char *lhf_last_error(void);

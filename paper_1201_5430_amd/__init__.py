@@ -26,7 +26,8 @@ STATUS = {0: "LHF_OK", 1: "LHF_WARN_CORE_SPLIT", -1: "LHF_ERR_ARG", -2: "LHF_ERR
 EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_plan_create_multi", "lhf_execute", "lhf_execute_parts",
            "lhf_evaluate", "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version",
            "lhf_profile_begin", "lhf_profile_end", "lhf_tune_default", "lhf_autotune", "lhf_choose_depth",
-           "lhf_batch_create", "lhf_batch_execute", "lhf_batch_info", "lhf_batch_destroy")
+           "lhf_batch_create", "lhf_batch_execute", "lhf_batch_info", "lhf_batch_destroy",
+           "lhf_release_cached_memory")
 PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 
 
@@ -78,6 +79,8 @@ def load():
         L.lhf_plan_stats.restype = C.c_int
         L.lhf_plan_destroy.argtypes = [vp]
         L.lhf_plan_destroy.restype = C.c_int
+        L.lhf_release_cached_memory.argtypes = []
+        L.lhf_release_cached_memory.restype = C.c_int
         L.lhf_last_error.restype = C.c_char_p
         L.lhf_version.restype = C.c_char_p
         L.lhf_profile_begin.argtypes = [vp, C.c_int32]
@@ -235,6 +238,11 @@ def evaluate(x, omega, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1
     _check(load().lhf_evaluate(C.byref(d), x.shape[0], C.c_void_p(x.data_ptr()), C.c_void_p(omega.data_ptr()),
                                float(a), C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr()), _stream()))
     return v, s
+
+
+def release_cached_memory():
+    """Return the idle device blocks the library keeps for later plans to the HIP runtime."""
+    _check(load().lhf_release_cached_memory())
 
 
 def tune_default(p, precision=FP32):

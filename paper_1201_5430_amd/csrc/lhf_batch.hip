@@ -149,8 +149,8 @@ static lhf_status group_plan(lhf_batch *B, const std::vector<int> &sys, int d, c
     const size_t ts = B->desc.precision == LHF_FP64 ? 8 : 4;
     int32_t *dg = nullptr;
     void *xg = nullptr;
-    hipError_t e = hipMalloc(&dg, sizeof(int32_t) * ng);
-    if (e == hipSuccess) e = hipMalloc(&xg, ts * 3 * ng);
+    hipError_t e = dev_malloc(&dg, sizeof(int32_t) * ng);
+    if (e == hipSuccess) e = dev_malloc(&xg, ts * 3 * ng);
     if (e == hipSuccess) e = hipMemcpyAsync(dg, gidx.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         const unsigned nb = (unsigned)((ng + 255) / 256);
@@ -171,8 +171,8 @@ static lhf_status group_plan(lhf_batch *B, const std::vector<int> &sys, int d, c
             if (e == hipSuccess) e = hipStreamSynchronize(st);
         }
     }
-    if (dg) (void)hipFree(dg);
-    if (xg) (void)hipFree(xg);
+    if (dg) (void)dev_free(dg);
+    if (xg) (void)dev_free(xg);
     if (e != hipSuccess) {
         if (*out) plan_free(*out);
         *out = nullptr;
@@ -241,10 +241,10 @@ static lhf_status measure_tune(int32_t p, int32_t precision, hipStream_t st, lhf
         pw = fw.data();
     }
     void *dx = nullptr, *dw = nullptr, *dv = nullptr, *ds = nullptr;
-    hipError_t e = hipMalloc(&dx, ts * 3 * n);
-    if (e == hipSuccess) e = hipMalloc(&dw, ts * 3 * n);
-    if (e == hipSuccess) e = hipMalloc(&dv, ts * 3 * n);
-    if (e == hipSuccess) e = hipMalloc(&ds, ts * 3 * n);
+    hipError_t e = dev_malloc(&dx, ts * 3 * n);
+    if (e == hipSuccess) e = dev_malloc(&dw, ts * 3 * n);
+    if (e == hipSuccess) e = dev_malloc(&dv, ts * 3 * n);
+    if (e == hipSuccess) e = dev_malloc(&ds, ts * 3 * n);
     if (e == hipSuccess) e = hipMemcpyAsync(dx, px, ts * 3 * n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dw, pw, ts * 3 * n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -281,8 +281,9 @@ static lhf_status measure_tune(int32_t p, int32_t precision, hipStream_t st, lhf
         lhf_status dr = lhf_plan_destroy(P);
         if (rs >= 0 && dr < 0) rs = dr;
     }
+    (void)hipStreamSynchronize(st);
     for (void *b : {dx, dw, dv, ds})
-        if (b) (void)hipFree(b);
+        if (b) (void)dev_free(b);
     if (rs < 0) return rs;
     out->p = p;
     out->precision = precision;

@@ -152,6 +152,18 @@ lhf_status arg_error(const std::string &msg);
 lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *off, const void *x,
                     const double *lo, const double *len, const double *a, hipStream_t stream);
 void plan_free(lhf_plan *P);
+
+// Device memory of plans and their temporaries.  Freed blocks are kept per (device, rounded
+// size) and handed to the next request of that size (a plan rebuilt every step allocates the
+// same sizes); LHF_NO_MEMCACHE=1 calls hipMalloc/hipFree directly.  A block may be freed only
+// once no queued work uses it (plan destruction synchronizes the device first).
+hipError_t dev_malloc_raw(void **p, size_t bytes);
+hipError_t dev_free(void *p);
+template <typename T>
+inline hipError_t dev_malloc(T **p, size_t bytes)
+{
+    return dev_malloc_raw((void **)p, bytes);
+}
 lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st);
 }  // namespace lhf
 

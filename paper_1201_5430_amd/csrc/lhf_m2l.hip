@@ -768,7 +768,7 @@ template <typename T, int P>
 static size_t wpad_build_t(lhf_plan *Pl, hipStream_t st)
 {
     const int64_t stride = wpad_stride<T, P>();
-    if (hipMalloc(&Pl->wpad, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return 0;
+    if (dev_malloc(&Pl->wpad, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return 0;
     k_wpad<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>(Pl->n_theta, (const T *)Pl->rot, (T *)Pl->wpad,
                                                                      stride);
     return (size_t)stride;

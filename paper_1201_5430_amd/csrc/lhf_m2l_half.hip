@@ -763,7 +763,7 @@ static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
     constexpr size_t shm = hv::tile_bytes<T, P, OWN>(NPAR);
     static_assert(shm <= 163840, "tile exceeds the LDS");
     const int64_t stride = 8 * (int64_t)hv::Shape<T, P>::WHS;
-    if (hipMalloc(&Pl->whalf, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
+    if (dev_malloc(&Pl->whalf, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
     k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->whalf, stride,
                                                                       ROT_S_FWD, ROT_R_BACK);
     return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, OWN>,
@@ -791,8 +791,8 @@ template <typename T, int P>
 static bool mmhalf_build_t(lhf_plan *Pl, hipStream_t st)
 {
     const int64_t stride = 8 * (int64_t)hv::Shape<T, P>::WHS;
-    if (hipMalloc(&Pl->wmm, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
-    if (hipMalloc(&Pl->wll, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
+    if (dev_malloc(&Pl->wmm, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
+    if (dev_malloc(&Pl->wll, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
     k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->wmm, stride,
                                                                       ROT_S_FWD, ROT_S_BACK);
     k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->wll, stride,

@@ -16,6 +16,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <unordered_map>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -38,6 +40,107 @@ bool wmfma_build(lhf_plan *Pl, hipStream_t st);
 static bool batched_m2l_supported(int precision, int p)
 {
     return m2l_tile_supported(precision, p) || (m2l_half_supported(precision, p) && !getenv("LHF_NO_HALF"));
+}
+
+// ---- device memory cache -----------------------------------------------------------------
+namespace {
+struct MemCache {
+    std::mutex mu;
+    std::map<std::pair<int, size_t>, std::vector<void *>> idle;  // (device, bytes) -> free blocks
+    std::unordered_map<void *, std::pair<int, size_t>> live;     // block -> (device, bytes)
+    size_t idle_bytes = 0;
+};
+MemCache &mem_cache()
+{
+    static MemCache *m = new MemCache();  // lives as long as the process
+    return *m;
+}
+bool mem_cache_on()
+{
+    static const bool on = getenv("LHF_NO_MEMCACHE") == nullptr;
+    return on;
+}
+// idle bytes kept at most (LHF_MEMCACHE_GB, default 16 GiB of the 288 GB)
+size_t mem_cache_cap()
+{
+    static const size_t cap = [] {
+        const char *e = getenv("LHF_MEMCACHE_GB");
+        const double gb = e ? atof(e) : 16.0;
+        return (size_t)(std::max(0.0, gb) * 1073741824.0);
+    }();
+    return cap;
+}
+size_t round_block(size_t b)
+{
+    const size_t small = 512, large = (size_t)2 << 20;
+    b = std::max<size_t>(b, 1);
+    return b < ((size_t)1 << 20) ? (b + small - 1) / small * small : (b + large - 1) / large * large;
+}
+// release idle blocks (of one device, or all with dev < 0) until at most keep bytes stay idle
+void mem_trim_locked(MemCache &m, int dev, size_t keep)
+{
+    for (auto it = m.idle.begin(); it != m.idle.end() && m.idle_bytes > keep;) {
+        if (dev >= 0 && it->first.first != dev) {
+            ++it;
+            continue;
+        }
+        while (!it->second.empty() && m.idle_bytes > keep) {
+            (void)hipFree(it->second.back());
+            it->second.pop_back();
+            m.idle_bytes -= it->first.second;
+        }
+        it = it->second.empty() ? m.idle.erase(it) : std::next(it);
+    }
+}
+}  // namespace
+
+hipError_t dev_malloc_raw(void **p, size_t bytes)
+{
+    if (!mem_cache_on()) return hipMalloc(p, bytes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const size_t rb = round_block(bytes);
+    MemCache &m = mem_cache();
+    {
+        std::lock_guard<std::mutex> lk(m.mu);
+        auto it = m.idle.find({dev, rb});
+        if (it != m.idle.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            m.idle_bytes -= rb;
+            m.live[*p] = {dev, rb};
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(p, rb);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        std::lock_guard<std::mutex> lk(m.mu);
+        mem_trim_locked(m, dev, 0);
+        e = hipMalloc(p, rb);
+    }
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(m.mu);
+        m.live[*p] = {dev, rb};
+    }
+    return e;
+}
+
+hipError_t dev_free(void *p)
+{
+    if (!p) return hipSuccess;
+    if (!mem_cache_on()) return hipFree(p);
+    MemCache &m = mem_cache();
+    std::lock_guard<std::mutex> lk(m.mu);
+    auto it = m.live.find(p);
+    if (it == m.live.end()) return hipFree(p);
+    const auto key = it->second;
+    m.live.erase(it);
+    m.idle[key].push_back(p);
+    m.idle_bytes += key.second;
+    if (m.idle_bytes > mem_cache_cap()) mem_trim_locked(m, -1, mem_cache_cap());
+    return hipSuccess;
 }
 
 static thread_local std::string g_err = "no error";
@@ -822,14 +925,14 @@ static lhf_status build_schedule(lhf_plan *P, const std::vector<int16_t> &cls, i
             for (int c = 0; c < 8; c++) rows.push_back(r < perc[c].size() ? perc[c][r] : (int16_t)-1);
     }
     rstart.push_back((int16_t)(rows.size() / 8));
-    LHF_HIP(hipMalloc(&P->sched_row_start, sizeof(int16_t) * rstart.size()));
-    LHF_HIP(hipMalloc(&P->sched_rows, sizeof(int16_t) * rows.size()));
+    LHF_HIP(dev_malloc(&P->sched_row_start, sizeof(int16_t) * rstart.size()));
+    LHF_HIP(dev_malloc(&P->sched_rows, sizeof(int16_t) * rows.size()));
     LHF_HIP(hipMemcpyAsync(P->sched_row_start, rstart.data(), sizeof(int16_t) * rstart.size(), hipMemcpyHostToDevice, st));
     LHF_HIP(hipMemcpyAsync(P->sched_rows, rows.data(), sizeof(int16_t) * rows.size(), hipMemcpyHostToDevice, st));
-    LHF_HIP(hipMalloc(&P->sched_cls_start, sizeof(int16_t) * start.size()));
-    LHF_HIP(hipMalloc(&P->sched_c, sizeof(int16_t) * ec.size()));
-    LHF_HIP(hipMalloc(&P->sched_dir, sizeof(int16_t) * ed.size()));
-    LHF_HIP(hipMalloc(&P->sched_cls_theta, sizeof(int16_t) * cth.size()));
+    LHF_HIP(dev_malloc(&P->sched_cls_start, sizeof(int16_t) * start.size()));
+    LHF_HIP(dev_malloc(&P->sched_c, sizeof(int16_t) * ec.size()));
+    LHF_HIP(dev_malloc(&P->sched_dir, sizeof(int16_t) * ed.size()));
+    LHF_HIP(dev_malloc(&P->sched_cls_theta, sizeof(int16_t) * cth.size()));
     LHF_HIP(hipMemcpyAsync(P->sched_cls_start, start.data(), sizeof(int16_t) * start.size(), hipMemcpyHostToDevice, st));
     LHF_HIP(hipMemcpyAsync(P->sched_c, ec.data(), sizeof(int16_t) * ec.size(), hipMemcpyHostToDevice, st));
     LHF_HIP(hipMemcpyAsync(P->sched_dir, ed.data(), sizeof(int16_t) * ed.size(), hipMemcpyHostToDevice, st));
@@ -846,11 +949,11 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     P->n_theta = (int)theta.size();
     const int p = P->p;
     const size_t RS = rot_set_size(p);
-    LHF_HIP(hipMalloc(&P->rot, sizeof(T) * RS * ROT_NKIND * theta.size()));
-    LHF_HIP(hipMalloc(&P->zph, sizeof(T) * NDIR * 2 * p));
-    LHF_HIP(hipMalloc(&P->coax, sizeof(T) * 28 * (2 * p + 2)));
-    LHF_HIP(hipMalloc(&P->dir_theta, sizeof(int16_t) * NDIR));
-    LHF_HIP(hipMalloc(&P->dtmp, sizeof(double) * theta.size()));
+    LHF_HIP(dev_malloc(&P->rot, sizeof(T) * RS * ROT_NKIND * theta.size()));
+    LHF_HIP(dev_malloc(&P->zph, sizeof(T) * NDIR * 2 * p));
+    LHF_HIP(dev_malloc(&P->coax, sizeof(T) * 28 * (2 * p + 2)));
+    LHF_HIP(dev_malloc(&P->dir_theta, sizeof(int16_t) * NDIR));
+    LHF_HIP(dev_malloc(&P->dtmp, sizeof(double) * theta.size()));
     LHF_HIP(hipMemcpyAsync(P->dir_theta, cls.data(), sizeof(int16_t) * NDIR, hipMemcpyHostToDevice, st));
     LHF_HIP(hipMemcpyAsync(P->dtmp, theta.data(), sizeof(double) * theta.size(), hipMemcpyHostToDevice, st));
     const int Dmax = 2 * p - 1;
@@ -878,7 +981,7 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
         }
         for (int l = 2; l <= P->depth; l++) {
             const size_t cells = (size_t)P->nsys << (3 * l);
-            LHF_HIP(hipMalloc(&P->dmap[l], sizeof(int32_t) * cells));
+            LHF_HIP(dev_malloc(&P->dmap[l], sizeof(int32_t) * cells));
             LHF_HIP(hipMemsetAsync(P->dmap[l], 0xff, sizeof(int32_t) * cells, st));
             dmap_build(P, l, st);
         }
@@ -921,19 +1024,22 @@ static void free_profile(lhf_plan *P)
 static void free_plan(lhf_plan *P)
 {
     if (!P) return;
+    // the blocks go back to the cache, where another plan may take them at once: nothing queued
+    // on any stream may still use them
+    (void)hipDeviceSynchronize();
     free_profile(P);
     void *bufs[] = {P->perm, P->xs, P->ws, P->vfar, P->bkey, P->bstart, P->bcount, P->bparent, P->bchild0,
                     P->bnchild, P->vcount, P->vsrc, P->vdir, P->ulist, P->eleaf, P->M, P->Lc, P->rot,
                     P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp, P->sys_geo, P->sys_a, P->sys_off,
                     P->blev, P->leaves, P->nl_start, P->nl_ent};
     for (void *b : bufs)
-        if (b) (void)hipFree(b);
+        if (b) (void)dev_free(b);
     for (int l = 0; l <= MAXDEPTH; l++)
-        if (P->dmap[l]) (void)hipFree(P->dmap[l]);
+        if (P->dmap[l]) (void)dev_free(P->dmap[l]);
     void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta, P->wpad, P->sched_row_start,
                   P->sched_rows, P->wmfma, P->whalf, P->wmm, P->wll};
     for (void *b : sb)
-        if (b) (void)hipFree(b);
+        if (b) (void)dev_free(b);
     delete P;
 }
 
@@ -964,13 +1070,14 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     std::vector<uint64_t *> lkey(d + 1, nullptr);
     std::vector<int32_t *> lstart(d + 1, nullptr), kid(d + 1, nullptr);
     auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);  // no queued kernel may still use a temporary
         for (void *b : {(void *)key, (void *)skey, (void *)idx, (void *)flag, (void *)id, (void *)dnb, (void *)dcnt,
                         (void *)dad, (void *)lcnt, tmp})
-            if (b) (void)hipFree(b);
+            if (b) (void)dev_free(b);
         for (int l = 0; l <= d; l++) {
-            if (lkey[l]) (void)hipFree(lkey[l]);
-            if (lstart[l]) (void)hipFree(lstart[l]);
-            if (kid[l]) (void)hipFree(kid[l]);
+            if (lkey[l]) (void)dev_free(lkey[l]);
+            if (lstart[l]) (void)dev_free(lstart[l]);
+            if (kid[l]) (void)dev_free(kid[l]);
         }
     };
 #define CK(call)                                        \
@@ -982,20 +1089,20 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
         }                                               \
     } while (0)
     // ---- keys and sort
-    CK(hipMalloc(&key, sizeof(uint64_t) * n));
-    CK(hipMalloc(&skey, sizeof(uint64_t) * n));
-    CK(hipMalloc(&idx, sizeof(int32_t) * n));
-    CK(hipMalloc(&P->perm, sizeof(int32_t) * n));
-    CK(hipMalloc(&flag, sizeof(int32_t) * n));
-    CK(hipMalloc(&id, sizeof(int32_t) * n));
-    CK(hipMalloc(&dnb, sizeof(int64_t) * (MAXDEPTH + 1)));
-    CK(hipMalloc(&dcnt, sizeof(int64_t) * 4));
-    CK(hipMalloc(&P->dflag, sizeof(int32_t) * 4));
+    CK(dev_malloc(&key, sizeof(uint64_t) * n));
+    CK(dev_malloc(&skey, sizeof(uint64_t) * n));
+    CK(dev_malloc(&idx, sizeof(int32_t) * n));
+    CK(dev_malloc(&P->perm, sizeof(int32_t) * n));
+    CK(dev_malloc(&flag, sizeof(int32_t) * n));
+    CK(dev_malloc(&id, sizeof(int32_t) * n));
+    CK(dev_malloc(&dnb, sizeof(int64_t) * (MAXDEPTH + 1)));
+    CK(dev_malloc(&dcnt, sizeof(int64_t) * 4));
+    CK(dev_malloc(&P->dflag, sizeof(int32_t) * 4));
     CK(hipMemsetAsync(P->dflag, 0, sizeof(int32_t) * 4, st));
     CK(hipMemsetAsync(dcnt, 0, sizeof(int64_t) * 4, st));
-    CK(hipMalloc(&P->sys_geo, sizeof(double) * 4 * ns));
-    CK(hipMalloc(&P->sys_a, sizeof(double) * ns));
-    CK(hipMalloc(&P->sys_off, sizeof(int64_t) * (ns + 1)));
+    CK(dev_malloc(&P->sys_geo, sizeof(double) * 4 * ns));
+    CK(dev_malloc(&P->sys_a, sizeof(double) * ns));
+    CK(dev_malloc(&P->sys_off, sizeof(int64_t) * (ns + 1)));
     CK(hipMemcpyAsync(P->sys_geo, P->h_sys_geo.data(), sizeof(double) * 4 * ns, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(P->sys_a, P->h_sys_a.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(P->sys_off, P->h_sys_off.data(), sizeof(int64_t) * (ns + 1), hipMemcpyHostToDevice, st));
@@ -1010,18 +1117,18 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, key, skey, idx, P->perm, (int)n, 0, end_bit, st));
     CK(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, flag, id, (int)n, st));
     tmp_bytes = std::max(sort_bytes, scan_bytes);
-    CK(hipMalloc(&tmp, tmp_bytes));
+    CK(dev_malloc(&tmp, tmp_bytes));
     CK(hipcub::DeviceRadixSort::SortPairs(tmp, sort_bytes, key, skey, idx, P->perm, (int)n, 0, end_bit, st));
-    CK(hipMalloc(&P->xs, sizeof(T) * 3 * n));
-    CK(hipMalloc(&P->ws, sizeof(T) * 3 * n));
-    CK(hipMalloc(&P->vfar, sizeof(T) * 6 * n));
-    CK(hipMalloc(&P->eleaf, sizeof(int32_t) * n));
+    CK(dev_malloc(&P->xs, sizeof(T) * 3 * n));
+    CK(dev_malloc(&P->ws, sizeof(T) * 3 * n));
+    CK(dev_malloc(&P->vfar, sizeof(T) * 6 * n));
+    CK(dev_malloc(&P->eleaf, sizeof(int32_t) * n));
     hipLaunchKernelGGL(k_gather_x<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)x, P->perm, (T *)P->xs);
     // ---- every non-empty box of every level
     for (int l = d; l >= 0; l--) {
         const int64_t cap = level_cap(l);
-        CK(hipMalloc(&lkey[l], sizeof(uint64_t) * cap));
-        CK(hipMalloc(&lstart[l], sizeof(int32_t) * cap));
+        CK(dev_malloc(&lkey[l], sizeof(uint64_t) * cap));
+        CK(dev_malloc(&lstart[l], sizeof(int32_t) * cap));
         const int sh = 3 * (d - l);
         hipLaunchKernelGGL(k_level_flags, dim3(nblk), dim3(tpb), 0, st, n, skey, sh, flag);
         CK(hipcub::DeviceScan::InclusiveSum(tmp, scan_bytes, flag, id, (int)n, st));
@@ -1030,11 +1137,11 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     }
     // ---- adaptive tree: keep flags, kept boxes and leaves per level
     if (adaptive) {
-        CK(hipMalloc(&dad, sizeof(int64_t) * 2 * (MAXDEPTH + 1)));
+        CK(dev_malloc(&dad, sizeof(int64_t) * 2 * (MAXDEPTH + 1)));
         CK(hipMemsetAsync(dad, 0, sizeof(int64_t) * 2 * (MAXDEPTH + 1), st));
         for (int l = 0; l <= d; l++) {
             const int64_t cap = level_cap(l);
-            CK(hipMalloc(&kid[l], sizeof(int32_t) * cap));
+            CK(dev_malloc(&kid[l], sizeof(int32_t) * cap));
             hipLaunchKernelGGL(k_akeep, grid(cap), dim3(tpb), 0, st, cap, l, d, (int64_t)P->max_per_leaf, n, dnb,
                                lkey[l], lstart[l], l ? lkey[l - 1] : nullptr, l ? lstart[l - 1] : nullptr, flag,
                                dad + MAXDEPTH + 1);
@@ -1089,23 +1196,23 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     lt.off[d + 1] = tot;
     P->nbox = tot;
     const int P2 = P->p * P->p;
-    CK(hipMalloc(&P->bkey, sizeof(uint64_t) * tot));
-    CK(hipMalloc(&P->bstart, sizeof(int32_t) * tot));
-    CK(hipMalloc(&P->bcount, sizeof(int32_t) * tot));
-    CK(hipMalloc(&P->bparent, sizeof(int32_t) * tot));
-    CK(hipMalloc(&P->bchild0, sizeof(int32_t) * tot));
-    CK(hipMalloc(&P->bnchild, sizeof(int32_t) * tot));
-    CK(hipMalloc(&P->vcount, sizeof(int32_t) * tot));
+    CK(dev_malloc(&P->bkey, sizeof(uint64_t) * tot));
+    CK(dev_malloc(&P->bstart, sizeof(int32_t) * tot));
+    CK(dev_malloc(&P->bcount, sizeof(int32_t) * tot));
+    CK(dev_malloc(&P->bparent, sizeof(int32_t) * tot));
+    CK(dev_malloc(&P->bchild0, sizeof(int32_t) * tot));
+    CK(dev_malloc(&P->bnchild, sizeof(int32_t) * tot));
+    CK(dev_malloc(&P->vcount, sizeof(int32_t) * tot));
     // batched M2L: used when a batched kernel exists for (precision, p) and the dense box maps
     // stay small (levels <= 8, at most 2^28 cells); then the V-lists are only counted
     P->use_tile = batched_m2l_supported(P->precision, P->p) && P->depth <= 8 &&
                   ((int64_t)ns << (3 * P->depth)) <= ((int64_t)1 << 28) && !getenv("LHF_NO_TILE");
     if (!P->use_tile) {
-        CK(hipMalloc(&P->vsrc, sizeof(int32_t) * tot * VMAX));
-        CK(hipMalloc(&P->vdir, sizeof(int16_t) * tot * VMAX));
+        CK(dev_malloc(&P->vsrc, sizeof(int32_t) * tot * VMAX));
+        CK(dev_malloc(&P->vdir, sizeof(int16_t) * tot * VMAX));
     }
-    CK(hipMalloc(&P->M, sizeof(T) * tot * 2 * P2));
-    CK(hipMalloc(&P->Lc, sizeof(T) * tot * 2 * P2));
+    CK(dev_malloc(&P->M, sizeof(T) * tot * 2 * P2));
+    CK(dev_malloc(&P->Lc, sizeof(T) * tot * 2 * P2));
     // multipoles of levels 0 and 1 are never formed, yet kernels read box 0 as a stand-in
     // source for inactive lanes: every multipole starts as a defined zero
     CK(hipMemsetAsync(P->M, 0, sizeof(T) * tot * 2 * P2, st));
@@ -1131,17 +1238,17 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
                 hipLaunchKernelGGL(k_vlist, grid(kept[l]), dim3(tpb), 0, st, lt.off[l], kept[l], l, P->bkey,
                                    P->vcount, P->vsrc, P->vdir);
     if (!adaptive) {
-        CK(hipMalloc(&P->ulist, sizeof(int32_t) * hnb[d] * 27));
+        CK(dev_malloc(&P->ulist, sizeof(int32_t) * hnb[d] * 27));
         hipLaunchKernelGGL(k_ulist, grid(hnb[d]), dim3(tpb), 0, st, lt.off[d], hnb[d], d, P->bkey, P->bcount,
                            P->ulist, dcnt + 1);
         hipLaunchKernelGGL(k_add_i32, dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, (int32_t)lt.off[d]);
     } else {
         // levels, the leaf list in element order, the leaf of every element
         const int64_t nl = P->nleaf;
-        CK(hipMalloc(&P->blev, sizeof(int8_t) * tot));
-        CK(hipMalloc(&P->leaves, sizeof(int32_t) * nl));
-        CK(hipMalloc(&P->nl_start, sizeof(int32_t) * (nl + 1)));
-        CK(hipMalloc(&lcnt, sizeof(int32_t) * (nl + 1)));
+        CK(dev_malloc(&P->blev, sizeof(int8_t) * tot));
+        CK(dev_malloc(&P->leaves, sizeof(int32_t) * nl));
+        CK(dev_malloc(&P->nl_start, sizeof(int32_t) * (nl + 1)));
+        CK(dev_malloc(&lcnt, sizeof(int32_t) * (nl + 1)));
         int32_t *head = flag, *ishead = idx;
         hipLaunchKernelGGL(k_fill_i32, dim3(nblk), dim3(tpb), 0, st, n, head, -1);
         hipLaunchKernelGGL(k_blev, grid(tot), dim3(tpb), 0, st, tot, d, lt, (int64_t)P->max_per_leaf, P->bstart,
@@ -1166,7 +1273,7 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
         int32_t nent = 0;
         CK(hipMemcpyAsync(&nent, P->nl_start + nl, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
-        CK(hipMalloc(&P->nl_ent, sizeof(int32_t) * std::max<int64_t>(nent, 1)));
+        CK(dev_malloc(&P->nl_ent, sizeof(int32_t) * std::max<int64_t>(nent, 1)));
         hipLaunchKernelGGL(k_adlist<1>, grid(nl), dim3(tpb), 0, st, nl, d, lt, P->leaves, P->blev, P->bkey,
                            P->bcount, P->bchild0, P->bnchild, P->nl_start, P->nl_ent, dcnt, P->dflag);
     }
@@ -1406,10 +1513,18 @@ lhf_status lhf_profile_end(lhf_plan *P, double *phase_ms, int32_t *n_exec)
     return LHF_OK;
 }
 
+lhf_status lhf_release_cached_memory(void)
+{
+    lhf::MemCache &m = lhf::mem_cache();
+    std::lock_guard<std::mutex> lk(m.mu);
+    lhf::mem_trim_locked(m, -1, 0);
+    return LHF_OK;
+}
+
 lhf_status lhf_plan_destroy(lhf_plan *P)
 {
     if (!P) return LHF_OK;
-    hipError_t e = hipStreamSynchronize(P->stream);
+    hipError_t e = hipDeviceSynchronize();  // executes may have been queued on any stream
     free_plan(P);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     return LHF_OK;

@@ -230,3 +230,21 @@ def test_half_vector_m2l(oracle, monkeypatch, prec, p):
     else:
         assert ev < 2e-6 and es < 2e-6
         assert _rel(vh, v1) < 2e-6 and _rel(sh, s1) < 2e-6
+
+
+def test_reused_device_blocks(oracle):
+    # a plan built on the blocks of a destroyed one (same sizes) gives the same field as a plan
+    # on fresh blocks; p = 6 runs the deterministic ownership tile, so the comparison is exact
+    import paper_1201_5430_amd as LH
+    rng = np.random.default_rng(77)
+    n = 5000
+    xa, wa = rng.uniform(0, 1, (n, 3)), rng.normal(size=(n, 3))
+    xb, wb = rng.uniform(0, 1, (n, 3)), rng.normal(size=(n, 3))
+    a = 0.5 * n ** (-1 / 3)
+    _gpu_fmm(xa, wa, a, 6, 3)
+    v1, s1, _ = _gpu_fmm(xb, wb, a, 6, 3)  # takes the blocks the first plan left
+    LH.release_cached_memory()
+    v2, s2, _ = _gpu_fmm(xb, wb, a, 6, 3)  # fresh blocks
+    assert np.array_equal(v1, v2) and np.array_equal(s1, s2)
+    vr, sr, _ = oracle.fmm(xb, wb, a, 6, 3)
+    _check(v1, s1, vr, sr)
