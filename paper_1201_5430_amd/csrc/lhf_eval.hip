@@ -684,6 +684,16 @@ __device__ inline void kernel_fg(T r2, T a, int smooth, T &f, T &g)
     const T c = (T)0.79788456080286535588;  // sqrt(2/pi)
     const T ia2 = (T)1 / (a * a);
     const T u = (T)0.5 * r2 * ia2;
+    // far enough out the core is 1 to working precision: 1 - K = erfc(sqrt u) + sqrt(2/pi)(r/a)e^-u
+    // and the relative change of g is sqrt(2/pi) e^-u (r/a)^3 / 3; both stay below 4e-9 for
+    // u >= 24 (FP32) and below 3e-18 for u >= 46 (FP64)
+    if (u >= (sizeof(T) == 4 ? (T)24 : (T)46)) {
+        const T ir = (T)1 / sqrt(r2);
+        const T ir2 = ir * ir;
+        f = ir2 * ir;
+        g = (T)-3 * f * ir2;
+        return;
+    }
     const T ia3 = ia2 / a;
     if (u < (T)0.02) {
         T fs = 0, gs = 0, term = 1, t2 = -1;
