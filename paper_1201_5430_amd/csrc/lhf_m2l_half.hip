@@ -367,37 +367,29 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         //      (chi to order P), then the R-conversion (eq. rcr1, scaled)
         //        phi~ = phi + i tau m/n chi ,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
         {
-            const T itau = (T)1 / tau, itau2 = itau * itau;
+            const T itau = (T)1 / tau;
+            T pw[P + 2];  // tau^-k
+            pw[0] = (T)1;
+#pragma unroll
+            for (int q = 1; q <= P + 1; q++) pw[q] = pw[q - 1] * itau;
             const T wphi = po ? (T)0 : (T)1, wchi = po ? (T)1 : (T)0;
             const T sconv = pp ? (T)1 : (T)-1;
             const T keep0 = hh ? (T)0 : (T)1;  // slot (n = 2c, c) holds m = 2c + h: empty on odd lanes
-            T p0 = (T)1;                      // tau^-(2c), kept as a running product
 #pragma unroll
             for (int c = 0; c < P / 2; c++) {
                 const int n0 = 2 * c;
                 const T mval = (T)(2 * c + hh);
                 T cl[P];
-                {
-                    T pq = p0;
 #pragma unroll
-                    for (int n2 = n0; n2 < P; n2++) {
-                        cl[n2] = v[hoff(n2) + c] * pq;
-                        pq *= itau;
-                    }
-                }
+                for (int n2 = n0; n2 < P; n2++) cl[n2] = v[hoff(n2) + c] * pw[n2];
                 T out[P + 1];
-                {
-                    T pq = p0 * itau;
 #pragma unroll
-                    for (int n = n0; n <= P; n++) {
-                        T a = 0;
+                for (int n = n0; n <= P; n++) {
+                    T a = 0;
 #pragma unroll
-                        for (int n2 = n0; n2 < P; n2++) a += (T)dfact(n + n2) * cl[n2];
-                        out[n] = a * pq;
-                        pq *= itau;
-                    }
+                    for (int n2 = n0; n2 < P; n2++) a += (T)dfact(n + n2) * cl[n2];
+                    out[n] = a * pw[n + 1];
                 }
-                p0 *= itau2;
 #pragma unroll
                 for (int n = n0; n < P; n++) {
                     const T other = swz_xor<6>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
