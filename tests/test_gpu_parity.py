@@ -248,3 +248,21 @@ def test_reused_device_blocks(oracle):
     assert np.array_equal(v1, v2) and np.array_equal(s1, s2)
     vr, sr, _ = oracle.fmm(xb, wb, a, 6, 3)
     _check(v1, s1, vr, sr)
+
+
+@pytest.mark.parametrize("prec,p,depth", [(0, 12, 5), (0, 16, 4), (1, 10, 5)])
+def test_batched_m2m_l2l_match_generic(monkeypatch, prec, p, depth):
+    # the half-vector M2M/L2L kernels (the default at p >= 8) against the generic per-box shifts
+    rng = np.random.default_rng(120 + p)
+    n = 30000
+    x = rng.uniform(0, 1, (n, 3))
+    w = rng.normal(size=(n, 3))
+    a = 0.5 * n ** (-1 / 3)
+    v1, s1, _ = _gpu_fmm(x, w, a, p, depth, precision=prec)
+    monkeypatch.setenv("LHF_NO_MMHALF", "1")
+    v2, s2, _ = _gpu_fmm(x, w, a, p, depth, precision=prec)
+    print(f"batched vs generic M2M/L2L prec={prec} p={p}: {_rel(v1, v2):.3e} {_rel(s1, s2):.3e}", flush=True)
+    if prec == 0:
+        _check(v1, s1, v2, s2, l2=1e-13, mx=1e-12)
+    else:
+        assert _rel(v1, v2) < 2e-6 and _rel(s1, s2) < 2e-6
