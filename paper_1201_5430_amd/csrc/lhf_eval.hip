@@ -734,18 +734,37 @@ struct CompSum {
     __device__ __forceinline__ T value() const { return s + c; }
 };
 
+// one packed element record: position and strength
+template <typename T>
+struct Rec {
+    T x, y, z, wx, wy, wz;
+};
+__device__ __forceinline__ Rec<float> load_rec(const float *__restrict__ xw, int k)
+{
+    const float4 a = *(const float4 *)(xw + 8 * (size_t)k);
+    const float2 b = *(const float2 *)(xw + 8 * (size_t)k + 4);
+    return {a.x, a.y, a.z, a.w, b.x, b.y};
+}
+__device__ __forceinline__ Rec<double> load_rec(const double *__restrict__ xw, int k)
+{
+    const double2 a = *(const double2 *)(xw + 8 * (size_t)k);
+    const double2 b = *(const double2 *)(xw + 8 * (size_t)k + 2);
+    const double2 c = *(const double2 *)(xw + 8 * (size_t)k + 4);
+    return {a.x, a.y, b.x, b.y, c.x, c.y};
+}
+
 // contribution of sorted source k to the target (xj, wj); r = x_j - x_k
 template <typename T>
-__device__ __forceinline__ void p2p_pair(int k, int64_t n, const T *__restrict__ xs, const T *__restrict__ ws, T xj,
-                                         T yj, T zj, T wjx, T wjy, T wjz, T a, int smooth, T &v0, T &v1, T &v2,
-                                         T &s0, T &s1, T &s2)
+__device__ __forceinline__ void p2p_pair(int k, const T *__restrict__ xw, T xj, T yj, T zj, T wjx, T wjy, T wjz,
+                                         T a, int smooth, T &v0, T &v1, T &v2, T &s0, T &s1, T &s2)
 {
-    const T rx = xj - xs[k], ry = yj - xs[n + k], rz = zj - xs[2 * n + k];
+    const Rec<T> q = load_rec(xw, k);
+    const T rx = xj - q.x, ry = yj - q.y, rz = zj - q.z;
     const T r2 = rx * rx + ry * ry + rz * rz;
     if (r2 == (T)0 && !smooth) return;  // coincident distinct points, singular kernel: no contribution
     T f, g;
     kernel_fg<T>(r2, a, smooth, f, g);
-    const T wix = ws[k], wiy = ws[n + k], wiz = ws[2 * n + k];
+    const T wix = q.wx, wiy = q.wy, wiz = q.wz;
     const T cx = wiy * rz - wiz * ry, cy = wiz * rx - wix * rz, cz = wix * ry - wiy * rx;
     const T dd = g * (wjx * rx + wjy * ry + wjz * rz);
     v0 += f * cx;
@@ -765,7 +784,8 @@ __global__ void __launch_bounds__(256) k_p2p_list(int64_t n, const int32_t *__re
                                                   const int32_t *__restrict__ nl_start, const int32_t *__restrict__ nl_ent,
                                                   const uint64_t *__restrict__ bkey, const int32_t *__restrict__ bstart,
                                                   const int32_t *__restrict__ bcount, const T *__restrict__ xs,
-                                                  const T *__restrict__ ws, const double *__restrict__ sys_a, int what,
+                                                  const T *__restrict__ ws, const T *__restrict__ xw,
+                                                  const double *__restrict__ sys_a, int what,
                                                   const T *__restrict__ vfar, const int32_t *__restrict__ perm,
                                                   T *__restrict__ vout, T *__restrict__ sout)
 {
@@ -790,7 +810,7 @@ __global__ void __launch_bounds__(256) k_p2p_list(int64_t n, const int32_t *__re
             for (int e = 0; e < ct; e++) {
                 const int k = st + e;
                 if (k == i) continue;
-                p2p_pair<T>(k, n, xs, ws, xj, yj, zj, wjx, wjy, wjz, a, sm, v0, v1, v2, s0, s1, s2);
+                p2p_pair<T>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, sm, v0, v1, v2, s0, s1, s2);
             }
             acc[0].add(v0);
             acc[1].add(v1);
@@ -814,7 +834,8 @@ __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_
                                              const int32_t *__restrict__ ulist, const uint64_t *__restrict__ bkey,
                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
                                              const T *__restrict__ xs, const T *__restrict__ ws,
-                                             const double *__restrict__ sys_a, int what, const T *__restrict__ vfar,
+                                             const T *__restrict__ xw, const double *__restrict__ sys_a, int what,
+                                             const T *__restrict__ vfar,
                                              const int32_t *__restrict__ perm, T *__restrict__ vout,
                                              T *__restrict__ sout)
 {
@@ -839,7 +860,7 @@ __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_
             for (int e = 0; e < ct; e++) {
                 const int k = st + e;
                 if (k == i) continue;
-                p2p_pair<T>(k, n, xs, ws, xj, yj, zj, wjx, wjy, wjz, a, smooth, v0, v1, v2, s0, s1, s2);
+                p2p_pair<T>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, smooth, v0, v1, v2, s0, s1, s2);
             }
             acc[0].add(v0);
             acc[1].add(v1);
@@ -860,14 +881,26 @@ __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_
 
 // gather omega into the sorted SoA layout
 template <typename T>
-__global__ void k_gather_w(int64_t n, const T *__restrict__ w, const int32_t *__restrict__ perm, T *__restrict__ ws)
+__global__ void k_gather_w(int64_t n, const T *__restrict__ w, const int32_t *__restrict__ perm,
+                           const T *__restrict__ xs, T *__restrict__ ws, T *__restrict__ xw)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int64_t o = perm[i];
-    ws[i] = w[3 * o];
-    ws[n + i] = w[3 * o + 1];
-    ws[2 * n + i] = w[3 * o + 2];
+    const T wx = w[3 * o], wy = w[3 * o + 1], wz = w[3 * o + 2];
+    ws[i] = wx;
+    ws[n + i] = wy;
+    ws[2 * n + i] = wz;
+    // the near field reads an element as one record (two 16-byte loads in FP32, three in FP64)
+    T *r = xw + 8 * i;
+    r[0] = xs[i];
+    r[1] = xs[n + i];
+    r[2] = xs[2 * n + i];
+    r[3] = wx;
+    r[4] = wy;
+    r[5] = wz;
+    r[6] = (T)0;
+    r[7] = (T)0;
 }
 
 template <typename T>
@@ -887,7 +920,8 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
-    hipLaunchKernelGGL(k_gather_w<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)omega, P->perm, ws);
+    hipLaunchKernelGGL(k_gather_w<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)omega, P->perm, (const T *)xs, ws,
+                       (T *)P->xw);
     mark(1);
     // uniform tree: the leaves are the boxes of level d; adaptive: the explicit leaf list
     const int64_t loff = P->lev[d].off, nleaf = P->adaptive ? P->nleaf : P->lev[d].nb;
@@ -951,12 +985,12 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
     mark(5);
     if (P->adaptive)
         hipLaunchKernelGGL(k_p2p_list<T>, dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, P->leaves, P->blev, P->nl_start,
-                           P->nl_ent, P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, P->sys_a, what,
-                           (const T *)vfar, P->perm, (T *)v, (T *)s);
+                           P->nl_ent, P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws,
+                           (const T *)P->xw, P->sys_a, what, (const T *)vfar, P->perm, (T *)v, (T *)s);
     else
         hipLaunchKernelGGL(k_p2p<T>, dim3(nblk), dim3(tpb), 0, st, n, d, loff, P->eleaf, P->ulist, P->bkey,
-                           P->bstart, P->bcount, (const T *)xs, (const T *)ws, P->sys_a, what, (const T *)vfar,
-                           P->perm, (T *)v, (T *)s);
+                           P->bstart, P->bcount, (const T *)xs, (const T *)ws, (const T *)P->xw, P->sys_a, what,
+                           (const T *)vfar, P->perm, (T *)v, (T *)s);
     mark(6);
     LHF_HIP(hipGetLastError());
     return LHF_OK;

@@ -86,6 +86,7 @@ struct lhf_plan {
     void *xs = nullptr;          // sorted coordinates, SoA [3][n], T
     void *ws = nullptr;          // sorted strengths, SoA [3][n], T (filled by execute)
     void *vfar = nullptr;        // far-field v, s in sorted order, SoA [6][n], T
+    void *xw = nullptr;          // sorted elements packed for the near field: [n][8] T = x y z wx wy wz - -
     uint64_t *bkey = nullptr;    // [nbox] Morton key of every box (level-local)
     int32_t *bstart = nullptr;   // [nbox] first sorted element
     int32_t *bcount = nullptr;   // [nbox] number of elements

@@ -1028,7 +1028,7 @@ static void free_plan(lhf_plan *P)
     // on any stream may still use them
     (void)hipDeviceSynchronize();
     free_profile(P);
-    void *bufs[] = {P->perm, P->xs, P->ws, P->vfar, P->bkey, P->bstart, P->bcount, P->bparent, P->bchild0,
+    void *bufs[] = {P->perm, P->xs, P->ws, P->vfar, P->xw, P->bkey, P->bstart, P->bcount, P->bparent, P->bchild0,
                     P->bnchild, P->vcount, P->vsrc, P->vdir, P->ulist, P->eleaf, P->M, P->Lc, P->rot,
                     P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp, P->sys_geo, P->sys_a, P->sys_off,
                     P->blev, P->leaves, P->nl_start, P->nl_ent};
@@ -1122,6 +1122,7 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(dev_malloc(&P->xs, sizeof(T) * 3 * n));
     CK(dev_malloc(&P->ws, sizeof(T) * 3 * n));
     CK(dev_malloc(&P->vfar, sizeof(T) * 6 * n));
+    CK(dev_malloc(&P->xw, sizeof(T) * 8 * n));
     CK(dev_malloc(&P->eleaf, sizeof(int32_t) * n));
     hipLaunchKernelGGL(k_gather_x<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)x, P->perm, (T *)P->xs);
     // ---- every non-empty box of every level
