@@ -135,6 +135,8 @@ struct lhf_plan {
     bool use_mfma = false;               // matrix-core M2L (same schedule and box maps)
     bool use_half = false;               // VALU M2L with each vector split over two lanes (large p)
     void *whalf = nullptr;               // its rotation tables
+    void *mh = nullptr;                  // its sources, one level at a time, in its lane layout
+    double *dtab = nullptr;              // its per-direction |t|, 1/|t|, e^{i phi} ([343][4])
     bool use_mmhalf = false;             // batched M2M and L2L in the same layout
     void *wmm = nullptr, *wll = nullptr; // their rotation tables (S basis, R basis)
     bool tile2 = false;                  // VALU tile with two schedule rows per batch (FP32 p = 8, 10)

@@ -1,5 +1,5 @@
 // lhf_m2l_half.hip -- batched M2L with each translation's coefficient vector split over two
-// lanes by the parity of m (the large orders: FP64 p = 8, 10, 12; FP32 p = 12, 16).
+// lanes by the parity of m (p = 8, 10, 12, 16 in both precisions).
 //
 // The translation is the same as in the one-lane tile kernel: rotation about z and y,
 // coaxial (S|R) shift, R-conversion (eq. rcr1), back-rotation (Sec. 4.4), for both
@@ -16,7 +16,10 @@
 //     columns for its own output rows (o) and for its partner's rows (t), and a DPP pair swap
 //     adds the partner's t to the lane's o.  The rotation blocks are stored per (kind, part,
 //     parity) as [o rows | t rows] x own columns, zero where m or m' exceeds n.
-// Slots of odd lanes whose m exceeds n (even n) stay zero and are never accumulated.
+// Slots of odd lanes whose m exceeds n (even n) stay zero and are never read back.
+// The sources of a level are first copied into the same lane layout (k_mhalf), so a lane
+// loads its entries as whole 16-byte vectors from one address; in shared mode the LDS
+// accumulators of the targets use it too, so the accumulation needs no per-entry selects.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,9 +60,23 @@ struct Shape {
     // at once (part x parity) start in different LDS banks
     static constexpr int WHS = WH + E<T>();
     static constexpr int P2 = P * P;
-    static constexpr int POS = P2 + 1;        // potential stride in the LDS accumulator (phi, chi apart)
-    static constexpr int SST = 2 * POS + 1;   // odd slot stride: slots fall in different LDS banks
+    // one lane's entries padded to whole 16-byte vectors: the stride of the source layout
+    static constexpr int NHP = (NH + E<T>() - 1) / E<T>() * E<T>();
 };
+
+// packed (phi, chi) expansion [pot][n^2 + (Re: m | Im: n + m)] -> lane layout
+// [role = 4 pot + 2 part + h][RS] (RS >= hoff(P)): position of packed index k
+template <int P, int RS>
+__device__ inline int entry_lane(int k)
+{
+    const int pot = k / (P * P), q = k % (P * P);
+    int n = (int)sqrtf((float)q);  // floor(sqrt(q)), corrected for rounding
+    if ((n + 1) * (n + 1) <= q) n++;
+    if (n * n > q) n--;
+    const int i = q - n * n, part = i > n, m = part ? i - n : i;
+    const int a = n >> 1, hn = (n & 1) ? (a + 1) * (a + 1) : a * (a + 1);  // hoff(n)
+    return (4 * pot + 2 * part + (m & 1)) * RS + hn + (m >> 1);
+}
 
 template <typename T>
 struct V16;
@@ -104,12 +121,65 @@ struct AccT<T, true> {
 template <typename T, bool OWN>
 using Acc = typename AccT<T, OWN>::type;
 
+// LDS accumulator of a target: the lane layout [role = 4 pot + 2 part + h][rs], one target
+// every ss entries.  A wavefront instruction accumulates one entry for 8 targets x 8 roles;
+// rs >= hoff(P) and ss >= 8 rs are the smallest paddings that spread those 64 addresses most
+// evenly over 32 (first) and 64 (then) four-byte LDS banks
+struct AccStride {
+    int rs, ss;
+};
+constexpr int bank_load(int rs, int ss, int words, int nb)
+{
+    int cnt[64] = {};
+    for (int t = 0; t < 8; t++)
+        for (int r = 0; r < 8; r++)
+            for (int k = 0; k < words; k++) cnt[((t * ss + r * rs) * words + k) % nb]++;
+    int mx = 0;
+    for (int b = 0; b < nb; b++) mx = cnt[b] > mx ? cnt[b] : mx;
+    return mx;
+}
+constexpr AccStride acc_stride(int nh, int words)
+{
+    AccStride best{nh, 8 * nh + 1};
+    int bc = 1 << 30;
+    for (int d = 0; d <= 4; d++)
+        for (int e = 1; e <= 20; e++) {
+            const int rs = nh + d, ss = 8 * rs + e;
+            const int c = (bank_load(rs, ss, words, 32) * 128 + bank_load(rs, ss, words, 64)) * 256 + 8 * d + e;
+            if (c < bc) {
+                bc = c;
+                best = AccStride{rs, ss};
+            }
+        }
+    return best;
+}
+template <typename T, int P, bool OWN>
+constexpr AccStride acc_stride()
+{
+    return acc_stride(hoff(P), (int)sizeof(Acc<T, OWN>) / 4);
+}
+// entries per target slot.  Ownership mode keeps the packed order ([pot][P^2 + 1], odd slot
+// stride), which is 15-20% smaller: at FP32 p = 10 it lets four workgroups share a compute
+// unit instead of three (M2L on the 2^20 cube 25.3 against 26.6 ms)
+template <typename T, int P, bool OWN>
+constexpr int acc_slot()
+{
+    return OWN ? 2 * (P * P + 1) + 1 : acc_stride<T, P, OWN>().ss;
+}
+// position inside a slot of packed index k (0 <= k < 2 P^2)
+template <int P, bool OWN, int RS>
+__device__ inline int acc_pos(int k)
+{
+    if constexpr (OWN) return k >= P * P ? k + 1 : k;
+    else return entry_lane<P, RS>(k);
+}
+
 // LDS footprint of a tile of NPAR sibling groups
 template <typename T, int P, bool OWN>
 constexpr size_t tile_bytes(int npar)
 {
     using Sh = Shape<T, P>;
-    return sizeof(T) * 8 * (size_t)Sh::WHS + sizeof(Acc<T, OWN>) * (size_t)(8 * npar + 1) * Sh::SST +
+    return sizeof(T) * 8 * (size_t)Sh::WHS + sizeof(Acc<T, OWN>) * (size_t)(8 * npar + 1) * acc_slot<T, P, OWN>() +
            sizeof(int) * 3 * 8 * npar + sizeof(int16_t) * (64 + (OWN ? 0 : 1512));
 }
 // two workgroups per compute unit (160 KB of LDS)
@@ -148,22 +218,25 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
                                                   const uint64_t *__restrict__ bkey,
                                                   const int32_t *__restrict__ bchild0,
                                                   const int32_t *__restrict__ bnchild,
-                                                  const int32_t *__restrict__ dmap, const T *__restrict__ M,
-                                                  T *__restrict__ Lc, const T *__restrict__ wh, int64_t wstride,
-                                                  M2LSched sch, const int16_t *__restrict__ cls_theta)
+                                                  const int32_t *__restrict__ dmap, const T *__restrict__ Mh,
+                                                  int64_t soff, T *__restrict__ Lc, const T *__restrict__ wh,
+                                                  int64_t wstride, M2LSched sch,
+                                                  const int16_t *__restrict__ cls_theta,
+                                                  const double *__restrict__ dtab)
 {
     using Sh = hv::Shape<T, P>;
     using hv::hoff;
     using hv::S;
-    constexpr int P2 = Sh::P2, SST = Sh::SST, NH = Sh::NH, POS = Sh::POS;
+    constexpr int P2 = Sh::P2, NH = Sh::NH, NHP = Sh::NHP;
+    constexpr int ARS = hv::acc_stride<T, P, OWN>().rs, SSTA = hv::acc_slot<T, P, OWN>();
     constexpr int NSLOT = 8 * NPAR;
     constexpr int NENT = 1512;  // schedule entries of one sibling group
     extern __shared__ char smem[];
     using A = hv::Acc<T, OWN>;
     static_assert(!OWN || NPAR == 4, "ownership mode: one sibling group per wavefront");
     T *Wl = (T *)smem;                                // [kind: fwd S, back R][part][parity][WHS]
-    A *acc = (A *)(Wl + 8 * Sh::WHS);                 // [NSLOT + 1][SST]: [pot][POS] (last slot absorbs)
-    int *slot_xyz = (int *)(acc + (NSLOT + 1) * SST);  // [NSLOT] packed target coordinates, -1: no box
+    A *acc = (A *)(Wl + 8 * Sh::WHS);                 // [NSLOT + 1][SSTA] (last slot absorbs)
+    int *slot_xyz = (int *)(acc + (NSLOT + 1) * SSTA);  // [NSLOT] packed target coordinates, -1: no box
     int *slot_box = slot_xyz + NSLOT;                 // [NSLOT] target box
     int *slot_sys = slot_box + NSLOT;                 // [NSLOT] system of the target
     int16_t *cst = (int16_t *)(slot_sys + NSLOT);     // [ncls + 1] class starts
@@ -210,10 +283,14 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         for (int i = tid; i < NENT; i += 256) ent[i] = (int16_t)((sch.ent_dir[i] << 3) | sch.ent_c[i]);
     for (int i = tid; i <= ncls; i += 256) cst[i] = OWN ? sch.row_start[i] : sch.cls_start[i];
     __syncthreads();
+    // local expansions of the targets into their slots (shared mode: the lane layout, whose
+    // entries without an (n, m) start at zero and are never read back)
+    for (int idx = tid; idx < NSLOT * SSTA; idx += 256) acc[idx] = (A)0;
+    __syncthreads();
     for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
-        acc[sl * SST + (r >= P2 ? POS - P2 : 0) + r] = box >= 0 ? (A)Lc[(size_t)box * 2 * P2 + r] : (A)0;
+        if (box >= 0) acc[sl * SSTA + hv::acc_pos<P, OWN, ARS>(r)] = (A)Lc[(size_t)box * 2 * P2 + r];
     }
 
     const int side = 1 << level;
@@ -259,19 +336,20 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
             r0 = 0;
         }
     };
-    // this lane's entries of the source: order n, m = 2j + h; zero where m > n or (Im, m = 0)
-    auto load_part = [&](const Job &j, T *dst, int hh, int pp, int po) {
-        const T *sp = M + (size_t)(j.src >= 0 ? j.src : 0) * 2 * P2 + po * P2;
+    // this lane's entries of the source (order n, m = 2j + h; zeros where m > n or (Im, m = 0)),
+    // stored contiguously per lane role by k_mhalf: whole 16-byte vectors from one address
+    auto load_part = [&](const Job &j, T *dst) {
+        using V = typename hv::V16<T>::type;
+        constexpr int e = hv::E<T>();
+        const V *sp = (const V *)(Mh + ((size_t)(j.src >= 0 ? j.src - soff : 0) * 8 + (lane & 7)) * NHP);
 #pragma unroll
-        for (int n = 0; n < P; n++)
+        for (int q = 0; q < NHP / e; q++) {
+            const V x = sp[q];
+            const T *xp = (const T *)&x;
 #pragma unroll
-            for (int jj = 0; jj < S(n); jj++) {
-                const int m = 2 * jj + hh;
-                const bool ok = m <= n && !(pp && m == 0);
-                const int off = ok ? n * n + (pp ? n : 0) + m : 0;
-                const T x = sp[off];
-                dst[hoff(n) + jj] = ok ? x : (T)0;
-            }
+            for (int k = 0; k < e; k++)
+                if (q * e + k < NH) dst[q * e + k] = xp[k];
+        }
     };
 
     int k = 0, r0 = 0;   // current batch
@@ -311,20 +389,12 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         const Job nn = setup(k2, r2);
         if (__ballot(act) != 0ull) {  // wavefront-uniform: skip batches with no active lane
         T v[NH];
-        load_part(j, v, hh, pp, po);
+        load_part(j, v);
 
-        const int dir = j.dir;
-        const int dx = dir % 7 - 3, dy = (dir / 7) % 7 - 3, dz = dir / 49 - 3;
-        const T tau = (T)sqrt((double)(dx * dx + dy * dy + dz * dz));
-        // e^{i phi} of the direction (phi = atan2(dy, dx); 0 on the z axis), FP64
-        double cph = 1.0, sph = 0.0;
-        {
-            const double rho = sqrt((double)(dx * dx + dy * dy));
-            if (rho > 0.0) {
-                cph = (double)dx / rho;
-                sph = (double)dy / rho;
-            }
-        }
+        // |t|, 1/|t| and e^{i phi} of the direction, from the plan's table (FP64)
+        const double2 d0 = ((const double2 *)dtab)[2 * j.dir], d1 = ((const double2 *)dtab)[2 * j.dir + 1];
+        const T tau = (T)d0.x, itau = (T)d0.y;
+        const double cph = d1.x, sph = d1.y;
         const double c2 = cph * cph - sph * sph, s2 = 2.0 * cph * sph;  // e^{2 i phi}
         // 1. rotate about z by +phi: Re' = re c - im s, Im' = im c + re s (m = 2j + h)
         {
@@ -367,7 +437,6 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         //      (chi to order P), then the R-conversion (eq. rcr1, scaled)
         //        phi~ = phi + i tau m/n chi ,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
         {
-            const T itau = (T)1 / tau;
             T pw[P + 2];  // tau^-k
             pw[0] = (T)1;
 #pragma unroll
@@ -404,10 +473,10 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         }
         rotate_y(Wb);
         // 6. back-rotation about z (-phi) and accumulation into the target slot (inactive lanes
-        //    and empty entries add into the spare slot)
+        //    add into the spare slot; in ownership mode so do entries without an (n, m))
         {
-            A *ap = acc + (size_t)(act ? j.slot : NSLOT) * SST + po * POS;
-            A *spare = acc + (size_t)NSLOT * SST + po * POS;
+            A *ap = acc + (size_t)(act ? j.slot : NSLOT) * SSTA + (OWN ? po * (P2 + 1) : (lane & 7) * ARS);
+            A *spare = acc + (size_t)NSLOT * SSTA + (OWN ? po * (P2 + 1) : 0);
             const T sgn = pp ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
             double cm = hh ? cph : 1.0, sm = hh ? sph : 0.0;
 #pragma unroll
@@ -424,11 +493,13 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
                     const T x = v[hoff(n) + jj];
                     const T o = dpp_f<DPP_XOR2>(x);
                     const T val = x * cz + o * sz;
-                    const bool ok = m <= n && !(pp && m == 0);
-                    const int off = n * n + (pp ? n : 0) + m;  // < P^2 also where !ok
-                    A *dst = (ok ? ap : spare) + off;
-                    if (OWN) *dst += (A)val;
-                    else atomicAdd(dst, (A)val);
+                    if constexpr (OWN) {
+                        const bool ok = m <= n && !(pp && m == 0);
+                        const int off = n * n + (pp ? n : 0) + m;  // < P^2 also where !ok
+                        *((ok ? ap : spare) + off) += (A)val;
+                    } else {
+                        atomicAdd(ap + hoff(n) + jj, (A)val);
+                    }
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -446,8 +517,49 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
-        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = (T)acc[sl * SST + (r >= P2 ? POS - P2 : 0) + r];
+        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = (T)acc[sl * SSTA + hv::acc_pos<P, OWN, ARS>(r)];
     }
+}
+
+// the sources of one level in the lane layout of the half-vector M2L: box b of the level at
+// Mh[(b * 8 + role) * NHP], role = 4 pot + 2 part + h (the lane's low three bits), entry
+// hoff(n) + j = order n, m = 2j + h of that potential and part; zero where m > n, for (Im, m = 0)
+// and in the padding
+template <typename T, int P>
+__global__ void k_mhalf(int64_t off, int64_t nb, const T *__restrict__ M, T *__restrict__ Mh)
+{
+    using Sh = hv::Shape<T, P>;
+    constexpr int NHP = Sh::NHP, NH = Sh::NH, P2 = P * P;
+    const int64_t total = nb * 8 * NHP;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / (8 * NHP);
+        const int rr = (int)(i % (8 * NHP)), r = rr / NHP, e = rr % NHP;
+        const int pot = r >> 2, part = (r >> 1) & 1, h = r & 1;
+        T val = 0;
+        if (e < NH) {
+            int n = 0;
+            while (hv::hoff(n + 1) <= e) n++;
+            const int m = 2 * (e - hv::hoff(n)) + h;
+            if (m <= n && !(part && m == 0))
+                val = M[(size_t)(off + b) * 2 * P2 + pot * P2 + n * n + (part ? n : 0) + m];
+        }
+        Mh[i] = val;
+    }
+}
+
+// per direction code d = (dz + 3) 49 + (dy + 3) 7 + dx + 3 of a translation t = (dx, dy, dz) (in
+// box sides): |t|, 1/|t| and e^{i phi} = (dx + i dy)/sqrt(dx^2 + dy^2) (1 on the z axis), FP64
+__global__ void k_dirtab(double *__restrict__ tab)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= 343) return;
+    const int dx = d % 7 - 3, dy = (d / 7) % 7 - 3, dz = d / 49 - 3;
+    const double tau = sqrt((double)(dx * dx + dy * dy + dz * dz));
+    const double rho = sqrt((double)(dx * dx + dy * dy));
+    tab[4 * d + 0] = tau;
+    tab[4 * d + 1] = tau > 0.0 ? 1.0 / tau : 0.0;
+    tab[4 * d + 2] = rho > 0.0 ? (double)dx / rho : 1.0;
+    tab[4 * d + 3] = rho > 0.0 ? (double)dy / rho : 0.0;
 }
 
 // Rotation tables of every polar-angle class in the half-vector layout:
@@ -758,6 +870,12 @@ static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
     if (dev_malloc(&Pl->whalf, sizeof(T) * stride * Pl->n_theta) != hipSuccess) return false;
     k_whalf<T, P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const T *)Pl->rot, (T *)Pl->whalf, stride,
                                                                       ROT_S_FWD, ROT_R_BACK);
+    if (dev_malloc(&Pl->dtab, sizeof(double) * 4 * 343) != hipSuccess) return false;
+    k_dirtab<<<dim3(2), dim3(256), 0, st>>>(Pl->dtab);
+    // sources in the kernel's lane layout, one level at a time: room for the largest level
+    int64_t nbmax = 0;
+    for (int l = 2; l <= Pl->depth; l++) nbmax = std::max(nbmax, Pl->lev[l].nb);
+    if (nbmax > 0 && dev_malloc(&Pl->mh, sizeof(T) * 8 * hv::Shape<T, P>::NHP * nbmax) != hipSuccess) return false;
     return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, OWN>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess;
 }
@@ -768,14 +886,20 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
     constexpr int NPAR = hv::tile_npar<T, P>();
     constexpr bool OWN = hv::tile_own<T, P>();
     const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
+    const int64_t soff = Pl->lev[level].off, nb = Pl->lev[level].nb;
+    if (nb == 0 || npar == 0) return;
+    // the level's sources in the lane layout
+    const int64_t cnt = nb * 8 * hv::Shape<T, P>::NHP;
+    k_mhalf<T, P><<<dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 16384)), dim3(256), 0, st>>>(
+        soff, nb, (const T *)Pl->M, (T *)Pl->mh);
     const int64_t ntiles = (npar + NPAR - 1) / NPAR;
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
     k_m2l_half<T, P, NPAR, OWN><<<dim3((unsigned)(per * 8)), dim3(256),
                                                           hv::tile_bytes<T, P, OWN>(NPAR),
                                                      st>>>(
-        level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const T *)Pl->M, (T *)Pl->Lc,
-        (const T *)Pl->whalf, 8 * (int64_t)hv::Shape<T, P>::WHS, sch, Pl->sched_cls_theta);
+        level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const T *)Pl->mh, soff,
+        (T *)Pl->Lc, (const T *)Pl->whalf, 8 * (int64_t)hv::Shape<T, P>::WHS, sch, Pl->sched_cls_theta, Pl->dtab);
 }
 
 // rotation tables of the M2M (S basis both ways) and L2L (R basis both ways) shifts

@@ -1037,7 +1037,7 @@ static void free_plan(lhf_plan *P)
     for (int l = 0; l <= MAXDEPTH; l++)
         if (P->dmap[l]) (void)dev_free(P->dmap[l]);
     void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta, P->wpad, P->sched_row_start,
-                  P->sched_rows, P->wmfma, P->whalf, P->wmm, P->wll};
+                  P->sched_rows, P->wmfma, P->whalf, P->mh, P->dtab, P->wmm, P->wll};
     for (void *b : sb)
         if (b) (void)dev_free(b);
     delete P;
