@@ -426,7 +426,10 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
                 for (int jj = 0; jj < S(n); jj++) {
                     o[jj] = hv::dotw<T>(Wn + jj * hv::RL<T>(n), &v[hoff(n)], S(n));
                     tt[jj] = hv::dotw<T>(Wn + (S(n) + jj) * hv::RL<T>(n), &v[hoff(n)], S(n));
-                    asm volatile("" : "+v"(o[jj]), "+v"(tt[jj]));
+                    // at one wavefront per SIMD (FP64 p = 16) finish each pair of rows before the
+                    // next: 251 against 329 ms of M2L on the 4M ring; elsewhere the scheduler's
+                    // own interleaving is faster
+                    if constexpr (hv::min_waves<T, P>() == 1) asm volatile("" : "+v"(o[jj]), "+v"(tt[jj]));
                 }
 #pragma unroll
                 for (int jj = 0; jj < S(n); jj++) v[hoff(n) + jj] = o[jj] + dpp_f<DPP_XOR1>(tt[jj]);
@@ -468,7 +471,10 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
                     if (n == n0) val *= keep0;
                     v[hoff(n) + c] = val;
                 }
-                __builtin_amdgcn_sched_barrier(0);
+                // FP32 and FP64 p = 16: one column at a time (FP32 p = 16 on the 4M ring: 107 ms
+                // with this fence, 109 ms without); FP64 p = 12 gains from interleaving columns
+                // with the y-rotations' LDS reads (2^20 cube: 59.3 -> 50.4 ms without it)
+                if constexpr (sizeof(T) == 4 || hv::min_waves<T, P>() == 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
         rotate_y(Wb);
