@@ -25,6 +25,7 @@ namespace lhf {
 void m2l_tile_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_mfma_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
+void m2l_half_stage(const lhf_plan *Pl, int level, hipStream_t st);
 void m2m_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void l2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 
@@ -954,6 +955,9 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
                     hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 0,
                                        P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M,
                                        Lc, rot, zph, P->dir_theta, coax);
+                // the half-vector kernel reads its sources from a copy in its lane layout
+                // (timed with L2L, outside the M2L phase)
+                if (!P->use_mfma && P->use_half) m2l_half_stage(P, l, st);
                 mark(7 + 2 * l);
                 if (P->use_mfma) m2l_mfma_launch(P, l, st);
                 else if (P->use_half) m2l_half_launch(P, l, st);

@@ -532,24 +532,32 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
 // hoff(n) + j = order n, m = 2j + h of that potential and part; zero where m > n, for (Im, m = 0)
 // and in the padding
 template <typename T, int P>
-__global__ void k_mhalf(int64_t off, int64_t nb, const T *__restrict__ M, T *__restrict__ Mh)
+__global__ void __launch_bounds__(256) k_mhalf(int64_t off, int64_t nb, const T *__restrict__ M, T *__restrict__ Mh)
 {
     using Sh = hv::Shape<T, P>;
-    constexpr int NHP = Sh::NHP, NH = Sh::NH, P2 = P * P;
-    const int64_t total = nb * 8 * NHP;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = i / (8 * NHP);
-        const int rr = (int)(i % (8 * NHP)), r = rr / NHP, e = rr % NHP;
+    constexpr int NHP = Sh::NHP, NH = Sh::NH, NE = 8 * NHP, P2 = P * P;
+    // packed index of every lane-layout entry of a box (-1: zero)
+    __shared__ int16_t src[NE];
+    for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+        const int r = t / NHP, e = t % NHP;
         const int pot = r >> 2, part = (r >> 1) & 1, h = r & 1;
-        T val = 0;
+        int k = -1;
         if (e < NH) {
             int n = 0;
             while (hv::hoff(n + 1) <= e) n++;
             const int m = 2 * (e - hv::hoff(n)) + h;
-            if (m <= n && !(part && m == 0))
-                val = M[(size_t)(off + b) * 2 * P2 + pot * P2 + n * n + (part ? n : 0) + m];
+            if (m <= n && !(part && m == 0)) k = pot * P2 + n * n + (part ? n : 0) + m;
         }
-        Mh[i] = val;
+        src[t] = (int16_t)k;
+    }
+    __syncthreads();
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const T *mb = M + (size_t)(off + b) * 2 * P2;
+        T *hb = Mh + (size_t)b * NE;
+        for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+            const int k = src[t];
+            hb[t] = k >= 0 ? mb[k] : (T)0;
+        }
     }
 }
 
@@ -894,10 +902,6 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
     const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
     const int64_t soff = Pl->lev[level].off, nb = Pl->lev[level].nb;
     if (nb == 0 || npar == 0) return;
-    // the level's sources in the lane layout
-    const int64_t cnt = nb * 8 * hv::Shape<T, P>::NHP;
-    k_mhalf<T, P><<<dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 16384)), dim3(256), 0, st>>>(
-        soff, nb, (const T *)Pl->M, (T *)Pl->mh);
     const int64_t ntiles = (npar + NPAR - 1) / NPAR;
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
@@ -906,6 +910,16 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
                                                      st>>>(
         level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const T *)Pl->mh, soff,
         (T *)Pl->Lc, (const T *)Pl->whalf, 8 * (int64_t)hv::Shape<T, P>::WHS, sch, Pl->sched_cls_theta, Pl->dtab);
+}
+
+// the sources of level l in the half-vector kernel's lane layout
+template <typename T, int P>
+static void stage_half(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    const int64_t nb = Pl->lev[level].nb;
+    if (nb == 0) return;
+    k_mhalf<T, P><<<dim3((unsigned)std::min<int64_t>(nb, 8192)), dim3(256), 0, st>>>(Pl->lev[level].off, nb,
+                                                                                     (const T *)Pl->M, (T *)Pl->mh);
 }
 
 // rotation tables of the M2M (S basis both ways) and L2L (R basis both ways) shifts
@@ -1031,6 +1045,25 @@ bool whalf_build(lhf_plan *Pl, hipStream_t st)
         }
     }
     return false;
+}
+
+void m2l_half_stage(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    if (Pl->precision == LHF_FP64) {
+        switch (Pl->p) {
+        case 8: stage_half<double, 8>(Pl, level, st); break;
+        case 10: stage_half<double, 10>(Pl, level, st); break;
+        case 12: stage_half<double, 12>(Pl, level, st); break;
+        case 16: stage_half<double, 16>(Pl, level, st); break;
+        }
+    } else {
+        switch (Pl->p) {
+        case 8: stage_half<float, 8>(Pl, level, st); break;
+        case 10: stage_half<float, 10>(Pl, level, st); break;
+        case 12: stage_half<float, 12>(Pl, level, st); break;
+        case 16: stage_half<float, 16>(Pl, level, st); break;
+        }
+    }
 }
 
 void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st)
