@@ -356,27 +356,44 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     int k1 = 0, r1 = 0;  // next batch
     advance(k1, r1);
     Job cur = setup(k, r0), nxt = setup(k1, r1);
-    int staged = -1;
+    // the rotation tables of one class, staged in LDS with 16-byte loads.  Where registers
+    // allow, a batch whose successor starts a new class loads the new tables into registers
+    // first, so that they arrive during the batch and only the LDS write sits between the
+    // two barriers of the class change
+    constexpr int N16 = (int)(8 * Sh::WHS * sizeof(T) / 16);
+    constexpr bool PREF = hv::min_waves<T, P>() > 1;
+    constexpr int NPF = PREF ? (N16 + 255) / 256 : 1;
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 pf[NPF];
+    auto fetch = [&](int kc) __attribute__((always_inline)) {
+        const u32x4 *src4 = (const u32x4 *)(wh + (size_t)cls_theta[kc] * wstride);
+#pragma unroll
+        for (int q = 0; q < NPF; q++) pf[q] = src4[q * 256 + tid < N16 ? q * 256 + tid : 0];
+    };
+    int staged = -1, fetched = -1;
     while (k < ncls) {
         if (k != staged) {
-            // stage the class's rotation tables with 16-byte loads
             __syncthreads();
-            const uint4 *src4 = (const uint4 *)(wh + (size_t)cls_theta[k] * wstride);
             uint4 *dst4 = (uint4 *)Wl;
-            constexpr int N16 = (int)(8 * Sh::WHS * sizeof(T) / 16);
+            if constexpr (PREF) {
+                if (fetched != k) fetch(k);
+#pragma unroll
+                for (int q = 0; q < NPF; q++)
+                    if (tid + 256 * q < N16) ((u32x4 *)dst4)[tid + 256 * q] = pf[q];
+            } else {
+                const uint4 *src4 = (const uint4 *)(wh + (size_t)cls_theta[k] * wstride);
 #pragma unroll 4
-            for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
+                for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
+            }
             __syncthreads();
             staged = k;
         }
-        // opaque per-batch offset: keeps the compiler from hoisting the class's rotation
-        // entries out of the batch loop
-        // ownership mode: the lane's role (parity, part, potential) is made opaque per batch as
-        // well, so the compiler recomputes the per-lane constants derived from it instead of
-        // holding them all in registers (FP32 p = 10: 143 -> 107 VGPRs, 30.4 -> 27.2 ms on the
-        // 2^20 cube); in shared mode that trade costs SGPR spills and time
-        int wo = (part * 2 + h) * Sh::WHS, hh = h, pp = part, po = pot;
-        asm volatile("" : "+v"(wo));
+        // ownership mode: the lane's role (parity, part, potential) is made opaque per batch, so
+        // the compiler recomputes the per-lane constants derived from it instead of holding
+        // them all in registers (FP32 p = 10: 143 -> 107 VGPRs, 30.4 -> 27.2 ms on the 2^20
+        // cube); in shared mode that trade costs SGPR spills and time
+        const int wo = (part * 2 + h) * Sh::WHS;
+        int hh = h, pp = part, po = pot;
         if (OWN) asm volatile("" : "+v"(hh), "+v"(pp), "+v"(po));
         const T *Wf = Wl + wo;
         const T *Wb = Wl + 4 * Sh::WHS + wo;
@@ -387,6 +404,12 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         int k2 = k1, r2 = r1;
         advance(k2, r2);
         const Job nn = setup(k2, r2);
+        if constexpr (PREF) {
+            if (k1 != k && k1 < ncls) {  // the next batch starts a new class
+                fetch(k1);
+                fetched = k1;
+            }
+        }
         if (__ballot(act) != 0ull) {  // wavefront-uniform: skip batches with no active lane
         T v[NH];
         load_part(j, v);
