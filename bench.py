@@ -291,7 +291,7 @@ def main():
                     help="only copy a buffer of this many MiB on the device (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

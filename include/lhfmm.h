@@ -60,7 +60,7 @@ typedef enum {
     LHF_ERR_DOMAIN = -2,      /* an element lies outside [lo, lo+L]^3 */
     LHF_ERR_NONFINITE = -3,   /* non-finite coordinate */
     LHF_ERR_HIP = -5,         /* a HIP runtime call failed */
-    LHF_ERR_UNSUPPORTED = -6, /* valid but not supported by this build */
+    LHF_ERR_UNSUPPORTED = -6, /* valid but not supported by this library version */
     LHF_ERR_STATE = -7        /* plan used inconsistently */
 } lhf_status;
 
