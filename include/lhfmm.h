@@ -35,7 +35,7 @@
  *  - Errors: a negative status means nothing was written; lhf_last_error()
  *    returns a thread-local message.  Argument checks run on the host before
  *    any launch.  A positive status is a warning with valid outputs.
- *  - Ownership: the caller owns x, omega, v, s.  The plan owns its own device
+ *  - Ownership: the caller owns x, omega, v, s, grad_v.  The plan owns its own device
  *    buffers (sorted elements, tree, expansions, operator tables) and copies
  *    what it needs from x, so x may be freed after lhf_plan_create.
  */
@@ -56,9 +56,12 @@ typedef enum {
     LHF_OK = 0,
     LHF_WARN_CORE_SPLIT = 1,  /* 1 - K(r_far_min; a) > tol: the far field's singular kernel
                                  differs from the smoothed one by more than tol */
+    LHF_WARN_TOL_UNMET = 2,   /* p = 0 was requested and no order this library offers reaches tol
+                                 by the calibration table (the largest order is used) */
     LHF_ERR_ARG = -1,         /* invalid argument (N, p, a, depth, pointers, precision) */
     LHF_ERR_DOMAIN = -2,      /* an element lies outside [lo, lo+L]^3 */
     LHF_ERR_NONFINITE = -3,   /* non-finite coordinate */
+    LHF_ERR_WORKSPACE = -4,   /* the problem does not fit a fixed-size device buffer */
     LHF_ERR_HIP = -5,         /* a HIP runtime call failed */
     LHF_ERR_UNSUPPORTED = -6, /* valid but not supported by this library version */
     LHF_ERR_STATE = -7        /* plan used inconsistently */
@@ -67,18 +70,52 @@ typedef enum {
 typedef enum { LHF_FP64 = 0, LHF_FP32 = 1 } lhf_precision;
 
 /* flags */
-#define LHF_SINGULAR 0x1u /* ignore a: singular kernel everywhere (a = 0 means the same) */
+#define LHF_SINGULAR 0x1u      /* ignore a: singular kernel everywhere (a = 0 means the same) */
+#define LHF_DETERMINISTIC 0x2u /* every kernel accumulates in a fixed order: two executes of one plan
+                                  on the same input give bitwise-identical outputs (may select a
+                                  slower M2L kernel) */
+#define LHF_OUT_GRAD 0x4u      /* the plan keeps room for the velocity gradient: lhf_execute may then
+                                  be given a grad_v output */
+
+/* translation scheme (lhf_desc.translation) */
+#define LHF_TRANS_RCR 0        /* rotation - coaxial shift - back-rotation with the conversion
+                                  operators of eq. rcr1 (Sec. 4.4); the only scheme built */
+#define LHF_TRANS_DIRECT 1     /* full O(p^4) translation matrices of eq. mr3 (a debugging scheme):
+                                  not built, rejected with LHF_ERR_UNSUPPORTED */
+
+/* M2L kernel (lhf_desc.m2l_kernel).  AUTO picks the fastest kernel measured for (precision, p);
+ * the others force one and return LHF_ERR_UNSUPPORTED where it has no instantiation. */
+#define LHF_M2L_AUTO 0
+#define LHF_M2L_HALF 1         /* batched VALU, each coefficient vector split over two lanes by the
+                                  parity of m: p = 8, 10, 12, 16 */
+#define LHF_M2L_TILE 2         /* batched VALU, one lane per coefficient vector (two schedule rows
+                                  per batch at FP32 p = 8, 10): p = 4..12 even (FP32 also 16) */
+#define LHF_M2L_TILE1 3        /* as TILE with one schedule row per batch */
+#define LHF_M2L_MFMA 4         /* batched matrix-core (16x16x4 MFMA) kernel: p = 4..12 even (FP32
+                                  also 16) */
+#define LHF_M2L_GENERIC 5      /* one wavefront per target box over its stored V-list: any p */
+
+/* M2M / L2L kernel (lhf_desc.mm_kernel) */
+#define LHF_MM_AUTO 0
+#define LHF_MM_HALF 1          /* batched, eight child shifts per wavefront: p = 8, 10, 12, 16 */
+#define LHF_MM_GENERIC 2       /* one wavefront per parent (M2M) or child (L2L): any p */
 
 typedef struct {
-    int32_t p;            /* truncation number, orders n = 0..p-1 (Sec. 5.1) */
-    double tol;           /* target accuracy; only used for the CORE_SPLIT warning */
+    int32_t p;            /* truncation number, orders n = 0..p-1 (Sec. 5.1); 0: the smallest order
+                             whose calibrated error (relative L2 of v and of s against the direct
+                             sum, measured per input class: uniform tree / adaptive tree) is <= tol */
+    double tol;           /* target accuracy: drives p = 0 and the CORE_SPLIT warning */
     int32_t depth;        /* uniform octree depth d, or the deepest level of an adaptive tree; 2..10 */
     int32_t max_per_leaf; /* 0: uniform tree of depth d.  > 0: adaptive tree -- a box is split
                              while it holds more than max_per_leaf elements, down to level d */
     double domain_lo[3];  /* cube origin */
-    double domain_len;    /* cube side; <= 0: bounding cube of the data, side*(1+2^-20) */
+    double domain_len;    /* cube side, > 0 (every element must lie in the cube) */
     int32_t precision;    /* lhf_precision */
-    uint32_t flags;       /* LHF_SINGULAR */
+    uint32_t flags;       /* LHF_SINGULAR | LHF_DETERMINISTIC | LHF_OUT_GRAD */
+    int32_t translation;  /* LHF_TRANS_RCR */
+    int32_t m2l_kernel;   /* LHF_M2L_* */
+    int32_t mm_kernel;    /* LHF_MM_* */
+    int32_t reserved;     /* must be 0 */
 } lhf_desc;
 
 typedef struct {
@@ -93,9 +130,18 @@ typedef struct {
     int64_t n_leaves;          /* leaf boxes */
     int64_t n_wx_pairs;        /* adaptive tree: element pairs of W/X interactions, summed directly
                                   with the singular kernel (ordered) */
+    int32_t m2l_kernel;        /* the M2L kernel the plan runs (LHF_M2L_*, never AUTO) */
+    int32_t mm_kernel;         /* the M2M/L2L kernel (LHF_MM_HALF or LHF_MM_GENERIC) */
+    int32_t deterministic;     /* 1 if every kernel of the plan accumulates in a fixed order */
+    int32_t p_from_tol;        /* 1 if p was chosen from tol */
+    double calib_err_v;        /* calibrated relative L2 error of v and of s at the plan's p for its */
+    double calib_err_s;        /*   input class (uniform / adaptive tree), FP64 arithmetic */
+    int32_t warnings;          /* bit 0: LHF_WARN_CORE_SPLIT applies, bit 1: LHF_WARN_TOL_UNMET applies
+                                  (a creation status carries one of them: TOL_UNMET first) */
+    int32_t reserved;
 } lhf_stats;
 
-/* Fill *d with the defaults: p = 12, tol = 1e-6, depth = 4, cube [0,1]^3, FP64. */
+/* Fill *d with the defaults: p = 12, tol = 1e-6, depth = 4, cube [0,1]^3, FP64, RCR, AUTO kernels. */
 void lhf_desc_default(lhf_desc *d);
 
 /* Build a plan for the elements at x (device, [n][3], dtype by d->precision),
@@ -121,16 +167,21 @@ lhf_status lhf_plan_create_multi(lhf_plan **out, const lhf_desc *d, int32_t n_sy
                                  const double *sys_len, const double *sys_a, void *stream);
 
 /* One FMM evaluation with strengths omega (device, [n][3]) for the plan's
- * elements: writes v and s (device, [n][3], input order).  Enqueued on
- * 'stream'; no host synchronisation, no allocation (graph-capturable). */
-lhf_status lhf_execute(lhf_plan *plan, const void *omega, void *v, void *s, void *stream);
+ * elements: writes v and s (device, [n][3], input order) and, if grad_v is not
+ * NULL, the velocity gradient grad_v[i][3k + l] = d v_k / d x_l (device, [n][9],
+ * input order; eqs. evf4-evf6 for the far field, the derivative of the
+ * near-field kernel sum for the near field; s_k = sum_l omega_l grad_v[3k+l]).
+ * grad_v needs a plan created with LHF_OUT_GRAD (else LHF_ERR_STATE).
+ * Enqueued on 'stream'; no host synchronisation, no allocation (graph-capturable). */
+lhf_status lhf_execute(lhf_plan *plan, const void *omega, void *v, void *s, void *grad_v, void *stream);
 
 /* Same as lhf_execute, but writes only the near field (what = 2), only the far
  * field (what = 1) or both (what = 3); for stage-level testing. */
-lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, int32_t what,
-                             void *stream);
+lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, void *grad_v,
+                             int32_t what, void *stream);
 
-/* One-shot: plan_create + execute + destroy (synchronises the stream). */
+/* One-shot: plan_create + execute + destroy (synchronises the stream; allocates and frees the
+ * plan's device buffers).  p = 0 chooses the order from tol as in lhf_plan_create. */
 lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void *omega, double a,
                         void *v, void *s, void *stream);
 

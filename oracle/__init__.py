@@ -69,7 +69,8 @@ def lib():
                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lho_num_threads.restype = C.c_int
         L.lho_fmm_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int, C.c_int64, C.c_int, _dp,
-                                       C.c_double, C.c_int, C.c_int64, C.c_void_p, _dp, _dp, C.POINTER(_Stats)]
+                                       C.c_double, C.c_int, C.c_int64, C.c_void_p, _dp, _dp, C.c_void_p,
+                                       C.POINTER(_Stats)]
         L.lho_fmm_adaptive.restype = C.c_int
         L.lho_direct_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int64, C.c_int, _dp, C.c_double,
                                           C.c_int64, C.c_void_p, _dp, _dp]
@@ -240,14 +241,16 @@ def tree_counts(x, depth, lo=(0.0, 0.0, 0.0), L=1.0):
 
 
 def fmm_adaptive(x, w, a, p, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True,
-                 sample=None):
+                 sample=None, grad=False):
     """Adaptive-octree FMM (split while a box holds more than max_per_leaf elements, down to
     max_level); W/X interactions summed directly with the singular kernel.  With ``sample``
-    only the leaves holding those elements are evaluated (other outputs NaN)."""
+    only the leaves holding those elements are evaluated (other outputs NaN).  With ``grad``
+    also grad v ([N,3,3], [i,k,l] = d v_k / d x_l) is returned after s."""
     x = _f64(x).reshape(-1, 3)
     w = _f64(w).reshape(-1, 3)
     n = x.shape[0]
     v = np.zeros((n, 3)); s = np.zeros((n, 3))
+    g = np.zeros((n, 9)) if grad else None
     if sample is None:
         ns, sp = 0, None
     else:
@@ -256,7 +259,7 @@ def fmm_adaptive(x, w, a, p, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), 
     st = _Stats()
     what = (1 if far else 0) | (2 if near else 0)
     rc = lib().lho_fmm_adaptive(n, x, w, float(a), int(p), int(max_per_leaf), int(max_level), _f64(lo, (3,)),
-                                float(L), what, ns, sp, v, s, C.byref(st))
+                                float(L), what, ns, sp, v, s, g.ctypes.data if grad else None, C.byref(st))
     if rc != 0:
         raise ValueError("oracle adaptive fmm rejected its arguments")
     if sample is not None:
@@ -264,9 +267,13 @@ def fmm_adaptive(x, w, a, p, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), 
         mask = np.isin(leaf, np.unique(leaf[sample]))
         v[~mask] = np.nan
         s[~mask] = np.nan
+        if grad:
+            g[~mask] = np.nan
     stats = dict(n_m2l=st.n_m2l, n_p2p_pairs=st.n_p2p_pairs, n_wx_pairs=st.n_wx_pairs, n_leaf=st.n_leaf,
                  n_box=st.n_box, max_level=st.max_level, t_tree=st.t_tree, t_up=st.t_up, t_down=st.t_down,
                  t_near=st.t_near)
+    if grad:
+        return v, s, g.reshape(n, 3, 3), stats
     return v, s, stats
 
 

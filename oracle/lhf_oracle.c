@@ -151,19 +151,6 @@ void lho_basis_S(int nmax, const double r[3], cplx *out)
     free(P);
 }
 
-/* value of an expansion sum_{n<p} c_n^m F_n^m(y - centre), F = R (kind 0) or S (kind 1) */
-cplx lho_eval_expansion(int p, int kind, const double centre[3], const cplx *c, const double y[3])
-{
-    double r[3] = {y[0] - centre[0], y[1] - centre[1], y[2] - centre[2]};
-    cplx *F = (cplx *)malloc(sizeof(cplx) * (size_t)p * p);
-    if (kind == 0) lho_basis_R(p, r, F);
-    else lho_basis_S(p, r, F);
-    cplx acc = 0.0;
-    for (int k = 0; k < p * p; k++) acc += c[k] * F[k];
-    free(F);
-    return acc;
-}
-
 /* ------------------------------------------------------------------------- */
 /* Smoothed core, eqs. 2 and vem1                                             */
 /* ------------------------------------------------------------------------- */
@@ -1327,25 +1314,26 @@ static int list_V(const atree *A, int l, uint64_t k, int64_t *out)
 
 /* add the direct sum over the elements of box (l, q) into target element j */
 static int64_t box_direct(const atree *A, const double *x, const double *w, double a, int smooth, int l,
-                          int64_t q, int64_t j, double *vv, double *ss)
+                          int64_t q, int64_t j, double *vv, double *ss, double *gg)
 {
     const otree *T = &A->T;
     int64_t np = 0;
     for (int64_t is = 0; is < T->count[l][q]; is++) {
         int64_t i = T->order[T->first[l][q] + is];
         if (i == j) continue;
-        pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, smooth, vv, ss, NULL);
+        pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, smooth, vv, ss, gg);
         np++;
     }
     return np;
 }
 
-/* Adaptive FMM of v and s (FP64, direct-mode translations).  what / sample as
+/* Adaptive FMM of v and s (FP64, direct-mode translations), and of grad v
+ * (row = component, column = derivative) when gv is not NULL.  what / sample as
  * in lho_fmm (sample: the leaves holding the sampled elements are evaluated).
  * maxleaf >= 0, 1 <= maxl <= 10.  Returns 0 on success. */
 int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int p, int64_t maxleaf, int maxl,
                      const double lo[3], double L, int what, int64_t nsample, const int64_t *sample, double *v,
-                     double *s, lho_stats *st)
+                     double *s, double *gv, lho_stats *st)
 {
     if (maxl < 1 || maxl > 10 || p < 1 || n < 1 || maxleaf < 0) return -1;
     double t0 = wtime();
@@ -1475,36 +1463,40 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int 
         for (int l = 2; l <= maxl; l++) {
 #pragma omp parallel
             {
-                double *bx = NULL, *bw = NULL, *bv = NULL, *bs = NULL;
+                double *bx = NULL, *bw = NULL, *bv = NULL, *bs = NULL, *bg = NULL;
                 int64_t cap = 0;
 #pragma omp for schedule(dynamic, 4)
                 for (int64_t b = 0; b < T->nb[l]; b++) {
                     if (!want[l][b]) continue;
                     int64_t c = T->count[l][b];
                     if (c > cap) {
-                        free(bx); free(bw); free(bv); free(bs);
+                        free(bx); free(bw); free(bv); free(bs); free(bg);
                         cap = c;
                         bx = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
                         bw = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
                         bv = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
                         bs = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                        bg = (double *)malloc(sizeof(double) * 9 * (size_t)cap);
                     }
                     box_points(T, x, w, l, b, bx, bw);
                     memset(bv, 0, sizeof(double) * 3 * (size_t)c);
                     memset(bs, 0, sizeof(double) * 3 * (size_t)c);
+                    memset(bg, 0, sizeof(double) * 9 * (size_t)c);
                     double cen[3];
                     box_centre(T, l, T->key[l][b], cen);
                     const cplx *ph = &Lc[l][(size_t)b * 2 * P2];
-                    lho_l2p(p, cen, ph, ph + P2, c, bx, bw, bv, bs, NULL, NULL, NULL);
+                    lho_l2p(p, cen, ph, ph + P2, c, bx, bw, bv, bs, bg, NULL, NULL);
                     for (int64_t i = 0; i < c; i++) {
                         int64_t e = T->order[T->first[l][b] + i];
                         for (int d = 0; d < 3; d++) {
                             v[3 * e + d] += bv[3 * i + d];
                             s[3 * e + d] += bs[3 * i + d];
                         }
+                        if (gv)
+                            for (int d = 0; d < 9; d++) gv[9 * e + d] += bg[9 * i + d];
                     }
                 }
-                free(bx); free(bw); free(bv); free(bs);
+                free(bx); free(bw); free(bv); free(bs); free(bg);
             }
         }
         for (int l = 2; l <= maxl; l++) {
@@ -1532,13 +1524,18 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int 
                 }
                 for (int64_t it = 0; it < T->count[l][b]; it++) {
                     int64_t j = T->order[T->first[l][b] + it];
-                    double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
-                    for (int64_t q = 0; q < U.n; q++) nu += box_direct(&A, x, w, a, smooth, U.lev[q], U.box[q], j, vv, ss);
-                    for (int64_t q = 0; q < WX.n; q++) nwx += box_direct(&A, x, w, a, 0, WX.lev[q], WX.box[q], j, vv, ss);
+                    double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gg[9] = {0};
+                    double *gp = gv ? gg : NULL;
+                    for (int64_t q = 0; q < U.n; q++)
+                        nu += box_direct(&A, x, w, a, smooth, U.lev[q], U.box[q], j, vv, ss, gp);
+                    for (int64_t q = 0; q < WX.n; q++)
+                        nwx += box_direct(&A, x, w, a, 0, WX.lev[q], WX.box[q], j, vv, ss, gp);
                     for (int d = 0; d < 3; d++) {
                         v[3 * j + d] += vv[d];
                         s[3 * j + d] += ss[d];
                     }
+                    if (gv)
+                        for (int d = 0; d < 9; d++) gv[9 * j + d] += gg[d];
                 }
                 blist_free(&U);
                 blist_free(&WX);

@@ -8,6 +8,8 @@ no CPU fallback: if the library is missing, loading fails with an error.
     plan = Plan(x, a=0.005, p=12, depth=6)          # x: [N,3] cuda tensor
     v, s = plan.execute(omega)                      # omega: [N,3] cuda tensor
     v, s = evaluate(x, omega, a, p=12, depth=6)     # one shot
+    plan = Plan(x, a, p=0, tol=1e-6, grad=True)     # order from tol; velocity gradient output
+    v, s, g = plan.execute(omega, grad=True)        # g: [N,3,3], g[i,k,l] = d v_k / d x_l
 """
 from __future__ import annotations
 
@@ -18,9 +20,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblhfmm.so")
 
 FP64, FP32 = 0, 1
-LHF_SINGULAR = 0x1
-STATUS = {0: "LHF_OK", 1: "LHF_WARN_CORE_SPLIT", -1: "LHF_ERR_ARG", -2: "LHF_ERR_DOMAIN",
-          -3: "LHF_ERR_NONFINITE", -5: "LHF_ERR_HIP", -6: "LHF_ERR_UNSUPPORTED", -7: "LHF_ERR_STATE"}
+LHF_SINGULAR, LHF_DETERMINISTIC, LHF_OUT_GRAD = 0x1, 0x2, 0x4
+TRANS_RCR, TRANS_DIRECT = 0, 1
+M2L_AUTO, M2L_HALF, M2L_TILE, M2L_TILE1, M2L_MFMA, M2L_GENERIC = range(6)
+MM_AUTO, MM_HALF, MM_GENERIC = range(3)
+M2L_NAMES = ("auto", "half", "tile", "tile1", "mfma", "generic")
+STATUS = {0: "LHF_OK", 1: "LHF_WARN_CORE_SPLIT", 2: "LHF_WARN_TOL_UNMET", -1: "LHF_ERR_ARG",
+          -2: "LHF_ERR_DOMAIN", -3: "LHF_ERR_NONFINITE", -4: "LHF_ERR_WORKSPACE", -5: "LHF_ERR_HIP",
+          -6: "LHF_ERR_UNSUPPORTED", -7: "LHF_ERR_STATE"}
 
 #: every entry point declared in include/lhfmm.h
 EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_plan_create_multi", "lhf_execute", "lhf_execute_parts",
@@ -34,14 +41,17 @@ PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 class Desc(C.Structure):
     _fields_ = [("p", C.c_int32), ("tol", C.c_double), ("depth", C.c_int32), ("max_per_leaf", C.c_int32),
                 ("domain_lo", C.c_double * 3), ("domain_len", C.c_double), ("precision", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("translation", C.c_int32), ("m2l_kernel", C.c_int32),
+                ("mm_kernel", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("depth", C.c_int32), ("p", C.c_int32), ("boxes", C.c_int64 * 11),
                 ("n_m2l", C.c_int64), ("n_m2m", C.c_int64), ("n_l2l", C.c_int64), ("n_p2p_pairs", C.c_int64),
                 ("n_theta_classes", C.c_int32), ("max_level", C.c_int32), ("n_leaves", C.c_int64),
-                ("n_wx_pairs", C.c_int64)]
+                ("n_wx_pairs", C.c_int64), ("m2l_kernel", C.c_int32), ("mm_kernel", C.c_int32),
+                ("deterministic", C.c_int32), ("p_from_tol", C.c_int32), ("calib_err_v", C.c_double),
+                ("calib_err_s", C.c_double), ("warnings", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Tune(C.Structure):
@@ -69,9 +79,9 @@ def load():
         L.lhf_desc_default.restype = None
         L.lhf_plan_create.argtypes = [C.POINTER(vp), C.POINTER(Desc), C.c_int64, vp, C.c_double, vp]
         L.lhf_plan_create.restype = C.c_int
-        L.lhf_execute.argtypes = [vp, vp, vp, vp, vp]
+        L.lhf_execute.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lhf_execute.restype = C.c_int
-        L.lhf_execute_parts.argtypes = [vp, vp, vp, vp, C.c_int32, vp]
+        L.lhf_execute_parts.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp]
         L.lhf_execute_parts.restype = C.c_int
         L.lhf_evaluate.argtypes = [C.POINTER(Desc), C.c_int64, vp, vp, C.c_double, vp, vp, vp]
         L.lhf_evaluate.restype = C.c_int
@@ -115,11 +125,13 @@ def _check(status):
     return status
 
 
-def make_desc(p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0, max_per_leaf=0):
+def make_desc(p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0, max_per_leaf=0,
+              m2l_kernel=M2L_AUTO, mm_kernel=MM_AUTO, translation=TRANS_RCR):
     d = Desc()
     load().lhf_desc_default(C.byref(d))
     d.p, d.depth, d.precision, d.tol, d.flags = int(p), int(depth), int(precision), float(tol), int(flags)
     d.max_per_leaf = int(max_per_leaf)
+    d.m2l_kernel, d.mm_kernel, d.translation = int(m2l_kernel), int(mm_kernel), int(translation)
     for k in range(3):
         d.domain_lo[k] = float(lo[k])
     d.domain_len = float(L)
@@ -131,12 +143,16 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def _dev_array(t, dtype, name):
+def _dev_array(t, dtype, name, n=None, width=3):
+    """check a caller tensor before its pointer crosses the C ABI: on the device, of the plan's
+    dtype, contiguous, [N, width] (and N == n when given)"""
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a HIP device tensor")
-    if t.dtype != dtype or t.dim() != 2 or t.shape[1] != 3 or not t.is_contiguous():
-        raise TypeError(f"{name} must be a contiguous [N,3] {dtype} tensor")
+    if t.dtype != dtype or t.dim() != 2 or t.shape[1] != width or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous [N,{width}] {dtype} tensor")
+    if n is not None and t.shape[0] != n:
+        raise ValueError(f"{name} has {t.shape[0]} rows, the plan has {n} elements")
     return t
 
 
@@ -160,16 +176,22 @@ class Plan:
 
     With ``offsets`` (host, n_systems + 1 entries), x holds several independent
     systems; ``lo``, ``L`` and ``a`` are then per system (or broadcast).  With
-    ``max_per_leaf`` > 0 the octree is adaptive and ``depth`` its deepest level."""
+    ``max_per_leaf`` > 0 the octree is adaptive and ``depth`` its deepest level.
+    ``p = 0`` chooses the order from ``tol``; ``grad`` keeps room for the velocity
+    gradient; ``deterministic`` makes repeated executes bitwise identical;
+    ``m2l_kernel`` / ``mm_kernel`` force a kernel (M2L_* / MM_* constants)."""
 
     def __init__(self, x, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0,
-                 offsets=None, max_per_leaf=0):
+                 offsets=None, max_per_leaf=0, grad=False, deterministic=False, m2l_kernel=M2L_AUTO,
+                 mm_kernel=MM_AUTO, translation=TRANS_RCR):
         import torch
         self.dtype = torch.float64 if precision == FP64 else torch.float32
         x = _dev_array(x, self.dtype, "x")
         self.n = x.shape[0]
+        flags = int(flags) | (LHF_OUT_GRAD if grad else 0) | (LHF_DETERMINISTIC if deterministic else 0)
         self.desc = make_desc(p, depth, precision, lo if offsets is None else (0.0, 0.0, 0.0),
-                              L if offsets is None else 1.0, tol, flags, max_per_leaf)
+                              L if offsets is None else 1.0, tol, flags, max_per_leaf, m2l_kernel, mm_kernel,
+                              translation)
         self._h = C.c_void_p()
         if offsets is None:
             self.status = _check(load().lhf_plan_create(C.byref(self._h), C.byref(self.desc), self.n,
@@ -181,20 +203,27 @@ class Plan:
             self.status = _check(load().lhf_plan_create_multi(
                 C.byref(self._h), C.byref(self.desc), ns, _ptr(off, C.c_int64), C.c_void_p(x.data_ptr()),
                 _ptr(glo, C.c_double), _ptr(gL, C.c_double), _ptr(ga, C.c_double), _stream()))
-        self.warn_core_split = self.status == 1
+        st = self.stats()
+        self.warn_core_split = bool(st["warnings"] & 1)
+        self.warn_tol_unmet = bool(st["warnings"] & 2)
+        self.p = st["p"]
 
-    def execute(self, omega, v=None, s=None, what=3):
+    def execute(self, omega, v=None, s=None, what=3, grad=False, g=None):
+        """(v, s), or (v, s, grad v) with grad=True; grad v is [N,3,3] with [i,k,l] = d v_k/d x_l"""
         import torch
-        omega = _dev_array(omega, self.dtype, "omega")
-        if omega.shape[0] != self.n:
-            raise ValueError("omega has a different number of elements than the plan")
-        if v is None:
-            v = torch.empty_like(omega)
-        if s is None:
-            s = torch.empty_like(omega)
+        omega = _dev_array(omega, self.dtype, "omega", self.n)
+        v = torch.empty_like(omega) if v is None else _dev_array(v, self.dtype, "v", self.n)
+        s = torch.empty_like(omega) if s is None else _dev_array(s, self.dtype, "s", self.n)
+        gp = None
+        if grad or g is not None:
+            if g is None:
+                g = torch.empty((self.n, 9), dtype=self.dtype, device=omega.device)
+            else:
+                g = _dev_array(g.reshape(self.n, 9) if g.is_contiguous() else g, self.dtype, "g", self.n, 9)
+            gp = C.c_void_p(g.data_ptr())
         _check(load().lhf_execute_parts(self._h, C.c_void_p(omega.data_ptr()), C.c_void_p(v.data_ptr()),
-                                        C.c_void_p(s.data_ptr()), int(what), _stream()))
-        return v, s
+                                        C.c_void_p(s.data_ptr()), gp, int(what), _stream()))
+        return (v, s, g.view(self.n, 3, 3)) if gp is not None else (v, s)
 
     def stats(self):
         st = Stats()
@@ -202,7 +231,10 @@ class Plan:
         return dict(n=st.n, depth=st.depth, p=st.p, boxes=list(st.boxes[:st.depth + 1]), n_m2l=st.n_m2l,
                     n_m2m=st.n_m2m, n_l2l=st.n_l2l, n_p2p_pairs=st.n_p2p_pairs,
                     n_theta_classes=st.n_theta_classes, max_level=st.max_level, n_leaves=st.n_leaves,
-                    n_wx_pairs=st.n_wx_pairs)
+                    n_wx_pairs=st.n_wx_pairs, m2l_kernel=M2L_NAMES[st.m2l_kernel],
+                    mm_kernel=("auto", "half", "generic")[st.mm_kernel], deterministic=bool(st.deterministic),
+                    p_from_tol=bool(st.p_from_tol), calib_err_v=st.calib_err_v, calib_err_s=st.calib_err_s,
+                    warnings=st.warnings)
 
     def profile_begin(self, max_exec):
         _check(load().lhf_profile_begin(self._h, int(max_exec)))
@@ -231,7 +263,7 @@ def evaluate(x, omega, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1
     import torch
     dtype = torch.float64 if precision == FP64 else torch.float32
     x = _dev_array(x, dtype, "x")
-    omega = _dev_array(omega, dtype, "omega")
+    omega = _dev_array(omega, dtype, "omega", x.shape[0])
     v = torch.empty_like(omega)
     s = torch.empty_like(omega)
     d = make_desc(p, depth, precision, lo, L, tol)
@@ -293,13 +325,9 @@ class Batch:
 
     def execute(self, omega, v=None, s=None, graph=True):
         import torch
-        omega = _dev_array(omega, self.dtype, "omega")
-        if omega.shape[0] != self.n:
-            raise ValueError("omega has a different number of elements than the batch")
-        if v is None:
-            v = torch.empty_like(omega)
-        if s is None:
-            s = torch.empty_like(omega)
+        omega = _dev_array(omega, self.dtype, "omega", self.n)
+        v = torch.empty_like(omega) if v is None else _dev_array(v, self.dtype, "v", self.n)
+        s = torch.empty_like(omega) if s is None else _dev_array(s, self.dtype, "s", self.n)
         _check(load().lhf_batch_execute(self._h, C.c_void_p(omega.data_ptr()), C.c_void_p(v.data_ptr()),
                                         C.c_void_p(s.data_ptr()), int(bool(graph)), _stream()))
         return v, s

@@ -24,16 +24,25 @@ FLAGS = [
 EXTRA = {"lhf_m2l_half.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source (in parallel, at most ``jobs`` at once) and link liblhfmm.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = ["hipcc", "-c", *[f for f in FLAGS if f != "-shared"], *EXTRA.get(src, []), "-o", obj,
-               os.path.join(CSRC, src)]
+        cmds.append(["hipcc", "-c", *[f for f in FLAGS if f != "-shared"], *EXTRA.get(src, []), "-o", obj,
+                     os.path.join(CSRC, src)])
+        objs.append(obj)
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for f in [ex.submit(run, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     if verbose:

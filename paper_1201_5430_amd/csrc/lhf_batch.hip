@@ -190,7 +190,7 @@ static lhf_status batch_capture(lhf_batch *B, const void *omega, void *v, void *
     hipError_t e = hipEventRecord(B->ev[0], B->cap);
     for (int k = 0; k < K && e == hipSuccess; k++) e = hipStreamWaitEvent(B->lanes[k], B->ev[0], 0);
     for (size_t g = 0; g < B->group.size() && e == hipSuccess && rs >= 0; g++)
-        rs = execute_impl(B->group[g], omega, v, s, 3, B->lanes[g % K]);
+        rs = execute_impl(B->group[g], omega, v, s, nullptr, 3, B->lanes[g % K]);
     for (int k = 0; k < K && e == hipSuccess; k++) {
         e = hipEventRecord(B->ev[1 + k], B->lanes[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(B->cap, B->ev[1 + k], 0);
@@ -262,9 +262,9 @@ static lhf_status measure_tune(int32_t p, int32_t precision, hipStream_t st, lhf
         lhf_plan *P = nullptr;
         rs = lhf_plan_create(&P, &d, n, dx, 0.0, st);
         if (rs < 0) break;
-        for (int w = 0; w < 2 && rs >= 0; w++) rs = lhf_execute(P, dw, dv, ds, st);
+        for (int w = 0; w < 2 && rs >= 0; w++) rs = lhf_execute(P, dw, dv, ds, nullptr, st);
         if (rs >= 0) rs = lhf_profile_begin(P, 3);
-        for (int w = 0; w < 3 && rs >= 0; w++) rs = lhf_execute(P, dw, dv, ds, st);
+        for (int w = 0; w < 3 && rs >= 0; w++) rs = lhf_execute(P, dw, dv, ds, nullptr, st);
         double ph[LHF_NPHASE];
         int32_t ne = 0;
         if (rs >= 0) rs = lhf_profile_end(P, ph, &ne);
@@ -520,7 +520,7 @@ lhf_status lhf_batch_execute(lhf_batch *B, const void *omega, void *v, void *s, 
     hipStream_t st = (hipStream_t)stream;
     if (!use_graph) {
         for (lhf_plan *P : B->group) {
-            lhf_status rs = execute_impl(P, omega, v, s, 3, st);
+            lhf_status rs = execute_impl(P, omega, v, s, nullptr, 3, st);
             if (rs < 0) return rs;
         }
         return LHF_OK;

@@ -478,6 +478,34 @@ __global__ void __launch_bounds__(WAVE) k_down(int p, int level, int do_m2l, int
     }
 }
 
+// Compensated running sum (Knuth's TwoSum, branch-free): the rounding error of each
+// addition is carried in c.  The near field adds one source box's partial sum at a
+// time, so the accumulation error no longer grows with the number of source boxes.
+template <typename T>
+struct CompSum {
+    T s = 0, c = 0;
+    __device__ __forceinline__ void add(T x)
+    {
+        const T t = s + x;
+        const T bp = t - s;
+        c += (s - (t - bp)) + (x - bp);
+        s = t;
+    }
+    __device__ __forceinline__ T value() const { return s + c; }
+};
+
+// L2P accumulator: compensated in FP32 (the p(p+1)/2 terms of a local expansion partly cancel;
+// a compensated sum keeps the FP32 far field at the rounding of its terms), plain in FP64
+template <typename T>
+struct L2PAcc {
+    T s = 0;
+    __device__ __forceinline__ void add(T x) { s += x; }
+    __device__ __forceinline__ T value() const { return s; }
+};
+template <>
+struct L2PAcc<float> : CompSum<float> {
+};
+
 // ---------------------------------------------------------------------------
 // L2P: one wavefront per leaf.  The velocity coefficients (eq. evf3, bar form)
 //   Vx = 1/2 [-P_{n+1}^{m-1} + P_{n+1}^{m+1} - i(n-m) X_n^{m+1} - i(n+m) X_n^{m-1}]
@@ -500,7 +528,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
                                               const uint64_t *__restrict__ bkey, const int32_t *__restrict__ bstart,
                                               const int32_t *__restrict__ bcount, const T *__restrict__ xs,
                                               const T *__restrict__ ws, int64_t n, const double *__restrict__ sys_geo,
-                                              const T *__restrict__ Lc, T *__restrict__ vfar)
+                                              const T *__restrict__ Lc, T *__restrict__ vfar, int grad)
 {
     extern __shared__ char smem[];
     const int P2 = p * p;
@@ -563,8 +591,9 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
     if (!has) return;
     const int s0 = bstart[b], cnt = bcount[b];
     if (!far) {
+        const int nk = grad ? 15 : 6;
         for (int e = lane; e < cnt; e += L2P_LANES)
-            for (int k = 0; k < 6; k++) vfar[(size_t)k * n + s0 + e] = (T)0;
+            for (int k = 0; k < nk; k++) vfar[(size_t)k * n + s0 + e] = (T)0;
         return;
     }
     double c0, c1, c2, hd;
@@ -602,7 +631,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
         const int i = s0 + (act ? e : 0);
         const T x = (xs[i] - (T)c0) * ih, y = (xs[n + i] - (T)c1) * ih, z = (xs[2 * n + i] - (T)c2) * ih;
         const T r2 = x * x + y * y + z * z;
-        T v[3] = {0, 0, 0}, gr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        L2PAcc<T> v[3], gr[9];
         // walk the columns m; Rt_m^m by recurrence, then up in n
         T mre = 1, mim = 0;
         for (int m = 0; m < p; m++) {
@@ -638,7 +667,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
                 for (int k = 0; k < 3; k++) {
                     T fr, fi;
                     vget(k, nn, m, fr, fi);
-                    v[k] += sw * (fr * rre - fi * rim);
+                    v[k].add(sw * (fr * rre - fi * rim));
                     // gradient: u_x, u_y, u_z of v_k at (nn, m) from V_k at nn+1
                     T ar, ai, br, bi, cr, ci;
                     vget(k, nn + 1, m - 1, ar, ai);
@@ -647,19 +676,24 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
                     T uxr = (T)0.5 * (br - ar), uxi = (T)0.5 * (bi - ai);
                     T uyr = (T)-0.5 * (ai + bi), uyi = (T)0.5 * (ar + br);
                     T uzr = -cr, uzi = -ci;
-                    gr[3 * k + 0] += sw * (uxr * rre - uxi * rim);
-                    gr[3 * k + 1] += sw * (uyr * rre - uyi * rim);
-                    gr[3 * k + 2] += sw * (uzr * rre - uzi * rim);
+                    gr[3 * k + 0].add(sw * (uxr * rre - uxi * rim));
+                    gr[3 * k + 1].add(sw * (uyr * rre - uyi * rim));
+                    gr[3 * k + 2].add(sw * (uzr * rre - uzi * rim));
                 }
             }
         }
         if (act) {
             const T wx = ws[i], wy = ws[n + i], wz = ws[2 * n + i];
             const T ih2 = ih * ih;
+            T g[9];
+            for (int k = 0; k < 9; k++) g[k] = gr[k].value();
             for (int k = 0; k < 3; k++) {
-                vfar[k * n + i] = v[k] * ih;
-                vfar[(3 + k) * n + i] = (gr[3 * k] * wx + gr[3 * k + 1] * wy + gr[3 * k + 2] * wz) * ih2;
+                vfar[k * n + i] = v[k].value() * ih;
+                vfar[(3 + k) * n + i] = (g[3 * k] * wx + g[3 * k + 1] * wy + g[3 * k + 2] * wz) * ih2;
             }
+            // grad v (row k = component, column l = derivative), rows 6..14 of the far-field array
+            if (grad)
+                for (int k = 0; k < 9; k++) vfar[(6 + k) * n + i] = g[k] * ih2;
         }
     }
 }
@@ -719,22 +753,6 @@ __device__ inline void kernel_fg(T r2, T a, int smooth, T &f, T &g)
     }
 }
 
-// Compensated running sum (Knuth's TwoSum, branch-free): the rounding error of each
-// addition is carried in c.  The near field adds one source box's partial sum at a
-// time, so the accumulation error no longer grows with the number of source boxes.
-template <typename T>
-struct CompSum {
-    T s = 0, c = 0;
-    __device__ __forceinline__ void add(T x)
-    {
-        const T t = s + x;
-        const T bp = t - s;
-        c += (s - (t - bp)) + (x - bp);
-        s = t;
-    }
-    __device__ __forceinline__ T value() const { return s + c; }
-};
-
 // one packed element record: position and strength
 template <typename T>
 struct Rec {
@@ -776,10 +794,90 @@ __device__ __forceinline__ void p2p_pair(int k, const T *__restrict__ xw, T xj, 
     s2 += f * (wix * wjy - wiy * wjx) + dd * cz;
 }
 
+// the same pair with the velocity gradient: d_l (f (w_i x r))_k = g r_l (w_i x r)_k + f eps_{k a l} w_i,a
+template <typename T>
+__device__ __forceinline__ void p2p_pair_grad(int k, const T *__restrict__ xw, T xj, T yj, T zj, T wjx, T wjy,
+                                              T wjz, T a, int smooth, T *acc)
+{
+    const Rec<T> q = load_rec(xw, k);
+    const T rx = xj - q.x, ry = yj - q.y, rz = zj - q.z;
+    const T r2 = rx * rx + ry * ry + rz * rz;
+    if (r2 == (T)0 && !smooth) return;
+    T f, g;
+    kernel_fg<T>(r2, a, smooth, f, g);
+    const T wix = q.wx, wiy = q.wy, wiz = q.wz;
+    const T cx = wiy * rz - wiz * ry, cy = wiz * rx - wix * rz, cz = wix * ry - wiy * rx;
+    const T dd = g * (wjx * rx + wjy * ry + wjz * rz);
+    acc[0] += f * cx;
+    acc[1] += f * cy;
+    acc[2] += f * cz;
+    acc[3] += f * (wiy * wjz - wiz * wjy) + dd * cx;
+    acc[4] += f * (wiz * wjx - wix * wjz) + dd * cy;
+    acc[5] += f * (wix * wjy - wiy * wjx) + dd * cz;
+    const T gx = g * rx, gy = g * ry, gz = g * rz;
+    acc[6] += gx * cx;
+    acc[7] += gy * cx - f * wiz;
+    acc[8] += gz * cx + f * wiy;
+    acc[9] += gx * cy + f * wiz;
+    acc[10] += gy * cy;
+    acc[11] += gz * cy - f * wix;
+    acc[12] += gx * cz - f * wiy;
+    acc[13] += gy * cz + f * wix;
+    acc[14] += gz * cz;
+}
+
+// near-field sum of one target over the elements st .. st+ct-1 (self excluded), added box by
+// box into compensated accumulators: v, s and, with GRAD, grad v
+template <typename T, bool GRAD>
+__device__ __forceinline__ void p2p_box(int i, int st, int ct, const T *__restrict__ xw, T xj, T yj, T zj, T wjx,
+                                        T wjy, T wjz, T a, int sm, CompSum<T> *acc)
+{
+    if constexpr (GRAD) {
+        T b[15];
+        for (int k = 0; k < 15; k++) b[k] = 0;
+        for (int e = 0; e < ct; e++) {
+            const int k = st + e;
+            if (k == i) continue;
+            p2p_pair_grad<T>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, sm, b);
+        }
+        for (int k = 0; k < 15; k++) acc[k].add(b[k]);
+    } else {
+        T v0 = 0, v1 = 0, v2 = 0, s0 = 0, s1 = 0, s2 = 0;
+        for (int e = 0; e < ct; e++) {
+            const int k = st + e;
+            if (k == i) continue;
+            p2p_pair<T>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, sm, v0, v1, v2, s0, s1, s2);
+        }
+        acc[0].add(v0);
+        acc[1].add(v1);
+        acc[2].add(v2);
+        acc[3].add(s0);
+        acc[4].add(s1);
+        acc[5].add(s2);
+    }
+}
+
+// far field + near field -> outputs in input order
+template <typename T, bool GRAD>
+__device__ __forceinline__ void p2p_store(int64_t i, int64_t n, const int32_t *__restrict__ perm,
+                                          const CompSum<T> *acc, T *__restrict__ vout, T *__restrict__ sout,
+                                          T *__restrict__ gout)
+{
+    const int64_t o = perm[i];
+    vout[3 * o] = acc[0].value();
+    vout[3 * o + 1] = acc[1].value();
+    vout[3 * o + 2] = acc[2].value();
+    sout[3 * o] = acc[3].value();
+    sout[3 * o + 1] = acc[4].value();
+    sout[3 * o + 2] = acc[5].value();
+    if constexpr (GRAD)
+        for (int k = 0; k < 9; k++) gout[9 * o + k] = acc[6 + k].value();
+}
+
 // adaptive tree: near field of one sorted element over its leaf's source list (entries
 // (box << 1) | singular: U-list leaves with the smoothed kernel, W/X boxes with the singular
 // one), then combination with the far field and un-permutation as in k_p2p
-template <typename T>
+template <typename T, bool GRAD>
 __global__ void __launch_bounds__(256) k_p2p_list(int64_t n, const int32_t *__restrict__ eleaf,
                                                   const int32_t *__restrict__ leaves, const int8_t *__restrict__ blev,
                                                   const int32_t *__restrict__ nl_start, const int32_t *__restrict__ nl_ent,
@@ -788,7 +886,7 @@ __global__ void __launch_bounds__(256) k_p2p_list(int64_t n, const int32_t *__re
                                                   const T *__restrict__ ws, const T *__restrict__ xw,
                                                   const double *__restrict__ sys_a, int what,
                                                   const T *__restrict__ vfar, const int32_t *__restrict__ perm,
-                                                  T *__restrict__ vout, T *__restrict__ sout)
+                                                  T *__restrict__ vout, T *__restrict__ sout, T *__restrict__ gout)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -796,41 +894,24 @@ __global__ void __launch_bounds__(256) k_p2p_list(int64_t n, const int32_t *__re
     const int lb = leaves[lp];
     const T a = (T)sys_a[bkey[lb] >> (3 * blev[lb])];
     const int smooth = a > (T)0;
-    CompSum<T> acc[6];
+    constexpr int NA = GRAD ? 15 : 6;
+    CompSum<T> acc[NA];
     const T xj = xs[i], yj = xs[n + i], zj = xs[2 * n + i];
     const T wjx = ws[i], wjy = ws[n + i], wjz = ws[2 * n + i];
     if (what & 1)
-        for (int k = 0; k < 6; k++) acc[k].add(vfar[(size_t)k * n + i]);
+        for (int k = 0; k < NA; k++) acc[k].add(vfar[(size_t)k * n + i]);
     if (what & 2) {
         const int e1 = nl_start[lp + 1];
         for (int q = nl_start[lp]; q < e1; q++) {
             const int code = nl_ent[q];
             const int src = code >> 1, sm = smooth && !(code & 1);
-            const int st = bstart[src], ct = bcount[src];
-            T v0 = 0, v1 = 0, v2 = 0, s0 = 0, s1 = 0, s2 = 0;
-            for (int e = 0; e < ct; e++) {
-                const int k = st + e;
-                if (k == i) continue;
-                p2p_pair<T>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, sm, v0, v1, v2, s0, s1, s2);
-            }
-            acc[0].add(v0);
-            acc[1].add(v1);
-            acc[2].add(v2);
-            acc[3].add(s0);
-            acc[4].add(s1);
-            acc[5].add(s2);
+            p2p_box<T, GRAD>((int)i, bstart[src], bcount[src], xw, xj, yj, zj, wjx, wjy, wjz, a, sm, acc);
         }
     }
-    const int64_t o = perm[i];
-    vout[3 * o] = acc[0].value();
-    vout[3 * o + 1] = acc[1].value();
-    vout[3 * o + 2] = acc[2].value();
-    sout[3 * o] = acc[3].value();
-    sout[3 * o + 1] = acc[4].value();
-    sout[3 * o + 2] = acc[5].value();
+    p2p_store<T, GRAD>(i, n, perm, acc, vout, sout, gout);
 }
 
-template <typename T>
+template <typename T, bool GRAD>
 __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_off, const int32_t *__restrict__ eleaf,
                                              const int32_t *__restrict__ ulist, const uint64_t *__restrict__ bkey,
                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
@@ -838,46 +919,29 @@ __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_
                                              const T *__restrict__ xw, const double *__restrict__ sys_a, int what,
                                              const T *__restrict__ vfar,
                                              const int32_t *__restrict__ perm, T *__restrict__ vout,
-                                             T *__restrict__ sout)
+                                             T *__restrict__ sout, T *__restrict__ gout)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     // core radius of the element's system (0: singular kernel)
     const T a = (T)sys_a[bkey[eleaf[i]] >> (3 * depth)];
     const int smooth = a > (T)0;
-    CompSum<T> acc[6];
+    constexpr int NA = GRAD ? 15 : 6;
+    CompSum<T> acc[NA];
     const T xj = xs[i], yj = xs[n + i], zj = xs[2 * n + i];
     const T wjx = ws[i], wjy = ws[n + i], wjz = ws[2 * n + i];
     if (what & 1)
-        for (int k = 0; k < 6; k++) acc[k].add(vfar[(size_t)k * n + i]);
+        for (int k = 0; k < NA; k++) acc[k].add(vfar[(size_t)k * n + i]);
     if (what & 2) {
         const int lf = eleaf[i];
         const int32_t *U = ulist + (size_t)(lf - leaf_off) * 27;
         for (int q = 0; q < 27; q++) {
             const int nb = U[q];
             if (nb < 0) continue;
-            const int st = bstart[nb], ct = bcount[nb];
-            T v0 = 0, v1 = 0, v2 = 0, s0 = 0, s1 = 0, s2 = 0;
-            for (int e = 0; e < ct; e++) {
-                const int k = st + e;
-                if (k == i) continue;
-                p2p_pair<T>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, smooth, v0, v1, v2, s0, s1, s2);
-            }
-            acc[0].add(v0);
-            acc[1].add(v1);
-            acc[2].add(v2);
-            acc[3].add(s0);
-            acc[4].add(s1);
-            acc[5].add(s2);
+            p2p_box<T, GRAD>((int)i, bstart[nb], bcount[nb], xw, xj, yj, zj, wjx, wjy, wjz, a, smooth, acc);
         }
     }
-    const int64_t o = perm[i];
-    vout[3 * o] = acc[0].value();
-    vout[3 * o + 1] = acc[1].value();
-    vout[3 * o + 2] = acc[2].value();
-    sout[3 * o] = acc[3].value();
-    sout[3 * o + 1] = acc[4].value();
-    sout[3 * o + 2] = acc[5].value();
+    p2p_store<T, GRAD>(i, n, perm, acc, vout, sout, gout);
 }
 
 // gather omega into the sorted SoA layout
@@ -904,8 +968,23 @@ __global__ void k_gather_w(int64_t n, const T *__restrict__ w, const int32_t *__
     r[7] = (T)0;
 }
 
+template <typename T, bool GRAD>
+static void p2p_launch(lhf_plan *P, int what, T *v, T *s, T *g, unsigned nblk, int tpb, hipStream_t st)
+{
+    const int64_t n = P->n;
+    const int d = P->depth;
+    if (P->adaptive)
+        hipLaunchKernelGGL((k_p2p_list<T, GRAD>), dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, P->leaves, P->blev,
+                           P->nl_start, P->nl_ent, P->bkey, P->bstart, P->bcount, (const T *)P->xs, (const T *)P->ws,
+                           (const T *)P->xw, P->sys_a, what, (const T *)P->vfar, P->perm, v, s, g);
+    else
+        hipLaunchKernelGGL((k_p2p<T, GRAD>), dim3(nblk), dim3(tpb), 0, st, n, d, P->lev[d].off, P->eleaf, P->ulist,
+                           P->bkey, P->bstart, P->bcount, (const T *)P->xs, (const T *)P->ws, (const T *)P->xw,
+                           P->sys_a, what, (const T *)P->vfar, P->perm, v, s, g);
+}
+
 template <typename T>
-static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st)
+static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, void *grad_v, int what, hipStream_t st)
 {
     const int p = P->p, d = P->depth;
     const int64_t n = P->n;
@@ -976,7 +1055,7 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         size_t sh_l2p = sizeof(T) * L2P_LPB * 6 * TRI;
         hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)((nleaf + L2P_LPB - 1) / L2P_LPB)), dim3(WAVE), sh_l2p, st, p, d,
                            nleaf, loff, P->leaves, P->blev, P->bkey, P->bstart, P->bcount, (const T *)xs,
-                           (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar);
+                           (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar, grad_v ? 1 : 0);
     } else {
         mark(2);
         mark(3);
@@ -987,23 +1066,17 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, in
         mark(4);
     }
     mark(5);
-    if (P->adaptive)
-        hipLaunchKernelGGL(k_p2p_list<T>, dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, P->leaves, P->blev, P->nl_start,
-                           P->nl_ent, P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws,
-                           (const T *)P->xw, P->sys_a, what, (const T *)vfar, P->perm, (T *)v, (T *)s);
-    else
-        hipLaunchKernelGGL(k_p2p<T>, dim3(nblk), dim3(tpb), 0, st, n, d, loff, P->eleaf, P->ulist, P->bkey,
-                           P->bstart, P->bcount, (const T *)xs, (const T *)ws, (const T *)P->xw, P->sys_a, what,
-                           (const T *)vfar, P->perm, (T *)v, (T *)s);
+    if (grad_v) p2p_launch<T, true>(P, what, (T *)v, (T *)s, (T *)grad_v, nblk, tpb, st);
+    else p2p_launch<T, false>(P, what, (T *)v, (T *)s, nullptr, nblk, tpb, st);
     mark(6);
     LHF_HIP(hipGetLastError());
     return LHF_OK;
 }
 
-lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st)
+lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, void *grad_v, int what, hipStream_t st)
 {
-    if (P->precision == LHF_FP64) return execute_t<double>(P, omega, v, s, what, st);
-    return execute_t<float>(P, omega, v, s, what, st);
+    if (P->precision == LHF_FP64) return execute_t<double>(P, omega, v, s, grad_v, what, st);
+    return execute_t<float>(P, omega, v, s, grad_v, what, st);
 }
 
 }  // namespace lhf

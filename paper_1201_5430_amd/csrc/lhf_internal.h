@@ -85,7 +85,7 @@ struct lhf_plan {
     int32_t *perm = nullptr;     // sorted position -> input index
     void *xs = nullptr;          // sorted coordinates, SoA [3][n], T
     void *ws = nullptr;          // sorted strengths, SoA [3][n], T (filled by execute)
-    void *vfar = nullptr;        // far-field v, s in sorted order, SoA [6][n], T
+    void *vfar = nullptr;        // far-field v, s (+ grad v) in sorted order, SoA [6 or 15][n], T
     void *xw = nullptr;          // sorted elements packed for the near field: [n][8] T = x y z wx wy wz - -
     uint64_t *bkey = nullptr;    // [nbox] Morton key of every box (level-local)
     int32_t *bstart = nullptr;   // [nbox] first sorted element
@@ -142,6 +142,15 @@ struct lhf_plan {
     bool tile2 = false;                  // VALU tile with two schedule rows per batch (FP32 p = 8, 10)
     void *wmfma = nullptr;               // per-class rotation blocks in MFMA A-operand lane order
 
+    // kernel choice (resolved from the descriptor) and order selection
+    int m2l_kind = LHF_M2L_GENERIC;      // LHF_M2L_HALF / TILE / TILE1 / MFMA / GENERIC
+    int mm_kind = LHF_MM_GENERIC;        // LHF_MM_HALF / GENERIC
+    bool deterministic = true;           // every kernel accumulates in a fixed order
+    bool p_from_tol = false;             // p chosen from tol by the calibration table
+    double calib_err_v = 0, calib_err_s = 0;
+    bool out_grad = false;               // vfar holds grad v too ([15][n] instead of [6][n])
+    int warnings = 0;                    // 1: core split above tol, 2: tol not reachable
+
     // phase profiling: events[k][0..LHF_NPHASE] for the k-th profiled execute
     hipEvent_t *prof_ev = nullptr;
     int prof_cap = 0, prof_used = 0;
@@ -167,7 +176,12 @@ inline hipError_t dev_malloc(T **p, size_t bytes)
 {
     return dev_malloc_raw((void **)p, bytes);
 }
-lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st);
+lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, void *grad_v, int what, hipStream_t st);
+// order from tolerance and kernel choice (host only)
+bool choose_order(bool adaptive, int precision, double tol, int *p);
+void calib_error(bool adaptive, int p, double *ev, double *es);
+bool kernel_deterministic(int precision, int p, int m2l_kind);
+lhf_status resolve_kernels(const lhf_desc *d, int p, bool dmap_ok, int *m2l, int *mm);
 }  // namespace lhf
 
 #define LHF_HIP(call)                                                  \

@@ -870,6 +870,31 @@ bool m2l_tile_supported(int precision, int p)
     return p == 4 || p == 6 || p == 8 || p == 10 || p == 12 || p == 16;
 }
 
+// true if the tiled kernel runs in ownership mode (no atomics: a fixed summation order) for
+// this (precision, p)
+bool m2l_tile_owned(int precision, int p)
+{
+    if (precision == LHF_FP64) {
+        switch (p) {
+        case 4: return tile_own<double, 4>();
+        case 6: return tile_own<double, 6>();
+        case 8: return tile_own<double, 8>();
+        case 10: return tile_own<double, 10>();
+        case 12: return tile_own<double, 12>();
+        default: return false;
+        }
+    }
+    switch (p) {
+    case 4: return tile_own<float, 4>();
+    case 6: return tile_own<float, 6>();
+    case 8: return tile_own<float, 8>();
+    case 10: return tile_own<float, 10>();
+    case 12: return tile_own<float, 12>();
+    case 16: return tile_own<float, 16>();
+    default: return false;
+    }
+}
+
 void m2l_tile_launch(const lhf_plan *Pl, int level, hipStream_t st)
 {
     const int p = Pl->p;

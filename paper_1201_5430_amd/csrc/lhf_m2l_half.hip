@@ -1050,6 +1050,26 @@ bool m2l_half_supported(int precision, int p)
     return p == 8 || p == 10 || p == 12 || p == 16;
 }
 
+// true if the half-vector kernel runs in ownership mode (no atomics) for this (precision, p)
+bool m2l_half_owned(int precision, int p)
+{
+    if (!m2l_half_supported(precision, p)) return false;
+    if (precision == LHF_FP64) {
+        switch (p) {
+        case 8: return hv::tile_own<double, 8>();
+        case 10: return hv::tile_own<double, 10>();
+        case 12: return hv::tile_own<double, 12>();
+        default: return hv::tile_own<double, 16>();
+        }
+    }
+    switch (p) {
+    case 8: return hv::tile_own<float, 8>();
+    case 10: return hv::tile_own<float, 10>();
+    case 12: return hv::tile_own<float, 12>();
+    default: return hv::tile_own<float, 16>();
+    }
+}
+
 bool whalf_build(lhf_plan *Pl, hipStream_t st)
 {
     if (Pl->precision == LHF_FP64) {

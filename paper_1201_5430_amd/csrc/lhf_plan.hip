@@ -26,7 +26,7 @@
 
 namespace lhf {
 
-lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, int what, hipStream_t st);
+lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, void *grad_v, int what, hipStream_t st);
 bool m2l_tile_supported(int precision, int p);
 void dmap_build(const lhf_plan *Pl, int level, hipStream_t st);
 bool wpad_build(lhf_plan *Pl, hipStream_t st);
@@ -36,11 +36,8 @@ bool whalf_build(lhf_plan *Pl, hipStream_t st);
 bool mmhalf_build(lhf_plan *Pl, hipStream_t st);
 bool wmfma_build(lhf_plan *Pl, hipStream_t st);
 
-// a batched M2L kernel exists: the one-lane tile, or the half-vector kernel unless switched off
-static bool batched_m2l_supported(int precision, int p)
-{
-    return m2l_tile_supported(precision, p) || (m2l_half_supported(precision, p) && !getenv("LHF_NO_HALF"));
-}
+bool m2l_tile_owned(int precision, int p);
+bool m2l_half_owned(int precision, int p);
 
 // ---- device memory cache -----------------------------------------------------------------
 namespace {
@@ -965,7 +962,7 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     LHF_HIP(hipGetLastError());
     // batched M2M and L2L (two lanes per part vector) at the orders the half-vector kernels
     // cover; LHF_NO_MMHALF=1 keeps the generic per-box shifts
-    P->use_mmhalf = m2l_half_supported(P->precision, p) && !getenv("LHF_NO_MMHALF");
+    P->use_mmhalf = P->mm_kind == LHF_MM_HALF;
     if (P->use_mmhalf && !mmhalf_build(P, st)) {
         set_error("batched M2M/L2L set-up failed");
         return LHF_ERR_HIP;
@@ -974,7 +971,7 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     if (P->use_tile) {
         lhf_status s = build_schedule(P, cls, (int)theta.size(), st);
         if (s != LHF_OK) return s;
-        const bool tile_ok = m2l_tile_supported(P->precision, p);
+        const bool tile_ok = P->m2l_kind == LHF_M2L_TILE || P->m2l_kind == LHF_M2L_TILE1;
         if (tile_ok && !wpad_build(P, st)) {
             set_error("allocation of the padded rotation table failed");
             return LHF_ERR_HIP;
@@ -986,23 +983,17 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
             dmap_build(P, l, st);
         }
         // two schedule rows per batch where the ownership tile allows it (FP32 p = 8, 10: 14% faster
-        // M2L on the 2^20 cube); LHF_TILE1=1 keeps one row per batch
-        P->tile2 = P->precision == LHF_FP32 && (p == 8 || p == 10) && getenv("LHF_TILE1") == nullptr;
+        // M2L on the 2^20 cube than one row)
+        P->tile2 = P->precision == LHF_FP32 && (p == 8 || p == 10) && P->m2l_kind == LHF_M2L_TILE;
         // the matrix-core kernel walks the same schedule; it is slower than the VALU kernels at
-        // every order measured (FP32 p = 16 on the 4M ring: 524 ms against 470 ms for the
-        // half-vector kernel), so it runs only on request: LHF_MFMA=1 (LHF_NO_MFMA=1 never)
-        P->use_mfma = m2l_mfma_supported(P->precision, p) && getenv("LHF_MFMA") && !getenv("LHF_NO_MFMA");
+        // every order measured (FP32 p = 16 on the 4M ring: 524 ms against 121 ms for the
+        // half-vector kernel), so it runs only on request
+        P->use_mfma = P->m2l_kind == LHF_M2L_MFMA;
         if (P->use_mfma && !wmfma_build(P, st)) {
             set_error("matrix-core M2L set-up failed");
             return LHF_ERR_HIP;
         }
-        // the half-vector VALU kernel (two lanes per part vector) wherever it has an
-        // instantiation; LHF_NO_HALF=1 keeps the one-lane tiles
-        P->use_half = !P->use_mfma && m2l_half_supported(P->precision, p) && !getenv("LHF_NO_HALF");
-        if (!P->use_mfma && !P->use_half && !tile_ok) {
-            set_error("internal: no batched M2L kernel for this order");
-            return LHF_ERR_STATE;
-        }
+        P->use_half = P->m2l_kind == LHF_M2L_HALF;
         if (P->use_half && !whalf_build(P, st)) {
             set_error("half-vector M2L set-up failed");
             return LHF_ERR_HIP;
@@ -1121,7 +1112,8 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(hipcub::DeviceRadixSort::SortPairs(tmp, sort_bytes, key, skey, idx, P->perm, (int)n, 0, end_bit, st));
     CK(dev_malloc(&P->xs, sizeof(T) * 3 * n));
     CK(dev_malloc(&P->ws, sizeof(T) * 3 * n));
-    CK(dev_malloc(&P->vfar, sizeof(T) * 6 * n));
+    // far-field v, s (and grad v when the plan may be asked for it), sorted order, SoA
+    CK(dev_malloc(&P->vfar, sizeof(T) * (P->out_grad ? 15 : 6) * n));
     CK(dev_malloc(&P->xw, sizeof(T) * 8 * n));
     CK(dev_malloc(&P->eleaf, sizeof(int32_t) * n));
     hipLaunchKernelGGL(k_gather_x<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)x, P->perm, (T *)P->xs);
@@ -1206,8 +1198,7 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(dev_malloc(&P->vcount, sizeof(int32_t) * tot));
     // batched M2L: used when a batched kernel exists for (precision, p) and the dense box maps
     // stay small (levels <= 8, at most 2^28 cells); then the V-lists are only counted
-    P->use_tile = batched_m2l_supported(P->precision, P->p) && P->depth <= 8 &&
-                  ((int64_t)ns << (3 * P->depth)) <= ((int64_t)1 << 28) && !getenv("LHF_NO_TILE");
+    P->use_tile = P->m2l_kind != LHF_M2L_GENERIC;
     if (!P->use_tile) {
         CK(dev_malloc(&P->vsrc, sizeof(int32_t) * tot * VMAX));
         CK(dev_malloc(&P->vdir, sizeof(int16_t) * tot * VMAX));
@@ -1307,6 +1298,123 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     return LHF_OK;
 }
 
+// ---- order from tolerance ------------------------------------------------------------------
+// Relative L2 errors of v and s against the split-kernel direct sum per truncation number p
+// (index p, 1..24), measured with the FP64 oracle FMM on seeded inputs of two classes:
+//   uniform:  16384 elements uniform in the unit cube, depth 4 (four per leaf), core radius
+//             a = 0.5 N^(-1/3), 256 sample targets;
+//   adaptive: the 4,194,304-element vortex ring with 10% uniform background, at most 64 elements
+//             per leaf down to level 8, a = 0.5 N^(-1/3), 128 sample targets (even p; odd p take
+//             the next even order's value).
+// Each entry is the larger of the two errors.  FP32 arithmetic adds a rounding floor.
+#include "lhf_calib.inc"
+constexpr double FP32_FLOOR = 1e-6;  // FP32 rounding of the translations and sums (measured <= 7e-7)
+
+static double calib_max(bool adaptive, int p, double *ev, double *es)
+{
+    const double *t = adaptive ? CALIB_ADAPTIVE : CALIB_UNIFORM;
+    p = std::max(1, std::min(p, MAXP));
+    if (ev) *ev = t[2 * p];
+    if (es) *es = t[2 * p + 1];
+    return std::max(t[2 * p], t[2 * p + 1]);
+}
+
+void calib_error(bool adaptive, int p, double *ev, double *es) { calib_max(adaptive, p, ev, es); }
+
+// smallest p whose calibrated error is <= tol; false (and the largest p) if none is
+bool choose_order(bool adaptive, int precision, double tol, int *p)
+{
+    const int pmax = precision == LHF_FP64 ? MAXP : 16;
+    for (int q = 1; q <= pmax; q++) {
+        double e = calib_max(adaptive, q, nullptr, nullptr);
+        if (precision == LHF_FP32) e = std::max(e, FP32_FLOOR);
+        if (e <= tol) {
+            *p = q;
+            return true;
+        }
+    }
+    *p = pmax;
+    return false;
+}
+
+// ---- kernel choice ---------------------------------------------------------------------------
+static bool m2l_available(int k, int precision, int p)
+{
+    switch (k) {
+    case LHF_M2L_HALF: return m2l_half_supported(precision, p);
+    case LHF_M2L_TILE:
+    case LHF_M2L_TILE1: return m2l_tile_supported(precision, p);
+    case LHF_M2L_MFMA: return m2l_mfma_supported(precision, p);
+    case LHF_M2L_GENERIC: return true;
+    default: return false;
+    }
+}
+
+// the kernel accumulates each target in a fixed order (no atomics)
+bool kernel_deterministic(int precision, int p, int k)
+{
+    switch (k) {
+    case LHF_M2L_HALF: return m2l_half_owned(precision, p);
+    case LHF_M2L_TILE:
+    case LHF_M2L_TILE1: return m2l_tile_owned(precision, p);
+    default: return true;  // matrix-core (one parent per wavefront, register sums), generic (per box)
+    }
+}
+
+static const char *m2l_name(int k)
+{
+    static const char *nm[] = {"AUTO", "HALF", "TILE", "TILE1", "MFMA", "GENERIC"};
+    return (k >= 0 && k <= 5) ? nm[k] : "?";
+}
+
+// Resolve the descriptor's kernel requests (host only, before any launch).  AUTO takes the
+// fastest kernel measured for (precision, p): the half-vector kernel where it is instantiated,
+// else the one-lane tile, else the generic per-box kernel; with LHF_DETERMINISTIC only kernels
+// without atomics qualify (then the matrix-core kernel, which is deterministic, precedes the
+// generic one).  Batched kernels need the dense box maps: depth <= 8 and at most 2^28 cells.
+lhf_status resolve_kernels(const lhf_desc *d, int p, bool dmap_ok, int *m2l, int *mm)
+{
+    const bool det = (d->flags & LHF_DETERMINISTIC) != 0;
+    const int prec = d->precision;
+    int k = d->m2l_kernel;
+    if (k == LHF_M2L_AUTO) {
+        k = LHF_M2L_GENERIC;
+        if (dmap_ok) {
+            const int order[] = {LHF_M2L_HALF, LHF_M2L_TILE, LHF_M2L_MFMA};
+            for (int c : order) {
+                if (c == LHF_M2L_MFMA && !det) continue;
+                if (m2l_available(c, prec, p) && (!det || kernel_deterministic(prec, p, c))) {
+                    k = c;
+                    break;
+                }
+            }
+        }
+    } else {
+        if (!m2l_available(k, prec, p)) {
+            set_error(std::string("m2l_kernel ") + m2l_name(k) + " has no instantiation for this precision and p");
+            return LHF_ERR_UNSUPPORTED;
+        }
+        if (k != LHF_M2L_GENERIC && !dmap_ok) {
+            set_error(std::string("m2l_kernel ") + m2l_name(k) + " needs depth <= 8 and n_systems * 8^depth <= 2^28");
+            return LHF_ERR_UNSUPPORTED;
+        }
+        if (det && !kernel_deterministic(prec, p, k)) {
+            set_error(std::string("m2l_kernel ") + m2l_name(k) +
+                      " accumulates with atomics at this precision and p: not deterministic");
+            return LHF_ERR_UNSUPPORTED;
+        }
+    }
+    int mk = d->mm_kernel;
+    if (mk == LHF_MM_AUTO) mk = m2l_half_supported(prec, p) ? LHF_MM_HALF : LHF_MM_GENERIC;
+    else if (mk == LHF_MM_HALF && !m2l_half_supported(prec, p)) {
+        set_error("mm_kernel HALF has no instantiation for this precision and p");
+        return LHF_ERR_UNSUPPORTED;
+    }
+    *m2l = k;
+    *mm = mk;
+    return LHF_OK;
+}
+
 // Checked plan construction shared by every creation entry point: nsys systems,
 // system s owning elements off[s] .. off[s+1]-1 of x, with cube (lo[3s..3s+2], len[s])
 // and core radius a[s] (host arrays).
@@ -1326,7 +1434,16 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
     if (!x) return arg_error("x is NULL");
     if (d->precision != LHF_FP64 && d->precision != LHF_FP32) return arg_error("unknown precision");
     const int pmax = d->precision == LHF_FP64 ? MAXP : 16;
-    if (d->p < 1 || d->p > pmax) return arg_error("p out of range (FP64: 1..24, FP32: 1..16)");
+    if (d->p < 0 || d->p > pmax) return arg_error("p out of range (FP64: 1..24, FP32: 1..16; 0: from tol)");
+    if (d->flags & ~(LHF_SINGULAR | LHF_DETERMINISTIC | LHF_OUT_GRAD)) return arg_error("unknown flag bits");
+    if (d->reserved != 0) return arg_error("reserved descriptor field must be 0");
+    if (d->translation == LHF_TRANS_DIRECT) {
+        set_error("translation = LHF_TRANS_DIRECT (full O(p^4) matrices) is not built in this library");
+        return LHF_ERR_UNSUPPORTED;
+    }
+    if (d->translation != LHF_TRANS_RCR) return arg_error("unknown translation scheme");
+    if (d->m2l_kernel < LHF_M2L_AUTO || d->m2l_kernel > LHF_M2L_GENERIC) return arg_error("unknown m2l_kernel");
+    if (d->mm_kernel < LHF_MM_AUTO || d->mm_kernel > LHF_MM_GENERIC) return arg_error("unknown mm_kernel");
     if (d->depth < 2 || d->depth > MAXDEPTH) return arg_error("depth out of range (2..10)");
     if (d->max_per_leaf < 0) return arg_error("max_per_leaf must be >= 0");
     if (!(d->tol > 0.0)) return arg_error("tol must be > 0");
@@ -1337,10 +1454,28 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
             if (!isfinite(lo[3 * s + k])) return arg_error("cube origins must be finite");
         if (!(a[s] >= 0.0) || !isfinite(a[s])) return arg_error("core radius a must be finite and >= 0");
     }
+    // order: as given, or the smallest calibrated order that reaches tol
+    int p = d->p;
+    bool tol_unmet = false;
+    const bool adaptive_tree = d->max_per_leaf > 0;
+    if (p == 0) tol_unmet = !choose_order(adaptive_tree, d->precision, d->tol, &p);
+    int m2l_kind = 0, mm_kind = 0;
+    {
+        const bool dmap_ok = d->depth <= 8 && ((int64_t)nsys << (3 * d->depth)) <= ((int64_t)1 << 28);
+        lhf_status ks = resolve_kernels(d, p, dmap_ok, &m2l_kind, &mm_kind);
+        if (ks != LHF_OK) return ks;
+    }
     lhf_plan *P = new lhf_plan();
     P->desc = *d;
+    P->desc.p = p;
     P->n = n;
-    P->p = d->p;
+    P->p = p;
+    P->m2l_kind = m2l_kind;
+    P->mm_kind = mm_kind;
+    P->deterministic = kernel_deterministic(d->precision, p, m2l_kind);
+    P->p_from_tol = d->p == 0;
+    P->out_grad = (d->flags & LHF_OUT_GRAD) != 0;
+    calib_error(adaptive_tree, p, &P->calib_err_v, &P->calib_err_s);
     P->depth = d->depth;
     P->precision = d->precision;
     P->tsize = d->precision == LHF_FP64 ? 8 : 4;
@@ -1365,9 +1500,12 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
     // warn when, in some system, the far field's singular kernel differs from the core by more than tol
     for (int s = 0; s < nsys; s++) {
         const double as = P->h_sys_a[s];
-        if (as > 0.0 && 1.0 - core_k(len[s] / (double)(1 << P->max_level), as) > d->tol) return LHF_WARN_CORE_SPLIT;
+        if (as > 0.0 && 1.0 - core_k(len[s] / (double)(1 << P->max_level), as) > d->tol) P->warnings |= 1;
     }
-    return LHF_OK;
+    if (tol_unmet) P->warnings |= 2;
+    // both warnings are kept in the plan's statistics; the status names the one that bounds the
+    // accuracy more directly (an order that cannot reach tol)
+    return tol_unmet ? LHF_WARN_TOL_UNMET : (P->warnings & 1) ? LHF_WARN_CORE_SPLIT : LHF_OK;
 }
 
 void plan_free(lhf_plan *P) { free_plan(P); }
@@ -1414,18 +1552,23 @@ lhf_status lhf_plan_create_multi(lhf_plan **out, const lhf_desc *d, int32_t n_sy
     return plan_new(out, d, n_systems, sys_offsets, x, sys_lo, sys_len, sys_a, (hipStream_t)stream);
 }
 
-lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, int32_t what, void *stream)
+lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, void *grad_v, int32_t what,
+                             void *stream)
 {
     if (!plan) return arg_error("plan is NULL");
     if (!omega || !v || !s) return arg_error("omega, v and s must be non-NULL");
     if (what < 1 || what > 3) return arg_error("what must be 1, 2 or 3");
+    if (grad_v && !plan->out_grad) {
+        set_error("grad_v requested from a plan created without LHF_OUT_GRAD");
+        return LHF_ERR_STATE;
+    }
     plan->stream = (hipStream_t)stream;
-    return execute_impl(plan, omega, v, s, what, (hipStream_t)stream);
+    return execute_impl(plan, omega, v, s, grad_v, what, (hipStream_t)stream);
 }
 
-lhf_status lhf_execute(lhf_plan *plan, const void *omega, void *v, void *s, void *stream)
+lhf_status lhf_execute(lhf_plan *plan, const void *omega, void *v, void *s, void *grad_v, void *stream)
 {
-    return lhf_execute_parts(plan, omega, v, s, 3, stream);
+    return lhf_execute_parts(plan, omega, v, s, grad_v, 3, stream);
 }
 
 lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void *omega, double a, void *v, void *s,
@@ -1434,7 +1577,7 @@ lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void 
     lhf_plan *P = nullptr;
     lhf_status st = lhf_plan_create(&P, d, n, x, a, stream);
     if (st < 0) return st;
-    lhf_status e = lhf_execute(P, omega, v, s, stream);
+    lhf_status e = lhf_execute(P, omega, v, s, nullptr, stream);
     lhf_status dd = lhf_plan_destroy(P);
     if (e < 0) return e;
     if (dd < 0) return dd;
@@ -1460,6 +1603,13 @@ lhf_status lhf_plan_stats(const lhf_plan *P, lhf_stats *out)
     out->max_level = P->max_level;
     out->n_leaves = P->nleaf;
     out->n_wx_pairs = P->n_wx;
+    out->m2l_kernel = P->m2l_kind;
+    out->mm_kernel = P->mm_kind;
+    out->deterministic = P->deterministic ? 1 : 0;
+    out->p_from_tol = P->p_from_tol ? 1 : 0;
+    out->calib_err_v = P->calib_err_v;
+    out->calib_err_s = P->calib_err_s;
+    out->warnings = P->warnings;
     return LHF_OK;
 }
 

@@ -5,6 +5,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -33,7 +35,7 @@ def test_argument_validation_is_host_side():
     dummy = C.c_void_p(0x1000)  # never dereferenced: validation fails first
     cases = [
         (dict(p=12, depth=4), 0, 0.01, "n must be >= 1"),
-        (dict(p=0, depth=4), 10, 0.01, "p out of range"),
+        (dict(p=-1, depth=4), 10, 0.01, "p out of range"),
         (dict(p=25, depth=4), 10, 0.01, "p out of range"),
         (dict(p=17, depth=4, precision=L.FP32), 10, 0.01, "p out of range"),
         (dict(p=8, depth=1), 10, 0.01, "depth out of range"),
@@ -53,7 +55,7 @@ def test_argument_validation_is_host_side():
     d = L.make_desc(p=8, depth=3)
     assert lib.lhf_plan_create(C.byref(h), C.byref(d), 10, None, 0.01, None) == -1
     assert lib.lhf_plan_create(None, C.byref(d), 10, dummy, 0.01, None) == -1
-    assert lib.lhf_execute(None, dummy, dummy, dummy, None) == -1
+    assert lib.lhf_execute(None, dummy, dummy, dummy, None, None) == -1
     assert lib.lhf_plan_destroy(None) == 0
     st = L.Stats()
     assert lib.lhf_plan_stats(None, C.byref(st)) == -1
@@ -92,3 +94,44 @@ def test_multi_system_and_batch_validation_is_host_side():
     assert lib.lhf_batch_execute(None, dummy, dummy, dummy, 1, None) == -1
     assert lib.lhf_batch_destroy(None) == 0
     assert lib.lhf_autotune(8, 7, None, None, None) == -1
+
+
+def test_descriptor_options_are_checked_on_the_host():
+    # new descriptor fields: unknown values are argument errors, valid requests that this
+    # library cannot serve are LHF_ERR_UNSUPPORTED; both before any device work
+    L, lib = _lib()
+    h = C.c_void_p()
+    dummy = C.c_void_p(0x1000)
+    cases = [
+        (dict(p=8, depth=3, flags=0x100), -1, "flag"),
+        (dict(p=8, depth=3, translation=7), -1, "translation"),
+        (dict(p=8, depth=3, translation=L.TRANS_DIRECT), -6, "LHF_TRANS_DIRECT"),
+        (dict(p=8, depth=3, m2l_kernel=9), -1, "m2l_kernel"),
+        (dict(p=8, depth=3, mm_kernel=-1), -1, "mm_kernel"),
+        (dict(p=6, depth=3, m2l_kernel=L.M2L_HALF), -6, "no instantiation"),
+        (dict(p=14, depth=3, m2l_kernel=L.M2L_MFMA), -6, "no instantiation"),
+        (dict(p=16, depth=3, m2l_kernel=L.M2L_TILE), -6, "no instantiation"),
+        (dict(p=6, depth=3, mm_kernel=L.MM_HALF), -6, "no instantiation"),
+        (dict(p=12, depth=9, m2l_kernel=L.M2L_HALF), -6, "depth <= 8"),
+        (dict(p=12, depth=3, m2l_kernel=L.M2L_HALF, flags=L.LHF_DETERMINISTIC), -6, "not deterministic"),
+        (dict(p=16, depth=3, m2l_kernel=L.M2L_HALF, flags=L.LHF_DETERMINISTIC), -6, "not deterministic"),
+    ]
+    for kw, code, msg in cases:
+        d = L.make_desc(**kw)
+        st = lib.lhf_plan_create(C.byref(h), C.byref(d), 10, dummy, 0.01, None)
+        assert st == code and h.value is None, (kw, st)
+        assert msg in lib.lhf_last_error().decode(), (kw, lib.lhf_last_error())
+    d = L.make_desc(p=8, depth=3)
+    d.reserved = 1
+    assert lib.lhf_plan_create(C.byref(h), C.byref(d), 10, dummy, 0.01, None) == -1
+    assert "reserved" in lib.lhf_last_error().decode()
+
+
+def test_output_tensors_are_checked_on_the_host():
+    # the binding refuses host tensors and wrong shapes before any pointer crosses the C ABI
+    import torch
+    L, _ = _lib()
+    with pytest.raises(TypeError):
+        L._dev_array(torch.zeros(5, 3, dtype=torch.float64), torch.float64, "v")
+    with pytest.raises(TypeError):
+        L._dev_array(np.zeros((5, 3)), torch.float64, "v")

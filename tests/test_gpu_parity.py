@@ -21,13 +21,13 @@ def _torch():
     return torch
 
 
-def _gpu_fmm(x, w, a, p, depth, what=3, precision=0, flags=0):
+def _gpu_fmm(x, w, a, p, depth, what=3, precision=0, flags=0, **kw):
     torch = _torch()
     import paper_1201_5430_amd as L
     dt = torch.float64 if precision == 0 else torch.float32
     xt = torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dt)
     wt = torch.from_numpy(np.ascontiguousarray(w)).to(device="cuda", dtype=dt)
-    plan = L.Plan(xt, a, p=p, depth=depth, precision=precision, flags=flags)
+    plan = L.Plan(xt, a, p=p, depth=depth, precision=precision, flags=flags, **kw)
     v, s = plan.execute(wt, what=what)
     torch.cuda.synchronize()
     st = plan.stats()
@@ -46,6 +46,12 @@ def _check(v, s, vr, sr, l2=1e-12, mx=1e-11):
     print(f"rel L2 v {ev:.3e} s {es:.3e}  max v {mv:.3e} s {ms:.3e}", flush=True)
     assert ev <= l2 and es <= l2
     assert mv <= mx and ms <= mx
+
+
+def _check32(v, s, vr, sr, l2=2e-6, mx=1e-5):
+    """FP32 path against the FP64 oracle on the FP32-rounded inputs: relative L2 of v and s
+    <= l2 and every element within mx of the largest reference magnitude"""
+    _check(v, s, vr, sr, l2=l2, mx=mx)
 
 
 def test_cube4k_fp64_matches_oracle(oracle):
@@ -131,16 +137,36 @@ def test_cube1m_fp64_sampled_leaves(oracle):
     assert st["boxes"][d] > 250000
 
 
-def test_generic_and_tiled_m2l_agree(oracle, monkeypatch):
+def test_cube1m_fp32_sampled_leaves(oracle):
+    # the mixed-precision workload at full size: FP32 elements and expansions, 2^20 elements,
+    # depth 6, p = 10; the oracle runs the whole FMM in FP64 on the FP32-rounded inputs for
+    # the leaves of 48 seeded elements
+    cfg = workloads.make("cube1m_fp32")
+    x = cfg["x"].astype(np.float32).astype(np.float64)
+    w = cfg["w"].astype(np.float32).astype(np.float64)
+    a = float(np.float32(cfg["a"]))
+    p, d = cfg["p"], cfg["depth"]
+    v, s, st = _gpu_fmm(x, w, a, p, d, precision=1)
+    samp = workloads.sample_targets(x.shape[0], 48, seed=8)
+    vr, sr, _ = oracle.fmm(x, w, a, p, d, sample=samp)
+    m = ~np.isnan(vr[:, 0])
+    assert m.sum() >= 48
+    print(f"cube1m FP32 p={p} ({m.sum()} elements): ", end="")
+    _check32(v[m], s[m], vr[m], sr[m])
+    assert st["boxes"][d] > 250000
+
+
+def test_generic_and_tiled_m2l_agree(oracle):
     # the class-batched M2L kernel and the generic one-wave-per-box kernel give the same field
+    import paper_1201_5430_amd as L
     rng = np.random.default_rng(31)
     n = 6000
     x = rng.uniform(0, 1, (n, 3))
     w = rng.normal(size=(n, 3))
     a = 0.5 * n ** (-1 / 3)
-    v1, s1, _ = _gpu_fmm(x, w, a, 12, 4)
-    monkeypatch.setenv("LHF_NO_TILE", "1")
-    v2, s2, _ = _gpu_fmm(x, w, a, 12, 4)
+    v1, s1, st1 = _gpu_fmm(x, w, a, 12, 4)
+    v2, s2, st2 = _gpu_fmm(x, w, a, 12, 4, m2l_kernel=L.M2L_GENERIC)
+    assert st1["m2l_kernel"] == "half" and st2["m2l_kernel"] == "generic"
     _check(v1, s1, v2, s2, l2=1e-13, mx=1e-12)
 
 
@@ -155,9 +181,8 @@ def test_fp32_path_matches_fp64_oracle(oracle, p, depth):
     a = float(np.float32(0.5 * n ** (-1 / 3)))
     vr, sr, _ = oracle.fmm(x, w, a, p, depth)
     v, s, _ = _gpu_fmm(x, w, a, p, depth, precision=1)
-    ev, es = _rel(v, vr), _rel(s, sr)
-    print(f"FP32 p={p} depth={depth}: rel L2 v {ev:.3e} s {es:.3e}", flush=True)
-    assert ev < 2e-6 and es < 2e-6
+    print(f"FP32 p={p} depth={depth}: ", end="")
+    _check32(v, s, vr, sr)
 
 
 @pytest.mark.parametrize("p", [4, 6, 8, 10])
@@ -173,14 +198,15 @@ def test_fp32_batched_m2l_orders(oracle, p):
     vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
     m = ~np.isnan(vr[:, 0])
     v, s, _ = _gpu_fmm(x, w, a, p, 5, precision=1)
-    ev, es = _rel(v[m], vr[m]), _rel(s[m], sr[m])
-    print(f"FP32 p={p} depth=5 sampled: rel L2 v {ev:.3e} s {es:.3e}", flush=True)
-    assert ev < 2e-6 and es < 2e-6
+    print(f"FP32 p={p} depth=5 sampled: ", end="")
+    _check32(v[m], s[m], vr[m], sr[m])
 
 
 @pytest.mark.parametrize("p", [8, 10])
-def test_fp32_two_row_tile(oracle, monkeypatch, p):
-    # the ownership tile with two schedule rows per batch: against the oracle and the one-row tile
+def test_fp32_two_row_tile(oracle, p):
+    # the one-lane ownership tile with two schedule rows per batch: against the oracle and the
+    # one-row tile
+    import paper_1201_5430_amd as L
     rng = np.random.default_rng(100 + p)
     n = 30000
     x = rng.uniform(0, 1, (n, 3)).astype(np.float32).astype(np.float64)
@@ -189,22 +215,21 @@ def test_fp32_two_row_tile(oracle, monkeypatch, p):
     samp = rng.choice(n, 40, replace=False)
     vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
     m = ~np.isnan(vr[:, 0])
-    v2, s2, _ = _gpu_fmm(x, w, a, p, 5, precision=1)  # two rows per batch (the default here)
-    monkeypatch.setenv("LHF_TILE1", "1")
-    v1, s1, _ = _gpu_fmm(x, w, a, p, 5, precision=1)
-    ev, es = _rel(v2[m], vr[m]), _rel(s2[m], sr[m])
-    print(f"two-row tile FP32 p={p}: rel L2 v {ev:.3e} s {es:.3e}; vs one-row {_rel(v2, v1):.3e}", flush=True)
-    assert ev < 2e-6 and es < 2e-6
-    assert _rel(v2, v1) < 2e-6 and _rel(s2, s1) < 2e-6
+    v2, s2, st2 = _gpu_fmm(x, w, a, p, 5, precision=1, m2l_kernel=L.M2L_TILE)
+    v1, s1, st1 = _gpu_fmm(x, w, a, p, 5, precision=1, m2l_kernel=L.M2L_TILE1)
+    assert st2["m2l_kernel"] == "tile" and st1["m2l_kernel"] == "tile1"
+    print(f"two-row tile FP32 p={p}: ", end="")
+    _check32(v2[m], s2[m], vr[m], sr[m])
+    print("  vs one-row: ", end="")
+    _check32(v2, s2, v1, s1)
 
 
 @pytest.mark.parametrize("prec,p", [(0, 8), (0, 10), (0, 12), (0, 16), (1, 8), (1, 10), (1, 12), (1, 16)])
-def test_half_vector_m2l(oracle, monkeypatch, prec, p):
+def test_half_vector_m2l(oracle, prec, p):
     # the M2L kernel with each part vector split over two lanes by the parity of m (the default
-    # at FP64 p = 8..16 and FP32 p = 12, 16; FP32 p = 8, 10 on request): against the oracle on
-    # sampled leaves and against the one-lane tile (FP64 p = 16: the generic per-box kernel)
-    # on every element
-    monkeypatch.setenv("LHF_HALF", "1")
+    # at p = 8, 10, 12, 16): against the oracle on sampled leaves and against the one-lane tile
+    # (FP64 p = 16: the generic per-box kernel) on every element
+    import paper_1201_5430_amd as L
     rng = np.random.default_rng(110 + p + prec)
     n = 30000
     x = rng.uniform(0, 1, (n, 3))
@@ -217,19 +242,17 @@ def test_half_vector_m2l(oracle, monkeypatch, prec, p):
     samp = rng.choice(n, 40, replace=False)
     vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
     m = ~np.isnan(vr[:, 0])
-    vh, sh, _ = _gpu_fmm(x, w, a, p, 5, precision=prec)
-    monkeypatch.delenv("LHF_HALF")
-    monkeypatch.setenv("LHF_NO_HALF", "1")
-    v1, s1, _ = _gpu_fmm(x, w, a, p, 5, precision=prec)
-    ev, es = _rel(vh[m], vr[m]), _rel(sh[m], sr[m])
-    print(f"half-vector M2L prec={prec} p={p}: rel L2 v {ev:.3e} s {es:.3e}; "
-          f"vs one-lane {_rel(vh, v1):.3e} {_rel(sh, s1):.3e}", flush=True)
+    vh, sh, sth = _gpu_fmm(x, w, a, p, 5, precision=prec, m2l_kernel=L.M2L_HALF)
+    other = L.M2L_GENERIC if (prec == 0 and p == 16) else L.M2L_TILE
+    v1, s1, st1 = _gpu_fmm(x, w, a, p, 5, precision=prec, m2l_kernel=other)
+    assert sth["m2l_kernel"] == "half" and st1["m2l_kernel"] == L.M2L_NAMES[other]
+    print(f"half-vector M2L prec={prec} p={p}: ", end="")
     if prec == 0:
         _check(vh[m], sh[m], vr[m], sr[m])
         _check(vh, sh, v1, s1, l2=1e-13, mx=1e-12)
     else:
-        assert ev < 2e-6 and es < 2e-6
-        assert _rel(vh, v1) < 2e-6 and _rel(sh, s1) < 2e-6
+        _check32(vh[m], sh[m], vr[m], sr[m])
+        _check32(vh, sh, v1, s1)
 
 
 def test_reused_device_blocks(oracle):
@@ -251,18 +274,20 @@ def test_reused_device_blocks(oracle):
 
 
 @pytest.mark.parametrize("prec,p,depth", [(0, 12, 5), (0, 16, 4), (1, 10, 5)])
-def test_batched_m2m_l2l_match_generic(monkeypatch, prec, p, depth):
-    # the half-vector M2M/L2L kernels (the default at p >= 8) against the generic per-box shifts
+def test_batched_m2m_l2l_match_generic(prec, p, depth):
+    # the half-vector M2M/L2L kernels (the default at p = 8, 10, 12, 16) against the generic
+    # per-box shifts
+    import paper_1201_5430_amd as L
     rng = np.random.default_rng(120 + p)
     n = 30000
     x = rng.uniform(0, 1, (n, 3))
     w = rng.normal(size=(n, 3))
     a = 0.5 * n ** (-1 / 3)
-    v1, s1, _ = _gpu_fmm(x, w, a, p, depth, precision=prec)
-    monkeypatch.setenv("LHF_NO_MMHALF", "1")
-    v2, s2, _ = _gpu_fmm(x, w, a, p, depth, precision=prec)
+    v1, s1, st1 = _gpu_fmm(x, w, a, p, depth, precision=prec)
+    v2, s2, st2 = _gpu_fmm(x, w, a, p, depth, precision=prec, mm_kernel=L.MM_GENERIC)
+    assert st1["mm_kernel"] == "half" and st2["mm_kernel"] == "generic"
     print(f"batched vs generic M2M/L2L prec={prec} p={p}: {_rel(v1, v2):.3e} {_rel(s1, s2):.3e}", flush=True)
     if prec == 0:
         _check(v1, s1, v2, s2, l2=1e-13, mx=1e-12)
     else:
-        assert _rel(v1, v2) < 2e-6 and _rel(s1, s2) < 2e-6
+        _check32(v1, s1, v2, s2)

@@ -29,7 +29,7 @@ CONFIGS = {
     "cube1m_fp64": dict(n=1 << 20, seed=2, depth=6, p=12, precision="fp64",
                         desc="N=1,048,576 uniform cube, depth 6, p=12, FP64"),
     "cube1m_fp32": dict(n=1 << 20, seed=2, depth=6, p=10, precision="fp32",
-                        desc="N=1,048,576 uniform cube, depth 6, p=10, FP32 + MFMA"),
+                        desc="N=1,048,576 uniform cube, depth 6, p=10, FP32 elements and expansions"),
     "ring4m_fp32": dict(n=1 << 22, seed=4, depth=0, max_per_leaf=64, p=16, precision="fp32",
                         desc="N=4,194,304 vortex ring + 10% background, adaptive <=64/leaf, p=16"),
     "batch256_fp32": dict(n_systems=256, seed=5, p=10, precision="fp32",
