@@ -185,6 +185,17 @@ lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s
 lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void *omega, double a,
                         void *v, void *s, void *stream);
 
+/* One-shot evaluation that allocates no device memory, for callers that cannot call hipMalloc
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, results and errors as lhf_evaluate; every device buffer of its plan comes
+ * from a fixed 256 MiB array the library holds on each device until the process ends.
+ * Limits: n <= 131072, and the plan must fit the array (about 65536 FP64 elements at p = 12,
+ * depth 5); otherwise LHF_ERR_WORKSPACE with nothing written.  Calls on one device share the
+ * array: calls that overlap on one device (other threads, other streams) race.  Synchronises
+ * 'stream'. */
+lhf_status lhf_evaluate_noalloc(const lhf_desc *d, int64_t n, const void *x, const void *omega, double a,
+                                void *v, void *s, void *stream);
+
 /* Counts of the plan (boxes, translations, near-field pairs). */
 lhf_status lhf_plan_stats(const lhf_plan *plan, lhf_stats *out);
 

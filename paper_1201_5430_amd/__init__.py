@@ -34,7 +34,7 @@ EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_plan_create_multi", "lhf_
            "lhf_evaluate", "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version",
            "lhf_profile_begin", "lhf_profile_end", "lhf_tune_default", "lhf_autotune", "lhf_choose_depth",
            "lhf_batch_create", "lhf_batch_execute", "lhf_batch_info", "lhf_batch_destroy",
-           "lhf_release_cached_memory")
+           "lhf_release_cached_memory", "lhf_evaluate_noalloc")
 PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 
 
@@ -85,6 +85,8 @@ def load():
         L.lhf_execute_parts.restype = C.c_int
         L.lhf_evaluate.argtypes = [C.POINTER(Desc), C.c_int64, vp, vp, C.c_double, vp, vp, vp]
         L.lhf_evaluate.restype = C.c_int
+        L.lhf_evaluate_noalloc.argtypes = [C.POINTER(Desc), C.c_int64, vp, vp, C.c_double, vp, vp, vp]
+        L.lhf_evaluate_noalloc.restype = C.c_int
         L.lhf_plan_stats.argtypes = [vp, C.POINTER(Stats)]
         L.lhf_plan_stats.restype = C.c_int
         L.lhf_plan_destroy.argtypes = [vp]
@@ -269,6 +271,23 @@ def evaluate(x, omega, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1
     d = make_desc(p, depth, precision, lo, L, tol)
     _check(load().lhf_evaluate(C.byref(d), x.shape[0], C.c_void_p(x.data_ptr()), C.c_void_p(omega.data_ptr()),
                                float(a), C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr()), _stream()))
+    return v, s
+
+
+def evaluate_noalloc(x, omega, a, p=8, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, v=None,
+                     s=None):
+    """One-shot evaluation that allocates no device memory inside the library (its plan lives in
+    a fixed per-device array); pass v and s to avoid torch allocations as well."""
+    import torch
+    dtype = torch.float64 if precision == FP64 else torch.float32
+    x = _dev_array(x, dtype, "x")
+    n = x.shape[0]
+    omega = _dev_array(omega, dtype, "omega", n)
+    v = torch.empty_like(omega) if v is None else _dev_array(v, dtype, "v", n)
+    s = torch.empty_like(omega) if s is None else _dev_array(s, dtype, "s", n)
+    d = make_desc(p, depth, precision, lo, L, tol)
+    _check(load().lhf_evaluate_noalloc(C.byref(d), n, C.c_void_p(x.data_ptr()), C.c_void_p(omega.data_ptr()),
+                                       float(a), C.c_void_p(v.data_ptr()), C.c_void_p(s.data_ptr()), _stream()))
     return v, s
 
 

@@ -91,8 +91,32 @@ void mem_trim_locked(MemCache &m, int dev, size_t keep)
 }
 }  // namespace
 
+// ---- allocation-free evaluation: a bump arena over a fixed device array ----------------------
+// While a thread runs lhf_evaluate_noalloc, every device block of its plan (and every temporary
+// of the plan's construction) is carved from that call's arena instead of hipMalloc; freeing
+// such a block is a no-op.  The arena's memory is the file-scope array 'scratch' below.
+namespace {
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, off = 0;
+    size_t need = 0;       // bytes the plan asked for when the arena ran out (0: it did not)
+};
+thread_local Arena *t_arena = nullptr;
+}  // namespace
+
 hipError_t dev_malloc_raw(void **p, size_t bytes)
 {
+    if (t_arena) {
+        const size_t at = (t_arena->off + 255) & ~(size_t)255;
+        if (at + bytes > t_arena->cap) {
+            t_arena->need = at + bytes;
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+        *p = t_arena->base + at;
+        t_arena->off = at + bytes;
+        return hipSuccess;
+    }
     if (!mem_cache_on()) return hipMalloc(p, bytes);
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -127,6 +151,7 @@ hipError_t dev_malloc_raw(void **p, size_t bytes)
 hipError_t dev_free(void *p)
 {
     if (!p) return hipSuccess;
+    if (t_arena && (char *)p >= t_arena->base && (char *)p < t_arena->base + t_arena->cap) return hipSuccess;
     if (!mem_cache_on()) return hipFree(p);
     MemCache &m = mem_cache();
     std::lock_guard<std::mutex> lk(m.mu);
@@ -1510,6 +1535,37 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
 
 void plan_free(lhf_plan *P) { free_plan(P); }
 
+// Device memory of lhf_evaluate_noalloc: one copy of this array per device, held until the
+// process ends.  Its name is a host-side stand-in in host code; kernels only ever receive the
+// device address that hipGetSymbolAddress returns for the current device (noalloc_scratch).
+constexpr size_t NOALLOC_BYTES = (size_t)256 << 20;
+constexpr int64_t NOALLOC_MAX_N = (int64_t)1 << 17;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int MAX_DEVICES = 64;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+// device address of 'scratch' on the current device, looked up once per device
+static lhf_status noalloc_scratch(void **out)
+{
+    int dev = 0;
+    LHF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return arg_error("device index beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                     "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LHF_OK;
+}
+
 }  // namespace lhf
 
 using namespace lhf;
@@ -1579,6 +1635,43 @@ lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void 
     if (st < 0) return st;
     lhf_status e = lhf_execute(P, omega, v, s, nullptr, stream);
     lhf_status dd = lhf_plan_destroy(P);
+    if (e < 0) return e;
+    if (dd < 0) return dd;
+    return st;
+}
+
+lhf_status lhf_evaluate_noalloc(const lhf_desc *d, int64_t n, const void *x, const void *omega, double a, void *v,
+                                void *s, void *stream)
+{
+    if (!d) return arg_error("desc is NULL");
+    if (!x || !omega || !v || !s) return arg_error("x, omega, v and s must be non-NULL");
+    if (n < 1) return arg_error("n must be >= 1");
+    if (n > NOALLOC_MAX_N) {
+        set_error("lhf_evaluate_noalloc: n = " + std::to_string(n) + " exceeds its maximum of " +
+                  std::to_string(NOALLOC_MAX_N) + " elements");
+        return LHF_ERR_WORKSPACE;
+    }
+    void *base = nullptr;
+    lhf_status st = noalloc_scratch(&base);
+    if (st != LHF_OK) return st;
+    Arena ar;
+    ar.base = (char *)base;
+    ar.cap = NOALLOC_BYTES;
+    t_arena = &ar;
+    lhf_plan *P = nullptr;
+    st = lhf_plan_create(&P, d, n, x, a, stream);
+    lhf_status e = LHF_OK, dd = LHF_OK;
+    if (st >= 0) {
+        e = lhf_execute(P, omega, v, s, nullptr, stream);
+        dd = lhf_plan_destroy(P);  // synchronises; its blocks return to nothing (arena)
+    }
+    t_arena = nullptr;
+    if (ar.need) {
+        set_error("lhf_evaluate_noalloc: the plan needs more than the " + std::to_string(NOALLOC_BYTES >> 20) +
+                  " MiB of its fixed device array (asked for " + std::to_string(ar.need) + " bytes)");
+        return LHF_ERR_WORKSPACE;
+    }
+    if (st < 0) return st;
     if (e < 0) return e;
     if (dd < 0) return dd;
     return st;
