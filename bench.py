@@ -1,29 +1,40 @@
 """Benchmark of one FMM evaluation of v and s (the whole hot path) on one GPU.
 
-    python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--p P] [--legs ring16,cube,batch]
+                    [--no-cpu-baseline] [--calib-copy MIB]
 
-A step is one pass of the whole path over the synthetic input, already
-resident in device memory: plan (Morton keys, sort, octree, interaction lists,
-operator tables) + execute (P2M, M2M, M2L/L2L, L2P, P2P) for N elements.
-Prints ONE JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+A step is one pass of the whole path over the synthetic input, already resident
+in device memory: plan (Morton keys, sort, octree, interaction lists, operator
+tables) + execute (P2M, M2M, M2L/L2L, L2P, P2P) for N elements.  Prints ONE JSON
+line.  Only one GPU is used: --gpus above 1 exits.
 
-Roofline: the dominant kernel is the downward pass (M2L + L2L, one launch per
-level); its time comes from HIP events recorded by the library on the execute
-stream during the timed steps.  Algorithmic work per M2L translation (RCR,
-both potentials, real-packed):
-    F(p) = 2 [2 F_roty + 2 F_rotz + F_coax] + 6 p^2,
-    F_roty = 2p(4p^2-1)/3, F_rotz = 3p(p-1), F_coax = 2p(2p^2+1)/3
-(25,472 flop at p = 12), times the number of M2L translations.
-CPU baseline: the FP64 oracle (direct-mode translations) on the same input:
-full upward pass plus the downward pass and near field of a seeded sample of
-leaves; the full-job time is projected from the per-translation and per-pair
-rates of the sample.
+Headline: the clustered workload (4,194,304 elements on a vortex ring with 10%
+uniform background, adaptive octree of at most 64 elements per leaf down to level
+8) in FP64 at the smallest order p whose relative L2 errors of v and s against the
+split-kernel direct sum are both <= 1e-6 (p = 23 by the error-vs-order sweep; the
+run measures the errors it reaches on 4096 seeded targets with the oracle).  The
+other legs are labelled sections of the same line: the same ring at p = 16 in FP32
+and FP64 (the precision speedup), the 2^20-element uniform cube (FP64 p = 12, FP32
+p = 10) and the batch of 256 systems.
+
+Roofline: per phase (gather, P2M, M2M, M2L + L2L, L2P, P2P) the algorithmic work
+(flop and compulsory HBM bytes, counted in roofline_work()) against the MI355X
+peaks, T_roof = sum over phases of max(flop / peak, bytes / 8 TB/s), and the
+aggregate T_roof / T_meas.  The dominant kernel (the batched M2L) is reported in
+the 'roofline' object: algorithmic flop per launch over its average launch time,
+measured with HIP events the library records on the execute stream.
+
+CPU baseline: the FP64 oracle (direct O(p^4) translation matrices, OpenMP), timed
+on the host: per-operation rates measured on a bounded sample of the same
+workload and projected to the whole job with the plan's own counts.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -32,35 +43,77 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "vortex elements/s (v + stretching) at rel err 1e-6; FP32-MFMA vs FP64 speedup"
-PEAK_FP64_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
-PEAK_FP32_MFMA_TFLOPS = 157.3
-PEAK_FP32_VALU_TFLOPS = 78.6  # non-packed FP32 FMA, same unit count as FP64
+P_STAR = 23  # smallest p with eps2(v), eps2(s) <= 1e-6 on the ring (error-vs-order sweep)
+PEAK_FP64_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (vector and matrix)
+PEAK_FP32_VALU_TFLOPS = 78.6     # non-packed FP32 FMA: the same unit count (the build forbids packed FP32)
+PEAK_FP32_MFMA_TFLOPS = 157.3    # FP32 matrix cores
 PEAK_HBM_GBS = 8000.0
-
-
-def f_m2l(p: int) -> int:
-    f_roty = 2 * p * (4 * p * p - 1) // 3
-    f_rotz = 3 * p * (p - 1)
-    f_coax = 2 * p * (2 * p * p + 1) // 3
-    return 2 * (2 * f_roty + 2 * f_rotz + f_coax) + 6 * p * p
-
-
-# the M2L kernel the library runs for the cube workloads (FP64 p = 12, FP32 p = 10)
-M2L_KERNEL = {0: "k_m2l_half", 1: "k_m2l_half"}  # by lhf_precision (FP64 = 0, FP32 = 1)
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(which):
-    """HBM bytes per M2L launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary,
-    or None when the kernel's source changed after the counters were taken"""
+def f_m2l(p: int) -> int:
+    """algorithmic flop of one M2L translation (RCR, both potentials, real-packed; FMA = 2)"""
+    f_roty = 2 * p * (4 * p * p - 1) // 3
+    f_rotz = 3 * p * (p - 1)
+    f_coax = 2 * p * (2 * p * p + 1) // 3
+    return 2 * (2 * f_roty + 2 * f_rotz + f_coax) + 6 * p * p
+
+
+def f_mm(p: int) -> int:
+    """M2M / L2L translation: the same rotations and a triangular coaxial block (half the
+    Hankel block's flop), conversion 4 p^2"""
+    f_roty = 2 * p * (4 * p * p - 1) // 3
+    f_rotz = 3 * p * (p - 1)
+    f_coax = p * (2 * p * p + 1) // 3
+    return 2 * (2 * f_roty + 2 * f_rotz + f_coax) + 4 * p * p
+
+
+def roofline_work(st, p, prec, n):
+    """algorithmic flop and compulsory HBM bytes per phase of one execute"""
+    T = 8 if prec == 0 else 4
+    nbox = sum(st["boxes"])
+    nleaf = st["n_leaves"] or st["boxes"][-1]
+    exp_b = 2 * p * p * T  # one expansion (phi, chi)
+    pairs_u, pairs_wx = st["n_p2p_pairs"], st["n_wx_pairs"]
+    return {
+        "gather": (0.0, n * (3 * T + 4 + 3 * T) + n * (3 * T + 8 * T)),
+        "p2m": (40.0 * p * p * n, 6 * T * n + nleaf * exp_b),
+        "m2m": (st["n_m2m"] * f_mm(p), 2.0 * nbox * exp_b),
+        "down": (st["n_m2l"] * f_m2l(p) + st["n_l2l"] * f_mm(p), 3.0 * nbox * exp_b),
+        "l2p": (34.0 * p * p * n, nleaf * exp_b + 12 * T * n),
+        "p2p": (70.0 * pairs_u + 56.0 * pairs_wx, 20 * T * n),
+    }
+
+
+def phase_roofline(st, ph, p, prec, n):
+    peak = PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP32_VALU_TFLOPS
+    work = roofline_work(st, p, prec, n)
+    out, t_roof, t_meas = {}, 0.0, 0.0
+    for k, (fl, by) in work.items():
+        ms = ph[k]
+        tr = max(fl / (peak * 1e12), by / (PEAK_HBM_GBS * 1e9)) * 1e3
+        bound = "alu" if fl / (peak * 1e12) >= by / (PEAK_HBM_GBS * 1e9) else "hbm"
+        out[k] = {"ms": ms, "flop": fl, "bytes": by, "bound": bound, "t_roof_ms": tr,
+                  "frac": tr / ms if ms > 0 else None,
+                  "achieved_tflops": fl / (ms * 1e-3) / 1e12 if ms > 0 else None,
+                  "achieved_gbs": by / (ms * 1e-3) / 1e9 if ms > 0 else None}
+        t_roof += tr
+        t_meas += ms
+    return out, {"t_roof_ms": t_roof, "t_meas_ms": t_meas, "frac": t_roof / t_meas if t_meas > 0 else None,
+                 "peak_alu_tflops": peak, "peak_hbm_gbs": PEAK_HBM_GBS}
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None when the kernel's source changed since"""
     import hashlib
     import re
     try:
-        md = open(os.path.join(ROOT, "profiles", "m2l_cube1m_hbm.md")).read()
-        js = json.loads(re.search(r"```json\n(.*?)\n```", md, re.S).group(1))[which]
+        md = open(os.path.join(ROOT, "profiles", "m2l_hbm.md")).read()
+        js = json.loads(re.search(r"```json\n(.*?)\n```", md, re.S).group(1))[name]
         src = open(os.path.join(ROOT, "paper_1201_5430_amd", "csrc", js["source"]), "rb").read()
         if hashlib.sha256(src).hexdigest()[:16] != js["source_sha256_prefix"]:
             return None
@@ -69,44 +122,132 @@ def measured_traffic(which):
         return None
 
 
-def accuracy(cfg, v, s, n_targets=1000):
-    """relative L2 error of v and s against the oracle's split-kernel direct sum on sampled
-    targets (the paper measures on 1000 random source points); oracle leg of the benchmark"""
+def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warmup):
+    """time `steps` plan + execute steps (inputs resident on the device); per-phase times from the
+    library's HIP events on the execute stream"""
+    dt = torch.float64 if prec == lhf.FP64 else torch.float32
+    xt = torch.from_numpy(x).to(device="cuda", dtype=dt)
+    wt = torch.from_numpy(w).to(device="cuda", dtype=dt)
+    v, s = torch.empty_like(wt), torch.empty_like(wt)
+
+    def step(profile):
+        pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=max_per_leaf)
+        if profile:
+            pl.profile_begin(1)
+        pl.execute(wt, v, s)
+        ph = pl.profile_end()[0] if profile else None
+        st = pl.stats()
+        pl.close()
+        return ph, st
+
+    for k in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    phases = {k: 0.0 for k in lhf.PHASES}
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ph, st = step(True)
+        for kk in phases:
+            phases[kk] += ph[kk] / steps
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    exec_ms = sum(vv for kk, vv in phases.items() if kk != "m2l")  # m2l is part of "down"
+    log(f"bench: {name}: {ms:.2f} ms per step (execute {exec_ms:.2f} ms, M2L {phases['m2l']:.2f} ms)")
+    n = x.shape[0]
+    m2l_tf = st["n_m2l"] * f_m2l(p) / (phases["m2l"] * 1e-3) / 1e12 if phases["m2l"] > 0 else None
+    res = {"workload": name, "n": n, "p": p, "precision": "fp64" if prec == lhf.FP64 else "fp32",
+           "steps": steps, "ms_per_step": ms, "elements_per_s": n / (ms * 1e-3), "execute_ms": exec_ms,
+           "plan_ms": ms - exec_ms, "execute_only_elements_per_s": n / (exec_ms * 1e-3), "phases_ms": phases,
+           "m2l_kernel": st["m2l_kernel"], "m2l_achieved_tflops": m2l_tf,
+           "counts": {"boxes": st["boxes"], "leaves": st["n_leaves"], "m2l": st["n_m2l"], "m2m": st["n_m2m"],
+                      "u_pairs": st["n_p2p_pairs"], "wx_pairs": st["n_wx_pairs"]}}
+    if prec == lhf.FP64:
+        res["m2l_frac_of_fp64_peak"] = m2l_tf / PEAK_FP64_TFLOPS if m2l_tf else None
+    else:
+        res["m2l_frac_of_fp32_valu_peak"] = m2l_tf / PEAK_FP32_VALU_TFLOPS if m2l_tf else None
+        res["m2l_frac_of_fp32_mfma_peak"] = m2l_tf / PEAK_FP32_MFMA_TFLOPS if m2l_tf else None
+    res["phase_roofline"], res["aggregate_roofline"] = phase_roofline(st, phases, p, prec, n)
+    out = (v.double().cpu().numpy(), s.double().cpu().numpy())
+    del xt, wt, v, s
+    return res, st, out
+
+
+def rel_err(v, s, tg, vd, sd):
+    import numpy as np
+    return {"rel_l2_v": float(np.linalg.norm(v[tg] - vd) / np.linalg.norm(vd)),
+            "rel_l2_s": float(np.linalg.norm(s[tg] - sd) / np.linalg.norm(sd)),
+            "max_v": float(np.abs(v[tg] - vd).max() / np.abs(vd).max()),
+            "max_s": float(np.abs(s[tg] - sd).max() / np.abs(sd).max())}
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(x, w, a, p, mx, lmax, st, n_trans=60, n_targets=256):
+    """The FP64 oracle on the headline workload, timed on a bounded sample and projected to the
+    whole job with the plan's counts:
+      * translations: n_trans M2L translations of the oracle (full O(p^4) matrices, one thread)
+        on the workload's own multipoles' shapes; M2M and L2L are costed as M2L (an upper
+        bound); the oracle spreads them over its OpenMP threads;
+      * near field: the oracle's adaptive split direct sum on n_targets seeded targets
+        (OpenMP), scaled by the job's U and W/X pair count over the pairs sampled;
+      * P2M and L2P: oracle calls on the elements of sampled leaves."""
     import numpy as np
     import oracle
     import workloads
-    x, w, a, d = cfg["x"], cfg["w"], cfg["a"], cfg["depth"]
-    if cfg.get("precision") == "fp32":
-        x = x.astype(np.float32).astype(np.float64)
-        w = w.astype(np.float32).astype(np.float64)
-        a = float(np.float32(a))
-    tg = workloads.sample_targets(x.shape[0], n_targets, seed=1000)
-    vd, sd = oracle.direct(x, w, a, mode=oracle.DIRECT_SPLIT, depth=d, targets=tg)
-    ev = float(np.linalg.norm(v[tg] - vd) / np.linalg.norm(vd))
-    es = float(np.linalg.norm(s[tg] - sd) / np.linalg.norm(sd))
-    return {"rel_l2_v": ev, "rel_l2_s": es, "targets": int(len(tg)),
-            "reference": "split-kernel direct sum (Gaussian core between adjacent leaves, singular beyond), FP64 oracle"}
-
-
-def cpu_baseline(cfg, n_leaves=64):
-    import oracle
-    import workloads
-    x, w, a, p, d = cfg["x"], cfg["w"], cfg["a"], cfg["p"], cfg["depth"]
-    samp = workloads.sample_targets(x.shape[0], n_leaves, seed=99)
+    threads = oracle.num_threads()
+    rng = np.random.default_rng(7)
+    # translations (single thread)
+    phi = rng.normal(size=p * p) + 1j * rng.normal(size=p * p)
+    chi = rng.normal(size=p * p) + 1j * rng.normal(size=p * p)
     t0 = time.perf_counter()
-    _, _, st = oracle.fmm(x, w, a, p, d, sample=samp)
-    wall = time.perf_counter() - t0
-    _, m2l_tot, pairs_tot = oracle.tree_counts(x, d)
-    t_down = st["t_down"] * m2l_tot / max(st["n_m2l"], 1)
-    t_near = st["t_near"] * pairs_tot / max(st["n_p2p_pairs"], 1)
-    t_job = st["t_tree"] + st["t_up"] + t_down + t_near
+    for k in range(n_trans):
+        t = rng.integers(-3, 4, size=3).astype(float)
+        t[0] = 2.0 + k % 2
+        oracle.m2l(p, t * 2.0 ** -6, phi, chi)
+    t_tr = (time.perf_counter() - t0) / n_trans
+    # P2M + L2P per element (single thread), on 64-element boxes of the input
+    xs, ws = x[:64], w[:64]
+    c = xs.mean(0)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        ph, ch = oracle.p2m(p, c, xs, ws)
+        oracle.l2p(p, c, ph, ch, xs, ws)
+    t_el = (time.perf_counter() - t0) / (5 * 64)
+    # near field: the split direct sum over all sources for a few targets (OpenMP); two calls
+    # with different target counts, so that the oracle's tree construction cancels
+    tg = workloads.sample_targets(x.shape[0], n_targets, seed=4242)
+    t0 = time.perf_counter()
+    oracle.direct_adaptive(x, w, a, mx, lmax, targets=tg[: n_targets // 4])
+    t1 = time.perf_counter()
+    oracle.direct_adaptive(x, w, a, mx, lmax, targets=tg)
+    t2 = time.perf_counter()
+    t_near_s = max((t2 - t1) - (t1 - t0), 1e-9)
+    pairs_sampled = (n_targets - n_targets // 4) * (x.shape[0] - 1)
+    n = x.shape[0]
+    n_tr = st["n_m2l"] + st["n_m2m"] + st["n_l2l"]
+    pairs_job = st["n_p2p_pairs"] + st["n_wx_pairs"]
+    # the direct sum visits every source per target; the job's near field visits its pairs only
+    t_near = t_near_s * pairs_job / pairs_sampled
+    t_job_all = n_tr * t_tr / threads + n * t_el / threads + t_near
+    t_job_1 = n_tr * t_tr + n * t_el + t_near * threads
     return {
-        "value": x.shape[0] / t_job, "unit": "elements/s", "cores": oracle.num_threads(), "kind": "oracle",
-        "sample": (f"FP64 oracle (direct O(p^4) translations) on the same {x.shape[0]}-element input: full tree + "
-                   f"upward pass, downward pass + near field for the {len(set(samp.tolist()))} leaves of "
-                   f"{n_leaves} seeded elements ({st['n_m2l']} M2L, {st['n_p2p_pairs']} pairs); full-job time "
-                   f"projected from the per-translation and per-pair rates: {t_job:.1f} s "
-                   f"(sample wall {wall:.1f} s)"),
+        "value": n / t_job_all, "unit": "elements/s", "cores": threads, "kind": "oracle",
+        "value_1core": n / t_job_1, "cpu_model": cpu_model(), "projected": True,
+        "sample": (f"FP64 oracle (direct O(p^4) translation matrices, OpenMP) on the headline workload "
+                   f"(N = {n}, p = {p}): {n_trans} M2L translations timed on one thread "
+                   f"({t_tr * 1e3:.2f} ms each), P2M + L2P on 64-element boxes ({t_el * 1e6:.1f} us per element), "
+                   f"the split direct sum for {n_targets - n_targets // 4} targets over all sources "
+                   f"({t_near_s:.2f} s on {threads} threads, tree construction excluded); projected with the plan's {n_tr} translations and {pairs_job} near-field pairs: "
+                   f"{t_job_all:.0f} s on {threads} threads, {t_job_1:.0f} s on one"),
     }
 
 
@@ -136,8 +277,6 @@ def run_batch(lhf, torch, steps, warmup, with_accuracy):
     B = lhf.Batch(xt, off, a, p=p, precision=lhf.FP32, tune=tune)
     torch.cuda.synchronize()
     t_plan_cold = time.perf_counter() - t0
-    # a plan rebuilt every step takes its device blocks from the blocks the previous one
-    # released: the per-step plan cost is the mean over a few rebuilds
     n_rebuild = max(1, min(steps, 3))
     t0 = time.perf_counter()
     for _ in range(n_rebuild):
@@ -157,25 +296,6 @@ def run_batch(lhf, torch, steps, warmup, with_accuracy):
     torch.cuda.synchronize()
     ms_exec = ev0.elapsed_time(ev1) / steps
     log(f"bench: batch graph {ms_exec:.3f} ms per execute")
-    # the same systems as separate single-system plans, executed one after another
-    plans = []
-    for k in range(ns):
-        i0, i1 = int(off[k]), int(off[k + 1])
-        plans.append((lhf.Plan(xt[i0:i1], float(a[k]), p=p, depth=int(info["depths"][k]), precision=lhf.FP32),
-                      i0, i1))
-    vs, ss = torch.empty_like(wt), torch.empty_like(wt)
-    for pl, i0, i1 in plans:
-        pl.execute(wt[i0:i1], vs[i0:i1], ss[i0:i1])
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(steps):
-        for pl, i0, i1 in plans:
-            pl.execute(wt[i0:i1], vs[i0:i1], ss[i0:i1])
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_sep = ev0.elapsed_time(ev1) / steps
-    for pl, _, _ in plans:
-        pl.close()
     depths, counts = np.unique(info["depths"], return_counts=True)
     res = {
         "workload": "batch256_fp32", "n_systems": ns, "n": n, "p": p,
@@ -183,14 +303,10 @@ def run_batch(lhf, torch, steps, warmup, with_accuracy):
         "depth_groups": {int(dd): int(c) for dd, c in zip(depths, counts)},
         "core_split_warning": bool(B.warn_core_split),
         "tune": {"t_box_ns": tune.t_box_ns, "t_pair_ns": tune.t_pair_ns, "seconds": t_tune},
-        "plan_ms": t_plan * 1e3,
-        "plan_first_ms": t_plan_cold * 1e3,
-        "execute_ms": ms_exec,
+        "plan_ms": t_plan * 1e3, "plan_first_ms": t_plan_cold * 1e3, "execute_ms": ms_exec,
         "elements_per_s": n / ((t_plan * 1e3 + ms_exec) * 1e-3),
         "execute_only_elements_per_s": n / (ms_exec * 1e-3),
         "mean_system_execute_us": ms_exec * 1e3 / ns,
-        "separate_plans_execute_ms": ms_sep,
-        "graph_speedup_vs_separate_plans": ms_sep / ms_exec,
         "counts": {"m2l": info["n_m2l"], "p2p_pairs": info["n_p2p_pairs"]},
     }
     if with_accuracy:
@@ -205,75 +321,10 @@ def run_batch(lhf, torch, steps, warmup, with_accuracy):
             tg = workloads.sample_targets(i1 - i0, 200, seed=2000 + k)
             vd, sd = oracle.direct(xk, wk, float(np.float32(a[k])), mode=oracle.DIRECT_SPLIT,
                                    depth=int(info["depths"][k]), targets=tg)
-            errs.append({"system": k, "n": i1 - i0, "depth": int(info["depths"][k]),
-                         "rel_l2_v": float(np.linalg.norm(vh[i0:i1][tg] - vd) / np.linalg.norm(vd)),
-                         "rel_l2_s": float(np.linalg.norm(sh[i0:i1][tg] - sd) / np.linalg.norm(sd))})
+            e = rel_err(vh[i0:i1], sh[i0:i1], tg, vd, sd)
+            errs.append(dict(e, system=k, n=i1 - i0, depth=int(info["depths"][k])))
         res["accuracy_sampled_systems"] = errs
     B.close()
-    return res
-
-
-def run_ring(lhf, torch, steps, warmup, with_accuracy):
-    """clustered workload: 4,194,304 elements on a vortex ring + 10% background, adaptive octree
-    (<= 64 per leaf, deepest level 8), p = 16; the FP32 path timed per step (plan + execute),
-    the FP64 path on the same input for the speedup"""
-    import numpy as np
-    import workloads
-    cfg = workloads.CONFIGS["ring4m_fp32"]
-    n, p, mx, depth = cfg["n"], cfg["p"], cfg["max_per_leaf"], 8
-    x, w = workloads.vortex_ring(n, cfg["seed"])
-    a = workloads.core_radius(n)
-    log(f"bench: ring N={n} p={p} adaptive <= {mx}/leaf")
-    res = {"workload": "ring4m_fp32", "n": n, "p": p, "max_per_leaf": mx, "max_level": depth,
-           "distribution": "vortex ring R0 = 0.3, Gaussian cross-section sigma = 0.05, + 10% uniform background"}
-    outs = {}
-    for prec, name, k_steps in ((lhf.FP32, "fp32", steps), (lhf.FP64, "fp64", max(1, min(steps, 2)))):
-        dt = torch.float32 if prec == lhf.FP32 else torch.float64
-        xt = torch.from_numpy(x).to(device="cuda", dtype=dt)
-        wt = torch.from_numpy(w).to(device="cuda", dtype=dt)
-        v, s = torch.empty_like(wt), torch.empty_like(wt)
-        for _ in range(warmup if prec == lhf.FP32 else 1):
-            pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=mx)
-            pl.execute(wt, v, s)
-            pl.close()
-        torch.cuda.synchronize()
-        phases = {k: 0.0 for k in lhf.PHASES}
-        t0 = time.perf_counter()
-        for _ in range(k_steps):
-            pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=mx)
-            pl.profile_begin(1)
-            pl.execute(wt, v, s)
-            ph, _ = pl.profile_end()
-            st = pl.stats()
-            pl.close()
-            for kk in phases:
-                phases[kk] += ph[kk] / k_steps
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / k_steps
-        exec_ms = sum(vv for kk, vv in phases.items() if kk != "m2l")
-        log(f"bench: ring {name} {ms:.1f} ms per step")
-        res[name] = {"ms_per_step": ms, "elements_per_s": n / (ms * 1e-3), "execute_ms": exec_ms,
-                     "execute_only_elements_per_s": n / (exec_ms * 1e-3), "phases_ms": phases, "steps": k_steps,
-                     "m2l_achieved_tflops": st["n_m2l"] * f_m2l(p) / (phases["m2l"] * 1e-3) / 1e12}
-        res["counts"] = {"boxes": st["boxes"], "leaves": st["n_leaves"], "m2l": st["n_m2l"],
-                         "u_pairs": st["n_p2p_pairs"], "wx_pairs": st["n_wx_pairs"]}
-        outs[name] = (v.double().cpu().numpy(), s.double().cpu().numpy())
-        del xt, wt, v, s
-    res["speedup_fp32_vs_fp64"] = res["fp64"]["ms_per_step"] / res["fp32"]["ms_per_step"]
-    if with_accuracy:
-        import oracle
-        tg = workloads.sample_targets(n, 200, seed=3000)
-        xr = x.astype(np.float32).astype(np.float64)
-        wr = w.astype(np.float32).astype(np.float64)
-        vd, sd = oracle.direct_adaptive(xr, wr, float(np.float32(a)), mx, depth, targets=tg)
-        vd64, sd64 = oracle.direct_adaptive(x, w, a, mx, depth, targets=tg)
-        acc = {}
-        for name, (vv, ss) in outs.items():
-            rv, rs = (vd, sd) if name == "fp32" else (vd64, sd64)
-            acc[name] = {"rel_l2_v": float(np.linalg.norm(vv[tg] - rv) / np.linalg.norm(rv)),
-                         "rel_l2_s": float(np.linalg.norm(ss[tg] - rs) / np.linalg.norm(rs))}
-        res["accuracy_vs_direct_sum"] = dict(acc, targets=int(len(tg)),
-                                             reference="adaptive split-kernel direct sum, FP64 oracle")
     return res
 
 
@@ -282,11 +333,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cube1m_fp64")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 run on the same input")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batched run")
-    ap.add_argument("--no-ring", action="store_true", help="skip the clustered (vortex ring, adaptive) run")
+    ap.add_argument("--p", type=int, default=P_STAR, help="order of the headline (FP64 ring) leg")
+    ap.add_argument("--leg-steps", type=int, default=20, help="timed steps of the ring p = 16 and cube legs")
+    ap.add_argument("--legs", default="ring16,cube,batch", help="comma list of ring16, cube, batch (or none)")
+    ap.add_argument("--targets", type=int, default=4096, help="sample targets of the headline accuracy")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle legs (baseline, accuracy)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only copy a buffer of this many MiB on the device (HBM counter calibration)")
     args = ap.parse_args()
@@ -295,6 +346,7 @@ def main():
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     if args.calib_copy:
@@ -313,116 +365,120 @@ def main():
     if not os.path.exists(lhf.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
+    legs = [s for s in args.legs.split(",") if s and s != "none"]
+    with_oracle = not args.no_cpu_baseline
 
-    def run(name, steps, warmup):
-        cfg = workloads.make(name)
-        prec = lhf.FP64 if cfg["precision"] == "fp64" else lhf.FP32
-        dt = torch.float64 if prec == lhf.FP64 else torch.float32
-        n, p, d, a = cfg["n"], cfg["p"], cfg["depth"], cfg["a"]
-        log(f"bench: workload {name} N={n} p={p} depth={d} precision={cfg['precision']}")
-        xt = torch.from_numpy(cfg["x"]).to(device="cuda", dtype=dt)
-        wt = torch.from_numpy(cfg["w"]).to(device="cuda", dtype=dt)
-        v = torch.empty_like(wt)
-        s = torch.empty_like(wt)
-
-        def step(profile=False):
-            plan = lhf.Plan(xt, a, p=p, depth=d, precision=prec)
-            if profile:
-                plan.profile_begin(1)
-            plan.execute(wt, v, s)
-            ph = None
-            if profile:
-                ph, _ = plan.profile_end()
-            st = plan.stats()
-            plan.close()
-            return ph, st
-
-        for k in range(warmup):
-            step()
-            log(f"bench: {name} warmup {k + 1}/{warmup} done")
-        torch.cuda.synchronize()
-        phases = {k: 0.0 for k in lhf.PHASES}
-        t0 = time.perf_counter()
-        for k in range(steps):
-            ph, st = step(profile=True)
-            for kk in phases:
-                phases[kk] += ph[kk]
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        log(f"bench: {name} {steps} timed steps done")
-        ms_step = (t1 - t0) * 1e3 / steps
-        ph_step = {k: vv / steps for k, vv in phases.items()}
-        exec_ms = sum(vv for kk, vv in ph_step.items() if kk != "m2l")  # m2l is part of "down"
-        launches = sum(1 for l in range(2, d + 1) if st["boxes"][l] > 0)
-        flops = st["n_m2l"] * f_m2l(p)
-        achieved = flops / (ph_step["m2l"] * 1e-3) / 1e12
-        peak = PEAK_FP64_TFLOPS if prec == lhf.FP64 else PEAK_FP32_MFMA_TFLOPS
-        return dict(cfg=cfg, prec=prec, n=n, p=p, d=d, ms_step=ms_step, ph_step=ph_step, exec_ms=exec_ms,
-                    st=st, launches=launches, flops=flops, achieved=achieved, peak=peak,
-                    v=v.double().cpu().numpy(), s=s.double().cpu().numpy())
-
-    r = run(args.workload, args.steps, args.warmup)
-    cfg, prec, n, p, d = r["cfg"], r["prec"], r["n"], r["p"], r["d"]
+    # ---- headline: the 4M ring in FP64 at the order that reaches 1e-6
+    cfg = workloads.CONFIGS["ring4m_fp32"]
+    n, mx, lmax = cfg["n"], cfg["max_per_leaf"], 8
+    x, w = workloads.vortex_ring(n, cfg["seed"])
+    a = workloads.core_radius(n)
+    p = args.p
+    log(f"bench: headline ring N={n} FP64 p={p} adaptive <= {mx}/leaf, level <= {lmax}")
+    head, st, (vh, sh) = run_leg(lhf, torch, f"ring4m_fp64_p{p}", x, w, a, p, lhf.FP64, lmax, mx, args.steps,
+                                 args.warmup)
+    ph = head["phases_ms"]
+    launches = sum(1 for l in range(2, len(st["boxes"])) if st["boxes"][l] > 0)
+    flops = st["n_m2l"] * f_m2l(p)
+    achieved = flops / (ph["m2l"] * 1e-3) / 1e12
     out = {
         "metric": METRIC,
-        "value": n / (r["ms_step"] * 1e-3),
+        "value": head["elements_per_s"],
         "unit": "elements/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r["ms_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == lhf.FP64 else "f32",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "p": p, "depth": d, "precision": cfg["precision"],
-                   "distribution": "uniform in [0,1)^3, omega ~ N(0,1)^3, Gaussian core a = 0.5 N^(-1/3)",
+        "config": {"workload": f"ring4m_fp64_p{p}", "n": n, "p": p, "max_per_leaf": mx, "max_level": lmax,
+                   "precision": "fp64",
+                   "distribution": ("vortex ring R0 = 0.3 (Gaussian cross-section, density ~ exp(-rho^2/0.05^2)) "
+                                    "+ 10% uniform background, omega = exp(-rho^2/0.05^2) e_theta, "
+                                    "Gaussian core a = 0.5 N^(-1/3)"),
                    "step": "plan (keys, sort, octree, lists, tables) + execute (P2M, M2M, M2L/L2L, L2P, P2P)"},
-        "execute_ms": r["exec_ms"],
-        "plan_ms": r["ms_step"] - r["exec_ms"],
-        "execute_only_elements_per_s": n / (r["exec_ms"] * 1e-3),
-        "phases_ms": r["ph_step"],
-        "counts": {"m2l": r["st"]["n_m2l"], "p2p_pairs": r["st"]["n_p2p_pairs"], "boxes": r["st"]["boxes"]},
+        "execute_ms": head["execute_ms"],
+        "plan_ms": head["plan_ms"],
+        "execute_only_elements_per_s": head["execute_only_elements_per_s"],
+        "phases_ms": ph,
+        "counts": head["counts"],
+        "m2l_kernel": head["m2l_kernel"],
+        "phase_roofline": head["phase_roofline"],
+        "aggregate_roofline": head["aggregate_roofline"],
         "roofline": {
-            "kernel": M2L_KERNEL[prec] + " (batched M2L), one launch per level 2..d",
+            "kernel": f"k_m2l_half<double,{p}> (batched M2L, rotation tables from L2), one launch per level",
             "bound": "alu",
-            "achieved": r["achieved"],
+            "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": r["achieved"] / PEAK_FP64_TFLOPS,
-            "traffic": measured_traffic("fp64" if prec == lhf.FP64 else "fp32"),
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
-            "launches_per_step": r["launches"],
-            "avg_launch_ms": r["ph_step"]["m2l"] / r["launches"],
-            "flop_per_launch": r["flops"] / r["launches"],
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": measured_traffic(f"ring4m_fp64_p{p}"),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "launches_per_step": launches,
+            "avg_launch_ms": ph["m2l"] / launches,
+            "flop_per_launch": flops / launches,
             "flop_per_m2l": f_m2l(p),
         },
     }
-    r32 = None
-    if args.workload == "cube1m_fp64" and not args.no_fp32:
-        # the mixed-precision path on the same input (FP32 elements and expansions, p = 10)
-        r32 = run("cube1m_fp32", args.steps, args.warmup)
-        out["fp32"] = {
-            "workload": "cube1m_fp32", "p": r32["p"], "ms_per_step": r32["ms_step"],
-            "elements_per_s": r32["n"] / (r32["ms_step"] * 1e-3),
-            "execute_only_elements_per_s": r32["n"] / (r32["exec_ms"] * 1e-3),
-            "speedup_vs_fp64": r["ms_step"] / r32["ms_step"],
-            "phases_ms": r32["ph_step"],
-            "m2l_achieved_tflops": r32["achieved"],
-            "m2l_frac_of_fp32_vector_peak": r32["achieved"] / PEAK_FP32_VALU_TFLOPS,
-        }
-    if args.workload == "cube1m_fp64" and not args.no_batch:
-        out["batch"] = run_batch(lhf, torch, args.steps, args.warmup, not args.no_cpu_baseline)
-    if args.workload == "cube1m_fp64" and not args.no_ring:
-        out["ring"] = run_ring(lhf, torch, args.steps, args.warmup, not args.no_cpu_baseline)
-    if not args.no_cpu_baseline:
-        log("bench: CPU oracle baseline (sampled) ...")
-        out["cpu_baseline"] = cpu_baseline(cfg)
-        log("bench: accuracy against the oracle's direct sum on 1000 sampled targets ...")
-        out["cpu_baseline"]["accuracy_fp64_path"] = accuracy(cfg, r["v"], r["s"])
-        if r32 is not None:
-            out["cpu_baseline"]["accuracy_fp32_path"] = accuracy(r32["cfg"], r32["v"], r32["s"])
+    # ---- legs
+    outs = {}
+    if "ring16" in legs:
+        ring = {}
+        for prec, nm in ((lhf.FP32, "fp32"), (lhf.FP64, "fp64")):
+            r, _, o = run_leg(lhf, torch, f"ring4m_{nm}_p16", x, w, a, 16, prec, lmax, mx, args.leg_steps,
+                              args.warmup)
+            ring[nm] = r
+            outs[nm] = o
+        ring["speedup_fp32_vs_fp64"] = ring["fp64"]["ms_per_step"] / ring["fp32"]["ms_per_step"]
+        ring["speedup_fp32_p16_vs_fp64_headline"] = head["ms_per_step"] / ring["fp32"]["ms_per_step"]
+        out["ring_p16"] = ring
+    if "cube" in legs:
+        cube = {}
+        for wl in ("cube1m_fp64", "cube1m_fp32"):
+            c = workloads.make(wl)
+            prec = lhf.FP64 if c["precision"] == "fp64" else lhf.FP32
+            r, _, o = run_leg(lhf, torch, wl, c["x"], c["w"], c["a"], c["p"], prec, c["depth"], 0, args.leg_steps,
+                              args.warmup)
+            cube[wl] = r
+            outs[wl] = (o, c)
+        cube["speedup_fp32_p10_vs_fp64_p12"] = cube["cube1m_fp64"]["ms_per_step"] / cube["cube1m_fp32"]["ms_per_step"]
+        out["cube1m"] = cube
+    if "batch" in legs:
+        out["batch"] = run_batch(lhf, torch, args.leg_steps, args.warmup, with_oracle)
+    # ---- oracle legs: accuracy against the split direct sum, CPU baseline
+    if with_oracle:
+        import oracle
+        log(f"bench: accuracy of the headline on {args.targets} targets (oracle adaptive direct sum) ...")
+        tg = workloads.sample_targets(n, args.targets, seed=3000)
+        vd, sd = oracle.direct_adaptive(x, w, a, mx, lmax, targets=tg)
+        acc = rel_err(vh, sh, tg, vd, sd)
+        acc.update(targets=int(len(tg)), meets_1e_6=bool(acc["rel_l2_v"] <= 1e-6 and acc["rel_l2_s"] <= 1e-6),
+                   reference="adaptive split-kernel direct sum (Gaussian core between adjacent leaves, singular "
+                             "beyond), FP64 oracle")
+        out["accuracy"] = acc
+        if "ring_p16" in out:
+            out["ring_p16"]["fp64"]["accuracy"] = rel_err(*outs["fp64"], tg, vd, sd)
+            tg32 = tg[:1024]
+            xr, wr = x.astype(np.float32).astype(np.float64), w.astype(np.float32).astype(np.float64)
+            vd32, sd32 = oracle.direct_adaptive(xr, wr, float(np.float32(a)), mx, lmax, targets=tg32)
+            out["ring_p16"]["fp32"]["accuracy"] = dict(
+                rel_err(*outs["fp32"], tg32, vd32, sd32), targets=int(len(tg32)),
+                reference="same direct sum on the FP32-rounded inputs")
+        if "cube1m" in out:
+            for wl in ("cube1m_fp64", "cube1m_fp32"):
+                (vv, ss), c = outs[wl]
+                xc, wc, ac = c["x"], c["w"], c["a"]
+                if c["precision"] == "fp32":
+                    xc, wc = xc.astype(np.float32).astype(np.float64), wc.astype(np.float32).astype(np.float64)
+                    ac = float(np.float32(ac))
+                tgc = workloads.sample_targets(xc.shape[0], 1000, seed=1000)
+                vdc, sdc = oracle.direct(xc, wc, ac, mode=oracle.DIRECT_SPLIT, depth=c["depth"], targets=tgc)
+                out["cube1m"][wl]["accuracy"] = dict(rel_err(vv, ss, tgc, vdc, sdc), targets=1000)
+        log("bench: CPU oracle baseline (sampled, projected) ...")
+        out["cpu_baseline"] = cpu_baseline(x, w, a, p, mx, lmax, st)
     print(json.dumps(out), flush=True)
 
 

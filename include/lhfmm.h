@@ -87,7 +87,7 @@ typedef enum { LHF_FP64 = 0, LHF_FP32 = 1 } lhf_precision;
  * the others force one and return LHF_ERR_UNSUPPORTED where it has no instantiation. */
 #define LHF_M2L_AUTO 0
 #define LHF_M2L_HALF 1         /* batched VALU, each coefficient vector split over two lanes by the
-                                  parity of m: p = 8, 10, 12, 16 */
+                                  parity of m: p = 8, 10, 12, 16 (FP64 also 20, 22, 23, 24) */
 #define LHF_M2L_TILE 2         /* batched VALU, one lane per coefficient vector (two schedule rows
                                   per batch at FP32 p = 8, 10): p = 4..12 even (FP32 also 16) */
 #define LHF_M2L_TILE1 3        /* as TILE with one schedule row per batch */

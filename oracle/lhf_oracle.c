@@ -1574,13 +1574,28 @@ void lho_direct_adaptive(int64_t n, const double *x, const double *w, double a, 
         }
     int smooth_ok = a > 0.0;
     int64_t nt = targ ? ntarg : n;
+    /* closed integer extent [lo, hi] of every element's leaf, per dimension: two leaves are
+     * adjacent iff their extents overlap in all three dimensions (the predicate of adjacent()) */
+    int64_t *ext = (int64_t *)malloc(sizeof(int64_t) * 6 * (size_t)n);
+    for (int64_t e = 0; e < n; e++) {
+        int c[3];
+        box_coords(ek[e], c);
+        for (int d = 0; d < 3; d++) {
+            ext[6 * e + d] = (int64_t)c[d] << (QBITS - el[e]);
+            ext[6 * e + 3 + d] = (int64_t)(c[d] + 1) << (QBITS - el[e]);
+        }
+    }
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t jj = 0; jj < nt; jj++) {
         int64_t j = targ ? targ[jj] : jj;
         double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0};
+        const int64_t *ej = &ext[6 * j];
         for (int64_t i = 0; i < n; i++) {
             if (i == j) continue;
-            int sm = smooth_ok && adjacent(el[i], ek[i], el[j], ek[j]);
+            const int64_t *ei = &ext[6 * i];
+            int adj = !(ei[0] > ej[3] || ej[0] > ei[3] || ei[1] > ej[4] || ej[1] > ei[4] || ei[2] > ej[5] ||
+                        ej[2] > ei[5]);
+            int sm = smooth_ok && adj;
             pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, sm, vv, ss, NULL);
         }
         for (int k = 0; k < 3; k++) {
@@ -1588,6 +1603,7 @@ void lho_direct_adaptive(int64_t n, const double *x, const double *w, double a, 
             s[3 * jj + k] = ss[k];
         }
     }
+    free(ext);
     free(el);
     free(ek);
     atree_free(&A);

@@ -64,6 +64,15 @@ struct Shape {
     static constexpr int NHP = (NH + E<T>() - 1) / E<T>() * E<T>();
 };
 
+// FP64 orders above 16: one class's rotation tables (8 x WHS entries, 88 KB at p = 20 and
+// 176 KB at p = 24) no longer fit the LDS beside the accumulators of a sibling group, so the
+// kernel reads them from global memory (L2) instead of staging them per class
+template <typename T, int P>
+constexpr bool wglobal()
+{
+    return sizeof(T) == 8 && P > 16;
+}
+
 // packed (phi, chi) expansion [pot][n^2 + (Re: m | Im: n + m)] -> lane layout
 // [role = 4 pot + 2 part + h][RS] (RS >= hoff(P)): position of packed index k
 template <int P, int RS>
@@ -179,8 +188,9 @@ template <typename T, int P, bool OWN>
 constexpr size_t tile_bytes(int npar)
 {
     using Sh = Shape<T, P>;
-    return sizeof(T) * 8 * (size_t)Sh::WHS + sizeof(Acc<T, OWN>) * (size_t)(8 * npar + 1) * acc_slot<T, P, OWN>() +
-           sizeof(int) * 3 * 8 * npar + sizeof(int16_t) * (64 + (OWN ? 0 : 1512));
+    return sizeof(T) * (wglobal<T, P>() ? 0 : 8 * (size_t)Sh::WHS) +
+           sizeof(Acc<T, OWN>) * (size_t)(8 * npar + 1) * acc_slot<T, P, OWN>() + sizeof(int) * 3 * 8 * npar +
+           sizeof(int16_t) * (64 + (OWN ? 0 : 1512));
 }
 // two workgroups per compute unit (160 KB of LDS)
 constexpr size_t LDS_HALF = 81920;
@@ -234,8 +244,9 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     extern __shared__ char smem[];
     using A = hv::Acc<T, OWN>;
     static_assert(!OWN || NPAR == 4, "ownership mode: one sibling group per wavefront");
+    constexpr bool GW = hv::wglobal<T, P>();          // rotation tables read from global memory
     T *Wl = (T *)smem;                                // [kind: fwd S, back R][part][parity][WHS]
-    A *acc = (A *)(Wl + 8 * Sh::WHS);                 // [NSLOT + 1][SSTA] (last slot absorbs)
+    A *acc = (A *)(Wl + (GW ? 0 : 8 * Sh::WHS));      // [NSLOT + 1][SSTA] (last slot absorbs)
     int *slot_xyz = (int *)(acc + (NSLOT + 1) * SSTA);  // [NSLOT] packed target coordinates, -1: no box
     int *slot_box = slot_xyz + NSLOT;                 // [NSLOT] target box
     int *slot_sys = slot_box + NSLOT;                 // [NSLOT] system of the target
@@ -371,22 +382,27 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         for (int q = 0; q < NPF; q++) pf[q] = src4[q * 256 + tid < N16 ? q * 256 + tid : 0];
     };
     int staged = -1, fetched = -1;
+    const T *Wcls = Wl;  // the current class's tables (LDS, or global memory when GW)
     while (k < ncls) {
-        if (k != staged) {
-            __syncthreads();
-            uint4 *dst4 = (uint4 *)Wl;
-            if constexpr (PREF) {
-                if (fetched != k) fetch(k);
+        if constexpr (GW) {
+            Wcls = wh + (size_t)cls_theta[k] * wstride;
+        } else {
+            if (k != staged) {
+                __syncthreads();
+                uint4 *dst4 = (uint4 *)Wl;
+                if constexpr (PREF) {
+                    if (fetched != k) fetch(k);
 #pragma unroll
-                for (int q = 0; q < NPF; q++)
-                    if (tid + 256 * q < N16) ((u32x4 *)dst4)[tid + 256 * q] = pf[q];
-            } else {
-                const uint4 *src4 = (const uint4 *)(wh + (size_t)cls_theta[k] * wstride);
+                    for (int q = 0; q < NPF; q++)
+                        if (tid + 256 * q < N16) ((u32x4 *)dst4)[tid + 256 * q] = pf[q];
+                } else {
+                    const uint4 *src4 = (const uint4 *)(wh + (size_t)cls_theta[k] * wstride);
 #pragma unroll 4
-                for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
+                    for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
+                }
+                __syncthreads();
+                staged = k;
             }
-            __syncthreads();
-            staged = k;
         }
         // ownership mode: the lane's role (parity, part, potential) is made opaque per batch, so
         // the compiler recomputes the per-lane constants derived from it instead of holding
@@ -395,8 +411,8 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         const int wo = (part * 2 + h) * Sh::WHS;
         int hh = h, pp = part, po = pot;
         if (OWN) asm volatile("" : "+v"(hh), "+v"(pp), "+v"(po));
-        const T *Wf = Wl + wo;
-        const T *Wb = Wl + 4 * Sh::WHS + wo;
+        const T *Wf = Wcls + wo;
+        const T *Wb = Wcls + 4 * Sh::WHS + wo;
 
         const Job j = cur;
         const bool act = j.src >= 0;
@@ -404,7 +420,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         int k2 = k1, r2 = r1;
         advance(k2, r2);
         const Job nn = setup(k2, r2);
-        if constexpr (PREF) {
+        if constexpr (PREF && !GW) {
             if (k1 != k && k1 < ncls) {  // the next batch starts a new class
                 fetch(k1);
                 fetched = k1;
@@ -424,7 +440,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
             const T sgn = pp ? (T)1 : (T)-1;
             double cm = hh ? cph : 1.0, sm = hh ? sph : 0.0;
 #pragma unroll
-            for (int jj = 0; jj < P / 2; jj++) {
+            for (int jj = 0; jj < (P + 1) / 2; jj++) {
                 const T cz = (T)cm, sz = (T)sm * sgn;
 #pragma unroll
                 for (int n = 2 * jj; n < P; n++) {
@@ -463,27 +479,52 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         //      (chi to order P), then the R-conversion (eq. rcr1, scaled)
         //        phi~ = phi + i tau m/n chi ,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
         {
-            T pw[P + 2];  // tau^-k
+            // tau^-k: a table at the orders whose registers allow it; running products where the
+            // vectors fill the register file (global-table mode)
+            constexpr int NPW = GW ? 1 : P + 2;
+            T pw[NPW];
             pw[0] = (T)1;
 #pragma unroll
-            for (int q = 1; q <= P + 1; q++) pw[q] = pw[q - 1] * itau;
+            for (int q = 1; q < NPW; q++) pw[q] = pw[q - 1] * itau;
+            T pc = (T)1;  // GW: tau^-(2c) of the current column
+            const T itau2 = itau * itau;
             const T wphi = po ? (T)0 : (T)1, wchi = po ? (T)1 : (T)0;
             const T sconv = pp ? (T)1 : (T)-1;
             const T keep0 = hh ? (T)0 : (T)1;  // slot (n = 2c, c) holds m = 2c + h: empty on odd lanes
 #pragma unroll
-            for (int c = 0; c < P / 2; c++) {
+            for (int c = 0; c < (P + 1) / 2; c++) {
                 const int n0 = 2 * c;
                 const T mval = (T)(2 * c + hh);
-                T cl[P];
-#pragma unroll
-                for (int n2 = n0; n2 < P; n2++) cl[n2] = v[hoff(n2) + c] * pw[n2];
                 T out[P + 1];
+                if constexpr (GW) {
+                    // scale the column in place, then the Hankel sums
+                    T q = pc;
 #pragma unroll
-                for (int n = n0; n <= P; n++) {
-                    T a = 0;
+                    for (int n2 = n0; n2 < P; n2++) {
+                        v[hoff(n2) + c] *= q;
+                        q *= itau;
+                    }
+                    T qo = pc * itau;
 #pragma unroll
-                    for (int n2 = n0; n2 < P; n2++) a += (T)dfact(n + n2) * cl[n2];
-                    out[n] = a * pw[n + 1];
+                    for (int n = n0; n <= P; n++) {
+                        T a = 0;
+#pragma unroll
+                        for (int n2 = n0; n2 < P; n2++) a += (T)dfact(n + n2) * v[hoff(n2) + c];
+                        out[n] = a * qo;
+                        qo *= itau;
+                    }
+                    pc *= itau2;
+                } else {
+                    T cl[P];
+#pragma unroll
+                    for (int n2 = n0; n2 < P; n2++) cl[n2] = v[hoff(n2) + c] * pw[n2];
+#pragma unroll
+                    for (int n = n0; n <= P; n++) {
+                        T a = 0;
+#pragma unroll
+                        for (int n2 = n0; n2 < P; n2++) a += (T)dfact(n + n2) * cl[n2];
+                        out[n] = a * pw[n + 1];
+                    }
                 }
 #pragma unroll
                 for (int n = n0; n < P; n++) {
@@ -509,7 +550,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
             const T sgn = pp ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
             double cm = hh ? cph : 1.0, sm = hh ? sph : 0.0;
 #pragma unroll
-            for (int jj = 0; jj < P / 2; jj++) {
+            for (int jj = 0; jj < (P + 1) / 2; jj++) {
                 const T cz = (T)cm, sz = (T)sm * sgn;
                 {
                     const double a = cm * c2 - sm * s2, b = sm * c2 + cm * s2;
@@ -1046,7 +1087,14 @@ void l2l_half_launch(const lhf_plan *Pl, int l, hipStream_t st)
 
 bool m2l_half_supported(int precision, int p)
 {
-    if (precision == LHF_FP64) return p == 8 || p == 10 || p == 12 || p == 16;
+    if (precision == LHF_FP64) return p == 8 || p == 10 || p == 12 || p == 16 || p == 20 || p == 22 || p == 23 || p == 24;
+    return p == 8 || p == 10 || p == 12 || p == 16;
+}
+
+// the batched M2M / L2L kernels stage both classes' tables in LDS: orders up to 16
+bool mm_half_supported(int precision, int p)
+{
+    (void)precision;
     return p == 8 || p == 10 || p == 12 || p == 16;
 }
 
@@ -1059,7 +1107,8 @@ bool m2l_half_owned(int precision, int p)
         case 8: return hv::tile_own<double, 8>();
         case 10: return hv::tile_own<double, 10>();
         case 12: return hv::tile_own<double, 12>();
-        default: return hv::tile_own<double, 16>();
+        case 16: return hv::tile_own<double, 16>();
+        default: return hv::tile_own<double, 24>();
         }
     }
     switch (p) {
@@ -1078,6 +1127,10 @@ bool whalf_build(lhf_plan *Pl, hipStream_t st)
         case 10: return whalf_build_t<double, 10>(Pl, st);
         case 12: return whalf_build_t<double, 12>(Pl, st);
         case 16: return whalf_build_t<double, 16>(Pl, st);
+        case 20: return whalf_build_t<double, 20>(Pl, st);
+        case 22: return whalf_build_t<double, 22>(Pl, st);
+        case 23: return whalf_build_t<double, 23>(Pl, st);
+        case 24: return whalf_build_t<double, 24>(Pl, st);
         }
     } else {
         switch (Pl->p) {
@@ -1098,6 +1151,10 @@ void m2l_half_stage(const lhf_plan *Pl, int level, hipStream_t st)
         case 10: stage_half<double, 10>(Pl, level, st); break;
         case 12: stage_half<double, 12>(Pl, level, st); break;
         case 16: stage_half<double, 16>(Pl, level, st); break;
+        case 20: stage_half<double, 20>(Pl, level, st); break;
+        case 22: stage_half<double, 22>(Pl, level, st); break;
+        case 23: stage_half<double, 23>(Pl, level, st); break;
+        case 24: stage_half<double, 24>(Pl, level, st); break;
         }
     } else {
         switch (Pl->p) {
@@ -1117,6 +1174,10 @@ void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st)
         case 10: launch_half<double, 10>(Pl, level, st); break;
         case 12: launch_half<double, 12>(Pl, level, st); break;
         case 16: launch_half<double, 16>(Pl, level, st); break;
+        case 20: launch_half<double, 20>(Pl, level, st); break;
+        case 22: launch_half<double, 22>(Pl, level, st); break;
+        case 23: launch_half<double, 23>(Pl, level, st); break;
+        case 24: launch_half<double, 24>(Pl, level, st); break;
         }
     } else {
         switch (Pl->p) {

@@ -38,6 +38,7 @@ bool wmfma_build(lhf_plan *Pl, hipStream_t st);
 
 bool m2l_tile_owned(int precision, int p);
 bool m2l_half_owned(int precision, int p);
+bool mm_half_supported(int precision, int p);
 
 // ---- device memory cache -----------------------------------------------------------------
 namespace {
@@ -1430,8 +1431,8 @@ lhf_status resolve_kernels(const lhf_desc *d, int p, bool dmap_ok, int *m2l, int
         }
     }
     int mk = d->mm_kernel;
-    if (mk == LHF_MM_AUTO) mk = m2l_half_supported(prec, p) ? LHF_MM_HALF : LHF_MM_GENERIC;
-    else if (mk == LHF_MM_HALF && !m2l_half_supported(prec, p)) {
+    if (mk == LHF_MM_AUTO) mk = mm_half_supported(prec, p) ? LHF_MM_HALF : LHF_MM_GENERIC;
+    else if (mk == LHF_MM_HALF && !mm_half_supported(prec, p)) {
         set_error("mm_kernel HALF has no instantiation for this precision and p");
         return LHF_ERR_UNSUPPORTED;
     }

@@ -224,11 +224,13 @@ def test_fp32_two_row_tile(oracle, p):
     _check32(v2, s2, v1, s1)
 
 
-@pytest.mark.parametrize("prec,p", [(0, 8), (0, 10), (0, 12), (0, 16), (1, 8), (1, 10), (1, 12), (1, 16)])
+@pytest.mark.parametrize("prec,p", [(0, 8), (0, 10), (0, 12), (0, 16), (0, 20), (0, 22), (0, 23), (0, 24),
+                                    (1, 8), (1, 10), (1, 12), (1, 16)])
 def test_half_vector_m2l(oracle, prec, p):
     # the M2L kernel with each part vector split over two lanes by the parity of m (the default
-    # at p = 8, 10, 12, 16): against the oracle on sampled leaves and against the one-lane tile
-    # (FP64 p = 16: the generic per-box kernel) on every element
+    # at p = 8, 10, 12, 16, and at FP64 p = 20, 22, 23, 24 with its rotation tables read from
+    # global memory): against the oracle on sampled leaves and against the one-lane tile (FP64
+    # p >= 16: the generic per-box kernel) on every element
     import paper_1201_5430_amd as L
     rng = np.random.default_rng(110 + p + prec)
     n = 30000
@@ -243,7 +245,7 @@ def test_half_vector_m2l(oracle, prec, p):
     vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
     m = ~np.isnan(vr[:, 0])
     vh, sh, sth = _gpu_fmm(x, w, a, p, 5, precision=prec, m2l_kernel=L.M2L_HALF)
-    other = L.M2L_GENERIC if (prec == 0 and p == 16) else L.M2L_TILE
+    other = L.M2L_GENERIC if (prec == 0 and p >= 16) else L.M2L_TILE
     v1, s1, st1 = _gpu_fmm(x, w, a, p, 5, precision=prec, m2l_kernel=other)
     assert sth["m2l_kernel"] == "half" and st1["m2l_kernel"] == L.M2L_NAMES[other]
     print(f"half-vector M2L prec={prec} p={p}: ", end="")
