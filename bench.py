@@ -191,14 +191,14 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(x, w, a, p, mx, lmax, st, n_trans=60, n_targets=256):
+def cpu_baseline(x, w, a, p, mx, lmax, st, n_trans=60, n_targets=2048):
     """The FP64 oracle on the headline workload, timed on a bounded sample and projected to the
     whole job with the plan's counts:
       * translations: n_trans M2L translations of the oracle (full O(p^4) matrices, one thread)
         on the workload's own multipoles' shapes; M2M and L2L are costed as M2L (an upper
         bound); the oracle spreads them over its OpenMP threads;
-      * near field: the oracle's adaptive split direct sum on n_targets seeded targets
-        (OpenMP), scaled by the job's U and W/X pair count over the pairs sampled;
+      * near field: the oracle's pair sum (Gaussian core, OpenMP) of n_targets seeded targets
+        over 131072 sources, scaled by the job's U and W/X pair count over the pairs sampled;
       * P2M and L2P: oracle calls on the elements of sampled leaves."""
     import numpy as np
     import oracle
@@ -222,16 +222,14 @@ def cpu_baseline(x, w, a, p, mx, lmax, st, n_trans=60, n_targets=256):
         ph, ch = oracle.p2m(p, c, xs, ws)
         oracle.l2p(p, c, ph, ch, xs, ws)
     t_el = (time.perf_counter() - t0) / (5 * 64)
-    # near field: the split direct sum over all sources for a few targets (OpenMP); two calls
-    # with different target counts, so that the oracle's tree construction cancels
-    tg = workloads.sample_targets(x.shape[0], n_targets, seed=4242)
+    # near field: the oracle's pair sum with the Gaussian core (the costlier kernel of the near
+    # field) over the first n_src elements for n_targets of them (OpenMP; no tree involved)
+    n_src = min(x.shape[0], 131072)
+    tg = workloads.sample_targets(n_src, n_targets, seed=4242)
     t0 = time.perf_counter()
-    oracle.direct_adaptive(x, w, a, mx, lmax, targets=tg[: n_targets // 4])
-    t1 = time.perf_counter()
-    oracle.direct_adaptive(x, w, a, mx, lmax, targets=tg)
-    t2 = time.perf_counter()
-    t_near_s = max((t2 - t1) - (t1 - t0), 1e-9)
-    pairs_sampled = (n_targets - n_targets // 4) * (x.shape[0] - 1)
+    oracle.direct(x[:n_src], w[:n_src], a, mode=oracle.DIRECT_SMOOTH, targets=tg)
+    t_near_s = time.perf_counter() - t0
+    pairs_sampled = n_targets * (n_src - 1)
     n = x.shape[0]
     n_tr = st["n_m2l"] + st["n_m2m"] + st["n_l2l"]
     pairs_job = st["n_p2p_pairs"] + st["n_wx_pairs"]
@@ -245,8 +243,8 @@ def cpu_baseline(x, w, a, p, mx, lmax, st, n_trans=60, n_targets=256):
         "sample": (f"FP64 oracle (direct O(p^4) translation matrices, OpenMP) on the headline workload "
                    f"(N = {n}, p = {p}): {n_trans} M2L translations timed on one thread "
                    f"({t_tr * 1e3:.2f} ms each), P2M + L2P on 64-element boxes ({t_el * 1e6:.1f} us per element), "
-                   f"the split direct sum for {n_targets - n_targets // 4} targets over all sources "
-                   f"({t_near_s:.2f} s on {threads} threads, tree construction excluded); projected with the plan's {n_tr} translations and {pairs_job} near-field pairs: "
+                   f"the smoothed pair sum of {n_targets} targets over {n_src} sources "
+                   f"({t_near_s:.2f} s on {threads} threads); projected with the plan's {n_tr} translations and {pairs_job} near-field pairs: "
                    f"{t_job_all:.0f} s on {threads} threads, {t_job_1:.0f} s on one"),
     }
 

@@ -180,6 +180,28 @@ lhf_status lhf_execute(lhf_plan *plan, const void *omega, void *v, void *s, void
 lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, void *grad_v,
                              int32_t what, void *stream);
 
+/* Inputs and outputs of one evaluation (lhf_execute_io); device pointers, input order.
+ * With monopole strengths q (divergence sources, eqs. 5-7), every element also adds
+ * -grad(q_i / |y - x_i|) to the velocity: the potential phi gains the sources' monopole terms
+ * (P2M: phi_n^m -= q g_n^m with the expansion of eq. rsbf5), the near field gains q_i f r with
+ * the same smoothing kernel f = K/r^3 as the vortex part, and s, grad v follow. */
+typedef struct {
+    const void *omega; /* [N][3] vortex strengths (required) */
+    const void *q;     /* [N] monopole strengths, or NULL (divergence-free field) */
+    void *v;           /* [N][3] velocity (required) */
+    void *s;           /* [N][3] stretching (omega . grad) v (required) */
+    void *grad_v;      /* [N][9], [3k + l] = d v_k / d x_l, or NULL (needs LHF_OUT_GRAD) */
+    void *beta;        /* [N] beta = grad v : grad v = sum_kl (d v_k / d x_l)^2 (Sec. 4.5; for
+                          compressible flows), or NULL (needs LHF_OUT_GRAD) */
+    int32_t what;      /* 3: whole field; 1: far field only; 2: near field only */
+    int32_t reserved;  /* must be 0 */
+} lhf_io;
+
+/* The general evaluation: as lhf_execute_parts with the optional monopole input and the
+ * beta output of lhf_io.  LHF_ERR_STATE if grad_v or beta is asked of a plan created without
+ * LHF_OUT_GRAD.  Enqueued on 'stream'; no host synchronisation, no allocation. */
+lhf_status lhf_execute_io(lhf_plan *plan, const lhf_io *io, void *stream);
+
 /* One-shot: plan_create + execute + destroy (synchronises the stream; allocates and frees the
  * plan's device buffers).  p = 0 chooses the order from tol as in lhf_plan_create. */
 lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void *omega, double a,

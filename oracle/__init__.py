@@ -54,26 +54,26 @@ def lib():
         L.lho_basis_S.argtypes = [C.c_int, _dp, _cp]
         L.lho_kernel_fg.argtypes = [C.c_double, C.c_double, C.c_int, C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]
-        for nm in ("lho_p2m_method1", "lho_p2m_method2"):
-            getattr(L, nm).argtypes = [C.c_int, _dp, C.c_int64, _dp, _dp, _cp, _cp]
+        L.lho_p2m_method1.argtypes = [C.c_int, _dp, C.c_int64, _dp, _dp, _cp, _cp]
+        L.lho_p2m_method2.argtypes = [C.c_int, _dp, C.c_int64, _dp, _dp, C.c_void_p, _cp, _cp]
         for nm in ("lho_m2m", "lho_m2l", "lho_l2l"):
             getattr(L, nm).argtypes = [C.c_int, _dp, _cp, _cp, _cp, _cp]
         L.lho_l2p.argtypes = [C.c_int, _dp, _cp, _cp, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
-        L.lho_direct.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int, C.c_int, _dp, C.c_double,
+        L.lho_direct.argtypes = [C.c_int64, _dp, _dp, C.c_void_p, C.c_double, C.c_int, C.c_int, _dp, C.c_double,
                                  C.c_int64, C.c_void_p, _dp, _dp, C.c_void_p]
-        L.lho_fmm.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int, C.c_int, _dp, C.c_double,
+        L.lho_fmm.argtypes = [C.c_int64, _dp, _dp, C.c_void_p, C.c_double, C.c_int, C.c_int, _dp, C.c_double,
                               C.c_int, C.c_int, C.c_int64, C.c_void_p, _dp, _dp, C.c_void_p,
                               C.POINTER(_Stats)]
         L.lho_fmm.restype = C.c_int
         L.lho_tree_counts.argtypes = [C.c_int64, _dp, C.c_int, _dp, C.c_double, _ip,
                                       C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lho_num_threads.restype = C.c_int
-        L.lho_fmm_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int, C.c_int64, C.c_int, _dp,
-                                       C.c_double, C.c_int, C.c_int64, C.c_void_p, _dp, _dp, C.c_void_p,
+        L.lho_fmm_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_void_p, C.c_double, C.c_int, C.c_int64, C.c_int,
+                                       _dp, C.c_double, C.c_int, C.c_int64, C.c_void_p, _dp, _dp, C.c_void_p,
                                        C.POINTER(_Stats)]
         L.lho_fmm_adaptive.restype = C.c_int
-        L.lho_direct_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_double, C.c_int64, C.c_int, _dp, C.c_double,
-                                          C.c_int64, C.c_void_p, _dp, _dp]
+        L.lho_direct_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_void_p, C.c_double, C.c_int64, C.c_int, _dp,
+                                          C.c_double, C.c_int64, C.c_void_p, _dp, _dp]
         L.lho_adaptive_coverage.argtypes = [C.c_int64, _dp, C.c_int64, C.c_int, _dp, C.c_double,
                                             C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lho_adaptive_counts.argtypes = [C.c_int64, _dp, C.c_int64, C.c_int, _dp, C.c_double, _ip, _ip]
@@ -115,14 +115,30 @@ def kernel_fg(r: float, a: float, smooth: bool = True):
     return f.value, g.value
 
 
-def p2m(p: int, centre, x, w, method: int = 2):
-    """(phi, chi) multipole coefficients about centre (eq. eve4 / eqs. eve5-eve10)."""
+def _qptr(q, n):
+    """monopole strengths as a float64 array of n entries and its address (None: no monopoles)"""
+    if q is None:
+        return None, None
+    q = _f64(q).reshape(-1)
+    if q.shape[0] != n:
+        raise ValueError("q must have one entry per element")
+    return q, q.ctypes.data
+
+
+def p2m(p: int, centre, x, w, method: int = 2, q=None):
+    """(phi, chi) multipole coefficients about centre (eq. eve4 / eqs. eve5-eve10); with q,
+    monopole strengths added to phi (method 2 only)."""
     x = _f64(x).reshape(-1, 3)
     w = _f64(w).reshape(-1, 3)
     phi = np.zeros(p * p, np.complex128)
     chi = np.zeros(p * p, np.complex128)
-    fn = lib().lho_p2m_method2 if method == 2 else lib().lho_p2m_method1
-    fn(p, _f64(centre, (3,)), x.shape[0], x, w, phi, chi)
+    if method == 2:
+        qa, qp = _qptr(q, x.shape[0])
+        lib().lho_p2m_method2(p, _f64(centre, (3,)), x.shape[0], x, w, qp, phi, chi)
+    else:
+        if q is not None:
+            raise ValueError("monopoles: method 2 only")
+        lib().lho_p2m_method1(p, _f64(centre, (3,)), x.shape[0], x, w, phi, chi)
     return phi, chi
 
 
@@ -162,7 +178,7 @@ DIRECT_SINGULAR, DIRECT_SMOOTH, DIRECT_SPLIT = 0, 1, 2
 
 
 def direct(x, w, a, mode=DIRECT_SPLIT, depth=2, lo=(0.0, 0.0, 0.0), L=1.0, targets=None,
-           grad=False):
+           grad=False, q=None):
     """Direct O(N |targets|) sums of v, s (and grad v) -- eqs. 1, 2, s1.1, vem1.
 
     mode: DIRECT_SINGULAR (K=1), DIRECT_SMOOTH (Gaussian everywhere) or
@@ -178,13 +194,14 @@ def direct(x, w, a, mode=DIRECT_SPLIT, depth=2, lo=(0.0, 0.0, 0.0), L=1.0, targe
         nt, tp = targets.shape[0], targets.ctypes.data
     v = np.zeros((nt, 3)); s = np.zeros((nt, 3))
     g = np.zeros((nt, 9)) if grad else None
-    lib().lho_direct(n, x, w, float(a), int(mode), int(depth), _f64(lo, (3,)), float(L), nt, tp, v, s,
+    qa, qp = _qptr(q, n)
+    lib().lho_direct(n, x, w, qp, float(a), int(mode), int(depth), _f64(lo, (3,)), float(L), nt, tp, v, s,
                      g.ctypes.data if grad else None)
     return (v, s, g.reshape(nt, 3, 3)) if grad else (v, s)
 
 
 def fmm(x, w, a, p, depth, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True, p2m_method=2,
-        sample=None, grad=False):
+        sample=None, grad=False, q=None):
     """Plain FP64 two-potential FMM (direct-mode translations).
 
     With ``sample`` (element indices), only the leaves holding those elements
@@ -201,7 +218,8 @@ def fmm(x, w, a, p, depth, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True, p2m_m
         ns, sp = sample.shape[0], sample.ctypes.data
     st = _Stats()
     what = (1 if far else 0) | (2 if near else 0)
-    rc = lib().lho_fmm(n, x, w, float(a), int(p), int(depth), _f64(lo, (3,)), float(L), what,
+    qa, qp = _qptr(q, n)
+    rc = lib().lho_fmm(n, x, w, qp, float(a), int(p), int(depth), _f64(lo, (3,)), float(L), what,
                        int(p2m_method), ns, sp, v, s, g.ctypes.data if grad else None, C.byref(st))
     if rc != 0:
         raise ValueError("oracle fmm rejected its arguments")
@@ -241,7 +259,7 @@ def tree_counts(x, depth, lo=(0.0, 0.0, 0.0), L=1.0):
 
 
 def fmm_adaptive(x, w, a, p, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True,
-                 sample=None, grad=False):
+                 sample=None, grad=False, q=None):
     """Adaptive-octree FMM (split while a box holds more than max_per_leaf elements, down to
     max_level); W/X interactions summed directly with the singular kernel.  With ``sample``
     only the leaves holding those elements are evaluated (other outputs NaN).  With ``grad``
@@ -258,7 +276,8 @@ def fmm_adaptive(x, w, a, p, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), 
         ns, sp = sample.shape[0], sample.ctypes.data
     st = _Stats()
     what = (1 if far else 0) | (2 if near else 0)
-    rc = lib().lho_fmm_adaptive(n, x, w, float(a), int(p), int(max_per_leaf), int(max_level), _f64(lo, (3,)),
+    qa, qp = _qptr(q, n)
+    rc = lib().lho_fmm_adaptive(n, x, w, qp, float(a), int(p), int(max_per_leaf), int(max_level), _f64(lo, (3,)),
                                 float(L), what, ns, sp, v, s, g.ctypes.data if grad else None, C.byref(st))
     if rc != 0:
         raise ValueError("oracle adaptive fmm rejected its arguments")
@@ -293,7 +312,7 @@ def adaptive_leaf_of(x, max_per_leaf, max_level, lo=(0.0, 0.0, 0.0), L=1.0):
     return out
 
 
-def direct_adaptive(x, w, a, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), L=1.0, targets=None):
+def direct_adaptive(x, w, a, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), L=1.0, targets=None, q=None):
     """Direct sums with the adaptive split rule (smoothed kernel between adjacent leaves)."""
     x = _f64(x).reshape(-1, 3)
     w = _f64(w).reshape(-1, 3)
@@ -304,7 +323,8 @@ def direct_adaptive(x, w, a, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), 
         targets = np.ascontiguousarray(targets, np.int64)
         nt, tp = targets.shape[0], targets.ctypes.data
     v = np.zeros((nt, 3)); s = np.zeros((nt, 3))
-    lib().lho_direct_adaptive(n, x, w, float(a), int(max_per_leaf), int(max_level), _f64(lo, (3,)), float(L),
+    qa, qp = _qptr(q, n)
+    lib().lho_direct_adaptive(n, x, w, qp, float(a), int(max_per_leaf), int(max_level), _f64(lo, (3,)), float(L),
                               nt, tp, v, s)
     return v, s
 

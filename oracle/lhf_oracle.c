@@ -195,9 +195,11 @@ void lho_kernel_fg(double r, double a, int smooth, double *f, double *g)
     }
 }
 
-/* contribution of source (xi, wi) to target (xj, wj): v, grad v (row k = component,
- * column l = derivative) and s.  r = xj - xi. */
-static void pair_accum(const double *xj, const double *wj, const double *xi, const double *wi,
+/* contribution of source (xi, wi, qi) to target (xj, wj): v, grad v (row k = component,
+ * column l = derivative) and s.  r = xj - xi.  The vortex part is eq. 1 with the kernel
+ * f = K/r^3; the monopole (source) part qi is the term -grad(qi/r) of eq. 7, smoothed with
+ * the same kernel: qi f r.  Its gradient is qi (f delta_kl + g r_k r_l) (g = f'/r). */
+static void pair_accum(const double *xj, const double *wj, const double *xi, const double *wi, double qi,
                        double a, int smooth, double *v, double *s, double *gv)
 {
     double r[3] = {xj[0] - xi[0], xj[1] - xi[1], xj[2] - xi[2]};
@@ -213,6 +215,11 @@ static void pair_accum(const double *xj, const double *wj, const double *xi, con
         v[k] += f * wxr[k];
         s[k] += f * wxw[k] + g * wjr * wxr[k];
     }
+    if (qi != 0.0)
+        for (int k = 0; k < 3; k++) {
+            v[k] += qi * f * r[k];
+            s[k] += qi * (f * wj[k] + g * wjr * r[k]);
+        }
     if (gv) {
         /* d_l (f (w x r))_k = g r_l (w x r)_k + f eps_{k a l} w_a */
         for (int k = 0; k < 3; k++)
@@ -223,6 +230,9 @@ static void pair_accum(const double *xj, const double *wj, const double *xi, con
         gv[3 * 1 + 2] += f * (-wi[0]); /* eps_{102} = -1 */
         gv[3 * 2 + 0] += f * (-wi[1]); /* eps_{210} = -1 */
         gv[3 * 2 + 1] += f * (wi[0]);  /* eps_{201} = +1 */
+        if (qi != 0.0)
+            for (int k = 0; k < 3; k++)
+                for (int l = 0; l < 3; l++) gv[3 * k + l] += qi * (g * r[k] * r[l] + (k == l ? f : 0.0));
     }
 }
 
@@ -369,7 +379,7 @@ static void box_centre(const otree *T, int l, uint64_t k, double c[3])
 
 /* Method 2 (eq. eve4): add the (phi, chi) multipole coefficients about
  * 'centre' of the vortex elements (x_l, w_l) into phi, chi (p^2 each). */
-void lho_p2m_method2(int p, const double centre[3], int64_t n, const double *x, const double *w,
+void lho_p2m_method2(int p, const double centre[3], int64_t n, const double *x, const double *w, const double *q,
                      cplx *phi, cplx *chi)
 {
     cplx *g = (cplx *)malloc(sizeof(cplx) * (size_t)p * p);
@@ -387,6 +397,8 @@ void lho_p2m_method2(int p, const double centre[3], int64_t n, const double *x, 
                          (wx + I * wy) * (nn + m + 1) / 2.0 * cget(g, p, nn, m + 1) -
                          I * wz * (double)m * cget(g, p, nn, m);
                 phi[IDX(nn, m)] += a / (double)(nn + 1);
+                /* monopole (eq. 7): phi gains -q_l / |y - x_l| = -q_l sum g_n^m S_n^m (eq. rsbf5) */
+                if (q) phi[IDX(nn, m)] -= q[l] * cget(g, p, nn, m);
                 if (nn > 0) {
                     cplx b = 0.5 * (wy + I * wx) * cget(g, p, nn - 1, m - 1) -
                              0.5 * (wy - I * wx) * cget(g, p, nn - 1, m + 1) -
@@ -666,7 +678,7 @@ void lho_l2p(int p, const double centre[3], const cplx *phi, const cplx *chi, in
  *    smoothed if the leaves of source and target are adjacent, else singular.
  * Targets: ntarg indices into the n elements (all if targ == NULL).
  * Outputs are indexed by target position in the list. */
-void lho_direct(int64_t n, const double *x, const double *w, double a, int mode, int depth,
+void lho_direct(int64_t n, const double *x, const double *w, const double *q, double a, int mode, int depth,
                 const double lo[3], double L, int64_t ntarg, const int64_t *targ, double *v, double *s,
                 double *gv)
 {
@@ -693,7 +705,8 @@ void lho_direct(int64_t n, const double *x, const double *w, double a, int mode,
                 }
                 smooth = adj;
             }
-            pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, smooth, vv, ss, gv ? gg : NULL);
+            pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], q ? q[i] : 0.0, a, smooth, vv, ss,
+                       gv ? gg : NULL);
         }
         for (int k = 0; k < 3; k++) {
             v[3 * jj + k] = vv[k];
@@ -752,8 +765,8 @@ static int vlist(const otree *T, int l, uint64_t k, int64_t *out)
 }
 
 /* gather the elements of box (l, b) */
-static void box_points(const otree *T, const double *x, const double *w, int l, int64_t b, double *bx,
-                       double *bw)
+static void box_points(const otree *T, const double *x, const double *w, const double *q, int l, int64_t b,
+                       double *bx, double *bw, double *bq)
 {
     int64_t f = T->first[l][b], c = T->count[l][b];
     for (int64_t i = 0; i < c; i++) {
@@ -762,6 +775,7 @@ static void box_points(const otree *T, const double *x, const double *w, int l, 
             bx[3 * i + d] = x[3 * e + d];
             bw[3 * i + d] = w[3 * e + d];
         }
+        if (q) bq[i] = q[e];
     }
 }
 
@@ -771,9 +785,9 @@ static void box_points(const otree *T, const double *x, const double *w, int l, 
  *          evaluated (their outputs written, others untouched); NULL = all.
  *  p2m_method: 1 or 2.
  * Returns 0 on success. */
-int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int depth, const double lo[3],
-            double L, int what, int p2m_method, int64_t nsample, const int64_t *sample, double *v,
-            double *s, double *gv, lho_stats *st)
+int lho_fmm(int64_t n, const double *x, const double *w, const double *q, double a, int p, int depth,
+            const double lo[3], double L, int what, int p2m_method, int64_t nsample, const int64_t *sample,
+            double *v, double *s, double *gv, lho_stats *st)
 {
     if (depth < 2 || depth > 10 || p < 1 || n < 1) return -1;
     double t0 = wtime();
@@ -807,7 +821,7 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
         for (int l = 2; l <= depth; l++) M[l] = (cplx *)calloc((size_t)T.nb[l] * 2 * P2, sizeof(cplx));
 #pragma omp parallel
         {
-            double *bx = NULL, *bw = NULL;
+            double *bx = NULL, *bw = NULL, *bq = NULL;
             int64_t cap = 0;
 #pragma omp for schedule(dynamic, 4)
             for (int64_t b = 0; b < nleaf; b++) {
@@ -815,19 +829,22 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
                 if (c > cap) {
                     free(bx);
                     free(bw);
+                    free(bq);
                     cap = c;
                     bx = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
                     bw = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                    bq = (double *)malloc(sizeof(double) * (size_t)cap);
                 }
-                box_points(&T, x, w, depth, b, bx, bw);
+                box_points(&T, x, w, q, depth, b, bx, bw, bq);
                 double cen[3];
                 box_centre(&T, depth, T.key[depth][b], cen);
                 cplx *ph = &M[depth][(size_t)b * 2 * P2], *ch = ph + P2;
                 if (p2m_method == 1) lho_p2m_method1(p, cen, c, bx, bw, ph, ch);
-                else lho_p2m_method2(p, cen, c, bx, bw, ph, ch);
+                else lho_p2m_method2(p, cen, c, bx, bw, q ? bq : NULL, ph, ch);
             }
             free(bx);
             free(bw);
+            free(bq);
         }
         for (int l = depth - 1; l >= 2; l--) {
             int sh = 3;
@@ -902,7 +919,7 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
                         bs = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
                         bg = (double *)malloc(sizeof(double) * 9 * (size_t)cap);
                     }
-                    box_points(&T, x, w, depth, b, bx, bw);
+                    box_points(&T, x, w, NULL, depth, b, bx, bw, NULL);
                     memset(bv, 0, sizeof(double) * 3 * (size_t)c);
                     memset(bs, 0, sizeof(double) * 3 * (size_t)c);
                     memset(bg, 0, sizeof(double) * 9 * (size_t)c);
@@ -969,7 +986,7 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
                         bs = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
                         bg = (double *)malloc(sizeof(double) * 9 * (size_t)cap);
                     }
-                    box_points(&T, x, w, depth, b, bx, bw);
+                    box_points(&T, x, w, NULL, depth, b, bx, bw, NULL);
                     memset(bv, 0, sizeof(double) * 3 * (size_t)c);
                     memset(bs, 0, sizeof(double) * 3 * (size_t)c);
                     memset(bg, 0, sizeof(double) * 9 * (size_t)c);
@@ -1021,11 +1038,12 @@ int lho_fmm(int64_t n, const double *x, const double *w, double a, int p, int de
             for (int64_t it = 0; it < T.count[depth][b]; it++) {
                 int64_t j = T.order[T.first[depth][b] + it];
                 double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gg[9] = {0};
-                for (int q = 0; q < nn; q++) {
-                    for (int64_t is = 0; is < T.count[depth][nb_list[q]]; is++) {
-                        int64_t i = T.order[T.first[depth][nb_list[q]] + is];
+                for (int u = 0; u < nn; u++) {
+                    for (int64_t is = 0; is < T.count[depth][nb_list[u]]; is++) {
+                        int64_t i = T.order[T.first[depth][nb_list[u]] + is];
                         if (i == j) continue;
-                        pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, smooth, vv, ss, gv ? gg : NULL);
+                        pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], q ? q[i] : 0.0, a, smooth, vv,
+                                   ss, gv ? gg : NULL);
                         npairs++;
                     }
                 }
@@ -1313,15 +1331,15 @@ static int list_V(const atree *A, int l, uint64_t k, int64_t *out)
 }
 
 /* add the direct sum over the elements of box (l, q) into target element j */
-static int64_t box_direct(const atree *A, const double *x, const double *w, double a, int smooth, int l,
-                          int64_t q, int64_t j, double *vv, double *ss, double *gg)
+static int64_t box_direct(const atree *A, const double *x, const double *w, const double *qm, double a,
+                          int smooth, int l, int64_t q, int64_t j, double *vv, double *ss, double *gg)
 {
     const otree *T = &A->T;
     int64_t np = 0;
     for (int64_t is = 0; is < T->count[l][q]; is++) {
         int64_t i = T->order[T->first[l][q] + is];
         if (i == j) continue;
-        pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, smooth, vv, ss, gg);
+        pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], qm ? qm[i] : 0.0, a, smooth, vv, ss, gg);
         np++;
     }
     return np;
@@ -1331,9 +1349,9 @@ static int64_t box_direct(const atree *A, const double *x, const double *w, doub
  * (row = component, column = derivative) when gv is not NULL.  what / sample as
  * in lho_fmm (sample: the leaves holding the sampled elements are evaluated).
  * maxleaf >= 0, 1 <= maxl <= 10.  Returns 0 on success. */
-int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int p, int64_t maxleaf, int maxl,
-                     const double lo[3], double L, int what, int64_t nsample, const int64_t *sample, double *v,
-                     double *s, double *gv, lho_stats *st)
+int lho_fmm_adaptive(int64_t n, const double *x, const double *w, const double *qm, double a, int p,
+                     int64_t maxleaf, int maxl, const double lo[3], double L, int what, int64_t nsample,
+                     const int64_t *sample, double *v, double *s, double *gv, lho_stats *st)
 {
     if (maxl < 1 || maxl > 10 || p < 1 || n < 1 || maxleaf < 0) return -1;
     double t0 = wtime();
@@ -1381,7 +1399,7 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int 
         for (int l = maxl; l >= 2; l--) {
 #pragma omp parallel
             {
-                double *bx = NULL, *bw = NULL;
+                double *bx = NULL, *bw = NULL, *bq = NULL;
                 int64_t cap = 0;
 #pragma omp for schedule(dynamic, 4)
                 for (int64_t b = 0; b < T->nb[l]; b++) {
@@ -1394,12 +1412,14 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int 
                         if (c > cap) {
                             free(bx);
                             free(bw);
+                            free(bq);
                             cap = c;
                             bx = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
                             bw = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                            bq = (double *)malloc(sizeof(double) * (size_t)cap);
                         }
-                        box_points(T, x, w, l, b, bx, bw);
-                        lho_p2m_method2(p, cen, c, bx, bw, ph, ch);
+                        box_points(T, x, w, qm, l, b, bx, bw, bq);
+                        lho_p2m_method2(p, cen, c, bx, bw, qm ? bq : NULL, ph, ch);
                     } else {
                         for (int chn = 0; chn < 8; chn++) {
                             int64_t cb = atree_find(&A, l + 1, (T->key[l][b] << 3) | (uint64_t)chn);
@@ -1414,6 +1434,7 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int 
                 }
                 free(bx);
                 free(bw);
+                free(bq);
             }
         }
         stats.t_up = wtime() - t1;
@@ -1478,7 +1499,7 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int 
                         bs = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
                         bg = (double *)malloc(sizeof(double) * 9 * (size_t)cap);
                     }
-                    box_points(T, x, w, l, b, bx, bw);
+                    box_points(T, x, w, NULL, l, b, bx, bw, NULL);
                     memset(bv, 0, sizeof(double) * 3 * (size_t)c);
                     memset(bs, 0, sizeof(double) * 3 * (size_t)c);
                     memset(bg, 0, sizeof(double) * 9 * (size_t)c);
@@ -1527,9 +1548,9 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int 
                     double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gg[9] = {0};
                     double *gp = gv ? gg : NULL;
                     for (int64_t q = 0; q < U.n; q++)
-                        nu += box_direct(&A, x, w, a, smooth, U.lev[q], U.box[q], j, vv, ss, gp);
+                        nu += box_direct(&A, x, w, qm, a, smooth, U.lev[q], U.box[q], j, vv, ss, gp);
                     for (int64_t q = 0; q < WX.n; q++)
-                        nwx += box_direct(&A, x, w, a, 0, WX.lev[q], WX.box[q], j, vv, ss, gp);
+                        nwx += box_direct(&A, x, w, qm, a, 0, WX.lev[q], WX.box[q], j, vv, ss, gp);
                     for (int d = 0; d < 3; d++) {
                         v[3 * j + d] += vv[d];
                         s[3 * j + d] += ss[d];
@@ -1553,8 +1574,9 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, double a, int 
 
 /* Direct sums with the adaptive split rule: the smoothed kernel between
  * elements of adjacent leaves of the adaptive tree, the singular one otherwise. */
-void lho_direct_adaptive(int64_t n, const double *x, const double *w, double a, int64_t maxleaf, int maxl,
-                         const double lo[3], double L, int64_t ntarg, const int64_t *targ, double *v, double *s)
+void lho_direct_adaptive(int64_t n, const double *x, const double *w, const double *q, double a, int64_t maxleaf,
+                         int maxl, const double lo[3], double L, int64_t ntarg, const int64_t *targ, double *v,
+                         double *s)
 {
     atree A;
     atree_build(&A, n, x, maxleaf, maxl, lo, L);
@@ -1596,7 +1618,7 @@ void lho_direct_adaptive(int64_t n, const double *x, const double *w, double a, 
             int adj = !(ei[0] > ej[3] || ej[0] > ei[3] || ei[1] > ej[4] || ej[1] > ei[4] || ei[2] > ej[5] ||
                         ej[2] > ei[5]);
             int sm = smooth_ok && adj;
-            pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], a, sm, vv, ss, NULL);
+            pair_accum(&x[3 * j], &w[3 * j], &x[3 * i], &w[3 * i], q ? q[i] : 0.0, a, sm, vv, ss, NULL);
         }
         for (int k = 0; k < 3; k++) {
             v[3 * jj + k] = vv[k];

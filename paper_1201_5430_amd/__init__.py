@@ -34,7 +34,7 @@ EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_plan_create_multi", "lhf_
            "lhf_evaluate", "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version",
            "lhf_profile_begin", "lhf_profile_end", "lhf_tune_default", "lhf_autotune", "lhf_choose_depth",
            "lhf_batch_create", "lhf_batch_execute", "lhf_batch_info", "lhf_batch_destroy",
-           "lhf_release_cached_memory", "lhf_evaluate_noalloc")
+           "lhf_release_cached_memory", "lhf_evaluate_noalloc", "lhf_execute_io")
 PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 
 
@@ -43,6 +43,11 @@ class Desc(C.Structure):
                 ("domain_lo", C.c_double * 3), ("domain_len", C.c_double), ("precision", C.c_int32),
                 ("flags", C.c_uint32), ("translation", C.c_int32), ("m2l_kernel", C.c_int32),
                 ("mm_kernel", C.c_int32), ("reserved", C.c_int32)]
+
+
+class IO(C.Structure):
+    _fields_ = [("omega", C.c_void_p), ("q", C.c_void_p), ("v", C.c_void_p), ("s", C.c_void_p),
+                ("grad_v", C.c_void_p), ("beta", C.c_void_p), ("what", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -82,6 +87,8 @@ def load():
         L.lhf_execute.argtypes = [vp, vp, vp, vp, vp, vp]
         L.lhf_execute.restype = C.c_int
         L.lhf_execute_parts.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp]
+        L.lhf_execute_io.argtypes = [vp, C.POINTER(IO), vp]
+        L.lhf_execute_io.restype = C.c_int
         L.lhf_execute_parts.restype = C.c_int
         L.lhf_evaluate.argtypes = [C.POINTER(Desc), C.c_int64, vp, vp, C.c_double, vp, vp, vp]
         L.lhf_evaluate.restype = C.c_int
@@ -210,22 +217,37 @@ class Plan:
         self.warn_tol_unmet = bool(st["warnings"] & 2)
         self.p = st["p"]
 
-    def execute(self, omega, v=None, s=None, what=3, grad=False, g=None):
-        """(v, s), or (v, s, grad v) with grad=True; grad v is [N,3,3] with [i,k,l] = d v_k/d x_l"""
+    def execute(self, omega, v=None, s=None, what=3, grad=False, g=None, q=None, beta=False):
+        """(v, s); with grad=True also grad v ([N,3,3], [i,k,l] = d v_k/d x_l); with beta=True also
+        beta = grad v : grad v ([N]); q: [N] monopole strengths (divergence sources) or None"""
         import torch
         omega = _dev_array(omega, self.dtype, "omega", self.n)
         v = torch.empty_like(omega) if v is None else _dev_array(v, self.dtype, "v", self.n)
         s = torch.empty_like(omega) if s is None else _dev_array(s, self.dtype, "s", self.n)
-        gp = None
+        io = IO()
+        io.omega, io.v, io.s, io.what = omega.data_ptr(), v.data_ptr(), s.data_ptr(), int(what)
+        if q is not None:
+            if not isinstance(q, torch.Tensor) or not q.is_cuda or q.dtype != self.dtype or \
+                    not q.is_contiguous() or q.dim() != 1 or q.shape[0] != self.n:
+                raise TypeError(f"q must be a contiguous [N] {self.dtype} device tensor with N = {self.n}")
+            io.q = q.data_ptr()
         if grad or g is not None:
             if g is None:
                 g = torch.empty((self.n, 9), dtype=self.dtype, device=omega.device)
             else:
                 g = _dev_array(g.reshape(self.n, 9) if g.is_contiguous() else g, self.dtype, "g", self.n, 9)
-            gp = C.c_void_p(g.data_ptr())
-        _check(load().lhf_execute_parts(self._h, C.c_void_p(omega.data_ptr()), C.c_void_p(v.data_ptr()),
-                                        C.c_void_p(s.data_ptr()), gp, int(what), _stream()))
-        return (v, s, g.view(self.n, 3, 3)) if gp is not None else (v, s)
+            io.grad_v = g.data_ptr()
+        b = None
+        if beta:
+            b = torch.empty(self.n, dtype=self.dtype, device=omega.device)
+            io.beta = b.data_ptr()
+        _check(load().lhf_execute_io(self._h, C.byref(io), _stream()))
+        out = (v, s)
+        if io.grad_v:
+            out = out + (g.view(self.n, 3, 3),)
+        if b is not None:
+            out = out + (b,)
+        return out
 
     def stats(self):
         st = Stats()

@@ -190,7 +190,15 @@ static lhf_status batch_capture(lhf_batch *B, const void *omega, void *v, void *
     hipError_t e = hipEventRecord(B->ev[0], B->cap);
     for (int k = 0; k < K && e == hipSuccess; k++) e = hipStreamWaitEvent(B->lanes[k], B->ev[0], 0);
     for (size_t g = 0; g < B->group.size() && e == hipSuccess && rs >= 0; g++)
-        rs = execute_impl(B->group[g], omega, v, s, nullptr, 3, B->lanes[g % K]);
+        {
+            lhf_io io;
+            memset(&io, 0, sizeof(io));
+            io.omega = omega;
+            io.v = v;
+            io.s = s;
+            io.what = 3;
+            rs = execute_impl(B->group[g], &io, B->lanes[g % K]);
+        }
     for (int k = 0; k < K && e == hipSuccess; k++) {
         e = hipEventRecord(B->ev[1 + k], B->lanes[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(B->cap, B->ev[1 + k], 0);
@@ -520,7 +528,13 @@ lhf_status lhf_batch_execute(lhf_batch *B, const void *omega, void *v, void *s, 
     hipStream_t st = (hipStream_t)stream;
     if (!use_graph) {
         for (lhf_plan *P : B->group) {
-            lhf_status rs = execute_impl(P, omega, v, s, nullptr, 3, st);
+            lhf_io io;
+            memset(&io, 0, sizeof(io));
+            io.omega = omega;
+            io.v = v;
+            io.s = s;
+            io.what = 3;
+            lhf_status rs = execute_impl(P, &io, st);
             if (rs < 0) return rs;
         }
         return LHF_OK;

@@ -77,7 +77,8 @@ template <typename T>
 __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off, const int32_t *__restrict__ leaves,
                                               const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
                                               const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
-                                              const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
+                                              const T *__restrict__ xs, const T *__restrict__ ws,
+                                              const T *__restrict__ qs, int64_t n,
                                               const double *__restrict__ sys_geo, T *__restrict__ M, int ch)
 {
     // the leaf's elements in chunks of ch: first every lane forms the regular solid harmonics of
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
     extern __shared__ char smem[];
     T *Rre = (T *)smem;              // [ch][p][p]  (element, n, m)
     T *Rim = Rre + (size_t)ch * p * p;
-    T *wsh = Rim + (size_t)ch * p * p;  // [ch][3] strengths
+    T *wsh = Rim + (size_t)ch * p * p;  // [ch][4] strengths: omega, q (0 without monopoles)
     const int lane = threadIdx.x;
     // uniform tree: leaves leaf_off + blockIdx.x at level depth; adaptive: leaves[blockIdx.x] at blev[]
     const int64_t b = leaves ? (int64_t)leaves[blockIdx.x] : leaf_off + blockIdx.x;
@@ -138,9 +139,10 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                 p1im = cim;
             }
             if (m == 0) {
-                wsh[3 * e] = ws[i];
-                wsh[3 * e + 1] = ws[n + i];
-                wsh[3 * e + 2] = ws[2 * n + i];
+                wsh[4 * e] = ws[i];
+                wsh[4 * e + 1] = ws[n + i];
+                wsh[4 * e + 2] = ws[2 * n + i];
+                wsh[4 * e + 3] = qs ? qs[i] : (T)0;
             }
         }
         __syncthreads();
@@ -154,7 +156,7 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
             const T sgn = (m & 1) ? (T)-1 : (T)1;
             for (int e = 0; e < ne; e++) {
                 const T *Re = Rre + (size_t)e * P2, *Im = Rim + (size_t)e * P2;
-                const T wx = wsh[3 * e], wy = wsh[3 * e + 1], wz = wsh[3 * e + 2];
+                const T wx = wsh[4 * e], wy = wsh[4 * e + 1], wz = wsh[4 * e + 2], qe = wsh[4 * e + 3];
                 // conj(Rt_n^k), with the convention conj(Rt_n^{-1}) = -Rt_n^1 that makes the m >= 1
                 // formulas valid at m = 0 as well
                 auto C = [&](int n2, int kk, T &re, T &im) {
@@ -189,6 +191,9 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                     T sc = sgn / (T)(nn + 1);
                     vre = sc * sim;  // -i (sre + i sim) = sim - i sre
                     vim = -sc * sre;
+                    // monopole q (eq. 7): phi gains -q g_n^m, i.e. -q (-1)^m C(m) in this form
+                    vre -= qe * sgn * c3re;
+                    vim -= qe * sgn * c3im;
                 } else {
                     if (nn == 0) {
                         vre = 0;
@@ -753,31 +758,40 @@ __device__ inline void kernel_fg(T r2, T a, int smooth, T &f, T &g)
     }
 }
 
-// one packed element record: position and strength
+// one packed element record: position, strength and (slot 6) monopole strength
 template <typename T>
 struct Rec {
-    T x, y, z, wx, wy, wz;
+    T x, y, z, wx, wy, wz, q;
 };
+template <bool Q>
 __device__ __forceinline__ Rec<float> load_rec(const float *__restrict__ xw, int k)
 {
     const float4 a = *(const float4 *)(xw + 8 * (size_t)k);
-    const float2 b = *(const float2 *)(xw + 8 * (size_t)k + 4);
-    return {a.x, a.y, a.z, a.w, b.x, b.y};
+    if constexpr (Q) {
+        const float4 b = *(const float4 *)(xw + 8 * (size_t)k + 4);
+        return {a.x, a.y, a.z, a.w, b.x, b.y, b.z};
+    } else {
+        const float2 b = *(const float2 *)(xw + 8 * (size_t)k + 4);
+        return {a.x, a.y, a.z, a.w, b.x, b.y, 0.f};
+    }
 }
+template <bool Q>
 __device__ __forceinline__ Rec<double> load_rec(const double *__restrict__ xw, int k)
 {
     const double2 a = *(const double2 *)(xw + 8 * (size_t)k);
     const double2 b = *(const double2 *)(xw + 8 * (size_t)k + 2);
     const double2 c = *(const double2 *)(xw + 8 * (size_t)k + 4);
-    return {a.x, a.y, b.x, b.y, c.x, c.y};
+    const double qv = Q ? xw[8 * (size_t)k + 6] : 0.0;
+    return {a.x, a.y, b.x, b.y, c.x, c.y, qv};
 }
 
-// contribution of sorted source k to the target (xj, wj); r = x_j - x_k
-template <typename T>
+// contribution of sorted source k to the target (xj, wj); r = x_j - x_k.  With Q the source's
+// monopole strength adds q f r to v and q (f w_j + g r (w_j . r)) to s (eq. 7, same kernel)
+template <typename T, bool Q>
 __device__ __forceinline__ void p2p_pair(int k, const T *__restrict__ xw, T xj, T yj, T zj, T wjx, T wjy, T wjz,
                                          T a, int smooth, T &v0, T &v1, T &v2, T &s0, T &s1, T &s2)
 {
-    const Rec<T> q = load_rec(xw, k);
+    const Rec<T> q = load_rec<Q>(xw, k);
     const T rx = xj - q.x, ry = yj - q.y, rz = zj - q.z;
     const T r2 = rx * rx + ry * ry + rz * rz;
     if (r2 == (T)0 && !smooth) return;  // coincident distinct points, singular kernel: no contribution
@@ -792,14 +806,23 @@ __device__ __forceinline__ void p2p_pair(int k, const T *__restrict__ xw, T xj, 
     s0 += f * (wiy * wjz - wiz * wjy) + dd * cx;
     s1 += f * (wiz * wjx - wix * wjz) + dd * cy;
     s2 += f * (wix * wjy - wiy * wjx) + dd * cz;
+    if constexpr (Q) {
+        const T qf = q.q * f, qd = q.q * dd;
+        v0 += qf * rx;
+        v1 += qf * ry;
+        v2 += qf * rz;
+        s0 += qf * wjx + qd * rx;
+        s1 += qf * wjy + qd * ry;
+        s2 += qf * wjz + qd * rz;
+    }
 }
 
 // the same pair with the velocity gradient: d_l (f (w_i x r))_k = g r_l (w_i x r)_k + f eps_{k a l} w_i,a
-template <typename T>
+template <typename T, bool Q>
 __device__ __forceinline__ void p2p_pair_grad(int k, const T *__restrict__ xw, T xj, T yj, T zj, T wjx, T wjy,
                                               T wjz, T a, int smooth, T *acc)
 {
-    const Rec<T> q = load_rec(xw, k);
+    const Rec<T> q = load_rec<Q>(xw, k);
     const T rx = xj - q.x, ry = yj - q.y, rz = zj - q.z;
     const T r2 = rx * rx + ry * ry + rz * rz;
     if (r2 == (T)0 && !smooth) return;
@@ -824,11 +847,30 @@ __device__ __forceinline__ void p2p_pair_grad(int k, const T *__restrict__ xw, T
     acc[12] += gx * cz - f * wiy;
     acc[13] += gy * cz + f * wix;
     acc[14] += gz * cz;
+    if constexpr (Q) {
+        // q (f r, f w_j + g r (w_j . r), f delta_kl + g r_k r_l)
+        const T qf = q.q * f, qd = q.q * dd, qgx = q.q * gx, qgy = q.q * gy, qgz = q.q * gz;
+        acc[0] += qf * rx;
+        acc[1] += qf * ry;
+        acc[2] += qf * rz;
+        acc[3] += qf * wjx + qd * rx;
+        acc[4] += qf * wjy + qd * ry;
+        acc[5] += qf * wjz + qd * rz;
+        acc[6] += qgx * rx + qf;
+        acc[7] += qgy * rx;
+        acc[8] += qgz * rx;
+        acc[9] += qgx * ry;
+        acc[10] += qgy * ry + qf;
+        acc[11] += qgz * ry;
+        acc[12] += qgx * rz;
+        acc[13] += qgy * rz;
+        acc[14] += qgz * rz + qf;
+    }
 }
 
 // near-field sum of one target over the elements st .. st+ct-1 (self excluded), added box by
 // box into compensated accumulators: v, s and, with GRAD, grad v
-template <typename T, bool GRAD>
+template <typename T, bool GRAD, bool Q>
 __device__ __forceinline__ void p2p_box(int i, int st, int ct, const T *__restrict__ xw, T xj, T yj, T zj, T wjx,
                                         T wjy, T wjz, T a, int sm, CompSum<T> *acc)
 {
@@ -838,7 +880,7 @@ __device__ __forceinline__ void p2p_box(int i, int st, int ct, const T *__restri
         for (int e = 0; e < ct; e++) {
             const int k = st + e;
             if (k == i) continue;
-            p2p_pair_grad<T>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, sm, b);
+            p2p_pair_grad<T, Q>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, sm, b);
         }
         for (int k = 0; k < 15; k++) acc[k].add(b[k]);
     } else {
@@ -846,7 +888,7 @@ __device__ __forceinline__ void p2p_box(int i, int st, int ct, const T *__restri
         for (int e = 0; e < ct; e++) {
             const int k = st + e;
             if (k == i) continue;
-            p2p_pair<T>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, sm, v0, v1, v2, s0, s1, s2);
+            p2p_pair<T, Q>(k, xw, xj, yj, zj, wjx, wjy, wjz, a, sm, v0, v1, v2, s0, s1, s2);
         }
         acc[0].add(v0);
         acc[1].add(v1);
@@ -861,7 +903,7 @@ __device__ __forceinline__ void p2p_box(int i, int st, int ct, const T *__restri
 template <typename T, bool GRAD>
 __device__ __forceinline__ void p2p_store(int64_t i, int64_t n, const int32_t *__restrict__ perm,
                                           const CompSum<T> *acc, T *__restrict__ vout, T *__restrict__ sout,
-                                          T *__restrict__ gout)
+                                          T *__restrict__ gout, T *__restrict__ bout)
 {
     const int64_t o = perm[i];
     vout[3 * o] = acc[0].value();
@@ -870,14 +912,21 @@ __device__ __forceinline__ void p2p_store(int64_t i, int64_t n, const int32_t *_
     sout[3 * o] = acc[3].value();
     sout[3 * o + 1] = acc[4].value();
     sout[3 * o + 2] = acc[5].value();
-    if constexpr (GRAD)
-        for (int k = 0; k < 9; k++) gout[9 * o + k] = acc[6 + k].value();
+    if constexpr (GRAD) {
+        T b = 0;
+        for (int k = 0; k < 9; k++) {
+            const T gk = acc[6 + k].value();
+            if (gout) gout[9 * o + k] = gk;
+            b += gk * gk;
+        }
+        if (bout) bout[o] = b;  // beta = grad v : grad v
+    }
 }
 
 // adaptive tree: near field of one sorted element over its leaf's source list (entries
 // (box << 1) | singular: U-list leaves with the smoothed kernel, W/X boxes with the singular
 // one), then combination with the far field and un-permutation as in k_p2p
-template <typename T, bool GRAD>
+template <typename T, bool GRAD, bool Q>
 __global__ void __launch_bounds__(256) k_p2p_list(int64_t n, const int32_t *__restrict__ eleaf,
                                                   const int32_t *__restrict__ leaves, const int8_t *__restrict__ blev,
                                                   const int32_t *__restrict__ nl_start, const int32_t *__restrict__ nl_ent,
@@ -886,7 +935,8 @@ __global__ void __launch_bounds__(256) k_p2p_list(int64_t n, const int32_t *__re
                                                   const T *__restrict__ ws, const T *__restrict__ xw,
                                                   const double *__restrict__ sys_a, int what,
                                                   const T *__restrict__ vfar, const int32_t *__restrict__ perm,
-                                                  T *__restrict__ vout, T *__restrict__ sout, T *__restrict__ gout)
+                                                  T *__restrict__ vout, T *__restrict__ sout, T *__restrict__ gout,
+                                                  T *__restrict__ bout)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -905,13 +955,13 @@ __global__ void __launch_bounds__(256) k_p2p_list(int64_t n, const int32_t *__re
         for (int q = nl_start[lp]; q < e1; q++) {
             const int code = nl_ent[q];
             const int src = code >> 1, sm = smooth && !(code & 1);
-            p2p_box<T, GRAD>((int)i, bstart[src], bcount[src], xw, xj, yj, zj, wjx, wjy, wjz, a, sm, acc);
+            p2p_box<T, GRAD, Q>((int)i, bstart[src], bcount[src], xw, xj, yj, zj, wjx, wjy, wjz, a, sm, acc);
         }
     }
-    p2p_store<T, GRAD>(i, n, perm, acc, vout, sout, gout);
+    p2p_store<T, GRAD>(i, n, perm, acc, vout, sout, gout, bout);
 }
 
-template <typename T, bool GRAD>
+template <typename T, bool GRAD, bool Q>
 __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_off, const int32_t *__restrict__ eleaf,
                                              const int32_t *__restrict__ ulist, const uint64_t *__restrict__ bkey,
                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
@@ -919,7 +969,7 @@ __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_
                                              const T *__restrict__ xw, const double *__restrict__ sys_a, int what,
                                              const T *__restrict__ vfar,
                                              const int32_t *__restrict__ perm, T *__restrict__ vout,
-                                             T *__restrict__ sout, T *__restrict__ gout)
+                                             T *__restrict__ sout, T *__restrict__ gout, T *__restrict__ bout)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -938,16 +988,17 @@ __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_
         for (int q = 0; q < 27; q++) {
             const int nb = U[q];
             if (nb < 0) continue;
-            p2p_box<T, GRAD>((int)i, bstart[nb], bcount[nb], xw, xj, yj, zj, wjx, wjy, wjz, a, smooth, acc);
+            p2p_box<T, GRAD, Q>((int)i, bstart[nb], bcount[nb], xw, xj, yj, zj, wjx, wjy, wjz, a, smooth, acc);
         }
     }
-    p2p_store<T, GRAD>(i, n, perm, acc, vout, sout, gout);
+    p2p_store<T, GRAD>(i, n, perm, acc, vout, sout, gout, bout);
 }
 
 // gather omega into the sorted SoA layout
 template <typename T>
-__global__ void k_gather_w(int64_t n, const T *__restrict__ w, const int32_t *__restrict__ perm,
-                           const T *__restrict__ xs, T *__restrict__ ws, T *__restrict__ xw)
+__global__ void k_gather_w(int64_t n, const T *__restrict__ w, const T *__restrict__ q,
+                           const int32_t *__restrict__ perm, const T *__restrict__ xs, T *__restrict__ ws,
+                           T *__restrict__ qs, T *__restrict__ xw)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -964,28 +1015,34 @@ __global__ void k_gather_w(int64_t n, const T *__restrict__ w, const int32_t *__
     r[3] = wx;
     r[4] = wy;
     r[5] = wz;
-    r[6] = (T)0;
+    const T qo = q ? q[o] : (T)0;
+    r[6] = qo;
     r[7] = (T)0;
+    if (q) qs[i] = qo;
 }
 
-template <typename T, bool GRAD>
-static void p2p_launch(lhf_plan *P, int what, T *v, T *s, T *g, unsigned nblk, int tpb, hipStream_t st)
+template <typename T, bool GRAD, bool Q>
+static void p2p_launch(lhf_plan *P, int what, T *v, T *s, T *g, T *b, unsigned nblk, int tpb, hipStream_t st)
 {
     const int64_t n = P->n;
     const int d = P->depth;
     if (P->adaptive)
-        hipLaunchKernelGGL((k_p2p_list<T, GRAD>), dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, P->leaves, P->blev,
+        hipLaunchKernelGGL((k_p2p_list<T, GRAD, Q>), dim3(nblk), dim3(tpb), 0, st, n, P->eleaf, P->leaves, P->blev,
                            P->nl_start, P->nl_ent, P->bkey, P->bstart, P->bcount, (const T *)P->xs, (const T *)P->ws,
-                           (const T *)P->xw, P->sys_a, what, (const T *)P->vfar, P->perm, v, s, g);
+                           (const T *)P->xw, P->sys_a, what, (const T *)P->vfar, P->perm, v, s, g, b);
     else
-        hipLaunchKernelGGL((k_p2p<T, GRAD>), dim3(nblk), dim3(tpb), 0, st, n, d, P->lev[d].off, P->eleaf, P->ulist,
-                           P->bkey, P->bstart, P->bcount, (const T *)P->xs, (const T *)P->ws, (const T *)P->xw,
-                           P->sys_a, what, (const T *)P->vfar, P->perm, v, s, g);
+        hipLaunchKernelGGL((k_p2p<T, GRAD, Q>), dim3(nblk), dim3(tpb), 0, st, n, d, P->lev[d].off, P->eleaf,
+                           P->ulist, P->bkey, P->bstart, P->bcount, (const T *)P->xs, (const T *)P->ws,
+                           (const T *)P->xw, P->sys_a, what, (const T *)P->vfar, P->perm, v, s, g, b);
 }
 
 template <typename T>
-static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, void *grad_v, int what, hipStream_t st)
+static lhf_status execute_t(lhf_plan *P, const lhf_io *io, hipStream_t st)
 {
+    const void *omega = io->omega;
+    const T *qin = (const T *)io->q;
+    void *v = io->v, *s = io->s, *grad_v = io->grad_v, *beta = io->beta;
+    const int what = io->what;
     const int p = P->p, d = P->depth;
     const int64_t n = P->n;
     const int P2 = p * p, ZS = (p + 1) * (p + 1);
@@ -1000,17 +1057,18 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, vo
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
-    hipLaunchKernelGGL(k_gather_w<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)omega, P->perm, (const T *)xs, ws,
-                       (T *)P->xw);
+    hipLaunchKernelGGL(k_gather_w<T>, dim3(nblk), dim3(tpb), 0, st, n, (const T *)omega, qin, P->perm,
+                       (const T *)xs, ws, (T *)P->qs, (T *)P->xw);
     mark(1);
     // uniform tree: the leaves are the boxes of level d; adaptive: the explicit leaf list
     const int64_t loff = P->lev[d].off, nleaf = P->adaptive ? P->nleaf : P->lev[d].nb;
     if (what & 1) {
         // elements per P2M chunk: 8, fewer at large p (LDS within 48 KB)
-        const int ch = std::max(1, std::min(8, (int)(49152 / (sizeof(T) * (2 * P2 + 3)))));
-        size_t sh_p2m = sizeof(T) * (size_t)ch * (2 * P2 + 3);
+        const int ch = std::max(1, std::min(8, (int)(49152 / (sizeof(T) * (2 * P2 + 4)))));
+        size_t sh_p2m = sizeof(T) * (size_t)ch * (2 * P2 + 4);
         hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_p2m, st, p, d, loff, P->leaves, P->blev,
-                           P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, M, ch);
+                           P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, qin ? (const T *)P->qs : nullptr,
+                           n, P->sys_geo, M, ch);
         mark(2);
         size_t sh_rcr = sizeof(T) * (4 * P2 + 2 * ZS + 2 * p + 2);
         for (int l = d - 1; l >= 2; l--) {
@@ -1055,7 +1113,7 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, vo
         size_t sh_l2p = sizeof(T) * L2P_LPB * 6 * TRI;
         hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)((nleaf + L2P_LPB - 1) / L2P_LPB)), dim3(WAVE), sh_l2p, st, p, d,
                            nleaf, loff, P->leaves, P->blev, P->bkey, P->bstart, P->bcount, (const T *)xs,
-                           (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar, grad_v ? 1 : 0);
+                           (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar, (grad_v || beta) ? 1 : 0);
     } else {
         mark(2);
         mark(3);
@@ -1066,17 +1124,21 @@ static lhf_status execute_t(lhf_plan *P, const void *omega, void *v, void *s, vo
         mark(4);
     }
     mark(5);
-    if (grad_v) p2p_launch<T, true>(P, what, (T *)v, (T *)s, (T *)grad_v, nblk, tpb, st);
-    else p2p_launch<T, false>(P, what, (T *)v, (T *)s, nullptr, nblk, tpb, st);
+    const bool gr = grad_v || beta;
+    T *vo = (T *)v, *so = (T *)s, *go = (T *)grad_v, *bo = (T *)beta;
+    if (gr && qin) p2p_launch<T, true, true>(P, what, vo, so, go, bo, nblk, tpb, st);
+    else if (gr) p2p_launch<T, true, false>(P, what, vo, so, go, bo, nblk, tpb, st);
+    else if (qin) p2p_launch<T, false, true>(P, what, vo, so, nullptr, nullptr, nblk, tpb, st);
+    else p2p_launch<T, false, false>(P, what, vo, so, nullptr, nullptr, nblk, tpb, st);
     mark(6);
     LHF_HIP(hipGetLastError());
     return LHF_OK;
 }
 
-lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, void *grad_v, int what, hipStream_t st)
+lhf_status execute_impl(lhf_plan *P, const lhf_io *io, hipStream_t st)
 {
-    if (P->precision == LHF_FP64) return execute_t<double>(P, omega, v, s, grad_v, what, st);
-    return execute_t<float>(P, omega, v, s, grad_v, what, st);
+    if (P->precision == LHF_FP64) return execute_t<double>(P, io, st);
+    return execute_t<float>(P, io, st);
 }
 
 }  // namespace lhf

@@ -85,6 +85,7 @@ struct lhf_plan {
     int32_t *perm = nullptr;     // sorted position -> input index
     void *xs = nullptr;          // sorted coordinates, SoA [3][n], T
     void *ws = nullptr;          // sorted strengths, SoA [3][n], T (filled by execute)
+    void *qs = nullptr;          // sorted monopole strengths [n], T (filled by an execute given q)
     void *vfar = nullptr;        // far-field v, s (+ grad v) in sorted order, SoA [6 or 15][n], T
     void *xw = nullptr;          // sorted elements packed for the near field: [n][8] T = x y z wx wy wz - -
     uint64_t *bkey = nullptr;    // [nbox] Morton key of every box (level-local)
@@ -176,7 +177,7 @@ inline hipError_t dev_malloc(T **p, size_t bytes)
 {
     return dev_malloc_raw((void **)p, bytes);
 }
-lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, void *grad_v, int what, hipStream_t st);
+lhf_status execute_impl(lhf_plan *P, const lhf_io *io, hipStream_t st);
 // order from tolerance and kernel choice (host only)
 bool choose_order(bool adaptive, int precision, double tol, int *p);
 void calib_error(bool adaptive, int p, double *ev, double *es);

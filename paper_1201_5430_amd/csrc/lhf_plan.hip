@@ -26,7 +26,7 @@
 
 namespace lhf {
 
-lhf_status execute_impl(lhf_plan *P, const void *omega, void *v, void *s, void *grad_v, int what, hipStream_t st);
+lhf_status execute_impl(lhf_plan *P, const lhf_io *io, hipStream_t st);
 bool m2l_tile_supported(int precision, int p);
 void dmap_build(const lhf_plan *Pl, int level, hipStream_t st);
 bool wpad_build(lhf_plan *Pl, hipStream_t st);
@@ -1138,6 +1138,7 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(hipcub::DeviceRadixSort::SortPairs(tmp, sort_bytes, key, skey, idx, P->perm, (int)n, 0, end_bit, st));
     CK(dev_malloc(&P->xs, sizeof(T) * 3 * n));
     CK(dev_malloc(&P->ws, sizeof(T) * 3 * n));
+    CK(dev_malloc(&P->qs, sizeof(T) * n));
     // far-field v, s (and grad v when the plan may be asked for it), sorted order, SoA
     CK(dev_malloc(&P->vfar, sizeof(T) * (P->out_grad ? 15 : 6) * n));
     CK(dev_malloc(&P->xw, sizeof(T) * 8 * n));
@@ -1609,18 +1610,32 @@ lhf_status lhf_plan_create_multi(lhf_plan **out, const lhf_desc *d, int32_t n_sy
     return plan_new(out, d, n_systems, sys_offsets, x, sys_lo, sys_len, sys_a, (hipStream_t)stream);
 }
 
-lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, void *grad_v, int32_t what,
-                             void *stream)
+lhf_status lhf_execute_io(lhf_plan *plan, const lhf_io *io, void *stream)
 {
     if (!plan) return arg_error("plan is NULL");
-    if (!omega || !v || !s) return arg_error("omega, v and s must be non-NULL");
-    if (what < 1 || what > 3) return arg_error("what must be 1, 2 or 3");
-    if (grad_v && !plan->out_grad) {
-        set_error("grad_v requested from a plan created without LHF_OUT_GRAD");
+    if (!io) return arg_error("io is NULL");
+    if (!io->omega || !io->v || !io->s) return arg_error("omega, v and s must be non-NULL");
+    if (io->what < 1 || io->what > 3) return arg_error("what must be 1, 2 or 3");
+    if (io->reserved != 0) return arg_error("reserved io field must be 0");
+    if ((io->grad_v || io->beta) && !plan->out_grad) {
+        set_error("grad_v or beta requested from a plan created without LHF_OUT_GRAD");
         return LHF_ERR_STATE;
     }
     plan->stream = (hipStream_t)stream;
-    return execute_impl(plan, omega, v, s, grad_v, what, (hipStream_t)stream);
+    return execute_impl(plan, io, (hipStream_t)stream);
+}
+
+lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, void *grad_v, int32_t what,
+                             void *stream)
+{
+    lhf_io io;
+    memset(&io, 0, sizeof(io));
+    io.omega = omega;
+    io.v = v;
+    io.s = s;
+    io.grad_v = grad_v;
+    io.what = what;
+    return lhf_execute_io(plan, &io, stream);
 }
 
 lhf_status lhf_execute(lhf_plan *plan, const void *omega, void *v, void *s, void *grad_v, void *stream)
