@@ -64,13 +64,26 @@ struct Shape {
     static constexpr int NHP = (NH + E<T>() - 1) / E<T>() * E<T>();
 };
 
-// FP64 orders above 16: one class's rotation tables (8 x WHS entries, 88 KB at p = 20 and
-// 176 KB at p = 24) no longer fit the LDS beside the accumulators of a sibling group, so the
-// kernel reads them from global memory (L2) instead of staging them per class
+// FP64 orders above 16: one class's rotation tables (8 x WHS entries, 105 KB at p = 20, 176 KB
+// at p = 24) and the accumulators of a whole sibling group no longer fit the LDS together.  A
+// tile then holds half a sibling group (four targets: children 4h .. 4h + 3 of one parent), and
+// only the forward (S-basis) tables are staged: the backward R-basis block of a polar angle is a
+// diagonal similarity of the transposed forward block,
+//   Re: W_back = D W_fwd^T D^-1, D = diag(1, -1/2, 1/2, -1/2, ..)  (m = 0, 1, 2, ..),
+//   Im: W_back = D W_fwd^T D^-1, D = diag((-1)^m)                  (m = 1, 2, ..),
+// (the N_m rescalings of the two bases cancel, the (-1)^(m+m') of the S basis and the pairing of
+// +-m into the real-packed blocks leave these factors), so the back-rotation runs on the staged
+// forward tables read row by row
 template <typename T, int P>
-constexpr bool wglobal()
+constexpr bool half_tiles()
 {
     return sizeof(T) == 8 && P > 16;
+}
+// rotation tables staged in LDS per class
+template <typename T, int P>
+constexpr int staged_tables()
+{
+    return half_tiles<T, P>() ? 4 : 8;
 }
 
 // packed (phi, chi) expansion [pot][n^2 + (Re: m | Im: n + m)] -> lane layout
@@ -114,6 +127,22 @@ __device__ __attribute__((always_inline)) inline T dotw(const T *W, const T *x, 
             if (q * e + k < N) a += wp[k] * x[q * e + k];
     }
     return a;
+}
+
+// acc[i] += a W[i], i < N, W read as 16-byte vectors
+template <typename T>
+__device__ __attribute__((always_inline)) inline void axpyw(const T *W, const T a, T *acc, const int N)
+{
+    using V = typename V16<T>::type;
+    constexpr int e = E<T>();
+#pragma unroll
+    for (int q = 0; q < (N + e - 1) / e; q++) {
+        const V w = ((const V *)W)[q];
+        const T *wp = (const T *)&w;
+#pragma unroll
+        for (int k = 0; k < e; k++)
+            if (q * e + k < N) acc[q * e + k] += a * wp[k];
+    }
 }
 
 // accumulator type of the LDS local expansions.  Shared mode: FP64 for both paths (LDS FP64
@@ -188,8 +217,9 @@ template <typename T, int P, bool OWN>
 constexpr size_t tile_bytes(int npar)
 {
     using Sh = Shape<T, P>;
-    return sizeof(T) * (wglobal<T, P>() ? 0 : 8 * (size_t)Sh::WHS) +
-           sizeof(Acc<T, OWN>) * (size_t)(8 * npar + 1) * acc_slot<T, P, OWN>() + sizeof(int) * 3 * 8 * npar +
+    const int nslot = half_tiles<T, P>() ? 4 : 8 * npar;
+    return sizeof(T) * (size_t)staged_tables<T, P>() * Sh::WHS +
+           sizeof(Acc<T, OWN>) * (size_t)(nslot + 1) * acc_slot<T, P, OWN>() + sizeof(int) * 3 * nslot +
            sizeof(int16_t) * (64 + (OWN ? 0 : 1512));
 }
 // two workgroups per compute unit (160 KB of LDS)
@@ -212,7 +242,14 @@ template <typename T, int P>
 constexpr int tile_npar()
 {
     return tile_own<T, P>() ? 4
-                            : tile_bytes<T, P, false>(4) <= LDS_HALF ? 4 : (tile_bytes<T, P, false>(2) <= LDS_HALF ? 2 : 1);
+           : half_tiles<T, P>() ? 1
+           : tile_bytes<T, P, false>(4) <= LDS_HALF ? 4 : (tile_bytes<T, P, false>(2) <= LDS_HALF ? 2 : 1);
+}
+// tiles of one level: NPAR sibling groups each, or half a sibling group each
+template <typename T, int P>
+constexpr int64_t n_tiles(int64_t npar)
+{
+    return half_tiles<T, P>() ? 2 * npar : (npar + tile_npar<T, P>() - 1) / tile_npar<T, P>();
 }
 
 }  // namespace hv
@@ -239,14 +276,16 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     using hv::S;
     constexpr int P2 = Sh::P2, NH = Sh::NH, NHP = Sh::NHP;
     constexpr int ARS = hv::acc_stride<T, P, OWN>().rs, SSTA = hv::acc_slot<T, P, OWN>();
-    constexpr int NSLOT = 8 * NPAR;
+    constexpr bool HT = hv::half_tiles<T, P>();       // half a sibling group per tile, forward tables only
+    constexpr bool GW = HT;                           // vectors fill the register file (see the coax)
+    constexpr int NSLOT = HT ? 4 : 8 * NPAR;
     constexpr int NENT = 1512;  // schedule entries of one sibling group
     extern __shared__ char smem[];
     using A = hv::Acc<T, OWN>;
     static_assert(!OWN || NPAR == 4, "ownership mode: one sibling group per wavefront");
-    constexpr bool GW = hv::wglobal<T, P>();          // rotation tables read from global memory
+    static_assert(!HT || (NPAR == 1 && !OWN), "half tiles: shared mode, one parent");
     T *Wl = (T *)smem;                                // [kind: fwd S, back R][part][parity][WHS]
-    A *acc = (A *)(Wl + (GW ? 0 : 8 * Sh::WHS));      // [NSLOT + 1][SSTA] (last slot absorbs)
+    A *acc = (A *)(Wl + hv::staged_tables<T, P>() * Sh::WHS);  // [NSLOT + 1][SSTA] (last slot absorbs)
     int *slot_xyz = (int *)(acc + (NSLOT + 1) * SSTA);  // [NSLOT] packed target coordinates, -1: no box
     int *slot_box = slot_xyz + NSLOT;                 // [NSLOT] target box
     int *slot_sys = slot_box + NSLOT;                 // [NSLOT] system of the target
@@ -255,17 +294,18 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // XCD-aware tile order: consecutive tiles stay on one XCD (shared L2)
-    const int64_t ntiles = (npar + NPAR - 1) / NPAR;
+    const int64_t ntiles = hv::n_tiles<T, P>(npar);
     const int64_t per = (ntiles + 7) / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= ntiles) return;
     const int ncls = sch.ncls;
+    const int hf = HT ? (int)(tile & 1) : 0;  // half tiles: children 4 hf .. 4 hf + 3
 
     int has_box = 0;
     if (tid < NSLOT) {
-        const int i = tid >> 3, c = tid & 7;
+        const int i = HT ? 0 : tid >> 3, c = HT ? 4 * hf + tid : tid & 7;
         int box = -1, xyz = -1, sys = 0;
-        const int64_t q = (int64_t)NPAR * tile + i;
+        const int64_t q = HT ? (tile >> 1) : (int64_t)NPAR * tile + i;
         if (q < npar) {
             const int64_t pb = poff + q;
             const int c0 = bchild0[pb], nc = bnchild[pb];
@@ -290,9 +330,29 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     }
     // a tile whose parents have no children (leaves of an adaptive tree) has nothing to do
     if (!__syncthreads_or(has_box)) return;
-    if (!OWN)
-        for (int i = tid; i < NENT; i += 256) ent[i] = (int16_t)((sch.ent_dir[i] << 3) | sch.ent_c[i]);
-    for (int i = tid; i <= ncls; i += 256) cst[i] = OWN ? sch.row_start[i] : sch.cls_start[i];
+    if constexpr (HT) {
+        // the class entries of this half, compacted per class: (dir << 3) | slot (child - 4 hf)
+        if (tid < ncls) {
+            int cnt = 0;
+            for (int e = sch.cls_start[tid]; e < sch.cls_start[tid + 1]; e++) cnt += (sch.ent_c[e] >> 2) == hf;
+            cst[tid + 1] = (int16_t)cnt;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            cst[0] = 0;
+            for (int k = 0; k < ncls; k++) cst[k + 1] = (int16_t)(cst[k] + cst[k + 1]);
+        }
+        __syncthreads();
+        if (tid < ncls) {
+            int o = cst[tid];
+            for (int e = sch.cls_start[tid]; e < sch.cls_start[tid + 1]; e++)
+                if ((sch.ent_c[e] >> 2) == hf) ent[o++] = (int16_t)((sch.ent_dir[e] << 3) | (sch.ent_c[e] & 3));
+        }
+    } else {
+        if (!OWN)
+            for (int i = tid; i < NENT; i += 256) ent[i] = (int16_t)((sch.ent_dir[i] << 3) | sch.ent_c[i]);
+        for (int i = tid; i <= ncls; i += 256) cst[i] = OWN ? sch.row_start[i] : sch.cls_start[i];
+    }
     __syncthreads();
     // local expansions of the targets into their slots (shared mode: the lane layout, whose
     // entries without an (n, m) start at zero and are never read back)
@@ -371,7 +431,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     // allow, a batch whose successor starts a new class loads the new tables into registers
     // first, so that they arrive during the batch and only the LDS write sits between the
     // two barriers of the class change
-    constexpr int N16 = (int)(8 * Sh::WHS * sizeof(T) / 16);
+    constexpr int N16 = (int)(hv::staged_tables<T, P>() * Sh::WHS * sizeof(T) / 16);
     constexpr bool PREF = hv::min_waves<T, P>() > 1;
     constexpr int NPF = PREF ? (N16 + 255) / 256 : 1;
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -382,27 +442,22 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         for (int q = 0; q < NPF; q++) pf[q] = src4[q * 256 + tid < N16 ? q * 256 + tid : 0];
     };
     int staged = -1, fetched = -1;
-    const T *Wcls = Wl;  // the current class's tables (LDS, or global memory when GW)
     while (k < ncls) {
-        if constexpr (GW) {
-            Wcls = wh + (size_t)cls_theta[k] * wstride;
-        } else {
-            if (k != staged) {
-                __syncthreads();
-                uint4 *dst4 = (uint4 *)Wl;
-                if constexpr (PREF) {
-                    if (fetched != k) fetch(k);
+        if (k != staged) {
+            __syncthreads();
+            uint4 *dst4 = (uint4 *)Wl;
+            if constexpr (PREF) {
+                if (fetched != k) fetch(k);
 #pragma unroll
-                    for (int q = 0; q < NPF; q++)
-                        if (tid + 256 * q < N16) ((u32x4 *)dst4)[tid + 256 * q] = pf[q];
-                } else {
-                    const uint4 *src4 = (const uint4 *)(wh + (size_t)cls_theta[k] * wstride);
+                for (int q = 0; q < NPF; q++)
+                    if (tid + 256 * q < N16) ((u32x4 *)dst4)[tid + 256 * q] = pf[q];
+            } else {
+                const uint4 *src4 = (const uint4 *)(wh + (size_t)cls_theta[k] * wstride);
 #pragma unroll 4
-                    for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
-                }
-                __syncthreads();
-                staged = k;
+                for (int i = tid; i < N16; i += 256) dst4[i] = src4[i];
             }
+            __syncthreads();
+            staged = k;
         }
         // ownership mode: the lane's role (parity, part, potential) is made opaque per batch, so
         // the compiler recomputes the per-lane constants derived from it instead of holding
@@ -411,8 +466,8 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         const int wo = (part * 2 + h) * Sh::WHS;
         int hh = h, pp = part, po = pot;
         if (OWN) asm volatile("" : "+v"(hh), "+v"(pp), "+v"(po));
-        const T *Wf = Wcls + wo;
-        const T *Wb = Wcls + 4 * Sh::WHS + wo;
+        const T *Wf = Wl + wo;
+        const T *Wb = Wl + (HT ? (pp * 2 + 1 - hh) * Sh::WHS : 4 * Sh::WHS + wo);  // HT: the partner's forward table
 
         const Job j = cur;
         const bool act = j.src >= 0;
@@ -420,7 +475,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         int k2 = k1, r2 = r1;
         advance(k2, r2);
         const Job nn = setup(k2, r2);
-        if constexpr (PREF && !GW) {
+        if constexpr (PREF) {
             if (k1 != k && k1 < ncls) {  // the next batch starts a new class
                 fetch(k1);
                 fetched = k1;
@@ -541,7 +596,38 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
                 if constexpr (sizeof(T) == 4 || hv::min_waves<T, P>() == 1) __builtin_amdgcn_sched_barrier(0);
             }
         }
-        rotate_y(Wb);
+        if constexpr (HT) {
+            // 5. back-rotation with the forward tables: v <- D W_fwd^T D^-1 v.  The lane's inputs
+            //    (m = 2j + h) scale by D^-1 and multiply rows j of its own table's o block (outputs of
+            //    its parity) and of the partner table's t block (outputs of the other parity); the
+            //    partner's partial sums arrive by the DPP pair swap, then D scales the outputs
+            const T sg = hh ? (T)-1 : (T)1;  // (-1)^m on this lane
+            const T fin = pp ? sg : (T)2 * sg, fout = pp ? sg : (T)0.5 * sg;
+#pragma unroll
+            for (int n = 0; n < P; n++) {
+                const T *Won = Wf + hv::woff<T>(n);
+                const T *Wpn = Wb + hv::woff<T>(n) + S(n) * hv::RL<T>(n);
+                constexpr int SM = P / 2 + 1;
+                T o[SM], tt[SM];
+#pragma unroll
+                for (int jj = 0; jj < S(n); jj++) {
+                    o[jj] = 0;
+                    tt[jj] = 0;
+                }
+#pragma unroll
+                for (int j = 0; j < S(n); j++) {
+                    // m = 0 (j = 0 on even lanes, Re part) is not doubled by D^-1
+                    const T xj = v[hoff(n) + j] * ((j == 0 && !hh && !pp) ? (T)1 : fin);
+                    hv::axpyw<T>(Won + j * hv::RL<T>(n), xj, o, S(n));
+                    hv::axpyw<T>(Wpn + j * hv::RL<T>(n), xj, tt, S(n));
+                }
+#pragma unroll
+                for (int jj = 0; jj < S(n); jj++)
+                    v[hoff(n) + jj] = (o[jj] + dpp_f<DPP_XOR1>(tt[jj])) * ((jj == 0 && !hh && !pp) ? (T)1 : fout);
+            }
+        } else {
+            rotate_y(Wb);
+        }
         // 6. back-rotation about z (-phi) and accumulation into the target slot (inactive lanes
         //    add into the spare slot; in ownership mode so do entries without an (n, m))
         {
@@ -966,7 +1052,7 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
     const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
     const int64_t soff = Pl->lev[level].off, nb = Pl->lev[level].nb;
     if (nb == 0 || npar == 0) return;
-    const int64_t ntiles = (npar + NPAR - 1) / NPAR;
+    const int64_t ntiles = hv::n_tiles<T, P>(npar);
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
     k_m2l_half<T, P, NPAR, OWN><<<dim3((unsigned)(per * 8)), dim3(256),
