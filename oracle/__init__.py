@@ -70,7 +70,9 @@ def lib():
         L.lho_num_threads.restype = C.c_int
         L.lho_fmm_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_void_p, C.c_double, C.c_int, C.c_int64, C.c_int,
                                        _dp, C.c_double, C.c_int, C.c_int64, C.c_void_p, _dp, _dp, C.c_void_p,
-                                       C.POINTER(_Stats)]
+                                       C.c_int, C.POINTER(_Stats)]
+        L.lho_p2l.argtypes = [C.c_int, _dp, C.c_int64, _dp, _dp, C.c_void_p, _cp, _cp]
+        L.lho_m2p.argtypes = [C.c_int, _dp, _cp, _cp, C.c_int64, _dp, _dp, _dp, _dp, C.c_void_p]
         L.lho_fmm_adaptive.restype = C.c_int
         L.lho_direct_adaptive.argtypes = [C.c_int64, _dp, _dp, C.c_void_p, C.c_double, C.c_int64, C.c_int, _dp,
                                           C.c_double, C.c_int64, C.c_void_p, _dp, _dp]
@@ -258,12 +260,36 @@ def tree_counts(x, depth, lo=(0.0, 0.0, 0.0), L=1.0):
     return nb, a.value, b.value
 
 
+def p2l(p, centre, x, w, q=None):
+    """local (phi, chi) expansion about centre of the field of elements outside its ball"""
+    x = _f64(x).reshape(-1, 3)
+    w = _f64(w).reshape(-1, 3)
+    phi = np.zeros(p * p, np.complex128)
+    chi = np.zeros(p * p, np.complex128)
+    qa, qp = _qptr(q, x.shape[0])
+    lib().lho_p2l(p, _f64(centre, (3,)), x.shape[0], x, w, qp, phi, chi)
+    return phi, chi
+
+
+def m2p(p, centre, phi, chi, y, w):
+    """v, s, grad v at targets y (strengths w) of a multipole expansion about centre"""
+    y = _f64(y).reshape(-1, 3)
+    w = _f64(w).reshape(-1, 3)
+    n = y.shape[0]
+    v = np.zeros((n, 3)); s = np.zeros((n, 3)); g = np.zeros((n, 9))
+    lib().lho_m2p(p, _f64(centre, (3,)), np.ascontiguousarray(phi, np.complex128),
+                  np.ascontiguousarray(chi, np.complex128), n, y, w, v, s, g.ctypes.data)
+    return v, s, g.reshape(n, 3, 3)
+
+
 def fmm_adaptive(x, w, a, p, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True,
-                 sample=None, grad=False, q=None):
+                 sample=None, grad=False, q=None, wx_expansions=False):
     """Adaptive-octree FMM (split while a box holds more than max_per_leaf elements, down to
     max_level); W/X interactions summed directly with the singular kernel.  With ``sample``
     only the leaves holding those elements are evaluated (other outputs NaN).  With ``grad``
-    also grad v ([N,3,3], [i,k,l] = d v_k / d x_l) is returned after s."""
+    also grad v ([N,3,3], [i,k,l] = d v_k / d x_l) is returned after s.  With ``wx_expansions``
+    the W boxes act by M2P and the X sources by P2L (both part of the far field) instead of
+    direct singular sums (near field); boxes above level 2 keep the direct sums."""
     x = _f64(x).reshape(-1, 3)
     w = _f64(w).reshape(-1, 3)
     n = x.shape[0]
@@ -278,7 +304,8 @@ def fmm_adaptive(x, w, a, p, max_per_leaf=64, max_level=10, lo=(0.0, 0.0, 0.0), 
     what = (1 if far else 0) | (2 if near else 0)
     qa, qp = _qptr(q, n)
     rc = lib().lho_fmm_adaptive(n, x, w, qp, float(a), int(p), int(max_per_leaf), int(max_level), _f64(lo, (3,)),
-                                float(L), what, ns, sp, v, s, g.ctypes.data if grad else None, C.byref(st))
+                                float(L), what, ns, sp, v, s, g.ctypes.data if grad else None,
+                                int(bool(wx_expansions)), C.byref(st))
     if rc != 0:
         raise ValueError("oracle adaptive fmm rejected its arguments")
     if sample is not None:

@@ -669,6 +669,62 @@ void lho_l2p(int p, const double centre[3], const cplx *phi, const cplx *chi, in
     }
 }
 
+/* P2L: local (R-basis) expansion about centre of the field of elements (x, w, q) lying
+ * outside its ball.  Defined as the translation (M2L with the R-basis conversion, reading B)
+ * of each element's own multipole expansion about its position: an element at the centre of
+ * its expansion has no truncation error (orders n <= 1 only), so the local coefficients of
+ * orders n <= p-1 are exact.  ADDED into (phi, chi). */
+void lho_p2l(int p, const double centre[3], int64_t n, const double *x, const double *w, const double *q,
+             cplx *phi, cplx *chi)
+{
+    size_t P2 = (size_t)p * p;
+    cplx *mp = (cplx *)malloc(sizeof(cplx) * P2), *mc = (cplx *)malloc(sizeof(cplx) * P2);
+    for (int64_t l = 0; l < n; l++) {
+        memset(mp, 0, sizeof(cplx) * P2);
+        memset(mc, 0, sizeof(cplx) * P2);
+        lho_p2m_method2(p, &x[3 * l], 1, &x[3 * l], &w[3 * l], q ? &q[l] : NULL, mp, mc);
+        double t[3] = {centre[0] - x[3 * l], centre[1] - x[3 * l + 1], centre[2] - x[3 * l + 2]};
+        lho_m2l(p, t, mp, mc, phi, chi);
+    }
+    free(mp);
+    free(mc);
+}
+
+/* M2P: the field of a multipole expansion (phi, chi) about centre (p orders) at target
+ * points y outside its ball: v, s = (w_j . grad) v (w: strengths at the targets) and, if g is
+ * not NULL, grad v (row = component, column = derivative).  Defined as the translation of the
+ * expansion to a local expansion about the target itself (M2L, at least three orders so that
+ * the orders n <= 2 the evaluation needs are formed) evaluated at its centre (L2P at r = 0):
+ * the exact field of the truncated multipole expansion.  ADDED into v, s, g. */
+void lho_m2p(int p, const double centre[3], const cplx *phi, const cplx *chi, int64_t n, const double *y,
+             const double *w, double *v, double *s, double *g)
+{
+    int pl = p < 3 ? 3 : p;
+    size_t PL2 = (size_t)pl * pl, P2 = (size_t)p * p;
+    cplx *ip = (cplx *)calloc(PL2, sizeof(cplx)), *ic = (cplx *)calloc(PL2, sizeof(cplx));
+    cplx *lp = (cplx *)malloc(sizeof(cplx) * PL2), *lc = (cplx *)malloc(sizeof(cplx) * PL2);
+    memcpy(ip, phi, sizeof(cplx) * P2);
+    memcpy(ic, chi, sizeof(cplx) * P2);
+    for (int64_t j = 0; j < n; j++) {
+        memset(lp, 0, sizeof(cplx) * PL2);
+        memset(lc, 0, sizeof(cplx) * PL2);
+        double t[3] = {y[3 * j] - centre[0], y[3 * j + 1] - centre[1], y[3 * j + 2] - centre[2]};
+        lho_m2l(pl, t, ip, ic, lp, lc);
+        double vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gg[9] = {0};
+        lho_l2p(pl, &y[3 * j], lp, lc, 1, &y[3 * j], &w[3 * j], vv, ss, gg, NULL, NULL);
+        for (int k = 0; k < 3; k++) {
+            v[3 * j + k] += vv[k];
+            s[3 * j + k] += ss[k];
+        }
+        if (g)
+            for (int k = 0; k < 9; k++) g[9 * j + k] += gg[k];
+    }
+    free(ip);
+    free(ic);
+    free(lp);
+    free(lc);
+}
+
 /* ------------------------------------------------------------------------- */
 /* (A) direct sums                                                            */
 /* ------------------------------------------------------------------------- */
@@ -1351,7 +1407,7 @@ static int64_t box_direct(const atree *A, const double *x, const double *w, cons
  * maxleaf >= 0, 1 <= maxl <= 10.  Returns 0 on success. */
 int lho_fmm_adaptive(int64_t n, const double *x, const double *w, const double *qm, double a, int p,
                      int64_t maxleaf, int maxl, const double lo[3], double L, int what, int64_t nsample,
-                     const int64_t *sample, double *v, double *s, double *gv, lho_stats *st)
+                     const int64_t *sample, double *v, double *s, double *gv, int wx_mode, lho_stats *st)
 {
     if (maxl < 1 || maxl > 10 || p < 1 || n < 1 || maxleaf < 0) return -1;
     double t0 = wtime();
@@ -1480,6 +1536,36 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, const double *
             }
         }
         stats.n_m2l = nm2l;
+        /* wx_mode 1: the X interactions of a wanted leaf and of its ancestors at levels >= 2 enter
+         * the leaf's local expansion by P2L (an ancestor's X source is at least as well separated
+         * from the leaf as from the ancestor) */
+        if (wx_mode)
+            for (int l = 2; l <= maxl; l++) {
+#pragma omp parallel for schedule(dynamic, 1)
+                for (int64_t b = 0; b < T->nb[l]; b++) {
+                    if (!want[l][b]) continue;
+                    double ct[3];
+                    box_centre(T, l, T->key[l][b], ct);
+                    cplx *ph = &Lc[l][(size_t)b * 2 * P2], *ch = ph + P2;
+                    blist X = {0};
+                    for (int la = l; la >= 2; la--) {
+                        int64_t ab = tree_find(T, la, T->key[l][b] >> (3 * (l - la)));
+                        list_X(&A, la, ab, &X);
+                    }
+                    for (int64_t qq = 0; qq < X.n; qq++) {
+                        int64_t c = T->count[X.lev[qq]][X.box[qq]];
+                        double *bx = (double *)malloc(sizeof(double) * 3 * (size_t)c);
+                        double *bw = (double *)malloc(sizeof(double) * 3 * (size_t)c);
+                        double *bq = (double *)malloc(sizeof(double) * (size_t)c);
+                        box_points(T, x, w, qm, X.lev[qq], X.box[qq], bx, bw, bq);
+                        lho_p2l(p, ct, c, bx, bw, qm ? bq : NULL, ph, ch);
+                        free(bx);
+                        free(bw);
+                        free(bq);
+                    }
+                    blist_free(&X);
+                }
+            }
         /* L2P at the wanted leaves of levels >= 2 */
         for (int l = 2; l <= maxl; l++) {
 #pragma omp parallel
@@ -1520,6 +1606,41 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, const double *
                 free(bx); free(bw); free(bv); free(bs); free(bg);
             }
         }
+        /* wx_mode 1: the W boxes (levels >= 2) of a wanted leaf act by M2P of their multipoles */
+        if (wx_mode)
+            for (int l = 0; l <= maxl; l++) {
+#pragma omp parallel for schedule(dynamic, 1)
+                for (int64_t b = 0; b < T->nb[l]; b++) {
+                    if (!want[l][b]) continue;
+                    blist W = {0};
+                    list_W(&A, l, b, &W);
+                    int64_t c = T->count[l][b];
+                    double *bx = (double *)malloc(sizeof(double) * 3 * (size_t)c);
+                    double *bw = (double *)malloc(sizeof(double) * 3 * (size_t)c);
+                    double *bv = (double *)calloc(3 * (size_t)c, sizeof(double));
+                    double *bs = (double *)calloc(3 * (size_t)c, sizeof(double));
+                    double *bg = (double *)calloc(9 * (size_t)c, sizeof(double));
+                    box_points(T, x, w, NULL, l, b, bx, bw, NULL);
+                    for (int64_t qq = 0; qq < W.n; qq++) {
+                        if (W.lev[qq] < 2) continue;  /* no multipole: summed directly below */
+                        double cs[3];
+                        box_centre(T, W.lev[qq], T->key[W.lev[qq]][W.box[qq]], cs);
+                        const cplx *mph = &M[W.lev[qq]][(size_t)W.box[qq] * 2 * P2];
+                        lho_m2p(p, cs, mph, mph + P2, c, bx, bw, bv, bs, bg);
+                    }
+                    for (int64_t i = 0; i < c; i++) {
+                        int64_t e = T->order[T->first[l][b] + i];
+                        for (int d = 0; d < 3; d++) {
+                            v[3 * e + d] += bv[3 * i + d];
+                            s[3 * e + d] += bs[3 * i + d];
+                        }
+                        if (gv)
+                            for (int d = 0; d < 9; d++) gv[9 * e + d] += bg[9 * i + d];
+                    }
+                    free(bx); free(bw); free(bv); free(bs); free(bg);
+                    blist_free(&W);
+                }
+            }
         for (int l = 2; l <= maxl; l++) {
             free(M[l]);
             free(Lc[l]);
@@ -1538,8 +1659,15 @@ int lho_fmm_adaptive(int64_t n, const double *x, const double *w, const double *
                 if (!want[l][b]) continue;
                 blist U = {0}, WX = {0};
                 list_U(&A, l, b, &U);
-                list_W(&A, l, b, &WX);
+                {
+                    blist Wb = {0};
+                    list_W(&A, l, b, &Wb);
+                    for (int64_t qq = 0; qq < Wb.n; qq++)  /* wx_mode 1: levels >= 2 by M2P */
+                        if (!wx_mode || Wb.lev[qq] < 2) blist_push(&WX, Wb.lev[qq], Wb.box[qq]);
+                    blist_free(&Wb);
+                }
                 for (int la = l; la >= 0; la--) {
+                    if (wx_mode && l >= 2 && la >= 2) continue;  /* by P2L into the leaf's local expansion */
                     int64_t ab = tree_find(T, la, T->key[l][b] >> (3 * (l - la)));
                     list_X(&A, la, ab, &WX);
                 }
