@@ -112,7 +112,7 @@ def measured_traffic(name):
     import hashlib
     import re
     try:
-        md = open(os.path.join(ROOT, "profiles", "m2l_hbm.md")).read()
+        md = open(os.path.join(ROOT, "profiles", f"m2l_{name}_hbm.md")).read()
         js = json.loads(re.search(r"```json\n(.*?)\n```", md, re.S).group(1))[name]
         src = open(os.path.join(ROOT, "paper_1201_5430_amd", "csrc", js["source"]), "rb").read()
         if hashlib.sha256(src).hexdigest()[:16] != js["source_sha256_prefix"]:
