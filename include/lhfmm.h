@@ -76,6 +76,15 @@ typedef enum { LHF_FP64 = 0, LHF_FP32 = 1 } lhf_precision;
                                   slower M2L kernel) */
 #define LHF_OUT_GRAD 0x4u      /* the plan keeps room for the velocity gradient: lhf_execute may then
                                   be given a grad_v output */
+#define LHF_WX_EXPANSIONS 0x8u /* adaptive tree: the W-list boxes of a leaf (levels >= 2) act on its
+                                  elements through their multipole expansions (M2P), and the
+                                  elements of its X-list leaves, and of its ancestors' X-lists,
+                                  enter its local expansion (P2L) before L2P, instead of the
+                                  singular direct sums over those pairs (Carrier, Greengard and
+                                  Rokhlin's W/X treatment with the (phi, chi) operators of App. A,
+                                  eqs. dt3 and drt5-drt7).  Adds the truncation error of order p to
+                                  those pairs; pays off where W boxes hold many more elements than
+                                  the leaves they act on.  No effect on a uniform tree. */
 
 /* translation scheme (lhf_desc.translation) */
 #define LHF_TRANS_RCR 0        /* rotation - coaxial shift - back-rotation with the conversion
@@ -111,7 +120,7 @@ typedef struct {
     double domain_lo[3];  /* cube origin */
     double domain_len;    /* cube side, > 0 (every element must lie in the cube) */
     int32_t precision;    /* lhf_precision */
-    uint32_t flags;       /* LHF_SINGULAR | LHF_DETERMINISTIC | LHF_OUT_GRAD */
+    uint32_t flags;       /* LHF_SINGULAR | LHF_DETERMINISTIC | LHF_OUT_GRAD | LHF_WX_EXPANSIONS */
     int32_t translation;  /* LHF_TRANS_RCR */
     int32_t m2l_kernel;   /* LHF_M2L_* */
     int32_t mm_kernel;    /* LHF_MM_* */
@@ -128,8 +137,8 @@ typedef struct {
     int32_t n_theta_classes;   /* distinct polar angles of the translation directions */
     int32_t max_level;         /* deepest level holding a box */
     int64_t n_leaves;          /* leaf boxes */
-    int64_t n_wx_pairs;        /* adaptive tree: element pairs of W/X interactions, summed directly
-                                  with the singular kernel (ordered) */
+    int64_t n_wx_pairs;        /* adaptive tree: element pairs of W/X interactions summed directly
+                                  with the singular kernel (ordered; those not taken by M2P / P2L) */
     int32_t m2l_kernel;        /* the M2L kernel the plan runs (LHF_M2L_*, never AUTO) */
     int32_t mm_kernel;         /* the M2M/L2L kernel (LHF_MM_HALF or LHF_MM_GENERIC) */
     int32_t deterministic;     /* 1 if every kernel of the plan accumulates in a fixed order */
@@ -138,7 +147,9 @@ typedef struct {
     double calib_err_s;        /*   input class (uniform / adaptive tree), FP64 arithmetic */
     int32_t warnings;          /* bit 0: LHF_WARN_CORE_SPLIT applies, bit 1: LHF_WARN_TOL_UNMET applies
                                   (a creation status carries one of them: TOL_UNMET first) */
-    int32_t reserved;
+    int32_t wx_expansions;     /* 1 if the adaptive plan treats W/X by M2P / P2L (LHF_WX_EXPANSIONS) */
+    int64_t n_m2p;             /* (W box, target element) pairs evaluated by M2P */
+    int64_t n_p2l;             /* (source element, target leaf) pairs expanded by P2L */
 } lhf_stats;
 
 /* Fill *d with the defaults: p = 12, tol = 1e-6, depth = 4, cube [0,1]^3, FP64, RCR, AUTO kernels. */

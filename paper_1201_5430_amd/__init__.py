@@ -20,7 +20,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblhfmm.so")
 
 FP64, FP32 = 0, 1
-LHF_SINGULAR, LHF_DETERMINISTIC, LHF_OUT_GRAD = 0x1, 0x2, 0x4
+LHF_SINGULAR, LHF_DETERMINISTIC, LHF_OUT_GRAD, LHF_WX_EXPANSIONS = 0x1, 0x2, 0x4, 0x8
 TRANS_RCR, TRANS_DIRECT = 0, 1
 M2L_AUTO, M2L_HALF, M2L_TILE, M2L_TILE1, M2L_MFMA, M2L_GENERIC = range(6)
 MM_AUTO, MM_HALF, MM_GENERIC = range(3)
@@ -56,7 +56,8 @@ class Stats(C.Structure):
                 ("n_theta_classes", C.c_int32), ("max_level", C.c_int32), ("n_leaves", C.c_int64),
                 ("n_wx_pairs", C.c_int64), ("m2l_kernel", C.c_int32), ("mm_kernel", C.c_int32),
                 ("deterministic", C.c_int32), ("p_from_tol", C.c_int32), ("calib_err_v", C.c_double),
-                ("calib_err_s", C.c_double), ("warnings", C.c_int32), ("reserved", C.c_int32)]
+                ("calib_err_s", C.c_double), ("warnings", C.c_int32), ("wx_expansions", C.c_int32),
+                ("n_m2p", C.c_int64), ("n_p2l", C.c_int64)]
 
 
 class Tune(C.Structure):
@@ -188,16 +189,18 @@ class Plan:
     ``max_per_leaf`` > 0 the octree is adaptive and ``depth`` its deepest level.
     ``p = 0`` chooses the order from ``tol``; ``grad`` keeps room for the velocity
     gradient; ``deterministic`` makes repeated executes bitwise identical;
-    ``m2l_kernel`` / ``mm_kernel`` force a kernel (M2L_* / MM_* constants)."""
+    ``m2l_kernel`` / ``mm_kernel`` force a kernel (M2L_* / MM_* constants); ``wx_expansions``
+    (adaptive tree) treats the W and X lists by M2P and P2L instead of direct sums."""
 
     def __init__(self, x, a, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6, flags=0,
                  offsets=None, max_per_leaf=0, grad=False, deterministic=False, m2l_kernel=M2L_AUTO,
-                 mm_kernel=MM_AUTO, translation=TRANS_RCR):
+                 mm_kernel=MM_AUTO, translation=TRANS_RCR, wx_expansions=False):
         import torch
         self.dtype = torch.float64 if precision == FP64 else torch.float32
         x = _dev_array(x, self.dtype, "x")
         self.n = x.shape[0]
-        flags = int(flags) | (LHF_OUT_GRAD if grad else 0) | (LHF_DETERMINISTIC if deterministic else 0)
+        flags = (int(flags) | (LHF_OUT_GRAD if grad else 0) | (LHF_DETERMINISTIC if deterministic else 0)
+                 | (LHF_WX_EXPANSIONS if wx_expansions else 0))
         self.desc = make_desc(p, depth, precision, lo if offsets is None else (0.0, 0.0, 0.0),
                               L if offsets is None else 1.0, tol, flags, max_per_leaf, m2l_kernel, mm_kernel,
                               translation)
@@ -258,7 +261,7 @@ class Plan:
                     n_wx_pairs=st.n_wx_pairs, m2l_kernel=M2L_NAMES[st.m2l_kernel],
                     mm_kernel=("auto", "half", "generic")[st.mm_kernel], deterministic=bool(st.deterministic),
                     p_from_tol=bool(st.p_from_tol), calib_err_v=st.calib_err_v, calib_err_s=st.calib_err_s,
-                    warnings=st.warnings)
+                    warnings=st.warnings, wx_expansions=bool(st.wx_expansions), n_m2p=st.n_m2p, n_p2l=st.n_p2l)
 
     def profile_begin(self, max_exec):
         _check(load().lhf_profile_begin(self._h, int(max_exec)))

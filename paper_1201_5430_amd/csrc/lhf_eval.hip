@@ -704,6 +704,332 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
 }
 
 // ---------------------------------------------------------------------------
+// W/X interactions by expansions (adaptive tree, LHF_WX_EXPANSIONS).
+//
+// Scaled S basis: St_n^m(x) = (n-m)! P_n^m(cos theta) e^{i m phi} / r^(n+1) (Condon-Shortley
+// P_n^m), St_n^{-m} = (-1)^m conj(St_n^m); S_n^m = (-i)^m St_n^m.  Column m by
+//   St_0^0 = 1/r,  St_m^m = -(2m-1)(x+iy)/r^2 St_{m-1}^{m-1},  St_{m+1}^m = (2m+1) z/r^2 St_m^m,
+//   St_n^m = ((2n-1) z St_{n-1}^m - (n+m-1)(n-m-1) St_{n-2}^m) / r^2.
+// In these functions the paper's derivative relations (eq. mr4) and the rotational operator in
+// the S basis (eq. drt5) read
+//   d_x St_n^m = (St_{n+1}^{m+1} - St_{n+1}^{m-1})/2,  d_y St_n^m = (St_{n+1}^{m+1} + St_{n+1}^{m-1})/(2i),
+//   d_z St_n^m = -St_{n+1}^m,
+//   D_{r x t} St_n^m = -i/2 [(t_x + i t_y)(n+m) St_n^{m-1} + (t_x - i t_y)(n-m) St_n^{m+1}] - i t_z m St_n^m,
+// and in the local basis Rt (R_n^m = (-1)^n i^m Rt_n^m; eqs. dt2 and drt4)
+//   D_t Rt_n^m = (t_x - i t_y)/2 Rt_{n-1}^{m+1} - (t_x + i t_y)/2 Rt_{n-1}^{m-1} + t_z Rt_{n-1}^m,
+//   D_{r x t} Rt_n^m = -i/2 [(t_x + i t_y)(n-m+1) Rt_n^{m-1} + (t_x - i t_y)(n+m+1) Rt_n^{m+1}] - i t_z m Rt_n^m.
+// ---------------------------------------------------------------------------
+
+// P2L: one wavefront per leaf b (level >= 2) with X sources.  In the leaf's scaled frame
+// (xhat = (x - c)/h) the potential of a unit source is 1/|yhat - xhat| = sum Rt_n^m(yhat) U_n^m,
+// U_n^m = conj(St_n^m(xhat)).  Its field grad U x omega - q grad U is the Lamb-Helmholtz pair
+//   Phi_n = -[D_{r x omega} U]_n / n - q U_n,   Chi_n = [D_omega U]_n / (n+1)
+// (Phi from r . v, Chi from curl v: both sides are harmonic and homogeneous order by order),
+// so the leaf's stored local coefficients gain c_n^m += (-1)^n Phi_n^m / h and
+// d_n^m += (-1)^n Chi_n^m / h (the bar form: c = i^m phi h^n, d = i^m chi h^(n+1)).
+// Elements in chunks of ch: the lanes first form the St columns of the chunk in LDS, then every
+// lane adds the chunk's contributions to its coefficient rows.  Runs after the downward pass
+// and before L2P; only the leaf's own wavefront writes its local expansion.
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_p2l(int p, const int32_t *__restrict__ leaves,
+                                              const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
+                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
+                                              const int32_t *__restrict__ wx_start, const int32_t *__restrict__ wx_ent,
+                                              const T *__restrict__ xs, const T *__restrict__ ws,
+                                              const T *__restrict__ qs, int64_t n, const double *__restrict__ sys_geo,
+                                              T *__restrict__ Lc, int ch)
+{
+    extern __shared__ char smem[];
+    const int P1 = p + 1, SS = P1 * P1, P2 = p * p;
+    T *Sre = (T *)smem;               // [ch][n <= p][m <= n]
+    T *Sim = Sre + (size_t)ch * SS;
+    T *wsh = Sim + (size_t)ch * SS;   // [ch][4]: omega, q
+    const int lane = threadIdx.x;
+    const int64_t li = blockIdx.x;
+    const int b = leaves[li];
+    const int level = blev[b];
+    const int ea = wx_start[li], eb = wx_start[li + 1];
+    int anyx = 0;
+    for (int e = ea + lane; e < eb; e += WAVE) anyx |= wx_ent[e] & 1;
+    if (level < 2 || !__syncthreads_or(anyx)) return;
+    double c0, c1, c2, hd;
+    box_centre(bkey[b], level, sys_geo, c0, c1, c2, hd);
+    const T ih = (T)(1.0 / hd);
+    T acc[NRMAX];
+#pragma unroll
+    for (int k = 0; k < NRMAX; k++) acc[k] = 0;
+    for (int e = ea; e < eb; e++) {
+        const int code = wx_ent[e];
+        if (!(code & 1)) continue;
+        const int q = code >> 1, s0 = bstart[q], cnt = bcount[q];
+        for (int e0 = 0; e0 < cnt; e0 += ch) {
+            const int ne = min(ch, cnt - e0);
+            __syncthreads();  // the previous chunk's columns are no longer read
+            for (int t = lane; t < ne * P1; t += WAVE) {
+                const int el = t / P1, m = t - el * P1;
+                const int i = s0 + e0 + el;
+                const T x = (xs[i] - (T)c0) * ih, y = (xs[n + i] - (T)c1) * ih, z = (xs[2 * n + i] - (T)c2) * ih;
+                const T ir2 = (T)1 / (x * x + y * y + z * z);
+                T are = sqrt(ir2), aim = 0;  // St_0^0 = 1/r, then up the diagonal to St_m^m
+                for (int k = 1; k <= m; k++) {
+                    const T f = -(T)(2 * k - 1) * ir2;
+                    const T nre = f * (are * x - aim * y), nim = f * (are * y + aim * x);
+                    are = nre;
+                    aim = nim;
+                }
+                T *Re = Sre + (size_t)el * SS, *Im = Sim + (size_t)el * SS;
+                Re[m * P1 + m] = are;
+                Im[m * P1 + m] = aim;
+                T p2re = 0, p2im = 0, p1re = are, p1im = aim;
+                for (int nn = m + 1; nn <= p; nn++) {
+                    const T a1 = (T)(2 * nn - 1) * z * ir2, a2 = (T)((nn + m - 1) * (nn - m - 1)) * ir2;
+                    const T cre = a1 * p1re - a2 * p2re, cim = a1 * p1im - a2 * p2im;
+                    Re[nn * P1 + m] = cre;
+                    Im[nn * P1 + m] = cim;
+                    p2re = p1re;
+                    p2im = p1im;
+                    p1re = cre;
+                    p1im = cim;
+                }
+                if (m == 0) {
+                    wsh[4 * el] = ws[i];
+                    wsh[4 * el + 1] = ws[n + i];
+                    wsh[4 * el + 2] = ws[2 * n + i];
+                    wsh[4 * el + 3] = qs ? qs[i] : (T)0;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NRMAX; k++) {
+                const int r = lane + WAVE * k;
+                if (r >= 2 * P2) break;
+                const int pot = r >= P2;
+                int nn, m, part;
+                decode_row(r - pot * P2, nn, m, part);
+                const T sgn = (nn & 1) ? (T)-1 : (T)1;
+                for (int el = 0; el < ne; el++) {
+                    const T *Re = Sre + (size_t)el * SS, *Im = Sim + (size_t)el * SS;
+                    const T wx = wsh[4 * el], wy = wsh[4 * el + 1], wz = wsh[4 * el + 2], qe = wsh[4 * el + 3];
+                    // U_n2^kk = conj(St_n2^kk); U_n2^{-1} = -conj(U_n2^1) = -St_n2^1
+                    auto U = [&](int n2, int kk, T &re, T &im) {
+                        if (n2 < 0 || n2 > p || kk > n2) {
+                            re = 0;
+                            im = 0;
+                        } else if (kk == -1) {
+                            re = n2 >= 1 ? -Re[n2 * P1 + 1] : (T)0;
+                            im = n2 >= 1 ? -Im[n2 * P1 + 1] : (T)0;
+                        } else {
+                            re = Re[n2 * P1 + kk];
+                            im = -Im[n2 * P1 + kk];
+                        }
+                    };
+                    T vre, vim;
+                    if (pot == 0) {
+                        // Phi = -D/n - q U, D = -(i/2)[(wx+iwy)(n-m) U^{m+1} + (wx-iwy)(n+m) U^{m-1}] - i wz m U^m
+                        T upr, upi, umr, umi, u0r, u0i;
+                        U(nn, m + 1, upr, upi);
+                        U(nn, m - 1, umr, umi);
+                        U(nn, m, u0r, u0i);
+                        const T fa = (T)(nn - m), fb = (T)(nn + m);
+                        const T xr = fa * (wx * upr - wy * upi) + fb * (wx * umr + wy * umi);
+                        const T xi = fa * (wx * upi + wy * upr) + fb * (wx * umi - wy * umr);
+                        const T dre = (T)0.5 * xi + wz * (T)m * u0i;
+                        const T dim = (T)-0.5 * xr - wz * (T)m * u0r;
+                        const T inv = nn > 0 ? (T)1 / (T)nn : (T)0;
+                        vre = -dre * inv - qe * u0r;
+                        vim = -dim * inv - qe * u0i;
+                    } else {
+                        // Chi = [1/2 (wx-iwy) U_{n+1}^{m-1} - 1/2 (wx+iwy) U_{n+1}^{m+1} + wz U_{n+1}^m] / (n+1)
+                        T umr, umi, upr, upi, u0r, u0i;
+                        U(nn + 1, m - 1, umr, umi);
+                        U(nn + 1, m + 1, upr, upi);
+                        U(nn + 1, m, u0r, u0i);
+                        const T inv = (T)1 / (T)(nn + 1);
+                        vre = ((T)0.5 * (wx * umr + wy * umi) - (T)0.5 * (wx * upr - wy * upi) + wz * u0r) * inv;
+                        vim = ((T)0.5 * (wx * umi - wy * umr) - (T)0.5 * (wx * upi + wy * upr) + wz * u0i) * inv;
+                    }
+                    acc[k] += sgn * (part ? vim : vre);
+                }
+            }
+        }
+    }
+    T *out = Lc + (size_t)b * 2 * P2;
+#pragma unroll
+    for (int k = 0; k < NRMAX; k++) {
+        const int r = lane + WAVE * k;
+        if (r >= 2 * P2) break;
+        out[r] += acc[k] * ih;
+    }
+}
+
+// M2P: one wavefront per leaf with W boxes, a lane per target element.  For each W box q
+// (centre c, side h) the velocity coefficients of its multipole in the St basis,
+//   V_x = (A_{N-1}^{M-1} - A_{N-1}^{M+1})/2 - i/2 [(N+M+1) B_N^{M+1} + (N-M+1) B_N^{M-1}]
+//   V_y = -i/2 (A_{N-1}^{M-1} + A_{N-1}^{M+1}) + 1/2 [(N+M+1) B_N^{M+1} - (N-M+1) B_N^{M-1}]
+//   V_z = -A_{N-1}^M - i M B_N^M,     A = (-1)^m a, B = (-1)^m b  (a, b: the stored bar form)
+// (v = grad phi + grad chi x r, eq. evf3's S-basis counterpart), are formed in LDS for N <= p;
+// each lane evaluates v = sum V_N^M St_N^M(yhat)/h and grad v from the derivative relations
+// at N + 1 (/h^2), yhat = (y - c)/h, and adds them (and s = grad v . omega) to the far field
+// that L2P wrote.
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_m2p(int p, const int32_t *__restrict__ leaves,
+                                              const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
+                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
+                                              const int32_t *__restrict__ wx_start, const int32_t *__restrict__ wx_ent,
+                                              const T *__restrict__ xs, const T *__restrict__ ws, int64_t n,
+                                              const double *__restrict__ sys_geo, const T *__restrict__ M,
+                                              T *__restrict__ vfar, int grad)
+{
+    extern __shared__ char smem[];
+    const int P2 = p * p, TRI = (p + 1) * (p + 2) / 2;  // (N, M >= 0), N <= p
+    T *Vre = (T *)smem, *Vim = Vre + 3 * TRI;           // [3][TRI]
+    const int lane = threadIdx.x;
+    const int64_t li = blockIdx.x;
+    const int b = leaves[li];
+    const int ea = wx_start[li], eb = wx_start[li + 1];
+    int anyw = 0;
+    for (int e = ea + lane; e < eb; e += WAVE) anyw |= !(wx_ent[e] & 1);
+    if (!__syncthreads_or(anyw)) return;
+    const int s0 = bstart[b], cnt = bcount[b];
+    auto vget = [&](int k, int nn, int m, T &re, T &im) {
+        if (nn < 0 || nn > p || m > nn) {
+            re = 0;
+            im = 0;
+        } else if (m == -1) {  // V^{-1} = -conj(V^1)
+            const int t = nn * (nn + 1) / 2 + 1;
+            re = nn >= 1 ? -Vre[k * TRI + t] : (T)0;
+            im = nn >= 1 ? Vim[k * TRI + t] : (T)0;
+        } else {
+            const int t = nn * (nn + 1) / 2 + m;
+            re = Vre[k * TRI + t];
+            im = Vim[k * TRI + t];
+        }
+    };
+    for (int tb = 0; tb < cnt; tb += WAVE) {
+        const int e = tb + lane;
+        const bool act = e < cnt;
+        const int i = s0 + (act ? e : 0);
+        const T yx = xs[i], yy = xs[n + i], yz = xs[2 * n + i];
+        L2PAcc<T> v[3], g[9];
+        for (int en = ea; en < eb; en++) {
+            const int code = wx_ent[en];
+            if (code & 1) continue;
+            const int q = code >> 1, lq = blev[q];
+            const T *ab = M + (size_t)q * 2 * P2;
+            __syncthreads();  // the previous box's coefficients are no longer read
+            for (int t = lane; t < TRI; t += WAVE) {
+                int nn = 0;
+                while ((nn + 1) * (nn + 2) / 2 <= t) nn++;
+                const int m = t - nn * (nn + 1) / 2;
+                // A_n^k (pot 0) or B_n^k (pot 1) = (-1)^k (stored a or b); k = -1: -conj(X^1)
+                auto X = [&](int pot, int n2, int kk, T &re, T &im) {
+                    if (n2 < 0 || n2 >= p || kk > n2 || (kk == -1 && n2 < 1)) {
+                        re = 0;
+                        im = 0;
+                        return;
+                    }
+                    const T *c = ab + pot * P2;
+                    const int ka = kk < 0 ? 1 : kk;
+                    T r = c[pk_re(n2, ka)], s = ka ? c[pk_im(n2, ka)] : (T)0;
+                    if (ka & 1) {
+                        r = -r;
+                        s = -s;
+                    }
+                    if (kk < 0) {
+                        re = -r;
+                        im = s;
+                    } else {
+                        re = r;
+                        im = s;
+                    }
+                };
+                T amr, ami, apr, api, a0r, a0i, bmr, bmi, bpr, bpi, b0r, b0i;
+                X(0, nn - 1, m - 1, amr, ami);
+                X(0, nn - 1, m + 1, apr, api);
+                X(0, nn - 1, m, a0r, a0i);
+                X(1, nn, m - 1, bmr, bmi);
+                X(1, nn, m + 1, bpr, bpi);
+                X(1, nn, m, b0r, b0i);
+                const T fp = (T)(nn + m + 1), fm = (T)(nn - m + 1);
+                // V_x = (A- - A+)/2 - i/2 (fp B+ + fm B-)
+                Vre[t] = (T)0.5 * (amr - apr) + (T)0.5 * (fp * bpi + fm * bmi);
+                Vim[t] = (T)0.5 * (ami - api) - (T)0.5 * (fp * bpr + fm * bmr);
+                // V_y = -i/2 (A- + A+) + 1/2 (fp B+ - fm B-)
+                Vre[TRI + t] = (T)0.5 * (ami + api) + (T)0.5 * (fp * bpr - fm * bmr);
+                Vim[TRI + t] = (T)-0.5 * (amr + apr) + (T)0.5 * (fp * bpi - fm * bmi);
+                // V_z = -A0 - i m B0
+                Vre[2 * TRI + t] = -a0r + (T)m * b0i;
+                Vim[2 * TRI + t] = -a0i - (T)m * b0r;
+            }
+            __syncthreads();
+            double c0, c1, c2, hd;
+            box_centre(bkey[q], lq, sys_geo, c0, c1, c2, hd);
+            const T ihq = (T)(1.0 / hd);
+            const T x = (yx - (T)c0) * ihq, y = (yy - (T)c1) * ihq, z = (yz - (T)c2) * ihq;
+            const T ir2 = (T)1 / (x * x + y * y + z * z);
+            L2PAcc<T> vl[3], gl[9];
+            T mre = sqrt(ir2), mim = 0;  // St_m^m
+            for (int m = 0; m <= p + 1; m++) {
+                if (m > 0) {
+                    const T f = -(T)(2 * m - 1) * ir2;
+                    const T nre = f * (mre * x - mim * y), nim = f * (mre * y + mim * x);
+                    mre = nre;
+                    mim = nim;
+                }
+                const T wgt = m ? (T)2 : (T)1;
+                T p1re = mre, p1im = mim, p2re = 0, p2im = 0;
+                for (int nn = m; nn <= p + 1; nn++) {
+                    T sre, sim;
+                    if (nn == m) {
+                        sre = mre;
+                        sim = mim;
+                    } else {
+                        const T a1 = (T)(2 * nn - 1) * z * ir2, a2 = (T)((nn + m - 1) * (nn - m - 1)) * ir2;
+                        sre = a1 * p1re - a2 * p2re;
+                        sim = a1 * p1im - a2 * p2im;
+                        p2re = p1re;
+                        p2im = p1im;
+                        p1re = sre;
+                        p1im = sim;
+                    }
+                    for (int k = 0; k < 3; k++) {
+                        T fr, fi;
+                        if (nn <= p) {
+                            vget(k, nn, m, fr, fi);
+                            vl[k].add(wgt * (fr * sre - fi * sim));
+                        }
+                        // d_x, d_y, d_z of V_k at (nn, m) from its coefficients at nn - 1
+                        T ar, ai, br, bi, cr, ci;
+                        vget(k, nn - 1, m - 1, ar, ai);
+                        vget(k, nn - 1, m + 1, br, bi);
+                        vget(k, nn - 1, m, cr, ci);
+                        const T gxr = (T)0.5 * (ar - br), gxi = (T)0.5 * (ai - bi);
+                        const T gyr = (T)0.5 * (ai + bi), gyi = (T)-0.5 * (ar + br);
+                        gl[3 * k + 0].add(wgt * (gxr * sre - gxi * sim));
+                        gl[3 * k + 1].add(wgt * (gyr * sre - gyi * sim));
+                        gl[3 * k + 2].add(wgt * (-cr * sre + ci * sim));
+                    }
+                }
+            }
+            const T ihq2 = ihq * ihq;
+            for (int k = 0; k < 3; k++) v[k].add(vl[k].value() * ihq);
+            for (int k = 0; k < 9; k++) g[k].add(gl[k].value() * ihq2);
+        }
+        if (act) {
+            const T wx = ws[i], wy = ws[n + i], wz = ws[2 * n + i];
+            T gg[9];
+            for (int k = 0; k < 9; k++) gg[k] = g[k].value();
+            for (int k = 0; k < 3; k++) {
+                vfar[k * n + i] += v[k].value();
+                vfar[(3 + k) * n + i] += gg[3 * k] * wx + gg[3 * k + 1] * wy + gg[3 * k + 2] * wz;
+            }
+            if (grad)
+                for (int k = 0; k < 9; k++) vfar[(6 + k) * n + i] += gg[k];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // P2P near field + combination + un-permutation: one lane per sorted element.
 // f = K/r^3, g = f'/r with the Gaussian core of eq. vem1; for u = r^2/(2a^2)
 // below 0.02 the Taylor series
@@ -1109,11 +1435,28 @@ static lhf_status execute_t(lhf_plan *P, const lhf_io *io, hipStream_t st)
             }
         }
         mark(4);
+        // W/X by expansions: X sources into the leaves' local expansions before L2P, W boxes'
+        // multipoles evaluated at the leaves' elements after it
+        if (P->wx_exp) {
+            const int SS = (p + 1) * (p + 1);
+            const int chl = std::max(1, std::min(8, (int)(49152 / (sizeof(T) * (2 * SS + 4)))));
+            hipLaunchKernelGGL(k_p2l<T>, dim3((unsigned)nleaf), dim3(WAVE), sizeof(T) * (size_t)chl * (2 * SS + 4), st,
+                               p, P->leaves, P->blev, P->bkey, P->bstart, P->bcount, P->wx_start, P->wx_ent,
+                               (const T *)xs, (const T *)ws, qin ? (const T *)P->qs : nullptr, n, P->sys_geo, Lc,
+                               chl);
+        }
         const int TRI = p * (p + 1) / 2;
         size_t sh_l2p = sizeof(T) * L2P_LPB * 6 * TRI;
         hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)((nleaf + L2P_LPB - 1) / L2P_LPB)), dim3(WAVE), sh_l2p, st, p, d,
                            nleaf, loff, P->leaves, P->blev, P->bkey, P->bstart, P->bcount, (const T *)xs,
                            (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar, (grad_v || beta) ? 1 : 0);
+        if (P->wx_exp) {
+            const int TRI1 = (p + 1) * (p + 2) / 2;
+            hipLaunchKernelGGL(k_m2p<T>, dim3((unsigned)nleaf), dim3(WAVE), sizeof(T) * 6 * (size_t)TRI1, st, p,
+                               P->leaves, P->blev, P->bkey, P->bstart, P->bcount, P->wx_start, P->wx_ent,
+                               (const T *)xs, (const T *)ws, n, P->sys_geo, (const T *)M, vfar,
+                               (grad_v || beta) ? 1 : 0);
+        }
     } else {
         mark(2);
         mark(3);

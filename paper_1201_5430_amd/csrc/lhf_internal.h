@@ -112,6 +112,11 @@ struct lhf_plan {
     int32_t *leaves = nullptr;   // [nleaf] leaf boxes in element (Morton) order
     int32_t *nl_start = nullptr; // [nleaf + 1] source-list offsets per leaf
     int32_t *nl_ent = nullptr;   // source entries (box << 1) | singular
+    // W/X by expansions (LHF_WX_EXPANSIONS): per-leaf lists of W boxes (M2P) and X sources (P2L)
+    bool wx_exp = false;
+    int32_t *wx_start = nullptr; // [nleaf + 1] offsets
+    int32_t *wx_ent = nullptr;   // entries (box << 1) | is_x
+    int64_t n_m2p = 0, n_p2l = 0;
     void *M = nullptr;           // multipoles [nbox][2][p^2], T
     void *Lc = nullptr;          // locals     [nbox][2][p^2], T
     void *rot = nullptr;         // rotation sets [n_theta][4][rot_set_size(p)], T

@@ -575,13 +575,17 @@ __device__ inline bool boxes_touch(int l1, const uint32_t c1[3], int l2, const u
 //      (these are exactly the leaves C with b or one of its ancestors in W(C)).
 // The finer boxes are found by a depth-first walk from each non-leaf colleague that
 // descends only into boxes touching b.  PASS 0 counts entries and element pairs;
-// PASS 1 writes the entries at the scanned offsets.
+// PASS 1 writes the entries at the scanned offsets.  With wxexp, W boxes of levels >= 2 and
+// the X entries of a leaf of level >= 2 go to the second list (box << 1 | is_x) instead:
+// M2P of the W box's multipole at b's elements, P2L of the X leaf's elements into b's local
+// expansion (every X entry qualifies: b or an ancestor of level >= 2 lies in the W-list of q).
 template <int PASS>
 __global__ void k_adlist(int64_t nleaf, int D, LevelTab lt, const int32_t *__restrict__ leaves,
                          const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
                          const int32_t *__restrict__ bcount, const int32_t *__restrict__ bchild0,
                          const int32_t *__restrict__ bnchild, int32_t *__restrict__ cnt_or_start,
-                         int32_t *__restrict__ ent, int64_t *__restrict__ pairs, int32_t *__restrict__ flags)
+                         int32_t *__restrict__ ent, int64_t *__restrict__ pairs, int32_t *__restrict__ flags,
+                         int wxexp, int32_t *__restrict__ wcnt_or_start, int32_t *__restrict__ went)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nleaf) return;
@@ -592,11 +596,22 @@ __global__ void k_adlist(int64_t nleaf, int D, LevelTab lt, const int32_t *__res
     uint32_t cb[3];
     box_ijk(kb, lb, cb);
     const int64_t nb_el = bcount[b];
-    int64_t pu = 0, pw = 0;
-    int nent = 0;
+    int64_t pu = 0, pw = 0, pm2p = 0, pp2l = 0;
+    int nent = 0, nwx = 0;
     const int base = PASS ? cnt_or_start[t] : 0;
-    auto emit = [&](int q, int sing) {
+    const int wbase = (PASS && wxexp) ? wcnt_or_start[t] : 0;
+    // sing: 0 = U, 1 = W, 2 = X
+    auto emit = [&](int q, int kind) {
         const int64_t c = bcount[q];
+        const bool byexp = wxexp && ((kind == 1 && blev[q] >= 2) || (kind == 2 && lb >= 2));
+        if (byexp) {
+            if (kind == 1) pm2p += nb_el;
+            else pp2l += c;
+            if (PASS) went[wbase + nwx] = (q << 1) | (kind == 2);
+            nwx++;
+            return;
+        }
+        const int sing = kind != 0;
         if (sing) pw += nb_el * c;
         else pu += nb_el * c;
         if (PASS) ent[base + nent] = (q << 1) | sing;
@@ -660,13 +675,16 @@ __global__ void k_adlist(int64_t nleaf, int D, LevelTab lt, const int32_t *__res
                     const int q = find_box(l, c);
                     if (q < 0 || bnchild[q] != 0) continue;
                     const uint32_t cq[3] = {(uint32_t)c[0], (uint32_t)c[1], (uint32_t)c[2]};
-                    emit(q, boxes_touch(l, cq, lb, cb, D) ? 0 : 1);  // U or X
+                    emit(q, boxes_touch(l, cq, lb, cb, D) ? 0 : 2);  // U or X
                 }
     }
     if (!PASS) {
         cnt_or_start[t] = nent;
+        if (wxexp) wcnt_or_start[t] = nwx;
         atomicAdd((unsigned long long *)&pairs[1], (unsigned long long)(pu - nb_el));
         atomicAdd((unsigned long long *)&pairs[2], (unsigned long long)pw);
+        atomicAdd((unsigned long long *)&pairs[4], (unsigned long long)pm2p);
+        atomicAdd((unsigned long long *)&pairs[5], (unsigned long long)pp2l);
     }
 }
 
@@ -1048,7 +1066,7 @@ static void free_plan(lhf_plan *P)
     void *bufs[] = {P->perm, P->xs, P->ws, P->vfar, P->xw, P->bkey, P->bstart, P->bcount, P->bparent, P->bchild0,
                     P->bnchild, P->vcount, P->vsrc, P->vdir, P->ulist, P->eleaf, P->M, P->Lc, P->rot,
                     P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp, P->sys_geo, P->sys_a, P->sys_off,
-                    P->blev, P->leaves, P->nl_start, P->nl_ent};
+                    P->blev, P->leaves, P->nl_start, P->nl_ent, P->qs, P->wx_start, P->wx_ent};
     for (void *b : bufs)
         if (b) (void)dev_free(b);
     for (int l = 0; l <= MAXDEPTH; l++)
@@ -1080,7 +1098,7 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     auto level_cap = [&](int l) { return std::min<int64_t>(n, (int64_t)ns << (3 * l)); };
     // ---- temporaries (all freed by cleanup)
     uint64_t *key = nullptr, *skey = nullptr;
-    int32_t *idx = nullptr, *flag = nullptr, *id = nullptr, *lcnt = nullptr;
+    int32_t *idx = nullptr, *flag = nullptr, *id = nullptr, *lcnt = nullptr, *wcnt = nullptr;
     int64_t *dnb = nullptr, *dcnt = nullptr, *dad = nullptr;
     void *tmp = nullptr;
     size_t tmp_bytes = 0;
@@ -1089,7 +1107,7 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     auto cleanup = [&]() {
         (void)hipStreamSynchronize(st);  // no queued kernel may still use a temporary
         for (void *b : {(void *)key, (void *)skey, (void *)idx, (void *)flag, (void *)id, (void *)dnb, (void *)dcnt,
-                        (void *)dad, (void *)lcnt, tmp})
+                        (void *)dad, (void *)lcnt, (void *)wcnt, tmp})
             if (b) (void)dev_free(b);
         for (int l = 0; l <= d; l++) {
             if (lkey[l]) (void)dev_free(lkey[l]);
@@ -1113,10 +1131,10 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     CK(dev_malloc(&flag, sizeof(int32_t) * n));
     CK(dev_malloc(&id, sizeof(int32_t) * n));
     CK(dev_malloc(&dnb, sizeof(int64_t) * (MAXDEPTH + 1)));
-    CK(dev_malloc(&dcnt, sizeof(int64_t) * 4));
+    CK(dev_malloc(&dcnt, sizeof(int64_t) * 6));
     CK(dev_malloc(&P->dflag, sizeof(int32_t) * 4));
     CK(hipMemsetAsync(P->dflag, 0, sizeof(int32_t) * 4, st));
-    CK(hipMemsetAsync(dcnt, 0, sizeof(int64_t) * 4, st));
+    CK(hipMemsetAsync(dcnt, 0, sizeof(int64_t) * 6, st));
     CK(dev_malloc(&P->sys_geo, sizeof(double) * 4 * ns));
     CK(dev_malloc(&P->sys_a, sizeof(double) * ns));
     CK(dev_malloc(&P->sys_off, sizeof(int64_t) * (ns + 1)));
@@ -1278,9 +1296,16 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
         hipLaunchKernelGGL(k_leaf_fill, dim3((unsigned)nl), dim3(64), 0, st, nl, P->leaves, P->bstart, P->bcount,
                            P->eleaf);
         // near-field source lists: count, scan, size on the host, fill
+        // (with W/X by expansions, a second list per leaf: the W boxes and X sources)
+        const int wxe = P->wx_exp ? 1 : 0;
+        if (wxe) {
+            CK(dev_malloc(&wcnt, sizeof(int32_t) * (nl + 1)));
+            CK(dev_malloc(&P->wx_start, sizeof(int32_t) * (nl + 1)));
+            hipLaunchKernelGGL(k_fill_i32, grid(nl + 1), dim3(tpb), 0, st, nl + 1, wcnt, 0);
+        }
         hipLaunchKernelGGL(k_fill_i32, grid(nl + 1), dim3(tpb), 0, st, nl + 1, lcnt, 0);
         hipLaunchKernelGGL(k_adlist<0>, grid(nl), dim3(tpb), 0, st, nl, d, lt, P->leaves, P->blev, P->bkey,
-                           P->bcount, P->bchild0, P->bnchild, lcnt, nullptr, dcnt, P->dflag);
+                           P->bcount, P->bchild0, P->bnchild, lcnt, nullptr, dcnt, P->dflag, wxe, wcnt, nullptr);
         size_t need = 0;
         CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, lcnt, P->nl_start, (int)(nl + 1), st));
         if (need > tmp_bytes) {
@@ -1289,12 +1314,16 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
             return LHF_ERR_HIP;
         }
         CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, lcnt, P->nl_start, (int)(nl + 1), st));
-        int32_t nent = 0;
+        if (wxe) CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, wcnt, P->wx_start, (int)(nl + 1), st));
+        int32_t nent = 0, nwx = 0;
         CK(hipMemcpyAsync(&nent, P->nl_start + nl, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        if (wxe) CK(hipMemcpyAsync(&nwx, P->wx_start + nl, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
         CK(dev_malloc(&P->nl_ent, sizeof(int32_t) * std::max<int64_t>(nent, 1)));
+        if (wxe) CK(dev_malloc(&P->wx_ent, sizeof(int32_t) * std::max<int64_t>(nwx, 1)));
         hipLaunchKernelGGL(k_adlist<1>, grid(nl), dim3(tpb), 0, st, nl, d, lt, P->leaves, P->blev, P->bkey,
-                           P->bcount, P->bchild0, P->bnchild, P->nl_start, P->nl_ent, dcnt, P->dflag);
+                           P->bcount, P->bchild0, P->bnchild, P->nl_start, P->nl_ent, dcnt, P->dflag, wxe,
+                           P->wx_start, P->wx_ent);
     }
     CK(hipGetLastError());
     lhf_status ts = build_tables<T>(P, st);
@@ -1309,8 +1338,8 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
                                    P->dmap[l], P->vcount);
     hipLaunchKernelGGL(k_sum_i32, dim3(256), dim3(256), 0, st, tot, P->vcount, dcnt);
     CK(hipGetLastError());
-    int64_t hc[4];
-    CK(hipMemcpyAsync(hc, dcnt, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st));
+    int64_t hc[6];
+    CK(hipMemcpyAsync(hc, dcnt, sizeof(int64_t) * 6, hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(hflag, P->dflag, sizeof(int32_t) * 4, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     cleanup();
@@ -1321,6 +1350,8 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     P->n_m2l = hc[0];
     P->n_p2p = hc[1];
     P->n_wx = hc[2];
+    P->n_m2p = hc[4];
+    P->n_p2l = hc[5];
 #undef CK
     return LHF_OK;
 }
@@ -1462,7 +1493,8 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
     if (d->precision != LHF_FP64 && d->precision != LHF_FP32) return arg_error("unknown precision");
     const int pmax = d->precision == LHF_FP64 ? MAXP : 16;
     if (d->p < 0 || d->p > pmax) return arg_error("p out of range (FP64: 1..24, FP32: 1..16; 0: from tol)");
-    if (d->flags & ~(LHF_SINGULAR | LHF_DETERMINISTIC | LHF_OUT_GRAD)) return arg_error("unknown flag bits");
+    if (d->flags & ~(LHF_SINGULAR | LHF_DETERMINISTIC | LHF_OUT_GRAD | LHF_WX_EXPANSIONS))
+        return arg_error("unknown flag bits");
     if (d->reserved != 0) return arg_error("reserved descriptor field must be 0");
     if (d->translation == LHF_TRANS_DIRECT) {
         set_error("translation = LHF_TRANS_DIRECT (full O(p^4) matrices) is not built in this library");
@@ -1509,6 +1541,7 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
     P->stream = stream;
     P->adaptive = d->max_per_leaf > 0;
     P->max_per_leaf = d->max_per_leaf;
+    P->wx_exp = P->adaptive && (d->flags & LHF_WX_EXPANSIONS) != 0;
     P->nsys = nsys;
     P->h_sys_off.assign(off, off + nsys + 1);
     P->h_sys_geo.resize(4 * (size_t)nsys);
@@ -1719,6 +1752,9 @@ lhf_status lhf_plan_stats(const lhf_plan *P, lhf_stats *out)
     out->calib_err_v = P->calib_err_v;
     out->calib_err_s = P->calib_err_s;
     out->warnings = P->warnings;
+    out->wx_expansions = P->wx_exp ? 1 : 0;
+    out->n_m2p = P->n_m2p;
+    out->n_p2l = P->n_p2l;
     return LHF_OK;
 }
 
