@@ -1,6 +1,6 @@
 """Benchmark of one FMM evaluation of v and s (the whole hot path) on one GPU.
 
-    python bench.py [--steps K] [--warmup W] [--p P] [--legs ring16,cube,batch]
+    python bench.py [--steps K] [--warmup W] [--p P] [--legs ring16,wx,cube,batch]
                     [--no-cpu-baseline] [--calib-copy MIB]
 
 A step is one pass of the whole path over the synthetic input, already resident
@@ -14,7 +14,8 @@ uniform background, adaptive octree of at most 64 elements per leaf down to leve
 split-kernel direct sum are both <= 1e-6 (p = 23 by the error-vs-order sweep; the
 run measures the errors it reaches on 4096 seeded targets with the oracle).  The
 other legs are labelled sections of the same line: the same ring at p = 16 in FP32
-and FP64 (the precision speedup), the 2^20-element uniform cube (FP64 p = 12, FP32
+and FP64 (the precision speedup), the ring in FP64 at p = 16 with the W/X lists by
+M2P / P2L instead of direct sums, the 2^20-element uniform cube (FP64 p = 12, FP32
 p = 10) and the batch of 256 systems.
 
 Roofline: per phase (gather, P2M, M2M, M2L + L2L, L2P, P2P) the algorithmic work
@@ -122,7 +123,7 @@ def measured_traffic(name):
         return None
 
 
-def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warmup):
+def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warmup, wx=False):
     """time `steps` plan + execute steps (inputs resident on the device); per-phase times from the
     library's HIP events on the execute stream"""
     dt = torch.float64 if prec == lhf.FP64 else torch.float32
@@ -131,7 +132,7 @@ def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warm
     v, s = torch.empty_like(wt), torch.empty_like(wt)
 
     def step(profile):
-        pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=max_per_leaf)
+        pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=max_per_leaf, wx_expansions=wx)
         if profile:
             pl.profile_begin(1)
         pl.execute(wt, v, s)
@@ -160,7 +161,10 @@ def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warm
            "plan_ms": ms - exec_ms, "execute_only_elements_per_s": n / (exec_ms * 1e-3), "phases_ms": phases,
            "m2l_kernel": st["m2l_kernel"], "m2l_achieved_tflops": m2l_tf,
            "counts": {"boxes": st["boxes"], "leaves": st["n_leaves"], "m2l": st["n_m2l"], "m2m": st["n_m2m"],
-                      "u_pairs": st["n_p2p_pairs"], "wx_pairs": st["n_wx_pairs"]}}
+                      "u_pairs": st["n_p2p_pairs"], "wx_pairs": st["n_wx_pairs"], "m2p_pairs": st["n_m2p"],
+                      "p2l_pairs": st["n_p2l"]}}
+    if wx:
+        res["wx_expansions"] = True
     if prec == lhf.FP64:
         res["m2l_frac_of_fp64_peak"] = m2l_tf / PEAK_FP64_TFLOPS if m2l_tf else None
     else:
@@ -333,7 +337,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--p", type=int, default=P_STAR, help="order of the headline (FP64 ring) leg")
     ap.add_argument("--leg-steps", type=int, default=20, help="timed steps of the ring p = 16 and cube legs")
-    ap.add_argument("--legs", default="ring16,cube,batch", help="comma list of ring16, cube, batch (or none)")
+    ap.add_argument("--legs", default="ring16,wx,cube,batch",
+                    help="comma list of ring16, wx, cube, batch (or none)")
     ap.add_argument("--targets", type=int, default=4096, help="sample targets of the headline accuracy")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle legs (baseline, accuracy)")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -433,6 +438,13 @@ def main():
         ring["speedup_fp32_vs_fp64"] = ring["fp64"]["ms_per_step"] / ring["fp32"]["ms_per_step"]
         ring["speedup_fp32_p16_vs_fp64_headline"] = head["ms_per_step"] / ring["fp32"]["ms_per_step"]
         out["ring_p16"] = ring
+    if "wx" in legs:
+        # the ring at p = 16 in FP64 with the W/X lists by M2P / P2L instead of direct sums
+        r, _, _ = run_leg(lhf, torch, "ring4m_fp64_p16_wx_expansions", x, w, a, 16, lhf.FP64, lmax, mx,
+                          max(1, args.leg_steps // 4), args.warmup, wx=True)
+        if "ring_p16" in out:
+            r["ms_vs_direct_wx"] = r["ms_per_step"] / out["ring_p16"]["fp64"]["ms_per_step"]
+        out["ring_p16_wx"] = r
     if "cube" in legs:
         cube = {}
         for wl in ("cube1m_fp64", "cube1m_fp32"):
