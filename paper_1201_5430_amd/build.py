@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblhfmm.so")
-SOURCES = ["lhf_plan.hip", "lhf_eval.hip", "lhf_m2l.hip", "lhf_m2l_half.hip", "lhf_m2l_mfma.hip", "lhf_batch.hip"]
+SOURCES = ["lhf_plan.hip", "lhf_eval.hip", "lhf_m2l.hip", "lhf_m2l_half.hip", "lhf_m2l_quarter.hip",
+           "lhf_m2l_mfma.hip", "lhf_batch.hip"]
 ARCH = os.environ.get("LHF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -21,7 +22,8 @@ FLAGS = [
 
 # per-source additions: the half-vector M2L's fully unrolled FP32 p = 16 body exceeds the
 # default size limit of '#pragma unroll' (a partly rolled loop would move its vectors to scratch)
-EXTRA = {"lhf_m2l_half.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
+EXTRA = {"lhf_m2l_half.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
+         "lhf_m2l_quarter.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
 
 
 def build(verbose: bool = False, jobs: int = 0) -> str:

@@ -26,6 +26,8 @@ void m2l_tile_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_mfma_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_half_stage(const lhf_plan *Pl, int level, hipStream_t st);
+void m2l_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st);
+void m2l_quarter_stage(const lhf_plan *Pl, int level, hipStream_t st);
 void m2m_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void l2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 
@@ -1421,9 +1423,11 @@ static lhf_status execute_t(lhf_plan *P, const lhf_io *io, hipStream_t st)
                 // the half-vector kernel reads its sources from a copy in its lane layout
                 // (timed with L2L, outside the M2L phase)
                 if (!P->use_mfma && P->use_half) m2l_half_stage(P, l, st);
+                if (P->use_quarter) m2l_quarter_stage(P, l, st);
                 mark(7 + 2 * l);
                 if (P->use_mfma) m2l_mfma_launch(P, l, st);
                 else if (P->use_half) m2l_half_launch(P, l, st);
+                else if (P->use_quarter) m2l_quarter_launch(P, l, st);
                 else m2l_tile_launch(P, l, st);
                 mark(8 + 2 * l);
             } else {

@@ -140,6 +140,7 @@ struct lhf_plan {
     void *wpad = nullptr;                // padded per-class rotation blocks (tiled M2L layout)
     bool use_mfma = false;               // matrix-core M2L (same schedule and box maps)
     bool use_half = false;               // VALU M2L with each vector split over two lanes (large p)
+    bool use_quarter = false;            // VALU M2L with each vector split over four lanes (FP64, high p)
     void *whalf = nullptr;               // its rotation tables
     void *mh = nullptr;                  // its sources, one level at a time, in its lane layout
     double *dtab = nullptr;              // its per-direction |t|, 1/|t|, e^{i phi} ([343][4])

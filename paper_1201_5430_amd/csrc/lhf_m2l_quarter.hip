@@ -1,0 +1,611 @@
+// lhf_m2l_quarter.hip -- batched FP64 M2L at high orders with each translation's coefficient
+// vector split over four lanes by m mod 4.
+//
+// The translation is the RCR scheme of Sec. 4.4 (rotation about z and y, coaxial (S|R) shift
+// with chi carried to order p, R-conversion of eq. rcr1, back-rotation) for both potentials,
+// as in the half-vector kernel.  What differs is how much of a vector one lane holds.  At
+// FP64 orders 16-24 half a part vector is 72-156 doubles: the register file then holds one
+// wavefront per SIMD and, from p = 22 on, spills.  Here
+//   lane = 16 t + 8 pot + 4 part + q      (t: translation of the batch, 4 per wavefront)
+// and the lane with residue q holds the entries m = 4j + q (j = 0 .. n/4) of every order n
+// (78 doubles at p = 23):
+//   * z-rotations act entry by entry (the partner part, lane ^ 4, by two DPP moves);
+//   * the coaxial shift and the conversion act column by column (fixed m) inside the lane;
+//     the conversion's other-potential partner (lane ^ 12) by ds_swizzle;
+//   * the y-rotation of order n mixes all m: each lane forms partial sums over its own columns
+//     for the output rows of all four residues (groups k = 0..3, residue q ^ k), and a two-step
+//     butterfly inside the quad (DPP lane ^ 1, then lane ^ 2) leaves each lane the full sums of
+//     its own rows: out = (G0 + G1[^1]) + (G2 + G3[^1])[^2].
+// Only the forward (S-basis) rotation tables are staged (one (part, residue) table per lane
+// role); the back-rotation uses W_back = D W_fwd^T D^-1 (D = diag(1, -1/2, 1/2, ..) on the Re
+// block, diag((-1)^m) on the Im block, as in the half-vector kernel), reading rows of the
+// table of residue q ^ k for output group k.  A tile is half a sibling group (four targets) and
+// eight wavefronts share it: one workgroup per compute unit with two wavefronts per SIMD.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "lhf_internal.h"
+#include "lhf_m2l_common.h"
+
+namespace lhf {
+namespace qv {
+
+// the value of lane ^ 4 by two DPP moves (VALU only, no LDS-pipe traffic): row_half_mirror
+// (lane ^ 7 within eight lanes), then quad_perm [3,2,1,0] (lane ^ 3)
+__device__ inline double xor4(double v)
+{
+    return dpp_f<DPP_XOR3>(dpp_f<0x141>(v));
+}
+
+// entries of order n held by one lane: m = 4j + q, j < S(n)
+__host__ __device__ constexpr int S(int n) { return n / 4 + 1; }
+__host__ __device__ constexpr int hoff(int n)
+{
+    int o = 0;
+    for (int k = 0; k < n; k++) o += S(k);
+    return o;
+}
+constexpr int E = 2;  // doubles per 16-byte vector
+// table rows padded to whole 16-byte vectors
+__host__ __device__ constexpr int RL(int n) { return (S(n) + E - 1) / E * E; }
+// offset of order n's block in one (part, residue) table: [group k][row j'][RL(n) columns]
+__host__ __device__ constexpr int woff(int n)
+{
+    int o = 0;
+    for (int k = 0; k < n; k++) o += 4 * S(k) * RL(k);
+    return o;
+}
+
+template <int P>
+struct Shape {
+    static constexpr int NQ = hoff(P);               // entries per lane
+    static constexpr int WQ = woff(P);               // one (part, residue) table
+    static constexpr int WQS = WQ + E;               // tables one 16-byte vector apart
+    static constexpr int NQP = (NQ + E - 1) / E * E; // source layout stride per lane role
+    static constexpr int P2 = P * P;
+    static constexpr int ARS = NQ + 1;               // accumulator stride per lane role (odd)
+    static constexpr int SSTA = 16 * ARS + 1;        // accumulator stride per target slot
+};
+constexpr int NSLOT = 4;     // targets of a tile: children 4h .. 4h + 3 of one parent
+constexpr int NTHREADS = 512;
+constexpr int NENT = 1512;   // schedule entries of one sibling group
+
+template <int P>
+constexpr size_t tile_bytes()
+{
+    using Sh = Shape<P>;
+    return sizeof(double) * (size_t)8 * Sh::WQS + sizeof(double) * (size_t)NSLOT * Sh::SSTA +
+           sizeof(int) * 3 * NSLOT + sizeof(int16_t) * (64 + NENT);
+}
+
+// packed (phi, chi) expansion index k -> position in a target slot (lane layout)
+template <int P>
+__device__ inline int acc_pos(int k)
+{
+    using Sh = Shape<P>;
+    const int pot = k / Sh::P2, qq = k % Sh::P2;
+    int n = (int)sqrtf((float)qq);
+    if ((n + 1) * (n + 1) <= qq) n++;
+    if (n * n > qq) n--;
+    const int i = qq - n * n, part = i > n, m = part ? i - n : i;
+    return (8 * pot + 4 * part + (m & 3)) * Sh::ARS + hoff(n) + (m >> 2);
+}
+
+// sum_{i<N} W[i] x[i], W read as 16-byte vectors
+__device__ __attribute__((always_inline)) inline double dotw(const double *W, const double *x, const int N)
+{
+    double a = 0;
+#pragma unroll
+    for (int q = 0; q < (N + E - 1) / E; q++) {
+        const double2 w = ((const double2 *)W)[q];
+        a += w.x * x[q * E];
+        if (q * E + 1 < N) a += w.y * x[q * E + 1];
+    }
+    return a;
+}
+
+// acc[i] += a W[i], i < N
+__device__ __attribute__((always_inline)) inline void axpyw(const double *W, const double a, double *acc, const int N)
+{
+#pragma unroll
+    for (int q = 0; q < (N + E - 1) / E; q++) {
+        const double2 w = ((const double2 *)W)[q];
+        acc[q * E] += a * w.x;
+        if (q * E + 1 < N) acc[q * E + 1] += a * w.y;
+    }
+}
+
+}  // namespace qv
+
+template <int P>
+__global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int64_t poff, int64_t npar,
+                                                                const uint64_t *__restrict__ bkey,
+                                                                const int32_t *__restrict__ bchild0,
+                                                                const int32_t *__restrict__ bnchild,
+                                                                const int32_t *__restrict__ dmap,
+                                                                const double *__restrict__ Mq, int64_t soff,
+                                                                double *__restrict__ Lc,
+                                                                const double *__restrict__ wq, int64_t wstride,
+                                                                M2LSched sch, const int16_t *__restrict__ cls_theta,
+                                                                const double *__restrict__ dtab)
+{
+    using Sh = qv::Shape<P>;
+    using qv::hoff;
+    using qv::S;
+    constexpr int P2 = Sh::P2, NQ = Sh::NQ, NQP = Sh::NQP, ARS = Sh::ARS, SSTA = Sh::SSTA, WQS = Sh::WQS;
+    constexpr int NSLOT = qv::NSLOT, NT = qv::NTHREADS;
+    extern __shared__ char smem[];
+    double *Wl = (double *)smem;                       // [part][residue][WQS] forward tables
+    double *acc = Wl + 8 * WQS;                        // [NSLOT][SSTA]
+    int *slot_xyz = (int *)(acc + NSLOT * SSTA);       // [NSLOT] packed target coordinates, -1: no box
+    int *slot_box = slot_xyz + NSLOT;                  // [NSLOT] target box
+    int *slot_sys = slot_box + NSLOT;                  // [NSLOT] system of the target
+    int16_t *cst = (int16_t *)(slot_sys + NSLOT);      // [ncls + 1] class starts (this half)
+    int16_t *ent = cst + 64;                           // [NENT] (dir << 3) | slot
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // XCD-aware tile order: consecutive tiles stay on one XCD (shared L2)
+    const int64_t ntiles = 2 * npar;
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= ntiles) return;
+    const int ncls = sch.ncls;
+    const int hf = (int)(tile & 1);  // children 4 hf .. 4 hf + 3 of parent tile / 2
+
+    int has_box = 0;
+    if (tid < NSLOT) {
+        const int c = 4 * hf + tid;
+        int box = -1, xyz = -1, sys = 0;
+        const int64_t q = tile >> 1;
+        if (q < npar) {
+            const int64_t pb = poff + q;
+            const int c0 = bchild0[pb], nc = bnchild[pb];
+            for (int k = 0; k < nc; k++)
+                if ((int)(bkey[c0 + k] & 7u) == c) box = c0 + k;
+        }
+        if (box >= 0) {
+            const uint64_t key = bkey[box];
+            uint32_t ix = 0, iy = 0, iz = 0;
+            for (int b = 0; b < level; b++) {
+                ix |= (uint32_t)((key >> (3 * b)) & 1u) << b;
+                iy |= (uint32_t)((key >> (3 * b + 1)) & 1u) << b;
+                iz |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
+            }
+            xyz = (int)(ix | (iy << 10) | (iz << 20));
+            sys = (int)(key >> (3 * level));
+        }
+        slot_box[tid] = box;
+        slot_xyz[tid] = xyz;
+        slot_sys[tid] = sys;
+        has_box = box >= 0;
+    }
+    // a tile whose parent has no children on this half has nothing to do
+    if (!__syncthreads_or(has_box)) return;
+    // the class entries of this half, compacted per class: (dir << 3) | slot
+    if (tid < ncls) {
+        int cnt = 0;
+        for (int e = sch.cls_start[tid]; e < sch.cls_start[tid + 1]; e++) cnt += (sch.ent_c[e] >> 2) == hf;
+        cst[tid + 1] = (int16_t)cnt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        cst[0] = 0;
+        for (int k = 0; k < ncls; k++) cst[k + 1] = (int16_t)(cst[k] + cst[k + 1]);
+    }
+    __syncthreads();
+    if (tid < ncls) {
+        int o = cst[tid];
+        for (int e = sch.cls_start[tid]; e < sch.cls_start[tid + 1]; e++)
+            if ((sch.ent_c[e] >> 2) == hf) ent[o++] = (int16_t)((sch.ent_dir[e] << 3) | (sch.ent_c[e] & 3));
+    }
+    // the targets' local expansions into their slots (entries without an (n, m) stay zero)
+    for (int idx = tid; idx < NSLOT * SSTA; idx += NT) acc[idx] = 0.0;
+    __syncthreads();
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += NT) {
+        const int sl = idx / (2 * P2), r = idx % (2 * P2);
+        const int box = slot_box[sl];
+        if (box >= 0) acc[sl * SSTA + qv::acc_pos<P>(r)] = Lc[(size_t)box * 2 * P2 + r];
+    }
+
+    const int side = 1 << level;
+    const int t = lane >> 4, pot = (lane >> 3) & 1, part = (lane >> 2) & 1, q = lane & 3;
+
+    struct Job {
+        int slot, dir, src;
+    };
+    // translation tr of class k (4 per wavefront and batch): (slot, dir) from LDS, source by one
+    // load.  Branch-free (every load at a valid address, the result chosen by selects): the batch
+    // body must run with all lanes active, since its DPP exchanges read other lanes' registers
+    // and a register restored inside a divergent region would hold a stale value in the lanes
+    // that region skipped
+    auto setup = [&](int k, int r0) -> Job {
+        const bool kin = k < ncls;
+        const int kc = kin ? k : 0;
+        const int e0 = cst[kc], cnt = kin ? cst[kc + 1] - e0 : 0;
+        const int tr = r0 + wave * 4 + t;
+        const bool ok0 = tr < cnt;
+        const int code = ent[ok0 ? e0 + tr : 0];
+        const int dir = ok0 ? code >> 3 : 0, slot = code & 3;
+        const int xyz = slot_xyz[slot];
+        const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
+                  sz = (xyz >> 20) - (dir / 49 - 3);
+        const bool inb = ok0 && xyz >= 0 && sx >= 0 && sy >= 0 && sz >= 0 && sx < side && sy < side && sz < side;
+        const size_t di = inb ? (((size_t)slot_sys[slot] * side + sz) * side + sy) * side + sx : 0;
+        const int src = dmap[di];
+        const bool ok = inb && src >= 0;
+        return Job{ok ? slot : -1, ok ? dir : 0, ok ? src : -1};
+    };
+    auto advance = [&](int &k, int &r0) {
+        r0 += 8 * 4;
+        if (k < ncls && r0 >= cst[k + 1] - cst[k]) {
+            k++;
+            r0 = 0;
+        }
+    };
+    // this lane's entries of the source, stored contiguously per lane role by k_mquarter
+    auto load_part = [&](const Job &j, double *dst) {
+        const double2 *sp = (const double2 *)(Mq + ((size_t)(j.src >= 0 ? j.src - soff : 0) * 16 + (lane & 15)) * NQP);
+#pragma unroll
+        for (int i = 0; i < NQP / 2; i++) {
+            const double2 x = sp[i];
+            dst[2 * i] = x.x;
+            if (2 * i + 1 < NQ) dst[2 * i + 1] = x.y;
+        }
+    };
+
+    int k = 0, r0 = 0;   // current batch
+    int k1 = 0, r1 = 0;  // next batch
+    advance(k1, r1);
+    Job cur = setup(k, r0), nxt = setup(k1, r1);
+    constexpr int N16 = 8 * WQS * 8 / 16;
+    int staged = -1;
+    while (k < ncls) {
+        if (k != staged) {
+            __syncthreads();
+            const uint4 *src4 = (const uint4 *)(wq + (size_t)cls_theta[k] * wstride);
+            uint4 *dst4 = (uint4 *)Wl;
+#pragma unroll 4
+            for (int i = tid; i < N16; i += NT) dst4[i] = src4[i];
+            __syncthreads();
+            staged = k;
+        }
+        const Job j = cur;
+        const bool act = j.src >= 0;
+        int k2 = k1, r2 = r1;
+        advance(k2, r2);
+        const Job nn = setup(k2, r2);
+        if (__ballot(act) != 0ull) {  // wavefront-uniform: skip batches with no active lane
+            double v[NQ];
+            load_part(j, v);
+            const double2 d0 = ((const double2 *)dtab)[2 * j.dir], d1 = ((const double2 *)dtab)[2 * j.dir + 1];
+            const double tau = d0.x, itau = d0.y;
+            const double cph = d1.x, sph = d1.y;
+            // e^{i q phi} (by selects: no lane-dependent loop) and e^{4 i phi}
+            const double c2 = cph * cph - sph * sph, s2 = 2.0 * cph * sph;
+            const double c3 = c2 * cph - s2 * sph, s3 = s2 * cph + c2 * sph;
+            const double c4 = c2 * c2 - s2 * s2, s4 = 2.0 * c2 * s2;
+            const double cq = q == 0 ? 1.0 : q == 1 ? cph : q == 2 ? c2 : c3;
+            const double sq = q == 0 ? 0.0 : q == 1 ? sph : q == 2 ? s2 : s3;
+            // 1. rotate about z by +phi: Re' = re c - im s, Im' = im c + re s (m = 4j + q)
+            {
+                const double sgn = part ? 1.0 : -1.0;
+                double cm = cq, sm = sq;
+#pragma unroll
+                for (int jj = 0; jj < S(P - 1); jj++) {
+                    const double sz = sm * sgn;
+#pragma unroll
+                    for (int n = 4 * jj; n < P; n++) {
+                        const double x = v[hoff(n) + jj];
+                        const double o = qv::xor4(x);
+                        v[hoff(n) + jj] = x * cm + o * sz;
+                    }
+                    const double a = cm * c4 - sm * s4, b = sm * c4 + cm * s4;
+                    cm = a;
+                    sm = b;
+                }
+            }
+            // 2. rotation about y of every order with this lane's forward table: partial sums of the
+            //    four output groups over the lane's columns, then the quad butterfly
+            {
+                const double *Wf = Wl + (part * 4 + q) * WQS;
+#pragma unroll
+                for (int n = 0; n < P; n++) {
+                    const double *Wn = Wf + qv::woff(n);
+                    constexpr int SM = (P - 1) / 4 + 1;
+                    double g[4][SM];
+#pragma unroll
+                    for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+                        for (int jj = 0; jj < S(n); jj++) {
+                            g[kk][jj] = qv::dotw(Wn + (kk * S(n) + jj) * qv::RL(n), &v[hoff(n)], S(n));
+                            // bound the table reads in flight (they do not depend on v)
+                            if (jj % 2 == 1 || jj == S(n) - 1) __builtin_amdgcn_sched_barrier(0);
+                        }
+#pragma unroll
+                    for (int jj = 0; jj < S(n); jj++) {
+                        const double a = g[0][jj] + dpp_f<DPP_XOR1>(g[1][jj]);
+                        const double b = g[2][jj] + dpp_f<DPP_XOR1>(g[3][jj]);
+                        v[hoff(n) + jj] = a + dpp_f<DPP_XOR2>(b);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // 3+4. per column m = 4c + q: coaxial (S|R) shift out_n = tau^-(n+1) sum_n' (n+n')! tau^-n' in_n'
+            //      (chi to order P), then the R-conversion (eq. rcr1, scaled)
+            //        phi~ = phi + i tau m/n chi ,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
+            {
+                const double wphi = pot ? 0.0 : 1.0, wchi = pot ? 1.0 : 0.0;
+                const double sconv = part ? 1.0 : -1.0;
+                const double itau4 = (itau * itau) * (itau * itau);
+                double pc = 1.0;  // tau^-(4c)
+#pragma unroll
+                for (int c = 0; c < S(P - 1); c++) {
+                    const int n0 = 4 * c;
+                    const double mval = (double)(4 * c + q);
+                    double out[P + 1];
+                    {
+                        double s = pc;
+#pragma unroll
+                        for (int n2 = n0; n2 < P; n2++) {
+                            v[hoff(n2) + c] *= s;
+                            s *= itau;
+                        }
+                        double so = pc * itau;
+#pragma unroll
+                        for (int n = n0; n <= P; n++) {
+                            double a = 0;
+#pragma unroll
+                            for (int n2 = n0; n2 < P; n2++) a += dfact(n + n2) * v[hoff(n2) + c];
+                            out[n] = a * so;
+                            so *= itau;
+                        }
+                    }
+                    pc *= itau4;
+#pragma unroll
+                    for (int n = n0; n < P; n++) {
+                        const double other = swz_xor<12>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
+                        const double fphi = (n > 0) ? tau * mval * (1.0 / (double)n) * sconv * wphi : 0.0;
+                        const double fchi = -tau * (1.0 / (double)(n + 1)) * wchi;
+                        double val = out[n] + fphi * other + fchi * out[n + 1];
+                        v[hoff(n) + c] = (n - n0 < q) ? 0.0 : val;  // slot (n, c) holds m = 4c + q > n: empty
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // 5. back-rotation with the forward tables: v <- D W_fwd^T D^-1 v.  Output group k
+            //    (residue q ^ k) takes rows j of the table of residue q ^ k, group k; the quad
+            //    butterfly gathers the groups; D scales the outputs
+            {
+                const double sg = (q & 1) ? -1.0 : 1.0;  // (-1)^m on this lane
+                const double fin = part ? sg : 2.0 * sg, fout = part ? sg : 0.5 * sg;
+                const double *Wp = Wl + part * 4 * WQS;
+#pragma unroll
+                for (int n = 0; n < P; n++) {
+                    constexpr int SM = (P - 1) / 4 + 1;
+                    double g[4][SM];
+#pragma unroll
+                    for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+                        for (int jj = 0; jj < S(n); jj++) g[kk][jj] = 0.0;
+#pragma unroll
+                    for (int jj = 0; jj < S(n); jj++) {
+                        // m = 0 (q = 0, j = 0, Re part) is not doubled by D^-1
+                        const double xj = v[hoff(n) + jj] * ((jj == 0 && q == 0 && !part) ? 1.0 : fin);
+#pragma unroll
+                        for (int kk = 0; kk < 4; kk++) {
+                            qv::axpyw(Wp + (q ^ kk) * WQS + qv::woff(n) + (kk * S(n) + jj) * qv::RL(n), xj, g[kk],
+                                      S(n));
+                            if (kk % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                        }
+                    }
+#pragma unroll
+                    for (int jj = 0; jj < S(n); jj++) {
+                        const double a = g[0][jj] + dpp_f<DPP_XOR1>(g[1][jj]);
+                        const double b = g[2][jj] + dpp_f<DPP_XOR1>(g[3][jj]);
+                        v[hoff(n) + jj] = (a + dpp_f<DPP_XOR2>(b)) * ((jj == 0 && q == 0 && !part) ? 1.0 : fout);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // 6. back-rotation about z (-phi) and accumulation into the target slot
+            {
+                double *ap = acc + (size_t)(act ? j.slot : 0) * SSTA + (lane & 15) * ARS;
+                const double sgn = part ? -1.0 : 1.0;  // Re' = re c + im s, Im' = im c - re s
+                double cm = cq, sm = sq;
+#pragma unroll
+                for (int jj = 0; jj < S(P - 1); jj++) {
+                    const double sz = sm * sgn;
+#pragma unroll
+                    for (int n = 4 * jj; n < P; n++) {
+                        const double x = v[hoff(n) + jj];
+                        const double o = qv::xor4(x);
+                        const double val = x * cm + o * sz;
+                        // no branch: a conditional add would let the compiler sink the whole
+                        // translation into it and keep every partial sum live (inactive lanes add 0)
+                        atomicAdd(ap + hoff(n) + jj, act ? val : 0.0);
+                    }
+                    const double a = cm * c4 - sm * s4, b = sm * c4 + cm * s4;
+                    cm = a;
+                    sm = b;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }  // active batch
+        cur = nxt;
+        nxt = nn;
+        k = k1;
+        r0 = r1;
+        k1 = k2;
+        r1 = r2;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += NT) {
+        const int sl = idx / (2 * P2), r = idx % (2 * P2);
+        const int box = slot_box[sl];
+        if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SSTA + qv::acc_pos<P>(r)];
+    }
+}
+
+// the sources of one level in the quarter layout: box b of the level at Mq[(b * 16 + role) * NQP],
+// role = 8 pot + 4 part + q (the lane's low four bits), entry hoff(n) + j = order n, m = 4j + q of
+// that potential and part; zero where m > n, for (Im, m = 0) and in the padding
+template <int P>
+__global__ void __launch_bounds__(256) k_mquarter(int64_t off, int64_t nb, const double *__restrict__ M,
+                                                  double *__restrict__ Mq)
+{
+    using Sh = qv::Shape<P>;
+    constexpr int NQP = Sh::NQP, NQ = Sh::NQ, NE = 16 * NQP, P2 = P * P;
+    __shared__ int16_t src[NE];
+    for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+        const int r = t / NQP, e = t % NQP;
+        const int pot = r >> 3, part = (r >> 2) & 1, q = r & 3;
+        int k = -1;
+        if (e < NQ) {
+            int n = 0;
+            while (qv::hoff(n + 1) <= e) n++;
+            const int m = 4 * (e - qv::hoff(n)) + q;
+            if (m <= n && !(part && m == 0)) k = pot * P2 + n * n + (part ? n : 0) + m;
+        }
+        src[t] = (int16_t)k;
+    }
+    __syncthreads();
+    for (int64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const double *mb = M + (size_t)(off + b) * 2 * P2;
+        double *hb = Mq + (size_t)b * NE;
+        for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+            const int k = src[t];
+            hb[t] = k >= 0 ? mb[k] : 0.0;
+        }
+    }
+}
+
+// Forward (S-basis) rotation tables of every polar-angle class in the quarter layout:
+// [part: Re, Im][residue q][order n][group k][row j'][RL(n)] (each table padded to WQS entries);
+// row j' of group k is m' = 4j' + (q ^ k), column i is m = 4i + q; the Im block (m, m' >= 1) is
+// embedded with zeros at m = 0 and m' = 0; zero where m or m' > n.
+template <int P>
+__global__ void k_wquarter(const double *__restrict__ rot, double *__restrict__ wq, int64_t stride)
+{
+    using Sh = qv::Shape<P>;
+    const int th = blockIdx.x;
+    const double *Rf = rot + ((size_t)th * ROT_NKIND + ROT_S_FWD) * rot_set_size(P);
+    for (int idx = threadIdx.x; idx < stride; idx += blockDim.x) {
+        double val = 0.0;
+        const int tb = idx / Sh::WQS, e = idx % Sh::WQS;
+        const int part = tb >> 2, q = tb & 3;
+        if (e < Sh::WQ) {
+            int n = 0;
+            while (qv::woff(n + 1) <= e) n++;
+            const int r = e - qv::woff(n), row = r / qv::RL(n), i = r % qv::RL(n);
+            const int kk = row / qv::S(n), jr = row % qv::S(n);
+            const int mp = 4 * jr + (q ^ kk), m = 4 * i + q;
+            if (i < qv::S(n) && mp <= n && m <= n) {
+                const double *blk = Rf + rot_block_off(n);
+                if (part == 0) val = blk[mp * (n + 1) + m];
+                else if (mp > 0 && m > 0) val = blk[(n + 1) * (n + 1) + (mp - 1) * n + (m - 1)];
+            }
+        }
+        wq[(size_t)th * stride + idx] = val;
+    }
+}
+
+__global__ void k_dirtab_q(double *__restrict__ tab)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= 343) return;
+    const int dx = d % 7 - 3, dy = (d / 7) % 7 - 3, dz = d / 49 - 3;
+    const double tau = sqrt((double)(dx * dx + dy * dy + dz * dz));
+    const double rho = sqrt((double)(dx * dx + dy * dy));
+    tab[4 * d + 0] = tau;
+    tab[4 * d + 1] = tau > 0.0 ? 1.0 / tau : 0.0;
+    tab[4 * d + 2] = rho > 0.0 ? (double)dx / rho : 1.0;
+    tab[4 * d + 3] = rho > 0.0 ? (double)dy / rho : 0.0;
+}
+
+namespace {
+
+template <int P>
+static bool wquarter_build_t(lhf_plan *Pl, hipStream_t st)
+{
+    constexpr size_t shm = qv::tile_bytes<P>();
+    static_assert(shm <= 163840, "tile exceeds the LDS");
+    const int64_t stride = 8 * (int64_t)qv::Shape<P>::WQS;
+    if (dev_malloc(&Pl->whalf, sizeof(double) * stride * Pl->n_theta) != hipSuccess) return false;
+    k_wquarter<P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const double *)Pl->rot, (double *)Pl->whalf,
+                                                                     stride);
+    if (dev_malloc(&Pl->dtab, sizeof(double) * 4 * 343) != hipSuccess) return false;
+    k_dirtab_q<<<dim3(2), dim3(256), 0, st>>>(Pl->dtab);
+    int64_t nbmax = 0;
+    for (int l = 2; l <= Pl->depth; l++) nbmax = std::max(nbmax, Pl->lev[l].nb);
+    if (nbmax > 0 && dev_malloc(&Pl->mh, sizeof(double) * 16 * qv::Shape<P>::NQP * nbmax) != hipSuccess) return false;
+    return hipFuncSetAttribute((const void *)k_m2l_quarter<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)shm) == hipSuccess;
+}
+
+template <int P>
+static void stage_quarter(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    const int64_t nb = Pl->lev[level].nb;
+    if (nb == 0) return;
+    k_mquarter<P><<<dim3((unsigned)std::min<int64_t>(nb, 8192)), dim3(256), 0, st>>>(
+        Pl->lev[level].off, nb, (const double *)Pl->M, (double *)Pl->mh);
+}
+
+template <int P>
+static void launch_quarter(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
+    const int64_t soff = Pl->lev[level].off, nb = Pl->lev[level].nb;
+    if (nb == 0 || npar == 0) return;
+    const int64_t ntiles = 2 * npar;
+    const int64_t per = (ntiles + 7) / 8;
+    M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
+    k_m2l_quarter<P><<<dim3((unsigned)(per * 8)), dim3(qv::NTHREADS), qv::tile_bytes<P>(), st>>>(
+        level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const double *)Pl->mh, soff,
+        (double *)Pl->Lc, (const double *)Pl->whalf, 8 * (int64_t)qv::Shape<P>::WQS, sch, Pl->sched_cls_theta,
+        Pl->dtab);
+}
+
+}  // namespace
+
+bool m2l_quarter_supported(int precision, int p)
+{
+    return precision == LHF_FP64 && (p == 16 || p == 20 || p == 22 || p == 23 || p == 24);
+}
+
+bool wquarter_build(lhf_plan *Pl, hipStream_t st)
+{
+    switch (Pl->p) {
+    case 16: return wquarter_build_t<16>(Pl, st);
+    case 20: return wquarter_build_t<20>(Pl, st);
+    case 22: return wquarter_build_t<22>(Pl, st);
+    case 23: return wquarter_build_t<23>(Pl, st);
+    case 24: return wquarter_build_t<24>(Pl, st);
+    }
+    return false;
+}
+
+void m2l_quarter_stage(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    switch (Pl->p) {
+    case 16: stage_quarter<16>(Pl, level, st); break;
+    case 20: stage_quarter<20>(Pl, level, st); break;
+    case 22: stage_quarter<22>(Pl, level, st); break;
+    case 23: stage_quarter<23>(Pl, level, st); break;
+    case 24: stage_quarter<24>(Pl, level, st); break;
+    }
+}
+
+void m2l_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    switch (Pl->p) {
+    case 16: launch_quarter<16>(Pl, level, st); break;
+    case 20: launch_quarter<20>(Pl, level, st); break;
+    case 22: launch_quarter<22>(Pl, level, st); break;
+    case 23: launch_quarter<23>(Pl, level, st); break;
+    case 24: launch_quarter<24>(Pl, level, st); break;
+    }
+}
+
+}  // namespace lhf

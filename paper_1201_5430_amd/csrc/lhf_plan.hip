@@ -38,6 +38,8 @@ bool wmfma_build(lhf_plan *Pl, hipStream_t st);
 
 bool m2l_tile_owned(int precision, int p);
 bool m2l_half_owned(int precision, int p);
+bool m2l_quarter_supported(int precision, int p);
+bool wquarter_build(lhf_plan *Pl, hipStream_t st);
 bool mm_half_supported(int precision, int p);
 
 // ---- device memory cache -----------------------------------------------------------------
@@ -1042,6 +1044,11 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
             set_error("half-vector M2L set-up failed");
             return LHF_ERR_HIP;
         }
+        P->use_quarter = P->m2l_kind == LHF_M2L_QUARTER;
+        if (P->use_quarter && !wquarter_build(P, st)) {
+            set_error("quarter-vector M2L set-up failed");
+            return LHF_ERR_HIP;
+        }
     }
     return LHF_OK;
 }
@@ -1400,6 +1407,7 @@ static bool m2l_available(int k, int precision, int p)
 {
     switch (k) {
     case LHF_M2L_HALF: return m2l_half_supported(precision, p);
+    case LHF_M2L_QUARTER: return m2l_quarter_supported(precision, p);
     case LHF_M2L_TILE:
     case LHF_M2L_TILE1: return m2l_tile_supported(precision, p);
     case LHF_M2L_MFMA: return m2l_mfma_supported(precision, p);
@@ -1413,6 +1421,7 @@ bool kernel_deterministic(int precision, int p, int k)
 {
     switch (k) {
     case LHF_M2L_HALF: return m2l_half_owned(precision, p);
+    case LHF_M2L_QUARTER: return false;  // LDS atomics
     case LHF_M2L_TILE:
     case LHF_M2L_TILE1: return m2l_tile_owned(precision, p);
     default: return true;  // matrix-core (one parent per wavefront, register sums), generic (per box)
@@ -1421,13 +1430,14 @@ bool kernel_deterministic(int precision, int p, int k)
 
 static const char *m2l_name(int k)
 {
-    static const char *nm[] = {"AUTO", "HALF", "TILE", "TILE1", "MFMA", "GENERIC"};
-    return (k >= 0 && k <= 5) ? nm[k] : "?";
+    static const char *nm[] = {"AUTO", "HALF", "TILE", "TILE1", "MFMA", "GENERIC", "QUARTER"};
+    return (k >= 0 && k <= 6) ? nm[k] : "?";
 }
 
 // Resolve the descriptor's kernel requests (host only, before any launch).  AUTO takes the
-// fastest kernel measured for (precision, p): the half-vector kernel where it is instantiated,
-// else the one-lane tile, else the generic per-box kernel; with LHF_DETERMINISTIC only kernels
+// fastest kernel measured for (precision, p): the quarter-vector kernel at FP64 p >= 20, the
+// half-vector kernel where it is instantiated, else the one-lane tile, else the generic per-box
+// kernel; with LHF_DETERMINISTIC only kernels
 // without atomics qualify (then the matrix-core kernel, which is deterministic, precedes the
 // generic one).  Batched kernels need the dense box maps: depth <= 8 and at most 2^28 cells.
 lhf_status resolve_kernels(const lhf_desc *d, int p, bool dmap_ok, int *m2l, int *mm)
@@ -1438,7 +1448,11 @@ lhf_status resolve_kernels(const lhf_desc *d, int p, bool dmap_ok, int *m2l, int
     if (k == LHF_M2L_AUTO) {
         k = LHF_M2L_GENERIC;
         if (dmap_ok) {
-            const int order[] = {LHF_M2L_HALF, LHF_M2L_TILE, LHF_M2L_MFMA};
+            // FP64 p >= 20: the quarter-vector kernel (two wavefronts per SIMD where the half-vector
+            // kernel holds one; 4M ring, p = 23: 630 against 1091 ms of M2L); equal at p = 16
+            const bool quarter_first = prec == LHF_FP64 && p >= 20;
+            const int order[] = {quarter_first ? LHF_M2L_QUARTER : LHF_M2L_HALF, LHF_M2L_HALF, LHF_M2L_TILE,
+                                 LHF_M2L_MFMA};
             for (int c : order) {
                 if (c == LHF_M2L_MFMA && !det) continue;
                 if (m2l_available(c, prec, p) && (!det || kernel_deterministic(prec, p, c))) {
@@ -1501,7 +1515,7 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
         return LHF_ERR_UNSUPPORTED;
     }
     if (d->translation != LHF_TRANS_RCR) return arg_error("unknown translation scheme");
-    if (d->m2l_kernel < LHF_M2L_AUTO || d->m2l_kernel > LHF_M2L_GENERIC) return arg_error("unknown m2l_kernel");
+    if (d->m2l_kernel < LHF_M2L_AUTO || d->m2l_kernel > LHF_M2L_QUARTER) return arg_error("unknown m2l_kernel");
     if (d->mm_kernel < LHF_MM_AUTO || d->mm_kernel > LHF_MM_GENERIC) return arg_error("unknown mm_kernel");
     if (d->depth < 2 || d->depth > MAXDEPTH) return arg_error("depth out of range (2..10)");
     if (d->max_per_leaf < 0) return arg_error("max_per_leaf must be >= 0");

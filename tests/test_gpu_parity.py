@@ -257,6 +257,36 @@ def test_half_vector_m2l(oracle, prec, p):
         _check32(vh, sh, v1, s1)
 
 
+@pytest.mark.parametrize("p", [16, 20, 22, 23, 24])
+def test_quarter_vector_m2l(oracle, p):
+    # the FP64 M2L kernel with each part vector split over four lanes by m mod 4: against the
+    # oracle on sampled leaves and against the half-vector kernel on every element, on a uniform
+    # tree and on an adaptive one (leaves on several levels, tiles whose parent lacks children)
+    import paper_1201_5430_amd as L
+    rng = np.random.default_rng(210 + p)
+    n = 30000
+    x = rng.uniform(0, 1, (n, 3))
+    w = rng.normal(size=(n, 3))
+    a = 0.5 * n ** (-1 / 3)
+    samp = rng.choice(n, 40, replace=False)
+    vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
+    m = ~np.isnan(vr[:, 0])
+    vq, sq, stq = _gpu_fmm(x, w, a, p, 5, m2l_kernel=L.M2L_QUARTER)
+    vh, sh, sth = _gpu_fmm(x, w, a, p, 5, m2l_kernel=L.M2L_HALF)
+    assert stq["m2l_kernel"] == "quarter" and sth["m2l_kernel"] == "half"
+    print(f"quarter-vector M2L p={p}: ", end="")
+    _check(vq[m], sq[m], vr[m], sr[m])
+    _check(vq, sq, vh, sh, l2=1e-13, mx=1e-12)
+    # adaptive tree: the vortex ring with its background, <= 16 per leaf down to level 7
+    import workloads
+    xr, wr = workloads.vortex_ring(8000, 211)
+    ar = workloads.core_radius(8000)
+    vq, sq, _ = _gpu_fmm(xr, wr, ar, p, 7, max_per_leaf=16, m2l_kernel=L.M2L_QUARTER)
+    vh, sh, _ = _gpu_fmm(xr, wr, ar, p, 7, max_per_leaf=16, m2l_kernel=L.M2L_HALF)
+    print(f"  adaptive ring: ", end="")
+    _check(vq, sq, vh, sh, l2=1e-13, mx=1e-12)
+
+
 def test_reused_device_blocks(oracle):
     # a plan built on the blocks of a destroyed one (same sizes) gives the same field as a plan
     # on fresh blocks; p = 6 runs the deterministic ownership tile, so the comparison is exact
