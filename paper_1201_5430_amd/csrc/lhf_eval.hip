@@ -33,6 +33,7 @@ void l2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 
 constexpr int WAVE = 64;
 constexpr int NRMAX = (2 * MAXP * MAXP + WAVE - 1) / WAVE;  // accumulator rows per lane
+constexpr int NPMAX = (MAXP * (MAXP + 1) / 2 + WAVE - 1) / WAVE;  // (n, m >= 0) pairs per lane
 
 __device__ inline void decode_row(int q, int &n, int &m, int &part)
 {
@@ -73,7 +74,7 @@ __device__ inline void box_centre(uint64_t key, int level, const double *__restr
 // column m of Rt_n^m(xhat) (R_n^m = (-1)^n i^m Rt_n^m) by the recurrence
 //   Rt_m^m = -(x+iy)/(2m) Rt_{m-1}^{m-1},  Rt_{m+1}^m = z Rt_m^m,
 //   Rt_n^m = ((2n-1) z Rt_{n-1}^m - r^2 Rt_{n-2}^m) / ((n-m)(n+m)),
-// then every lane adds the eq. eve4 contributions of its packed rows.
+// then every lane adds the eq. eve4 contributions of its (n, m) pairs (both potentials, Re and Im).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off, const int32_t *__restrict__ leaves,
@@ -98,10 +99,10 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
     double c0, c1, c2, hd;
     box_centre(bkey[b], level, sys_geo, c0, c1, c2, hd);
     const T ih = (T)(1.0 / hd);
-    const int P2 = p * p;
-    T acc[NRMAX];
+    const int P2 = p * p, TRI = p * (p + 1) / 2;
+    T acc[4 * NPMAX];  // per (n, m) pair of the lane: Re a, Im a, Re b, Im b
 #pragma unroll
-    for (int k = 0; k < NRMAX; k++) acc[k] = 0;
+    for (int k = 0; k < 4 * NPMAX; k++) acc[k] = 0;
     const int s0 = bstart[b], cnt = bcount[b];
     for (int e0 = 0; e0 < cnt; e0 += ch) {
         const int ne = min(ch, cnt - e0);
@@ -148,13 +149,16 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
             }
         }
         __syncthreads();
+        // lane per (n, m >= 0) pair: the three conj(Rt) values of order n (phi) and of order n - 1
+        // (chi) serve all four outputs (Re and Im of a and b)
 #pragma unroll
-        for (int k = 0; k < NRMAX; k++) {
-            const int r = lane + WAVE * k;
-            if (r >= 2 * P2) break;
-            const int pot = r >= P2;
-            int nn, m, part;
-            decode_row(r - pot * P2, nn, m, part);
+        for (int k = 0; k < NPMAX; k++) {
+            const int t = lane + WAVE * k;
+            if (t >= TRI) break;
+            int nn = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+            while (nn * (nn + 1) / 2 > t) --nn;
+            while ((nn + 1) * (nn + 2) / 2 <= t) ++nn;
+            const int m = t - nn * (nn + 1) / 2;
             const T sgn = (m & 1) ? (T)-1 : (T)1;
             for (int e = 0; e < ne; e++) {
                 const T *Re = Rre + (size_t)e * P2, *Im = Rim + (size_t)e * P2;
@@ -180,8 +184,7 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                 };
                 const T wmre = wx, wmim = -wy;  // wx - i wy
                 const T wpre = wx, wpim = wy;   // wx + i wy
-                T vre, vim;
-                if (pot == 0) {
+                {
                     // a = -i (-1)^m / (n+1) [ (wx-iwy)(n-m+1)/2 C(m-1) + (wx+iwy)(n+m+1)/2 C(m+1) + wz m C(m) ]
                     T c1re, c1im, c2re, c2im, c3re, c3im;
                     C(nn, m - 1, c1re, c1im);
@@ -191,38 +194,40 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                     T sre = f1 * (wmre * c1re - wmim * c1im) + f2 * (wpre * c2re - wpim * c2im) + f3 * c3re;
                     T sim = f1 * (wmre * c1im + wmim * c1re) + f2 * (wpre * c2im + wpim * c2re) + f3 * c3im;
                     T sc = sgn / (T)(nn + 1);
-                    vre = sc * sim;  // -i (sre + i sim) = sim - i sre
-                    vim = -sc * sre;
-                    // monopole q (eq. 7): phi gains -q g_n^m, i.e. -q (-1)^m C(m) in this form
-                    vre -= qe * sgn * c3re;
-                    vim -= qe * sgn * c3im;
-                } else {
-                    if (nn == 0) {
-                        vre = 0;
-                        vim = 0;
-                    } else {
-                        // b = (-1)^m / n [ -1/2 (wx-iwy) C'(m-1) + 1/2 (wx+iwy) C'(m+1) + wz C'(m) ]
-                        T c1re, c1im, c2re, c2im, c3re, c3im;
-                        C(nn - 1, m - 1, c1re, c1im);
-                        C(nn - 1, m + 1, c2re, c2im);
-                        C(nn - 1, m, c3re, c3im);
-                        T sre = (T)-0.5 * (wmre * c1re - wmim * c1im) + (T)0.5 * (wpre * c2re - wpim * c2im) + wz * c3re;
-                        T sim = (T)-0.5 * (wmre * c1im + wmim * c1re) + (T)0.5 * (wpre * c2im + wpim * c2re) + wz * c3im;
-                        T sc = sgn / (T)nn;
-                        vre = sc * sre;
-                        vim = sc * sim;
-                    }
+                    // -i (sre + i sim) = sim - i sre; monopole q (eq. 7): phi gains -q g_n^m = -q (-1)^m C(m)
+                    acc[4 * k + 0] += sc * sim - qe * sgn * c3re;
+                    acc[4 * k + 1] += -sc * sre - qe * sgn * c3im;
                 }
-                acc[k] += part ? vim : vre;
+                if (nn >= 1) {
+                    // b = (-1)^m / n [ -1/2 (wx-iwy) C'(m-1) + 1/2 (wx+iwy) C'(m+1) + wz C'(m) ]
+                    T c1re, c1im, c2re, c2im, c3re, c3im;
+                    C(nn - 1, m - 1, c1re, c1im);
+                    C(nn - 1, m + 1, c2re, c2im);
+                    C(nn - 1, m, c3re, c3im);
+                    T sre = (T)-0.5 * (wmre * c1re - wmim * c1im) + (T)0.5 * (wpre * c2re - wpim * c2im) + wz * c3re;
+                    T sim = (T)-0.5 * (wmre * c1im + wmim * c1re) + (T)0.5 * (wpre * c2im + wpim * c2re) + wz * c3im;
+                    T sc = sgn / (T)nn;
+                    acc[4 * k + 2] += sc * sre;
+                    acc[4 * k + 3] += sc * sim;
+                }
             }
         }
     }
     T *out = M + (size_t)b * 2 * P2;
 #pragma unroll
-    for (int k = 0; k < NRMAX; k++) {
-        const int r = lane + WAVE * k;
-        if (r >= 2 * P2) break;
-        out[r] = acc[k] * ih;
+    for (int k = 0; k < NPMAX; k++) {
+        const int t = lane + WAVE * k;
+        if (t >= TRI) break;
+        int nn = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while (nn * (nn + 1) / 2 > t) --nn;
+        while ((nn + 1) * (nn + 2) / 2 <= t) ++nn;
+        const int m = t - nn * (nn + 1) / 2;
+        out[pk_re(nn, m)] = acc[4 * k] * ih;
+        out[P2 + pk_re(nn, m)] = acc[4 * k + 2] * ih;
+        if (m > 0) {
+            out[pk_im(nn, m)] = acc[4 * k + 1] * ih;
+            out[P2 + pk_im(nn, m)] = acc[4 * k + 3] * ih;
+        }
     }
 }
 
@@ -730,7 +735,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
 // so the leaf's stored local coefficients gain c_n^m += (-1)^n Phi_n^m / h and
 // d_n^m += (-1)^n Chi_n^m / h (the bar form: c = i^m phi h^n, d = i^m chi h^(n+1)).
 // Elements in chunks of ch: the lanes first form the St columns of the chunk in LDS, then every
-// lane adds the chunk's contributions to its coefficient rows.  Runs after the downward pass
+// lane adds the chunk's contributions to its (n, m) pairs (both potentials, Re and Im).  Runs after the downward pass
 // and before L2P; only the leaf's own wavefront writes its local expansion.
 template <typename T>
 __global__ void __launch_bounds__(WAVE) k_p2l(int p, const int32_t *__restrict__ leaves,
@@ -742,7 +747,7 @@ __global__ void __launch_bounds__(WAVE) k_p2l(int p, const int32_t *__restrict__
                                               T *__restrict__ Lc, int ch)
 {
     extern __shared__ char smem[];
-    const int P1 = p + 1, SS = P1 * P1, P2 = p * p;
+    const int P1 = p + 1, SS = P1 * P1, P2 = p * p, TRI = p * (p + 1) / 2;
     T *Sre = (T *)smem;               // [ch][n <= p][m <= n]
     T *Sim = Sre + (size_t)ch * SS;
     T *wsh = Sim + (size_t)ch * SS;   // [ch][4]: omega, q
@@ -757,9 +762,9 @@ __global__ void __launch_bounds__(WAVE) k_p2l(int p, const int32_t *__restrict__
     double c0, c1, c2, hd;
     box_centre(bkey[b], level, sys_geo, c0, c1, c2, hd);
     const T ih = (T)(1.0 / hd);
-    T acc[NRMAX];
+    T acc[4 * NPMAX];  // per (n, m) pair of the lane: Re c, Im c, Re d, Im d
 #pragma unroll
-    for (int k = 0; k < NRMAX; k++) acc[k] = 0;
+    for (int k = 0; k < 4 * NPMAX; k++) acc[k] = 0;
     for (int e = ea; e < eb; e++) {
         const int code = wx_ent[e];
         if (!(code & 1)) continue;
@@ -801,13 +806,15 @@ __global__ void __launch_bounds__(WAVE) k_p2l(int p, const int32_t *__restrict__
                 }
             }
             __syncthreads();
+            // lane per (n, m >= 0) pair: the U values of orders n and n + 1 serve all four outputs
 #pragma unroll
-            for (int k = 0; k < NRMAX; k++) {
-                const int r = lane + WAVE * k;
-                if (r >= 2 * P2) break;
-                const int pot = r >= P2;
-                int nn, m, part;
-                decode_row(r - pot * P2, nn, m, part);
+            for (int k = 0; k < NPMAX; k++) {
+                const int t = lane + WAVE * k;
+                if (t >= TRI) break;
+                int nn = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+                while (nn * (nn + 1) / 2 > t) --nn;
+                while ((nn + 1) * (nn + 2) / 2 <= t) ++nn;
+                const int m = t - nn * (nn + 1) / 2;
                 const T sgn = (nn & 1) ? (T)-1 : (T)1;
                 for (int el = 0; el < ne; el++) {
                     const T *Re = Sre + (size_t)el * SS, *Im = Sim + (size_t)el * SS;
@@ -825,8 +832,7 @@ __global__ void __launch_bounds__(WAVE) k_p2l(int p, const int32_t *__restrict__
                             im = -Im[n2 * P1 + kk];
                         }
                     };
-                    T vre, vim;
-                    if (pot == 0) {
+                    {
                         // Phi = -D/n - q U, D = -(i/2)[(wx+iwy)(n-m) U^{m+1} + (wx-iwy)(n+m) U^{m-1}] - i wz m U^m
                         T upr, upi, umr, umi, u0r, u0i;
                         U(nn, m + 1, upr, upi);
@@ -838,29 +844,40 @@ __global__ void __launch_bounds__(WAVE) k_p2l(int p, const int32_t *__restrict__
                         const T dre = (T)0.5 * xi + wz * (T)m * u0i;
                         const T dim = (T)-0.5 * xr - wz * (T)m * u0r;
                         const T inv = nn > 0 ? (T)1 / (T)nn : (T)0;
-                        vre = -dre * inv - qe * u0r;
-                        vim = -dim * inv - qe * u0i;
-                    } else {
+                        acc[4 * k + 0] += sgn * (-dre * inv - qe * u0r);
+                        acc[4 * k + 1] += sgn * (-dim * inv - qe * u0i);
+                    }
+                    {
                         // Chi = [1/2 (wx-iwy) U_{n+1}^{m-1} - 1/2 (wx+iwy) U_{n+1}^{m+1} + wz U_{n+1}^m] / (n+1)
                         T umr, umi, upr, upi, u0r, u0i;
                         U(nn + 1, m - 1, umr, umi);
                         U(nn + 1, m + 1, upr, upi);
                         U(nn + 1, m, u0r, u0i);
                         const T inv = (T)1 / (T)(nn + 1);
-                        vre = ((T)0.5 * (wx * umr + wy * umi) - (T)0.5 * (wx * upr - wy * upi) + wz * u0r) * inv;
-                        vim = ((T)0.5 * (wx * umi - wy * umr) - (T)0.5 * (wx * upi + wy * upr) + wz * u0i) * inv;
+                        acc[4 * k + 2] +=
+                            sgn * ((T)0.5 * (wx * umr + wy * umi) - (T)0.5 * (wx * upr - wy * upi) + wz * u0r) * inv;
+                        acc[4 * k + 3] +=
+                            sgn * ((T)0.5 * (wx * umi - wy * umr) - (T)0.5 * (wx * upi + wy * upr) + wz * u0i) * inv;
                     }
-                    acc[k] += sgn * (part ? vim : vre);
                 }
             }
         }
     }
     T *out = Lc + (size_t)b * 2 * P2;
 #pragma unroll
-    for (int k = 0; k < NRMAX; k++) {
-        const int r = lane + WAVE * k;
-        if (r >= 2 * P2) break;
-        out[r] += acc[k] * ih;
+    for (int k = 0; k < NPMAX; k++) {
+        const int t = lane + WAVE * k;
+        if (t >= TRI) break;
+        int nn = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while (nn * (nn + 1) / 2 > t) --nn;
+        while ((nn + 1) * (nn + 2) / 2 <= t) ++nn;
+        const int m = t - nn * (nn + 1) / 2;
+        out[pk_re(nn, m)] += acc[4 * k] * ih;
+        out[P2 + pk_re(nn, m)] += acc[4 * k + 2] * ih;
+        if (m > 0) {
+            out[pk_im(nn, m)] += acc[4 * k + 1] * ih;
+            out[P2 + pk_im(nn, m)] += acc[4 * k + 3] * ih;
+        }
     }
 }
 
