@@ -79,6 +79,10 @@ def lib():
         L.lho_adaptive_coverage.argtypes = [C.c_int64, _dp, C.c_int64, C.c_int, _dp, C.c_double,
                                             C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lho_adaptive_counts.argtypes = [C.c_int64, _dp, C.c_int64, C.c_int, _dp, C.c_double, _ip, _ip]
+        L.lho_scalar_direct.argtypes = [C.c_int64, _dp, _dp, C.c_int64, C.c_void_p, _dp, _dp]
+        L.lho_fmm_scalar.argtypes = [C.c_int64, _dp, _dp, C.c_int, C.c_int, _dp, C.c_double, C.c_int, C.c_int64,
+                                     C.c_void_p, _dp, _dp, C.POINTER(_Stats)]
+        L.lho_fmm_scalar.restype = C.c_int
         _lib = L
     return _lib
 
@@ -372,3 +376,48 @@ def adaptive_counts(x, max_per_leaf, max_level, lo=(0.0, 0.0, 0.0), L=1.0):
     nl = np.zeros(max_level + 1, np.int64)
     lib().lho_adaptive_counts(x.shape[0], x, int(max_per_leaf), int(max_level), _f64(lo, (3,)), float(L), nb, nl)
     return nb, nl
+
+
+def scalar_direct(x, q, targets=None):
+    """Direct sums of the scalar potential Phi_j = sum_{i != j} q_i / |x_j - x_i| and of grad Phi
+    (singular kernel) at the targets (all elements when None): returns (phi [T], grad [T, 3])."""
+    x = _f64(x).reshape(-1, 3)
+    q = _f64(q).reshape(-1)
+    n = x.shape[0]
+    if targets is None:
+        nt, tp, m = 0, None, n
+    else:
+        targets = np.ascontiguousarray(targets, np.int64)
+        nt, tp, m = targets.shape[0], targets.ctypes.data, targets.shape[0]
+    phi = np.zeros(m)
+    g = np.zeros((m, 3))
+    lib().lho_scalar_direct(n, x, q, nt, tp, phi, g)
+    return phi, g
+
+
+def fmm_scalar(x, q, p, depth, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True, sample=None):
+    """Scalar harmonic FMM of Phi and grad Phi on the uniform octree (the single-potential
+    comparison workload): returns (phi [N], grad [N, 3], stats); with ``sample`` only the leaves
+    holding those elements are evaluated (other outputs NaN)."""
+    x = _f64(x).reshape(-1, 3)
+    q = _f64(q).reshape(-1)
+    n = x.shape[0]
+    phi = np.zeros(n)
+    g = np.zeros((n, 3))
+    if sample is None:
+        ns, sp = 0, None
+    else:
+        sample = np.ascontiguousarray(sample, np.int64)
+        ns, sp = sample.shape[0], sample.ctypes.data
+    st = _Stats()
+    what = (1 if far else 0) | (2 if near else 0)
+    rc = lib().lho_fmm_scalar(n, x, q, int(p), int(depth), _f64(lo, (3,)), float(L), what, ns, sp, phi, g,
+                              C.byref(st))
+    if rc != 0:
+        raise ValueError("oracle scalar fmm rejected its arguments")
+    if sample is not None:
+        mask = np.zeros(n, bool)
+        mask[_leaf_members(x, depth, lo, L, sample)] = True
+        phi[~mask] = np.nan
+        g[~mask] = np.nan
+    return phi, g, dict(n_m2l=st.n_m2l, n_p2p_pairs=st.n_p2p_pairs)

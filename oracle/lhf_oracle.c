@@ -1838,3 +1838,236 @@ void lho_adaptive_counts(int64_t n, const double *x, int64_t maxleaf, int maxl, 
     }
     atree_free(&A);
 }
+
+/* ---------------------------------------------------------------------------------------------
+ * Scalar harmonic FMM: the comparison workload of Sec. 5.2 (potential and gradient of sources in
+ * a potential flow, run on the same tree at the same truncation number):
+ *   Phi(y_j) = sum_{i != j} q_i / |y_j - x_i|,   grad Phi(y_j) = -sum_{i != j} q_i (y_j - x_i) / |y_j - x_i|^3
+ * with the singular kernel everywhere.  The expansions carry the single potential phi:
+ *   P2M   phi_n^m = sum q_i g_n^m(x_i - c), the expansion of eq. rsbf5 of each source (the monopole
+ *         part of eq. eve4 with the opposite sign: there the monopole enters v with a minus);
+ *   M2M, M2L, L2L by eq. mr3 on the pair (phi, chi = 0): the conversions of eqs. drt10 / drt11
+ *         add chi terms only, so phi is translated as a scalar expansion and chi stays zero;
+ *   L2P   Phi = sum_n sum_m phi_n^m R_n^m(y - c), grad Phi by eq. evf3 with chi = 0;
+ *   near field over adjacent leaves.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Direct sums of Phi and grad Phi at the targets (all elements when targets == NULL), the
+ * target's own source excluded. */
+void lho_scalar_direct(int64_t n, const double *x, const double *q, int64_t nt, const int64_t *targets, double *phi,
+                       double *gphi)
+{
+    int64_t m = targets ? nt : n;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < m; k++) {
+        int64_t j = targets ? targets[k] : k;
+        double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+        for (int64_t i = 0; i < n; i++) {
+            if (i == j) continue;
+            double r[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
+            double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            if (r2 == 0.0) continue;
+            double ir = 1.0 / sqrt(r2), ir3 = ir * ir * ir;
+            f += q[i] * ir;
+            for (int d = 0; d < 3; d++) g[d] -= q[i] * r[d] * ir3;
+        }
+        phi[k] = f;
+        for (int d = 0; d < 3; d++) gphi[3 * k + d] = g[d];
+    }
+}
+
+/* Scalar FMM on the uniform octree of the given depth.  what / sample as in lho_fmm (outputs of
+ * the elements of the sampled leaves, others untouched).  Returns 0 on success. */
+int lho_fmm_scalar(int64_t n, const double *x, const double *q, int p, int depth, const double lo[3], double L,
+                   int what, int64_t nsample, const int64_t *sample, double *phi, double *gphi, lho_stats *st)
+{
+    if (depth < 2 || depth > 8 || p < 1 || n < 1) return -1;
+    otree T;
+    tree_build(&T, n, x, depth, lo, L);
+    size_t P2 = (size_t)p * p;
+    lho_stats stats;
+    memset(&stats, 0, sizeof(stats));
+    int64_t nleaf = T.nb[depth];
+    char *want = (char *)calloc((size_t)nleaf + 1, 1);
+    if (!sample) {
+        memset(want, 1, (size_t)nleaf);
+    } else {
+        int sh = QBITS - depth;
+        for (int64_t i = 0; i < nsample; i++) {
+            int64_t e = sample[i];
+            int64_t b = tree_find(&T, depth, morton(T.q[3 * e] >> sh, T.q[3 * e + 1] >> sh, T.q[3 * e + 2] >> sh));
+            if (b >= 0) want[b] = 1;
+        }
+    }
+    if (what & 1) {
+        /* upward: P2M at the leaves, M2M to level 2 (phi only; chi inputs zero, chi outputs discarded) */
+        cplx *M[MAXLEV + 1], *Lc[MAXLEV + 1];
+        for (int l = 2; l <= depth; l++) {
+            M[l] = (cplx *)calloc((size_t)T.nb[l] * P2 + 1, sizeof(cplx));
+            Lc[l] = (cplx *)calloc((size_t)T.nb[l] * P2 + 1, sizeof(cplx));
+        }
+        double *wzero = (double *)calloc(3 * (size_t)n, sizeof(double));
+#pragma omp parallel
+        {
+            cplx *zero = (cplx *)calloc(P2, sizeof(cplx)), *sink = (cplx *)calloc(P2, sizeof(cplx));
+            cplx *tmp = (cplx *)calloc(P2, sizeof(cplx));
+            double *bx = NULL, *bw = NULL, *bq = NULL;
+            int64_t cap = 0;
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t b = 0; b < nleaf; b++) {
+                int64_t c = T.count[depth][b];
+                if (c > cap) {
+                    free(bx);
+                    free(bw);
+                    free(bq);
+                    cap = c;
+                    bx = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                    bw = (double *)malloc(sizeof(double) * 3 * (size_t)cap);
+                    bq = (double *)malloc(sizeof(double) * (size_t)cap);
+                }
+                box_points(&T, x, wzero, q, depth, b, bx, bw, bq);  /* no vortex strengths */
+                double cen[3];
+                box_centre(&T, depth, T.key[depth][b], cen);
+                memset(tmp, 0, sizeof(cplx) * P2);
+                memset(sink, 0, sizeof(cplx) * P2);
+                lho_p2m_method2(p, cen, c, bx, bw, bq, tmp, sink);  /* phi = -sum q g */
+                cplx *ph = &M[depth][(size_t)b * P2];
+                for (size_t k = 0; k < P2; k++) ph[k] = -tmp[k];
+            }
+            free(bx);
+            free(bw);
+            free(bq);
+            free(zero);
+            free(sink);
+            free(tmp);
+        }
+        for (int l = depth - 1; l >= 2; l--) {
+#pragma omp parallel
+            {
+                cplx *zero = (cplx *)calloc(P2, sizeof(cplx)), *sink = (cplx *)calloc(P2, sizeof(cplx));
+#pragma omp for schedule(dynamic, 4)
+                for (int64_t b = 0; b < T.nb[l]; b++) {
+                    double cp[3];
+                    box_centre(&T, l, T.key[l][b], cp);
+                    for (int chn = 0; chn < 8; chn++) {
+                        int64_t cb = tree_find(&T, l + 1, (T.key[l][b] << 3) | (uint64_t)chn);
+                        if (cb < 0) continue;
+                        double cc[3];
+                        box_centre(&T, l + 1, T.key[l + 1][cb], cc);
+                        double t[3] = {cp[0] - cc[0], cp[1] - cc[1], cp[2] - cc[2]};
+                        lho_m2m(p, t, &M[l + 1][(size_t)cb * P2], zero, &M[l][(size_t)b * P2], sink);
+                    }
+                }
+                free(zero);
+                free(sink);
+            }
+        }
+        /* downward: L2L from the parent and M2L over the V-list, every box of levels 2..depth */
+        int64_t nm2l = 0;
+        for (int l = 2; l <= depth; l++) {
+#pragma omp parallel reduction(+ : nm2l)
+            {
+                cplx *zero = (cplx *)calloc(P2, sizeof(cplx)), *sink = (cplx *)calloc(P2, sizeof(cplx));
+#pragma omp for schedule(dynamic, 4)
+                for (int64_t b = 0; b < T.nb[l]; b++) {
+                    double ct[3];
+                    box_centre(&T, l, T.key[l][b], ct);
+                    cplx *ph = &Lc[l][(size_t)b * P2];
+                    if (l > 2) {
+                        int64_t pb = tree_find(&T, l - 1, T.key[l][b] >> 3);
+                        double cp[3];
+                        box_centre(&T, l - 1, T.key[l - 1][pb], cp);
+                        double t[3] = {ct[0] - cp[0], ct[1] - cp[1], ct[2] - cp[2]};
+                        lho_l2l(p, t, &Lc[l - 1][(size_t)pb * P2], zero, ph, sink);
+                    }
+                    int64_t vl[189];
+                    int nv = vlist(&T, l, T.key[l][b], vl);
+                    for (int i = 0; i < nv; i++) {
+                        double cs[3];
+                        box_centre(&T, l, T.key[l][vl[i]], cs);
+                        double t[3] = {ct[0] - cs[0], ct[1] - cs[1], ct[2] - cs[2]};
+                        lho_m2l(p, t, &M[l][(size_t)vl[i] * P2], zero, ph, sink);
+                    }
+                    nm2l += nv;
+                }
+                free(zero);
+                free(sink);
+            }
+        }
+        stats.n_m2l = nm2l;
+        /* L2P: Phi = sum phi_n^m R_n^m, grad Phi from eq. evf3 with chi = 0 */
+#pragma omp parallel
+        {
+            cplx *zero = (cplx *)calloc(P2, sizeof(cplx)), *R = (cplx *)malloc(sizeof(cplx) * P2);
+#pragma omp for schedule(dynamic, 4)
+            for (int64_t b = 0; b < nleaf; b++) {
+                if (!want[b]) continue;
+                double cen[3];
+                box_centre(&T, depth, T.key[depth][b], cen);
+                const cplx *ph = &Lc[depth][(size_t)b * P2];
+                for (int64_t i = 0; i < T.count[depth][b]; i++) {
+                    int64_t e = T.order[T.first[depth][b] + i];
+                    double r[3] = {x[3 * e] - cen[0], x[3 * e + 1] - cen[1], x[3 * e + 2] - cen[2]};
+                    lho_basis_R(p, r, R);
+                    cplx f = 0.0;
+                    for (size_t k = 0; k < P2; k++) f += ph[k] * R[k];
+                    phi[e] += creal(f);
+                    double w0[3] = {0, 0, 0}, vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gg[9];
+                    lho_l2p(p, cen, ph, zero, 1, &x[3 * e], w0, vv, ss, gg, NULL, NULL);
+                    for (int d = 0; d < 3; d++) gphi[3 * e + d] += vv[d];
+                }
+            }
+            free(zero);
+            free(R);
+        }
+        for (int l = 2; l <= depth; l++) {
+            free(M[l]);
+            free(Lc[l]);
+        }
+        free(wzero);
+    }
+    if (what & 2) {
+        /* near field: adjacent leaves (incl. the own one), singular kernel */
+        int64_t npairs = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : npairs)
+        for (int64_t b = 0; b < nleaf; b++) {
+            if (!want[b]) continue;
+            int c[3];
+            box_coords(T.key[depth][b], c);
+            int nside = 1 << depth;
+            for (int64_t it = 0; it < T.count[depth][b]; it++) {
+                int64_t j = T.order[T.first[depth][b] + it];
+                double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+                for (int dz = -1; dz <= 1; dz++)
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++) {
+                            int cc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                            if (cc[0] < 0 || cc[1] < 0 || cc[2] < 0 || cc[0] >= nside || cc[1] >= nside ||
+                                cc[2] >= nside)
+                                continue;
+                            int64_t nb = tree_find(&T, depth, morton((uint32_t)cc[0], (uint32_t)cc[1], (uint32_t)cc[2]));
+                            if (nb < 0) continue;
+                            for (int64_t k = 0; k < T.count[depth][nb]; k++) {
+                                int64_t i = T.order[T.first[depth][nb] + k];
+                                if (i == j) continue;
+                                double r[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1],
+                                               x[3 * j + 2] - x[3 * i + 2]};
+                                double r2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+                                if (r2 == 0.0) continue;
+                                double ir = 1.0 / sqrt(r2), ir3 = ir * ir * ir;
+                                f += q[i] * ir;
+                                for (int d = 0; d < 3; d++) g[d] -= q[i] * r[d] * ir3;
+                                npairs++;
+                            }
+                        }
+                phi[j] += f;
+                for (int d = 0; d < 3; d++) gphi[3 * j + d] += g[d];
+            }
+        }
+        stats.n_p2p_pairs = npairs;
+    }
+    if (st) *st = stats;
+    free(want);
+    tree_free(&T);
+    return 0;
+}
