@@ -1,6 +1,6 @@
 """Benchmark of one FMM evaluation of v and s (the whole hot path) on one GPU.
 
-    python bench.py [--steps K] [--warmup W] [--p P] [--legs ring16,wx,cube,batch]
+    python bench.py [--steps K] [--warmup W] [--p P] [--legs ring16,wx,scalar,cube,batch]
                     [--no-cpu-baseline] [--calib-copy MIB]
 
 A step is one pass of the whole path over the synthetic input, already resident
@@ -15,8 +15,9 @@ split-kernel direct sum are both <= 1e-6 (p = 23 by the error-vs-order sweep; th
 run measures the errors it reaches on 4096 seeded targets with the oracle).  The
 other legs are labelled sections of the same line: the same ring at p = 16 in FP32
 and FP64 (the precision speedup), the ring in FP64 at p = 16 with the W/X lists by
-M2P / P2L instead of direct sums, the 2^20-element uniform cube (FP64 p = 12, FP32
-p = 10) and the batch of 256 systems.
+M2P / P2L instead of direct sums, the scalar harmonic FMM against the vortex FMM on
+the 2^20-element cube (the paper's comparison), the 2^20-element uniform cube (FP64
+p = 12, FP32 p = 10) and the batch of 256 systems.
 
 Roofline: per phase (gather, P2M, M2M, M2L + L2L, L2P, P2P) the algorithmic work
 (flop and compulsory HBM bytes, counted in roofline_work()) against the MI355X
@@ -123,19 +124,23 @@ def measured_traffic(name):
         return None
 
 
-def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warmup, wx=False):
+def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warmup, wx=False, q=None):
     """time `steps` plan + execute steps (inputs resident on the device); per-phase times from the
     library's HIP events on the execute stream"""
     dt = torch.float64 if prec == lhf.FP64 else torch.float32
     xt = torch.from_numpy(x).to(device="cuda", dtype=dt)
     wt = torch.from_numpy(w).to(device="cuda", dtype=dt)
     v, s = torch.empty_like(wt), torch.empty_like(wt)
+    qt = None if q is None else torch.from_numpy(q).to(device="cuda", dtype=dt)
 
     def step(profile):
         pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=max_per_leaf, wx_expansions=wx)
         if profile:
             pl.profile_begin(1)
-        pl.execute(wt, v, s)
+        if qt is None:
+            pl.execute(wt, v, s)
+        else:  # the scalar harmonic FMM of the sources q on the same tree
+            pl.execute_scalar(qt)
         ph = pl.profile_end()[0] if profile else None
         st = pl.stats()
         pl.close()
@@ -155,7 +160,8 @@ def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warm
     exec_ms = sum(vv for kk, vv in phases.items() if kk != "m2l")  # m2l is part of "down"
     log(f"bench: {name}: {ms:.2f} ms per step (execute {exec_ms:.2f} ms, M2L {phases['m2l']:.2f} ms)")
     n = x.shape[0]
-    m2l_tf = st["n_m2l"] * f_m2l(p) / (phases["m2l"] * 1e-3) / 1e12 if phases["m2l"] > 0 else None
+    # (the flop model counts both potentials: not applied to the scalar FMM)
+    m2l_tf = st["n_m2l"] * f_m2l(p) / (phases["m2l"] * 1e-3) / 1e12 if phases["m2l"] > 0 and q is None else None
     res = {"workload": name, "n": n, "p": p, "precision": "fp64" if prec == lhf.FP64 else "fp32",
            "steps": steps, "ms_per_step": ms, "elements_per_s": n / (ms * 1e-3), "execute_ms": exec_ms,
            "plan_ms": ms - exec_ms, "execute_only_elements_per_s": n / (exec_ms * 1e-3), "phases_ms": phases,
@@ -170,7 +176,8 @@ def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warm
     else:
         res["m2l_frac_of_fp32_valu_peak"] = m2l_tf / PEAK_FP32_VALU_TFLOPS if m2l_tf else None
         res["m2l_frac_of_fp32_mfma_peak"] = m2l_tf / PEAK_FP32_MFMA_TFLOPS if m2l_tf else None
-    res["phase_roofline"], res["aggregate_roofline"] = phase_roofline(st, phases, p, prec, n)
+    if q is None:
+        res["phase_roofline"], res["aggregate_roofline"] = phase_roofline(st, phases, p, prec, n)
     out = (v.double().cpu().numpy(), s.double().cpu().numpy())
     del xt, wt, v, s
     return res, st, out
@@ -337,8 +344,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--p", type=int, default=P_STAR, help="order of the headline (FP64 ring) leg")
     ap.add_argument("--leg-steps", type=int, default=20, help="timed steps of the ring p = 16 and cube legs")
-    ap.add_argument("--legs", default="ring16,wx,cube,batch",
-                    help="comma list of ring16, wx, cube, batch (or none)")
+    ap.add_argument("--legs", default="ring16,wx,scalar,cube,batch",
+                    help="comma list of ring16, wx, scalar, cube, batch (or none)")
     ap.add_argument("--targets", type=int, default=4096, help="sample targets of the headline accuracy")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle legs (baseline, accuracy)")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -445,6 +452,24 @@ def main():
         if "ring_p16" in out:
             r["ms_vs_direct_wx"] = r["ms_per_step"] / out["ring_p16"]["fp64"]["ms_per_step"]
         out["ring_p16_wx"] = r
+    if "scalar" in legs:
+        # the paper's comparison (Sec. 5.2): the scalar harmonic FMM (potential and gradient of
+        # sources) on the 2^20 cube against the vortex FMM (v and s) on the same tree and p
+        sc = {}
+        for wl in ("cube1m_fp64", "cube1m_fp32"):
+            c = workloads.make(wl)
+            prec = lhf.FP64 if c["precision"] == "fp64" else lhf.FP32
+            qv = np.random.default_rng(c["seed"] + 100).normal(size=c["n"])
+            r, _, _ = run_leg(lhf, torch, wl + "_scalar", c["x"], c["w"], 0.0, c["p"], prec, c["depth"], 0,
+                              args.leg_steps, args.warmup, q=qv)
+            rv, _, _ = run_leg(lhf, torch, wl, c["x"], c["w"], c["a"], c["p"], prec, c["depth"], 0,
+                               args.leg_steps, args.warmup)
+            r["vortex_ms_per_step"] = rv["ms_per_step"]
+            r["vortex_execute_ms"] = rv["execute_ms"]
+            r["ratio_vortex_to_scalar_execute"] = rv["execute_ms"] / r["execute_ms"]
+            r["ratio_vortex_to_scalar_m2l"] = rv["phases_ms"]["m2l"] / r["phases_ms"]["m2l"]
+            sc[wl] = r
+        out["scalar_vs_vortex"] = sc
     if "cube" in legs:
         cube = {}
         for wl in ("cube1m_fp64", "cube1m_fp32"):

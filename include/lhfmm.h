@@ -215,6 +215,17 @@ typedef struct {
  * LHF_OUT_GRAD.  Enqueued on 'stream'; no host synchronisation, no allocation. */
 lhf_status lhf_execute_io(lhf_plan *plan, const lhf_io *io, void *stream);
 
+/* Scalar harmonic FMM on the plan's tree (the paper's single-potential comparison workload,
+ * Sec. 5.2): with the plan's elements as sources of strength q and as receivers,
+ *   phi_j = sum_{i != j} q_i / |x_j - x_i|,   grad_phi_j = -sum_{i != j} q_i (x_j - x_i) / |x_j - x_i|^3
+ * with the singular kernel (the plan's core radius is not used).  The expansions carry the single
+ * potential phi: P2M of the sources, the plan's M2M / M2L / L2L on phi alone (the half-vector M2L
+ * translates phi without conversion at p = 8, 10, 12, 16; the other kernels on (phi, chi = 0)),
+ * L2P of phi and grad phi, near field over the adjacent leaves.  q [N], phi [N], grad_phi [N][3]
+ * (may be NULL): device pointers of the plan's precision, input order.  Uniform single-system plans
+ * only (else LHF_ERR_UNSUPPORTED).  Enqueued on 'stream'; no host synchronisation, no allocation. */
+lhf_status lhf_execute_scalar(lhf_plan *plan, const void *q, void *phi, void *grad_phi, void *stream);
+
 /* One-shot: plan_create + execute + destroy (synchronises the stream; allocates and frees the
  * plan's device buffers).  p = 0 chooses the order from tol as in lhf_plan_create. */
 lhf_status lhf_evaluate(const lhf_desc *d, int64_t n, const void *x, const void *omega, double a,

@@ -1962,14 +1962,26 @@ int lho_fmm_scalar(int64_t n, const double *x, const double *q, int p, int depth
                 free(sink);
             }
         }
-        /* downward: L2L from the parent and M2L over the V-list, every box of levels 2..depth */
+        /* downward: L2L from the parent and M2L over the V-list, every box of levels 2..depth (when
+         * sampling: only the ancestor chains of the wanted leaves) */
         int64_t nm2l = 0;
+        char *need[MAXLEV + 1] = {0};
+        for (int l = 2; l <= depth; l++) {
+            need[l] = (char *)calloc((size_t)T.nb[l] + 1, 1);
+            for (int64_t b = 0; b < T.nb[l]; b++) need[l][b] = (char)!sample;
+        }
+        if (sample)
+            for (int64_t b = 0; b < nleaf; b++)
+                if (want[b])
+                    for (int la = 2; la <= depth; la++)
+                        need[la][tree_find(&T, la, T.key[depth][b] >> (3 * (depth - la)))] = 1;
         for (int l = 2; l <= depth; l++) {
 #pragma omp parallel reduction(+ : nm2l)
             {
                 cplx *zero = (cplx *)calloc(P2, sizeof(cplx)), *sink = (cplx *)calloc(P2, sizeof(cplx));
 #pragma omp for schedule(dynamic, 4)
                 for (int64_t b = 0; b < T.nb[l]; b++) {
+                    if (!need[l][b]) continue;
                     double ct[3];
                     box_centre(&T, l, T.key[l][b], ct);
                     cplx *ph = &Lc[l][(size_t)b * P2];
@@ -2023,6 +2035,7 @@ int lho_fmm_scalar(int64_t n, const double *x, const double *q, int p, int depth
         for (int l = 2; l <= depth; l++) {
             free(M[l]);
             free(Lc[l]);
+            free(need[l]);
         }
         free(wzero);
     }

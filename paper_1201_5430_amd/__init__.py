@@ -34,7 +34,7 @@ EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_plan_create_multi", "lhf_
            "lhf_evaluate", "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version",
            "lhf_profile_begin", "lhf_profile_end", "lhf_tune_default", "lhf_autotune", "lhf_choose_depth",
            "lhf_batch_create", "lhf_batch_execute", "lhf_batch_info", "lhf_batch_destroy",
-           "lhf_release_cached_memory", "lhf_evaluate_noalloc", "lhf_execute_io")
+           "lhf_release_cached_memory", "lhf_evaluate_noalloc", "lhf_execute_io", "lhf_execute_scalar")
 PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 
 
@@ -90,6 +90,8 @@ def load():
         L.lhf_execute_parts.argtypes = [vp, vp, vp, vp, vp, C.c_int32, vp]
         L.lhf_execute_io.argtypes = [vp, C.POINTER(IO), vp]
         L.lhf_execute_io.restype = C.c_int
+        L.lhf_execute_scalar.argtypes = [vp, vp, vp, vp, vp]
+        L.lhf_execute_scalar.restype = C.c_int
         L.lhf_execute_parts.restype = C.c_int
         L.lhf_evaluate.argtypes = [C.POINTER(Desc), C.c_int64, vp, vp, C.c_double, vp, vp, vp]
         L.lhf_evaluate.restype = C.c_int
@@ -155,11 +157,14 @@ def _stream():
 
 def _dev_array(t, dtype, name, n=None, width=3):
     """check a caller tensor before its pointer crosses the C ABI: on the device, of the plan's
-    dtype, contiguous, [N, width] (and N == n when given)"""
+    dtype, contiguous, [N, width] ([N] when width is None; N == n when given)"""
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a HIP device tensor")
-    if t.dtype != dtype or t.dim() != 2 or t.shape[1] != width or not t.is_contiguous():
+    if width is None:
+        if t.dtype != dtype or t.dim() != 1 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous [N] {dtype} tensor")
+    elif t.dtype != dtype or t.dim() != 2 or t.shape[1] != width or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous [N,{width}] {dtype} tensor")
     if n is not None and t.shape[0] != n:
         raise ValueError(f"{name} has {t.shape[0]} rows, the plan has {n} elements")
@@ -251,6 +256,18 @@ class Plan:
         if b is not None:
             out = out + (b,)
         return out
+
+    def execute_scalar(self, q, phi=None, grad=None):
+        """Scalar harmonic FMM (singular kernel): phi_j = sum_{i != j} q_i / r_ij and grad phi
+        ([N], [N, 3]); uniform single-system plans only."""
+        import torch
+        q = _dev_array(q, self.dtype, "q", self.n, width=None)
+        phi = torch.empty_like(q) if phi is None else _dev_array(phi, self.dtype, "phi", self.n, width=None)
+        grad = (torch.empty((self.n, 3), dtype=self.dtype, device=q.device) if grad is None
+                else _dev_array(grad, self.dtype, "grad", self.n))
+        _check(load().lhf_execute_scalar(self._h, C.c_void_p(q.data_ptr()), C.c_void_p(phi.data_ptr()),
+                                         C.c_void_p(grad.data_ptr()), _stream()))
+        return phi, grad
 
     def stats(self):
         st = Stats()

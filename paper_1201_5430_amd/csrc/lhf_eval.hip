@@ -15,6 +15,8 @@
 // per-translation intermediate vectors in LDS.
 #include <hip/hip_runtime.h>
 
+#include <functional>
+
 #include <algorithm>
 #include <math.h>
 
@@ -27,6 +29,9 @@ void m2l_mfma_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_half_stage(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st);
+bool m2l_half_scalar_supported(int precision, int p);
+void m2l_half_scalar_stage(const lhf_plan *Pl, int level, hipStream_t st);
+void m2l_half_scalar_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_quarter_stage(const lhf_plan *Pl, int level, hipStream_t st);
 void m2m_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void l2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
@@ -76,7 +81,8 @@ __device__ inline void box_centre(uint64_t key, int level, const double *__restr
 //   Rt_n^m = ((2n-1) z Rt_{n-1}^m - r^2 Rt_{n-2}^m) / ((n-m)(n+m)),
 // then every lane adds the eq. eve4 contributions of its (n, m) pairs (both potentials, Re and Im).
 // ---------------------------------------------------------------------------
-template <typename T>
+// SC: scalar harmonic FMM -- phi = sum q g_n^m (the expansion of eq. rsbf5 of each source), chi = 0
+template <typename T, bool SC = false>
 __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off, const int32_t *__restrict__ leaves,
                                               const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
                                               const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
@@ -142,9 +148,9 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                 p1im = cim;
             }
             if (m == 0) {
-                wsh[4 * e] = ws[i];
-                wsh[4 * e + 1] = ws[n + i];
-                wsh[4 * e + 2] = ws[2 * n + i];
+                wsh[4 * e] = SC ? (T)0 : ws[i];
+                wsh[4 * e + 1] = SC ? (T)0 : ws[n + i];
+                wsh[4 * e + 2] = SC ? (T)0 : ws[2 * n + i];
                 wsh[4 * e + 3] = qs ? qs[i] : (T)0;
             }
         }
@@ -184,6 +190,13 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                 };
                 const T wmre = wx, wmim = -wy;  // wx - i wy
                 const T wpre = wx, wpim = wy;   // wx + i wy
+                if constexpr (SC) {
+                    T c3re, c3im;
+                    C(nn, m, c3re, c3im);
+                    acc[4 * k + 0] += qe * sgn * c3re;
+                    acc[4 * k + 1] += qe * sgn * c3im;
+                    continue;
+                }
                 {
                     // a = -i (-1)^m / (n+1) [ (wx-iwy)(n-m+1)/2 C(m-1) + (wx+iwy)(n+m+1)/2 C(m+1) + wz m C(m) ]
                     T c1re, c1im, c2re, c2im, c3re, c3im;
@@ -1417,6 +1430,174 @@ __global__ void __launch_bounds__(64) k_p2p_tile(int64_t n, const int32_t *__res
     }
 }
 
+// ---------------------------------------------------------------------------
+// Scalar harmonic FMM (the single-potential comparison workload): Phi = sum q / r and grad Phi.
+// ---------------------------------------------------------------------------
+// L2P of Phi and grad Phi: Phi(y) = sum (-1)^n c_n^m Rt_n^m(yhat) (bar form, no scale factor),
+// grad Phi = (1/h) sum (-1)^n V Rt with the velocity coefficients of eq. evf3 at chi = 0.
+// Four leaves per 64-lane workgroup as in k_l2p; rows 0 (Phi) and 1..3 (grad Phi) of vfar.
+template <typename T>
+__global__ void __launch_bounds__(WAVE) k_l2p_scalar(int p, int depth, int64_t nleaf, int64_t leaf_off,
+                                                     const uint64_t *__restrict__ bkey,
+                                                     const int32_t *__restrict__ bstart,
+                                                     const int32_t *__restrict__ bcount, const T *__restrict__ xs,
+                                                     int64_t n, const double *__restrict__ sys_geo,
+                                                     const T *__restrict__ Lc, T *__restrict__ vfar)
+{
+    extern __shared__ char smem[];
+    const int P2 = p * p;
+    const int TRI = p * (p + 1) / 2;
+    const int g = threadIdx.x / L2P_LANES, lane = threadIdx.x % L2P_LANES;
+    T *Cre = (T *)smem + (size_t)g * 8 * TRI, *Cim = Cre + 4 * TRI;  // [4][TRI]: Phi, V_x, V_y, V_z
+    const int64_t li = (int64_t)blockIdx.x * L2P_LPB + g;
+    const bool has = li < nleaf;
+    const int64_t b = has ? leaf_off + li : 0;
+    const T *cd = Lc + (size_t)b * 2 * P2;
+    auto get = [&](int nn, int m, T &re, T &im) {
+        if (nn < 0 || nn >= p || m > nn || (m == -1 && nn < 1)) {
+            re = 0;
+            im = 0;
+        } else if (m == -1) {
+            re = -cd[pk_re(nn, 1)];
+            im = cd[pk_im(nn, 1)];
+        } else {
+            re = cd[pk_re(nn, m)];
+            im = m ? cd[pk_im(nn, m)] : (T)0;
+        }
+    };
+    if (has)
+        for (int t = lane; t < TRI; t += L2P_LANES) {
+            int nn = 0;
+            while ((nn + 1) * (nn + 2) / 2 <= t) nn++;
+            const int m = t - nn * (nn + 1) / 2;
+            T c0r, c0i, pm1r, pm1i, pp1r, pp1i, p0r, p0i;
+            get(nn, m, c0r, c0i);
+            get(nn + 1, m - 1, pm1r, pm1i);
+            get(nn + 1, m + 1, pp1r, pp1i);
+            get(nn + 1, m, p0r, p0i);
+            Cre[t] = c0r;
+            Cim[t] = c0i;
+            Cre[TRI + t] = (T)0.5 * (-pm1r + pp1r);  // V_x = 1/2 (-P^{m-1} + P^{m+1})
+            Cim[TRI + t] = (T)0.5 * (-pm1i + pp1i);
+            Cre[2 * TRI + t] = (T)0.5 * (-pm1i - pp1i);  // V_y = i/2 (P^{m-1} + P^{m+1})
+            Cim[2 * TRI + t] = (T)0.5 * (pm1r + pp1r);
+            Cre[3 * TRI + t] = -p0r;  // V_z = -P^m
+            Cim[3 * TRI + t] = -p0i;
+        }
+    __syncthreads();
+    if (!has) return;
+    const int s0 = bstart[b], cnt = bcount[b];
+    double c0, c1, c2, hd;
+    box_centre(bkey[b], depth, sys_geo, c0, c1, c2, hd);
+    const T ih = (T)(1.0 / hd);
+    for (int e0 = 0; e0 < cnt; e0 += L2P_LANES) {
+        const int e = e0 + lane;
+        if (e >= cnt) break;
+        const int i = s0 + e;
+        const T x = (xs[i] - (T)c0) * ih, y = (xs[n + i] - (T)c1) * ih, z = (xs[2 * n + i] - (T)c2) * ih;
+        const T r2 = x * x + y * y + z * z;
+        L2PAcc<T> f[4];
+        T mre = 1, mim = 0;
+        for (int m = 0; m < p; m++) {
+            if (m > 0) {
+                const T fm = (T)(-0.5) / (T)m;
+                const T nre = fm * (mre * x - mim * y), nim = fm * (mre * y + mim * x);
+                mre = nre;
+                mim = nim;
+            }
+            T p1re = mre, p1im = mim, p2re = 0, p2im = 0;
+            const T wgt = m ? (T)2 : (T)1;
+            for (int nn = m; nn < p; nn++) {
+                T rre, rim;
+                if (nn == m) {
+                    rre = mre;
+                    rim = mim;
+                } else if (nn == m + 1) {
+                    rre = z * p1re;
+                    rim = z * p1im;
+                } else {
+                    const T inv = (T)1 / (T)((nn - m) * (nn + m));
+                    rre = ((T)(2 * nn - 1) * z * p1re - r2 * p2re) * inv;
+                    rim = ((T)(2 * nn - 1) * z * p1im - r2 * p2im) * inv;
+                }
+                if (nn > m) {
+                    p2re = p1re;
+                    p2im = p1im;
+                    p1re = rre;
+                    p1im = rim;
+                }
+                const T sw = (nn & 1) ? -wgt : wgt;
+                const int t = nn * (nn + 1) / 2 + m;
+                for (int k = 0; k < 4; k++) f[k].add(sw * (Cre[k * TRI + t] * rre - Cim[k * TRI + t] * rim));
+            }
+        }
+        vfar[i] = f[0].value();
+        for (int k = 1; k < 4; k++) vfar[(size_t)k * n + i] = f[k].value() * ih;
+    }
+}
+
+// near field of the scalar FMM on the uniform tree, lane per target over the 27 adjacent leaves
+// (singular kernel), combined with the far field and written in input order
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2p_scalar(int64_t n, int64_t leaf_off, const int32_t *__restrict__ eleaf,
+                                                    const int32_t *__restrict__ ulist,
+                                                    const int32_t *__restrict__ bstart,
+                                                    const int32_t *__restrict__ bcount, const T *__restrict__ xw,
+                                                    const T *__restrict__ vfar, const int32_t *__restrict__ perm,
+                                                    T *__restrict__ phi, T *__restrict__ gphi)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T xj = xw[8 * i], yj = xw[8 * i + 1], zj = xw[8 * i + 2];
+    CompSum<T> acc[4];
+    for (int k = 0; k < 4; k++) acc[k].add(vfar[(size_t)k * n + i]);
+    const int32_t *U = ulist + (size_t)(eleaf[i] - leaf_off) * 27;
+    for (int u = 0; u < 27; u++) {
+        const int nb = U[u];
+        if (nb < 0) continue;
+        T f = 0, g0 = 0, g1 = 0, g2 = 0;
+        const int st = bstart[nb], ct = bcount[nb];
+        for (int k = st; k < st + ct; k++) {
+            if (k == i) continue;
+            const Rec<T> r = load_rec<true>(xw, k);
+            const T rx = xj - r.x, ry = yj - r.y, rz = zj - r.z;
+            const T r2 = rx * rx + ry * ry + rz * rz;
+            if (r2 == (T)0) continue;
+            const T ir = (T)1 / sqrt(r2), qir = r.q * ir, qir3 = qir * ir * ir;
+            f += qir;
+            g0 -= qir3 * rx;
+            g1 -= qir3 * ry;
+            g2 -= qir3 * rz;
+        }
+        acc[0].add(f);
+        acc[1].add(g0);
+        acc[2].add(g1);
+        acc[3].add(g2);
+    }
+    const int64_t o = perm[i];
+    phi[o] = acc[0].value();
+    if (gphi)
+        for (int k = 0; k < 3; k++) gphi[3 * o + k] = acc[1 + k].value();
+}
+
+// gather the source strengths into the sorted order and the near-field records (no vortex part)
+template <typename T>
+__global__ void k_gather_q(int64_t n, const T *__restrict__ q, const int32_t *__restrict__ perm,
+                           const T *__restrict__ xs, T *__restrict__ qs, T *__restrict__ xw)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const T qo = q[perm[i]];
+    qs[i] = qo;
+    T *r = xw + 8 * i;
+    r[0] = xs[i];
+    r[1] = xs[n + i];
+    r[2] = xs[2 * n + i];
+    r[3] = r[4] = r[5] = (T)0;
+    r[6] = qo;
+    r[7] = (T)0;
+}
+
 // gather omega into the sorted SoA layout
 template <typename T>
 __global__ void k_gather_w(int64_t n, const T *__restrict__ w, const T *__restrict__ q,
@@ -1461,6 +1642,62 @@ static void p2p_launch(lhf_plan *P, int what, T *v, T *s, T *g, T *b, unsigned n
     }
 }
 
+// M2M into levels depth-1 .. 2, then per level L2L and M2L (events ev[3] after the upward pass and
+// ev[7 + 2l], ev[8 + 2l] around the M2L of level l).  scalar: the expansions carry phi only (chi is
+// zero and stays zero through every translation); where the half-vector kernel has a scalar
+// instantiation it translates phi alone, the other kernels run on (phi, 0).
+template <typename T>
+static void translations(lhf_plan *P, hipStream_t st, bool scalar, const std::function<void(int)> &mark)
+{
+    const int p = P->p, d = P->depth;
+    const int P2 = p * p, ZS = (p + 1) * (p + 1);
+    T *M = (T *)P->M, *Lc = (T *)P->Lc;
+    const T *rot = (const T *)P->rot, *zph = (const T *)P->zph, *coax = (const T *)P->coax;
+    const bool sc_half = scalar && P->use_half && !P->use_mfma && m2l_half_scalar_supported(P->precision, p);
+        size_t sh_rcr = sizeof(T) * (4 * P2 + 2 * ZS + 2 * p + 2);
+    for (int l = d - 1; l >= 2; l--) {
+        if (P->lev[l].nb == 0) continue;
+        if (P->use_mmhalf) m2m_half_launch(P, l, st);
+        else
+            hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, P->lev[l].off,
+                               P->bchild0, P->bnchild, P->bkey, M, rot, zph, P->dir_theta);
+    }
+    mark(3);
+    for (int l = 2; l <= d; l++) {
+        if (P->lev[l].nb == 0) {
+            mark(7 + 2 * l);
+            mark(8 + 2 * l);
+            continue;
+        }
+        if (P->use_tile) {
+            // L2L from the parents (zeros at level 2), then the batched M2L adds into it
+            if (P->use_mmhalf) l2l_half_launch(P, l, st);
+            else
+                hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 0,
+                                   P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M,
+                                   Lc, rot, zph, P->dir_theta, coax);
+            // the half-vector kernel reads its sources from a copy in its lane layout
+            // (timed with L2L, outside the M2L phase)
+            if (sc_half) m2l_half_scalar_stage(P, l, st);
+            else if (!P->use_mfma && P->use_half) m2l_half_stage(P, l, st);
+            if (P->use_quarter) m2l_quarter_stage(P, l, st);
+            mark(7 + 2 * l);
+            if (P->use_mfma) m2l_mfma_launch(P, l, st);
+            else if (sc_half) m2l_half_scalar_launch(P, l, st);
+            else if (P->use_half) m2l_half_launch(P, l, st);
+            else if (P->use_quarter) m2l_quarter_launch(P, l, st);
+            else m2l_tile_launch(P, l, st);
+            mark(8 + 2 * l);
+        } else {
+            mark(7 + 2 * l);
+            hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 1,
+                               P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M, Lc,
+                               rot, zph, P->dir_theta, coax);
+            mark(8 + 2 * l);
+        }
+    }
+}
+
 template <typename T>
 static lhf_status execute_t(lhf_plan *P, const lhf_io *io, hipStream_t st)
 {
@@ -1478,7 +1715,7 @@ static lhf_status execute_t(lhf_plan *P, const lhf_io *io, hipStream_t st)
     hipEvent_t *ev = nullptr;
     if (P->prof_ev && P->prof_used < P->prof_cap) ev = P->prof_ev + (size_t)(P->prof_used++) * PROF_EV_PER_EXEC;
     // ev[0..6]: phase boundaries; ev[7 + 2l], ev[8 + 2l]: around the M2L launch of level l
-    auto mark = [&](int k) {
+    const std::function<void(int)> mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
@@ -1495,46 +1732,7 @@ static lhf_status execute_t(lhf_plan *P, const lhf_io *io, hipStream_t st)
                            P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, qin ? (const T *)P->qs : nullptr,
                            n, P->sys_geo, M, ch);
         mark(2);
-        size_t sh_rcr = sizeof(T) * (4 * P2 + 2 * ZS + 2 * p + 2);
-        for (int l = d - 1; l >= 2; l--) {
-            if (P->lev[l].nb == 0) continue;
-            if (P->use_mmhalf) m2m_half_launch(P, l, st);
-            else
-                hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, P->lev[l].off,
-                                   P->bchild0, P->bnchild, P->bkey, M, rot, zph, P->dir_theta);
-        }
-        mark(3);
-        for (int l = 2; l <= d; l++) {
-            if (P->lev[l].nb == 0) {
-                mark(7 + 2 * l);
-                mark(8 + 2 * l);
-                continue;
-            }
-            if (P->use_tile) {
-                // L2L from the parents (zeros at level 2), then the batched M2L adds into it
-                if (P->use_mmhalf) l2l_half_launch(P, l, st);
-                else
-                    hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 0,
-                                       P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M,
-                                       Lc, rot, zph, P->dir_theta, coax);
-                // the half-vector kernel reads its sources from a copy in its lane layout
-                // (timed with L2L, outside the M2L phase)
-                if (!P->use_mfma && P->use_half) m2l_half_stage(P, l, st);
-                if (P->use_quarter) m2l_quarter_stage(P, l, st);
-                mark(7 + 2 * l);
-                if (P->use_mfma) m2l_mfma_launch(P, l, st);
-                else if (P->use_half) m2l_half_launch(P, l, st);
-                else if (P->use_quarter) m2l_quarter_launch(P, l, st);
-                else m2l_tile_launch(P, l, st);
-                mark(8 + 2 * l);
-            } else {
-                mark(7 + 2 * l);
-                hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 1,
-                                   P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M, Lc,
-                                   rot, zph, P->dir_theta, coax);
-                mark(8 + 2 * l);
-            }
-        }
+        translations<T>(P, st, false, mark);
         mark(4);
         // W/X by expansions: X sources into the leaves' local expansions before L2P, W boxes'
         // multipoles evaluated at the leaves' elements after it
@@ -1577,6 +1775,53 @@ static lhf_status execute_t(lhf_plan *P, const lhf_io *io, hipStream_t st)
     mark(6);
     LHF_HIP(hipGetLastError());
     return LHF_OK;
+}
+
+// scalar harmonic FMM on the plan's uniform tree: Phi and grad Phi of the sources q (singular
+// kernel); gphi may be null
+template <typename T>
+static lhf_status execute_scalar_t(lhf_plan *P, const T *q, T *phi, T *gphi, hipStream_t st)
+{
+    const int p = P->p, d = P->depth;
+    const int64_t n = P->n;
+    const int P2 = p * p;
+    T *xs = (T *)P->xs, *M = (T *)P->M, *vfar = (T *)P->vfar;
+    const int tpb = 256;
+    const unsigned nblk = (unsigned)((n + tpb - 1) / tpb);
+    hipEvent_t *ev = nullptr;
+    if (P->prof_ev && P->prof_used < P->prof_cap) ev = P->prof_ev + (size_t)(P->prof_used++) * PROF_EV_PER_EXEC;
+    const std::function<void(int)> mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], st);
+    };
+    mark(0);
+    hipLaunchKernelGGL(k_gather_q<T>, dim3(nblk), dim3(tpb), 0, st, n, q, P->perm, (const T *)xs, (T *)P->qs,
+                       (T *)P->xw);
+    mark(1);
+    const int64_t loff = P->lev[d].off, nleaf = P->lev[d].nb;
+    const int ch = std::max(1, std::min(8, (int)(49152 / (sizeof(T) * (2 * P2 + 4)))));
+    hipLaunchKernelGGL((k_p2m<T, true>), dim3((unsigned)nleaf), dim3(WAVE), sizeof(T) * (size_t)ch * (2 * P2 + 4), st,
+                       p, d, loff, nullptr, nullptr, P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)P->ws,
+                       (const T *)P->qs, n, P->sys_geo, M, ch);
+    mark(2);
+    translations<T>(P, st, true, mark);
+    mark(4);
+    const int TRI = p * (p + 1) / 2;
+    hipLaunchKernelGGL(k_l2p_scalar<T>, dim3((unsigned)((nleaf + L2P_LPB - 1) / L2P_LPB)), dim3(WAVE),
+                       sizeof(T) * L2P_LPB * 8 * TRI, st, p, d, nleaf, loff, P->bkey, P->bstart, P->bcount,
+                       (const T *)xs, n, P->sys_geo, (const T *)P->Lc, vfar);
+    mark(5);
+    hipLaunchKernelGGL(k_p2p_scalar<T>, dim3(nblk), dim3(tpb), 0, st, n, loff, P->eleaf, P->ulist, P->bstart,
+                       P->bcount, (const T *)P->xw, (const T *)vfar, P->perm, phi, gphi);
+    mark(6);
+    LHF_HIP(hipGetLastError());
+    return LHF_OK;
+}
+
+lhf_status execute_scalar_impl(lhf_plan *P, const void *q, void *phi, void *gphi, hipStream_t st)
+{
+    if (P->precision == LHF_FP64)
+        return execute_scalar_t<double>(P, (const double *)q, (double *)phi, (double *)gphi, st);
+    return execute_scalar_t<float>(P, (const float *)q, (float *)phi, (float *)gphi, st);
 }
 
 lhf_status execute_impl(lhf_plan *P, const lhf_io *io, hipStream_t st)

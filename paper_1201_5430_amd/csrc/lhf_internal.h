@@ -184,6 +184,7 @@ inline hipError_t dev_malloc(T **p, size_t bytes)
     return dev_malloc_raw((void **)p, bytes);
 }
 lhf_status execute_impl(lhf_plan *P, const lhf_io *io, hipStream_t st);
+lhf_status execute_scalar_impl(lhf_plan *P, const void *q, void *phi, void *gphi, hipStream_t st);
 // order from tolerance and kernel choice (host only)
 bool choose_order(bool adaptive, int precision, double tol, int *p);
 void calib_error(bool adaptive, int p, double *ev, double *es);

@@ -245,11 +245,18 @@ constexpr int tile_npar()
            : half_tiles<T, P>() ? 1
            : tile_bytes<T, P, false>(4) <= LDS_HALF ? 4 : (tile_bytes<T, P, false>(2) <= LDS_HALF ? 2 : 1);
 }
-// tiles of one level: NPAR sibling groups each, or half a sibling group each
+// the scalar translations always run in shared mode (LDS atomics); the largest parent count
+// that leaves room for two workgroups per compute unit
 template <typename T, int P>
+constexpr int tile_npar_sc()
+{
+    return tile_bytes<T, P, false>(4) <= LDS_HALF ? 4 : (tile_bytes<T, P, false>(2) <= LDS_HALF ? 2 : 1);
+}
+// tiles of one level: NPAR sibling groups each, or half a sibling group each
+template <typename T, int P, int NPAR>
 constexpr int64_t n_tiles(int64_t npar)
 {
-    return half_tiles<T, P>() ? 2 * npar : (npar + tile_npar<T, P>() - 1) / tile_npar<T, P>();
+    return half_tiles<T, P>() ? 2 * npar : (npar + NPAR - 1) / NPAR;
 }
 
 }  // namespace hv
@@ -260,7 +267,11 @@ constexpr int64_t n_tiles(int64_t npar)
 // per child position), so the 8 translations of a batch hit 8 distinct targets that no other
 // lane touches: accumulation is a plain LDS read-add-write.
 // Tiles without any child box leave at once; a wavefront skips batches with no active lane.
-template <typename T, int P, int NPAR, bool OWN>
+// SC (scalar harmonic FMM, p <= 16, shared mode): only the potential phi is translated, without
+// conversion (chi is absent); the lanes of the other potential carry a second translation, so a
+// wavefront runs 16 translations per batch, and the sources come in the four-role scalar lane
+// layout.
+template <typename T, int P, int NPAR, bool OWN, bool SC = false>
 __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int level, int64_t poff, int64_t npar,
                                                   const uint64_t *__restrict__ bkey,
                                                   const int32_t *__restrict__ bchild0,
@@ -284,6 +295,9 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     using A = hv::Acc<T, OWN>;
     static_assert(!OWN || NPAR == 4, "ownership mode: one sibling group per wavefront");
     static_assert(!HT || (NPAR == 1 && !OWN), "half tiles: shared mode, one parent");
+    static_assert(!SC || (!HT && !OWN), "scalar translations: orders up to 16, shared mode");
+    constexpr int NROLE = SC ? 4 : 8;      // lane roles of one translation
+    constexpr int NPOT = SC ? 1 : 2;       // potentials in the target slots
     T *Wl = (T *)smem;                                // [kind: fwd S, back R][part][parity][WHS]
     A *acc = (A *)(Wl + hv::staged_tables<T, P>() * Sh::WHS);  // [NSLOT + 1][SSTA] (last slot absorbs)
     int *slot_xyz = (int *)(acc + (NSLOT + 1) * SSTA);  // [NSLOT] packed target coordinates, -1: no box
@@ -294,7 +308,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // XCD-aware tile order: consecutive tiles stay on one XCD (shared L2)
-    const int64_t ntiles = hv::n_tiles<T, P>(npar);
+    const int64_t ntiles = hv::n_tiles<T, P, NPAR>(npar);
     const int64_t per = (ntiles + 7) / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= ntiles) return;
@@ -358,14 +372,15 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     // entries without an (n, m) start at zero and are never read back)
     for (int idx = tid; idx < NSLOT * SSTA; idx += 256) acc[idx] = (A)0;
     __syncthreads();
-    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
-        const int sl = idx / (2 * P2), r = idx % (2 * P2);
+    for (int idx = tid; idx < NSLOT * NPOT * P2; idx += 256) {
+        const int sl = idx / (NPOT * P2), r = idx % (NPOT * P2);
         const int box = slot_box[sl];
         if (box >= 0) acc[sl * SSTA + hv::acc_pos<P, OWN, ARS>(r)] = (A)Lc[(size_t)box * 2 * P2 + r];
     }
 
     const int side = 1 << level;
-    const int t = lane >> 3, pot = (lane >> 2) & 1, part = (lane >> 1) & 1, h = lane & 1;
+    const int t = lane >> 3, pot = SC ? 0 : (lane >> 2) & 1, part = (lane >> 1) & 1, h = lane & 1;
+    const int t2 = SC ? (lane >> 2) & 1 : 0;  // scalar: second translation of the lane group
 
     struct Job {
         int slot, dir, src;
@@ -382,7 +397,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
             slot = wave * 8 + t;
         } else {
             const int e0 = cst[k], cnt = cst[k + 1] - e0;
-            const int tr = r0 + wave * 8 + t;
+            const int tr = r0 + (SC ? wave * 16 + 2 * t + t2 : wave * 8 + t);
             if (tr >= NPAR * cnt) return j;
             const int code = ent[e0 + tr / NPAR];
             dir = code >> 3;
@@ -401,7 +416,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         return j;
     };
     auto advance = [&](int &k, int &r0) {
-        r0 += OWN ? 1 : 32;
+        r0 += (OWN ? 1 : 32) * (SC ? 2 : 1);
         if (k < ncls && r0 >= (OWN ? 1 : NPAR) * (cst[k + 1] - cst[k])) {
             k++;
             r0 = 0;
@@ -412,7 +427,8 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
     auto load_part = [&](const Job &j, T *dst) {
         using V = typename hv::V16<T>::type;
         constexpr int e = hv::E<T>();
-        const V *sp = (const V *)(Mh + ((size_t)(j.src >= 0 ? j.src - soff : 0) * 8 + (lane & 7)) * NHP);
+        const V *sp =
+            (const V *)(Mh + ((size_t)(j.src >= 0 ? j.src - soff : 0) * NROLE + (lane & (NROLE - 1))) * NHP);
 #pragma unroll
         for (int q = 0; q < NHP / e; q++) {
             const V x = sp[q];
@@ -561,7 +577,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
                     }
                     T qo = pc * itau;
 #pragma unroll
-                    for (int n = n0; n <= P; n++) {
+                    for (int n = n0; n <= (SC ? P - 1 : P); n++) {
                         T a = 0;
 #pragma unroll
                         for (int n2 = n0; n2 < P; n2++) a += (T)dfact(n + n2) * v[hoff(n2) + c];
@@ -574,7 +590,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
 #pragma unroll
                     for (int n2 = n0; n2 < P; n2++) cl[n2] = v[hoff(n2) + c] * pw[n2];
 #pragma unroll
-                    for (int n = n0; n <= P; n++) {
+                    for (int n = n0; n <= (SC ? P - 1 : P); n++) {
                         T a = 0;
 #pragma unroll
                         for (int n2 = n0; n2 < P; n2++) a += (T)dfact(n + n2) * cl[n2];
@@ -583,10 +599,15 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
                 }
 #pragma unroll
                 for (int n = n0; n < P; n++) {
-                    const T other = swz_xor<6>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
-                    const T fphi = (n > 0) ? tau * mval * (T)(1.0 / (double)n) * sconv * wphi : (T)0;
-                    const T fchi = -tau * (T)(1.0 / (double)(n + 1)) * wchi;
-                    T val = out[n] + fphi * other + fchi * out[n + 1];
+                    T val;
+                    if constexpr (SC) {
+                        val = out[n];  // a single potential: no conversion
+                    } else {
+                        const T other = swz_xor<6>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
+                        const T fphi = (n > 0) ? tau * mval * (T)(1.0 / (double)n) * sconv * wphi : (T)0;
+                        const T fchi = -tau * (T)(1.0 / (double)(n + 1)) * wchi;
+                        val = out[n] + fphi * other + fchi * out[n + 1];
+                    }
                     if (n == n0) val *= keep0;
                     v[hoff(n) + c] = val;
                 }
@@ -631,7 +652,7 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         // 6. back-rotation about z (-phi) and accumulation into the target slot (inactive lanes
         //    add into the spare slot; in ownership mode so do entries without an (n, m))
         {
-            A *ap = acc + (size_t)(act ? j.slot : NSLOT) * SSTA + (OWN ? po * (P2 + 1) : (lane & 7) * ARS);
+            A *ap = acc + (size_t)(act ? j.slot : NSLOT) * SSTA + (OWN ? po * (P2 + 1) : (lane & (NROLE - 1)) * ARS);
             A *spare = acc + (size_t)NSLOT * SSTA + (OWN ? po * (P2 + 1) : 0);
             const T sgn = pp ? (T)-1 : (T)1;  // Re' = re c + im s, Im' = im c - re s
             double cm = hh ? cph : 1.0, sm = hh ? sph : 0.0;
@@ -670,8 +691,8 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
         r1 = r2;
     }
     __syncthreads();
-    for (int idx = tid; idx < NSLOT * 2 * P2; idx += 256) {
-        const int sl = idx / (2 * P2), r = idx % (2 * P2);
+    for (int idx = tid; idx < NSLOT * NPOT * P2; idx += 256) {
+        const int sl = idx / (NPOT * P2), r = idx % (NPOT * P2);
         const int box = slot_box[sl];
         if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = (T)acc[sl * SSTA + hv::acc_pos<P, OWN, ARS>(r)];
     }
@@ -681,11 +702,11 @@ __global__ void __launch_bounds__(256, (hv::min_waves<T, P>())) k_m2l_half(int l
 // Mh[(b * 8 + role) * NHP], role = 4 pot + 2 part + h (the lane's low three bits), entry
 // hoff(n) + j = order n, m = 2j + h of that potential and part; zero where m > n, for (Im, m = 0)
 // and in the padding
-template <typename T, int P>
+template <typename T, int P, int NR = 8>
 __global__ void __launch_bounds__(256) k_mhalf(int64_t off, int64_t nb, const T *__restrict__ M, T *__restrict__ Mh)
 {
     using Sh = hv::Shape<T, P>;
-    constexpr int NHP = Sh::NHP, NH = Sh::NH, NE = 8 * NHP, P2 = P * P;
+    constexpr int NHP = Sh::NHP, NH = Sh::NH, NE = NR * NHP, P2 = P * P;  // NR = 4: phi only (scalar)
     // packed index of every lane-layout entry of a box (-1: zero)
     __shared__ int16_t src[NE];
     for (int t = threadIdx.x; t < NE; t += blockDim.x) {
@@ -1040,22 +1061,30 @@ static bool whalf_build_t(lhf_plan *Pl, hipStream_t st)
     int64_t nbmax = 0;
     for (int l = 2; l <= Pl->depth; l++) nbmax = std::max(nbmax, Pl->lev[l].nb);
     if (nbmax > 0 && dev_malloc(&Pl->mh, sizeof(T) * 8 * hv::Shape<T, P>::NHP * nbmax) != hipSuccess) return false;
+    if constexpr (!hv::half_tiles<T, P>()) {
+        constexpr int NPS = hv::tile_npar_sc<T, P>();
+        if (hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPS, false, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)hv::tile_bytes<T, P, false>(NPS)) != hipSuccess)
+            return false;
+    }
     return hipFuncSetAttribute((const void *)k_m2l_half<T, P, NPAR, OWN>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess;
 }
 
-template <typename T, int P>
+template <typename T, int P, bool SC = false>
 static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
 {
-    constexpr int NPAR = hv::tile_npar<T, P>();
-    constexpr bool OWN = hv::tile_own<T, P>();
+    // scalar translations: shared mode (two schedule rows per batch would share their targets)
+    constexpr bool OWN = SC ? false : hv::tile_own<T, P>();
+    constexpr int NPAR = SC ? hv::tile_npar_sc<T, P>() : hv::tile_npar<T, P>();
     const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
     const int64_t soff = Pl->lev[level].off, nb = Pl->lev[level].nb;
     if (nb == 0 || npar == 0) return;
-    const int64_t ntiles = hv::n_tiles<T, P>(npar);
+    const int64_t ntiles = hv::n_tiles<T, P, NPAR>(npar);
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
-    k_m2l_half<T, P, NPAR, OWN><<<dim3((unsigned)(per * 8)), dim3(256),
+    k_m2l_half<T, P, NPAR, OWN, SC><<<dim3((unsigned)(per * 8)), dim3(256),
                                                           hv::tile_bytes<T, P, OWN>(NPAR),
                                                      st>>>(
         level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const T *)Pl->mh, soff,
@@ -1063,13 +1092,13 @@ static void launch_half(const lhf_plan *Pl, int level, hipStream_t st)
 }
 
 // the sources of level l in the half-vector kernel's lane layout
-template <typename T, int P>
+template <typename T, int P, int NR = 8>
 static void stage_half(const lhf_plan *Pl, int level, hipStream_t st)
 {
     const int64_t nb = Pl->lev[level].nb;
     if (nb == 0) return;
-    k_mhalf<T, P><<<dim3((unsigned)std::min<int64_t>(nb, 8192)), dim3(256), 0, st>>>(Pl->lev[level].off, nb,
-                                                                                     (const T *)Pl->M, (T *)Pl->mh);
+    k_mhalf<T, P, NR><<<dim3((unsigned)std::min<int64_t>(nb, 8192)), dim3(256), 0, st>>>(
+        Pl->lev[level].off, nb, (const T *)Pl->M, (T *)Pl->mh);
 }
 
 // rotation tables of the M2M (S basis both ways) and L2L (R basis both ways) shifts
@@ -1169,6 +1198,51 @@ void l2l_half_launch(const lhf_plan *Pl, int l, hipStream_t st)
         return;
     }
     mm_dispatch<2>(Pl, l, st);
+}
+
+// scalar harmonic FMM (phi only): the orders without half tiles
+bool m2l_half_scalar_supported(int precision, int p)
+{
+    (void)precision;
+    return p == 8 || p == 10 || p == 12 || p == 16;
+}
+
+void m2l_half_scalar_stage(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    if (Pl->precision == LHF_FP64) {
+        switch (Pl->p) {
+        case 8: stage_half<double, 8, 4>(Pl, level, st); break;
+        case 10: stage_half<double, 10, 4>(Pl, level, st); break;
+        case 12: stage_half<double, 12, 4>(Pl, level, st); break;
+        case 16: stage_half<double, 16, 4>(Pl, level, st); break;
+        }
+    } else {
+        switch (Pl->p) {
+        case 8: stage_half<float, 8, 4>(Pl, level, st); break;
+        case 10: stage_half<float, 10, 4>(Pl, level, st); break;
+        case 12: stage_half<float, 12, 4>(Pl, level, st); break;
+        case 16: stage_half<float, 16, 4>(Pl, level, st); break;
+        }
+    }
+}
+
+void m2l_half_scalar_launch(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    if (Pl->precision == LHF_FP64) {
+        switch (Pl->p) {
+        case 8: launch_half<double, 8, true>(Pl, level, st); break;
+        case 10: launch_half<double, 10, true>(Pl, level, st); break;
+        case 12: launch_half<double, 12, true>(Pl, level, st); break;
+        case 16: launch_half<double, 16, true>(Pl, level, st); break;
+        }
+    } else {
+        switch (Pl->p) {
+        case 8: launch_half<float, 8, true>(Pl, level, st); break;
+        case 10: launch_half<float, 10, true>(Pl, level, st); break;
+        case 12: launch_half<float, 12, true>(Pl, level, st); break;
+        case 16: launch_half<float, 16, true>(Pl, level, st); break;
+        }
+    }
 }
 
 bool m2l_half_supported(int precision, int p)

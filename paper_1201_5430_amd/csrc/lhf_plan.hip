@@ -1672,6 +1672,18 @@ lhf_status lhf_execute_io(lhf_plan *plan, const lhf_io *io, void *stream)
     return execute_impl(plan, io, (hipStream_t)stream);
 }
 
+lhf_status lhf_execute_scalar(lhf_plan *plan, const void *q, void *phi, void *grad_phi, void *stream)
+{
+    if (!plan) return arg_error("plan is NULL");
+    if (!q || !phi) return arg_error("q and phi must be non-NULL");
+    if (plan->adaptive || plan->nsys != 1) {
+        set_error("the scalar FMM runs on single-system uniform trees only");
+        return LHF_ERR_UNSUPPORTED;
+    }
+    plan->stream = (hipStream_t)stream;
+    return execute_scalar_impl(plan, q, phi, grad_phi, (hipStream_t)stream);
+}
+
 lhf_status lhf_execute_parts(lhf_plan *plan, const void *omega, void *v, void *s, void *grad_v, int32_t what,
                              void *stream)
 {

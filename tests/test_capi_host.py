@@ -138,3 +138,9 @@ def test_output_tensors_are_checked_on_the_host():
         L._dev_array(torch.zeros(5, 3, dtype=torch.float64), torch.float64, "v")
     with pytest.raises(TypeError):
         L._dev_array(np.zeros((5, 3)), torch.float64, "v")
+
+
+def test_scalar_entry_point_checks_its_arguments():
+    L, lib = _lib()
+    assert lib.lhf_execute_scalar(None, C.c_void_p(0x1000), C.c_void_p(0x1000), None, None) == -1
+    assert "plan" in lib.lhf_last_error().decode()
