@@ -24,6 +24,7 @@ _lib = None
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 _cp = np.ctypeslib.ndpointer(dtype=np.complex128, flags="C_CONTIGUOUS")
 _ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 
 
 def build(force: bool = True) -> str:
@@ -80,6 +81,11 @@ def lib():
                                             C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lho_adaptive_counts.argtypes = [C.c_int64, _dp, C.c_int64, C.c_int, _dp, C.c_double, _ip, _ip]
         L.lho_scalar_direct.argtypes = [C.c_int64, _dp, _dp, C.c_int64, C.c_void_p, _dp, _dp]
+        L.lho_gauss_legendre.argtypes = [C.c_int, _dp, _dp]
+        L.lho_filament_direct.argtypes = [C.c_int64, _dp, C.c_int64, _i32p, _dp, C.c_int64, C.c_void_p, _dp]
+        L.lho_filament_fmm.argtypes = [C.c_int64, _dp, C.c_int64, _i32p, _dp, C.c_int, C.c_int, _dp, C.c_double,
+                                       C.c_int, C.c_int, _dp, C.POINTER(_Stats)]
+        L.lho_filament_fmm.restype = C.c_int
         L.lho_fmm_scalar.argtypes = [C.c_int64, _dp, _dp, C.c_int, C.c_int, _dp, C.c_double, C.c_int, C.c_int64,
                                      C.c_void_p, _dp, _dp, C.POINTER(_Stats)]
         L.lho_fmm_scalar.restype = C.c_int
@@ -421,3 +427,48 @@ def fmm_scalar(x, q, p, depth, lo=(0.0, 0.0, 0.0), L=1.0, far=True, near=True, s
         phi[~mask] = np.nan
         g[~mask] = np.nan
     return phi, g, dict(n_m2l=st.n_m2l, n_p2p_pairs=st.n_p2p_pairs)
+
+
+def gauss_legendre(nq):
+    """Gauss-Legendre nodes and weights on [-1, 1]"""
+    xi = np.zeros(nq)
+    w = np.zeros(nq)
+    lib().lho_gauss_legendre(int(nq), xi, w)
+    return xi, w
+
+
+def _segs(seg):
+    return np.ascontiguousarray(np.asarray(seg).reshape(-1, 2), np.int32)
+
+
+def filament_direct(X, seg, G, targets=None):
+    """velocity (eq. dis2, no 1/(4 pi)) of the straight segments seg [S, 2] (vertex indices) with
+    circulations G at the vertices X (the targets' own segments skipped): [T, 3]"""
+    X = _f64(X).reshape(-1, 3)
+    seg = _segs(seg)
+    G = _f64(G).reshape(-1)
+    nv = X.shape[0]
+    if targets is None:
+        nt, tp, m = 0, None, nv
+    else:
+        targets = np.ascontiguousarray(targets, np.int64)
+        nt, tp, m = targets.shape[0], targets.ctypes.data, targets.shape[0]
+    v = np.zeros((m, 3))
+    lib().lho_filament_direct(nv, X, seg.shape[0], seg, G, nt, tp, v)
+    return v
+
+
+def filament_fmm(X, seg, G, p, depth, lo=(0.0, 0.0, 0.0), L=1.0, nq=0, far=True, near=True):
+    """FMM of the filament velocity at the vertices (tree on segment centres and vertices,
+    quadrature P2M with nq points per segment, 0: floor((p-1)/2)+1): returns (v [V, 3], stats)"""
+    X = _f64(X).reshape(-1, 3)
+    seg = _segs(seg)
+    G = _f64(G).reshape(-1)
+    v = np.zeros((X.shape[0], 3))
+    st = _Stats()
+    what = (1 if far else 0) | (2 if near else 0)
+    rc = lib().lho_filament_fmm(X.shape[0], X, seg.shape[0], seg, G, int(p), int(depth), _f64(lo, (3,)), float(L),
+                                int(nq), what, v, C.byref(st))
+    if rc != 0:
+        raise ValueError("oracle filament fmm rejected its arguments")
+    return v, dict(n_m2l=st.n_m2l, n_p2p_pairs=st.n_p2p_pairs)

@@ -2084,3 +2084,251 @@ int lho_fmm_scalar(int64_t n, const double *x, const double *q, int p, int depth
     tree_free(&T);
     return 0;
 }
+
+/* ---------------------------------------------------------------------------------------------
+ * Vortex filaments (Sec. 5.3, App. B): straight segments C_i from X[s0_i] to X[s1_i] with constant
+ * circulation G_i; receivers are the vertices X.  With the library's convention (no 1/(4 pi), as
+ * for the particles), the velocity of one segment at y not on it is eq. dis2 without its factor:
+ *   v_i(y) = G_i (r1 x r2) / (r1 r2 + r1 . r2) (1/r1 + 1/r2),  r1 = y - x1, r2 = y - x2,
+ * and v_i(y) = 0 for y on C_i (a vertex of the segment).  Far away a segment is the point vortex
+ * of strength G_i l_i (l_i = x2 - x1) at its centre; its multipole is that of N_q Gauss-Legendre
+ * points x_c + l xi_j / 2 with strengths G_i l_i w_j / 2 (eqs. vf5, vf6), exact for every order
+ * n < p when N_q = floor((p - 1)/2) + 1 (eq. vf7).
+ * ------------------------------------------------------------------------------------------- */
+
+/* Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_nq (nq <= 64) */
+void lho_gauss_legendre(int nq, double *xi, double *w)
+{
+    for (int i = 0; i < nq; i++) {
+        double x = cos(M_PI * (i + 0.75) / (nq + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= nq; k++) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (nq == 1) {
+                p1 = x;
+                p0 = 1.0;
+            }
+            dp = nq * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= nq; k++) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (nq == 1) {
+                p1 = x;
+                p0 = 1.0;
+            }
+            dp = nq * (x * p1 - p0) / (x * x - 1.0);
+        }
+        xi[i] = x;
+        w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+/* velocity of segment (x1, x2, G) at y (eq. dis2 without 1/(4 pi)); 0 on the segment's line */
+static void seg_velocity(const double *y, const double *x1, const double *x2, double G, double *v)
+{
+    double r1[3] = {y[0] - x1[0], y[1] - x1[1], y[2] - x1[2]};
+    double r2[3] = {y[0] - x2[0], y[1] - x2[1], y[2] - x2[2]};
+    double a = sqrt(r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2]);
+    double b = sqrt(r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2]);
+    double c[3] = {r1[1] * r2[2] - r1[2] * r2[1], r1[2] * r2[0] - r1[0] * r2[2], r1[0] * r2[1] - r1[1] * r2[0]};
+    double den = a * b + r1[0] * r2[0] + r1[1] * r2[1] + r1[2] * r2[2];
+    double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+    if (a == 0.0 || b == 0.0 || c2 == 0.0 || den == 0.0) return;
+    double f = G * (1.0 / a + 1.0 / b) / den;
+    for (int d = 0; d < 3; d++) v[d] += f * c[d];
+}
+
+/* direct sum at the vertices (all when targets == NULL): segments containing the receiver vertex
+ * are skipped */
+void lho_filament_direct(int64_t nv, const double *X, int64_t ns, const int32_t *seg, const double *G, int64_t nt,
+                         const int64_t *targets, double *v)
+{
+    int64_t m = targets ? nt : nv;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < m; k++) {
+        int64_t j = targets ? targets[k] : k;
+        double vv[3] = {0, 0, 0};
+        for (int64_t i = 0; i < ns; i++) {
+            if (seg[2 * i] == j || seg[2 * i + 1] == j) continue;
+            seg_velocity(&X[3 * j], &X[3 * seg[2 * i]], &X[3 * seg[2 * i + 1]], G[i], vv);
+        }
+        for (int d = 0; d < 3; d++) v[3 * k + d] = vv[d];
+    }
+}
+
+/* FMM of the filament velocity at the vertices on the uniform octree of the given depth built on
+ * the points {segment centres} U {vertices} (points 0..ns-1 the centres, ns..ns+nv-1 the
+ * vertices).  nq quadrature points per segment in P2M (0: eq. vf7).  what: bit 0 far field
+ * (expansions of the segments in non-adjacent boxes), bit 1 near field (eq. dis2 over the
+ * segments whose centres lie in leaves adjacent to the vertex's).  Returns 0 on success. */
+int lho_filament_fmm(int64_t nv, const double *X, int64_t ns, const int32_t *seg, const double *G, int p, int depth,
+                     const double lo[3], double L, int nq, int what, double *v, lho_stats *st)
+{
+    if (depth < 2 || depth > 8 || p < 1 || nv < 1 || ns < 1) return -1;
+    if (nq <= 0) nq = (p - 1) / 2 + 1;
+    if (nq > 64) return -1;
+    double xi[64], wq[64];
+    lho_gauss_legendre(nq, xi, wq);
+    int64_t n = ns + nv;
+    double *pts = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *om = (double *)calloc(3 * (size_t)n, sizeof(double));
+    for (int64_t i = 0; i < ns; i++)
+        for (int d = 0; d < 3; d++) {
+            double x1 = X[3 * seg[2 * i] + d], x2 = X[3 * seg[2 * i + 1] + d];
+            pts[3 * i + d] = 0.5 * (x1 + x2);
+            om[3 * i + d] = G[i] * (x2 - x1);  /* G l */
+        }
+    memcpy(pts + 3 * ns, X, sizeof(double) * 3 * (size_t)nv);
+    otree T;
+    tree_build(&T, n, pts, depth, lo, L);
+    size_t P2 = (size_t)p * p;
+    lho_stats stats;
+    memset(&stats, 0, sizeof(stats));
+    int64_t nleaf = T.nb[depth];
+    memset(v, 0, sizeof(double) * 3 * (size_t)nv);
+    if (what & 1) {
+        cplx *M[MAXLEV + 1], *Lc[MAXLEV + 1];
+        for (int l = 2; l <= depth; l++) {
+            M[l] = (cplx *)calloc((size_t)T.nb[l] * 2 * P2 + 1, sizeof(cplx));
+            Lc[l] = (cplx *)calloc((size_t)T.nb[l] * 2 * P2 + 1, sizeof(cplx));
+        }
+        /* P2M: the quadrature points of the leaf's segments (eq. vf6) */
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t b = 0; b < nleaf; b++) {
+            int64_t c = T.count[depth][b];
+            double *bx = (double *)malloc(sizeof(double) * 3 * (size_t)(c * nq + 1));
+            double *bw = (double *)malloc(sizeof(double) * 3 * (size_t)(c * nq + 1));
+            int64_t k = 0;
+            for (int64_t it = 0; it < c; it++) {
+                int64_t e = T.order[T.first[depth][b] + it];
+                if (e >= ns) continue;  /* a vertex: no source */
+                double l[3];
+                for (int d = 0; d < 3; d++) l[d] = X[3 * seg[2 * e + 1] + d] - X[3 * seg[2 * e] + d];
+                for (int j = 0; j < nq; j++, k++)
+                    for (int d = 0; d < 3; d++) {
+                        bx[3 * k + d] = pts[3 * e + d] + 0.5 * l[d] * xi[j];
+                        bw[3 * k + d] = 0.5 * wq[j] * om[3 * e + d];
+                    }
+            }
+            double cen[3];
+            box_centre(&T, depth, T.key[depth][b], cen);
+            cplx *ph = &M[depth][(size_t)b * 2 * P2];
+            if (k > 0) lho_p2m_method2(p, cen, k, bx, bw, NULL, ph, ph + P2);
+            free(bx);
+            free(bw);
+        }
+        for (int l = depth - 1; l >= 2; l--) {
+#pragma omp parallel for schedule(dynamic, 4)
+            for (int64_t b = 0; b < T.nb[l]; b++) {
+                double cp[3];
+                box_centre(&T, l, T.key[l][b], cp);
+                cplx *ph = &M[l][(size_t)b * 2 * P2];
+                for (int chn = 0; chn < 8; chn++) {
+                    int64_t cb = tree_find(&T, l + 1, (T.key[l][b] << 3) | (uint64_t)chn);
+                    if (cb < 0) continue;
+                    double cc[3];
+                    box_centre(&T, l + 1, T.key[l + 1][cb], cc);
+                    double t[3] = {cp[0] - cc[0], cp[1] - cc[1], cp[2] - cc[2]};
+                    const cplx *iph = &M[l + 1][(size_t)cb * 2 * P2];
+                    lho_m2m(p, t, iph, iph + P2, ph, ph + P2);
+                }
+            }
+        }
+        int64_t nm2l = 0;
+        for (int l = 2; l <= depth; l++) {
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : nm2l)
+            for (int64_t b = 0; b < T.nb[l]; b++) {
+                double ct[3];
+                box_centre(&T, l, T.key[l][b], ct);
+                cplx *ph = &Lc[l][(size_t)b * 2 * P2];
+                if (l > 2) {
+                    int64_t pb = tree_find(&T, l - 1, T.key[l][b] >> 3);
+                    double cp[3];
+                    box_centre(&T, l - 1, T.key[l - 1][pb], cp);
+                    double t[3] = {ct[0] - cp[0], ct[1] - cp[1], ct[2] - cp[2]};
+                    const cplx *iph = &Lc[l - 1][(size_t)pb * 2 * P2];
+                    lho_l2l(p, t, iph, iph + P2, ph, ph + P2);
+                }
+                int64_t vl[189];
+                int nvl = vlist(&T, l, T.key[l][b], vl);
+                for (int i = 0; i < nvl; i++) {
+                    double cs[3];
+                    box_centre(&T, l, T.key[l][vl[i]], cs);
+                    double t[3] = {ct[0] - cs[0], ct[1] - cs[1], ct[2] - cs[2]};
+                    const cplx *iph = &M[l][(size_t)vl[i] * 2 * P2];
+                    lho_m2l(p, t, iph, iph + P2, ph, ph + P2);
+                }
+                nm2l += nvl;
+            }
+        }
+        stats.n_m2l = nm2l;
+        /* L2P at the vertices */
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int64_t b = 0; b < nleaf; b++) {
+            double cen[3];
+            box_centre(&T, depth, T.key[depth][b], cen);
+            const cplx *ph = &Lc[depth][(size_t)b * 2 * P2];
+            for (int64_t it = 0; it < T.count[depth][b]; it++) {
+                int64_t e = T.order[T.first[depth][b] + it];
+                if (e < ns) continue;
+                double w0[3] = {0, 0, 0}, vv[3] = {0, 0, 0}, ss[3] = {0, 0, 0}, gg[9];
+                lho_l2p(p, cen, ph, ph + P2, 1, &pts[3 * e], w0, vv, ss, gg, NULL, NULL);
+                for (int d = 0; d < 3; d++) v[3 * (e - ns) + d] += vv[d];
+            }
+        }
+        for (int l = 2; l <= depth; l++) {
+            free(M[l]);
+            free(Lc[l]);
+        }
+    }
+    if (what & 2) {
+        int64_t npairs = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : npairs)
+        for (int64_t b = 0; b < nleaf; b++) {
+            int c[3];
+            box_coords(T.key[depth][b], c);
+            int nside = 1 << depth;
+            for (int64_t it = 0; it < T.count[depth][b]; it++) {
+                int64_t e = T.order[T.first[depth][b] + it];
+                if (e < ns) continue;
+                int64_t j = e - ns;
+                double vv[3] = {0, 0, 0};
+                for (int dz = -1; dz <= 1; dz++)
+                    for (int dy = -1; dy <= 1; dy++)
+                        for (int dx = -1; dx <= 1; dx++) {
+                            int cc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                            if (cc[0] < 0 || cc[1] < 0 || cc[2] < 0 || cc[0] >= nside || cc[1] >= nside ||
+                                cc[2] >= nside)
+                                continue;
+                            int64_t nb = tree_find(&T, depth, morton((uint32_t)cc[0], (uint32_t)cc[1], (uint32_t)cc[2]));
+                            if (nb < 0) continue;
+                            for (int64_t k = 0; k < T.count[depth][nb]; k++) {
+                                int64_t i = T.order[T.first[depth][nb] + k];
+                                if (i >= ns || seg[2 * i] == j || seg[2 * i + 1] == j) continue;
+                                seg_velocity(&X[3 * j], &X[3 * seg[2 * i]], &X[3 * seg[2 * i + 1]], G[i], vv);
+                                npairs++;
+                            }
+                        }
+                for (int d = 0; d < 3; d++) v[3 * j + d] += vv[d];
+            }
+        }
+        stats.n_p2p_pairs = npairs;
+    }
+    if (st) *st = stats;
+    free(pts);
+    free(om);
+    tree_free(&T);
+    return 0;
+}

@@ -103,6 +103,31 @@ def make(name: str):
     return cfg
 
 
+def filament_rings(n_rings: int, n_per_ring: int, seed: int, rmin=0.03, rmax=0.12):
+    """Closed polygonal vortex filaments (Sec. 5.3): n_rings circles of n_per_ring straight
+    segments each, radius ~ U[rmin, rmax], random orientation, centres uniform in the part of the
+    unit cube that keeps every ring inside it, circulation ~ N(0, 1) per ring.  Returns
+    (X [V, 3] vertices, seg [S, 2] int32 vertex indices, G [S] circulations), V = S."""
+    rng = np.random.default_rng(seed)
+    X, seg, G = [], [], []
+    for k in range(n_rings):
+        r = rng.uniform(rmin, rmax)
+        c = rng.uniform(r, 1.0 - r, size=3)
+        ax = rng.normal(size=3)
+        ax /= np.linalg.norm(ax)
+        u = np.cross(ax, [1.0, 0.0, 0.0] if abs(ax[0]) < 0.9 else [0.0, 1.0, 0.0])
+        u /= np.linalg.norm(u)
+        v = np.cross(ax, u)
+        th = 2.0 * math.pi * (np.arange(n_per_ring) + rng.uniform()) / n_per_ring
+        pts = c[None, :] + r * (np.cos(th)[:, None] * u[None, :] + np.sin(th)[:, None] * v[None, :])
+        base = k * n_per_ring
+        X.append(np.clip(pts, 0.0, np.nextafter(1.0, 0.0)))
+        i = np.arange(n_per_ring)
+        seg.append(np.stack([base + i, base + (i + 1) % n_per_ring], axis=1))
+        G.append(np.full(n_per_ring, rng.normal()))
+    return np.concatenate(X), np.concatenate(seg).astype(np.int32), np.concatenate(G)
+
+
 def sample_targets(n: int, k: int, seed: int = 12345):
     """Seeded sample of k distinct element indices (the paper measures errors
     on 1000 random source points)."""
