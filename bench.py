@@ -1,6 +1,6 @@
 """Benchmark of one FMM evaluation of v and s (the whole hot path) on one GPU.
 
-    python bench.py [--steps K] [--warmup W] [--p P] [--legs ring16,wx,scalar,cube,batch]
+    python bench.py [--steps K] [--warmup W] [--p P] [--legs ring16,wx,scalar,filament,cube,batch]
                     [--no-cpu-baseline] [--calib-copy MIB]
 
 A step is one pass of the whole path over the synthetic input, already resident
@@ -183,6 +183,52 @@ def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warm
     return res, st, out
 
 
+def run_filament(lhf, torch, steps, warmup):
+    """vortex filaments (Sec. 5.3): 4096 closed rings of 256 straight segments (2^20 segments,
+    2^20 vertices) in the unit cube, FP64 p = 12 on a uniform tree of depth 6 over the segment
+    centres and the vertices; a step = filament set-up (tree over 2^21 points) + execute"""
+    import numpy as np
+    import workloads
+    X, seg, G = workloads.filament_rings(4096, 256, 81)
+    Xt = torch.from_numpy(X).cuda()
+    st = torch.from_numpy(seg).cuda()
+    Gt = torch.from_numpy(G).cuda()
+
+    def step(profile):
+        f = lhf.Filament(Xt, st, p=12, depth=6)
+        pl = lhf.load().lhf_filament_plan(f._h)
+        if profile:
+            lhf._check(lhf.load().lhf_profile_begin(pl, 1))
+        v = f.execute(Gt)
+        ph = None
+        if profile:
+            import ctypes as C
+            ms = (C.c_double * len(lhf.PHASES))()
+            k = C.c_int32()
+            lhf._check(lhf.load().lhf_profile_end(pl, ms, C.byref(k)))
+            ph = dict(zip(lhf.PHASES, list(ms)))
+        s = f.stats()
+        f.close()
+        return v, ph, s
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    phases = {k: 0.0 for k in lhf.PHASES}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        v, ph, s = step(True)
+        for k in phases:
+            phases[k] += ph[k] / steps
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ex = sum(vv for kk, vv in phases.items() if kk != "m2l")
+    log(f"bench: filaments: {ms:.2f} ms per step (execute {ex:.2f} ms)")
+    return {"workload": "filaments_4096x256_fp64_p12", "segments": int(seg.shape[0]), "vertices": int(X.shape[0]),
+            "p": 12, "depth": 6, "quadrature_points": 6, "steps": steps, "ms_per_step": ms, "execute_ms": ex,
+            "segments_per_s": seg.shape[0] / (ms * 1e-3), "phases_ms": phases, "n_m2l": s["n_m2l"]}
+
+
 def rel_err(v, s, tg, vd, sd):
     import numpy as np
     return {"rel_l2_v": float(np.linalg.norm(v[tg] - vd) / np.linalg.norm(vd)),
@@ -344,8 +390,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--p", type=int, default=P_STAR, help="order of the headline (FP64 ring) leg")
     ap.add_argument("--leg-steps", type=int, default=20, help="timed steps of the ring p = 16 and cube legs")
-    ap.add_argument("--legs", default="ring16,wx,scalar,cube,batch",
-                    help="comma list of ring16, wx, scalar, cube, batch (or none)")
+    ap.add_argument("--legs", default="ring16,wx,scalar,filament,cube,batch",
+                    help="comma list of ring16, wx, scalar, filament, cube, batch (or none)")
     ap.add_argument("--targets", type=int, default=4096, help="sample targets of the headline accuracy")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle legs (baseline, accuracy)")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -470,6 +516,8 @@ def main():
             r["ratio_vortex_to_scalar_m2l"] = rv["phases_ms"]["m2l"] / r["phases_ms"]["m2l"]
             sc[wl] = r
         out["scalar_vs_vortex"] = sc
+    if "filament" in legs:
+        out["filament"] = run_filament(lhf, torch, max(1, args.leg_steps // 4), args.warmup)
     if "cube" in legs:
         cube = {}
         for wl in ("cube1m_fp64", "cube1m_fp32"):

@@ -51,6 +51,7 @@ extern "C" {
 
 typedef struct lhf_plan lhf_plan;   /* opaque, owned by the library */
 typedef struct lhf_batch lhf_batch; /* opaque, owned by the library */
+typedef struct lhf_filament lhf_filament; /* opaque, owned by the library */
 
 typedef enum {
     LHF_OK = 0,
@@ -225,6 +226,25 @@ lhf_status lhf_execute_io(lhf_plan *plan, const lhf_io *io, void *stream);
  * (may be NULL): device pointers of the plan's precision, input order.  Uniform single-system plans
  * only (else LHF_ERR_UNSUPPORTED).  Enqueued on 'stream'; no host synchronisation, no allocation. */
 lhf_status lhf_execute_scalar(lhf_plan *plan, const void *q, void *phi, void *grad_phi, void *stream);
+
+/* Vortex filaments (Sec. 5.3, App. B): ns straight segments seg[i] = (a, b) from vertex X[a] to
+ * X[b] with constant circulations, evaluated at the nv vertices.  The plan's octree (d: uniform,
+ * max_per_leaf = 0; p, depth, cube, precision as for particles) is built over the segment centres
+ * and the vertices.  A segment's far field is the multipole of floor((p - 1)/2) + 1 Gauss-Legendre
+ * points of it (eqs. vf5-vf7), its near field at a vertex in an adjacent leaf the closed form of
+ * eq. dis2; both without the factor 1/(4 pi), so that a short segment is the point vortex
+ * omega = G l (l = X[b] - X[a]) of the particle path.  A segment contributes nothing at its own
+ * vertices (nor at points on its line).  X: device [nv][3] of the precision, seg: device int32
+ * [ns][2] (copied; indices checked on the host: LHF_ERR_ARG if out of range or a == b).
+ * Synchronises 'stream'.  lhf_filament_destroy releases everything. */
+lhf_status lhf_filament_create(lhf_filament **out, const lhf_desc *d, int64_t nv, const void *X, int64_t ns,
+                               const int32_t *seg, void *stream);
+/* Velocity at the vertices for circulations G (device [ns]) into v (device [nv][3]), both of the
+ * filament's precision.  Enqueued on 'stream'; no host synchronisation, no allocation. */
+lhf_status lhf_filament_execute(lhf_filament *f, const void *G, void *v, void *stream);
+/* The filament's plan (for lhf_plan_stats and the profiling calls; owned by the filament). */
+lhf_plan *lhf_filament_plan(lhf_filament *f);
+lhf_status lhf_filament_destroy(lhf_filament *f);
 
 /* One-shot: plan_create + execute + destroy (synchronises the stream; allocates and frees the
  * plan's device buffers).  p = 0 chooses the order from tol as in lhf_plan_create. */

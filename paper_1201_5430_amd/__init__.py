@@ -34,7 +34,8 @@ EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_plan_create_multi", "lhf_
            "lhf_evaluate", "lhf_plan_stats", "lhf_plan_destroy", "lhf_last_error", "lhf_version",
            "lhf_profile_begin", "lhf_profile_end", "lhf_tune_default", "lhf_autotune", "lhf_choose_depth",
            "lhf_batch_create", "lhf_batch_execute", "lhf_batch_info", "lhf_batch_destroy",
-           "lhf_release_cached_memory", "lhf_evaluate_noalloc", "lhf_execute_io", "lhf_execute_scalar")
+           "lhf_release_cached_memory", "lhf_evaluate_noalloc", "lhf_execute_io", "lhf_execute_scalar",
+           "lhf_filament_create", "lhf_filament_execute", "lhf_filament_plan", "lhf_filament_destroy")
 PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 
 
@@ -92,6 +93,14 @@ def load():
         L.lhf_execute_io.restype = C.c_int
         L.lhf_execute_scalar.argtypes = [vp, vp, vp, vp, vp]
         L.lhf_execute_scalar.restype = C.c_int
+        L.lhf_filament_create.argtypes = [C.POINTER(vp), C.POINTER(Desc), C.c_int64, vp, C.c_int64, vp, vp]
+        L.lhf_filament_create.restype = C.c_int
+        L.lhf_filament_execute.argtypes = [vp, vp, vp, vp]
+        L.lhf_filament_execute.restype = C.c_int
+        L.lhf_filament_plan.argtypes = [vp]
+        L.lhf_filament_plan.restype = vp
+        L.lhf_filament_destroy.argtypes = [vp]
+        L.lhf_filament_destroy.restype = C.c_int
         L.lhf_execute_parts.restype = C.c_int
         L.lhf_evaluate.argtypes = [C.POINTER(Desc), C.c_int64, vp, vp, C.c_double, vp, vp, vp]
         L.lhf_evaluate.restype = C.c_int
@@ -405,6 +414,51 @@ class Batch:
     def close(self):
         if self._h:
             _check(load().lhf_batch_destroy(self._h))
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Filament:
+    """Vortex filaments: straight segments seg [S, 2] (vertex indices) between the vertices X
+    [V, 3], velocity at the vertices (uniform octree over segment centres and vertices).
+    ``execute(G)`` takes the circulations [S] and returns v [V, 3]."""
+
+    def __init__(self, X, seg, p=12, depth=4, precision=FP64, lo=(0.0, 0.0, 0.0), L=1.0, tol=1e-6,
+                 m2l_kernel=M2L_AUTO):
+        import torch
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        X = _dev_array(X, self.dtype, "X")
+        if not isinstance(seg, torch.Tensor) or not seg.is_cuda or seg.dtype != torch.int32 or \
+                seg.dim() != 2 or seg.shape[1] != 2 or not seg.is_contiguous():
+            raise TypeError("seg must be a contiguous [S,2] int32 device tensor")
+        self.nv, self.ns = X.shape[0], seg.shape[0]
+        self.desc = make_desc(p, depth, precision, lo, L, tol, 0, 0, m2l_kernel)
+        self._h = C.c_void_p()
+        self.status = _check(load().lhf_filament_create(C.byref(self._h), C.byref(self.desc), self.nv,
+                                                        C.c_void_p(X.data_ptr()), self.ns,
+                                                        C.c_void_p(seg.data_ptr()), _stream()))
+
+    def execute(self, G, v=None):
+        import torch
+        G = _dev_array(G, self.dtype, "G", self.ns, width=None)
+        v = torch.empty((self.nv, 3), dtype=self.dtype, device=G.device) if v is None else \
+            _dev_array(v, self.dtype, "v", self.nv)
+        _check(load().lhf_filament_execute(self._h, C.c_void_p(G.data_ptr()), C.c_void_p(v.data_ptr()), _stream()))
+        return v
+
+    def stats(self):
+        st = Stats()
+        _check(load().lhf_plan_stats(load().lhf_filament_plan(self._h), C.byref(st)))
+        return dict(n=st.n, p=st.p, n_m2l=st.n_m2l, boxes=list(st.boxes[:st.depth + 1]))
+
+    def close(self):
+        if self._h:
+            load().lhf_filament_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblhfmm.so")
 SOURCES = ["lhf_plan.hip", "lhf_eval.hip", "lhf_m2l.hip", "lhf_m2l_half.hip", "lhf_m2l_quarter.hip",
-           "lhf_m2l_mfma.hip", "lhf_batch.hip"]
+           "lhf_m2l_mfma.hip", "lhf_batch.hip", "lhf_filament.hip"]
 ARCH = os.environ.get("LHF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

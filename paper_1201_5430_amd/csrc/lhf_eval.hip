@@ -81,14 +81,19 @@ __device__ inline void box_centre(uint64_t key, int level, const double *__restr
 //   Rt_n^m = ((2n-1) z Rt_{n-1}^m - r^2 Rt_{n-2}^m) / ((n-m)(n+m)),
 // then every lane adds the eq. eve4 contributions of its (n, m) pairs (both potentials, Re and Im).
 // ---------------------------------------------------------------------------
-// SC: scalar harmonic FMM -- phi = sum q g_n^m (the expansion of eq. rsbf5 of each source), chi = 0
-template <typename T, bool SC = false>
+// SC: scalar harmonic FMM -- phi = sum q g_n^m (the expansion of eq. rsbf5 of each source), chi = 0.
+// SEG: vortex filaments -- each element is a segment (centre x, vector sl) expanded as nq
+// Gauss-Legendre points x + sl xi_j / 2 of strength omega w_j / 2 (eqs. vf5, vf6); quad holds
+// (xi_j, w_j).
+template <typename T, bool SC = false, bool SEG = false>
 __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off, const int32_t *__restrict__ leaves,
                                               const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
                                               const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
                                               const T *__restrict__ xs, const T *__restrict__ ws,
                                               const T *__restrict__ qs, int64_t n,
-                                              const double *__restrict__ sys_geo, T *__restrict__ M, int ch)
+                                              const double *__restrict__ sys_geo, T *__restrict__ M, int ch,
+                                              const T *__restrict__ sl = nullptr, int nq = 1,
+                                              const double *__restrict__ quad = nullptr)
 {
     // the leaf's elements in chunks of ch: first every lane forms the regular solid harmonics of
     // one (element, m) column of the chunk, then every lane adds the chunk's contributions to
@@ -109,14 +114,23 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
     T acc[4 * NPMAX];  // per (n, m) pair of the lane: Re a, Im a, Re b, Im b
 #pragma unroll
     for (int k = 0; k < 4 * NPMAX; k++) acc[k] = 0;
-    const int s0 = bstart[b], cnt = bcount[b];
+    const int s0 = bstart[b], cnt = bcount[b] * (SEG ? nq : 1);  // SEG: (element, quadrature point)
     for (int e0 = 0; e0 < cnt; e0 += ch) {
         const int ne = min(ch, cnt - e0);
         __syncthreads();  // the previous chunk's tables are no longer read
         for (int q = lane; q < ne * p; q += WAVE) {
             const int e = q / p, m = q - e * p;
-            const int i = s0 + e0 + e;
-            const T x = (xs[i] - (T)c0) * ih, y = (xs[n + i] - (T)c1) * ih, z = (xs[2 * n + i] - (T)c2) * ih;
+            const int i = SEG ? s0 + (e0 + e) / nq : s0 + e0 + e;
+            T px = xs[i], py = xs[n + i], pz = xs[2 * n + i], wf = (T)1;
+            if constexpr (SEG) {
+                const int jq = (e0 + e) % nq;
+                const T hx = (T)(0.5 * quad[2 * jq]);
+                px += hx * sl[i];
+                py += hx * sl[n + i];
+                pz += hx * sl[2 * n + i];
+                wf = (T)(0.5 * quad[2 * jq + 1]);
+            }
+            const T x = (px - (T)c0) * ih, y = (py - (T)c1) * ih, z = (pz - (T)c2) * ih;
             const T r2 = x * x + y * y + z * z;
             T *Re = Rre + (size_t)e * P2, *Im = Rim + (size_t)e * P2;
             // Rt_m^m = (-(x+iy)/2)^m / m!, then up in n
@@ -148,10 +162,10 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
                 p1im = cim;
             }
             if (m == 0) {
-                wsh[4 * e] = SC ? (T)0 : ws[i];
-                wsh[4 * e + 1] = SC ? (T)0 : ws[n + i];
-                wsh[4 * e + 2] = SC ? (T)0 : ws[2 * n + i];
-                wsh[4 * e + 3] = qs ? qs[i] : (T)0;
+                wsh[4 * e] = SC ? (T)0 : wf * ws[i];
+                wsh[4 * e + 1] = SC ? (T)0 : wf * ws[n + i];
+                wsh[4 * e + 2] = SC ? (T)0 : wf * ws[2 * n + i];
+                wsh[4 * e + 3] = qs ? wf * qs[i] : (T)0;
             }
         }
         __syncthreads();
@@ -1598,6 +1612,57 @@ __global__ void k_gather_q(int64_t n, const T *__restrict__ q, const int32_t *__
     r[7] = (T)0;
 }
 
+// ---------------------------------------------------------------------------
+// Vortex filaments: near field at the vertices.  Lane per sorted point; a vertex point sums the
+// segments whose centres lie in the 27 adjacent leaves with eq. dis2 (no 1/(4 pi)):
+//   v += G (r1 x r2) / (r1 r2 + r1 . r2) (1/r1 + 1/r2),  r1 = y - x1, r2 = y - x2,
+// skipping the segments it is a vertex of (and any point on a segment's line); then far + near
+// into the vertex's output row.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_p2p_filament(int64_t n, int64_t leaf_off, const int32_t *__restrict__ eleaf,
+                                                      const int32_t *__restrict__ ulist,
+                                                      const int32_t *__restrict__ bstart,
+                                                      const int32_t *__restrict__ bcount, const T *__restrict__ xs,
+                                                      const int32_t *__restrict__ sseg,
+                                                      const int32_t *__restrict__ svid, const T *__restrict__ gam,
+                                                      const T *__restrict__ X, const T *__restrict__ vfar,
+                                                      T *__restrict__ vout)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int vid = svid[i];
+    if (vid < 0) return;  // a segment centre: not a receiver
+    const T yx = X[3 * vid], yy = X[3 * vid + 1], yz = X[3 * vid + 2];
+    CompSum<T> acc[3];
+    for (int k = 0; k < 3; k++) acc[k].add(vfar[(size_t)k * n + i]);
+    const int32_t *U = ulist + (size_t)(eleaf[i] - leaf_off) * 27;
+    for (int u = 0; u < 27; u++) {
+        const int nb = U[u];
+        if (nb < 0) continue;
+        T v0 = 0, v1 = 0, v2 = 0;
+        const int st = bstart[nb], ct = bcount[nb];
+        for (int k = st; k < st + ct; k++) {
+            const int a = sseg[2 * k], b = sseg[2 * k + 1];
+            if (a < 0 || a == vid || b == vid) continue;
+            const T r1x = yx - X[3 * a], r1y = yy - X[3 * a + 1], r1z = yz - X[3 * a + 2];
+            const T r2x = yx - X[3 * b], r2y = yy - X[3 * b + 1], r2z = yz - X[3 * b + 2];
+            const T cx = r1y * r2z - r1z * r2y, cy = r1z * r2x - r1x * r2z, cz = r1x * r2y - r1y * r2x;
+            const T ra = sqrt(r1x * r1x + r1y * r1y + r1z * r1z), rb = sqrt(r2x * r2x + r2y * r2y + r2z * r2z);
+            const T den = ra * rb + r1x * r2x + r1y * r2y + r1z * r2z;
+            if (ra == (T)0 || rb == (T)0 || den == (T)0 || cx * cx + cy * cy + cz * cz == (T)0) continue;
+            const T f = gam[k] * ((T)1 / ra + (T)1 / rb) / den;
+            v0 += f * cx;
+            v1 += f * cy;
+            v2 += f * cz;
+        }
+        acc[0].add(v0);
+        acc[1].add(v1);
+        acc[2].add(v2);
+    }
+    for (int k = 0; k < 3; k++) vout[3 * (size_t)vid + k] = acc[k].value();
+}
+
 // gather omega into the sorted SoA layout
 template <typename T>
 __global__ void k_gather_w(int64_t n, const T *__restrict__ w, const T *__restrict__ q,
@@ -1822,6 +1887,61 @@ lhf_status execute_scalar_impl(lhf_plan *P, const void *q, void *phi, void *gphi
     if (P->precision == LHF_FP64)
         return execute_scalar_t<double>(P, (const double *)q, (double *)phi, (double *)gphi, st);
     return execute_scalar_t<float>(P, (const float *)q, (float *)phi, (float *)gphi, st);
+}
+
+// vortex filaments: far field of the segments (quadrature P2M) and the analytic near field at the
+// vertices; omega [n][3] input order (G l at segment centres, 0 at vertices), sgam [n] the sorted
+// circulations, sl / sseg / svid the sorted segment vectors, endpoints and vertex indices
+template <typename T>
+static lhf_status execute_filament_t(lhf_plan *P, const T *omega, const T *sgam, const T *sl, const int32_t *sseg,
+                                     const int32_t *svid, const T *X, int nq, const double *quad, T *vout,
+                                     hipStream_t st)
+{
+    const int p = P->p, d = P->depth;
+    const int64_t n = P->n;
+    const int P2 = p * p;
+    T *xs = (T *)P->xs, *ws = (T *)P->ws, *M = (T *)P->M, *vfar = (T *)P->vfar;
+    const int tpb = 256;
+    const unsigned nblk = (unsigned)((n + tpb - 1) / tpb);
+    hipEvent_t *ev = nullptr;
+    if (P->prof_ev && P->prof_used < P->prof_cap) ev = P->prof_ev + (size_t)(P->prof_used++) * PROF_EV_PER_EXEC;
+    const std::function<void(int)> mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], st);
+    };
+    mark(0);
+    hipLaunchKernelGGL(k_gather_w<T>, dim3(nblk), dim3(tpb), 0, st, n, omega, (const T *)nullptr, P->perm,
+                       (const T *)xs, ws, (T *)P->qs, (T *)P->xw);
+    mark(1);
+    const int64_t loff = P->lev[d].off, nleaf = P->lev[d].nb;
+    const int ch = std::max(1, std::min(8, (int)(49152 / (sizeof(T) * (2 * P2 + 4)))));
+    hipLaunchKernelGGL((k_p2m<T, false, true>), dim3((unsigned)nleaf), dim3(WAVE),
+                       sizeof(T) * (size_t)ch * (2 * P2 + 4), st, p, d, loff, nullptr, nullptr, P->bkey, P->bstart,
+                       P->bcount, (const T *)xs, (const T *)ws, (const T *)nullptr, n, P->sys_geo, M, ch, sl, nq,
+                       quad);
+    mark(2);
+    translations<T>(P, st, false, mark);
+    mark(4);
+    const int TRI = p * (p + 1) / 2;
+    hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)((nleaf + L2P_LPB - 1) / L2P_LPB)), dim3(WAVE),
+                       sizeof(T) * L2P_LPB * 6 * TRI, st, p, d, nleaf, loff, nullptr, nullptr, P->bkey, P->bstart,
+                       P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, (const T *)P->Lc, vfar, 0);
+    mark(5);
+    hipLaunchKernelGGL(k_p2p_filament<T>, dim3(nblk), dim3(tpb), 0, st, n, loff, P->eleaf, P->ulist, P->bstart,
+                       P->bcount, (const T *)xs, sseg, svid, sgam, X, (const T *)vfar, vout);
+    mark(6);
+    LHF_HIP(hipGetLastError());
+    return LHF_OK;
+}
+
+lhf_status execute_filament_impl(lhf_plan *P, const void *omega, const void *sgam, const void *sl,
+                                 const int32_t *sseg, const int32_t *svid, const void *X, int nq,
+                                 const double *quad, void *v, hipStream_t st)
+{
+    if (P->precision == LHF_FP64)
+        return execute_filament_t<double>(P, (const double *)omega, (const double *)sgam, (const double *)sl, sseg,
+                                          svid, (const double *)X, nq, quad, (double *)v, st);
+    return execute_filament_t<float>(P, (const float *)omega, (const float *)sgam, (const float *)sl, sseg, svid,
+                                     (const float *)X, nq, quad, (float *)v, st);
 }
 
 lhf_status execute_impl(lhf_plan *P, const lhf_io *io, hipStream_t st)

@@ -185,6 +185,9 @@ inline hipError_t dev_malloc(T **p, size_t bytes)
 }
 lhf_status execute_impl(lhf_plan *P, const lhf_io *io, hipStream_t st);
 lhf_status execute_scalar_impl(lhf_plan *P, const void *q, void *phi, void *gphi, hipStream_t st);
+lhf_status execute_filament_impl(lhf_plan *P, const void *omega, const void *sgam, const void *sl,
+                                 const int32_t *sseg, const int32_t *svid, const void *X, int nq,
+                                 const double *quad, void *v, hipStream_t st);
 // order from tolerance and kernel choice (host only)
 bool choose_order(bool adaptive, int precision, double tol, int *p);
 void calib_error(bool adaptive, int p, double *ev, double *es);

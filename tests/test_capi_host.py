@@ -144,3 +144,16 @@ def test_scalar_entry_point_checks_its_arguments():
     L, lib = _lib()
     assert lib.lhf_execute_scalar(None, C.c_void_p(0x1000), C.c_void_p(0x1000), None, None) == -1
     assert "plan" in lib.lhf_last_error().decode()
+
+
+def test_filament_entry_points_check_their_arguments():
+    L, lib = _lib()
+    h = C.c_void_p()
+    d = L.make_desc(p=8, depth=3, max_per_leaf=16)
+    dummy = C.c_void_p(0x1000)
+    assert lib.lhf_filament_create(C.byref(h), C.byref(d), 10, dummy, 5, dummy, None) == -6
+    assert "uniform" in lib.lhf_last_error().decode() and h.value is None
+    d = L.make_desc(p=8, depth=3)
+    assert lib.lhf_filament_create(C.byref(h), C.byref(d), 1, dummy, 5, dummy, None) == -1
+    assert lib.lhf_filament_execute(None, dummy, dummy, None) == -1
+    assert lib.lhf_filament_destroy(None) == 0
