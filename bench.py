@@ -108,6 +108,14 @@ def phase_roofline(st, ph, p, prec, n):
                  "peak_alu_tflops": peak, "peak_hbm_gbs": PEAK_HBM_GBS}
 
 
+# the dominant kernel of the headline per M2L kernel family the plan chose
+KERNEL_LABEL = {
+    "half": "k_m2l_half<{t},{p}> (batched M2L, half-vector lanes, rotation tables from L2), one launch per level",
+    "quarter": "k_m2l_quarter<{p}> (batched M2L, quarter-vector lanes, rotation tables from L2), one launch per level",
+    "tile": "k_m2l_tile<{t},{p},...> (batched M2L, LDS-tiled target boxes), one launch per level",
+}
+
+
 def measured_traffic(name):
     """HBM bytes per launch of the dominant kernel from a committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary (copy-calibrated), or None when the kernel's source changed since"""
@@ -465,7 +473,7 @@ def main():
         "phase_roofline": head["phase_roofline"],
         "aggregate_roofline": head["aggregate_roofline"],
         "roofline": {
-            "kernel": f"k_m2l_half<double,{p}> (batched M2L, rotation tables from L2), one launch per level",
+            "kernel": KERNEL_LABEL.get(head["m2l_kernel"], head["m2l_kernel"]).format(t="double", p=p),
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,

@@ -46,8 +46,8 @@ bool mm_half_supported(int precision, int p);
 namespace {
 struct MemCache {
     std::mutex mu;
-    std::map<std::pair<int, size_t>, std::vector<void *>> idle;  // (device, bytes) -> free blocks
-    std::unordered_map<void *, std::pair<int, size_t>> live;     // block -> (device, bytes)
+    std::map<std::pair<size_t, int>, std::vector<void *>> idle;  // (bytes, device) -> free blocks
+    std::unordered_map<void *, std::pair<size_t, int>> live;     // block -> (bytes, device)
     size_t idle_bytes = 0;
 };
 MemCache &mem_cache()
@@ -76,20 +76,20 @@ size_t round_block(size_t b)
     b = std::max<size_t>(b, 1);
     return b < ((size_t)1 << 20) ? (b + small - 1) / small * small : (b + large - 1) / large * large;
 }
-// release idle blocks (of one device, or all with dev < 0) until at most keep bytes stay idle
+// release idle blocks (of one device, or of all with dev < 0), largest first, until at most keep
+// bytes stay idle: a later reallocation costs one call per block whatever its size, so the cap
+// is met with the fewest blocks given back, and the many small blocks of small plans stay
 void mem_trim_locked(MemCache &m, int dev, size_t keep)
 {
-    for (auto it = m.idle.begin(); it != m.idle.end() && m.idle_bytes > keep;) {
-        if (dev >= 0 && it->first.first != dev) {
-            ++it;
-            continue;
-        }
+    for (auto it = m.idle.end(); it != m.idle.begin() && m.idle_bytes > keep;) {
+        --it;
+        if (dev >= 0 && it->first.second != dev) continue;
         while (!it->second.empty() && m.idle_bytes > keep) {
             (void)hipFree(it->second.back());
             it->second.pop_back();
-            m.idle_bytes -= it->first.second;
+            m.idle_bytes -= it->first.first;
         }
-        it = it->second.empty() ? m.idle.erase(it) : std::next(it);
+        if (it->second.empty()) it = m.idle.erase(it);
     }
 }
 }  // namespace
@@ -128,12 +128,12 @@ hipError_t dev_malloc_raw(void **p, size_t bytes)
     MemCache &m = mem_cache();
     {
         std::lock_guard<std::mutex> lk(m.mu);
-        auto it = m.idle.find({dev, rb});
+        auto it = m.idle.find({rb, dev});
         if (it != m.idle.end() && !it->second.empty()) {
             *p = it->second.back();
             it->second.pop_back();
             m.idle_bytes -= rb;
-            m.live[*p] = {dev, rb};
+            m.live[*p] = {rb, dev};
             return hipSuccess;
         }
     }
@@ -146,7 +146,7 @@ hipError_t dev_malloc_raw(void **p, size_t bytes)
     }
     if (e == hipSuccess) {
         std::lock_guard<std::mutex> lk(m.mu);
-        m.live[*p] = {dev, rb};
+        m.live[*p] = {rb, dev};
     }
     return e;
 }
@@ -163,7 +163,7 @@ hipError_t dev_free(void *p)
     const auto key = it->second;
     m.live.erase(it);
     m.idle[key].push_back(p);
-    m.idle_bytes += key.second;
+    m.idle_bytes += key.first;
     if (m.idle_bytes > mem_cache_cap()) mem_trim_locked(m, -1, mem_cache_cap());
     return hipSuccess;
 }
