@@ -26,22 +26,36 @@ EXTRA = {"lhf_m2l_half.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
          "lhf_m2l_quarter.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
 
 
-def build(verbose: bool = False, jobs: int = 0) -> str:
-    """Compile every source (in parallel, at most ``jobs`` at once) and link liblhfmm.so."""
+def _stale(obj: str, src: str) -> bool:
+    """True if obj is missing or older than its source or any header of csrc/."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith((".h", ".inc"))]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, jobs: int = 0, incremental: bool = False) -> str:
+    """Compile every source (in parallel, at most ``jobs`` at once) and link liblhfmm.so.
+
+    incremental=True recompiles only the sources whose object is older than the source or a header.
+    """
     from concurrent.futures import ThreadPoolExecutor
     objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
+        objs.append(obj)
+        if incremental and not _stale(obj, os.path.join(CSRC, src)):
+            continue
         cmds.append(["hipcc", "-c", *[f for f in FLAGS if f != "-shared"], *EXTRA.get(src, []), "-o", obj,
                      os.path.join(CSRC, src)])
-        objs.append(obj)
 
     def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
 
-    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    jobs = jobs or max(1, min(len(cmds), 8, os.cpu_count() or 1))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         for f in [ex.submit(run, c) for c in cmds]:
             f.result()
@@ -55,4 +69,4 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

@@ -67,16 +67,30 @@ struct Shape {
     static constexpr int ARS = NQ + 1;               // accumulator stride per lane role (odd)
     static constexpr int SSTA = 16 * ARS + 1;        // accumulator stride per target slot
 };
-constexpr int NSLOT = 4;     // targets of a tile: children 4h .. 4h + 3 of one parent
 constexpr int NTHREADS = 512;
-constexpr int NENT = 1512;   // schedule entries of one sibling group
+constexpr int NV = 189;      // interaction offsets of one target box
+constexpr int MAXCLS = 64;   // polar-angle classes (49 for the 316 offsets of the 7^3 stencil)
+constexpr int LDS_MAX = 163840;
+
+// Target slots of a tile: as many consecutive target boxes of the level as the LDS holds
+// beside one class's rotation tables (6 at p = 23, 5 at p = 24), at most 16.
+template <int P>
+constexpr int nslot()
+{
+    using Sh = Shape<P>;
+    const int fixed = (int)sizeof(double) * 8 * Sh::WQS + (int)sizeof(int16_t) * (MAXCLS + 1) + 64;
+    const int per = (int)sizeof(double) * Sh::SSTA + (int)sizeof(int16_t) * (NV + MAXCLS) + 4 * (int)sizeof(int);
+    const int n = (LDS_MAX - fixed) / per;
+    return n > 16 ? 16 : n;
+}
 
 template <int P>
 constexpr size_t tile_bytes()
 {
     using Sh = Shape<P>;
-    return sizeof(double) * (size_t)8 * Sh::WQS + sizeof(double) * (size_t)NSLOT * Sh::SSTA +
-           sizeof(int) * 3 * NSLOT + sizeof(int16_t) * (64 + NENT);
+    constexpr int NS = nslot<P>();
+    return sizeof(double) * (size_t)8 * Sh::WQS + sizeof(double) * (size_t)NS * Sh::SSTA + sizeof(int) * 4 * NS +
+           sizeof(int16_t) * ((MAXCLS + 1) + MAXCLS * NS + NV * NS);
 }
 
 // packed (phi, chi) expansion index k -> position in a target slot (lane layout)
@@ -119,12 +133,10 @@ __device__ __attribute__((always_inline)) inline void axpyw(const double *W, con
 }  // namespace qv
 
 template <int P>
-__global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int64_t poff, int64_t npar,
+__global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int64_t soff, int64_t nb, int ns,
                                                                 const uint64_t *__restrict__ bkey,
-                                                                const int32_t *__restrict__ bchild0,
-                                                                const int32_t *__restrict__ bnchild,
                                                                 const int32_t *__restrict__ dmap,
-                                                                const double *__restrict__ Mq, int64_t soff,
+                                                                const double *__restrict__ Mq,
                                                                 double *__restrict__ Lc,
                                                                 const double *__restrict__ wq, int64_t wstride,
                                                                 M2LSched sch, const int16_t *__restrict__ cls_theta,
@@ -134,70 +146,89 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
     using qv::hoff;
     using qv::S;
     constexpr int P2 = Sh::P2, NQ = Sh::NQ, NQP = Sh::NQP, ARS = Sh::ARS, SSTA = Sh::SSTA, WQS = Sh::WQS;
-    constexpr int NSLOT = qv::NSLOT, NT = qv::NTHREADS;
+    constexpr int NSLOT = qv::nslot<P>(), NT = qv::NTHREADS, MAXCLS = qv::MAXCLS;
     extern __shared__ char smem[];
     double *Wl = (double *)smem;                       // [part][residue][WQS] forward tables
     double *acc = Wl + 8 * WQS;                        // [NSLOT][SSTA]
     int *slot_xyz = (int *)(acc + NSLOT * SSTA);       // [NSLOT] packed target coordinates, -1: no box
     int *slot_box = slot_xyz + NSLOT;                  // [NSLOT] target box
     int *slot_sys = slot_box + NSLOT;                  // [NSLOT] system of the target
-    int16_t *cst = (int16_t *)(slot_sys + NSLOT);      // [ncls + 1] class starts (this half)
-    int16_t *ent = cst + 64;                           // [NENT] (dir << 3) | slot
+    int *slot_c = slot_sys + NSLOT;                    // [NSLOT] child position of the target
+    int16_t *cst = (int16_t *)(slot_c + NSLOT);        // [ncls + 1] class starts in ent
+    int16_t *kcnt = cst + (MAXCLS + 1);                // [ncls][NSLOT] entries per (class, slot)
+    int16_t *ent = kcnt + MAXCLS * NSLOT;              // [<= NV * NSLOT] (dir << 4) | slot, by class
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // XCD-aware tile order: consecutive tiles stay on one XCD (shared L2)
-    const int64_t ntiles = 2 * npar;
+    const int64_t ntiles = (nb + ns - 1) / ns;
     const int64_t per = (ntiles + 7) / 8;
     const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
     if (tile >= ntiles) return;
     const int ncls = sch.ncls;
-    const int hf = (int)(tile & 1);  // children 4 hf .. 4 hf + 3 of parent tile / 2
+    const int side = 1 << level;
 
-    int has_box = 0;
+    // the tile's targets: ns consecutive boxes of the level (Morton order)
     if (tid < NSLOT) {
-        const int c = 4 * hf + tid;
-        int box = -1, xyz = -1, sys = 0;
-        const int64_t q = tile >> 1;
-        if (q < npar) {
-            const int64_t pb = poff + q;
-            const int c0 = bchild0[pb], nc = bnchild[pb];
-            for (int k = 0; k < nc; k++)
-                if ((int)(bkey[c0 + k] & 7u) == c) box = c0 + k;
-        }
-        if (box >= 0) {
+        int box = -1, xyz = -1, sys = 0, c = 0;
+        const int64_t b = tile * ns + tid;
+        if (tid < ns && b < nb) {
+            box = (int)(soff + b);
             const uint64_t key = bkey[box];
             uint32_t ix = 0, iy = 0, iz = 0;
-            for (int b = 0; b < level; b++) {
-                ix |= (uint32_t)((key >> (3 * b)) & 1u) << b;
-                iy |= (uint32_t)((key >> (3 * b + 1)) & 1u) << b;
-                iz |= (uint32_t)((key >> (3 * b + 2)) & 1u) << b;
+            for (int bb = 0; bb < level; bb++) {
+                ix |= (uint32_t)((key >> (3 * bb)) & 1u) << bb;
+                iy |= (uint32_t)((key >> (3 * bb + 1)) & 1u) << bb;
+                iz |= (uint32_t)((key >> (3 * bb + 2)) & 1u) << bb;
             }
             xyz = (int)(ix | (iy << 10) | (iz << 20));
             sys = (int)(key >> (3 * level));
+            c = (int)(key & 7u);
         }
         slot_box[tid] = box;
         slot_xyz[tid] = xyz;
         slot_sys[tid] = sys;
-        has_box = box >= 0;
+        slot_c[tid] = c;
     }
-    // a tile whose parent has no children on this half has nothing to do
-    if (!__syncthreads_or(has_box)) return;
-    // the class entries of this half, compacted per class: (dir << 3) | slot
-    if (tid < ncls) {
+    __syncthreads();
+    // source box of offset dir from the target in slot sl, -1 if it is outside the system's cube or empty
+    auto source_of = [&](int dir, int sl) -> int {
+        const int xyz = slot_xyz[sl];
+        const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
+                  sz = (xyz >> 20) - (dir / 49 - 3);
+        const bool inb = xyz >= 0 && sx >= 0 && sy >= 0 && sz >= 0 && sx < side && sy < side && sz < side;
+        return inb ? dmap[(((size_t)slot_sys[sl] * side + sz) * side + sy) * side + sx] : -1;
+    };
+    // per (class, slot): the V-list offsets of the slot's child position in that class whose
+    // source box exists; counted, scanned, then listed class by class
+    for (int ks = tid; ks < ncls * NSLOT; ks += NT) {
+        const int kk = ks / NSLOT, sl = ks % NSLOT;
         int cnt = 0;
-        for (int e = sch.cls_start[tid]; e < sch.cls_start[tid + 1]; e++) cnt += (sch.ent_c[e] >> 2) == hf;
-        cst[tid + 1] = (int16_t)cnt;
+        if (slot_box[sl] >= 0)
+            for (int r = sch.row_start[kk]; r < sch.row_start[kk + 1]; r++) {
+                const int dir = sch.rows[r * 8 + slot_c[sl]];
+                if (dir >= 0 && source_of(dir, sl) >= 0) cnt++;
+            }
+        kcnt[ks] = (int16_t)cnt;
     }
     __syncthreads();
     if (tid == 0) {
-        cst[0] = 0;
-        for (int k = 0; k < ncls; k++) cst[k + 1] = (int16_t)(cst[k] + cst[k + 1]);
+        int o = 0;
+        for (int kk = 0; kk < ncls; kk++) {
+            cst[kk] = (int16_t)o;
+            for (int sl = 0; sl < NSLOT; sl++) o += kcnt[kk * NSLOT + sl];
+        }
+        cst[ncls] = (int16_t)o;
     }
     __syncthreads();
-    if (tid < ncls) {
-        int o = cst[tid];
-        for (int e = sch.cls_start[tid]; e < sch.cls_start[tid + 1]; e++)
-            if ((sch.ent_c[e] >> 2) == hf) ent[o++] = (int16_t)((sch.ent_dir[e] << 3) | (sch.ent_c[e] & 3));
+    for (int ks = tid; ks < ncls * NSLOT; ks += NT) {
+        const int kk = ks / NSLOT, sl = ks % NSLOT;
+        int o = cst[kk];
+        for (int s2 = 0; s2 < sl; s2++) o += kcnt[kk * NSLOT + s2];
+        if (slot_box[sl] >= 0)
+            for (int r = sch.row_start[kk]; r < sch.row_start[kk + 1]; r++) {
+                const int dir = sch.rows[r * 8 + slot_c[sl]];
+                if (dir >= 0 && source_of(dir, sl) >= 0) ent[o++] = (int16_t)((dir << 4) | sl);
+            }
     }
     // the targets' local expansions into their slots (entries without an (n, m) stay zero)
     for (int idx = tid; idx < NSLOT * SSTA; idx += NT) acc[idx] = 0.0;
@@ -208,25 +239,27 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
         if (box >= 0) acc[sl * SSTA + qv::acc_pos<P>(r)] = Lc[(size_t)box * 2 * P2 + r];
     }
 
-    const int side = 1 << level;
     const int t = lane >> 4, pot = (lane >> 3) & 1, part = (lane >> 2) & 1, q = lane & 3;
 
     struct Job {
         int slot, dir, src;
     };
-    // translation tr of class k (4 per wavefront and batch): (slot, dir) from LDS, source by one
-    // load.  Branch-free (every load at a valid address, the result chosen by selects): the batch
-    // body must run with all lanes active, since its DPP exchanges read other lanes' registers
-    // and a register restored inside a divergent region would hold a stale value in the lanes
-    // that region skipped
+    // translation of class k for this lane group: the class's entries, read as a 4 x Q matrix
+    // (Q = ceil(count / 4)) column by column, so that the four translations of one wavefront
+    // come from four places of the list (different targets where the class has several).
+    // (slot, dir) from LDS, source by one load.  Branch-free (every load at a valid address, the
+    // result chosen by selects): the batch body must run with all lanes active, since its DPP
+    // exchanges read other lanes' registers and a register restored inside a divergent region
+    // would hold a stale value in the lanes that region skipped
     auto setup = [&](int k, int r0) -> Job {
         const bool kin = k < ncls;
         const int kc = kin ? k : 0;
         const int e0 = cst[kc], cnt = kin ? cst[kc + 1] - e0 : 0;
-        const int tr = r0 + wave * 4 + t;
-        const bool ok0 = tr < cnt;
-        const int code = ent[ok0 ? e0 + tr : 0];
-        const int dir = ok0 ? code >> 3 : 0, slot = code & 3;
+        const int Q = (cnt + 3) >> 2;
+        const int col = (r0 >> 2) + wave, e = t * Q + col;
+        const bool ok0 = col < Q && e < cnt;
+        const int code = ent[ok0 ? e0 + e : 0];
+        const int dir = ok0 ? code >> 4 : 0, slot = code & 15;
         const int xyz = slot_xyz[slot];
         const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
                   sz = (xyz >> 20) - (dir / 49 - 3);
@@ -236,10 +269,15 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
         const bool ok = inb && src >= 0;
         return Job{ok ? slot : -1, ok ? dir : 0, ok ? src : -1};
     };
+    // the first class at or after k with entries (ncls if none)
+    auto nonempty = [&](int k) {
+        while (k < ncls && cst[k + 1] == cst[k]) k++;
+        return k;
+    };
     auto advance = [&](int &k, int &r0) {
         r0 += 8 * 4;
-        if (k < ncls && r0 >= cst[k + 1] - cst[k]) {
-            k++;
+        if (k < ncls && r0 >= 4 * ((cst[k + 1] - cst[k] + 3) >> 2)) {
+            k = nonempty(k + 1);
             r0 = 0;
         }
     };
@@ -254,8 +292,8 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
         }
     };
 
-    int k = 0, r0 = 0;   // current batch
-    int k1 = 0, r1 = 0;  // next batch
+    int k = nonempty(0), r0 = 0;  // current batch
+    int k1 = k, r1 = 0;           // next batch
     advance(k1, r1);
     Job cur = setup(k, r0), nxt = setup(k1, r1);
     constexpr int N16 = 8 * WQS * 8 / 16;
@@ -529,7 +567,9 @@ template <int P>
 static bool wquarter_build_t(lhf_plan *Pl, hipStream_t st)
 {
     constexpr size_t shm = qv::tile_bytes<P>();
-    static_assert(shm <= 163840, "tile exceeds the LDS");
+    static_assert(shm <= (size_t)qv::LDS_MAX, "tile exceeds the LDS");
+    static_assert(qv::nslot<P>() >= 1, "no target slot fits beside the tables");
+    if (Pl->sched_ncls > qv::MAXCLS) return false;
     const int64_t stride = 8 * (int64_t)qv::Shape<P>::WQS;
     if (dev_malloc(&Pl->whalf, sizeof(double) * stride * Pl->n_theta) != hipSuccess) return false;
     k_wquarter<P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const double *)Pl->rot, (double *)Pl->whalf,
@@ -555,16 +595,16 @@ static void stage_quarter(const lhf_plan *Pl, int level, hipStream_t st)
 template <int P>
 static void launch_quarter(const lhf_plan *Pl, int level, hipStream_t st)
 {
-    const int64_t poff = Pl->lev[level - 1].off, npar = Pl->lev[level - 1].nb;
     const int64_t soff = Pl->lev[level].off, nb = Pl->lev[level].nb;
-    if (nb == 0 || npar == 0) return;
-    const int64_t ntiles = 2 * npar;
+    if (nb == 0) return;
+    // as many slots as fit, but no fewer than ~1024 tiles where the level has the boxes
+    const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(qv::nslot<P>(), (nb + 1023) / 1024));
+    const int64_t ntiles = (nb + ns - 1) / ns;
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
     k_m2l_quarter<P><<<dim3((unsigned)(per * 8)), dim3(qv::NTHREADS), qv::tile_bytes<P>(), st>>>(
-        level, poff, npar, Pl->bkey, Pl->bchild0, Pl->bnchild, Pl->dmap[level], (const double *)Pl->mh, soff,
-        (double *)Pl->Lc, (const double *)Pl->whalf, 8 * (int64_t)qv::Shape<P>::WQS, sch, Pl->sched_cls_theta,
-        Pl->dtab);
+        level, soff, nb, ns, Pl->bkey, Pl->dmap[level], (const double *)Pl->mh, (double *)Pl->Lc,
+        (const double *)Pl->whalf, 8 * (int64_t)qv::Shape<P>::WQS, sch, Pl->sched_cls_theta, Pl->dtab);
 }
 
 }  // namespace
