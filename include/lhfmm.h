@@ -111,6 +111,8 @@ typedef enum { LHF_FP64 = 0, LHF_FP32 = 1 } lhf_precision;
 #define LHF_MM_AUTO 0
 #define LHF_MM_HALF 1          /* batched, eight child shifts per wavefront: p = 8, 10, 12, 16 */
 #define LHF_MM_GENERIC 2       /* one wavefront per parent (M2M) or child (L2L): any p */
+#define LHF_MM_QUARTER 3       /* batched, four child shifts per wavefront, each vector over four lanes
+                                  by m mod 4: FP64 p = 20, 22, 23, 24 (the default there) */
 
 typedef struct {
     int32_t p;            /* truncation number, orders n = 0..p-1 (Sec. 5.1); 0: the smallest order
@@ -143,7 +145,7 @@ typedef struct {
     int64_t n_wx_pairs;        /* adaptive tree: element pairs of W/X interactions summed directly
                                   with the singular kernel (ordered; those not taken by M2P / P2L) */
     int32_t m2l_kernel;        /* the M2L kernel the plan runs (LHF_M2L_*, never AUTO) */
-    int32_t mm_kernel;         /* the M2M/L2L kernel (LHF_MM_HALF or LHF_MM_GENERIC) */
+    int32_t mm_kernel;         /* the M2M/L2L kernel (LHF_MM_HALF, LHF_MM_GENERIC or LHF_MM_QUARTER) */
     int32_t deterministic;     /* 1 if every kernel of the plan accumulates in a fixed order */
     int32_t p_from_tol;        /* 1 if p was chosen from tol */
     double calib_err_v;        /* calibrated relative L2 error of v and of s at the plan's p for its */

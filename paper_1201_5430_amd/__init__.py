@@ -23,7 +23,7 @@ FP64, FP32 = 0, 1
 LHF_SINGULAR, LHF_DETERMINISTIC, LHF_OUT_GRAD, LHF_WX_EXPANSIONS = 0x1, 0x2, 0x4, 0x8
 TRANS_RCR, TRANS_DIRECT = 0, 1
 M2L_AUTO, M2L_HALF, M2L_TILE, M2L_TILE1, M2L_MFMA, M2L_GENERIC, M2L_QUARTER = range(7)
-MM_AUTO, MM_HALF, MM_GENERIC = range(3)
+MM_AUTO, MM_HALF, MM_GENERIC, MM_QUARTER = range(4)
 M2L_NAMES = ("auto", "half", "tile", "tile1", "mfma", "generic", "quarter")
 STATUS = {0: "LHF_OK", 1: "LHF_WARN_CORE_SPLIT", 2: "LHF_WARN_TOL_UNMET", -1: "LHF_ERR_ARG",
           -2: "LHF_ERR_DOMAIN", -3: "LHF_ERR_NONFINITE", -4: "LHF_ERR_WORKSPACE", -5: "LHF_ERR_HIP",
@@ -285,7 +285,7 @@ class Plan:
                     n_m2m=st.n_m2m, n_l2l=st.n_l2l, n_p2p_pairs=st.n_p2p_pairs,
                     n_theta_classes=st.n_theta_classes, max_level=st.max_level, n_leaves=st.n_leaves,
                     n_wx_pairs=st.n_wx_pairs, m2l_kernel=M2L_NAMES[st.m2l_kernel],
-                    mm_kernel=("auto", "half", "generic")[st.mm_kernel], deterministic=bool(st.deterministic),
+                    mm_kernel=("auto", "half", "generic", "quarter")[st.mm_kernel], deterministic=bool(st.deterministic),
                     p_from_tol=bool(st.p_from_tol), calib_err_v=st.calib_err_v, calib_err_s=st.calib_err_s,
                     warnings=st.warnings, wx_expansions=bool(st.wx_expansions), n_m2p=st.n_m2p, n_p2l=st.n_p2l)
 

@@ -35,6 +35,8 @@ void m2l_half_scalar_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_quarter_stage(const lhf_plan *Pl, int level, hipStream_t st);
 void m2m_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void l2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
+void m2m_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st);
+void l2l_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st);
 
 constexpr int WAVE = 64;
 constexpr int NRMAX = (2 * MAXP * MAXP + WAVE - 1) / WAVE;  // accumulator rows per lane
@@ -75,34 +77,54 @@ __device__ inline void box_centre(uint64_t key, int level, const double *__restr
 }
 
 // ---------------------------------------------------------------------------
-// P2M: one wavefront per leaf.  For each element, the lanes m < p build the
-// column m of Rt_n^m(xhat) (R_n^m = (-1)^n i^m Rt_n^m) by the recurrence
+// P2M: one workgroup per leaf, one thread per (n, m >= 0) pair (64 * ceil(p(p+1)/2 / 64) threads).
+// For each element, the threads (element, m) build the column m of Rt_n^m(xhat)
+// (R_n^m = (-1)^n i^m Rt_n^m) by the recurrence
 //   Rt_m^m = -(x+iy)/(2m) Rt_{m-1}^{m-1},  Rt_{m+1}^m = z Rt_m^m,
 //   Rt_n^m = ((2n-1) z Rt_{n-1}^m - r^2 Rt_{n-2}^m) / ((n-m)(n+m)),
-// then every lane adds the eq. eve4 contributions of its (n, m) pairs (both potentials, Re and Im).
+// (the divisions by tables of reciprocals), then every thread adds the eq. eve4 contributions of
+// its (n, m) pair (both potentials, Re and Im).  The columns are stored as triangles (n, m <= n).
 // ---------------------------------------------------------------------------
 // SC: scalar harmonic FMM -- phi = sum q g_n^m (the expansion of eq. rsbf5 of each source), chi = 0.
 // SEG: vortex filaments -- each element is a segment (centre x, vector sl) expanded as nq
 // Gauss-Legendre points x + sl xi_j / 2 of strength omega w_j / 2 (eqs. vf5, vf6); quad holds
 // (xi_j, w_j).
-template <typename T, bool SC = false, bool SEG = false>
-__global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off, const int32_t *__restrict__ leaves,
-                                              const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
-                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
-                                              const T *__restrict__ xs, const T *__restrict__ ws,
-                                              const T *__restrict__ qs, int64_t n,
-                                              const double *__restrict__ sys_geo, T *__restrict__ M, int ch,
-                                              const T *__restrict__ sl = nullptr, int nq = 1,
-                                              const double *__restrict__ quad = nullptr)
+constexpr int P2M_MAXT = 512;  // threads per workgroup at most (p(p+1)/2 = 300 at p = 24)
+
+__host__ __device__ inline int tri_idx(int n, int m) { return n * (n + 1) / 2 + m; }
+
+// workgroup size, elements per chunk and LDS bytes of k_p2m at order p for elements of tsize bytes
+inline void p2m_config(int p, size_t tsize, int &nthr, int &ch, size_t &shm)
 {
-    // the leaf's elements in chunks of ch: first every lane forms the regular solid harmonics of
-    // one (element, m) column of the chunk, then every lane adds the chunk's contributions to
-    // its coefficient rows (two barriers per chunk)
+    const int TRI = p * (p + 1) / 2;
+    nthr = std::min(P2M_MAXT, (TRI + WAVE - 1) / WAVE * WAVE);
+    const size_t fixed = tsize * (size_t)(TRI + p + 1);
+    const size_t per = tsize * (size_t)(2 * TRI + 4);
+    ch = (int)std::max<size_t>(1, std::min<size_t>(16, (40960 - fixed) / per));
+    shm = fixed + per * (size_t)ch;
+}
+
+template <typename T, bool SC = false, bool SEG = false>
+__global__ void __launch_bounds__(P2M_MAXT) k_p2m(int p, int depth, int64_t leaf_off, const int32_t *__restrict__ leaves,
+                                                  const int8_t *__restrict__ blev, const uint64_t *__restrict__ bkey,
+                                                  const int32_t *__restrict__ bstart, const int32_t *__restrict__ bcount,
+                                                  const T *__restrict__ xs, const T *__restrict__ ws,
+                                                  const T *__restrict__ qs, int64_t n,
+                                                  const double *__restrict__ sys_geo, T *__restrict__ M, int ch,
+                                                  const T *__restrict__ sl = nullptr, int nq = 1,
+                                                  const double *__restrict__ quad = nullptr)
+{
+    // the leaf's elements in chunks of ch: first the threads form the regular solid harmonics of
+    // the chunk's (element, m) columns, then every thread adds the chunk's contributions to its
+    // coefficient pair (two barriers per chunk)
     extern __shared__ char smem[];
-    T *Rre = (T *)smem;              // [ch][p][p]  (element, n, m)
-    T *Rim = Rre + (size_t)ch * p * p;
-    T *wsh = Rim + (size_t)ch * p * p;  // [ch][4] strengths: omega, q (0 without monopoles)
-    const int lane = threadIdx.x;
+    const int TRI = p * (p + 1) / 2, P2 = p * p;
+    T *rinv = (T *)smem;                 // [TRI] 1 / ((n - m)(n + m)) at (n, m), n >= m + 2
+    T *kinv = rinv + TRI;                // [p + 1] -1 / (2k)
+    T *Rre = kinv + p + 1;               // [ch][TRI]  (element, n, m <= n)
+    T *Rim = Rre + (size_t)ch * TRI;
+    T *wsh = Rim + (size_t)ch * TRI;     // [ch][4] strengths: omega, q (0 without monopoles)
+    const int tid = threadIdx.x, nthr = blockDim.x;
     // uniform tree: leaves leaf_off + blockIdx.x at level depth; adaptive: leaves[blockIdx.x] at blev[]
     const int64_t b = leaves ? (int64_t)leaves[blockIdx.x] : leaf_off + blockIdx.x;
     const int level = blev ? (int)blev[b] : depth;
@@ -110,16 +132,25 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
     double c0, c1, c2, hd;
     box_centre(bkey[b], level, sys_geo, c0, c1, c2, hd);
     const T ih = (T)(1.0 / hd);
-    const int P2 = p * p, TRI = p * (p + 1) / 2;
-    T acc[4 * NPMAX];  // per (n, m) pair of the lane: Re a, Im a, Re b, Im b
-#pragma unroll
-    for (int k = 0; k < 4 * NPMAX; k++) acc[k] = 0;
+    for (int t = tid; t < TRI; t += nthr) {
+        int nn = 0;
+        while (tri_idx(nn + 1, 0) <= t) nn++;
+        const int m = t - tri_idx(nn, 0);
+        rinv[t] = nn >= m + 2 ? (T)(1.0 / (double)((nn - m) * (nn + m))) : (T)0;
+    }
+    for (int k = tid; k <= p; k += nthr) kinv[k] = k ? (T)(-0.5 / (double)k) : (T)0;
+    // this thread's (n, m) pair
+    const bool own = tid < TRI;
+    int nn = 0;
+    while (own && tri_idx(nn + 1, 0) <= tid) nn++;
+    const int m = own ? tid - tri_idx(nn, 0) : 0;
+    T acc[4] = {0, 0, 0, 0};  // Re a, Im a, Re b, Im b
     const int s0 = bstart[b], cnt = bcount[b] * (SEG ? nq : 1);  // SEG: (element, quadrature point)
     for (int e0 = 0; e0 < cnt; e0 += ch) {
         const int ne = min(ch, cnt - e0);
-        __syncthreads();  // the previous chunk's tables are no longer read
-        for (int q = lane; q < ne * p; q += WAVE) {
-            const int e = q / p, m = q - e * p;
+        __syncthreads();  // the previous chunk's tables are no longer read (first pass: the reciprocals are written)
+        for (int q = tid; q < ne * p; q += nthr) {
+            const int e = q / p, mc = q - e * p;
             const int i = SEG ? s0 + (e0 + e) / nq : s0 + e0 + e;
             T px = xs[i], py = xs[n + i], pz = xs[2 * n + i], wf = (T)1;
             if constexpr (SEG) {
@@ -132,36 +163,34 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
             }
             const T x = (px - (T)c0) * ih, y = (py - (T)c1) * ih, z = (pz - (T)c2) * ih;
             const T r2 = x * x + y * y + z * z;
-            T *Re = Rre + (size_t)e * P2, *Im = Rim + (size_t)e * P2;
+            T *Re = Rre + (size_t)e * TRI, *Im = Rim + (size_t)e * TRI;
             // Rt_m^m = (-(x+iy)/2)^m / m!, then up in n
             T are = 1, aim = 0;
-            for (int k = 1; k <= m; k++) {
-                T f = (T)(-0.5) / (T)k;
-                T nre = f * (are * x - aim * y), nim = f * (are * y + aim * x);
+            for (int k = 1; k <= mc; k++) {
+                const T f = kinv[k];
+                const T nre = f * (are * x - aim * y), nim = f * (are * y + aim * x);
                 are = nre;
                 aim = nim;
             }
-            T p2re = 0, p2im = 0, p1re = are, p1im = aim;
-            Re[m * p + m] = are;
-            Im[m * p + m] = aim;
-            for (int nn = m + 1; nn < p; nn++) {
-                T cre, cim;
-                if (nn == m + 1) {
-                    cre = z * p1re;
-                    cim = z * p1im;
-                } else {
-                    T inv = (T)1 / (T)((nn - m) * (nn + m));
-                    cre = ((T)(2 * nn - 1) * z * p1re - r2 * p2re) * inv;
-                    cim = ((T)(2 * nn - 1) * z * p1im - r2 * p2im) * inv;
+            Re[tri_idx(mc, mc)] = are;
+            Im[tri_idx(mc, mc)] = aim;
+            if (mc + 1 < p) {
+                T p2re = are, p2im = aim, p1re = z * are, p1im = z * aim;
+                Re[tri_idx(mc + 1, mc)] = p1re;
+                Im[tri_idx(mc + 1, mc)] = p1im;
+                for (int k = mc + 2; k < p; k++) {
+                    const T inv = rinv[tri_idx(k, mc)], zc = (T)(2 * k - 1) * z;
+                    const T cre = (zc * p1re - r2 * p2re) * inv;
+                    const T cim = (zc * p1im - r2 * p2im) * inv;
+                    Re[tri_idx(k, mc)] = cre;
+                    Im[tri_idx(k, mc)] = cim;
+                    p2re = p1re;
+                    p2im = p1im;
+                    p1re = cre;
+                    p1im = cim;
                 }
-                Re[nn * p + m] = cre;
-                Im[nn * p + m] = cim;
-                p2re = p1re;
-                p2im = p1im;
-                p1re = cre;
-                p1im = cim;
             }
-            if (m == 0) {
+            if (mc == 0) {
                 wsh[4 * e] = SC ? (T)0 : wf * ws[i];
                 wsh[4 * e + 1] = SC ? (T)0 : wf * ws[n + i];
                 wsh[4 * e + 2] = SC ? (T)0 : wf * ws[2 * n + i];
@@ -169,92 +198,76 @@ __global__ void __launch_bounds__(WAVE) k_p2m(int p, int depth, int64_t leaf_off
             }
         }
         __syncthreads();
-        // lane per (n, m >= 0) pair: the three conj(Rt) values of order n (phi) and of order n - 1
-        // (chi) serve all four outputs (Re and Im of a and b)
-#pragma unroll
-        for (int k = 0; k < NPMAX; k++) {
-            const int t = lane + WAVE * k;
-            if (t >= TRI) break;
-            int nn = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-            while (nn * (nn + 1) / 2 > t) --nn;
-            while ((nn + 1) * (nn + 2) / 2 <= t) ++nn;
-            const int m = t - nn * (nn + 1) / 2;
-            const T sgn = (m & 1) ? (T)-1 : (T)1;
-            for (int e = 0; e < ne; e++) {
-                const T *Re = Rre + (size_t)e * P2, *Im = Rim + (size_t)e * P2;
-                const T wx = wsh[4 * e], wy = wsh[4 * e + 1], wz = wsh[4 * e + 2], qe = wsh[4 * e + 3];
-                // conj(Rt_n^k), with the convention conj(Rt_n^{-1}) = -Rt_n^1 that makes the m >= 1
-                // formulas valid at m = 0 as well
-                auto C = [&](int n2, int kk, T &re, T &im) {
-                    if (n2 < 0 || kk > n2) {
+        if (!own) continue;
+        // the three conj(Rt) values of order n (phi) and of order n - 1 (chi) serve all four
+        // outputs (Re and Im of a and b)
+        const T sgn = (m & 1) ? (T)-1 : (T)1;
+        for (int e = 0; e < ne; e++) {
+            const T *Re = Rre + (size_t)e * TRI, *Im = Rim + (size_t)e * TRI;
+            const T wx = wsh[4 * e], wy = wsh[4 * e + 1], wz = wsh[4 * e + 2], qe = wsh[4 * e + 3];
+            // conj(Rt_n^k), with the convention conj(Rt_n^{-1}) = -Rt_n^1 that makes the m >= 1
+            // formulas valid at m = 0 as well
+            auto C = [&](int n2, int kk, T &re, T &im) {
+                if (n2 < 0 || kk > n2) {
+                    re = 0;
+                    im = 0;
+                } else if (kk == -1) {
+                    if (n2 >= 1) {
+                        re = -Re[tri_idx(n2, 1)];
+                        im = -Im[tri_idx(n2, 1)];
+                    } else {
                         re = 0;
                         im = 0;
-                    } else if (kk == -1) {
-                        if (n2 >= 1) {
-                            re = -Re[n2 * p + 1];
-                            im = -Im[n2 * p + 1];
-                        } else {
-                            re = 0;
-                            im = 0;
-                        }
-                    } else {
-                        re = Re[n2 * p + kk];
-                        im = -Im[n2 * p + kk];
                     }
-                };
-                const T wmre = wx, wmim = -wy;  // wx - i wy
-                const T wpre = wx, wpim = wy;   // wx + i wy
-                if constexpr (SC) {
-                    T c3re, c3im;
-                    C(nn, m, c3re, c3im);
-                    acc[4 * k + 0] += qe * sgn * c3re;
-                    acc[4 * k + 1] += qe * sgn * c3im;
-                    continue;
+                } else {
+                    re = Re[tri_idx(n2, kk)];
+                    im = -Im[tri_idx(n2, kk)];
                 }
-                {
-                    // a = -i (-1)^m / (n+1) [ (wx-iwy)(n-m+1)/2 C(m-1) + (wx+iwy)(n+m+1)/2 C(m+1) + wz m C(m) ]
-                    T c1re, c1im, c2re, c2im, c3re, c3im;
-                    C(nn, m - 1, c1re, c1im);
-                    C(nn, m + 1, c2re, c2im);
-                    C(nn, m, c3re, c3im);
-                    T f1 = (T)(nn - m + 1) * (T)0.5, f2 = (T)(nn + m + 1) * (T)0.5, f3 = wz * (T)m;
-                    T sre = f1 * (wmre * c1re - wmim * c1im) + f2 * (wpre * c2re - wpim * c2im) + f3 * c3re;
-                    T sim = f1 * (wmre * c1im + wmim * c1re) + f2 * (wpre * c2im + wpim * c2re) + f3 * c3im;
-                    T sc = sgn / (T)(nn + 1);
-                    // -i (sre + i sim) = sim - i sre; monopole q (eq. 7): phi gains -q g_n^m = -q (-1)^m C(m)
-                    acc[4 * k + 0] += sc * sim - qe * sgn * c3re;
-                    acc[4 * k + 1] += -sc * sre - qe * sgn * c3im;
-                }
-                if (nn >= 1) {
-                    // b = (-1)^m / n [ -1/2 (wx-iwy) C'(m-1) + 1/2 (wx+iwy) C'(m+1) + wz C'(m) ]
-                    T c1re, c1im, c2re, c2im, c3re, c3im;
-                    C(nn - 1, m - 1, c1re, c1im);
-                    C(nn - 1, m + 1, c2re, c2im);
-                    C(nn - 1, m, c3re, c3im);
-                    T sre = (T)-0.5 * (wmre * c1re - wmim * c1im) + (T)0.5 * (wpre * c2re - wpim * c2im) + wz * c3re;
-                    T sim = (T)-0.5 * (wmre * c1im + wmim * c1re) + (T)0.5 * (wpre * c2im + wpim * c2re) + wz * c3im;
-                    T sc = sgn / (T)nn;
-                    acc[4 * k + 2] += sc * sre;
-                    acc[4 * k + 3] += sc * sim;
-                }
+            };
+            const T wmre = wx, wmim = -wy;  // wx - i wy
+            const T wpre = wx, wpim = wy;   // wx + i wy
+            if constexpr (SC) {
+                T c3re, c3im;
+                C(nn, m, c3re, c3im);
+                acc[0] += qe * sgn * c3re;
+                acc[1] += qe * sgn * c3im;
+                continue;
+            }
+            {
+                // a = -i (-1)^m / (n+1) [ (wx-iwy)(n-m+1)/2 C(m-1) + (wx+iwy)(n+m+1)/2 C(m+1) + wz m C(m) ]
+                T c1re, c1im, c2re, c2im, c3re, c3im;
+                C(nn, m - 1, c1re, c1im);
+                C(nn, m + 1, c2re, c2im);
+                C(nn, m, c3re, c3im);
+                T f1 = (T)(nn - m + 1) * (T)0.5, f2 = (T)(nn + m + 1) * (T)0.5, f3 = wz * (T)m;
+                T sre = f1 * (wmre * c1re - wmim * c1im) + f2 * (wpre * c2re - wpim * c2im) + f3 * c3re;
+                T sim = f1 * (wmre * c1im + wmim * c1re) + f2 * (wpre * c2im + wpim * c2re) + f3 * c3im;
+                T sc = sgn / (T)(nn + 1);
+                // -i (sre + i sim) = sim - i sre; monopole q (eq. 7): phi gains -q g_n^m = -q (-1)^m C(m)
+                acc[0] += sc * sim - qe * sgn * c3re;
+                acc[1] += -sc * sre - qe * sgn * c3im;
+            }
+            if (nn >= 1) {
+                // b = (-1)^m / n [ -1/2 (wx-iwy) C'(m-1) + 1/2 (wx+iwy) C'(m+1) + wz C'(m) ]
+                T c1re, c1im, c2re, c2im, c3re, c3im;
+                C(nn - 1, m - 1, c1re, c1im);
+                C(nn - 1, m + 1, c2re, c2im);
+                C(nn - 1, m, c3re, c3im);
+                T sre = (T)-0.5 * (wmre * c1re - wmim * c1im) + (T)0.5 * (wpre * c2re - wpim * c2im) + wz * c3re;
+                T sim = (T)-0.5 * (wmre * c1im + wmim * c1re) + (T)0.5 * (wpre * c2im + wpim * c2re) + wz * c3im;
+                T sc = sgn / (T)nn;
+                acc[2] += sc * sre;
+                acc[3] += sc * sim;
             }
         }
     }
+    if (!own) return;
     T *out = M + (size_t)b * 2 * P2;
-#pragma unroll
-    for (int k = 0; k < NPMAX; k++) {
-        const int t = lane + WAVE * k;
-        if (t >= TRI) break;
-        int nn = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-        while (nn * (nn + 1) / 2 > t) --nn;
-        while ((nn + 1) * (nn + 2) / 2 <= t) ++nn;
-        const int m = t - nn * (nn + 1) / 2;
-        out[pk_re(nn, m)] = acc[4 * k] * ih;
-        out[P2 + pk_re(nn, m)] = acc[4 * k + 2] * ih;
-        if (m > 0) {
-            out[pk_im(nn, m)] = acc[4 * k + 1] * ih;
-            out[P2 + pk_im(nn, m)] = acc[4 * k + 3] * ih;
-        }
+    out[pk_re(nn, m)] = acc[0] * ih;
+    out[P2 + pk_re(nn, m)] = acc[2] * ih;
+    if (m > 0) {
+        out[pk_im(nn, m)] = acc[1] * ih;
+        out[P2 + pk_im(nn, m)] = acc[3] * ih;
     }
 }
 
@@ -557,9 +570,21 @@ struct L2PAcc<float> : CompSum<float> {
 //   F(xhat) = sum_n (-1)^n [F_n^0 Rt_n^0 + 2 Re sum_{m>0} F_n^m Rt_n^m].
 // ---------------------------------------------------------------------------
 // Four leaves per 64-lane workgroup, 16 lanes each (leaves hold a few elements at the depths
-// that minimise the total work, so one wavefront per leaf would leave most lanes idle).
+// that minimise the total work, so one wavefront per leaf would leave most lanes idle).  The
+// velocity coefficients go to a per-leaf block of global memory (Vg, [3][TRI] complex, column-major
+// in (n, m): the column sweep of the evaluation then reads consecutive addresses) rather than to
+// LDS: at high orders the LDS copies of four leaves (53 KB at p = 23 in FP64) left 3 wavefronts
+// per compute unit.  The recurrence divides by a table of reciprocals built in LDS.
 constexpr int L2P_LPB = 4;   // leaves per workgroup
 constexpr int L2P_LANES = WAVE / L2P_LPB;
+
+// column-major offset of (n, m), m <= n < p: columns m = 0 .. p-1 of lengths p - m
+__host__ __device__ inline int cm_idx(int p, int n, int m) { return m * p - m * (m - 1) / 2 + (n - m); }
+
+template <typename T>
+struct Cplx {
+    T re, im;
+};
 
 template <typename T>
 __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, int64_t leaf_off,
@@ -567,18 +592,25 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
                                               const uint64_t *__restrict__ bkey, const int32_t *__restrict__ bstart,
                                               const int32_t *__restrict__ bcount, const T *__restrict__ xs,
                                               const T *__restrict__ ws, int64_t n, const double *__restrict__ sys_geo,
-                                              const T *__restrict__ Lc, T *__restrict__ vfar, int grad)
+                                              const T *__restrict__ Lc, T *__restrict__ vfar, int grad,
+                                              Cplx<T> *__restrict__ Vg)
 {
     extern __shared__ char smem[];
     const int P2 = p * p;
     const int TRI = p * (p + 1) / 2;  // (n, m >= 0) pairs, n < p
+    T *rinv = (T *)smem;              // [TRI] 1 / ((n - m)(n + m)) at cm_idx(n, m), n >= m + 2
+    T *kinv = rinv + TRI;             // [p + 1] -1 / (2k)
+    for (int m = 0; m < p; m++)
+        for (int nn = m + threadIdx.x; nn < p; nn += WAVE)
+            rinv[cm_idx(p, nn, m)] = nn >= m + 2 ? (T)(1.0 / (double)((nn - m) * (nn + m))) : (T)0;
+    for (int k = threadIdx.x; k <= p; k += WAVE) kinv[k] = k ? (T)(-0.5 / (double)k) : (T)0;
     const int g = threadIdx.x / L2P_LANES, lane = threadIdx.x % L2P_LANES;
-    T *Vre = (T *)smem + (size_t)g * 6 * TRI, *Vim = Vre + 3 * TRI;  // this leaf's [3][TRI]
     const int64_t li = (int64_t)blockIdx.x * L2P_LPB + g;
     const bool has = li < nleaf;
     const int64_t b = has ? (leaves ? (int64_t)leaves[li] : leaf_off + li) : 0;
     const int level = has ? (blev ? (int)blev[b] : depth) : 0;
     const bool far = has && level >= 2;  // a leaf above level 2 has no local expansion: far field zero
+    Cplx<T> *V = Vg + (size_t)(has ? li : 0) * 3 * TRI;  // this leaf's [3][TRI]
     const T *cd = Lc + (size_t)b * 2 * P2;
     auto get = [&](int pot, int nn, int m, T &re, T &im) {
         if (nn < 0 || nn >= p) {
@@ -616,17 +648,16 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
             get(1, nn, m + 1, xp1r, xp1i);
             get(1, nn, m, x0r, x0i);
             const T a = (T)(nn - m), c = (T)(nn + m);
+            const int ci = cm_idx(p, nn, m);
             // Vx = 1/2[-Pm1 + Pp1 - i a Xp1 - i c Xm1]
-            Vre[t] = (T)0.5 * (-pm1r + pp1r + a * xp1i + c * xm1i);
-            Vim[t] = (T)0.5 * (-pm1i + pp1i - a * xp1r - c * xm1r);
+            V[ci] = Cplx<T>{(T)0.5 * (-pm1r + pp1r + a * xp1i + c * xm1i), (T)0.5 * (-pm1i + pp1i - a * xp1r - c * xm1r)};
             // Vy = 1/2[i Pm1 + i Pp1 + a Xp1 - c Xm1]
-            Vre[TRI + t] = (T)0.5 * (-pm1i - pp1i + a * xp1r - c * xm1r);
-            Vim[TRI + t] = (T)0.5 * (pm1r + pp1r + a * xp1i - c * xm1i);
+            V[TRI + ci] =
+                Cplx<T>{(T)0.5 * (-pm1i - pp1i + a * xp1r - c * xm1r), (T)0.5 * (pm1r + pp1r + a * xp1i - c * xm1i)};
             // Vz = -P0 - i m X0
-            Vre[2 * TRI + t] = -p0r + (T)m * x0i;
-            Vim[2 * TRI + t] = -p0i - (T)m * x0r;
+            V[2 * TRI + ci] = Cplx<T>{-p0r + (T)m * x0i, -p0i - (T)m * x0r};
         }
-    __syncthreads();
+    __syncthreads();  // the leaf's coefficients (global memory, written by this workgroup) and the tables
     if (!has) return;
     const int s0 = bstart[b], cnt = bcount[b];
     if (!far) {
@@ -638,31 +669,27 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
     double c0, c1, c2, hd;
     box_centre(bkey[b], level, sys_geo, c0, c1, c2, hd);
     const T ih = (T)(1.0 / hd);
+    // V_k at (nn, m) for m = -1 .. nn + 1 (V^{-1} = -conj(V^1), zero beyond the triangle)
     auto vget = [&](int k, int nn, int m, T &re, T &im) {
-        if (nn >= p || nn < 0) {
+        if (nn >= p || nn < 0 || m > nn) {
             re = 0;
             im = 0;
             return;
         }
         if (m == -1) {
             if (nn >= 1) {
-                const int t = nn * (nn + 1) / 2 + 1;
-                re = -Vre[k * TRI + t];
-                im = Vim[k * TRI + t];
+                const Cplx<T> c = V[k * TRI + cm_idx(p, nn, 1)];
+                re = -c.re;
+                im = c.im;
             } else {
                 re = 0;
                 im = 0;
             }
             return;
         }
-        if (m > nn) {
-            re = 0;
-            im = 0;
-            return;
-        }
-        const int t = nn * (nn + 1) / 2 + m;
-        re = Vre[k * TRI + t];
-        im = Vim[k * TRI + t];
+        const Cplx<T> c = V[k * TRI + cm_idx(p, nn, m)];
+        re = c.re;
+        im = c.im;
     };
     for (int e0 = 0; e0 < cnt; e0 += L2P_LANES) {
         const int e = e0 + lane;
@@ -675,7 +702,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
         T mre = 1, mim = 0;
         for (int m = 0; m < p; m++) {
             if (m > 0) {
-                T f = (T)(-0.5) / (T)m;
+                const T f = kinv[m];
                 T nre = f * (mre * x - mim * y), nim = f * (mre * y + mim * x);
                 mre = nre;
                 mim = nim;
@@ -691,7 +718,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(int p, int depth, int64_t nleaf, i
                     rre = z * p1re;
                     rim = z * p1im;
                 } else {
-                    T inv = (T)1 / (T)((nn - m) * (nn + m));
+                    const T inv = rinv[cm_idx(p, nn, m)];
                     rre = ((T)(2 * nn - 1) * z * p1re - r2 * p2re) * inv;
                     rim = ((T)(2 * nn - 1) * z * p1im - r2 * p2im) * inv;
                 }
@@ -1723,6 +1750,7 @@ static void translations(lhf_plan *P, hipStream_t st, bool scalar, const std::fu
     for (int l = d - 1; l >= 2; l--) {
         if (P->lev[l].nb == 0) continue;
         if (P->use_mmhalf) m2m_half_launch(P, l, st);
+        else if (P->use_mmquarter) m2m_quarter_launch(P, l, st);
         else
             hipLaunchKernelGGL(k_m2m<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, P->lev[l].off,
                                P->bchild0, P->bnchild, P->bkey, M, rot, zph, P->dir_theta);
@@ -1737,6 +1765,7 @@ static void translations(lhf_plan *P, hipStream_t st, bool scalar, const std::fu
         if (P->use_tile) {
             // L2L from the parents (zeros at level 2), then the batched M2L adds into it
             if (P->use_mmhalf) l2l_half_launch(P, l, st);
+            else if (P->use_mmquarter) l2l_quarter_launch(P, l, st);
             else
                 hipLaunchKernelGGL(k_down<T>, dim3((unsigned)P->lev[l].nb), dim3(WAVE), sh_rcr, st, p, l, 0,
                                    P->lev[l].off, P->bparent, P->bkey, P->vcount, P->vsrc, P->vdir, (const T *)M,
@@ -1790,10 +1819,10 @@ static lhf_status execute_t(lhf_plan *P, const lhf_io *io, hipStream_t st)
     // uniform tree: the leaves are the boxes of level d; adaptive: the explicit leaf list
     const int64_t loff = P->lev[d].off, nleaf = P->adaptive ? P->nleaf : P->lev[d].nb;
     if (what & 1) {
-        // elements per P2M chunk: 8, fewer at large p (LDS within 48 KB)
-        const int ch = std::max(1, std::min(8, (int)(49152 / (sizeof(T) * (2 * P2 + 4)))));
-        size_t sh_p2m = sizeof(T) * (size_t)ch * (2 * P2 + 4);
-        hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)nleaf), dim3(WAVE), sh_p2m, st, p, d, loff, P->leaves, P->blev,
+        int nthr, ch;
+        size_t sh_p2m;
+        p2m_config(p, sizeof(T), nthr, ch, sh_p2m);
+        hipLaunchKernelGGL(k_p2m<T>, dim3((unsigned)nleaf), dim3(nthr), sh_p2m, st, p, d, loff, P->leaves, P->blev,
                            P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)ws, qin ? (const T *)P->qs : nullptr,
                            n, P->sys_geo, M, ch);
         mark(2);
@@ -1810,10 +1839,10 @@ static lhf_status execute_t(lhf_plan *P, const lhf_io *io, hipStream_t st)
                                chl);
         }
         const int TRI = p * (p + 1) / 2;
-        size_t sh_l2p = sizeof(T) * L2P_LPB * 6 * TRI;
-        hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)((nleaf + L2P_LPB - 1) / L2P_LPB)), dim3(WAVE), sh_l2p, st, p, d,
-                           nleaf, loff, P->leaves, P->blev, P->bkey, P->bstart, P->bcount, (const T *)xs,
-                           (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar, (grad_v || beta) ? 1 : 0);
+        hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)((nleaf + L2P_LPB - 1) / L2P_LPB)), dim3(WAVE),
+                           sizeof(T) * (size_t)(TRI + p + 1), st, p, d, nleaf, loff, P->leaves, P->blev, P->bkey,
+                           P->bstart, P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, (const T *)Lc, vfar,
+                           (grad_v || beta) ? 1 : 0, (Cplx<T> *)P->l2pv);
         if (P->wx_exp) {
             const int TRI1 = (p + 1) * (p + 2) / 2;
             hipLaunchKernelGGL(k_m2p<T>, dim3((unsigned)nleaf), dim3(WAVE), sizeof(T) * 6 * (size_t)TRI1, st, p,
@@ -1863,8 +1892,10 @@ static lhf_status execute_scalar_t(lhf_plan *P, const T *q, T *phi, T *gphi, hip
                        (T *)P->xw);
     mark(1);
     const int64_t loff = P->lev[d].off, nleaf = P->lev[d].nb;
-    const int ch = std::max(1, std::min(8, (int)(49152 / (sizeof(T) * (2 * P2 + 4)))));
-    hipLaunchKernelGGL((k_p2m<T, true>), dim3((unsigned)nleaf), dim3(WAVE), sizeof(T) * (size_t)ch * (2 * P2 + 4), st,
+    int nthr, ch;
+    size_t sh_p2m;
+    p2m_config(p, sizeof(T), nthr, ch, sh_p2m);
+    hipLaunchKernelGGL((k_p2m<T, true>), dim3((unsigned)nleaf), dim3(nthr), sh_p2m, st,
                        p, d, loff, nullptr, nullptr, P->bkey, P->bstart, P->bcount, (const T *)xs, (const T *)P->ws,
                        (const T *)P->qs, n, P->sys_geo, M, ch);
     mark(2);
@@ -1913,9 +1944,10 @@ static lhf_status execute_filament_t(lhf_plan *P, const T *omega, const T *sgam,
                        (const T *)xs, ws, (T *)P->qs, (T *)P->xw);
     mark(1);
     const int64_t loff = P->lev[d].off, nleaf = P->lev[d].nb;
-    const int ch = std::max(1, std::min(8, (int)(49152 / (sizeof(T) * (2 * P2 + 4)))));
-    hipLaunchKernelGGL((k_p2m<T, false, true>), dim3((unsigned)nleaf), dim3(WAVE),
-                       sizeof(T) * (size_t)ch * (2 * P2 + 4), st, p, d, loff, nullptr, nullptr, P->bkey, P->bstart,
+    int nthr, ch;
+    size_t sh_p2m;
+    p2m_config(p, sizeof(T), nthr, ch, sh_p2m);
+    hipLaunchKernelGGL((k_p2m<T, false, true>), dim3((unsigned)nleaf), dim3(nthr), sh_p2m, st, p, d, loff, nullptr, nullptr, P->bkey, P->bstart,
                        P->bcount, (const T *)xs, (const T *)ws, (const T *)nullptr, n, P->sys_geo, M, ch, sl, nq,
                        quad);
     mark(2);
@@ -1923,8 +1955,9 @@ static lhf_status execute_filament_t(lhf_plan *P, const T *omega, const T *sgam,
     mark(4);
     const int TRI = p * (p + 1) / 2;
     hipLaunchKernelGGL(k_l2p<T>, dim3((unsigned)((nleaf + L2P_LPB - 1) / L2P_LPB)), dim3(WAVE),
-                       sizeof(T) * L2P_LPB * 6 * TRI, st, p, d, nleaf, loff, nullptr, nullptr, P->bkey, P->bstart,
-                       P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, (const T *)P->Lc, vfar, 0);
+                       sizeof(T) * (size_t)(TRI + p + 1), st, p, d, nleaf, loff, nullptr, nullptr, P->bkey, P->bstart,
+                       P->bcount, (const T *)xs, (const T *)ws, n, P->sys_geo, (const T *)P->Lc, vfar, 0,
+                       (Cplx<T> *)P->l2pv);
     mark(5);
     hipLaunchKernelGGL(k_p2p_filament<T>, dim3(nblk), dim3(tpb), 0, st, n, loff, P->eleaf, P->ulist, P->bstart,
                        P->bcount, (const T *)xs, sseg, svid, sgam, X, (const T *)vfar, vout);

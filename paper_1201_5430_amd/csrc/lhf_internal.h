@@ -119,6 +119,7 @@ struct lhf_plan {
     int64_t n_m2p = 0, n_p2l = 0;
     void *M = nullptr;           // multipoles [nbox][2][p^2], T
     void *Lc = nullptr;          // locals     [nbox][2][p^2], T
+    void *l2pv = nullptr;        // L2P velocity coefficients [nleaf][3][p(p+1)/2] complex, T
     void *rot = nullptr;         // rotation sets [n_theta][4][rot_set_size(p)], T
     void *zph = nullptr;         // z phases [NDIR][2][p] (cos m phi, sin m phi), T
     int16_t *dir_theta = nullptr;   // [NDIR] polar-angle class of every direction
@@ -145,6 +146,7 @@ struct lhf_plan {
     void *mh = nullptr;                  // its sources, one level at a time, in its lane layout
     double *dtab = nullptr;              // its per-direction |t|, 1/|t|, e^{i phi} ([343][4])
     bool use_mmhalf = false;             // batched M2M and L2L in the same layout
+    bool use_mmquarter = false;          // batched M2M and L2L, four lanes per part vector (FP64 p = 20-24)
     void *wmm = nullptr, *wll = nullptr; // their rotation tables (S basis, R basis)
     bool tile2 = false;                  // VALU tile with two schedule rows per batch (FP32 p = 8, 10)
     void *wmfma = nullptr;               // per-class rotation blocks in MFMA A-operand lane order

@@ -561,6 +561,301 @@ __global__ void k_dirtab_q(double *__restrict__ tab)
     tab[4 * d + 3] = rho > 0.0 ? (double)dy / rho : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// M2M and L2L at the high orders in the same lane layout.  One wavefront per parent box; its
+// children's shifts four at a time (one per 16 lanes: t = lane >> 4), the same RCR steps as the
+// M2L above: rotation about z (phases of the child direction), rotation about y (forward table
+// of the direction's polar class), coaxial (S|S) (M2M) or (R|R) (L2L) shift along z by the
+// parent-child distance with the S- or R-conversion (eq. rcr1) per column m = 4c + q, rotation
+// back about y (the class's back table, read as rows like the forward one) and about z.
+// M2M sums the four shifts by lane exchanges (lane ^ 16, ^ 32) and the wavefront writes the
+// parent's multipole (first group of children) or adds to it (second group); L2L writes each
+// child's local expansion.  The rotation tables (a class's forward and back tables, 186 KB at
+// p = 23) are read from global memory: only two polar classes occur, so they stay in the caches.
+// ---------------------------------------------------------------------------
+namespace qv {
+__host__ __device__ constexpr double taup() { return 0.4330127018922193; }  // sqrt(3)/4
+// (-tau_p)^k / k! as a compile-time constant
+__host__ __device__ constexpr double mm_cf(int k)
+{
+    double c = 1.0;
+    for (int i = 1; i <= k; i++) c *= -taup() / (double)i;
+    return c;
+}
+// the sum of a lane's value over lanes l, l ^ 32 (permlane32 swap of the value with itself)
+__device__ inline double xor32_sum(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)(u & 0xffffffffull), hi = (unsigned)(u >> 32);
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    const double a = __longlong_as_double((long long)(((unsigned long long)rh[0] << 32) | rl[0]));
+    const double b = __longlong_as_double((long long)(((unsigned long long)rh[1] << 32) | rl[1]));
+    return a + b;
+}
+}  // namespace qv
+
+template <int P, int KIND>
+__global__ void __launch_bounds__(256, 1) k_mm_quarter(int64_t poff, int64_t npar, const int32_t *__restrict__ bchild0,
+                                                       const int32_t *__restrict__ bnchild,
+                                                       const int32_t *__restrict__ bparent,
+                                                       const uint64_t *__restrict__ bkey,
+                                                    const double *__restrict__ src_exp, double *__restrict__ dst_exp,
+                                                    const double *__restrict__ wq, int64_t wstride,
+                                                    const int16_t *__restrict__ dir_theta,
+                                                    const double *__restrict__ zph)
+{
+    static_assert(KIND == 0 || KIND == 2, "M2M or L2L");
+    using Sh = qv::Shape<P>;
+    using qv::hoff;
+    using qv::S;
+    constexpr int P2 = Sh::P2, NQ = Sh::NQ, WQS = Sh::WQS;
+    constexpr int DIR0 = NDIR_M2L + (KIND == 0 ? 0 : 8);  // child->parent (M2M), parent->child (L2L)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = lane >> 4, pot0 = (lane >> 3) & 1, part0 = (lane >> 2) & 1, q0 = lane & 3;
+    // coefficient tables in LDS, read through an opaque pointer (as compile-time constants the
+    // compiler would keep all of them in registers across the loop): (-tau_p)^k / k!, 1 / n
+    __shared__ double ktab[2 * 32];
+    if (threadIdx.x < 32) {
+        ktab[threadIdx.x] = threadIdx.x < P ? qv::mm_cf(threadIdx.x) : 0.0;
+        ktab[32 + threadIdx.x] = threadIdx.x ? 1.0 / (double)threadIdx.x : 0.0;
+    }
+    __syncthreads();
+
+    // M2M: one wavefront per parent (poff, npar: the parents' level), its children four at a time;
+    // L2L: four consecutive children per wavefront (poff, npar: the children's level)
+    for (int64_t pq = (int64_t)blockIdx.x * 4 + wave; KIND == 0 ? pq < npar : 4 * pq < npar;
+         pq += (int64_t)gridDim.x * 4) {
+        const int64_t b0 = KIND == 0 ? poff + pq : 0;
+        const int nc = KIND == 0 ? bnchild[b0] : (npar - 4 * pq < 4 ? (int)(npar - 4 * pq) : 4);
+        if (nc == 0) continue;  // M2M: a leaf keeps its own multipole
+        const int c0 = KIND == 0 ? bchild0[b0] : (int)(poff + 4 * pq);
+        for (int bt = 0; bt < nc; bt += 4) {
+            // the lane's role, opaque per batch: keeps the compiler from hoisting the per-lane gather
+            // and scatter offsets of all entries out of the loop (which would exhaust the registers)
+            int part = part0, q = q0, pot = pot0;
+            asm volatile("" : "+v"(part), "+v"(q), "+v"(pot));
+            const bool act = bt + t < nc;
+            const int cb = c0 + (act ? bt + t : 0);
+            const int64_t b = KIND == 0 ? b0 : (int64_t)bparent[cb];  // the parent
+            const int oct = (int)(bkey[cb] & 7u);
+            const int dir = DIR0 + oct;
+            const double *Wt = wq + (size_t)dir_theta[dir] * 2 * wstride + (part * 4 + q) * WQS;  // forward
+            const double *zc = zph + (size_t)dir * 2 * P, *zs = zc + P;  // cos, sin of m phi
+            // the source's entries m = 4j + q of this lane's potential and part
+            const double *sp = src_exp + (size_t)(KIND == 0 ? cb : b) * 2 * P2 + pot * P2;
+            double v[NQ];
+            // all loads first (clamped to the row: every address inside the box), then the masks
+#pragma unroll
+            for (int n = 0; n < P; n++)
+#pragma unroll
+                for (int jj = 0; jj < S(n); jj++) {
+                    const int m = 4 * jj + q;
+                    v[hoff(n) + jj] = sp[n * n + part * n + (m <= n ? m : n)];
+                }
+#pragma unroll
+            for (int n = 0; n < P; n++)
+#pragma unroll
+                for (int jj = 0; jj < S(n); jj++) {
+                    const int m = 4 * jj + q;
+                    const bool ok = act && m <= n && !(part && m == 0);
+                    v[hoff(n) + jj] = ok ? v[hoff(n) + jj] : 0.0;
+                }
+            // 1. rotate about z by +phi: Re' = re c - im s, Im' = im c + re s
+            {
+                const double sgn = part ? 1.0 : -1.0;
+#pragma unroll
+                for (int jj = 0; jj < S(P - 1); jj++) {
+                    const int m = 4 * jj + q < P ? 4 * jj + q : 0;
+                    const double cm = zc[m], sz = zs[m] * sgn;
+#pragma unroll
+                    for (int n = 4 * jj; n < P; n++) {
+                        const double x = v[hoff(n) + jj];
+                        const double o = qv::xor4(x);
+                        v[hoff(n) + jj] = x * cm + o * sz;
+                    }
+                }
+            }
+            // 2. and 5.: rotation about y of every order with table W: partial sums of the four
+            //    output groups over the lane's columns, then the quad butterfly
+            auto rotate_y = [&](const double *W) __attribute__((always_inline)) {
+#pragma unroll
+                for (int n = 0; n < P; n++) {
+                    // one opaque base address per order: the rows' loads take immediate offsets from it
+                    // (precomputed addresses of every row would fill the register file)
+                    const double *Wn = W + qv::woff(n);
+                    asm volatile("" : "+v"(Wn));
+                    constexpr int SM = (P - 1) / 4 + 1;
+                    double g[4][SM];
+#pragma unroll
+                    for (int kk = 0; kk < 4; kk++)
+#pragma unroll
+                        for (int jj = 0; jj < S(n); jj++) {
+                            g[kk][jj] = qv::dotw(Wn + (kk * S(n) + jj) * qv::RL(n), &v[hoff(n)], S(n));
+                            // bound the table reads in flight (they do not depend on v)
+                            if (jj % 2 == 1 || jj == S(n) - 1) __builtin_amdgcn_sched_barrier(0);
+                        }
+#pragma unroll
+                    for (int jj = 0; jj < S(n); jj++) {
+                        const double a = g[0][jj] + dpp_f<DPP_XOR1>(g[1][jj]);
+                        const double bb = g[2][jj] + dpp_f<DPP_XOR1>(g[3][jj]);
+                        v[hoff(n) + jj] = a + dpp_f<DPP_XOR2>(bb);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            rotate_y(Wt);
+            // 3+4. per column m = 4c + q: coaxial shift, then the conversion
+            {
+                const double *kt = ktab;
+                asm volatile("" : "+v"(kt));
+                const double *cf = kt, *rn = kt + 32;
+                const double wphi = pot ? 0.0 : 1.0, wchi = pot ? 1.0 : 0.0;
+#pragma unroll
+                for (int c = 0; c < S(P - 1); c++) {
+                    const int n0 = 4 * c;
+                    const double mval = (double)(4 * c + q);
+                    // the column's entries are read in place (they are overwritten only after out[]),
+                    // through an opaque copy: otherwise the compiler starts the sums of every column
+                    // while the rotation produces their entries and runs out of registers
+#pragma unroll
+                    for (int n2 = n0; n2 < P; n2++) asm volatile("" : "+v"(v[hoff(n2) + c]));
+                    double out[P];
+                    if (KIND == 0) {
+                        // (S|S): out_n = sum_{n' = m}^{n} cf_{n-n'} (1/2 [phi] | 1 [chi]) 2^-n' in_n'
+                        const int e0 = pot ? 0 : -1;
+#pragma unroll
+                        for (int n2 = n0; n2 < P; n2++) v[hoff(n2) + c] = ldexp(v[hoff(n2) + c], e0 - n2);
+#pragma unroll
+                        for (int n = n0; n < P; n++) {
+                            double a = 0;
+#pragma unroll
+                            for (int n2 = n0; n2 <= n; n2++) a += cf[n - n2] * v[hoff(n2) + c];
+                            out[n] = a;
+                        }
+                    } else {
+                        // (R|R): out_n = (1 [phi] | 1/2 [chi]) 2^-n sum_{n' = n}^{p-1} cf_{n'-n} in_n'
+                        const int e0 = pot ? -1 : 0;
+#pragma unroll
+                        for (int n = n0; n < P; n++) {
+                            double a = 0;
+#pragma unroll
+                            for (int n2 = n; n2 < P; n2++) a += cf[n2 - n] * v[hoff(n2) + c];
+                            out[n] = ldexp(a, e0 - n);
+                        }
+                    }
+#pragma unroll
+                    for (int n = n0; n < P; n++) {
+                        const double other = swz_xor<12>(out[n]);  // phi-Re <-> chi-Im, phi-Im <-> chi-Re
+                        double val;
+                        if (KIND == 0) {
+                            // S-conversion: phi~ = phi - i tau m/(n+1) chi,  chi~_n = chi_n + tau/n chi_{n-1}
+                            const double tau = qv::taup();
+                            const double fphi = tau * mval * rn[n + 1] * (part ? -1.0 : 1.0) * wphi;
+                            const double prev = (n > n0) ? out[n - 1] : 0.0;
+                            const double fchi = tau * rn[n] * wchi;  // rn[0] = 0
+                            val = out[n] + fphi * other + fchi * prev;
+                        } else {
+                            // R-conversion: phi~ = phi + i tau m/n chi,  chi~_n = chi_n - tau/(n+1) chi_{n+1}
+                            const double tau = 2.0 * qv::taup();
+                            const double fphi = tau * mval * rn[n] * (part ? 1.0 : -1.0) * wphi;  // rn[0] = 0
+                            const double next = (n + 1 < P) ? out[n + 1] : 0.0;
+                            const double fchi = -tau * rn[n + 1] * wchi;
+                            val = out[n] + fphi * other + fchi * next;
+                        }
+                        v[hoff(n) + c] = (n - n0 < q) ? 0.0 : val;  // slot (n, c) holds m = 4c + q > n: empty
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            rotate_y(Wt + wstride);  // the back table of the class
+            // the lane's role again, opaque: the offsets and phases of the gather and of step 1 are
+            // recomputed rather than kept live through the translation
+            asm volatile("" : "+v"(part), "+v"(q), "+v"(pot));
+            zc = zph + (size_t)dir * 2 * P;
+            asm volatile("" : "+v"(zc));
+            zs = zc + P;
+            // 6. rotate about z by -phi: Re' = re c + im s, Im' = im c - re s
+            {
+                const double sgn = part ? -1.0 : 1.0;
+#pragma unroll
+                for (int jj = 0; jj < S(P - 1); jj++) {
+                    const int m = 4 * jj + q < P ? 4 * jj + q : 0;
+                    const double cm = zc[m], sz = zs[m] * sgn;
+#pragma unroll
+                    for (int n = 4 * jj; n < P; n++) {
+                        const double x = v[hoff(n) + jj];
+                        const double o = qv::xor4(x);
+                        v[hoff(n) + jj] = x * cm + o * sz;
+                    }
+                }
+            }
+            if (KIND == 0) {
+                // sum over the four children of this group (lane ^ 16, ^ 32); the first group writes
+                // the parent's multipole, the second adds to it
+#pragma unroll
+                for (int i = 0; i < NQ; i++) {
+                    double x = v[i];
+                    x += swz_xor<16>(x);
+                    v[i] = qv::xor32_sum(x);
+                }
+                if (t == 0) {
+                    double *dp = dst_exp + (size_t)b * 2 * P2 + pot * P2;
+#pragma unroll
+                    for (int n = 0; n < P; n++)
+#pragma unroll
+                        for (int jj = 0; jj < S(n); jj++) {
+                            const int m = 4 * jj + q;
+                            if (m <= n && !(part && m == 0)) {
+                                const int k = n * n + part * n + m;
+                                dp[k] = bt ? dp[k] + v[hoff(n) + jj] : v[hoff(n) + jj];
+                            }
+                        }
+                }
+            } else if (act) {
+                double *dp = dst_exp + (size_t)cb * 2 * P2 + pot * P2;
+#pragma unroll
+                for (int n = 0; n < P; n++)
+#pragma unroll
+                    for (int jj = 0; jj < S(n); jj++) {
+                        const int m = 4 * jj + q;
+                        if (m <= n && !(part && m == 0)) dp[n * n + part * n + m] = v[hoff(n) + jj];
+                    }
+            }
+        }
+    }
+}
+
+// Forward and back rotation tables of every polar-angle class for M2M (S basis both ways) or L2L
+// (R basis both ways) in the quarter layout of k_wquarter: [class][fwd, back][part][residue][WQS]
+template <int P>
+__global__ void k_wquarter_mm(const double *__restrict__ rot, double *__restrict__ wq, int64_t stride, int kfwd,
+                              int kback)
+{
+    using Sh = qv::Shape<P>;
+    const int th = blockIdx.x, fb = blockIdx.y;
+    const double *Rf = rot + ((size_t)th * ROT_NKIND + (fb ? kback : kfwd)) * rot_set_size(P);
+    double *dst = wq + ((size_t)th * 2 + fb) * stride;
+    for (int idx = threadIdx.x; idx < stride; idx += blockDim.x) {
+        double val = 0.0;
+        const int tb = idx / Sh::WQS, e = idx % Sh::WQS;
+        const int part = tb >> 2, q = tb & 3;
+        if (e < Sh::WQ) {
+            int n = 0;
+            while (qv::woff(n + 1) <= e) n++;
+            const int r = e - qv::woff(n), row = r / qv::RL(n), i = r % qv::RL(n);
+            const int kk = row / qv::S(n), jr = row % qv::S(n);
+            const int mp = 4 * jr + (q ^ kk), m = 4 * i + q;
+            if (i < qv::S(n) && mp <= n && m <= n) {
+                const double *blk = Rf + rot_block_off(n);
+                if (part == 0) val = blk[mp * (n + 1) + m];
+                else if (mp > 0 && m > 0) val = blk[(n + 1) * (n + 1) + (mp - 1) * n + (m - 1)];
+            }
+        }
+        dst[idx] = val;
+    }
+}
+
 namespace {
 
 template <int P>
@@ -607,6 +902,54 @@ static void launch_quarter(const lhf_plan *Pl, int level, hipStream_t st)
         (const double *)Pl->whalf, 8 * (int64_t)qv::Shape<P>::WQS, sch, Pl->sched_cls_theta, Pl->dtab);
 }
 
+
+template <int P>
+static bool mmquarter_build_t(lhf_plan *Pl, hipStream_t st)
+{
+    const int64_t stride = 8 * (int64_t)qv::Shape<P>::WQS;
+    if (dev_malloc(&Pl->wmm, sizeof(double) * 2 * stride * Pl->n_theta) != hipSuccess) return false;
+    if (dev_malloc(&Pl->wll, sizeof(double) * 2 * stride * Pl->n_theta) != hipSuccess) return false;
+    k_wquarter_mm<P><<<dim3((unsigned)Pl->n_theta, 2), dim3(256), 0, st>>>((const double *)Pl->rot, (double *)Pl->wmm,
+                                                                           stride, ROT_S_FWD, ROT_S_BACK);
+    k_wquarter_mm<P><<<dim3((unsigned)Pl->n_theta, 2), dim3(256), 0, st>>>((const double *)Pl->rot, (double *)Pl->wll,
+                                                                           stride, ROT_R_FWD, ROT_R_BACK);
+    return hipGetLastError() == hipSuccess;
+}
+
+// KIND 0: M2M into the parents of level l; KIND 2: L2L from level l - 1 into level l (l >= 3)
+template <int P, int KIND>
+static void launch_mm_quarter(const lhf_plan *Pl, int l, hipStream_t st)
+{
+    // M2M: the parents of level l; L2L: the children of level l
+    const int64_t off = Pl->lev[l].off, nb = Pl->lev[l].nb;
+    if (nb == 0) return;
+    const int64_t nwave = KIND == 0 ? nb : (nb + 3) / 4;
+    const unsigned grid = (unsigned)std::min<int64_t>((nwave + 3) / 4, 16384);
+    const double *src = (const double *)(KIND == 0 ? Pl->M : Pl->Lc);
+    double *dst = (double *)(KIND == 0 ? Pl->M : Pl->Lc);
+    k_mm_quarter<P, KIND><<<dim3(grid), dim3(256), 0, st>>>(
+        off, nb, Pl->bchild0, Pl->bnchild, Pl->bparent, Pl->bkey, src, dst,
+        (const double *)(KIND == 0 ? Pl->wmm : Pl->wll),
+        8 * (int64_t)qv::Shape<P>::WQS, Pl->dir_theta, (const double *)Pl->zph);
+}
+
+__global__ void k_zero_exp_q(int64_t count, double *__restrict__ dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = 0.0;
+}
+
+template <int KIND>
+static void mm_quarter_dispatch(const lhf_plan *Pl, int l, hipStream_t st)
+{
+    switch (Pl->p) {
+    case 20: launch_mm_quarter<20, KIND>(Pl, l, st); break;
+    case 22: launch_mm_quarter<22, KIND>(Pl, l, st); break;
+    case 23: launch_mm_quarter<23, KIND>(Pl, l, st); break;
+    case 24: launch_mm_quarter<24, KIND>(Pl, l, st); break;
+    }
+}
+
 }  // namespace
 
 bool m2l_quarter_supported(int precision, int p)
@@ -646,6 +989,38 @@ void m2l_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st)
     case 23: launch_quarter<23>(Pl, level, st); break;
     case 24: launch_quarter<24>(Pl, level, st); break;
     }
+}
+
+bool mm_quarter_supported(int precision, int p)
+{
+    return precision == LHF_FP64 && (p == 20 || p == 22 || p == 23 || p == 24);
+}
+
+bool mmquarter_build(lhf_plan *Pl, hipStream_t st)
+{
+    switch (Pl->p) {
+    case 20: return mmquarter_build_t<20>(Pl, st);
+    case 22: return mmquarter_build_t<22>(Pl, st);
+    case 23: return mmquarter_build_t<23>(Pl, st);
+    case 24: return mmquarter_build_t<24>(Pl, st);
+    }
+    return false;
+}
+
+// M2M into the boxes of level l from their children
+void m2m_quarter_launch(const lhf_plan *Pl, int l, hipStream_t st) { mm_quarter_dispatch<0>(Pl, l, st); }
+
+// L2L into the boxes of level l from their parents; level 2 starts from zero
+void l2l_quarter_launch(const lhf_plan *Pl, int l, hipStream_t st)
+{
+    if (l <= 2) {
+        const int64_t cnt = Pl->lev[l].nb * 2 * (int64_t)Pl->p * Pl->p;
+        if (cnt > 0)
+            k_zero_exp_q<<<dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st>>>(
+                cnt, (double *)Pl->Lc + Pl->lev[l].off * 2 * (int64_t)Pl->p * Pl->p);
+        return;
+    }
+    mm_quarter_dispatch<2>(Pl, l, st);
 }
 
 }  // namespace lhf

@@ -41,6 +41,8 @@ bool m2l_half_owned(int precision, int p);
 bool m2l_quarter_supported(int precision, int p);
 bool wquarter_build(lhf_plan *Pl, hipStream_t st);
 bool mm_half_supported(int precision, int p);
+bool mm_quarter_supported(int precision, int p);
+bool mmquarter_build(lhf_plan *Pl, hipStream_t st);
 
 // ---- device memory cache -----------------------------------------------------------------
 namespace {
@@ -1006,11 +1008,15 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     hipLaunchKernelGGL(k_zph<T>, dim3((NDIR * p + 255) / 256), dim3(256), 0, st, p, (T *)P->zph);
     hipLaunchKernelGGL(k_coax<T>, dim3(1), dim3(32), 0, st, p, (T *)P->coax);
     LHF_HIP(hipGetLastError());
-    // batched M2M and L2L (two lanes per part vector) at the orders the half-vector kernels
-    // cover; LHF_NO_MMHALF=1 keeps the generic per-box shifts
+    // batched M2M and L2L: two lanes per part vector (p = 8-16) or four (FP64 p = 20-24)
     P->use_mmhalf = P->mm_kind == LHF_MM_HALF;
     if (P->use_mmhalf && !mmhalf_build(P, st)) {
         set_error("batched M2M/L2L set-up failed");
+        return LHF_ERR_HIP;
+    }
+    P->use_mmquarter = P->mm_kind == LHF_MM_QUARTER;
+    if (P->use_mmquarter && !mmquarter_build(P, st)) {
+        set_error("quarter-vector M2M/L2L set-up failed");
         return LHF_ERR_HIP;
     }
     // batched M2L (decided with the tree): schedule, padded rotation blocks, dense box maps
@@ -1073,7 +1079,7 @@ static void free_plan(lhf_plan *P)
     void *bufs[] = {P->perm, P->xs, P->ws, P->vfar, P->xw, P->bkey, P->bstart, P->bcount, P->bparent, P->bchild0,
                     P->bnchild, P->vcount, P->vsrc, P->vdir, P->ulist, P->eleaf, P->M, P->Lc, P->rot,
                     P->zph, P->dir_theta, P->coax, P->dflag, P->dtmp, P->sys_geo, P->sys_a, P->sys_off,
-                    P->blev, P->leaves, P->nl_start, P->nl_ent, P->qs, P->wx_start, P->wx_ent};
+                    P->blev, P->leaves, P->nl_start, P->nl_ent, P->qs, P->wx_start, P->wx_ent, P->l2pv};
     for (void *b : bufs)
         if (b) (void)dev_free(b);
     for (int l = 0; l <= MAXDEPTH; l++)
@@ -1257,6 +1263,8 @@ static lhf_status plan_create_t(lhf_plan *P, const void *x, hipStream_t st)
     }
     CK(dev_malloc(&P->M, sizeof(T) * tot * 2 * P2));
     CK(dev_malloc(&P->Lc, sizeof(T) * tot * 2 * P2));
+    // L2P velocity coefficients, per leaf [3][p(p+1)/2] complex
+    CK(dev_malloc(&P->l2pv, sizeof(T) * (size_t)std::max<int64_t>(P->nleaf, 1) * 3 * P->p * (P->p + 1)));
     // multipoles of levels 0 and 1 are never formed, yet kernels read box 0 as a stand-in
     // source for inactive lanes: every multipole starts as a defined zero
     CK(hipMemsetAsync(P->M, 0, sizeof(T) * tot * 2 * P2, st));
@@ -1477,9 +1485,15 @@ lhf_status resolve_kernels(const lhf_desc *d, int p, bool dmap_ok, int *m2l, int
         }
     }
     int mk = d->mm_kernel;
-    if (mk == LHF_MM_AUTO) mk = mm_half_supported(prec, p) ? LHF_MM_HALF : LHF_MM_GENERIC;
+    if (mk == LHF_MM_AUTO)
+        mk = mm_half_supported(prec, p)      ? LHF_MM_HALF
+             : mm_quarter_supported(prec, p) ? LHF_MM_QUARTER
+                                             : LHF_MM_GENERIC;
     else if (mk == LHF_MM_HALF && !mm_half_supported(prec, p)) {
         set_error("mm_kernel HALF has no instantiation for this precision and p");
+        return LHF_ERR_UNSUPPORTED;
+    } else if (mk == LHF_MM_QUARTER && !mm_quarter_supported(prec, p)) {
+        set_error("mm_kernel QUARTER has no instantiation for this precision and p");
         return LHF_ERR_UNSUPPORTED;
     }
     *m2l = k;
@@ -1516,7 +1530,7 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
     }
     if (d->translation != LHF_TRANS_RCR) return arg_error("unknown translation scheme");
     if (d->m2l_kernel < LHF_M2L_AUTO || d->m2l_kernel > LHF_M2L_QUARTER) return arg_error("unknown m2l_kernel");
-    if (d->mm_kernel < LHF_MM_AUTO || d->mm_kernel > LHF_MM_GENERIC) return arg_error("unknown mm_kernel");
+    if (d->mm_kernel < LHF_MM_AUTO || d->mm_kernel > LHF_MM_QUARTER) return arg_error("unknown mm_kernel");
     if (d->depth < 2 || d->depth > MAXDEPTH) return arg_error("depth out of range (2..10)");
     if (d->max_per_leaf < 0) return arg_error("max_per_leaf must be >= 0");
     if (!(d->tol > 0.0)) return arg_error("tol must be > 0");

@@ -323,3 +323,34 @@ def test_batched_m2m_l2l_match_generic(prec, p, depth):
         _check(v1, s1, v2, s2, l2=1e-13, mx=1e-12)
     else:
         _check32(v1, s1, v2, s2)
+
+
+@pytest.mark.parametrize("p", [20, 23, 24])
+def test_quarter_m2m_l2l_match_generic(oracle, p):
+    # the quarter-vector M2M/L2L kernels (the default at FP64 p = 20, 22, 23, 24) against the
+    # generic per-box shifts, on a uniform tree and on the adaptive ring (parents with one to eight
+    # children), and against the oracle on sampled elements
+    import paper_1201_5430_amd as L
+    import workloads
+    rng = np.random.default_rng(130 + p)
+    n = 20000
+    x = rng.uniform(0, 1, (n, 3))
+    w = rng.normal(size=(n, 3))
+    a = 0.5 * n ** (-1 / 3)
+    v1, s1, st1 = _gpu_fmm(x, w, a, p, 4)
+    v2, s2, st2 = _gpu_fmm(x, w, a, p, 4, mm_kernel=L.MM_GENERIC)
+    assert st1["mm_kernel"] == "quarter" and st2["mm_kernel"] == "generic"
+    print(f"quarter vs generic M2M/L2L p={p}: ", end="")
+    _check(v1, s1, v2, s2, l2=1e-13, mx=1e-12)
+    samp = rng.choice(n, 30, replace=False)
+    vr, sr, _ = oracle.fmm(x, w, a, p, 4, sample=samp)
+    m = ~np.isnan(vr[:, 0])
+    print("  vs oracle: ", end="")
+    _check(v1[m], s1[m], vr[m], sr[m])
+    xr, wr = workloads.vortex_ring(8000, 131)
+    ar = workloads.core_radius(8000)
+    v1, s1, st1 = _gpu_fmm(xr, wr, ar, p, 7, max_per_leaf=16)
+    v2, s2, _ = _gpu_fmm(xr, wr, ar, p, 7, max_per_leaf=16, mm_kernel=L.MM_GENERIC)
+    assert st1["mm_kernel"] == "quarter"
+    print("  adaptive ring: ", end="")
+    _check(v1, s1, v2, s2, l2=1e-13, mx=1e-12)
