@@ -132,17 +132,29 @@ def measured_traffic(name):
         return None
 
 
-def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warmup, wx=False, q=None):
+def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warmup, wx=False, q=None, tune=False):
     """time `steps` plan + execute steps (inputs resident on the device); per-phase times from the
-    library's HIP events on the execute stream"""
+    library's HIP events on the execute stream.  tune: the run-time kernel shapes (M2L tile per
+    level, near-field source tile) are measured once on a plan of the workload before the warm-up
+    (not timed) and applied to every plan of the timed steps"""
     dt = torch.float64 if prec == lhf.FP64 else torch.float32
     xt = torch.from_numpy(x).to(device="cuda", dtype=dt)
     wt = torch.from_numpy(w).to(device="cuda", dtype=dt)
     v, s = torch.empty_like(wt), torch.empty_like(wt)
     qt = None if q is None else torch.from_numpy(q).to(device="cuda", dtype=dt)
+    shapes, tune_s = None, None
+    if tune:
+        t0 = time.perf_counter()
+        pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=max_per_leaf, wx_expansions=wx)
+        shapes = pl.autotune(wt)
+        pl.close()
+        tune_s = time.perf_counter() - t0
+        log(f"bench: {name}: tuned shapes {shapes} in {tune_s:.1f} s")
 
     def step(profile):
         pl = lhf.Plan(xt, a, p=p, depth=depth, precision=prec, max_per_leaf=max_per_leaf, wx_expansions=wx)
+        if shapes is not None:
+            pl.set_shapes(shapes)
         if profile:
             pl.profile_begin(1)
         if qt is None:
@@ -179,6 +191,9 @@ def run_leg(lhf, torch, name, x, w, a, p, prec, depth, max_per_leaf, steps, warm
                       "p2l_pairs": st["n_p2l"]}}
     if wx:
         res["wx_expansions"] = True
+    if shapes is not None:
+        res["tuned_shapes"] = shapes
+        res["tune_s"] = tune_s
     if prec == lhf.FP64:
         res["m2l_frac_of_fp64_peak"] = m2l_tf / PEAK_FP64_TFLOPS if m2l_tf else None
     else:
@@ -402,6 +417,8 @@ def main():
                     help="comma list of ring16, wx, scalar, filament, cube, batch (or none)")
     ap.add_argument("--targets", type=int, default=4096, help="sample targets of the headline accuracy")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle legs (baseline, accuracy)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="built-in kernel shapes (no run-time autotuning of M2L and near-field tiles)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="only copy a buffer of this many MiB on the device (HBM counter calibration)")
     args = ap.parse_args()
@@ -440,7 +457,7 @@ def main():
     p = args.p
     log(f"bench: headline ring N={n} FP64 p={p} adaptive <= {mx}/leaf, level <= {lmax}")
     head, st, (vh, sh) = run_leg(lhf, torch, f"ring4m_fp64_p{p}", x, w, a, p, lhf.FP64, lmax, mx, args.steps,
-                                 args.warmup)
+                                 args.warmup, tune=not args.no_tune)
     ph = head["phases_ms"]
     launches = sum(1 for l in range(2, len(st["boxes"])) if st["boxes"][l] > 0)
     flops = st["n_m2l"] * f_m2l(p)
@@ -493,7 +510,7 @@ def main():
         ring = {}
         for prec, nm in ((lhf.FP32, "fp32"), (lhf.FP64, "fp64")):
             r, _, o = run_leg(lhf, torch, f"ring4m_{nm}_p16", x, w, a, 16, prec, lmax, mx, args.leg_steps,
-                              args.warmup)
+                              args.warmup, tune=not args.no_tune)
             ring[nm] = r
             outs[nm] = o
         ring["speedup_fp32_vs_fp64"] = ring["fp64"]["ms_per_step"] / ring["fp32"]["ms_per_step"]

@@ -292,6 +292,34 @@ const char *lhf_last_error(void);
 lhf_status lhf_profile_begin(lhf_plan *plan, int32_t max_exec);
 lhf_status lhf_profile_end(lhf_plan *plan, double *phase_ms, int32_t *n_exec);
 
+/* ---- Run-time kernel shapes of a plan (autotuner) ----
+ *
+ * Shapes the library can choose at run time without rebuilding the plan: the number of target
+ * boxes per workgroup tile of the quarter-vector M2L kernel at every level (FP64 p = 16-24;
+ * 1 .. 6 at p = 23, more at lower orders, as the LDS allows), and the number of source elements
+ * staged per LDS tile by the adaptive near-field kernel (64, 128 or 256; v and s outputs only:
+ * with grad_v, beta or monopoles the kernel keeps 128).  0 means the built-in choice. */
+typedef struct {
+    int32_t m2l_tile[9];  /* [level 0 .. 8]; 0: built-in (as many targets as fit, at least ~1024 tiles) */
+    int32_t p2p_tile;     /* 0: built-in (128) */
+} lhf_shapes;
+
+/* Measure the shapes on the plan's own tree and keep the fastest in the plan: one whole
+ * evaluation with omega (device [N][3], the plan's precision), then every level's M2L launched
+ * once per candidate tile and the adaptive near field once per candidate source tile, timed with
+ * HIP events on 'stream'.  With a non-NULL cache_path the shapes are looked up first in, and else
+ * appended to, a JSON file keyed by device architecture, precision, p, tree kind, depth and N.
+ * Synchronises 'stream', allocates temporary device memory (two [N][3] buffers); the plan's
+ * intermediate buffers are left inconsistent, so the next lhf_execute recomputes them (outputs
+ * are only ever written by lhf_execute).  out may be NULL. */
+lhf_status lhf_plan_autotune(lhf_plan *plan, const void *omega, const char *cache_path, lhf_shapes *out,
+                             void *stream);
+
+/* Apply shapes (for instance those measured on an earlier plan of the same workload), or read the
+ * plan's current ones.  Values outside the ranges above give LHF_ERR_ARG and change nothing. */
+lhf_status lhf_plan_set_shapes(lhf_plan *plan, const lhf_shapes *shapes);
+lhf_status lhf_plan_get_shapes(const lhf_plan *plan, lhf_shapes *shapes);
+
 /* ---- Batches of independent systems with per-system depth (one HIP graph) ----
  *
  * Unit costs of the depth cost model (the paper's complexity analysis, Sec. 4.1,

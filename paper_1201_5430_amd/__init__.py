@@ -35,7 +35,8 @@ EXPORTS = ("lhf_desc_default", "lhf_plan_create", "lhf_plan_create_multi", "lhf_
            "lhf_profile_begin", "lhf_profile_end", "lhf_tune_default", "lhf_autotune", "lhf_choose_depth",
            "lhf_batch_create", "lhf_batch_execute", "lhf_batch_info", "lhf_batch_destroy",
            "lhf_release_cached_memory", "lhf_evaluate_noalloc", "lhf_execute_io", "lhf_execute_scalar",
-           "lhf_filament_create", "lhf_filament_execute", "lhf_filament_plan", "lhf_filament_destroy")
+           "lhf_filament_create", "lhf_filament_execute", "lhf_filament_plan", "lhf_filament_destroy",
+           "lhf_plan_autotune", "lhf_plan_set_shapes", "lhf_plan_get_shapes")
 PHASES = ("gather", "p2m", "m2m", "down", "l2p", "p2p", "m2l")
 
 
@@ -63,6 +64,10 @@ class Stats(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("p", C.c_int32), ("precision", C.c_int32), ("t_box_ns", C.c_double), ("t_pair_ns", C.c_double)]
+
+
+class Shapes(C.Structure):
+    _fields_ = [("m2l_tile", C.c_int32 * 9), ("p2p_tile", C.c_int32)]
 
 
 class LhfError(RuntimeError):
@@ -136,6 +141,12 @@ def load():
         L.lhf_batch_info.restype = C.c_int
         L.lhf_batch_destroy.argtypes = [vp]
         L.lhf_batch_destroy.restype = C.c_int
+        L.lhf_plan_autotune.argtypes = [vp, vp, C.c_char_p, C.POINTER(Shapes), vp]
+        L.lhf_plan_autotune.restype = C.c_int
+        L.lhf_plan_set_shapes.argtypes = [vp, C.POINTER(Shapes)]
+        L.lhf_plan_set_shapes.restype = C.c_int
+        L.lhf_plan_get_shapes.argtypes = [vp, C.POINTER(Shapes)]
+        L.lhf_plan_get_shapes.restype = C.c_int
         _lib = L
     return _lib
 
@@ -288,6 +299,27 @@ class Plan:
                     mm_kernel=("auto", "half", "generic", "quarter")[st.mm_kernel], deterministic=bool(st.deterministic),
                     p_from_tol=bool(st.p_from_tol), calib_err_v=st.calib_err_v, calib_err_s=st.calib_err_s,
                     warnings=st.warnings, wx_expansions=bool(st.wx_expansions), n_m2p=st.n_m2p, n_p2l=st.n_p2l)
+
+    def autotune(self, omega, cache_path=None):
+        """measure the run-time kernel shapes on this plan (one evaluation, then timed candidates);
+        returns them as dict(m2l_tile=[levels 0..8], p2p_tile=...)"""
+        omega = _dev_array(omega, self.dtype, "omega", self.n)
+        sh = Shapes()
+        cp = cache_path.encode() if cache_path else None
+        _check(load().lhf_plan_autotune(self._h, C.c_void_p(omega.data_ptr()), cp, C.byref(sh), _stream()))
+        return dict(m2l_tile=list(sh.m2l_tile), p2p_tile=sh.p2p_tile)
+
+    def set_shapes(self, shapes):
+        sh = Shapes()
+        for i, t in enumerate(shapes.get("m2l_tile", [0] * 9)):
+            sh.m2l_tile[i] = int(t)
+        sh.p2p_tile = int(shapes.get("p2p_tile", 0))
+        _check(load().lhf_plan_set_shapes(self._h, C.byref(sh)))
+
+    def get_shapes(self):
+        sh = Shapes()
+        _check(load().lhf_plan_get_shapes(self._h, C.byref(sh)))
+        return dict(m2l_tile=list(sh.m2l_tile), p2p_tile=sh.p2p_tile)
 
     def profile_begin(self, max_exec):
         _check(load().lhf_profile_begin(self._h, int(max_exec)))

@@ -15,6 +15,7 @@
 // per-translation intermediate vectors in LDS.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <functional>
 
 #include <algorithm>
@@ -33,6 +34,7 @@ bool m2l_half_scalar_supported(int precision, int p);
 void m2l_half_scalar_stage(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_half_scalar_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_quarter_stage(const lhf_plan *Pl, int level, hipStream_t st);
+int m2l_quarter_max_ns(int p);
 void m2m_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void l2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2m_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st);
@@ -1367,7 +1369,7 @@ __global__ void __launch_bounds__(256) k_p2p(int64_t n, int depth, int64_t leaf_
 // branch in the kernel).  Per tile the lane's partial sums enter compensated accumulators.
 constexpr int P2P_TS = 128;
 
-template <typename T, bool GRAD, bool Q>
+template <typename T, bool GRAD, bool Q, int TS = P2P_TS>
 __global__ void __launch_bounds__(64) k_p2p_tile(int64_t n, const int32_t *__restrict__ leaves,
                                                  const int8_t *__restrict__ blev, const int32_t *__restrict__ nl_start,
                                                  const int32_t *__restrict__ nl_ent, const uint64_t *__restrict__ bkey, const int32_t *__restrict__ bstart,
@@ -1378,7 +1380,6 @@ __global__ void __launch_bounds__(64) k_p2p_tile(int64_t n, const int32_t *__res
                                                  T *__restrict__ bout)
 {
     constexpr int NA = GRAD ? 15 : 6;
-    constexpr int TS = P2P_TS;
     __shared__ T tr[7][TS];          // x y z wx wy wz q of the staged sources
     __shared__ int tix[TS];          // their sorted indices (self exclusion)
     __shared__ T red[64 * NA];       // partial sums of the lanes
@@ -1724,9 +1725,20 @@ static void p2p_launch(lhf_plan *P, int what, T *v, T *s, T *g, T *b, unsigned n
     const int d = P->depth;
     if (P->adaptive) {
         if (P->nleaf == 0) return;
-        hipLaunchKernelGGL((k_p2p_tile<T, GRAD, Q>), dim3((unsigned)P->nleaf), dim3(64), 0, st, n, P->leaves,
-                           P->blev, P->nl_start, P->nl_ent, P->bkey, P->bstart, P->bcount, (const T *)P->xw,
-                           P->sys_a, what, (const T *)P->vfar, P->perm, v, s, g, b);
+        // the source tile: the plan's tuned choice on the v, s path, else the built-in one
+        const int ts = (!GRAD && !Q && P->p2p_ts > 0) ? P->p2p_ts : P2P_TS;
+#define LHF_P2P_TILE(TSV)                                                                                       \
+    hipLaunchKernelGGL((k_p2p_tile<T, GRAD, Q, TSV>), dim3((unsigned)P->nleaf), dim3(64), 0, st, n, P->leaves,     \
+                       P->blev, P->nl_start, P->nl_ent, P->bkey, P->bstart, P->bcount, (const T *)P->xw,           \
+                       P->sys_a, what, (const T *)P->vfar, P->perm, v, s, g, b)
+        if constexpr (!GRAD && !Q) {
+            if (ts == 64) LHF_P2P_TILE(64);
+            else if (ts == 256) LHF_P2P_TILE(256);
+            else LHF_P2P_TILE(P2P_TS);
+        } else {
+            LHF_P2P_TILE(P2P_TS);
+        }
+#undef LHF_P2P_TILE
     } else {
         hipLaunchKernelGGL((k_p2p<T, GRAD, Q>), dim3(nblk), dim3(tpb), 0, st, n, d, P->lev[d].off, P->eleaf,
                            P->ulist, P->bkey, P->bstart, P->bcount, (const T *)P->xs, (const T *)P->ws,
@@ -1981,6 +1993,96 @@ lhf_status execute_impl(lhf_plan *P, const lhf_io *io, hipStream_t st)
 {
     if (P->precision == LHF_FP64) return execute_t<double>(P, io, st);
     return execute_t<float>(P, io, st);
+}
+
+// Run-time kernel shapes measured on the plan's own tree: after one whole evaluation (every
+// level's multipoles in place), each level's quarter-vector M2L is launched once per candidate
+// number of targets per tile, and the adaptive near field once per candidate source tile; the
+// fastest of each is kept in the plan.  The timed launches leave the local expansions and the
+// outputs of scratch buffers inconsistent: the next execute recomputes all of them.
+template <typename T>
+static lhf_status autotune_t(lhf_plan *P, const T *omega, int *ns, int *ts, hipStream_t st)
+{
+    const int64_t n = P->n;
+    T *v = nullptr, *s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    lhf_status rs = LHF_OK;
+    auto fail = [&](hipError_t e, const char *what) {
+        if (rs == LHF_OK) rs = hip_fail(e, what);
+    };
+    hipError_t e = dev_malloc(&v, sizeof(T) * 3 * (size_t)n);
+    if (e == hipSuccess) e = dev_malloc(&s, sizeof(T) * 3 * (size_t)n);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) fail(e, "autotune buffers");
+    if (rs == LHF_OK) {
+        lhf_io io;
+        memset(&io, 0, sizeof(io));
+        io.omega = omega;
+        io.v = v;
+        io.s = s;
+        io.what = 3;
+        rs = execute_t<T>(P, &io, st);
+    }
+    auto timed = [&](const std::function<void()> &launch) -> float {
+        float ms = -1.0f;
+        if (rs != LHF_OK) return ms;
+        hipError_t r = hipEventRecord(e0, st);
+        launch();
+        if (r == hipSuccess) r = hipEventRecord(e1, st);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+        if (r != hipSuccess) fail(r, "autotune timing");
+        return ms;
+    };
+    for (int l = 0; l <= MAXDEPTH; l++) ns[l] = 0;
+    const int maxns = P->use_quarter ? m2l_quarter_max_ns(P->p) : 0;
+    for (int l = 2; l <= P->depth && maxns > 0 && rs == LHF_OK; l++) {
+        if (P->lev[l].nb == 0) continue;
+        m2l_quarter_stage(P, l, st);
+        int best = 0;
+        float tbest = 0;
+        for (int c : {1, 2, 3, 4, 6, 8, 12, 16}) {
+            if (c > maxns) break;
+            P->m2l_ns[l] = c;
+            const float t = timed([&] { m2l_quarter_launch(P, l, st); });
+            if (t >= 0 && (best == 0 || t < tbest)) {
+                best = c;
+                tbest = t;
+            }
+        }
+        P->m2l_ns[l] = ns[l] = best;
+    }
+    *ts = 0;
+    if (P->adaptive && P->nleaf > 0 && rs == LHF_OK) {
+        int best = 0;
+        float tbest = 0;
+        for (int c : {64, 128, 256}) {
+            P->p2p_ts = c;
+            const float t = timed([&] { p2p_launch<T, false, false>(P, 2, v, s, nullptr, nullptr, 0, 0, st); });
+            if (t >= 0 && (best == 0 || t < tbest)) {
+                best = c;
+                tbest = t;
+            }
+        }
+        P->p2p_ts = *ts = best;
+    }
+    if (rs == LHF_OK) {
+        hipError_t r = hipGetLastError();
+        if (r == hipSuccess) r = hipStreamSynchronize(st);
+        if (r != hipSuccess) fail(r, "autotune launches");
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (v) (void)dev_free(v);
+    if (s) (void)dev_free(s);
+    return rs;
+}
+
+lhf_status autotune_impl(lhf_plan *P, const void *omega, int *ns, int *ts, hipStream_t st)
+{
+    if (P->precision == LHF_FP64) return autotune_t<double>(P, (const double *)omega, ns, ts, st);
+    return autotune_t<float>(P, (const float *)omega, ns, ts, st);
 }
 
 }  // namespace lhf

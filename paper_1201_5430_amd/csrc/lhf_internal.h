@@ -147,6 +147,8 @@ struct lhf_plan {
     double *dtab = nullptr;              // its per-direction |t|, 1/|t|, e^{i phi} ([343][4])
     bool use_mmhalf = false;             // batched M2M and L2L in the same layout
     bool use_mmquarter = false;          // batched M2M and L2L, four lanes per part vector (FP64 p = 20-24)
+    int m2l_ns[lhf::MAXDEPTH + 1] = {};  // targets per tile of the quarter-vector M2L per level (0: built-in)
+    int p2p_ts = 0;                      // sources per LDS tile of the adaptive near field (0: built-in)
     void *wmm = nullptr, *wll = nullptr; // their rotation tables (S basis, R basis)
     bool tile2 = false;                  // VALU tile with two schedule rows per batch (FP32 p = 8, 10)
     void *wmfma = nullptr;               // per-class rotation blocks in MFMA A-operand lane order

@@ -892,8 +892,11 @@ static void launch_quarter(const lhf_plan *Pl, int level, hipStream_t st)
 {
     const int64_t soff = Pl->lev[level].off, nb = Pl->lev[level].nb;
     if (nb == 0) return;
-    // as many slots as fit, but no fewer than ~1024 tiles where the level has the boxes
-    const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(qv::nslot<P>(), (nb + 1023) / 1024));
+    // the plan's tuned choice, else as many slots as fit but no fewer than ~1024 tiles where the
+    // level has the boxes
+    const int ns = Pl->m2l_ns[level] > 0
+                       ? std::min(Pl->m2l_ns[level], qv::nslot<P>())
+                       : (int)std::max<int64_t>(1, std::min<int64_t>(qv::nslot<P>(), (nb + 1023) / 1024));
     const int64_t ntiles = (nb + ns - 1) / ns;
     const int64_t per = (ntiles + 7) / 8;
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
@@ -951,6 +954,19 @@ static void mm_quarter_dispatch(const lhf_plan *Pl, int l, hipStream_t st)
 }
 
 }  // namespace
+
+// targets per tile the quarter-vector M2L can take at order p (0: no such kernel)
+int m2l_quarter_max_ns(int p)
+{
+    switch (p) {
+    case 16: return qv::nslot<16>();
+    case 20: return qv::nslot<20>();
+    case 22: return qv::nslot<22>();
+    case 23: return qv::nslot<23>();
+    case 24: return qv::nslot<24>();
+    }
+    return 0;
+}
 
 bool m2l_quarter_supported(int precision, int p)
 {

@@ -27,6 +27,8 @@
 namespace lhf {
 
 lhf_status execute_impl(lhf_plan *P, const lhf_io *io, hipStream_t st);
+lhf_status autotune_impl(lhf_plan *P, const void *omega, int *ns, int *ts, hipStream_t st);
+int m2l_quarter_max_ns(int p);
 bool m2l_tile_supported(int precision, int p);
 void dmap_build(const lhf_plan *Pl, int level, hipStream_t st);
 bool wpad_build(lhf_plan *Pl, hipStream_t st);
@@ -1846,6 +1848,123 @@ lhf_status lhf_profile_end(lhf_plan *P, double *phase_ms, int32_t *n_exec)
     }
     *n_exec = P->prof_used;
     free_profile(P);
+    return LHF_OK;
+}
+
+constexpr int LHF_SHAPE_LEVELS = 9;  // lhf_shapes.m2l_tile: levels 0 .. 8 (the batched M2L kernels' range)
+static_assert(sizeof(((lhf_shapes *)nullptr)->m2l_tile) / sizeof(int32_t) == LHF_SHAPE_LEVELS, "lhf_shapes");
+
+static std::string shapes_key(const lhf_plan *P)
+{
+    std::string arch = "unknown";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch = arch.substr(0, c);
+    }
+    return arch + "/" + (P->precision == LHF_FP64 ? "fp64" : "fp32") + "/p" + std::to_string(P->p) + "/" +
+           (P->adaptive ? "adaptive" : "uniform") + "/d" + std::to_string(P->depth) + "/n" + std::to_string(P->n);
+}
+
+// shapes cache: a JSON array with one object per line
+//   {"key": "gfx950/fp64/p23/adaptive/d8/n4194304", "m2l_tile": [0, 0, 1, 1, 4, 6, 6, 6, 6], "p2p_tile": 128}
+static bool read_shapes(const char *path, const std::string &key, lhf_shapes *out, std::vector<std::string> *lines)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[1024];
+    while (fgets(line, sizeof(line), f)) {
+        char k[256];
+        lhf_shapes sh;
+        int *t = sh.m2l_tile;
+        if (sscanf(line, " {\"key\": \"%255[^\"]\", \"m2l_tile\": [%d, %d, %d, %d, %d, %d, %d, %d, %d], \"p2p_tile\": %d}", k,
+                   &t[0], &t[1], &t[2], &t[3], &t[4], &t[5], &t[6], &t[7], &t[8], &sh.p2p_tile) != 11)
+            continue;
+        std::string ln(line);
+        while (!ln.empty() && (ln.back() == '\n' || ln.back() == ',' || ln.back() == ' ')) ln.pop_back();
+        lines->push_back(ln.substr(ln.find('{')));
+        if (k == key) {
+            *out = sh;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static lhf_status check_shapes(const lhf_plan *P, const lhf_shapes *sh)
+{
+    const int maxns = P->use_quarter ? m2l_quarter_max_ns(P->p) : 0;
+    for (int l = 0; l < LHF_SHAPE_LEVELS; l++)
+        if (sh->m2l_tile[l] < 0 || sh->m2l_tile[l] > std::max(maxns, 0) || (maxns == 0 && sh->m2l_tile[l] != 0))
+            return arg_error("m2l_tile out of range for this plan's M2L kernel");
+    if (sh->p2p_tile != 0 && sh->p2p_tile != 64 && sh->p2p_tile != 128 && sh->p2p_tile != 256)
+        return arg_error("p2p_tile must be 0, 64, 128 or 256");
+    return LHF_OK;
+}
+
+lhf_status lhf_plan_set_shapes(lhf_plan *P, const lhf_shapes *sh)
+{
+    if (!P || !sh) return arg_error("plan and shapes must be non-NULL");
+    lhf_status s = check_shapes(P, sh);
+    if (s != LHF_OK) return s;
+    for (int l = 0; l < LHF_SHAPE_LEVELS; l++) P->m2l_ns[l] = sh->m2l_tile[l];
+    P->p2p_ts = sh->p2p_tile;
+    return LHF_OK;
+}
+
+lhf_status lhf_plan_get_shapes(const lhf_plan *P, lhf_shapes *sh)
+{
+    if (!P || !sh) return arg_error("plan and shapes must be non-NULL");
+    for (int l = 0; l < LHF_SHAPE_LEVELS; l++) sh->m2l_tile[l] = P->m2l_ns[l];
+    sh->p2p_tile = P->p2p_ts;
+    return LHF_OK;
+}
+
+lhf_status lhf_plan_autotune(lhf_plan *P, const void *omega, const char *cache_path, lhf_shapes *out, void *stream)
+{
+    if (!P) return arg_error("plan is NULL");
+    if (!omega) return arg_error("omega is NULL");
+    const std::string key = shapes_key(P);
+    std::vector<std::string> lines;
+    lhf_shapes sh;
+    memset(&sh, 0, sizeof(sh));
+    if (cache_path && cache_path[0] && read_shapes(cache_path, key, &sh, &lines)) {
+        lhf_status s = lhf_plan_set_shapes(P, &sh);
+        if (s != LHF_OK) return s;
+        if (out) *out = sh;
+        return LHF_OK;
+    }
+    P->stream = (hipStream_t)stream;
+    int ns[MAXDEPTH + 1], ts = 0;
+    lhf_status rs = autotune_impl(P, omega, ns, &ts, (hipStream_t)stream);
+    if (rs != LHF_OK) return rs;
+    for (int l = 0; l < LHF_SHAPE_LEVELS; l++) sh.m2l_tile[l] = ns[l];
+    sh.p2p_tile = ts;
+    if (out) *out = sh;
+    if (cache_path && cache_path[0]) {
+        char buf[512];
+        const int *t = sh.m2l_tile;
+        snprintf(buf, sizeof(buf), "{\"key\": \"%s\", \"m2l_tile\": [%d, %d, %d, %d, %d, %d, %d, %d, %d], \"p2p_tile\": %d}",
+                 key.c_str(), t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8], sh.p2p_tile);
+        lines.push_back(buf);
+        const std::string tmp = std::string(cache_path) + ".tmp";
+        FILE *f = fopen(tmp.c_str(), "w");
+        bool ok = f != nullptr;
+        if (ok) {
+            fprintf(f, "[\n");
+            for (size_t i = 0; i < lines.size(); i++) fprintf(f, " %s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+            fprintf(f, "]\n");
+            ok = fclose(f) == 0 && rename(tmp.c_str(), cache_path) == 0;
+        }
+        if (!ok) {
+            set_error(std::string("could not write the shapes cache ") + cache_path);
+            return LHF_ERR_ARG;
+        }
+    }
     return LHF_OK;
 }
 

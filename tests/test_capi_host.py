@@ -160,3 +160,12 @@ def test_filament_entry_points_check_their_arguments():
     assert lib.lhf_filament_create(C.byref(h), C.byref(d), 1, dummy, 5, dummy, None) == -1
     assert lib.lhf_filament_execute(None, dummy, dummy, None) == -1
     assert lib.lhf_filament_destroy(None) == 0
+
+
+def test_shape_entry_points_check_their_arguments():
+    L, lib = _lib()
+    sh = L.Shapes()
+    assert lib.lhf_plan_set_shapes(None, C.byref(sh)) == -1
+    assert lib.lhf_plan_get_shapes(None, C.byref(sh)) == -1
+    assert lib.lhf_plan_autotune(None, None, None, C.byref(sh), None) == -1
+    assert b"NULL" in lib.lhf_last_error()

@@ -354,3 +354,49 @@ def test_quarter_m2m_l2l_match_generic(oracle, p):
     assert st1["mm_kernel"] == "quarter"
     print("  adaptive ring: ", end="")
     _check(v1, s1, v2, s2, l2=1e-13, mx=1e-12)
+
+
+def test_autotuned_shapes(tmp_path):
+    # the run-time shape autotuner on an adaptive ring at FP64 p = 23 (quarter-vector M2L tiles per
+    # level, near-field source tile): valid shapes, the field unchanged to rounding after tuning,
+    # the cache file read back, and out-of-range shapes refused
+    torch = _torch()
+    import paper_1201_5430_amd as L
+    import workloads
+    n = 20000
+    x, w = workloads.vortex_ring(n, 141)
+    a = workloads.core_radius(n)
+    xt = torch.from_numpy(x).to("cuda")
+    wt = torch.from_numpy(w).to("cuda")
+    plan = L.Plan(xt, a, p=23, depth=7, max_per_leaf=32)
+    v0, s0 = plan.execute(wt)
+    v0, s0 = v0.cpu().numpy(), s0.cpu().numpy()
+    cache = str(tmp_path / "shapes.json")
+    sh = plan.autotune(wt, cache_path=cache)
+    print("tuned shapes", sh, flush=True)
+    assert sh["p2p_tile"] in (64, 128, 256)
+    st = plan.stats()
+    for l in range(9):
+        if 2 <= l <= st["depth"] and st["boxes"][l] > 0:
+            assert 1 <= sh["m2l_tile"][l] <= 6
+        else:
+            assert sh["m2l_tile"][l] == 0
+    assert plan.get_shapes() == sh
+    v1, s1 = plan.execute(wt)
+    torch.cuda.synchronize()
+    print("after tuning: ", end="")
+    _check(v1.cpu().numpy(), s1.cpu().numpy(), v0, s0, l2=1e-13, mx=1e-12)
+    # every tile size gives the same field
+    for ts in (64, 256):
+        plan.set_shapes(dict(m2l_tile=[0, 0, 1, 1, 2, 3, 4, 5, 6], p2p_tile=ts))
+        v2, s2 = plan.execute(wt)
+        _check(v2.cpu().numpy(), s2.cpu().numpy(), v0, s0, l2=1e-13, mx=1e-12)
+    # second plan of the same workload: the shapes come from the cache
+    plan2 = L.Plan(xt, a, p=23, depth=7, max_per_leaf=32)
+    assert plan2.autotune(wt, cache_path=cache) == sh
+    with pytest.raises(L.LhfError):
+        plan2.set_shapes(dict(m2l_tile=[0, 0, 7, 0, 0, 0, 0, 0, 0]))
+    with pytest.raises(L.LhfError):
+        plan2.set_shapes(dict(p2p_tile=100))
+    plan.close()
+    plan2.close()
