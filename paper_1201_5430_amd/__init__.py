@@ -22,9 +22,9 @@ LIB_PATH = os.path.join(HERE, "liblhfmm.so")
 FP64, FP32 = 0, 1
 LHF_SINGULAR, LHF_DETERMINISTIC, LHF_OUT_GRAD, LHF_WX_EXPANSIONS = 0x1, 0x2, 0x4, 0x8
 TRANS_RCR, TRANS_DIRECT = 0, 1
-M2L_AUTO, M2L_HALF, M2L_TILE, M2L_TILE1, M2L_MFMA, M2L_GENERIC, M2L_QUARTER = range(7)
+M2L_AUTO, M2L_HALF, M2L_TILE, M2L_TILE1, M2L_MFMA, M2L_GENERIC, M2L_QUARTER, M2L_QMFMA = range(8)
 MM_AUTO, MM_HALF, MM_GENERIC, MM_QUARTER = range(4)
-M2L_NAMES = ("auto", "half", "tile", "tile1", "mfma", "generic", "quarter")
+M2L_NAMES = ("auto", "half", "tile", "tile1", "mfma", "generic", "quarter", "qmfma")
 STATUS = {0: "LHF_OK", 1: "LHF_WARN_CORE_SPLIT", 2: "LHF_WARN_TOL_UNMET", -1: "LHF_ERR_ARG",
           -2: "LHF_ERR_DOMAIN", -3: "LHF_ERR_NONFINITE", -4: "LHF_ERR_WORKSPACE", -5: "LHF_ERR_HIP",
           -6: "LHF_ERR_UNSUPPORTED", -7: "LHF_ERR_STATE"}

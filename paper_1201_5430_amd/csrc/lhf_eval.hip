@@ -35,6 +35,8 @@ void m2l_half_scalar_stage(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_half_scalar_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2l_quarter_stage(const lhf_plan *Pl, int level, hipStream_t st);
 int m2l_quarter_max_ns(int p);
+int m2l_qmfma_max_ns(int p);
+void m2l_qmfma_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2m_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void l2l_half_launch(const lhf_plan *Pl, int level, hipStream_t st);
 void m2m_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st);
@@ -1786,12 +1788,13 @@ static void translations(lhf_plan *P, hipStream_t st, bool scalar, const std::fu
             // (timed with L2L, outside the M2L phase)
             if (sc_half) m2l_half_scalar_stage(P, l, st);
             else if (!P->use_mfma && P->use_half) m2l_half_stage(P, l, st);
-            if (P->use_quarter) m2l_quarter_stage(P, l, st);
+            if (P->use_quarter || P->use_qmfma) m2l_quarter_stage(P, l, st);
             mark(7 + 2 * l);
             if (P->use_mfma) m2l_mfma_launch(P, l, st);
             else if (sc_half) m2l_half_scalar_launch(P, l, st);
             else if (P->use_half) m2l_half_launch(P, l, st);
             else if (P->use_quarter) m2l_quarter_launch(P, l, st);
+            else if (P->use_qmfma) m2l_qmfma_launch(P, l, st);
             else m2l_tile_launch(P, l, st);
             mark(8 + 2 * l);
         } else {
@@ -2036,16 +2039,19 @@ static lhf_status autotune_t(lhf_plan *P, const T *omega, int *ns, int *ts, hipS
         return ms;
     };
     for (int l = 0; l <= MAXDEPTH; l++) ns[l] = 0;
-    const int maxns = P->use_quarter ? m2l_quarter_max_ns(P->p) : 0;
+    const int maxns = P->use_quarter ? m2l_quarter_max_ns(P->p) : P->use_qmfma ? m2l_qmfma_max_ns(P->p) : 0;
     for (int l = 2; l <= P->depth && maxns > 0 && rs == LHF_OK; l++) {
         if (P->lev[l].nb == 0) continue;
         m2l_quarter_stage(P, l, st);
         int best = 0;
         float tbest = 0;
-        for (int c : {1, 2, 3, 4, 6, 8, 12, 16}) {
+        for (int c : {1, 2, 3, 4, 6, 8, 10, 12, 16}) {
             if (c > maxns) break;
             P->m2l_ns[l] = c;
-            const float t = timed([&] { m2l_quarter_launch(P, l, st); });
+            const float t = timed([&] {
+                if (P->use_qmfma) m2l_qmfma_launch(P, l, st);
+                else m2l_quarter_launch(P, l, st);
+            });
             if (t >= 0 && (best == 0 || t < tbest)) {
                 best = c;
                 tbest = t;

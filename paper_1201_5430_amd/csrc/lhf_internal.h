@@ -142,6 +142,7 @@ struct lhf_plan {
     bool use_mfma = false;               // matrix-core M2L (same schedule and box maps)
     bool use_half = false;               // VALU M2L with each vector split over two lanes (large p)
     bool use_quarter = false;            // VALU M2L with each vector split over four lanes (FP64, high p)
+    bool use_qmfma = false;              // matrix-core M2L in the same residue layout (FP64, high p)
     void *whalf = nullptr;               // its rotation tables
     void *mh = nullptr;                  // its sources, one level at a time, in its lane layout
     double *dtab = nullptr;              // its per-direction |t|, 1/|t|, e^{i phi} ([343][4])

@@ -106,30 +106,6 @@ __device__ inline int acc_pos(int k)
     return (8 * pot + 4 * part + (m & 3)) * Sh::ARS + hoff(n) + (m >> 2);
 }
 
-// sum_{i<N} W[i] x[i], W read as 16-byte vectors
-__device__ __attribute__((always_inline)) inline double dotw(const double *W, const double *x, const int N)
-{
-    double a = 0;
-#pragma unroll
-    for (int q = 0; q < (N + E - 1) / E; q++) {
-        const double2 w = ((const double2 *)W)[q];
-        a += w.x * x[q * E];
-        if (q * E + 1 < N) a += w.y * x[q * E + 1];
-    }
-    return a;
-}
-
-// acc[i] += a W[i], i < N
-__device__ __attribute__((always_inline)) inline void axpyw(const double *W, const double a, double *acc, const int N)
-{
-#pragma unroll
-    for (int q = 0; q < (N + E - 1) / E; q++) {
-        const double2 w = ((const double2 *)W)[q];
-        acc[q * E] += a * w.x;
-        if (q * E + 1 < N) acc[q * E + 1] += a * w.y;
-    }
-}
-
 }  // namespace qv
 
 template <int P>
@@ -352,14 +328,48 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
                     const double *Wn = Wf + qv::woff(n);
                     constexpr int SM = (P - 1) / 4 + 1;
                     double g[4][SM];
+                    // the table rows (output group kk, row jj) in pairs, each pair's LDS reads issued
+                    // before the previous pair is computed (software pipelining: two pairs of rows in
+                    // registers, so the LDS latency overlaps the dot products)
+                    {
+                        constexpr int GR = 2;  // rows per group
+                        constexpr int RLMAX = qv::RL(P - 1) / 2;
+                        const int R = 4 * S(n), H = qv::RL(n) / 2, NG = (R + GR - 1) / GR;
+                        double2 buf[2][GR][RLMAX];
+                        auto ld = [&](int gg, double2 (&b)[GR][RLMAX]) __attribute__((always_inline)) {
 #pragma unroll
-                    for (int kk = 0; kk < 4; kk++)
+                            for (int rr = 0; rr < GR; rr++) {
+                                const int row = gg * GR + rr;
+                                if (row < R) {
 #pragma unroll
-                        for (int jj = 0; jj < S(n); jj++) {
-                            g[kk][jj] = qv::dotw(Wn + (kk * S(n) + jj) * qv::RL(n), &v[hoff(n)], S(n));
-                            // bound the table reads in flight (they do not depend on v)
-                            if (jj % 2 == 1 || jj == S(n) - 1) __builtin_amdgcn_sched_barrier(0);
+                                    for (int h = 0; h < RLMAX; h++)
+                                        if (h < H) b[rr][h] = ((const double2 *)(Wn + row * qv::RL(n)))[h];
+                                }
+                            }
+                        };
+                        ld(0, buf[0]);
+#pragma unroll
+                        for (int gg = 0; gg < (4 * S(P - 1) + GR - 1) / GR; gg++) {
+                            if (gg >= NG) break;
+                            if (gg + 1 < NG) ld(gg + 1, buf[(gg + 1) & 1]);
+#pragma unroll
+                            for (int rr = 0; rr < GR; rr++) {
+                                const int row = gg * GR + rr;
+                                if (row < R) {
+                                    const int kk = row / S(n), jj = row % S(n);
+                                    double a = 0;
+#pragma unroll
+                                    for (int h = 0; h < RLMAX; h++) {
+                                        if (h >= H) break;
+                                        a += buf[gg & 1][rr][h].x * v[hoff(n) + 2 * h];
+                                        if (2 * h + 1 < S(n)) a += buf[gg & 1][rr][h].y * v[hoff(n) + 2 * h + 1];
+                                    }
+                                    g[kk][jj] = a;
+                                }
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
                         }
+                    }
 #pragma unroll
                     for (int jj = 0; jj < S(n); jj++) {
                         const double a = g[0][jj] + dpp_f<DPP_XOR1>(g[1][jj]);
@@ -426,15 +436,47 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
                     for (int kk = 0; kk < 4; kk++)
 #pragma unroll
                         for (int jj = 0; jj < S(n); jj++) g[kk][jj] = 0.0;
+                    // the rows one at a time (input slot jj outer, output group kk inner), each row's LDS
+                    // reads issued before the previous row is accumulated (software pipelining)
+                    {
+                        constexpr int GR = 1;  // rows per group
+                        constexpr int RLMAX = qv::RL(P - 1) / 2;
+                        const int R = 4 * S(n), H = qv::RL(n) / 2, NG = (R + GR - 1) / GR;
+                        double2 buf[2][GR][RLMAX];
+                        auto ld = [&](int gg, double2 (&b)[GR][RLMAX]) __attribute__((always_inline)) {
 #pragma unroll
-                    for (int jj = 0; jj < S(n); jj++) {
-                        // m = 0 (q = 0, j = 0, Re part) is not doubled by D^-1
-                        const double xj = v[hoff(n) + jj] * ((jj == 0 && q == 0 && !part) ? 1.0 : fin);
+                            for (int rr = 0; rr < GR; rr++) {
+                                const int row = gg * GR + rr;
+                                if (row < R) {
+                                    const int jj = row / 4, kk = row % 4;
+                                    const double *wr = Wp + (q ^ kk) * WQS + qv::woff(n) + (kk * S(n) + jj) * qv::RL(n);
 #pragma unroll
-                        for (int kk = 0; kk < 4; kk++) {
-                            qv::axpyw(Wp + (q ^ kk) * WQS + qv::woff(n) + (kk * S(n) + jj) * qv::RL(n), xj, g[kk],
-                                      S(n));
-                            if (kk % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+                                    for (int h = 0; h < RLMAX; h++)
+                                        if (h < H) b[rr][h] = ((const double2 *)wr)[h];
+                                }
+                            }
+                        };
+                        ld(0, buf[0]);
+#pragma unroll
+                        for (int gg = 0; gg < (4 * S(P - 1) + GR - 1) / GR; gg++) {
+                            if (gg >= NG) break;
+                            if (gg + 1 < NG) ld(gg + 1, buf[(gg + 1) & 1]);
+#pragma unroll
+                            for (int rr = 0; rr < GR; rr++) {
+                                const int row = gg * GR + rr;
+                                if (row < R) {
+                                    const int jj = row / 4, kk = row % 4;
+                                    // m = 0 (q = 0, j = 0, Re part) is not doubled by D^-1
+                                    const double xj = v[hoff(n) + jj] * ((jj == 0 && q == 0 && !part) ? 1.0 : fin);
+#pragma unroll
+                                    for (int h = 0; h < RLMAX; h++) {
+                                        if (h >= H) break;
+                                        g[kk][2 * h] += xj * buf[gg & 1][rr][h].x;
+                                        if (2 * h + 1 < S(n)) g[kk][2 * h + 1] += xj * buf[gg & 1][rr][h].y;
+                                    }
+                                }
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
                         }
                     }
 #pragma unroll
@@ -482,6 +524,399 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
         const int sl = idx / (2 * P2), r = idx % (2 * P2);
         const int box = slot_box[sl];
         if (box >= 0) Lc[(size_t)box * 2 * P2 + r] = acc[sl * SSTA + qv::acc_pos<P>(r)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The same M2L with the rotations about y on the matrix cores (v_mfma_f64_16x16x4f64), the
+// coefficient vectors kept in registers in the instruction's operand layout.
+//
+// A wavefront holds eight translations of one polar-angle class, both potentials: the 16 MFMA
+// columns j = 2 t + pot (t: translation, 0..7).  Lane l = 16 k + j holds, for its column, the
+// entries m = 4 jj + k of every order n and of both parts (Re, Im) -- slot hoff(n) + jj, the
+// residue layout of the quarter-vector kernel with both parts in one lane.  This is exactly how
+// the instruction wants its operands: B[k][j] comes from lane j + 16 k, and D rows 4 r + k of
+// column j land in lane j + 16 k, register r.  So the rotation of order n, part p is, per block b
+// of 16 output rows,
+//   D_b = sum_s A_{b,s} B_s,  A_{b,s}[i][kk] = W_p[16 b + i][4 s + kk],  B_s[kk][j] = slot (n, s),
+// and D_b's register r is the lane's output slot 4 b + r: no lane exchange at all.  W_p is the
+// class's forward S-basis block of order n (the Im block embedded in (n+1) x (n+1) with a zero row
+// and column m = 0), staged in LDS; lane l reads A[l % 16][l / 16].  The back-rotation reads the
+// same table transposed through the diagonal similarity W_back = D W_fwd^T D^-1 (scalings of the
+// inputs and outputs).  z-rotations act on (Re, Im) inside the lane; the coaxial shift and the
+// conversion act on the lane's column m as in the quarter-vector kernel, the other potential of
+// the conversion coming from lane ^ 1 (one DPP move).  Four wavefronts per workgroup, one
+// workgroup per compute unit: the 156-double vector per lane takes the register file of one
+// wavefront per SIMD (VGPRs and AGPRs).
+// ---------------------------------------------------------------------------
+namespace qm {
+constexpr int NTHREADS = 256;
+constexpr int NV = 189;
+constexpr int MAXCLS = 64;
+__host__ __device__ constexpr int rsz(int P) { return P * (2 * P * P + 1) / 3; }  // one rotation set
+template <int P>
+constexpr int nslot()
+{
+    const int fixed = (int)sizeof(double) * rsz(P) + (int)sizeof(int16_t) * (MAXCLS + 1) + 64;
+    const int per = (int)sizeof(double) * 2 * P * P + (int)sizeof(int16_t) * (NV + MAXCLS) + 4 * (int)sizeof(int);
+    const int n = (qv::LDS_MAX - fixed) / per;
+    return n > 16 ? 16 : n;
+}
+template <int P>
+constexpr size_t tile_bytes()
+{
+    constexpr int NS = nslot<P>();
+    return sizeof(double) * ((size_t)rsz(P) + (size_t)NS * 2 * P * P) + sizeof(int) * 4 * NS +
+           sizeof(int16_t) * ((MAXCLS + 1) + MAXCLS * NS + NV * NS);
+}
+typedef double v4d __attribute__((ext_vector_type(4)));
+}  // namespace qm
+
+template <int P>
+__global__ void __launch_bounds__(qm::NTHREADS, 1) k_m2l_qmfma(int level, int64_t soff, int64_t nb, int ns,
+                                                               const uint64_t *__restrict__ bkey,
+                                                               const int32_t *__restrict__ dmap,
+                                                               const double *__restrict__ Mq,
+                                                               double *__restrict__ Lc,
+                                                               const double *__restrict__ rot, M2LSched sch,
+                                                               const int16_t *__restrict__ cls_theta,
+                                                               const double *__restrict__ dtab)
+{
+    using Sh = qv::Shape<P>;
+    using qv::hoff;
+    using qv::S;
+    using qm::v4d;
+    constexpr int P2 = Sh::P2, NQ = Sh::NQ, NQP = Sh::NQP, RS = qm::rsz(P);
+    constexpr int NSLOT = qm::nslot<P>(), NT = qm::NTHREADS, MAXCLS = qm::MAXCLS;
+    extern __shared__ char smem[];
+    double *Wl = (double *)smem;                       // [RS] the class's forward S-basis blocks
+    double *acc = Wl + RS;                             // [NSLOT][2 P^2] targets, packed (pot, n, part, m)
+    int *slot_xyz = (int *)(acc + NSLOT * 2 * P2);     // [NSLOT] packed target coordinates, -1: no box
+    int *slot_box = slot_xyz + NSLOT;
+    int *slot_sys = slot_box + NSLOT;
+    int *slot_c = slot_sys + NSLOT;
+    int16_t *cst = (int16_t *)(slot_c + NSLOT);        // [ncls + 1] class starts in ent
+    int16_t *kcnt = cst + (MAXCLS + 1);                // [ncls][NSLOT]
+    int16_t *ent = kcnt + MAXCLS * NSLOT;              // [<= NV * NSLOT] (dir << 4) | slot, by class
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t ntiles = (nb + ns - 1) / ns;
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t tile = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (tile >= ntiles) return;
+    const int ncls = sch.ncls;
+    const int side = 1 << level;
+
+    if (tid < NSLOT) {
+        int box = -1, xyz = -1, sys = 0, c = 0;
+        const int64_t b = tile * ns + tid;
+        if (tid < ns && b < nb) {
+            box = (int)(soff + b);
+            const uint64_t key = bkey[box];
+            uint32_t ix = 0, iy = 0, iz = 0;
+            for (int bb = 0; bb < level; bb++) {
+                ix |= (uint32_t)((key >> (3 * bb)) & 1u) << bb;
+                iy |= (uint32_t)((key >> (3 * bb + 1)) & 1u) << bb;
+                iz |= (uint32_t)((key >> (3 * bb + 2)) & 1u) << bb;
+            }
+            xyz = (int)(ix | (iy << 10) | (iz << 20));
+            sys = (int)(key >> (3 * level));
+            c = (int)(key & 7u);
+        }
+        slot_box[tid] = box;
+        slot_xyz[tid] = xyz;
+        slot_sys[tid] = sys;
+        slot_c[tid] = c;
+    }
+    __syncthreads();
+    auto source_of = [&](int dir, int sl) -> int {
+        const int xyz = slot_xyz[sl];
+        const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
+                  sz = (xyz >> 20) - (dir / 49 - 3);
+        const bool inb = xyz >= 0 && sx >= 0 && sy >= 0 && sz >= 0 && sx < side && sy < side && sz < side;
+        return inb ? dmap[(((size_t)slot_sys[sl] * side + sz) * side + sy) * side + sx] : -1;
+    };
+    for (int ks = tid; ks < ncls * NSLOT; ks += NT) {
+        const int kk = ks / NSLOT, sl = ks % NSLOT;
+        int cnt = 0;
+        if (slot_box[sl] >= 0)
+            for (int r = sch.row_start[kk]; r < sch.row_start[kk + 1]; r++) {
+                const int dir = sch.rows[r * 8 + slot_c[sl]];
+                if (dir >= 0 && source_of(dir, sl) >= 0) cnt++;
+            }
+        kcnt[ks] = (int16_t)cnt;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int o = 0;
+        for (int kk = 0; kk < ncls; kk++) {
+            cst[kk] = (int16_t)o;
+            for (int sl = 0; sl < NSLOT; sl++) o += kcnt[kk * NSLOT + sl];
+        }
+        cst[ncls] = (int16_t)o;
+    }
+    __syncthreads();
+    for (int ks = tid; ks < ncls * NSLOT; ks += NT) {
+        const int kk = ks / NSLOT, sl = ks % NSLOT;
+        int o = cst[kk];
+        for (int s2 = 0; s2 < sl; s2++) o += kcnt[kk * NSLOT + s2];
+        if (slot_box[sl] >= 0)
+            for (int r = sch.row_start[kk]; r < sch.row_start[kk + 1]; r++) {
+                const int dir = sch.rows[r * 8 + slot_c[sl]];
+                if (dir >= 0 && source_of(dir, sl) >= 0) ent[o++] = (int16_t)((dir << 4) | sl);
+            }
+    }
+    // the targets' local expansions into their slots (packed as in Lc)
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += NT) {
+        const int sl = idx / (2 * P2);
+        const int box = slot_box[sl];
+        acc[idx] = box >= 0 ? Lc[(size_t)box * 2 * P2 + idx % (2 * P2)] : 0.0;
+    }
+    __syncthreads();
+
+    const int k = lane >> 4, col = lane & 15, tt = col >> 1, pot = col & 1;
+
+    struct Job {
+        int slot, dir, src;
+    };
+    // translation (wave, tt) of class kk: the class's entries read as an 8 x Q matrix column by
+    // column (Q = ceil(count / 8)); branch-free, every load at a valid address
+    auto setup = [&](int kk, int r0) -> Job {
+        const bool kin = kk < ncls;
+        const int kc = kin ? kk : 0;
+        const int e0 = cst[kc], cnt = kin ? cst[kc + 1] - e0 : 0;
+        const int Q = (cnt + 7) >> 3;
+        const int cc = (r0 >> 3) + wave, e = tt * Q + cc;
+        const bool ok0 = cc < Q && e < cnt;
+        const int code = ent[ok0 ? e0 + e : 0];
+        const int dir = ok0 ? code >> 4 : 0, slot = code & 15;
+        const int xyz = slot_xyz[slot < NSLOT ? slot : 0];
+        const int sx = (xyz & 1023) - (dir % 7 - 3), sy = ((xyz >> 10) & 1023) - ((dir / 7) % 7 - 3),
+                  sz = (xyz >> 20) - (dir / 49 - 3);
+        const bool inb = ok0 && xyz >= 0 && sx >= 0 && sy >= 0 && sz >= 0 && sx < side && sy < side && sz < side;
+        const size_t di = inb ? (((size_t)slot_sys[slot] * side + sz) * side + sy) * side + sx : 0;
+        const int src = dmap[di];
+        const bool ok = inb && src >= 0;
+        return Job{ok ? slot : -1, ok ? dir : 0, ok ? src : -1};
+    };
+    auto nonempty = [&](int kk) {
+        while (kk < ncls && cst[kk + 1] == cst[kk]) kk++;
+        return kk;
+    };
+    auto advance = [&](int &kk, int &r0) {
+        r0 += 8 * (NT / 64);
+        if (kk < ncls && r0 >= 8 * ((cst[kk + 1] - cst[kk] + 7) >> 3)) {
+            kk = nonempty(kk + 1);
+            r0 = 0;
+        }
+    };
+
+    // the y rotation of order n, part p (vv: that part's entries), on the matrix cores.  BACK: the
+    // transposed table with the D scalings (inputs by D^-1, outputs by D)
+    const double sg = (k & 1) ? -1.0 : 1.0;  // (-1)^m on this lane's entries
+    auto rotate_part = [&](double (&vv)[NQ], const int p, const int n, const bool back, const int ai, const int ak)
+                           __attribute__((always_inline)) {
+        constexpr int NB = (P + 15) / 16;
+        const int nbk = (n + 1 + 15) / 16, nst = (n + 1 + 3) / 4;
+        v4d d[NB];
+#pragma unroll
+        for (int b = 0; b < NB; b++) d[b] = v4d{0.0, 0.0, 0.0, 0.0};
+        const double *blk = Wl + rot_block_off(n) + (p ? (n + 1) * (n + 1) : 0);
+        const int ld = p ? n : n + 1;  // row length of the stored block
+#pragma unroll
+        for (int s = 0; s < (P + 3) / 4; s++) {
+            if (s >= nst) break;
+            // B: this lane's slot (n, s) (m = 4 s + k), scaled by D^-1 on the way back
+            double bval = vv[hoff(n) + s];
+            if (back) bval *= (p ? sg : ((s == 0 && k == 0) ? 1.0 : 2.0 * sg));
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                if (b >= nbk) break;
+                // A[ai][ak]: forward W[16 b + ai][4 s + ak], back W[4 s + ak][16 b + ai]; outside the
+                // block (or the Im block's row and column m = 0) zero, read at a valid address
+                const int mo = 16 * b + ai, mi = 4 * s + ak;
+                const int r = back ? mi : mo, c = back ? mo : mi;
+                const bool ok = r <= n && c <= n && (p == 0 || (r >= 1 && c >= 1));
+                const int at = ok ? (p ? (r - 1) * ld + (c - 1) : r * ld + c) : 0;
+                const double araw = blk[at];
+                const double a = ok ? araw : 0.0;
+                d[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bval, d[b], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < S(n); jj++) {
+            double o = d[jj / 4][jj % 4];
+            if (back) o *= (p ? sg : ((jj == 0 && k == 0) ? 1.0 : 0.5 * sg));
+            vv[hoff(n) + jj] = o;
+        }
+    };
+    auto rotate_y = [&](double (&vre)[NQ], double (&vim)[NQ], const bool back) __attribute__((always_inline)) {
+#pragma unroll
+        for (int n = 0; n < P; n++) {
+            // the lane's A entry, opaque per order: the compiler would otherwise precompute the LDS
+            // offsets of every MFMA of the translation once, outside the batch loop, and keep them
+            int ai = lane & 15, ak = lane >> 4;
+            asm volatile("" : "+v"(ai), "+v"(ak));
+            rotate_part(vre, 0, n, back, ai, ak);
+            rotate_part(vim, 1, n, back, ai, ak);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    int kc = nonempty(0), r0 = 0;
+    int k1 = kc, r1 = 0;
+    advance(k1, r1);
+    Job cur = setup(kc, r0), nxt = setup(k1, r1);
+    int staged = -1;
+    while (kc < ncls) {
+        if (kc != staged) {
+            __syncthreads();
+            const double *srcw = rot + ((size_t)cls_theta[kc] * ROT_NKIND + ROT_S_FWD) * RS;
+#pragma unroll 8
+            for (int i = tid; i < RS; i += NT) Wl[i] = srcw[i];
+            __syncthreads();
+            staged = kc;
+        }
+        const Job j = cur;
+        const bool act = j.src >= 0;
+        int k2 = k1, r2 = r1;
+        advance(k2, r2);
+        const Job nn = setup(k2, r2);
+        if (__ballot(act) != 0ull) {
+            double vre[NQ], vim[NQ];
+            // the source's entries of this lane's potential, both parts (quarter layout of k_mquarter)
+            {
+                const double2 *spr =
+                    (const double2 *)(Mq + ((size_t)(act ? j.src - soff : 0) * 16 + 8 * pot + 0 + k) * NQP);
+                const double2 *spi =
+                    (const double2 *)(Mq + ((size_t)(act ? j.src - soff : 0) * 16 + 8 * pot + 4 + k) * NQP);
+#pragma unroll
+                for (int i = 0; i < NQP / 2; i++) {
+                    const double2 x = spr[i], y = spi[i];
+                    vre[2 * i] = act ? x.x : 0.0;
+                    vim[2 * i] = act ? y.x : 0.0;
+                    if (2 * i + 1 < NQ) {
+                        vre[2 * i + 1] = act ? x.y : 0.0;
+                        vim[2 * i + 1] = act ? y.y : 0.0;
+                    }
+                }
+            }
+            const double2 d0 = ((const double2 *)dtab)[2 * j.dir], d1 = ((const double2 *)dtab)[2 * j.dir + 1];
+            const double tau = d0.x, itau = d0.y;
+            const double cph = d1.x, sph = d1.y;
+            const double c2 = cph * cph - sph * sph, s2 = 2.0 * cph * sph;
+            const double c3 = c2 * cph - s2 * sph, s3 = s2 * cph + c2 * sph;
+            const double c4 = c2 * c2 - s2 * s2, s4 = 2.0 * c2 * s2;
+            const double cq = k == 0 ? 1.0 : k == 1 ? cph : k == 2 ? c2 : c3;
+            const double sq = k == 0 ? 0.0 : k == 1 ? sph : k == 2 ? s2 : s3;
+            // 1. rotate about z by +phi: Re' = re c - im s, Im' = im c + re s (m = 4 jj + k)
+            {
+                double cm = cq, sm = sq;
+#pragma unroll
+                for (int jj = 0; jj < S(P - 1); jj++) {
+#pragma unroll
+                    for (int n = 4 * jj; n < P; n++) {
+                        const double re = vre[hoff(n) + jj], im = vim[hoff(n) + jj];
+                        vre[hoff(n) + jj] = re * cm - im * sm;
+                        vim[hoff(n) + jj] = im * cm + re * sm;
+                    }
+                    const double a = cm * c4 - sm * s4, b = sm * c4 + cm * s4;
+                    cm = a;
+                    sm = b;
+                }
+            }
+            // 2. rotation about y (S basis)
+            rotate_y(vre, vim, false);
+            // 3+4. per column m = 4c + k and part: coaxial (S|R) shift with chi to order P, then the
+            //      R-conversion (eq. rcr1, scaled): phi~ = phi + i tau m/n chi, chi~_n = chi_n - tau/(n+1) chi_{n+1}
+            {
+                const double wphi = pot ? 0.0 : 1.0, wchi = pot ? 1.0 : 0.0;
+                const double itau4 = (itau * itau) * (itau * itau);
+                double pc = 1.0;  // tau^-(4c)
+                auto coax = [&](double (&vv)[NQ], double (&out)[P + 1], const int c) __attribute__((always_inline)) {
+                    const int n0 = 4 * c;
+                    // the column through an opaque copy: otherwise the compiler starts the sums of every
+                    // column while the rotation produces their entries and runs out of registers
+#pragma unroll
+                    for (int n2 = n0; n2 < P; n2++) asm volatile("" : "+v"(vv[hoff(n2) + c]));
+                    double sc = pc;
+#pragma unroll
+                    for (int n2 = n0; n2 < P; n2++) {
+                        vv[hoff(n2) + c] *= sc;
+                        sc *= itau;
+                    }
+                    double so = pc * itau;
+#pragma unroll
+                    for (int n = n0; n <= P; n++) {
+                        double a = 0;
+#pragma unroll
+                        for (int n2 = n0; n2 < P; n2++) a += dfact(n + n2) * vv[hoff(n2) + c];
+                        out[n] = a * so;
+                        so *= itau;
+                    }
+                };
+                auto convert = [&](double (&vv)[NQ], const double (&out)[P + 1], const double (&oth)[P + 1],
+                                   const double sconv, const int c) __attribute__((always_inline)) {
+                    const int n0 = 4 * c;
+                    const double mval = (double)(4 * c + k);
+#pragma unroll
+                    for (int n = n0; n < P; n++) {
+                        // phi-Re <-> chi-Im, phi-Im <-> chi-Re: the other part of the other potential
+                        const double other = dpp_f<DPP_XOR1>(oth[n]);
+                        const double fphi = (n > 0) ? tau * mval * (1.0 / (double)n) * sconv * wphi : 0.0;
+                        const double fchi = -tau * (1.0 / (double)(n + 1)) * wchi;
+                        const double val = out[n] + fphi * other + fchi * out[n + 1];
+                        vv[hoff(n) + c] = (n - n0 < k) ? 0.0 : val;
+                    }
+                };
+#pragma unroll
+                for (int c = 0; c < S(P - 1); c++) {
+                    double outr[P + 1], outi[P + 1];
+                    coax(vre, outr, c);
+                    coax(vim, outi, c);
+                    pc *= itau4;
+                    convert(vre, outr, outi, -1.0, c);
+                    convert(vim, outi, outr, 1.0, c);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            // 5. back-rotation about y (R basis, through the transposed forward table)
+            rotate_y(vre, vim, true);
+            // 6. back-rotation about z (-phi) and accumulation into the target slot
+            {
+                double *ap = acc + (size_t)(act ? j.slot : 0) * 2 * P2 + pot * P2;
+                double cm = cq, sm = sq;
+#pragma unroll
+                for (int jj = 0; jj < S(P - 1); jj++) {
+                    const int m = 4 * jj + k;
+#pragma unroll
+                    for (int n = 4 * jj; n < P; n++) {
+                        const double re = vre[hoff(n) + jj], im = vim[hoff(n) + jj];
+                        const double vr = re * cm + im * sm, vi = im * cm - re * sm;
+                        const bool okr = act && m <= n, oki = act && m <= n && m > 0;
+                        // no branch around the adds (inactive lanes add 0 at a valid address)
+                        atomicAdd(ap + n * n + (okr ? m : 0), okr ? vr : 0.0);
+                        atomicAdd(ap + n * n + n + (oki ? m : 0), oki ? vi : 0.0);
+                    }
+                    const double a = cm * c4 - sm * s4, b = sm * c4 + cm * s4;
+                    cm = a;
+                    sm = b;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+        cur = nxt;
+        nxt = nn;
+        kc = k1;
+        r0 = r1;
+        k1 = k2;
+        r1 = r2;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < NSLOT * 2 * P2; idx += NT) {
+        const int sl = idx / (2 * P2);
+        const int box = slot_box[sl];
+        if (box >= 0) Lc[(size_t)box * 2 * P2 + idx % (2 * P2)] = acc[idx];
     }
 }
 
@@ -687,14 +1122,47 @@ __global__ void __launch_bounds__(256, 1) k_mm_quarter(int64_t poff, int64_t npa
                     asm volatile("" : "+v"(Wn));
                     constexpr int SM = (P - 1) / 4 + 1;
                     double g[4][SM];
+                    // the table rows in pairs, the next pair's loads issued before this pair's dot
+                    // products (software pipelining, as in the M2L above)
+                    {
+                        constexpr int GR = 2;
+                        constexpr int RLMAX = qv::RL(P - 1) / 2;
+                        const int R = 4 * S(n), H = qv::RL(n) / 2, NG = (R + GR - 1) / GR;
+                        double2 buf[2][GR][RLMAX];
+                        auto ld = [&](int gg, double2 (&b)[GR][RLMAX]) __attribute__((always_inline)) {
 #pragma unroll
-                    for (int kk = 0; kk < 4; kk++)
+                            for (int rr = 0; rr < GR; rr++) {
+                                const int row = gg * GR + rr;
+                                if (row < R) {
 #pragma unroll
-                        for (int jj = 0; jj < S(n); jj++) {
-                            g[kk][jj] = qv::dotw(Wn + (kk * S(n) + jj) * qv::RL(n), &v[hoff(n)], S(n));
-                            // bound the table reads in flight (they do not depend on v)
-                            if (jj % 2 == 1 || jj == S(n) - 1) __builtin_amdgcn_sched_barrier(0);
+                                    for (int h = 0; h < RLMAX; h++)
+                                        if (h < H) b[rr][h] = ((const double2 *)(Wn + row * qv::RL(n)))[h];
+                                }
+                            }
+                        };
+                        ld(0, buf[0]);
+#pragma unroll
+                        for (int gg = 0; gg < (4 * S(P - 1) + GR - 1) / GR; gg++) {
+                            if (gg >= NG) break;
+                            if (gg + 1 < NG) ld(gg + 1, buf[(gg + 1) & 1]);
+#pragma unroll
+                            for (int rr = 0; rr < GR; rr++) {
+                                const int row = gg * GR + rr;
+                                if (row < R) {
+                                    const int kk = row / S(n), jj = row % S(n);
+                                    double a = 0;
+#pragma unroll
+                                    for (int h = 0; h < RLMAX; h++) {
+                                        if (h >= H) break;
+                                        a += buf[gg & 1][rr][h].x * v[hoff(n) + 2 * h];
+                                        if (2 * h + 1 < S(n)) a += buf[gg & 1][rr][h].y * v[hoff(n) + 2 * h + 1];
+                                    }
+                                    g[kk][jj] = a;
+                                }
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
                         }
+                    }
 #pragma unroll
                     for (int jj = 0; jj < S(n); jj++) {
                         const double a = g[0][jj] + dpp_f<DPP_XOR1>(g[1][jj]);
@@ -888,6 +1356,38 @@ static void stage_quarter(const lhf_plan *Pl, int level, hipStream_t st)
 }
 
 template <int P>
+static bool qmfma_build_t(lhf_plan *Pl, hipStream_t st)
+{
+    constexpr size_t shm = qm::tile_bytes<P>();
+    static_assert(shm <= (size_t)qv::LDS_MAX, "tile exceeds the LDS");
+    static_assert(qm::nslot<P>() >= 1, "no target slot fits beside the table");
+    if (Pl->sched_ncls > qm::MAXCLS) return false;
+    if (dev_malloc(&Pl->dtab, sizeof(double) * 4 * 343) != hipSuccess) return false;
+    k_dirtab_q<<<dim3(2), dim3(256), 0, st>>>(Pl->dtab);
+    int64_t nbmax = 0;
+    for (int l = 2; l <= Pl->depth; l++) nbmax = std::max(nbmax, Pl->lev[l].nb);
+    if (nbmax > 0 && dev_malloc(&Pl->mh, sizeof(double) * 16 * qv::Shape<P>::NQP * nbmax) != hipSuccess) return false;
+    return hipFuncSetAttribute((const void *)k_m2l_qmfma<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)shm) == hipSuccess;
+}
+
+template <int P>
+static void launch_qmfma(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    const int64_t soff = Pl->lev[level].off, nb = Pl->lev[level].nb;
+    if (nb == 0) return;
+    const int ns = Pl->m2l_ns[level] > 0
+                       ? std::min(Pl->m2l_ns[level], qm::nslot<P>())
+                       : (int)std::max<int64_t>(1, std::min<int64_t>(qm::nslot<P>(), (nb + 1023) / 1024));
+    const int64_t ntiles = (nb + ns - 1) / ns;
+    const int64_t per = (ntiles + 7) / 8;
+    M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
+    k_m2l_qmfma<P><<<dim3((unsigned)(per * 8)), dim3(qm::NTHREADS), qm::tile_bytes<P>(), st>>>(
+        level, soff, nb, ns, Pl->bkey, Pl->dmap[level], (const double *)Pl->mh, (double *)Pl->Lc,
+        (const double *)Pl->rot, sch, Pl->sched_cls_theta, Pl->dtab);
+}
+
+template <int P>
 static void launch_quarter(const lhf_plan *Pl, int level, hipStream_t st)
 {
     const int64_t soff = Pl->lev[level].off, nb = Pl->lev[level].nb;
@@ -1004,6 +1504,44 @@ void m2l_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st)
     case 22: launch_quarter<22>(Pl, level, st); break;
     case 23: launch_quarter<23>(Pl, level, st); break;
     case 24: launch_quarter<24>(Pl, level, st); break;
+    }
+}
+
+// the matrix-core M2L in the quarter residue layout (FP64 p = 20, 22, 23, 24)
+bool m2l_qmfma_supported(int precision, int p)
+{
+    return precision == LHF_FP64 && (p == 20 || p == 22 || p == 23 || p == 24);
+}
+
+int m2l_qmfma_max_ns(int p)
+{
+    switch (p) {
+    case 20: return qm::nslot<20>();
+    case 22: return qm::nslot<22>();
+    case 23: return qm::nslot<23>();
+    case 24: return qm::nslot<24>();
+    }
+    return 0;
+}
+
+bool qmfma_build(lhf_plan *Pl, hipStream_t st)
+{
+    switch (Pl->p) {
+    case 20: return qmfma_build_t<20>(Pl, st);
+    case 22: return qmfma_build_t<22>(Pl, st);
+    case 23: return qmfma_build_t<23>(Pl, st);
+    case 24: return qmfma_build_t<24>(Pl, st);
+    }
+    return false;
+}
+
+void m2l_qmfma_launch(const lhf_plan *Pl, int level, hipStream_t st)
+{
+    switch (Pl->p) {
+    case 20: launch_qmfma<20>(Pl, level, st); break;
+    case 22: launch_qmfma<22>(Pl, level, st); break;
+    case 23: launch_qmfma<23>(Pl, level, st); break;
+    case 24: launch_qmfma<24>(Pl, level, st); break;
     }
 }
 

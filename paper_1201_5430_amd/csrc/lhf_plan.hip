@@ -44,6 +44,9 @@ bool m2l_quarter_supported(int precision, int p);
 bool wquarter_build(lhf_plan *Pl, hipStream_t st);
 bool mm_half_supported(int precision, int p);
 bool mm_quarter_supported(int precision, int p);
+bool m2l_qmfma_supported(int precision, int p);
+int m2l_qmfma_max_ns(int p);
+bool qmfma_build(lhf_plan *Pl, hipStream_t st);
 bool mmquarter_build(lhf_plan *Pl, hipStream_t st);
 
 // ---- device memory cache -----------------------------------------------------------------
@@ -1052,6 +1055,11 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
             set_error("half-vector M2L set-up failed");
             return LHF_ERR_HIP;
         }
+        P->use_qmfma = P->m2l_kind == LHF_M2L_QMFMA;
+        if (P->use_qmfma && !qmfma_build(P, st)) {
+            set_error("matrix-core quarter-layout M2L set-up failed");
+            return LHF_ERR_HIP;
+        }
         P->use_quarter = P->m2l_kind == LHF_M2L_QUARTER;
         if (P->use_quarter && !wquarter_build(P, st)) {
             set_error("quarter-vector M2L set-up failed");
@@ -1418,6 +1426,7 @@ static bool m2l_available(int k, int precision, int p)
     switch (k) {
     case LHF_M2L_HALF: return m2l_half_supported(precision, p);
     case LHF_M2L_QUARTER: return m2l_quarter_supported(precision, p);
+    case LHF_M2L_QMFMA: return m2l_qmfma_supported(precision, p);
     case LHF_M2L_TILE:
     case LHF_M2L_TILE1: return m2l_tile_supported(precision, p);
     case LHF_M2L_MFMA: return m2l_mfma_supported(precision, p);
@@ -1432,6 +1441,7 @@ bool kernel_deterministic(int precision, int p, int k)
     switch (k) {
     case LHF_M2L_HALF: return m2l_half_owned(precision, p);
     case LHF_M2L_QUARTER: return false;  // LDS atomics
+    case LHF_M2L_QMFMA: return false;    // LDS atomics
     case LHF_M2L_TILE:
     case LHF_M2L_TILE1: return m2l_tile_owned(precision, p);
     default: return true;  // matrix-core (one parent per wavefront, register sums), generic (per box)
@@ -1440,8 +1450,8 @@ bool kernel_deterministic(int precision, int p, int k)
 
 static const char *m2l_name(int k)
 {
-    static const char *nm[] = {"AUTO", "HALF", "TILE", "TILE1", "MFMA", "GENERIC", "QUARTER"};
-    return (k >= 0 && k <= 6) ? nm[k] : "?";
+    static const char *nm[] = {"AUTO", "HALF", "TILE", "TILE1", "MFMA", "GENERIC", "QUARTER", "QMFMA"};
+    return (k >= 0 && k <= 7) ? nm[k] : "?";
 }
 
 // Resolve the descriptor's kernel requests (host only, before any launch).  AUTO takes the
@@ -1531,7 +1541,7 @@ lhf_status plan_new(lhf_plan **out, const lhf_desc *d, int nsys, const int64_t *
         return LHF_ERR_UNSUPPORTED;
     }
     if (d->translation != LHF_TRANS_RCR) return arg_error("unknown translation scheme");
-    if (d->m2l_kernel < LHF_M2L_AUTO || d->m2l_kernel > LHF_M2L_QUARTER) return arg_error("unknown m2l_kernel");
+    if (d->m2l_kernel < LHF_M2L_AUTO || d->m2l_kernel > LHF_M2L_QMFMA) return arg_error("unknown m2l_kernel");
     if (d->mm_kernel < LHF_MM_AUTO || d->mm_kernel > LHF_MM_QUARTER) return arg_error("unknown mm_kernel");
     if (d->depth < 2 || d->depth > MAXDEPTH) return arg_error("depth out of range (2..10)");
     if (d->max_per_leaf < 0) return arg_error("max_per_leaf must be >= 0");
@@ -1897,7 +1907,7 @@ static bool read_shapes(const char *path, const std::string &key, lhf_shapes *ou
 
 static lhf_status check_shapes(const lhf_plan *P, const lhf_shapes *sh)
 {
-    const int maxns = P->use_quarter ? m2l_quarter_max_ns(P->p) : 0;
+    const int maxns = P->use_quarter ? m2l_quarter_max_ns(P->p) : P->use_qmfma ? m2l_qmfma_max_ns(P->p) : 0;
     for (int l = 0; l < LHF_SHAPE_LEVELS; l++)
         if (sh->m2l_tile[l] < 0 || sh->m2l_tile[l] > std::max(maxns, 0) || (maxns == 0 && sh->m2l_tile[l] != 0))
             return arg_error("m2l_tile out of range for this plan's M2L kernel");

@@ -400,3 +400,32 @@ def test_autotuned_shapes(tmp_path):
         plan2.set_shapes(dict(p2p_tile=100))
     plan.close()
     plan2.close()
+
+
+@pytest.mark.parametrize("p", [20, 23, 24])
+def test_qmfma_m2l(oracle, p):
+    # the matrix-core M2L with the vectors in registers (residue layout, both parts per lane): against
+    # the oracle on sampled leaves and against the quarter-vector VALU kernel on every element, on a
+    # uniform tree and on the adaptive ring
+    import paper_1201_5430_amd as L
+    rng = np.random.default_rng(220 + p)
+    n = 30000
+    x = rng.uniform(0, 1, (n, 3))
+    w = rng.normal(size=(n, 3))
+    a = 0.5 * n ** (-1 / 3)
+    samp = rng.choice(n, 40, replace=False)
+    vr, sr, _ = oracle.fmm(x, w, a, p, 5, sample=samp)
+    m = ~np.isnan(vr[:, 0])
+    vq, sq, stq = _gpu_fmm(x, w, a, p, 5, m2l_kernel=L.M2L_QMFMA)
+    vh, sh, sth = _gpu_fmm(x, w, a, p, 5, m2l_kernel=L.M2L_QUARTER)
+    assert stq["m2l_kernel"] == "qmfma" and sth["m2l_kernel"] == "quarter"
+    print(f"matrix-core residue-layout M2L p={p}: ", end="")
+    _check(vq[m], sq[m], vr[m], sr[m])
+    _check(vq, sq, vh, sh, l2=1e-13, mx=1e-12)
+    import workloads
+    xr, wr = workloads.vortex_ring(8000, 221)
+    ar = workloads.core_radius(8000)
+    vq, sq, _ = _gpu_fmm(xr, wr, ar, p, 7, max_per_leaf=16, m2l_kernel=L.M2L_QMFMA)
+    vh, sh, _ = _gpu_fmm(xr, wr, ar, p, 7, max_per_leaf=16, m2l_kernel=L.M2L_QUARTER)
+    print(f"  adaptive ring: ", end="")
+    _check(vq, sq, vh, sh, l2=1e-13, mx=1e-12)
