@@ -111,7 +111,9 @@ def phase_roofline(st, ph, p, prec, n):
 # the dominant kernel of the headline per M2L kernel family the plan chose
 KERNEL_LABEL = {
     "half": "k_m2l_half<{t},{p}> (batched M2L, half-vector lanes, rotation tables from L2), one launch per level",
-    "quarter": "k_m2l_quarter<{p}> (batched M2L, quarter-vector lanes, rotation tables from L2), one launch per level",
+    "quarter": "k_m2l_quarter<{p}> (batched M2L, quarter-vector lanes, class rotation tables staged in LDS, "
+               "pipelined table reads), one launch per level",
+    "qmfma": "k_m2l_qmfma<{p}> (batched M2L on the FP64 matrix cores, vectors in registers), one launch per level",
     "tile": "k_m2l_tile<{t},{p},...> (batched M2L, LDS-tiled target boxes), one launch per level",
 }
 

@@ -105,7 +105,8 @@ typedef enum { LHF_FP64 = 0, LHF_FP32 = 1 } lhf_precision;
                                   also 16) */
 #define LHF_M2L_GENERIC 5      /* one wavefront per target box over its stored V-list: any p */
 #define LHF_M2L_QUARTER 6      /* batched VALU, each coefficient vector split over four lanes by m mod 4
-                                  (two wavefronts per SIMD at high orders): FP64 p = 16, 20, 22, 23, 24 */
+                                  (two wavefronts per SIMD at high orders): FP64 p = 8, 10, 12, 16, 20,
+                                  22, 23, 24 */
 #define LHF_M2L_QMFMA 7        /* batched matrix-core (16x16x4 FP64 MFMA) kernel with the coefficient vectors
                                   in registers in the instruction's operand layout (residue m mod 4 per
                                   lane, both parts, eight translations per wavefront): FP64 p = 20, 22,

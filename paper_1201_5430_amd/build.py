@@ -27,11 +27,13 @@ EXTRA = {"lhf_m2l_half.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
 
 
 def _stale(obj: str, src: str) -> bool:
-    """True if obj is missing or older than its source or any header of csrc/."""
+    """True if obj is missing or older than its source or any header of csrc/ or include/."""
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
+    inc = os.path.join(os.path.dirname(HERE), "include")
     deps = [src] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith((".h", ".inc"))]
+    deps += [os.path.join(inc, h) for h in os.listdir(inc) if h.endswith(".h")]
     return any(os.path.getmtime(d) > t for d in deps)
 
 

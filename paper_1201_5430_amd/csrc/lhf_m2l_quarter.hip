@@ -1459,6 +1459,9 @@ static void mm_quarter_dispatch(const lhf_plan *Pl, int l, hipStream_t st)
 int m2l_quarter_max_ns(int p)
 {
     switch (p) {
+    case 8: return qv::nslot<8>();
+    case 10: return qv::nslot<10>();
+    case 12: return qv::nslot<12>();
     case 16: return qv::nslot<16>();
     case 20: return qv::nslot<20>();
     case 22: return qv::nslot<22>();
@@ -1470,12 +1473,15 @@ int m2l_quarter_max_ns(int p)
 
 bool m2l_quarter_supported(int precision, int p)
 {
-    return precision == LHF_FP64 && (p == 16 || p == 20 || p == 22 || p == 23 || p == 24);
+    return precision == LHF_FP64 && (p == 8 || p == 10 || p == 12 || p == 16 || p == 20 || p == 22 || p == 23 || p == 24);
 }
 
 bool wquarter_build(lhf_plan *Pl, hipStream_t st)
 {
     switch (Pl->p) {
+    case 8: return wquarter_build_t<8>(Pl, st);
+    case 10: return wquarter_build_t<10>(Pl, st);
+    case 12: return wquarter_build_t<12>(Pl, st);
     case 16: return wquarter_build_t<16>(Pl, st);
     case 20: return wquarter_build_t<20>(Pl, st);
     case 22: return wquarter_build_t<22>(Pl, st);
@@ -1488,6 +1494,9 @@ bool wquarter_build(lhf_plan *Pl, hipStream_t st)
 void m2l_quarter_stage(const lhf_plan *Pl, int level, hipStream_t st)
 {
     switch (Pl->p) {
+    case 8: stage_quarter<8>(Pl, level, st); break;
+    case 10: stage_quarter<10>(Pl, level, st); break;
+    case 12: stage_quarter<12>(Pl, level, st); break;
     case 16: stage_quarter<16>(Pl, level, st); break;
     case 20: stage_quarter<20>(Pl, level, st); break;
     case 22: stage_quarter<22>(Pl, level, st); break;
@@ -1499,6 +1508,9 @@ void m2l_quarter_stage(const lhf_plan *Pl, int level, hipStream_t st)
 void m2l_quarter_launch(const lhf_plan *Pl, int level, hipStream_t st)
 {
     switch (Pl->p) {
+    case 8: launch_quarter<8>(Pl, level, st); break;
+    case 10: launch_quarter<10>(Pl, level, st); break;
+    case 12: launch_quarter<12>(Pl, level, st); break;
     case 16: launch_quarter<16>(Pl, level, st); break;
     case 20: launch_quarter<20>(Pl, level, st); break;
     case 22: launch_quarter<22>(Pl, level, st); break;

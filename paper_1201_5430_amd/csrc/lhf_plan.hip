@@ -1455,7 +1455,7 @@ static const char *m2l_name(int k)
 }
 
 // Resolve the descriptor's kernel requests (host only, before any launch).  AUTO takes the
-// fastest kernel measured for (precision, p): the quarter-vector kernel at FP64 p >= 20, the
+// fastest kernel measured for (precision, p): the quarter-vector kernel at FP64 p >= 16, the
 // half-vector kernel where it is instantiated, else the one-lane tile, else the generic per-box
 // kernel; with LHF_DETERMINISTIC only kernels
 // without atomics qualify (then the matrix-core kernel, which is deterministic, precedes the
@@ -1468,9 +1468,11 @@ lhf_status resolve_kernels(const lhf_desc *d, int p, bool dmap_ok, int *m2l, int
     if (k == LHF_M2L_AUTO) {
         k = LHF_M2L_GENERIC;
         if (dmap_ok) {
-            // FP64 p >= 20: the quarter-vector kernel (two wavefronts per SIMD where the half-vector
-            // kernel holds one; 4M ring, p = 23: 630 against 1091 ms of M2L); equal at p = 16
-            const bool quarter_first = prec == LHF_FP64 && p >= 20;
+            // FP64 p >= 16: the quarter-vector kernel (two wavefronts per SIMD where the half-vector
+            // kernel holds one, tiles of consecutive targets, pipelined table reads; M2L per execute
+            // on the 4M ring: 119 against 245 ms at p = 16, 440 against 1091 ms at p = 23); at p <= 12
+            // the half-vector kernel is faster (2^20 cube, p = 12: 48 against 71 ms)
+            const bool quarter_first = prec == LHF_FP64 && p >= 16;
             const int order[] = {quarter_first ? LHF_M2L_QUARTER : LHF_M2L_HALF, LHF_M2L_HALF, LHF_M2L_TILE,
                                  LHF_M2L_MFMA};
             for (int c : order) {

@@ -118,7 +118,7 @@ def test_descriptor_options_are_checked_on_the_host():
         (dict(p=12, depth=9, m2l_kernel=L.M2L_HALF), -6, "depth <= 8"),
         (dict(p=12, depth=3, m2l_kernel=L.M2L_HALF, flags=L.LHF_DETERMINISTIC), -6, "not deterministic"),
         (dict(p=16, depth=3, m2l_kernel=L.M2L_HALF, flags=L.LHF_DETERMINISTIC), -6, "not deterministic"),
-        (dict(p=12, depth=3, m2l_kernel=L.M2L_QUARTER), -6, "no instantiation"),
+        (dict(p=14, depth=3, m2l_kernel=L.M2L_QUARTER), -6, "no instantiation"),
         (dict(p=16, depth=3, m2l_kernel=L.M2L_QUARTER, precision=L.FP32), -6, "no instantiation"),
         (dict(p=23, depth=3, m2l_kernel=L.M2L_QUARTER, flags=L.LHF_DETERMINISTIC), -6, "not deterministic"),
     ]

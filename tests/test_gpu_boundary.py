@@ -181,6 +181,10 @@ def test_kernel_requests():
     xt = _dev(rng.uniform(0, 1, (2000, 3)), 0)
     st = L.Plan(xt, 0.02, p=12, depth=3).stats()
     assert st["m2l_kernel"] == "half" and st["mm_kernel"] == "half" and not st["deterministic"]
+    st = L.Plan(xt, 0.02, p=16, depth=3).stats()
+    assert st["m2l_kernel"] == "quarter" and st["mm_kernel"] == "half"
+    st = L.Plan(xt, 0.02, p=23, depth=3).stats()
+    assert st["m2l_kernel"] == "quarter" and st["mm_kernel"] == "quarter"
     st = L.Plan(xt, 0.02, p=6, depth=3).stats()
     assert st["m2l_kernel"] == "tile" and st["mm_kernel"] == "generic" and st["deterministic"]
     st = L.Plan(xt, 0.02, p=7, depth=3).stats()

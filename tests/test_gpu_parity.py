@@ -257,7 +257,7 @@ def test_half_vector_m2l(oracle, prec, p):
         _check32(vh, sh, v1, s1)
 
 
-@pytest.mark.parametrize("p", [16, 20, 22, 23, 24])
+@pytest.mark.parametrize("p", [8, 12, 16, 20, 22, 23, 24])
 def test_quarter_vector_m2l(oracle, p):
     # the FP64 M2L kernel with each part vector split over four lanes by m mod 4: against the
     # oracle on sampled leaves and against the half-vector kernel on every element, on a uniform
