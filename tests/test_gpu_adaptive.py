@@ -176,3 +176,37 @@ def test_ring4m_p16_full_size_sampled(oracle):
     assert st["n_leaves"] == ost["n_leaf"] and st["max_level"] == ost["max_level"]
     check(v64[m], s64[m], vr[m], sr[m], l2=1e-11, mx=1e-10, label=f"ring4m FP64 p=16 ({m.sum()} elements):")
     check32(v32[m], s32[m], vr[m], sr[m], l2=5e-6, mx=2e-5, label=f"ring4m FP32 p=16 ({m.sum()} elements):")
+
+
+def test_ring4m_p23_full_size_sampled(oracle):
+    # the headline configuration as the benchmark times it: the full clustered workload (4,194,304
+    # elements, <= 64 per leaf, deepest level 8) in FP64 at p = 23 (the quarter-vector M2L and
+    # M2M/L2L), with the run-time shapes the autotuner picks for it, checked on the leaves of 24
+    # seeded elements against the oracle's adaptive FMM at p = 23.  Bar 1e-11 / 1e-10 as for the
+    # other full-size FP64 comparisons (the sampled targets sum over every level of the tree)
+    torch = _torch()
+    import paper_1201_5430_amd as LH
+    cfg = workloads.CONFIGS["ring4m_fp32"]
+    x, w = workloads.vortex_ring(cfg["n"], cfg["seed"])
+    a = workloads.core_radius(cfg["n"])
+    mx, p = cfg["max_per_leaf"], 23
+    xt = torch.from_numpy(x).to(device="cuda", dtype=torch.float64)
+    wt = torch.from_numpy(w).to(device="cuda", dtype=torch.float64)
+    plan = LH.Plan(xt, a, p=p, depth=8, precision=LH.FP64, max_per_leaf=mx)
+    shapes = plan.autotune(wt)
+    plan.close()
+    plan = LH.Plan(xt, a, p=p, depth=8, precision=LH.FP64, max_per_leaf=mx)
+    plan.set_shapes(shapes)
+    v, s = plan.execute(wt)
+    torch.cuda.synchronize()
+    st = plan.stats()
+    plan.close()
+    assert st["m2l_kernel"] == "quarter"
+    v, s = v.cpu().numpy(), s.cpu().numpy()
+    samp = workloads.sample_targets(cfg["n"], 24, seed=7)
+    vr, sr, ost = oracle.fmm_adaptive(x, w, a, p, mx, 8, sample=samp)
+    m = ~np.isnan(vr[:, 0])
+    assert m.sum() >= 24
+    assert st["n_leaves"] == ost["n_leaf"] and st["max_level"] == ost["max_level"]
+    check(v[m], s[m], vr[m], sr[m], l2=1e-11, mx=1e-10,
+          label=f"ring4m FP64 p=23, tuned shapes {shapes} ({m.sum()} elements):")
