@@ -144,6 +144,10 @@ struct lhf_plan {
     bool use_quarter = false;            // VALU M2L with each vector split over four lanes (FP64, high p)
     bool use_qmfma = false;              // matrix-core M2L in the same residue layout (FP64, high p)
     void *whalf = nullptr;               // its rotation tables
+    int16_t *qsched = nullptr;           // quarter-vector M2L: [3][ncls] class order, staged table, mirrored
+    std::vector<double> h_theta;         // host copies: polar angle of every rotation-table class
+    std::vector<int16_t> h_cls_theta;    //   and the table class of every schedule class
+    std::vector<int16_t> h_qsched;       //   and of qsched (kept until the plan is destroyed)
     void *mh = nullptr;                  // its sources, one level at a time, in its lane layout
     double *dtab = nullptr;              // its per-direction |t|, 1/|t|, e^{i phi} ([343][4])
     bool use_mmhalf = false;             // batched M2M and L2L in the same layout

@@ -78,7 +78,7 @@ template <int P>
 constexpr int nslot()
 {
     using Sh = Shape<P>;
-    const int fixed = (int)sizeof(double) * 8 * Sh::WQS + (int)sizeof(int16_t) * (MAXCLS + 1) + 64;
+    const int fixed = (int)sizeof(double) * 8 * Sh::WQS + (int)sizeof(int16_t) * (2 * MAXCLS + 1) + 64;
     const int per = (int)sizeof(double) * Sh::SSTA + (int)sizeof(int16_t) * (NV + MAXCLS) + 4 * (int)sizeof(int);
     const int n = (LDS_MAX - fixed) / per;
     return n > 16 ? 16 : n;
@@ -90,7 +90,7 @@ constexpr size_t tile_bytes()
     using Sh = Shape<P>;
     constexpr int NS = nslot<P>();
     return sizeof(double) * (size_t)8 * Sh::WQS + sizeof(double) * (size_t)NS * Sh::SSTA + sizeof(int) * 4 * NS +
-           sizeof(int16_t) * ((MAXCLS + 1) + MAXCLS * NS + NV * NS);
+           sizeof(int16_t) * ((2 * MAXCLS + 1) + MAXCLS * NS + NV * NS);
 }
 
 // packed (phi, chi) expansion index k -> position in a target slot (lane layout)
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
                                                                 const double *__restrict__ Mq,
                                                                 double *__restrict__ Lc,
                                                                 const double *__restrict__ wq, int64_t wstride,
-                                                                M2LSched sch, const int16_t *__restrict__ cls_theta,
+                                                                M2LSched sch, const int16_t *__restrict__ qsched,
                                                                 const double *__restrict__ dtab)
 {
     using Sh = qv::Shape<P>;
@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
     int16_t *cst = (int16_t *)(slot_c + NSLOT);        // [ncls + 1] class starts in ent
     int16_t *kcnt = cst + (MAXCLS + 1);                // [ncls][NSLOT] entries per (class, slot)
     int16_t *ent = kcnt + MAXCLS * NSLOT;              // [<= NV * NSLOT] (dir << 4) | slot, by class
+    int16_t *coff = ent + qv::NV * NSLOT;                // [ncls] wavefront of each class's first column
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // XCD-aware tile order: consecutive tiles stay on one XCD (shared L2)
@@ -177,10 +178,10 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
     // per (class, slot): the V-list offsets of the slot's child position in that class whose
     // source box exists; counted, scanned, then listed class by class
     for (int ks = tid; ks < ncls * NSLOT; ks += NT) {
-        const int kk = ks / NSLOT, sl = ks % NSLOT;
+        const int kk = ks / NSLOT, sl = ks % NSLOT, ko = qsched[kk];
         int cnt = 0;
         if (slot_box[sl] >= 0)
-            for (int r = sch.row_start[kk]; r < sch.row_start[kk + 1]; r++) {
+            for (int r = sch.row_start[ko]; r < sch.row_start[ko + 1]; r++) {
                 const int dir = sch.rows[r * 8 + slot_c[sl]];
                 if (dir >= 0 && source_of(dir, sl) >= 0) cnt++;
             }
@@ -194,14 +195,22 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
             for (int sl = 0; sl < NSLOT; sl++) o += kcnt[kk * NSLOT + sl];
         }
         cst[ncls] = (int16_t)o;
+        // the columns of consecutive classes continue round the eight wavefronts: classes on one staged
+        // table (a polar angle and its mirror) run without a barrier between them, and their last,
+        // partly filled rounds then land on different wavefronts
+        int w8 = 0;
+        for (int kk = 0; kk < ncls; kk++) {
+            coff[kk] = (int16_t)w8;
+            w8 = (w8 + ((cst[kk + 1] - cst[kk] + 3) >> 2)) & 7;
+        }
     }
     __syncthreads();
     for (int ks = tid; ks < ncls * NSLOT; ks += NT) {
-        const int kk = ks / NSLOT, sl = ks % NSLOT;
+        const int kk = ks / NSLOT, sl = ks % NSLOT, ko = qsched[kk];
         int o = cst[kk];
         for (int s2 = 0; s2 < sl; s2++) o += kcnt[kk * NSLOT + s2];
         if (slot_box[sl] >= 0)
-            for (int r = sch.row_start[kk]; r < sch.row_start[kk + 1]; r++) {
+            for (int r = sch.row_start[ko]; r < sch.row_start[ko + 1]; r++) {
                 const int dir = sch.rows[r * 8 + slot_c[sl]];
                 if (dir >= 0 && source_of(dir, sl) >= 0) ent[o++] = (int16_t)((dir << 4) | sl);
             }
@@ -232,7 +241,7 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
         const int kc = kin ? k : 0;
         const int e0 = cst[kc], cnt = kin ? cst[kc + 1] - e0 : 0;
         const int Q = (cnt + 3) >> 2;
-        const int col = (r0 >> 2) + wave, e = t * Q + col;
+        const int col = (r0 >> 2) + ((wave - coff[kc]) & 7), e = t * Q + col;
         const bool ok0 = col < Q && e < cnt;
         const int code = ent[ok0 ? e0 + e : 0];
         const int dir = ok0 ? code >> 4 : 0, slot = code & 15;
@@ -275,15 +284,17 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
     constexpr int N16 = 8 * WQS * 8 / 16;
     int staged = -1;
     while (k < ncls) {
-        if (k != staged) {
+        const int tb = qsched[ncls + k];  // a mirrored class reuses the staged table
+        if (tb != staged) {
             __syncthreads();
-            const uint4 *src4 = (const uint4 *)(wq + (size_t)cls_theta[k] * wstride);
+            const uint4 *src4 = (const uint4 *)(wq + (size_t)tb * wstride);
             uint4 *dst4 = (uint4 *)Wl;
 #pragma unroll 4
             for (int i = tid; i < N16; i += NT) dst4[i] = src4[i];
             __syncthreads();
-            staged = k;
+            staged = tb;
         }
+        const bool mir = qsched[2 * ncls + k] != 0;
         const Job j = cur;
         const bool act = j.src >= 0;
         int k2 = k1, r2 = r1;
@@ -301,10 +312,16 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
             const double c4 = c2 * c2 - s2 * s2, s4 = 2.0 * c2 * s2;
             const double cq = q == 0 ? 1.0 : q == 1 ? cph : q == 2 ? c2 : c3;
             const double sq = q == 0 ? 0.0 : q == 1 ? sph : q == 2 ? s2 : s3;
+            // a mirrored class (theta' = pi - theta) runs on the staged table of theta: per order n the
+            // S-basis rotation block is W(theta') = c_n D W(theta) D with D = diag((-1)^m) and c_n = (-1)^n
+            // on the Re block, -(-1)^n on the Im block; D acts as the sign (-1)^q of this lane's entries
+            const double sgq = (mir && (q & 1)) ? -1.0 : 1.0;
+            const double g0 = mir ? sgq * (part ? -1.0 : 1.0) : 1.0, g1 = mir ? -g0 : g0;  // c_n (-1)^q, n even / odd
+            const double itm = mir ? -itau : itau;
             // 1. rotate about z by +phi: Re' = re c - im s, Im' = im c + re s (m = 4j + q)
             {
                 const double sgn = part ? 1.0 : -1.0;
-                double cm = cq, sm = sq;
+                double cm = cq * sgq, sm = sq * sgq;
 #pragma unroll
                 for (int jj = 0; jj < S(P - 1); jj++) {
                     const double sz = sm * sgn;
@@ -393,11 +410,11 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
                     const double mval = (double)(4 * c + q);
                     double out[P + 1];
                     {
-                        double s = pc;
+                        double s = pc * g0;
 #pragma unroll
                         for (int n2 = n0; n2 < P; n2++) {
                             v[hoff(n2) + c] *= s;
-                            s *= itau;
+                            s *= itm;
                         }
                         double so = pc * itau;
 #pragma unroll
@@ -427,6 +444,7 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
             {
                 const double sg = (q & 1) ? -1.0 : 1.0;  // (-1)^m on this lane
                 const double fin = part ? sg : 2.0 * sg, fout = part ? sg : 0.5 * sg;
+                const double fin0 = fin * g0, fin1 = fin * g1;  // with the mirrored class's input signs
                 const double *Wp = Wl + part * 4 * WQS;
 #pragma unroll
                 for (int n = 0; n < P; n++) {
@@ -467,7 +485,7 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
                                 if (row < R) {
                                     const int jj = row / 4, kk = row % 4;
                                     // m = 0 (q = 0, j = 0, Re part) is not doubled by D^-1
-                                    const double xj = v[hoff(n) + jj] * ((jj == 0 && q == 0 && !part) ? 1.0 : fin);
+                                    const double xj = v[hoff(n) + jj] * ((jj == 0 && q == 0 && !part) ? ((n & 1) ? g1 : g0) : ((n & 1) ? fin1 : fin0));
 #pragma unroll
                                     for (int h = 0; h < RLMAX; h++) {
                                         if (h >= H) break;
@@ -492,7 +510,7 @@ __global__ void __launch_bounds__(qv::NTHREADS, 1) k_m2l_quarter(int level, int6
             {
                 double *ap = acc + (size_t)(act ? j.slot : 0) * SSTA + (lane & 15) * ARS;
                 const double sgn = part ? -1.0 : 1.0;  // Re' = re c + im s, Im' = im c - re s
-                double cm = cq, sm = sq;
+                double cm = cq * sgq, sm = sq * sgq;
 #pragma unroll
                 for (int jj = 0; jj < S(P - 1); jj++) {
                     const double sz = sm * sgn;
@@ -1337,6 +1355,40 @@ static bool wquarter_build_t(lhf_plan *Pl, hipStream_t st)
     if (dev_malloc(&Pl->whalf, sizeof(double) * stride * Pl->n_theta) != hipSuccess) return false;
     k_wquarter<P><<<dim3((unsigned)Pl->n_theta), dim3(256), 0, st>>>((const double *)Pl->rot, (double *)Pl->whalf,
                                                                      stride);
+    // class order of the kernel: each polar angle theta > pi/2 right after its mirror pi - theta, whose
+    // table it reuses (one staging for both); [order | staged table | mirrored]
+    {
+        const int nc = Pl->sched_ncls;
+        std::vector<int16_t> &qs = Pl->h_qsched;
+        qs.assign(3 * (size_t)nc, 0);
+        std::vector<char> used(nc, 0);
+        auto th = [&](int c) { return Pl->h_theta[Pl->h_cls_theta[c]]; };
+        const double pi = 3.14159265358979323846;
+        int o = 0;
+        for (int a = 0; a < nc; a++) {
+            if (used[a]) continue;
+            int b = -1;
+            for (int c = 0; c < nc && b < 0; c++)
+                if (c != a && !used[c] && std::fabs(th(a) + th(c) - pi) < 1e-9) b = c;
+            int can = a, mir = b;
+            if (b >= 0 && th(a) > 0.5 * pi) std::swap(can, mir);
+            used[a] = 1;
+            if (b >= 0) used[b] = 1;
+            qs[o] = (int16_t)can;
+            qs[nc + o] = Pl->h_cls_theta[can];
+            qs[2 * nc + o] = 0;
+            o++;
+            if (b >= 0) {
+                qs[o] = (int16_t)mir;
+                qs[nc + o] = Pl->h_cls_theta[can];
+                qs[2 * nc + o] = 1;
+                o++;
+            }
+        }
+        if (dev_malloc(&Pl->qsched, sizeof(int16_t) * qs.size()) != hipSuccess) return false;
+        if (hipMemcpyAsync(Pl->qsched, qs.data(), sizeof(int16_t) * qs.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+            return false;
+    }
     if (dev_malloc(&Pl->dtab, sizeof(double) * 4 * 343) != hipSuccess) return false;
     k_dirtab_q<<<dim3(2), dim3(256), 0, st>>>(Pl->dtab);
     int64_t nbmax = 0;
@@ -1402,7 +1454,7 @@ static void launch_quarter(const lhf_plan *Pl, int level, hipStream_t st)
     M2LSched sch{Pl->sched_cls_start, Pl->sched_c, Pl->sched_dir, Pl->sched_ncls, Pl->sched_row_start, Pl->sched_rows};
     k_m2l_quarter<P><<<dim3((unsigned)(per * 8)), dim3(qv::NTHREADS), qv::tile_bytes<P>(), st>>>(
         level, soff, nb, ns, Pl->bkey, Pl->dmap[level], (const double *)Pl->mh, (double *)Pl->Lc,
-        (const double *)Pl->whalf, 8 * (int64_t)qv::Shape<P>::WQS, sch, Pl->sched_cls_theta, Pl->dtab);
+        (const double *)Pl->whalf, 8 * (int64_t)qv::Shape<P>::WQS, sch, Pl->qsched, Pl->dtab);
 }
 
 

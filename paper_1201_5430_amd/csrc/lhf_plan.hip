@@ -962,6 +962,7 @@ static lhf_status build_schedule(lhf_plan *P, const std::vector<int16_t> &cls, i
     }
     start.push_back((int16_t)ec.size());
     P->sched_ncls = (int)cth.size();
+    P->h_cls_theta = cth;
     // the same entries as rows of 8 indexed by child position (holes = -1)
     std::vector<int16_t> rstart, rows;
     for (int k = 0; k < ntheta; k++) {
@@ -997,6 +998,7 @@ static lhf_status build_tables(lhf_plan *P, hipStream_t st)
     std::vector<double> theta;
     theta_classes(cls, theta);
     P->n_theta = (int)theta.size();
+    P->h_theta = theta;
     const int p = P->p;
     const size_t RS = rot_set_size(p);
     LHF_HIP(dev_malloc(&P->rot, sizeof(T) * RS * ROT_NKIND * theta.size()));
@@ -1095,7 +1097,7 @@ static void free_plan(lhf_plan *P)
     for (int l = 0; l <= MAXDEPTH; l++)
         if (P->dmap[l]) (void)dev_free(P->dmap[l]);
     void *sb[] = {P->sched_cls_start, P->sched_c, P->sched_dir, P->sched_cls_theta, P->wpad, P->sched_row_start,
-                  P->sched_rows, P->wmfma, P->whalf, P->mh, P->dtab, P->wmm, P->wll};
+                  P->sched_rows, P->wmfma, P->whalf, P->mh, P->dtab, P->wmm, P->wll, P->qsched};
     for (void *b : sb)
         if (b) (void)dev_free(b);
     delete P;
