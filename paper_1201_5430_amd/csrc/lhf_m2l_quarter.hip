@@ -19,8 +19,10 @@
 // Only the forward (S-basis) rotation tables are staged (one (part, residue) table per lane
 // role); the back-rotation uses W_back = D W_fwd^T D^-1 (D = diag(1, -1/2, 1/2, ..) on the Re
 // block, diag((-1)^m) on the Im block, as in the half-vector kernel), reading rows of the
-// table of residue q ^ k for output group k.  A tile is half a sibling group (four targets) and
-// eight wavefronts share it: one workgroup per compute unit with two wavefronts per SIMD.
+// table of residue q ^ k for output group k.  A polar angle pi - theta runs on the staged table
+// of theta with signs (see the kernel).  A tile is up to nslot() consecutive target boxes of the
+// level and eight wavefronts share it: one workgroup per compute unit with two wavefronts per
+// SIMD; the columns of consecutive classes continue round the wavefronts.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
