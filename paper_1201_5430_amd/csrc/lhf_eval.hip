@@ -1117,45 +1117,52 @@ __global__ void __launch_bounds__(WAVE) k_m2p(int p, const int32_t *__restrict__
 template <typename T>
 __device__ inline void kernel_fg(T r2, T a, int smooth, T &f, T &g)
 {
+    // 1/a and its powers are loop-invariant (hoisted out of the pair loops): the pair costs
+    // multiplications by them, not divisions; 1/r from one reciprocal square root
     if (!smooth) {
-        T ir = (T)1 / sqrt(r2);
-        T ir2 = ir * ir;
-        f = ir2 * ir;
-        g = (T)-3 * f * ir2;
-        return;
-    }
-    const T c = (T)0.79788456080286535588;  // sqrt(2/pi)
-    const T ia2 = (T)1 / (a * a);
-    const T u = (T)0.5 * r2 * ia2;
-    // far enough out the core is 1 to working precision: 1 - K = erfc(sqrt u) + sqrt(2/pi)(r/a)e^-u
-    // and the relative change of g is sqrt(2/pi) e^-u (r/a)^3 / 3; both stay below 4e-9 for
-    // u >= 24 (FP32) and below 3e-18 for u >= 46 (FP64)
-    if (u >= (sizeof(T) == 4 ? (T)24 : (T)46)) {
-        const T ir = (T)1 / sqrt(r2);
+        const T ir = rsqrt(r2);
         const T ir2 = ir * ir;
         f = ir2 * ir;
         g = (T)-3 * f * ir2;
         return;
     }
-    const T ia3 = ia2 / a;
+    const T c = (T)0.79788456080286535588;  // sqrt(2/pi)
+    const T ia = (T)1 / a;
+    const T ia2 = ia * ia;
+    const T u = (T)0.5 * r2 * ia2;
+    // far enough out the core is 1 to working precision: 1 - K = erfc(sqrt u) + sqrt(2/pi)(r/a)e^-u
+    // and the relative change of g is sqrt(2/pi) e^-u (r/a)^3 / 3; both stay below 4e-9 for
+    // u >= 24 (FP32) and below 3e-18 for u >= 46 (FP64)
+    if (u >= (sizeof(T) == 4 ? (T)24 : (T)46)) {
+        const T ir = rsqrt(r2);
+        const T ir2 = ir * ir;
+        f = ir2 * ir;
+        g = (T)-3 * f * ir2;
+        return;
+    }
+    const T ia3 = ia2 * ia;
     if (u < (T)0.02) {
+        // the series of K / r^3 and of its derivative term in u (coefficients folded at compile time)
         T fs = 0, gs = 0, term = 1, t2 = -1;
+#pragma unroll
         for (int k = 0; k < 12; k++) {
-            fs += term / (T)(2 * k + 3);
-            term *= -u / (T)(k + 1);
+            fs += term * (T)(1.0 / (2 * k + 3));
+            term *= -u * (T)(1.0 / (k + 1));
         }
+#pragma unroll
         for (int k = 1; k < 13; k++) {
-            gs += t2 / (T)(2 * k + 3);
-            t2 *= -u / (T)k;
+            gs += t2 * (T)(1.0 / (2 * k + 3));
+            t2 *= -u * (T)(1.0 / k);
         }
         f = c * ia3 * fs;
         g = c * ia3 * ia2 * gs;
     } else {
-        T r = sqrt(r2);
-        T ir = (T)1 / r;
-        T ex = exp(-u);
-        T K = erf(r * (T)0.70710678118654752440 / a) - c * r / a * ex;
-        T ir2 = ir * ir;
+        const T ir = rsqrt(r2);
+        const T r = r2 * ir;
+        const T ex = exp(-u);
+        const T ria = r * ia;
+        const T K = erf(ria * (T)0.70710678118654752440) - c * ria * ex;
+        const T ir2 = ir * ir;
         f = K * ir2 * ir;
         g = c * ex * ia3 * ir2 - (T)3 * f * ir2;
     }
