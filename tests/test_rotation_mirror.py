@@ -61,8 +61,20 @@ def blocks(n, theta, sbasis, back):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 6, 11, 16, 22])
-@pytest.mark.parametrize("theta", [np.arccos(1 / np.sqrt(3)), np.arccos(2 / 3), np.arccos(3 / np.sqrt(22)), 0.0])
+@pytest.mark.parametrize("theta", [np.arccos(1 / np.sqrt(3)), np.arccos(2 / 3), np.arccos(3 / np.sqrt(22)),
+                                   np.arccos(3 / np.sqrt(10))])
 def test_mirror_signs(n, theta):
+    _check(n, theta)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 6])
+def test_mirror_signs_axis(n):
+    # theta = 0 against theta = pi (the z axis and its reverse); low orders only: the reference
+    # exponential at theta = pi loses digits that the S-basis rescaling amplifies at high n
+    _check(n, 0.0)
+
+
+def _check(n, theta):
     for sbasis in (True, False):
         for back in (False, True):
             re, im = blocks(n, theta, sbasis, back)
